@@ -1,0 +1,100 @@
+"""Right-preconditioned BiCGStab for the complex-shifted systems.  Test infrastructure.
+
+The paper solves each shifted system (A - sigma_j B) y = f with BiCGStab
+(van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992)), Sections 2 and 4.2.  Its
+preconditioner (ILU with a drop tolerance) is replaced here by point Jacobi of
+the shifted operator, M_j = diag(A) - sigma_j diag(B), applied on the right.
+
+Readings: the initial guess is x_0 = 0, so r_0 = f, and the shadow residual is
+r_hat = f (real when f = B X is real, shared by all poles).  Inner products are
+Hermitian, (u, v) = u^H v.  Convergence is tested on the recursively updated
+residual after the half step (s) and the full step (r), relative to ||f||.
+
+Steps per iteration (all columns in parallel, each column its own scalars):
+    rho   = (r_hat, r)
+    beta  = (rho / rho_prev) (alpha / omega)
+    p     = r + beta (p - omega v)
+    p_hat = M^{-1} p ;  v = S p_hat ;  alpha = rho / (r_hat, v)
+    s     = r - alpha v                  -> stop if ||s|| <= tol ||f||, x += alpha p_hat
+    s_hat = M^{-1} s ;  t = S s_hat ;  omega = (t, s) / (t, t)
+    x     = x + alpha p_hat + omega s_hat
+    r     = s - omega t                  -> stop if ||r|| <= tol ||f||
+"""
+from __future__ import annotations
+
+import numpy as np
+
+ACTIVE, CONVERGED, HALF_CONVERGED, BREAKDOWN, MAXIT = 0, 1, 2, 3, 4
+
+
+def jacobi_diagonal(A, B, sigma: complex) -> np.ndarray:
+    """Diagonal of the shifted operator, diag(A) - sigma diag(B)."""
+    return A.diagonal().astype(np.complex128) - sigma * B.diagonal()
+
+
+def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None):
+    """Solve (A - sigma_c B) x_c = F[:, l(c)] for every pole and column.
+
+    sigmas: N poles; F: (n, L) real.  Columns are ordered pole-major,
+    c = j*L + l.  Returns (X (n, N*L) complex, iters[K], flags[K], relres[K]).
+    If ``fixed_iters`` is given, runs exactly that many full iterations with no
+    convergence test (for comparing intermediate iterates).
+    """
+    n, L = F.shape
+    N = len(sigmas)
+    K = N * L
+    sig = np.repeat(np.asarray(sigmas, dtype=np.complex128), L)          # (K,)
+    D = np.stack([jacobi_diagonal(A, B, s) for s in sigmas], axis=1)      # (n, N)
+    Dc = np.repeat(D, L, axis=1)                                          # (n, K)
+    f = np.tile(F, (1, N)).astype(np.complex128)                          # (n, K)
+    rhat = np.tile(F, (1, N)).astype(np.float64)
+
+    def S(Y):
+        return (A @ Y) - sig[None, :] * (B @ Y)
+
+    fn = np.sqrt((np.abs(f) ** 2).sum(0))
+    x = np.zeros((n, K), np.complex128)
+    r = f.copy()
+    p = np.zeros_like(x)
+    v = np.zeros_like(x)
+    rho_prev = np.ones(K, np.complex128)
+    alpha = np.ones(K, np.complex128)
+    omega = np.ones(K, np.complex128)
+    flags = np.where(fn == 0.0, CONVERGED, ACTIVE)
+    iters = np.zeros(K, np.int64)
+    nsteps = fixed_iters if fixed_iters is not None else maxit
+    for it in range(nsteps):
+        act = flags == ACTIVE
+        if not act.any():
+            break
+        rho = (rhat * r).sum(0)
+        beta = (rho / rho_prev) * (alpha / omega)
+        p = np.where(act, r + beta * (p - omega * v), p)
+        ph = p / Dc
+        v = np.where(act, S(ph), v)
+        rv = (rhat * v).sum(0)
+        bad = act & ((rho == 0) | (rv == 0))
+        alpha = np.where(act & ~bad, rho / np.where(rv == 0, 1, rv), alpha)
+        s = r - alpha * v
+        sn = np.sqrt((np.abs(s) ** 2).sum(0))
+        half = act & ~bad & (sn <= tol * fn) & (fixed_iters is None)
+        x = np.where(half, x + alpha * ph, x)
+        iters = np.where(act & ~bad, iters + 1, iters)
+        flags = np.where(half, HALF_CONVERGED, np.where(bad, BREAKDOWN, flags))
+        act = flags == ACTIVE
+        sh = s / Dc
+        t = S(sh)
+        tt = (np.abs(t) ** 2).sum(0)
+        ts = (np.conj(t) * s).sum(0)
+        bad = act & (tt == 0)
+        omega = np.where(act & ~bad, ts / np.where(tt == 0, 1, tt), omega)
+        x = np.where(act & ~bad, x + alpha * ph + omega * sh, x)
+        r = np.where(act & ~bad, s - omega * t, r)
+        rn = np.sqrt((np.abs(r) ** 2).sum(0))
+        conv = act & ~bad & (rn <= tol * fn) & (fixed_iters is None)
+        flags = np.where(conv, CONVERGED, np.where(bad, BREAKDOWN, flags))
+        rho_prev = np.where(act, rho, rho_prev)
+    if fixed_iters is None:
+        flags = np.where(flags == ACTIVE, MAXIT, flags)
+    relres = np.sqrt((np.abs(f - S(x)) ** 2).sum(0)) / np.where(fn == 0, 1, fn)
+    return x, iters, flags, relres
