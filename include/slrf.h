@@ -1,0 +1,160 @@
+/*
+ * slrf.h -- C ABI of the shifted-Laplace rational filter (SLRF) eigensolver for
+ * gfx950 (AMD Instinct MI355X).
+ *
+ * Problem (Wang, Meerbergen, Vandebril, An, Mo, arXiv:2503.21618, Section 1):
+ * every eigenpair (lambda, x) of A x = lambda B x with lambda in (0, gamma], for
+ * sparse symmetric positive definite A (stiffness) and B (mass).
+ *
+ * Method (Algorithm 1, Section 3): rational-filter subspace iteration.  Each
+ * outer iteration applies the filter Phi(A, B) = sum_j 2 Re(w_j (A - sigma_j B)^{-1} B)
+ * to an n x L block (N complex shifted solves per column, conjugate poles folded
+ * into the real part, Section 3), then Rayleigh-Ritz, then relative residuals
+ * rho_i = ||A x_i - theta_i B x_i||_2 / (|theta_i| ||B x_i||_2).  Poles lie on the
+ * shifted-Laplace line sigma_j = x_j (1 + alpha i) (Section 3.1, equation of
+ * the lines L+-).
+ *
+ * Conventions for every call:
+ *  - Dense blocks are row-major (n, L) float64 on the DEVICE: element (i, l) at
+ *    ptr[i * L + l] (a contiguous torch tensor of shape (n, L)).
+ *  - CSR arrays passed to slrf_create are HOST pointers, int32 row pointers and
+ *    column indices, float64 values, columns sorted within each row.
+ *  - The caller owns every buffer.  The library never allocates device memory:
+ *    all device scratch lives in the caller's workspace (size from
+ *    slrf_workspace_bytes), which must outlive the context.
+ *  - Work is enqueued on the HIP stream given at create; calls that return host
+ *    data synchronise that stream before returning.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - Errors: the return value is the status; slrf_last_error(ctx) gives detail.
+ *    No C++ exception crosses the ABI.
+ */
+#ifndef SLRF_H
+#define SLRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slrf_ctx_s* slrf_ctx;
+
+typedef enum {
+  SLRF_OK = 0,
+  SLRF_E_INVALID_ARG = 1,        /* bad size, NULL pointer, unsorted/out-of-range CSR, NaN */
+  SLRF_E_NOT_SPD = 2,            /* a diagonal entry of A or B is <= 0 or missing */
+  SLRF_E_WORKSPACE = 3,          /* workspace too small or misaligned (256 B) */
+  SLRF_E_DEVICE = 4,             /* a HIP runtime call failed */
+  SLRF_E_NOT_CONVERGED = 5,      /* outer iteration limit reached; partial result written */
+  SLRF_E_SUBSPACE_TOO_SMALL = 6, /* every one of the L Ritz values lies in (0, gamma] */
+  SLRF_E_BREAKDOWN = 7           /* projected problem not solvable (non-finite Gram) */
+} slrf_status;
+
+typedef enum { SLRF_FP64 = 0, SLRF_MIXED = 1 } slrf_precision;
+
+/* Pole set in the upper half plane (Section 3: the N conjugate partners are
+ * implied).  sigma and weight point to 2N HOST doubles, (re, im) interleaved;
+ * Im(sigma_j) > 0 is required. */
+typedef struct {
+  int32_t n_poles;
+  const double* sigma;
+  const double* weight;
+} slrf_poles;
+
+typedef struct {
+  int32_t precision;   /* slrf_precision.  FP64: complex FP64 inner solves.  MIXED:
+                          complex FP32 inner solves with FP64 defect correction */
+  double inner_tol;    /* relative residual ||f - S y|| / ||f|| of each shifted solve */
+  int32_t inner_maxit; /* BiCGStab iteration limit per solve (paper: 1000) */
+  double outer_tol;    /* tau of the residual test (paper Section 4.2: 1e-8) */
+  int32_t outer_maxit; /* outer (subspace) iteration limit */
+  int32_t check_every; /* inner iterations between host polls of the convergence count */
+  uint64_t seed;       /* SplitMix64 seed of the Gaussian start block when V0 is NULL */
+} slrf_options;
+
+typedef struct {
+  int32_t max_iterations;   /* largest BiCGStab iteration count over the columns */
+  double mean_iterations;   /* mean BiCGStab iterations per (pole, column) */
+  int64_t spmv;             /* single-vector products with A - sigma_j B (2 per full
+                               iteration, 1 when a solve stops at the half step) */
+  int32_t n_breakdown;      /* columns stopped by a zero denominator */
+  int32_t n_maxit;          /* columns that hit inner_maxit */
+  int32_t refinements;      /* MIXED: defect-correction rounds used */
+  double max_relres;        /* largest final relative residual over the columns */
+  double seconds;           /* wall time of the call */
+} slrf_filter_stats;
+
+typedef struct {
+  int32_t outer_iterations;
+  int64_t spmv_total;       /* paper Table 4 "spMV" */
+  int32_t n_found;          /* converged Ritz pairs in (0, gamma] */
+  double max_resid;         /* largest rho_i over those pairs */
+  double seconds;           /* wall time of the call */
+  double filter_seconds;    /* of which in filter application */
+} slrf_solve_stats;
+
+/* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
+ * outer_maxit 40, check_every 10, seed 1. */
+void slrf_default_options(slrf_options* opt);
+
+/* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance
+ * between Phi(x) = sum_j 2 Re(w_j/(x - sigma_j)) and the step h (1 on [0, gamma],
+ * 0 on (gamma, 10 gamma]), delta = beta on [0, gamma], 1 on (gamma, 10 gamma],
+ * over sigma_j = x_j (1 + alpha i), x_j in (0, gamma], and complex w_j, plus a
+ * ridge term 1e-6 gamma^-2 sum |w_j|^2 that keeps the poles distinct (without it
+ * the infimum is a merged pole with unbounded weights).  Host-only.
+ * Outputs: sigma_out, weight_out: 2N doubles each, sorted by Re(sigma);
+ * sep_factor_out (may be NULL): |Phi'(gamma)| (Definition 3.1).
+ * Errors: INVALID_ARG for N < 1 or N > 16, alpha <= 0, beta <= 0, gamma <= 0. */
+slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma,
+                              double* sigma_out, double* weight_out, double* sep_factor_out);
+
+/* Bytes of device workspace slrf_create needs for a pencil with n rows and
+ * nnz_union entries in the union of the patterns of A and B, subspace size up
+ * to L and up to N poles, at the given precision. */
+slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
+                                 int32_t precision, size_t* bytes);
+
+/* Validates A and B (square, sorted in-range columns, finite values, symmetric
+ * pattern sizes, positive diagonals), merges them into one CSR over the union
+ * pattern with (a_ij, b_ij) value pairs, and uploads it into the workspace.
+ * d_workspace: device, 256-byte aligned, ws_bytes from slrf_workspace_bytes
+ * with the largest L and N that later calls use.  hip_stream: a hipStream_t
+ * (NULL = default stream).  opt may be NULL (defaults). */
+slrf_status slrf_create(slrf_ctx* out, int64_t n,
+                        const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                        const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                        void* d_workspace, size_t ws_bytes, int64_t max_L, int32_t max_poles,
+                        const slrf_options* opt, void* hip_stream);
+
+/* One filter application (Algorithm 1, the "Solve" loop and "Compute U"):
+ *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
+ * every (pole, column) system solved by right-preconditioned BiCGStab with the
+ * point-Jacobi preconditioner diag(A) - sigma_j diag(B) of the shifted operator,
+ * x_0 = 0 and shadow residual B X.  d_X, d_U: device (n, L) row-major float64
+ * (may not alias).  stats may be NULL.  Returns SLRF_OK even if some columns hit
+ * inner_maxit or broke down; stats reports them. */
+slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L,
+                              const double* d_X, double* d_U, slrf_filter_stats* stats);
+
+/* All eigenpairs in (0, gamma] by Algorithm 1.  poles: NULL designs N = 4,
+ * alpha = 1, beta = 0.01 (Section 4.2).  d_V0: device (n, L) start block, or
+ * NULL for a seeded Gaussian block.  Outputs: n_found (host), h_evals (host, L
+ * doubles: all Ritz values ascending, the first n_found are the eigenvalues in
+ * (0, gamma]), d_evecs (device (n, L), B-orthonormal Ritz vectors in the same
+ * order), h_resid (host, L doubles: rho_i).  stats may be NULL.
+ * Stopping: every Ritz value in (0, gamma] has rho_i <= outer_tol and their
+ * number is unchanged from the previous outer iteration. */
+slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slrf_poles* poles,
+                                const double* d_V0, int64_t* n_found, double* h_evals,
+                                double* d_evecs, double* h_resid, slrf_solve_stats* stats);
+
+void slrf_destroy(slrf_ctx ctx);
+const char* slrf_status_string(slrf_status s);
+const char* slrf_last_error(slrf_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLRF_H */

@@ -1,0 +1,17 @@
+// Host FP64 dense helpers for the projected (L x L) problems.
+#pragma once
+
+namespace slrf {
+
+// Eigen-decomposition of a symmetric n x n row-major matrix A (destroyed):
+// w ascending, V row-major with column j the eigenvector of w[j].
+bool sym_eig(int n, double* A, double* w, double* V);
+
+// Ritz values theta (ascending) and coefficients Z (L x L row-major) of the
+// projected pencil (GA, GB): Z^T GB Z = I, Z^T GA Z = diag(theta).
+bool projected_pencil(int L, const double* GA, const double* GB, double* theta, double* Z);
+
+// SLRF design at gamma = 1 (see slrf.h): xi[N] sorted, omega[2N] (re, im).
+bool design_poles_unit(int N, double alpha, double beta, double* xi, double* omega);
+
+}  // namespace slrf

@@ -1,0 +1,111 @@
+// Device-side data types and kernel launchers of the SLRF library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slrf {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+  R re, im;
+};
+
+// One merged-CSR value: stiffness a_ij and mass b_ij of the same entry.
+template <typename R>
+struct alignas(2 * sizeof(R)) ab_pair {
+  R a, b;
+};
+
+// Per-column state of the inner BiCGStab solves.
+enum ColFlag : int {
+  COL_ACTIVE = 0,
+  COL_CONVERGED = 1,
+  COL_HALF_CONVERGED = 2,
+  COL_BREAKDOWN = 3,
+  COL_MAXIT = 4,
+  COL_HALF_PENDING = 5,  // converged at the half step; x still takes alpha * p_hat
+};
+
+// Geometry of an (n, K) complex Krylov block: rows split into row blocks of
+// `rows_per_block`, columns into tiles of 64 (one column per lane).  Every
+// kernel over the block uses the same decomposition, so per-column partial
+// sums live in [nrb][K] arrays and are reduced in a fixed order.
+struct KGeom {
+  int n;
+  int K;             // columns = poles * L, pole-major (c = j * L + l)
+  int L;
+  int N;             // poles
+  int rows_per_block;
+  int nrb;           // row blocks
+  int nct;           // column tiles of 64
+  int64_t total;     // nrb * nct workgroups
+  int64_t padded;    // total rounded up to a multiple of 8 (XCD count)
+};
+
+KGeom make_geom(int n, int N, int L, int rows_per_block);
+
+template <typename R>
+struct KrylovState {
+  cx<R>* x;
+  cx<R>* r;
+  cx<R>* ph;   // preconditioned search direction M^{-1} p
+  cx<R>* v;
+  cx<R>* sh;   // preconditioned half-step residual M^{-1} s
+  cx<R>* t;
+  const R* rhat;       // (n, L) shared shadow residual = right-hand side
+  const cx<R>* d;      // (n, N) shifted-operator diagonal
+  const cx<R>* dinv;   // (n, N) its inverse
+  const cx<R>* sigma_col;  // (K) pole of each column
+  cx<R>* part_a;       // (nrb, K) complex partial sums
+  R* part_b;           // (nrb, K) real partial sums
+  // per-column scalars
+  cx<R>* rho;
+  cx<R>* alpha;
+  cx<R>* omega;
+  cx<R>* beta;
+  R* fnorm;
+  R* rnorm;
+  int* flags;
+  int* iters;
+};
+
+// ---- launchers (stream-ordered) -----------------------------------------
+template <typename R>
+void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
+                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv);
+template <typename R>
+void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const R* F);
+template <typename R>
+void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st);
+template <typename R>
+void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st,
+                      const int* rowptr, const int* col, const ab_pair<R>* ab,
+                      R tol, int maxit, bool first);
+void launch_count_active(hipStream_t s, int K, const int* flags, int* out);
+
+template <typename R>
+void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x,
+                       const double* w /* 2N */, double* U, bool accumulate);
+
+// real products with the merged pencil: AX = A X, BX = B X (either may be null)
+template <typename R>
+void launch_spmm_real(hipStream_t s, int n, int L, const int* rowptr, const int* col,
+                      const ab_pair<R>* ab, const double* X, double* AX, double* BX);
+
+// Gram matrices GA = U^T WA, GB = U^T WB (L x L), FP64 MFMA, deterministic.
+void launch_gram(hipStream_t s, int n, int L, const double* U, const double* WA,
+                 const double* WB, double* part, int nchunks, double* GA, double* GB);
+int gram_chunks(int n, int L);
+
+// Y_b = X_b Z for b < nb blocks (n x L times L x r), FP64 MFMA.
+void launch_gemm_nz(hipStream_t s, int n, int L, int r, int nb, const double* const* X,
+                    const double* Z, double* const* Y);
+
+// per-column sums of |AX - theta BX|^2 and |BX|^2 over row blocks of 256
+void launch_resid(hipStream_t s, int n, int L, const double* AX, const double* BX,
+                  const double* theta, double* part /* [nrb][2][L] */, int nrb);
+
+void launch_gaussian(hipStream_t s, int64_t count, uint64_t seed, double* out);
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
+
+}  // namespace slrf

@@ -1,0 +1,767 @@
+// gfx950 kernels of the SLRF eigensolver.
+//
+// Layout in HBM: every dense block is row-major.  The Krylov state of all
+// N poles x L columns is one (n, K) complex block, K = N * L, column
+// c = j * L + l belongs to pole j and right-hand side l; complex numbers are
+// (re, im) interleaved, so one row of a 64-column tile is a contiguous
+// 64 * sizeof(cx<R>) byte segment (1 KiB in FP64).
+//
+// Work decomposition shared by all Krylov kernels: a workgroup of 256 threads
+// (4 wavefronts of 64) owns one row block x one 64-column tile; each lane owns
+// one column, each wavefront walks every 4th row of the block.  Per-column dot
+// products therefore accumulate in registers with no cross-lane traffic; the 4
+// wavefronts are combined through LDS and the row blocks by a per-column kernel
+// that sums [nrb][K] partials in a fixed order (bitwise reproducible).
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; blockIdx is remapped
+// so that each XCD owns a contiguous range of row blocks of one column tile, so
+// the neighbouring rows gathered by the sparse product stay in that XCD's L2.
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace slrf {
+
+constexpr int WAVE = 64;
+constexpr int WG = 256;
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t padded) {
+  const int64_t per = padded >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cdiv(cx<R> a, cx<R> b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    R q = b.im / b.re, den = b.re + b.im * q;
+    return {(a.re + a.im * q) / den, (a.im - a.re * q) / den};
+  }
+  R q = b.re / b.im, den = b.re * q + b.im;
+  return {(a.re * q + a.im) / den, (a.im * q - a.re) / den};
+}
+
+KGeom make_geom(int n, int N, int L, int rows_per_block) {
+  KGeom g;
+  g.n = n;
+  g.N = N;
+  g.L = L;
+  g.K = N * L;
+  g.rows_per_block = rows_per_block;
+  g.nrb = (n + rows_per_block - 1) / rows_per_block;
+  g.nct = (g.K + WAVE - 1) / WAVE;
+  g.total = (int64_t)g.nrb * g.nct;
+  g.padded = (g.total + 7) / 8 * 8;
+  return g;
+}
+
+struct BlockPos {
+  int rb, ct, c, lane, w, r0, r1;
+  bool valid;
+};
+
+__device__ __forceinline__ bool block_pos(const KGeom& g, BlockPos& p) {
+  int64_t id = xcd_remap(blockIdx.x, g.padded);
+  if (id >= g.total) return false;
+  p.rb = (int)(id % g.nrb);
+  p.ct = (int)(id / g.nrb);
+  p.lane = lane_id();
+  p.w = wave_id();
+  p.c = p.ct * WAVE + p.lane;
+  p.valid = p.c < g.K;
+  p.r0 = p.rb * g.rows_per_block;
+  p.r1 = min(p.r0 + g.rows_per_block, g.n);
+  return true;
+}
+
+// true if any column of the tile is in one of the given states
+__device__ __forceinline__ bool tile_has(const int* flags, const BlockPos& p, int s0, int s1) {
+  int f = p.valid ? flags[p.c] : -1;
+  return __any(f == s0 || f == s1);
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_store_partial(T v, const BlockPos& p, T* out, int K) {
+  __shared__ T red[4][WAVE];
+  red[p.w][p.lane] = v;
+  __syncthreads();
+  if (p.w == 0 && p.valid) {
+    T s = red[0][p.lane];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) s = s + red[q][p.lane];
+    out[(size_t)p.rb * K + p.c] = s;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void wg_store_partial_cx(cx<R> v, const BlockPos& p, cx<R>* out, int K) {
+  __shared__ R rr[4][WAVE], ri[4][WAVE];
+  rr[p.w][p.lane] = v.re;
+  ri[p.w][p.lane] = v.im;
+  __syncthreads();
+  if (p.w == 0 && p.valid) {
+    R sr = rr[0][p.lane], si = ri[0][p.lane];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      sr += rr[q][p.lane];
+      si += ri[q][p.lane];
+    }
+    out[(size_t)p.rb * K + p.c] = {sr, si};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Complex-shifted sparse product over the merged CSR:
+//   Q[i, c] = sum_j (a_ij - sigma_c b_ij) P[j, c]
+// (A - sigma B is never formed: each (a, b) pair is read once per tile and the
+// pole of the column is applied when the row is finished.)
+template <typename R>
+__device__ __forceinline__ cx<R> shifted_row(int i, const int* __restrict__ rowptr,
+                                             const int* __restrict__ col,
+                                             const ab_pair<R>* __restrict__ ab,
+                                             const cx<R>* __restrict__ P, int K, int c,
+                                             bool valid, cx<R> sig) {
+  const int k0 = rowptr[i], k1 = rowptr[i + 1];
+  R apr = 0, api = 0, bpr = 0, bpi = 0;
+  const cx<R>* Pc = P + c;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const int j = col[k];
+    const ab_pair<R> m = ab[k];
+    cx<R> x = {0, 0};
+    if (valid) x = Pc[(size_t)j * K];
+    apr += m.a * x.re;
+    api += m.a * x.im;
+    bpr += m.b * x.re;
+    bpi += m.b * x.im;
+  }
+  return {apr - (sig.re * bpr - sig.im * bpi), api - (sig.re * bpi + sig.im * bpr)};
+}
+
+// v = S p_hat, partial (rhat, v)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_spmm_v(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
+                                              const int* __restrict__ col,
+                                              const ab_pair<R>* __restrict__ ab) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
+  const int l = p.c % g.L;
+  R dr = 0, di = 0;
+  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+    cx<R> q = shifted_row<R>(i, rowptr, col, ab, st.ph, g.K, p.c, p.valid, sig);
+    if (p.valid) {
+      st.v[(size_t)i * g.K + p.c] = q;
+      const R rh = st.rhat[(size_t)i * g.L + l];
+      dr += rh * q.re;
+      di += rh * q.im;
+    }
+  }
+  wg_store_partial_cx<R>({dr, di}, p, st.part_a, g.K);
+}
+
+// t = S s_hat, partials (t, s) = t^H s with s = d s_hat, and (t, t)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
+                                              const int* __restrict__ col,
+                                              const ab_pair<R>* __restrict__ ab) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
+  const int pole = p.c / g.L;
+  R tsr = 0, tsi = 0, tt = 0;
+  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+    cx<R> t = shifted_row<R>(i, rowptr, col, ab, st.sh, g.K, p.c, p.valid, sig);
+    if (p.valid) {
+      st.t[(size_t)i * g.K + p.c] = t;
+      const cx<R> s = cmul(st.d[(size_t)i * g.N + pole], st.sh[(size_t)i * g.K + p.c]);
+      // conj(t) * s
+      tsr += t.re * s.re + t.im * s.im;
+      tsi += t.re * s.im - t.im * s.re;
+      tt += t.re * t.re + t.im * t.im;
+    }
+  }
+  wg_store_partial_cx<R>({tsr, tsi}, p, st.part_a, g.K);
+  __syncthreads();
+  wg_store_partial<R>(tt, p, st.part_b, g.K);
+}
+
+// p_hat = (r + beta (d p_hat - omega v)) / d     (first iteration: r / d)
+template <typename R>
+__global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int first) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
+  if (!act) return;
+  const int pole = p.c / g.L;
+  const cx<R> beta = st.beta[p.c], omega = st.omega[p.c];
+  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+    const size_t e = (size_t)i * g.K + p.c;
+    const cx<R> di = st.dinv[(size_t)i * g.N + pole];
+    cx<R> pn = st.r[e];
+    if (!first) {
+      const cx<R> dd = st.d[(size_t)i * g.N + pole];
+      pn = cadd(pn, cmul(beta, csub(cmul(dd, st.ph[e]), cmul(omega, st.v[e]))));
+    }
+    st.ph[e] = cmul(pn, di);
+  }
+}
+
+// s = r - alpha v ; s_hat = s / d ; partial |s|^2
+template <typename R>
+__global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
+  const int pole = p.c / g.L;
+  const cx<R> alpha = act ? st.alpha[p.c] : cx<R>{0, 0};
+  R ss = 0;
+  if (act) {
+    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+      const size_t e = (size_t)i * g.K + p.c;
+      const cx<R> s = csub(st.r[e], cmul(alpha, st.v[e]));
+      ss += s.re * s.re + s.im * s.im;
+      st.sh[e] = cmul(s, st.dinv[(size_t)i * g.N + pole]);
+    }
+  }
+  wg_store_partial<R>(ss, p, st.part_b, g.K);
+}
+
+// x += alpha p_hat + omega s_hat ; r = d s_hat - omega t ; partials (rhat, r), |r|^2
+// Columns that converged at the half step take x += alpha p_hat only.
+template <typename R>
+__global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int first) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  if (!tile_has(st.flags, p, COL_ACTIVE, COL_HALF_PENDING)) return;
+  const int f = p.valid ? st.flags[p.c] : -1;
+  const bool act = f == COL_ACTIVE, half = f == COL_HALF_PENDING;
+  const int pole = p.c / g.L;
+  const int l = p.c % g.L;
+  const cx<R> alpha = (act || half) ? st.alpha[p.c] : cx<R>{0, 0};
+  const cx<R> omega = act ? st.omega[p.c] : cx<R>{0, 0};
+  R rr = 0, ri = 0, nn = 0;
+  if (act || half) {
+    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+      const size_t e = (size_t)i * g.K + p.c;
+      cx<R> x = first ? cx<R>{0, 0} : st.x[e];
+      x = cadd(x, cmul(alpha, st.ph[e]));
+      if (act) {
+        const cx<R> sh = st.sh[e];
+        x = cadd(x, cmul(omega, sh));
+        const cx<R> r = csub(cmul(st.d[(size_t)i * g.N + pole], sh), cmul(omega, st.t[e]));
+        st.r[e] = r;
+        const R rh = st.rhat[(size_t)i * g.L + l];
+        rr += rh * r.re;
+        ri += rh * r.im;
+        nn += r.re * r.re + r.im * r.im;
+      }
+      st.x[e] = x;
+    }
+  }
+  wg_store_partial_cx<R>({rr, ri}, p, st.part_a, g.K);
+  __syncthreads();
+  wg_store_partial<R>(nn, p, st.part_b, g.K);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> sum_part_cx(const cx<R>* part, int nrb, int K, int c) {
+  R sr = 0, si = 0;
+  for (int b = 0; b < nrb; ++b) {
+    const cx<R> v = part[(size_t)b * K + c];
+    sr += v.re;
+    si += v.im;
+  }
+  return {sr, si};
+}
+template <typename R>
+__device__ __forceinline__ R sum_part(const R* part, int nrb, int K, int c) {
+  R s = 0;
+  for (int b = 0; b < nrb; ++b) s += part[(size_t)b * K + c];
+  return s;
+}
+template <typename R>
+__device__ __forceinline__ bool cfinite(cx<R> z) { return isfinite(z.re) && isfinite(z.im); }
+
+// alpha = rho / (rhat, v)
+template <typename R>
+__global__ void k_sc_alpha(KGeom g, KrylovState<R> st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
+  const cx<R> rv = sum_part_cx(st.part_a, g.nrb, g.K, c);
+  const cx<R> rho = st.rho[c];
+  if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
+    st.flags[c] = COL_BREAKDOWN;
+    return;
+  }
+  st.alpha[c] = cdiv(rho, rv);
+  st.iters[c] += 1;
+}
+
+// half-step test ||s|| <= tol ||f||
+template <typename R>
+__global__ void k_sc_half(KGeom g, KrylovState<R> st, R tol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
+  const R sn = sqrt(sum_part(st.part_b, g.nrb, g.K, c));
+  if (sn <= tol * st.fnorm[c]) {
+    st.flags[c] = COL_HALF_PENDING;
+    st.rnorm[c] = sn;
+  }
+}
+
+// omega = (t, s) / (t, t)
+template <typename R>
+__global__ void k_sc_omega(KGeom g, KrylovState<R> st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
+  const cx<R> ts = sum_part_cx(st.part_a, g.nrb, g.K, c);
+  const R tt = sum_part(st.part_b, g.nrb, g.K, c);
+  if (tt == 0 || !isfinite(tt)) {
+    st.flags[c] = COL_BREAKDOWN;
+    return;
+  }
+  st.omega[c] = {ts.re / tt, ts.im / tt};
+}
+
+// rho_new = (rhat, r); ||r|| test; beta = (rho_new / rho)(alpha / omega)
+template <typename R>
+__global__ void k_sc_beta(KGeom g, KrylovState<R> st, R tol, int maxit) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.K) return;
+  const int f = st.flags[c];
+  if (f == COL_HALF_PENDING) {
+    st.flags[c] = COL_HALF_CONVERGED;
+    return;
+  }
+  if (f != COL_ACTIVE) return;
+  const cx<R> rn = sum_part_cx(st.part_a, g.nrb, g.K, c);
+  const R nn = sqrt(sum_part(st.part_b, g.nrb, g.K, c));
+  st.rnorm[c] = nn;
+  if (nn <= tol * st.fnorm[c]) {
+    st.flags[c] = COL_CONVERGED;
+    return;
+  }
+  if (st.iters[c] >= maxit) {
+    st.flags[c] = COL_MAXIT;
+    return;
+  }
+  const cx<R> om = st.omega[c];
+  if ((om.re == 0 && om.im == 0) || !cfinite(rn)) {
+    st.flags[c] = COL_BREAKDOWN;
+    return;
+  }
+  st.beta[c] = cmul(cdiv(rn, st.rho[c]), cdiv(st.alpha[c], om));
+  st.rho[c] = rn;
+}
+
+template <typename R>
+void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const int* rowptr,
+                      const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first) {
+  const dim3 grid((unsigned)g.padded), blk(WG);
+  const dim3 cgrid((g.K + 255) / 256), cblk(256);
+  k_update_p<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
+  k_spmm_v<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
+  k_sc_alpha<R><<<cgrid, cblk, 0, s>>>(g, st);
+  k_update_s<R><<<grid, blk, 0, s>>>(g, st);
+  k_sc_half<R><<<cgrid, cblk, 0, s>>>(g, st, tol);
+  k_spmm_t<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
+  k_sc_omega<R><<<cgrid, cblk, 0, s>>>(g, st);
+  k_update_x<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
+  k_sc_beta<R><<<cgrid, cblk, 0, s>>>(g, st, tol, maxit);
+}
+
+// x = 0, r = f (broadcast over poles); partials of (rhat, r) = ||f||^2
+template <typename R>
+__global__ __launch_bounds__(WG) void k_init(KGeom g, KrylovState<R> st, const R* __restrict__ F) {
+  BlockPos p;
+  if (!block_pos(g, p)) return;
+  const int l = p.c % g.L;
+  R nn = 0;
+  if (p.valid) {
+    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
+      const R f = F[(size_t)i * g.L + l];
+      st.r[(size_t)i * g.K + p.c] = {f, 0};
+      st.x[(size_t)i * g.K + p.c] = {0, 0};
+      nn += f * f;
+    }
+  }
+  wg_store_partial<R>(nn, p, st.part_b, g.K);
+}
+
+template <typename R>
+__global__ void k_init_scalars(KGeom g, KrylovState<R> st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.K) return;
+  const R nn = sum_part(st.part_b, g.nrb, g.K, c);
+  st.fnorm[c] = sqrt(nn);
+  st.rnorm[c] = sqrt(nn);
+  st.rho[c] = {nn, 0};
+  st.alpha[c] = {1, 0};
+  st.omega[c] = {1, 0};
+  st.beta[c] = {0, 0};
+  st.iters[c] = 0;
+  st.flags[c] = nn == 0 ? COL_CONVERGED : COL_ACTIVE;
+}
+
+template <typename R>
+void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const R* F) {
+  k_init<R><<<dim3((unsigned)g.padded), dim3(WG), 0, s>>>(g, st, F);
+}
+template <typename R>
+void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st) {
+  k_init_scalars<R><<<dim3((g.K + 255) / 256), dim3(256), 0, s>>>(g, st);
+}
+
+__global__ void k_count_active(int K, const int* flags, int* out) {
+  __shared__ int cnt[256];
+  int c0 = 0;
+  for (int c = threadIdx.x; c < K; c += 256) c0 += (flags[c] == COL_ACTIVE) ? 1 : 0;
+  cnt[threadIdx.x] = c0;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = cnt[0];
+}
+void launch_count_active(hipStream_t s, int K, const int* flags, int* out) {
+  k_count_active<<<1, 256, 0, s>>>(K, flags, out);
+}
+
+// d = diag(A) - sigma_j diag(B), dinv = 1 / d
+template <typename R>
+__global__ void k_jacobi(int n, int N, const R* dA, const R* dB, const cx<R>* sigma, cx<R>* d,
+                         cx<R>* dinv) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * N) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  const cx<R> s = sigma[j];
+  const cx<R> v = {dA[i] - s.re * dB[i], -s.im * dB[i]};
+  d[e] = v;
+  dinv[e] = cdiv(cx<R>{1, 0}, v);
+}
+template <typename R>
+void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
+                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv) {
+  const int64_t tot = (int64_t)n * N;
+  k_jacobi<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, N, diagA, diagB, sigma, d, dinv);
+}
+
+// U[i, l] (+)= sum_j 2 Re(w_j x[i, j L + l])
+template <typename R>
+__global__ void k_filter_sum(int n, int L, int N, const cx<R>* __restrict__ x, const double* __restrict__ w,
+                             double* __restrict__ U, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * L) return;
+  const int64_t i = e / L;
+  const int l = (int)(e % L);
+  const int64_t K = (int64_t)N * L;
+  double s = accumulate ? U[e] : 0.0;
+  for (int j = 0; j < N; ++j) {
+    const cx<R> y = x[i * K + (int64_t)j * L + l];
+    s += 2.0 * (w[2 * j] * (double)y.re - w[2 * j + 1] * (double)y.im);
+  }
+  U[e] = s;
+}
+template <typename R>
+void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x, const double* w, double* U,
+                       bool accumulate) {
+  const int64_t tot = (int64_t)n * L;
+  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, x, w, U, accumulate ? 1 : 0);
+}
+
+// Real products of the merged pencil with a real block: one wavefront per row.
+template <typename R>
+__global__ __launch_bounds__(WG) void k_spmm_real(int n, int L, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ col,
+                                                 const ab_pair<R>* __restrict__ ab,
+                                                 const double* __restrict__ X, double* __restrict__ AX,
+                                                 double* __restrict__ BX) {
+  const int row = blockIdx.x * 4 + wave_id();
+  if (row >= n) return;
+  const int lane = lane_id();
+  const int k0 = rowptr[row], k1 = rowptr[row + 1];
+  for (int c = lane; c < L; c += WAVE) {
+    double sa = 0, sb = 0;
+    for (int k = k0; k < k1; ++k) {
+      const int j = col[k];
+      const ab_pair<R> m = ab[k];
+      const double x = X[(size_t)j * L + c];
+      sa += (double)m.a * x;
+      sb += (double)m.b * x;
+    }
+    if (AX) AX[(size_t)row * L + c] = sa;
+    if (BX) BX[(size_t)row * L + c] = sb;
+  }
+}
+template <typename R>
+void launch_spmm_real(hipStream_t s, int n, int L, const int* rowptr, const int* col, const ab_pair<R>* ab,
+                      const double* X, double* AX, double* BX) {
+  k_spmm_real<R><<<dim3((n + 3) / 4), dim3(WG), 0, s>>>(n, L, rowptr, col, ab, X, AX, BX);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA (v_mfma_f64_16x16x4_f64).  Operand layout for D(16x16) += A(16x4) B(4x16):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it receives
+// D[l / 16 + 4 q][l % 16] in accumulator element q (checked on gfx950 with
+// indicator inputs).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Partial Gram matrices over a chunk of rows: GA = U^T WA, GB = U^T WB.
+// A workgroup covers a 128 (rows of G) x 64 (columns of G) region; wavefront w
+// covers 64 x 32 of it as 4 x 2 tiles of 16 x 16, for both products.
+__global__ __launch_bounds__(WG) void k_gram(int n, int L, const double* __restrict__ U,
+                                            const double* __restrict__ WA, const double* __restrict__ WB,
+                                            int rows_per_chunk, double* __restrict__ part) {
+  const int chunk = blockIdx.x;
+  const int nbb = (L + 63) / 64;
+  const int ba = blockIdx.y / nbb, bb = blockIdx.y % nbb;
+  const int w = wave_id(), lane = lane_id();
+  const int a0 = ba * 128 + (w >> 1) * 64;
+  const int b0 = bb * 64 + (w & 1) * 32;
+  const int li = lane >> 4, lj = lane & 15;
+  d4 accA[4][2], accB[4][2];
+#pragma unroll
+  for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      accA[ta][tb] = d4{0, 0, 0, 0};
+      accB[ta][tb] = d4{0, 0, 0, 0};
+    }
+  const int i0 = chunk * rows_per_chunk;
+  const int i1 = min(n, i0 + rows_per_chunk);
+  for (int i = i0; i < i1; i += 4) {
+    const int row = i + li;
+    const bool rv = row < i1;
+    double a[4], xa[2], xb[2];
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta) {
+      const int cidx = a0 + 16 * ta + lj;
+      a[ta] = (rv && cidx < L) ? U[(size_t)row * L + cidx] : 0.0;
+    }
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      const int cidx = b0 + 16 * tb + lj;
+      const bool ok = rv && cidx < L;
+      xa[tb] = ok ? WA[(size_t)row * L + cidx] : 0.0;
+      xb[tb] = ok ? WB[(size_t)row * L + cidx] : 0.0;
+    }
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) {
+        accA[ta][tb] = mfma64(a[ta], xa[tb], accA[ta][tb]);
+        accB[ta][tb] = mfma64(a[ta], xb[tb], accB[ta][tb]);
+      }
+  }
+  const size_t LL = (size_t)L * L;
+  double* pA = part + (size_t)chunk * 2 * LL;
+  double* pB = pA + LL;
+#pragma unroll
+  for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ga = a0 + 16 * ta + li + 4 * q;
+        const int gb = b0 + 16 * tb + lj;
+        if (ga < L && gb < L) {
+          pA[(size_t)ga * L + gb] = accA[ta][tb][q];
+          pB[(size_t)ga * L + gb] = accB[ta][tb][q];
+        }
+      }
+}
+
+__global__ void k_gram_reduce(int L, int nchunks, const double* __restrict__ part, double* __restrict__ GA,
+                              double* __restrict__ GB) {
+  const size_t LL = (size_t)L * L;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * LL) return;
+  const int which = (int)(e / LL);
+  const size_t o = e % LL;
+  double s = 0;
+  for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * 2 * LL + which * LL + o];
+  (which ? GB : GA)[o] = s;
+}
+
+// Row chunks of the split-K Gram product: independent of L so that the partial
+// buffer sized for the largest L also fits every smaller L.
+int gram_chunks(int n, int /*L*/) {
+  int rows = (n + 255) / 256;
+  rows = std::max(64, (rows + 3) / 4 * 4);
+  return (n + rows - 1) / rows;
+}
+
+void launch_gram(hipStream_t s, int n, int L, const double* U, const double* WA, const double* WB,
+                 double* part, int nchunks, double* GA, double* GB) {
+  int rows = (n + nchunks - 1) / nchunks;
+  rows = (rows + 3) / 4 * 4;
+  const int tiles = ((L + 127) / 128) * ((L + 63) / 64);
+  k_gram<<<dim3(nchunks, tiles), dim3(WG), 0, s>>>(n, L, U, WA, WB, rows, part);
+  const size_t tot = 2 * (size_t)L * L;
+  k_gram_reduce<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(L, nchunks, part, GA, GB);
+}
+
+// Y_b = X_b Z : (n x L)(L x r).  Wavefront w of workgroup bx owns rows
+// [64 bx + 16 w, +16) and sweeps the output columns in groups of 8 tiles.
+struct GemmBlocks {
+  const double* X[3];
+  double* Y[3];
+};
+
+__global__ __launch_bounds__(WG) void k_gemm_nz(int n, int L, int r, GemmBlocks gb,
+                                               const double* __restrict__ Z) {
+  const double* __restrict__ X = gb.X[blockIdx.y];
+  double* __restrict__ Y = gb.Y[blockIdx.y];
+  const int w = wave_id(), lane = lane_id();
+  const int li = lane >> 4, lj = lane & 15;
+  const int row0 = blockIdx.x * 64 + w * 16;
+  if (row0 >= n) return;
+  for (int c0 = 0; c0 < r; c0 += 128) {
+    d4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = d4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < L; k0 += 4) {
+      const int row = row0 + lj;
+      const int k = k0 + li;
+      const double a = (row < n && k < L) ? X[(size_t)row * L + k] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int cc = c0 + 16 * t + lj;
+        const double b = (k < L && cc < r) ? Z[(size_t)k * r + cc] : 0.0;
+        acc[t] = mfma64(a, b, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + li + 4 * q;
+        const int cc = c0 + 16 * t + lj;
+        if (row < n && cc < r) Y[(size_t)row * r + cc] = acc[t][q];
+      }
+  }
+}
+
+void launch_gemm_nz(hipStream_t s, int n, int L, int r, int nb, const double* const* X, const double* Z,
+                    double* const* Y) {
+  GemmBlocks gbk{};
+  for (int b = 0; b < nb; ++b) {
+    gbk.X[b] = X[b];
+    gbk.Y[b] = Y[b];
+  }
+  k_gemm_nz<<<dim3((n + 63) / 64, nb), dim3(WG), 0, s>>>(n, L, r, gbk, Z);
+}
+
+// Residual column sums over row blocks of 256 rows.
+__global__ __launch_bounds__(WG) void k_resid(int n, int L, const double* __restrict__ AX,
+                                             const double* __restrict__ BX, const double* __restrict__ theta,
+                                             double* __restrict__ part) {
+  const int w = wave_id(), lane = lane_id();
+  const int r0 = blockIdx.x * 256, r1 = min(n, r0 + 256);
+  __shared__ double red[2][4][WAVE];
+  for (int c0 = 0; c0 < L; c0 += WAVE) {
+    const int c = c0 + lane;
+    double rr = 0, bb = 0;
+    if (c < L) {
+      const double th = theta[c];
+      for (int i = r0 + w; i < r1; i += 4) {
+        const double b = BX[(size_t)i * L + c];
+        const double d = AX[(size_t)i * L + c] - th * b;
+        rr += d * d;
+        bb += b * b;
+      }
+    }
+    red[0][w][lane] = rr;
+    red[1][w][lane] = bb;
+    __syncthreads();
+    if (w == 0 && c < L) {
+      part[((size_t)blockIdx.x * 2 + 0) * L + c] = red[0][0][lane] + red[0][1][lane] + red[0][2][lane] + red[0][3][lane];
+      part[((size_t)blockIdx.x * 2 + 1) * L + c] = red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_resid_reduce(int L, int nrb, double* part) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * L) return;
+  const int which = e / L, c = e % L;
+  double s = 0;
+  for (int b = 0; b < nrb; ++b) s += part[((size_t)b * 2 + which) * L + c];
+  // the reduced sums go after the per-block partials
+  part[(size_t)nrb * 2 * L + e] = s;
+}
+
+void launch_resid(hipStream_t s, int n, int L, const double* AX, const double* BX, const double* theta,
+                  double* part, int nrb) {
+  k_resid<<<dim3(nrb), dim3(WG), 0, s>>>(n, L, AX, BX, theta, part);
+  k_resid_reduce<<<dim3((2 * L + 255) / 256), dim3(256), 0, s>>>(L, nrb, part);
+}
+
+// SplitMix64 + Box-Muller, element e of the stream for `seed`
+__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t idx) {
+  uint64_t z = seed + (idx + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_gaussian(int64_t count, uint64_t seed, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int64_t pair = e >> 1;
+  const double u1 = ((double)(splitmix(seed, 2 * pair) >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = ((double)(splitmix(seed, 2 * pair + 1) >> 11) + 1.0) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double t = 6.283185307179586476925 * u2;
+  out[e] = (e & 1) ? r * sin(t) : r * cos(t);
+}
+void launch_gaussian(hipStream_t s, int64_t count, uint64_t seed, double* out) {
+  k_gaussian<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s>>>(count, seed, out);
+}
+
+__global__ void k_fill_zero(uint32_t* p, size_t words) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < words) p[e] = 0;
+}
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
+  const size_t words = bytes / 4;
+  if (words) k_fill_zero<<<dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s>>>((uint32_t*)p, words);
+}
+
+// explicit instantiations
+#define SLRF_INST(R)                                                                                          \
+  template void launch_jacobi_diag<R>(hipStream_t, int, int, const R*, const R*, const cx<R>*, cx<R>*,     \
+                                      cx<R>*);                                                              \
+  template void launch_init<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const R*);                \
+  template void launch_init_scalars<R>(hipStream_t, const KGeom&, const KrylovState<R>&);                  \
+  template void launch_iteration<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const int*,          \
+                                    const int*, const ab_pair<R>*, R, int, bool);                          \
+  template void launch_filter_sum<R>(hipStream_t, int, int, int, const cx<R>*, const double*, double*,     \
+                                     bool);                                                                 \
+  template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \
+                                    const double*, double*, double*);
+SLRF_INST(double)
+SLRF_INST(float)
+
+}  // namespace slrf

@@ -1,0 +1,120 @@
+"""CPU checks of the compiled C-ABI library: exports, host-only entry points,
+argument validation.  No GPU compute is called here."""
+import ctypes as C
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pencils
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2503_21618_amd as m
+    return m
+
+
+def header_symbols(name="slrf.h"):
+    txt = open(os.path.join(ROOT, "include", name)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(slrf_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = header_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(lib._lib, s), s
+    assert set(syms) == set(lib.EXPORTED)
+    tsyms = header_symbols("slrf_testing.h")
+    assert set(tsyms) == set(lib.TESTING_EXPORTED)
+    for s in tsyms:
+        assert hasattr(lib._lib, s), s
+
+
+def test_default_options(lib):
+    o = lib.default_options()
+    assert o.precision == lib.FP64 and o.inner_maxit == 1000 and o.outer_tol == 1e-8
+
+
+@pytest.mark.parametrize("N", [4, 6])
+def test_design_matches_oracle_tables(lib, N):
+    """Product pole design (host C++) vs the oracle's design (stored tables)."""
+    with open(os.path.join(GOLDEN, f"poles_N{N}_a1_b0.01.json")) as f:
+        d = json.load(f)
+    s_or = np.array(d["sigma_re"]) + 1j * np.array(d["sigma_im"])
+    w_or = np.array(d["w_re"]) + 1j * np.array(d["w_im"])
+    s, w, sep = lib.design_poles(N, 1.0, 0.01, 1.0)
+    from oracle import poles
+    rows = poles.trapezoid_rows(0.01)
+    J_prod = poles.objective(s.real, 1.0, rows)
+    J_or = poles.objective(s_or.real, 1.0, rows)
+    # same local optimum: objective within 1e-9 relative, poles and weights close
+    assert abs(J_prod - J_or) <= 1e-9 * J_or
+    assert np.abs(s - s_or).max() < 1e-4
+    assert np.abs(w - w_or).max() < 1e-3 * np.abs(w_or).max()
+    assert abs(sep - d["separation_factor"]) < 1e-3 * d["separation_factor"]
+
+
+def test_design_gamma_scaling(lib):
+    s1, w1, _ = lib.design_poles(2, 1.0, 0.01, 1.0)
+    s2, w2, _ = lib.design_poles(2, 1.0, 0.01, 421.0)
+    assert np.abs(s2 / 421.0 - s1).max() < 1e-14
+    assert np.abs(w2 / 421.0 - w1).max() < 1e-14
+    assert np.all(s1.imag == s1.real)  # alpha = 1 line
+
+
+def test_design_rejects_bad_args(lib):
+    for args in [(0, 1.0, 0.01, 1.0), (2, -1.0, 0.01, 1.0), (2, 1.0, 0.0, 1.0), (2, 1.0, 0.01, 0.0)]:
+        with pytest.raises(lib.SlrfError):
+            lib.design_poles(*args)
+
+
+def test_workspace_bytes_monotone(lib):
+    a = lib.workspace_bytes(1000, 3000, 16, 2)
+    b = lib.workspace_bytes(1000, 3000, 32, 2)
+    c = lib.workspace_bytes(1000, 3000, 32, 4)
+    assert 0 < a < b < c
+    with pytest.raises(lib.SlrfError):
+        lib.workspace_bytes(0, 3000, 16, 2)
+
+
+def _create(lib, A, B, ws_ptr=0x100000, ws_bytes=1 << 40):
+    """slrf_create with a fake device pointer: validation runs before any device use."""
+    arrs = [np.ascontiguousarray(x) for x in (
+        A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64),
+        B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64))]
+    h = C.c_void_p()
+    opt = lib.default_options()
+    st = lib._lib.slrf_create(C.byref(h), A.shape[0], *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                              C.c_void_p(ws_ptr), ws_bytes, 8, 2, C.byref(opt), None)
+    msg = lib._lib.slrf_last_error(h).decode() if h else ""
+    if h:
+        lib._lib.slrf_destroy(h)
+    return st, msg
+
+
+def test_create_rejects_bad_matrices(lib):
+    p = pencils.string_1d(20)
+    B0 = p.B.copy()
+    B0.data[B0.indptr[3]:B0.indptr[4]] *= 0.0          # zero row => zero diagonal
+    st, msg = _create(lib, p.A, B0)
+    assert st == 2 and "diagonal" in msg
+    An = p.A.copy()
+    An.data[5] = np.nan
+    st, msg = _create(lib, An, p.B)
+    assert st == 1 and "non-finite" in msg
+    Au = p.A.copy()
+    Au.indices[Au.indptr[5]], Au.indices[Au.indptr[5] + 1] = Au.indices[Au.indptr[5] + 1], Au.indices[Au.indptr[5]]
+    st, msg = _create(lib, Au, p.B)
+    assert st == 1 and "increasing" in msg
+    st, msg = _create(lib, p.A, p.B, ws_ptr=0x100001)
+    assert st == 3
+    st, msg = _create(lib, p.A, p.B, ws_bytes=1024)
+    assert st == 3 and "needs" in msg

@@ -15,24 +15,11 @@ import scipy.integrate as si
 import scipy.sparse as sp
 
 import pencils
+from closed_forms import closed_1d
 from oracle import dense, inertia, krylov, poles, subspace
 from oracle import filter as oflt
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-
-
-def closed_1d(n):
-    """Eigenpairs of the 1D linear-FE string, h = 1/(n+1):
-    lambda_k = (6/h^2)(1 - cos k pi h)/(2 + cos k pi h),
-    x_k(i) = sin(k pi i h) / sqrt((h/6)(4 + 2 cos k pi h)(n+1)/2)  (B-normalised)."""
-    h = 1.0 / (n + 1)
-    k = np.arange(1, n + 1)
-    c = np.cos(k * np.pi * h)
-    one_minus_c = 2.0 * np.sin(0.5 * k * np.pi * h) ** 2   # 1 - cos, without cancellation
-    lam = (6.0 / h ** 2) * one_minus_c / (2 + c)
-    i = np.arange(1, n + 1)
-    X = np.sin(np.outer(i, k) * np.pi * h) / np.sqrt((h / 6) * (4 + 2 * c) * (n + 1) / 2)
-    return lam, X
 
 
 def golden_poles(N, gamma=1.0):
