@@ -71,6 +71,10 @@ typedef struct {
   int32_t outer_maxit; /* outer (subspace) iteration limit */
   int32_t check_every; /* inner iterations between host polls of the convergence count */
   uint64_t seed;       /* SplitMix64 seed of the Gaussian start block when V0 is NULL */
+  int32_t precond;     /* preconditioner M_j of the shifted operator A - sigma_j B:
+                          0 auto: ILU(0) if the merged pattern has nnz <= 5 n, else Jacobi
+                          1 point Jacobi, M_j = diag(A) - sigma_j diag(B)
+                          2 ILU(0) on the merged pattern (requires nnz <= 5 n) */
 } slrf_options;
 
 typedef struct {
@@ -95,7 +99,7 @@ typedef struct {
 } slrf_solve_stats;
 
 /* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
- * outer_maxit 40, check_every 10, seed 1. */
+ * outer_maxit 40, check_every 10, seed 1, precond 0 (auto). */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance
@@ -121,7 +125,8 @@ slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz_union, int64_t L, int32_
  * pattern with (a_ij, b_ij) value pairs, and uploads it into the workspace.
  * d_workspace: device, 256-byte aligned, ws_bytes from slrf_workspace_bytes
  * with the largest L and N that later calls use.  hip_stream: a hipStream_t
- * (NULL = default stream).  opt may be NULL (defaults). */
+ * (NULL = default stream).  opt may be NULL (defaults).  On failure *out may
+ * still hold a context: read slrf_last_error(*out), then slrf_destroy(*out). */
 slrf_status slrf_create(slrf_ctx* out, int64_t n,
                         const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
                         const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
@@ -130,9 +135,8 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n,
 
 /* One filter application (Algorithm 1, the "Solve" loop and "Compute U"):
  *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
- * every (pole, column) system solved by right-preconditioned BiCGStab with the
- * point-Jacobi preconditioner diag(A) - sigma_j diag(B) of the shifted operator,
- * x_0 = 0 and shadow residual B X.  d_X, d_U: device (n, L) row-major float64
+ * every (pole, column) system solved by right-preconditioned BiCGStab (the
+ * preconditioner of slrf_options.precond), x_0 = 0 and shadow residual B X.  d_X, d_U: device (n, L) row-major float64
  * (may not alias).  stats may be NULL.  Returns SLRF_OK even if some columns hit
  * inner_maxit or broke down; stats reports them. */
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L,

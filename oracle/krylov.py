@@ -1,9 +1,12 @@
 """Right-preconditioned BiCGStab for the complex-shifted systems.  Test infrastructure.
 
 The paper solves each shifted system (A - sigma_j B) y = f with BiCGStab
-(van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992)), Sections 2 and 4.2.  Its
-preconditioner (ILU with a drop tolerance) is replaced here by point Jacobi of
-the shifted operator, M_j = diag(A) - sigma_j diag(B), applied on the right.
+(van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992)), Sections 2 and 4.2, with an
+ILU preconditioner of the shifted operator.  Two preconditioners M_j of
+S_j = A - sigma_j B are used here, both applied on the right:
+  * point Jacobi, M_j = diag(A) - sigma_j diag(B);
+  * ILU(0), M_j = L_j U_j with the sparsity pattern of S_j (no fill), which is
+    the exact LU factorisation when S_j is tridiagonal.
 
 Readings: the initial guess is x_0 = 0, so r_0 = f, and the shadow residual is
 r_hat = f (real when f = B X is real, shared by all poles).  Inner products are
@@ -32,7 +35,62 @@ def jacobi_diagonal(A, B, sigma: complex) -> np.ndarray:
     return A.diagonal().astype(np.complex128) - sigma * B.diagonal()
 
 
-def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None):
+def union_pattern(A, B):
+    """CSR pattern of A + B (union), sorted, as (indptr, indices)."""
+    P = (abs(A) + abs(B)).tocsr()
+    P.sort_indices()
+    return P.indptr, P.indices
+
+
+def ilu0(A, B, sigma: complex):
+    """ILU(0) of S = A - sigma B on the union pattern (IKJ variant):
+    for each row i and each k < i in the pattern, l_ik = s_ik / u_kk and
+    s_ij -= l_ik u_kj for every j > k with (i, j) and (k, j) in the pattern.
+    Returns (indptr, indices, values) with L (unit, strictly lower) and U
+    (upper with diagonal) stored together."""
+    indptr, indices = union_pattern(A, B)
+    n = A.shape[0]
+    Ad, Bd = A.tolil(), B.tolil()
+    rows = []
+    for i in range(n):
+        cols = indices[indptr[i]:indptr[i + 1]]
+        rows.append({int(j): complex(Ad[i, j]) - sigma * complex(Bd[i, j]) for j in cols})
+    for i in range(n):
+        ri = rows[i]
+        for k in sorted(c for c in ri if c < i):
+            ri[k] /= rows[k][k]
+            lik = ri[k]
+            for j, ukj in rows[k].items():
+                if j > k and j in ri:
+                    ri[j] -= lik * ukj
+    vals = np.array([rows[i][int(j)] for i in range(n) for j in indices[indptr[i]:indptr[i + 1]]])
+    return indptr, indices, vals
+
+
+def ilu0_solve(fac, Y):
+    """(L U)^{-1} Y by forward and backward substitution (Y is (n, m))."""
+    indptr, indices, vals = fac
+    n = len(indptr) - 1
+    Z = np.array(Y, dtype=np.complex128, copy=True)
+    for i in range(n):
+        for k in range(indptr[i], indptr[i + 1]):
+            j = indices[k]
+            if j < i:
+                Z[i] -= vals[k] * Z[j]
+    for i in range(n - 1, -1, -1):
+        d = None
+        for k in range(indptr[i], indptr[i + 1]):
+            j = indices[k]
+            if j > i:
+                Z[i] -= vals[k] * Z[j]
+            elif j == i:
+                d = vals[k]
+        Z[i] /= d
+    return Z
+
+
+def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None,
+             precond: str = "jacobi"):
     """Solve (A - sigma_c B) x_c = F[:, l(c)] for every pole and column.
 
     sigmas: N poles; F: (n, L) real.  Columns are ordered pole-major,
@@ -44,8 +102,20 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
     N = len(sigmas)
     K = N * L
     sig = np.repeat(np.asarray(sigmas, dtype=np.complex128), L)          # (K,)
-    D = np.stack([jacobi_diagonal(A, B, s) for s in sigmas], axis=1)      # (n, N)
-    Dc = np.repeat(D, L, axis=1)                                          # (n, K)
+    if precond == "jacobi":
+        D = np.stack([jacobi_diagonal(A, B, s) for s in sigmas], axis=1)  # (n, N)
+        Dc = np.repeat(D, L, axis=1)                                      # (n, K)
+
+        def Minv(Y):
+            return Y / Dc
+    elif precond == "ilu0":
+        facs = [ilu0(A, B, s) for s in sigmas]
+
+        def Minv(Y):
+            return np.concatenate([ilu0_solve(facs[j], Y[:, j * L:(j + 1) * L])
+                                   for j in range(N)], axis=1)
+    else:
+        raise ValueError(precond)
     f = np.tile(F, (1, N)).astype(np.complex128)                          # (n, K)
     rhat = np.tile(F, (1, N)).astype(np.float64)
 
@@ -70,7 +140,7 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
         rho = (rhat * r).sum(0)
         beta = (rho / rho_prev) * (alpha / omega)
         p = np.where(act, r + beta * (p - omega * v), p)
-        ph = p / Dc
+        ph = Minv(p)
         v = np.where(act, S(ph), v)
         rv = (rhat * v).sum(0)
         bad = act & ((rho == 0) | (rv == 0))
@@ -82,7 +152,7 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
         iters = np.where(act & ~bad, iters + 1, iters)
         flags = np.where(half, HALF_CONVERGED, np.where(bad, BREAKDOWN, flags))
         act = flags == ACTIVE
-        sh = s / Dc
+        sh = Minv(s)
         t = S(sh)
         tt = (np.abs(t) ** 2).sum(0)
         ts = (np.conj(t) * s).sum(0)

@@ -142,7 +142,7 @@ def design(N: int, alpha: float, beta: float, gamma: float = 1.0,
     for x0 in start_points(N):
         th0 = np.log(x0 / (1.0 - x0))
         r = least_squares(f, th0, method="lm", xtol=1e-13, ftol=1e-15, gtol=1e-15,
-                          max_nfev=400 * (N + 1))
+                          max_nfev=5000 * (N + 1))
         J = float(r.fun @ r.fun)
         if J < best_J:
             best, best_J = r, J

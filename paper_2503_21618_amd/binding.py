@@ -20,6 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 FP64, MIXED = 0, 1
+PRECOND_AUTO, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_DEVICE",
           5: "E_NOT_CONVERGED", 6: "E_SUBSPACE_TOO_SMALL", 7: "E_BREAKDOWN"}
 
@@ -27,7 +28,7 @@ STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_D
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("precond", C.c_int32)]
 
 
 class Poles(C.Structure):

@@ -52,6 +52,8 @@ struct KrylovState {
   cx<R>* v;
   cx<R>* sh;   // preconditioned half-step residual M^{-1} s
   cx<R>* t;
+  cx<R>* p;    // unpreconditioned search direction (general preconditioner only)
+  cx<R>* s;    // unpreconditioned half-step residual (general preconditioner only)
   const R* rhat;       // (n, L) shared shadow residual = right-hand side
   const cx<R>* d;      // (n, N) shifted-operator diagonal
   const cx<R>* dinv;   // (n, N) its inverse
@@ -69,6 +71,17 @@ struct KrylovState {
   int* iters;
 };
 
+// ILU(0) factors of A - sigma_j B on the merged pattern, one value array per pole
+// (L strictly lower with unit diagonal, U upper; the U diagonal is stored inverted).
+template <typename R>
+struct IluFactors {
+  const int* rowptr;
+  const int* col;
+  const int* diagpos;  // position of the diagonal entry in each row
+  const cx<R>* f;      // (N, nnz)
+  int64_t nnz;
+};
+
 // ---- launchers (stream-ordered) -----------------------------------------
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
@@ -80,7 +93,7 @@ void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st
 template <typename R>
 void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st,
                       const int* rowptr, const int* col, const ab_pair<R>* ab,
-                      R tol, int maxit, bool first);
+                      R tol, int maxit, bool first, const IluFactors<R>* ilu);
 void launch_count_active(hipStream_t s, int K, const int* flags, int* out);
 
 template <typename R>

@@ -187,7 +187,8 @@ __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const
     cx<R> t = shifted_row<R>(i, rowptr, col, ab, st.sh, g.K, p.c, p.valid, sig);
     if (p.valid) {
       st.t[(size_t)i * g.K + p.c] = t;
-      const cx<R> s = cmul(st.d[(size_t)i * g.N + pole], st.sh[(size_t)i * g.K + p.c]);
+      const size_t e = (size_t)i * g.K + p.c;
+      const cx<R> s = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], st.sh[e]);
       // conj(t) * s
       tsr += t.re * s.re + t.im * s.im;
       tsi += t.re * s.im - t.im * s.re;
@@ -199,7 +200,9 @@ __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const
   wg_store_partial<R>(tt, p, st.part_b, g.K);
 }
 
-// p_hat = (r + beta (d p_hat - omega v)) / d     (first iteration: r / d)
+// p = r + beta (p - omega v)  (first iteration: p = r).
+// Jacobi: p itself is not stored; p_hat = p / d with p = d p_hat.
+// General preconditioner: p is stored and p_hat is formed by the preconditioner.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int first) {
   BlockPos p;
@@ -211,17 +214,22 @@ __global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int
   const cx<R> beta = st.beta[p.c], omega = st.omega[p.c];
   for (int i = p.r0 + p.w; i < p.r1; i += 4) {
     const size_t e = (size_t)i * g.K + p.c;
-    const cx<R> di = st.dinv[(size_t)i * g.N + pole];
     cx<R> pn = st.r[e];
-    if (!first) {
-      const cx<R> dd = st.d[(size_t)i * g.N + pole];
-      pn = cadd(pn, cmul(beta, csub(cmul(dd, st.ph[e]), cmul(omega, st.v[e]))));
+    if (st.p) {
+      if (!first) pn = cadd(pn, cmul(beta, csub(st.p[e], cmul(omega, st.v[e]))));
+      st.p[e] = pn;
+    } else {
+      const cx<R> di = st.dinv[(size_t)i * g.N + pole];
+      if (!first) {
+        const cx<R> dd = st.d[(size_t)i * g.N + pole];
+        pn = cadd(pn, cmul(beta, csub(cmul(dd, st.ph[e]), cmul(omega, st.v[e]))));
+      }
+      st.ph[e] = cmul(pn, di);
     }
-    st.ph[e] = cmul(pn, di);
   }
 }
 
-// s = r - alpha v ; s_hat = s / d ; partial |s|^2
+// s = r - alpha v (Jacobi: s_hat = s / d is stored instead) ; partial |s|^2
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st) {
   BlockPos p;
@@ -236,13 +244,16 @@ __global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st) {
       const size_t e = (size_t)i * g.K + p.c;
       const cx<R> s = csub(st.r[e], cmul(alpha, st.v[e]));
       ss += s.re * s.re + s.im * s.im;
-      st.sh[e] = cmul(s, st.dinv[(size_t)i * g.N + pole]);
+      if (st.s)
+        st.s[e] = s;
+      else
+        st.sh[e] = cmul(s, st.dinv[(size_t)i * g.N + pole]);
     }
   }
   wg_store_partial<R>(ss, p, st.part_b, g.K);
 }
 
-// x += alpha p_hat + omega s_hat ; r = d s_hat - omega t ; partials (rhat, r), |r|^2
+// x += alpha p_hat + omega s_hat ; r = s - omega t ; partials (rhat, r), |r|^2
 // Columns that converged at the half step take x += alpha p_hat only.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int first) {
@@ -264,7 +275,8 @@ __global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int
       if (act) {
         const cx<R> sh = st.sh[e];
         x = cadd(x, cmul(omega, sh));
-        const cx<R> r = csub(cmul(st.d[(size_t)i * g.N + pole], sh), cmul(omega, st.t[e]));
+        const cx<R> sv = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], sh);
+        const cx<R> r = csub(sv, cmul(omega, st.t[e]));
         st.r[e] = r;
         const R rh = st.rhat[(size_t)i * g.L + l];
         rr += rh * r.re;
@@ -370,16 +382,57 @@ __global__ void k_sc_beta(KGeom g, KrylovState<R> st, R tol, int maxit) {
   st.rho[c] = rn;
 }
 
+// out = (L U)^{-1} in, one thread per column: forward then backward substitution
+// over the rows in order.  The previous row's result stays in a register, so a
+// tridiagonal factor has no memory dependence between rows.  Inactive columns
+// are skipped (their preconditioned vectors are not used).
+template <typename R>
+__global__ __launch_bounds__(64) void k_ilu_apply(int n, int K, int L, IluFactors<R> fac, const int* __restrict__ flags,
+                                                 const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K || flags[c] != COL_ACTIVE) return;
+  const cx<R>* f = fac.f + (size_t)(c / L) * fac.nnz;
+  cx<R> prev = {0, 0};
+  for (int i = 0; i < n; ++i) {
+    cx<R> y = in[(size_t)i * K + c];
+    const int kd = fac.diagpos[i];
+    for (int k = fac.rowptr[i]; k < kd; ++k) {
+      const int j = fac.col[k];
+      const cx<R> yj = (j == i - 1) ? prev : out[(size_t)j * K + c];
+      y = csub(y, cmul(f[k], yj));
+    }
+    out[(size_t)i * K + c] = y;
+    prev = y;
+  }
+  prev = {0, 0};
+  for (int i = n - 1; i >= 0; --i) {
+    cx<R> z = out[(size_t)i * K + c];
+    const int kd = fac.diagpos[i];
+    for (int k = kd + 1; k < fac.rowptr[i + 1]; ++k) {
+      const int j = fac.col[k];
+      const cx<R> zj = (j == i + 1) ? prev : out[(size_t)j * K + c];
+      z = csub(z, cmul(f[k], zj));
+    }
+    z = cmul(z, f[kd]);
+    out[(size_t)i * K + c] = z;
+    prev = z;
+  }
+}
+
 template <typename R>
 void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const int* rowptr,
-                      const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first) {
+                      const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first,
+                      const IluFactors<R>* ilu) {
   const dim3 grid((unsigned)g.padded), blk(WG);
   const dim3 cgrid((g.K + 255) / 256), cblk(256);
+  const dim3 igrid((g.K + 63) / 64), iblk(64);
   k_update_p<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
+  if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(g.n, g.K, g.L, *ilu, st.flags, st.p, st.ph);
   k_spmm_v<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
   k_sc_alpha<R><<<cgrid, cblk, 0, s>>>(g, st);
   k_update_s<R><<<grid, blk, 0, s>>>(g, st);
   k_sc_half<R><<<cgrid, cblk, 0, s>>>(g, st, tol);
+  if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(g.n, g.K, g.L, *ilu, st.flags, st.s, st.sh);
   k_spmm_t<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
   k_sc_omega<R><<<cgrid, cblk, 0, s>>>(g, st);
   k_update_x<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
@@ -756,7 +809,7 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
   template void launch_init<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const R*);                \
   template void launch_init_scalars<R>(hipStream_t, const KGeom&, const KrylovState<R>&);                  \
   template void launch_iteration<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const int*,          \
-                                    const int*, const ab_pair<R>*, R, int, bool);                          \
+                                    const int*, const ab_pair<R>*, R, int, bool, const IluFactors<R>*);    \
   template void launch_filter_sum<R>(hipStream_t, int, int, int, const cx<R>*, const double*, double*,     \
                                      bool);                                                                 \
   template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \

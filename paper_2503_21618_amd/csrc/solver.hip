@@ -49,11 +49,15 @@ struct DynLayout {
   size_t krylov64 = 0, outer = 0, total = 0;
 };
 
-size_t krylov_bytes_fp64(int64_t n, int64_t L, int64_t N) {
+// ILU(0) runs one thread per column over all rows: only for narrow patterns.
+bool ilu_allowed(int64_t n, int64_t nnz) { return nnz <= 5 * n; }
+
+size_t krylov_bytes_fp64(int64_t n, int64_t nnz, int64_t L, int64_t N) {
   const int64_t K = N * L;
   const int64_t nrb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
   size_t b = 0;
   b += 6 * al((size_t)n * K * 16);          // x r ph v sh t
+  if (ilu_allowed(n, nnz)) b += 2 * al((size_t)n * K * 16) + al((size_t)N * nnz * 16);  // p s factors
   b += al((size_t)n * L * 8);               // rhat = B X
   b += 2 * al((size_t)n * N * 16);          // d, dinv
   b += al((size_t)N * 16) + al((size_t)K * 16) + al((size_t)2 * N * 8);  // sigma, sigma_col, w
@@ -92,6 +96,11 @@ struct slrf_ctx_s {
   double* diagB = nullptr;
   std::string err;
   bool verbose = false;
+  bool use_ilu = false;
+  int* diagpos = nullptr;
+  // host copy of the merged CSR, kept for the per-pole ILU(0) factorisations
+  std::vector<int32_t> h_rp, h_cl, h_dpos;
+  std::vector<double> h_ab;
 };
 
 namespace {
@@ -109,7 +118,41 @@ slrf_status fail(slrf_ctx ctx, slrf_status s, const std::string& msg) {
   } while (0)
 
 size_t static_bytes_for(int64_t n, int64_t nnz) {
-  return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8);
+  return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8) +
+         al((size_t)n * 4);
+}
+
+// ILU(0) of A - sigma B on the merged pattern (row-wise IKJ elimination without
+// fill); the U diagonal is returned inverted.
+bool ilu0_factor(const slrf_ctx ctx, std::complex<double> sigma, std::vector<std::complex<double>>& f) {
+  const int64_t n = ctx->n, nnz = ctx->nnz;
+  const auto& rp = ctx->h_rp;
+  const auto& cl = ctx->h_cl;
+  const auto& dp = ctx->h_dpos;
+  f.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) f[k] = std::complex<double>(ctx->h_ab[2 * k], 0.0) - sigma * ctx->h_ab[2 * k + 1];
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t k = rp[i]; k < dp[i]; ++k) {
+      const int32_t c = cl[k];
+      f[k] /= f[dp[c]];
+      const std::complex<double> lik = f[k];
+      int32_t a = k + 1, b = dp[c] + 1;
+      while (a < rp[i + 1] && b < rp[c + 1]) {
+        if (cl[a] == cl[b]) {
+          f[a] -= lik * f[b];
+          ++a;
+          ++b;
+        } else if (cl[a] < cl[b]) {
+          ++a;
+        } else {
+          ++b;
+        }
+      }
+    }
+    if (std::abs(f[dp[i]]) == 0.0 || !std::isfinite(std::abs(f[dp[i]]))) return false;
+  }
+  for (int64_t i = 0; i < n; ++i) f[dp[i]] = 1.0 / f[dp[i]];
+  return true;
 }
 
 std::mutex g_design_mu;
@@ -163,6 +206,12 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   st.v = cv.take<cx<double>>((size_t)n * K);
   st.sh = cv.take<cx<double>>((size_t)n * K);
   st.t = cv.take<cx<double>>((size_t)n * K);
+  cx<double>* fac = nullptr;
+  if (ctx->use_ilu) {
+    st.p = cv.take<cx<double>>((size_t)n * K);
+    st.s = cv.take<cx<double>>((size_t)n * K);
+    fac = cv.take<cx<double>>((size_t)N * ctx->nnz);
+  }
   double* rhat = cv.take<double>((size_t)n * L);
   cx<double>* d = cv.take<cx<double>>((size_t)n * N);
   cx<double>* dinv = cv.take<cx<double>>((size_t)n * N);
@@ -199,6 +248,19 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   HIPCHK(ctx, hipMemcpyAsync(sigc, hsigc.data(), 16 * (size_t)K, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemcpyAsync(w, poles->weight, 16 * N, hipMemcpyHostToDevice, s));
 
+  IluFactors<double> ilu{};
+  std::vector<std::complex<double>> hf;
+  if (ctx->use_ilu) {
+    hf.resize((size_t)N * ctx->nnz);
+    std::vector<std::complex<double>> fj;
+    for (int j = 0; j < N; ++j) {
+      if (!ilu0_factor(ctx, {poles->sigma[2 * j], poles->sigma[2 * j + 1]}, fj))
+        return fail(ctx, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
+      std::copy(fj.begin(), fj.end(), hf.begin() + (size_t)j * ctx->nnz);
+    }
+    HIPCHK(ctx, hipMemcpyAsync(fac, hf.data(), 16 * hf.size(), hipMemcpyHostToDevice, s));
+    ilu = {ctx->rowptr, ctx->col, ctx->diagpos, fac, ctx->nnz};
+  }
   launch_jacobi_diag<double>(s, n, N, ctx->diagA, ctx->diagB, sig, d, dinv);
   launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, X, nullptr, rhat);
   launch_init<double>(s, g, st, rhat);
@@ -212,7 +274,8 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   while (it < maxit) {
     const int chunk = std::min(every, maxit - it);
     for (int q = 0; q < chunk; ++q, ++it)
-      launch_iteration<double>(s, g, st, ctx->rowptr, ctx->col, ctx->ab64, tol, maxit, it == 0);
+      launch_iteration<double>(s, g, st, ctx->rowptr, ctx->col, ctx->ab64, tol, maxit, it == 0,
+                               ctx->use_ilu ? &ilu : nullptr);
     launch_count_active(s, K, st.flags, d_count);
     HIPCHK(ctx, hipGetLastError());
     int active = 0;
@@ -287,6 +350,7 @@ void slrf_default_options(slrf_options* o) {
   o->outer_maxit = 40;
   o->check_every = 10;
   o->seed = 1;
+  o->precond = 0;
 }
 
 const char* slrf_status_string(slrf_status s) {
@@ -328,7 +392,7 @@ slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma
 slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
   if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
   if (precision != SLRF_FP64) return SLRF_E_INVALID_ARG;
-  *bytes = static_bytes_for(n, nnz) + krylov_bytes_fp64(n, L, N) + outer_bytes(n, L);
+  *bytes = static_bytes_for(n, nnz) + krylov_bytes_fp64(n, nnz, L, N) + outer_bytes(n, L);
   return SLRF_OK;
 }
 
@@ -372,7 +436,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (!m1.empty()) return bail(SLRF_E_INVALID_ARG, m1);
   std::string m2 = check_csr(b_rowptr, b_col, b_val, "B");
   if (!m2.empty()) return bail(SLRF_E_INVALID_ARG, m2);
-  std::vector<int32_t> rp(n + 1, 0), cl;
+  std::vector<int32_t> rp(n + 1, 0), cl, dpos(n, -1);
   std::vector<double> ab, dA(n, 0.0), dB(n, 0.0);
   cl.reserve(std::max(a_rowptr[n], b_rowptr[n]));
   ab.reserve(2 * (size_t)std::max(a_rowptr[n], b_rowptr[n]));
@@ -390,6 +454,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
       if (c == i) {
         dA[i] = va;
         dB[i] = vb;
+        dpos[i] = (int32_t)cl.size() - 1;
       }
     }
     rp[i + 1] = (int32_t)cl.size();
@@ -399,6 +464,10 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
       return bail(SLRF_E_NOT_SPD, "row " + std::to_string(i) + ": diagonal of A or B not positive");
   const int64_t nnz = (int64_t)cl.size();
   ctx->nnz = nnz;
+  if (ctx->opt.precond < 0 || ctx->opt.precond > 2) return bail(SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (ctx->opt.precond == 2 && !ilu_allowed(n, nnz))
+    return bail(SLRF_E_INVALID_ARG, "ILU(0) needs a narrow pattern (nnz <= 5 n)");
+  ctx->use_ilu = ctx->opt.precond == 2 || (ctx->opt.precond == 0 && ilu_allowed(n, nnz));
   if (((uintptr_t)d_workspace & 255) != 0 || !d_workspace) return bail(SLRF_E_WORKSPACE, "workspace not 256-byte aligned");
   size_t need = 0;
   if (slrf_workspace_bytes(n, nnz, max_L, max_N, ctx->opt.precision, &need) != SLRF_OK)
@@ -413,13 +482,21 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   ctx->ab64 = cv.take<ab_pair<double>>(nnz);
   ctx->diagA = cv.take<double>(n);
   ctx->diagB = cv.take<double>(n);
+  ctx->diagpos = cv.take<int>(n);
   ctx->static_bytes = cv.off;
   hipStream_t s = ctx->stream;
   auto cp = [&](void* dst, const void* src, size_t b) { return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s); };
   if (cp(ctx->rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(ctx->col, cl.data(), 4 * nnz) != hipSuccess ||
       cp(ctx->ab64, ab.data(), 16 * nnz) != hipSuccess || cp(ctx->diagA, dA.data(), 8 * n) != hipSuccess ||
-      cp(ctx->diagB, dB.data(), 8 * n) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      cp(ctx->diagB, dB.data(), 8 * n) != hipSuccess || cp(ctx->diagpos, dpos.data(), 4 * n) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
     return bail(SLRF_E_DEVICE, "upload of the merged CSR failed");
+  if (ctx->use_ilu) {
+    ctx->h_rp = std::move(rp);
+    ctx->h_cl = std::move(cl);
+    ctx->h_ab = std::move(ab);
+    ctx->h_dpos = std::move(dpos);
+  }
   *out = ctx;
   return SLRF_OK;
 }
@@ -461,7 +538,7 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
   if (st != SLRF_OK) return st;
   hipStream_t s = ctx->stream;
   // outer buffers sit after the Krylov region sized for max_L, max_N
-  Carver co{ctx->ws, ctx->static_bytes + krylov_bytes_fp64(n, ctx->max_L, ctx->max_N), ctx->ws_bytes};
+  Carver co{ctx->ws, ctx->static_bytes + krylov_bytes_fp64(n, ctx->nnz, ctx->max_L, ctx->max_N), ctx->ws_bytes};
   const int nch = gram_chunks(n, L);
   const int nrr = (n + 255) / 256;
   double* V = co.take<double>((size_t)n * L);

@@ -214,3 +214,27 @@ def test_mfma_gemm_kernel(slrf, torch, n, L, r):
     e = np.abs(Y.cpu().numpy() - X @ Z).max()
     say(f"  err {e:.2e}")
     assert e < 1e-12 * L * 10
+
+
+@pytest.mark.parametrize("iters", [1, 2, 5])
+def test_bicgstab_ilu0_iterates_match_oracle(slrf, torch, iters):
+    """ILU(0)-preconditioned iterates (narrow pattern) against the oracle's."""
+    n, L = 517, 40
+    p = pencils.string_1d(n)
+    lam, _ = closed_1d(n)
+    sig, w = golden_poles(4, 0.5 * (lam[9] + lam[10]))
+    sig, w = sig[:3], w[:3]
+    X = pencils.start_block(n, L, 8)
+    # bands at +-3 (nnz <= 5 n): ILU(0) drops the fill at +-2, so it is not exact
+    import scipy.sparse as sp
+    A = (p.A + sp.diags([np.full(n - 3, -0.1 * (n + 1))] * 2, [-3, 3])).tocsr()
+    say(f"case ilu0 iterates iters={iters}")
+    opt = slrf.default_options(inner_tol=0.0, inner_maxit=iters, check_every=1, precond=2)
+    s = slrf.Solver(A, p.B, max_L=L, max_poles=3, options=opt)
+    U, st = s.filter_apply(torch.from_numpy(X).cuda(), sig, w)
+    x, it, fl, _ = krylov.bicgstab(A, p.B, sig, p.B @ X, 0.0, iters, fixed_iters=iters, precond="ilu0")
+    Uo = sum(2.0 * np.real(w[j] * x[:, j * L:(j + 1) * L]) for j in range(3))
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    say(f"  rel err {err:.3e}, its {st['max_iterations']}")
+    assert st["max_iterations"] == iters
+    assert err < max(1e-12, 1e-13 * 3.0 ** iters)

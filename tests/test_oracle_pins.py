@@ -177,6 +177,46 @@ def test_bicgstab_closed_form_rhs():
     assert np.abs(x - expect).max() < 1e-9 * np.abs(expect).max()
 
 
+def test_ilu0_defining_property_and_exactness():
+    """ILU(0): (L U)_ij = S_ij on the pattern of S; exact LU for a tridiagonal S."""
+    q = pencils.scalar_q1(5, 3, 0.5, 3)
+    sig = 120.0 * (1 + 1j)
+    indptr, indices, vals = krylov.ilu0(q.A, q.B, sig)
+    n = q.n
+    Lm = np.eye(n, dtype=complex)
+    Um = np.zeros((n, n), dtype=complex)
+    for i in range(n):
+        for k in range(indptr[i], indptr[i + 1]):
+            j = indices[k]
+            if j < i:
+                Lm[i, j] = vals[k]
+            else:
+                Um[i, j] = vals[k]
+    S = (q.A - sig * q.B).toarray()
+    P = Lm @ Um
+    mask = np.zeros((n, n), bool)
+    for i in range(n):
+        mask[i, indices[indptr[i]:indptr[i + 1]]] = True
+    assert np.abs((P - S)[mask]).max() < 1e-12 * np.abs(S).max()
+    assert np.abs((P - S)[~mask]).max() > 1e-6 * np.abs(S).max()   # dropped fill is real
+    p = pencils.string_1d(60)
+    fac = krylov.ilu0(p.A, p.B, sig)
+    x = np.random.default_rng(1).standard_normal((60, 2))
+    y = krylov.ilu0_solve(fac, (p.A - sig * p.B) @ x)
+    assert np.abs(y - x).max() < 1e-12
+
+
+def test_bicgstab_ilu0_tridiagonal_converges_at_once():
+    n = 2000
+    p = pencils.c1_string()
+    lam, _ = closed_1d(n)
+    gamma = 0.5 * (lam[19] + lam[20])
+    s, w, _ = golden_poles(4, gamma)
+    F = p.B @ pencils.start_block(n, 3, 1)
+    x, it, fl, rr = krylov.bicgstab(p.A, p.B, s, F, 1e-12, 50, precond="ilu0")
+    assert it.max() == 1 and rr.max() < 1e-12
+
+
 def test_bicgstab_alpha_trend():
     """Iterations fall as the pole moves away from the real axis (Table 1 trend)."""
     q = pencils.scalar_q1(10, 3, 0.5, 3)
