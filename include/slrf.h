@@ -75,6 +75,9 @@ typedef struct {
                           0 auto: ILU(0) if the merged pattern has nnz <= 5 n, else Jacobi
                           1 point Jacobi, M_j = diag(A) - sigma_j diag(B)
                           2 ILU(0) on the merged pattern (requires nnz <= 5 n) */
+  int32_t profile;     /* 1: time the sparse-product and vector-update kernels with HIP
+                          events and count the column tiles each launch processes
+                          (stats fields spmm_* and update_*); 0: off */
 } slrf_options;
 
 typedef struct {
@@ -87,6 +90,16 @@ typedef struct {
   int32_t refinements;      /* MIXED: defect-correction rounds used */
   double max_relres;        /* largest final relative residual over the columns */
   double seconds;           /* wall time of the call */
+  /* profile = 1 only (else 0): kernel time from HIP events, launches, and the
+   * algorithmic HBM bytes of those launches (each processed column tile reads
+   * its input block and writes its output block once; the merged CSR is read
+   * once per launch) */
+  double spmm_seconds;
+  int64_t spmm_launches;
+  double spmm_bytes;
+  double update_seconds;
+  int64_t update_launches;
+  double update_bytes;
 } slrf_filter_stats;
 
 typedef struct {
@@ -96,10 +109,12 @@ typedef struct {
   double max_resid;         /* largest rho_i over those pairs */
   double seconds;           /* wall time of the call */
   double filter_seconds;    /* of which in filter application */
+  double inner_iterations;  /* mean BiCGStab iterations per (pole, column), all outer its */
+  slrf_filter_stats kernels;/* profile = 1: spmm_* / update_* summed over the call */
 } slrf_solve_stats;
 
 /* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
- * outer_maxit 40, check_every 10, seed 1, precond 0 (auto). */
+ * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0. */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance

@@ -28,7 +28,7 @@ STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_D
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
-                ("seed", C.c_uint64), ("precond", C.c_int32)]
+                ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32)]
 
 
 class Poles(C.Structure):
@@ -39,7 +39,10 @@ class Poles(C.Structure):
 class FilterStats(C.Structure):
     _fields_ = [("max_iterations", C.c_int32), ("mean_iterations", C.c_double), ("spmv", C.c_int64),
                 ("n_breakdown", C.c_int32), ("n_maxit", C.c_int32), ("refinements", C.c_int32),
-                ("max_relres", C.c_double), ("seconds", C.c_double)]
+                ("max_relres", C.c_double), ("seconds", C.c_double),
+                ("spmm_seconds", C.c_double), ("spmm_launches", C.c_int64), ("spmm_bytes", C.c_double),
+                ("update_seconds", C.c_double), ("update_launches", C.c_int64),
+                ("update_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -47,10 +50,13 @@ class FilterStats(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("outer_iterations", C.c_int32), ("spmv_total", C.c_int64), ("n_found", C.c_int32),
-                ("max_resid", C.c_double), ("seconds", C.c_double), ("filter_seconds", C.c_double)]
+                ("max_resid", C.c_double), ("seconds", C.c_double), ("filter_seconds", C.c_double),
+                ("inner_iterations", C.c_double), ("kernels", FilterStats)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["kernels"] = self.kernels.as_dict()
+        return d
 
 
 _P = C.c_void_p

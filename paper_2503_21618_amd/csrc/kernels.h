@@ -82,6 +82,27 @@ struct IluFactors {
   int64_t nnz;
 };
 
+// Optional per-launch instrumentation of the Krylov kernels: a HIP event pair
+// around each sparse-product / vector-update launch and a device counter of the
+// column tiles the launch processed (tiles whose columns are all converged exit
+// at once).  Host-side records say which kernel and how many n x K passes it
+// makes per processed tile.
+struct LaunchTimer {
+  hipEvent_t* events = nullptr;  // 2 * capacity
+  int* d_counts = nullptr;       // capacity
+  int capacity = 0;
+  int used = 0;
+  struct Rec {
+    int kind;           // 0 sparse product, 1 vector update
+    double tile_bytes;  // bytes of a launch that processes every tile (scale with tiles)
+    double fixed;       // bytes read once per launch whatever the tiles (merged CSR)
+  };
+  Rec recs[512];
+  // returns the counter for the next launch (records its start event) or nullptr
+  int* begin(hipStream_t s, int kind, double tile_bytes, double fixed);
+  void end(hipStream_t s);
+};
+
 // ---- launchers (stream-ordered) -----------------------------------------
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
@@ -93,7 +114,8 @@ void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st
 template <typename R>
 void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st,
                       const int* rowptr, const int* col, const ab_pair<R>* ab,
-                      R tol, int maxit, bool first, const IluFactors<R>* ilu);
+                      R tol, int maxit, bool first, const IluFactors<R>* ilu,
+                      LaunchTimer* timer, double matrix_bytes);
 void launch_count_active(hipStream_t s, int K, const int* flags, int* out);
 
 template <typename R>

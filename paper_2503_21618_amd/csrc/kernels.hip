@@ -91,6 +91,11 @@ __device__ __forceinline__ bool tile_has(const int* flags, const BlockPos& p, in
   return __any(f == s0 || f == s1);
 }
 
+// one vector atomic per processed workgroup when instrumented
+__device__ __forceinline__ void count_tile(int* counter) {
+  if (counter && threadIdx.x == 0) atomicAdd(counter, 1);
+}
+
 template <typename T>
 __device__ __forceinline__ void wg_store_partial(T v, const BlockPos& p, T* out, int K) {
   __shared__ T red[4][WAVE];
@@ -153,10 +158,11 @@ __device__ __forceinline__ cx<R> shifted_row(int i, const int* __restrict__ rowp
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_v(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
                                               const int* __restrict__ col,
-                                              const ab_pair<R>* __restrict__ ab) {
+                                              const ab_pair<R>* __restrict__ ab, int* counter) {
   BlockPos p;
   if (!block_pos(g, p)) return;
   if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  count_tile(counter);
   const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
   const int l = p.c % g.L;
   R dr = 0, di = 0;
@@ -176,10 +182,11 @@ __global__ __launch_bounds__(WG) void k_spmm_v(KGeom g, KrylovState<R> st, const
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
                                               const int* __restrict__ col,
-                                              const ab_pair<R>* __restrict__ ab) {
+                                              const ab_pair<R>* __restrict__ ab, int* counter) {
   BlockPos p;
   if (!block_pos(g, p)) return;
   if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  count_tile(counter);
   const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
   const int pole = p.c / g.L;
   R tsr = 0, tsi = 0, tt = 0;
@@ -204,10 +211,11 @@ __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const
 // Jacobi: p itself is not stored; p_hat = p / d with p = d p_hat.
 // General preconditioner: p is stored and p_hat is formed by the preconditioner.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int first) {
+__global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int first, int* counter) {
   BlockPos p;
   if (!block_pos(g, p)) return;
   if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  count_tile(counter);
   const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
   if (!act) return;
   const int pole = p.c / g.L;
@@ -231,10 +239,11 @@ __global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int
 
 // s = r - alpha v (Jacobi: s_hat = s / d is stored instead) ; partial |s|^2
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st) {
+__global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st, int* counter) {
   BlockPos p;
   if (!block_pos(g, p)) return;
   if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
+  count_tile(counter);
   const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
   const int pole = p.c / g.L;
   const cx<R> alpha = act ? st.alpha[p.c] : cx<R>{0, 0};
@@ -256,10 +265,11 @@ __global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st) {
 // x += alpha p_hat + omega s_hat ; r = s - omega t ; partials (rhat, r), |r|^2
 // Columns that converged at the half step take x += alpha p_hat only.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int first) {
+__global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int first, int* counter) {
   BlockPos p;
   if (!block_pos(g, p)) return;
   if (!tile_has(st.flags, p, COL_ACTIVE, COL_HALF_PENDING)) return;
+  count_tile(counter);
   const int f = p.valid ? st.flags[p.c] : -1;
   const bool act = f == COL_ACTIVE, half = f == COL_HALF_PENDING;
   const int pole = p.c / g.L;
@@ -419,23 +429,53 @@ __global__ __launch_bounds__(64) void k_ilu_apply(int n, int K, int L, IluFactor
   }
 }
 
+int* LaunchTimer::begin(hipStream_t s, int kind, double tile_bytes, double fixed) {
+  if (used >= capacity || used >= 512) return nullptr;
+  recs[used] = {kind, tile_bytes, fixed};
+  (void)hipEventRecord(events[2 * used], s);
+  return d_counts + used;
+}
+void LaunchTimer::end(hipStream_t s) {
+  (void)hipEventRecord(events[2 * used + 1], s);
+  ++used;
+}
+
 template <typename R>
 void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const int* rowptr,
                       const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first,
-                      const IluFactors<R>* ilu) {
+                      const IluFactors<R>* ilu, LaunchTimer* tm, double matrix_bytes) {
   const dim3 grid((unsigned)g.padded), blk(WG);
   const dim3 cgrid((g.K + 255) / 256), cblk(256);
   const dim3 igrid((g.K + 63) / 64), iblk(64);
-  k_update_p<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
+  // algorithmic traffic: n x K complex passes per fully processed launch, plus
+  // per-launch fixed bytes (merged CSR; shared real rhat (n, L); diagonals (n, N))
+  const double blk_b = (double)g.n * g.K * 2 * sizeof(R);
+  const double rhat_b = (double)g.n * g.L * sizeof(R), diag_b = (double)g.n * g.N * 2 * sizeof(R);
+  const bool jac = st.p == nullptr;
+  int* c;
+  // p update: read r (p, v), write p_hat or p; Jacobi reads d and 1/d
+  c = tm ? tm->begin(s, 1, (first ? 2 : 4) * blk_b + (jac ? 2 * diag_b : 0), 0) : nullptr;
+  k_update_p<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0, c);
+  if (c) tm->end(s);
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(g.n, g.K, g.L, *ilu, st.flags, st.p, st.ph);
-  k_spmm_v<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
+  // v = S p_hat: gather p_hat once, write v, read rhat; the merged CSR once per launch
+  c = tm ? tm->begin(s, 0, 2 * blk_b + rhat_b, matrix_bytes) : nullptr;
+  k_spmm_v<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab, c);
+  if (c) tm->end(s);
   k_sc_alpha<R><<<cgrid, cblk, 0, s>>>(g, st);
-  k_update_s<R><<<grid, blk, 0, s>>>(g, st);
+  c = tm ? tm->begin(s, 1, 3 * blk_b + (jac ? diag_b : 0), 0) : nullptr;
+  k_update_s<R><<<grid, blk, 0, s>>>(g, st, c);
+  if (c) tm->end(s);
   k_sc_half<R><<<cgrid, cblk, 0, s>>>(g, st, tol);
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(g.n, g.K, g.L, *ilu, st.flags, st.s, st.sh);
-  k_spmm_t<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab);
+  c = tm ? tm->begin(s, 0, (jac ? 2 : 3) * blk_b + (jac ? diag_b : 0), matrix_bytes) : nullptr;
+  k_spmm_t<R><<<grid, blk, 0, s>>>(g, st, rowptr, col, ab, c);
+  if (c) tm->end(s);
   k_sc_omega<R><<<cgrid, cblk, 0, s>>>(g, st);
-  k_update_x<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0);
+  c = tm ? tm->begin(s, 1, (first ? 5 : 6) * blk_b + (jac ? 0 : blk_b) + rhat_b + (jac ? diag_b : 0), 0)
+         : nullptr;
+  k_update_x<R><<<grid, blk, 0, s>>>(g, st, first ? 1 : 0, c);
+  if (c) tm->end(s);
   k_sc_beta<R><<<cgrid, cblk, 0, s>>>(g, st, tol, maxit);
 }
 
@@ -809,7 +849,8 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
   template void launch_init<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const R*);                \
   template void launch_init_scalars<R>(hipStream_t, const KGeom&, const KrylovState<R>&);                  \
   template void launch_iteration<R>(hipStream_t, const KGeom&, const KrylovState<R>&, const int*,          \
-                                    const int*, const ab_pair<R>*, R, int, bool, const IluFactors<R>*);    \
+                                    const int*, const ab_pair<R>*, R, int, bool, const IluFactors<R>*,     \
+                                    LaunchTimer*, double);                                                 \
   template void launch_filter_sum<R>(hipStream_t, int, int, int, const cx<R>*, const double*, double*,     \
                                      bool);                                                                 \
   template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \

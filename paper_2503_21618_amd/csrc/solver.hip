@@ -101,6 +101,12 @@ struct slrf_ctx_s {
   // host copy of the merged CSR, kept for the per-pole ILU(0) factorisations
   std::vector<int32_t> h_rp, h_cl, h_dpos;
   std::vector<double> h_ab;
+  LaunchTimer timer;
+  std::vector<hipEvent_t> events;
+  ~slrf_ctx_s() {
+    for (hipEvent_t e : events)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -117,9 +123,43 @@ slrf_status fail(slrf_ctx ctx, slrf_status s, const std::string& msg) {
       return fail(ctx, SLRF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+constexpr int kTimerSlots = 512;
+
 size_t static_bytes_for(int64_t n, int64_t nnz) {
   return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8) +
-         al((size_t)n * 4);
+         al((size_t)n * 4) + al(kTimerSlots * 4);
+}
+
+double merged_csr_bytes(const slrf_ctx ctx, size_t value_bytes) {
+  return (double)(ctx->n + 1) * 4 + (double)ctx->nnz * (4 + value_bytes);
+}
+
+// Reads back the event pairs and tile counters of the current window into the
+// kernel statistics, then clears the window.
+slrf_status harvest_timer(slrf_ctx ctx, int64_t total_tiles, slrf_filter_stats* fs) {
+  LaunchTimer& tm = ctx->timer;
+  if (tm.used == 0) return SLRF_OK;
+  std::vector<int> cnt(tm.used);
+  HIPCHK(ctx, hipMemcpyAsync(cnt.data(), tm.d_counts, 4 * (size_t)tm.used, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (int u = 0; u < tm.used; ++u) {
+    float ms = 0;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, tm.events[2 * u], tm.events[2 * u + 1]));
+    const LaunchTimer::Rec& r = tm.recs[u];
+    const double bytes = r.tile_bytes * (double)cnt[u] / (double)total_tiles + (cnt[u] > 0 ? r.fixed : 0.0);
+    if (r.kind == 0) {
+      fs->spmm_seconds += 1e-3 * ms;
+      fs->spmm_launches += 1;
+      fs->spmm_bytes += bytes;
+    } else {
+      fs->update_seconds += 1e-3 * ms;
+      fs->update_launches += 1;
+      fs->update_bytes += bytes;
+    }
+  }
+  tm.used = 0;
+  launch_fill_zero(ctx->stream, tm.d_counts, 4 * (size_t)tm.capacity);
+  return SLRF_OK;
 }
 
 // ILU(0) of A - sigma B on the merged pattern (row-wise IKJ elimination without
@@ -268,19 +308,26 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   HIPCHK(ctx, hipGetLastError());
 
   const int maxit = std::max(1, ctx->opt.inner_maxit);
-  const int every = std::max(1, ctx->opt.check_every);
+  const int every = std::max(1, std::min(ctx->opt.check_every, 64));
   const double tol = ctx->opt.inner_tol;
+  LaunchTimer* tm = ctx->opt.profile ? &ctx->timer : nullptr;
+  const double mbytes = merged_csr_bytes(ctx, 16);
+  slrf_filter_stats ks{};
   int it = 0;
   while (it < maxit) {
     const int chunk = std::min(every, maxit - it);
     for (int q = 0; q < chunk; ++q, ++it)
       launch_iteration<double>(s, g, st, ctx->rowptr, ctx->col, ctx->ab64, tol, maxit, it == 0,
-                               ctx->use_ilu ? &ilu : nullptr);
+                               ctx->use_ilu ? &ilu : nullptr, tm, mbytes);
     launch_count_active(s, K, st.flags, d_count);
     HIPCHK(ctx, hipGetLastError());
     int active = 0;
     HIPCHK(ctx, hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
+    if (tm) {
+      slrf_status hs = harvest_timer(ctx, g.total, &ks);
+      if (hs != SLRF_OK) return hs;
+    }
     if (active == 0) break;
   }
   launch_filter_sum<double>(s, n, L, N, st.x, w, U, false);
@@ -308,6 +355,12 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
     fs.mean_iterations = K ? sum_it / K : 0.0;
     HIPCHK(ctx, hipStreamSynchronize(s));
     fs.seconds = now_s() - t0;
+    fs.spmm_seconds = ks.spmm_seconds;
+    fs.spmm_launches = ks.spmm_launches;
+    fs.spmm_bytes = ks.spmm_bytes;
+    fs.update_seconds = ks.update_seconds;
+    fs.update_launches = ks.update_launches;
+    fs.update_bytes = ks.update_bytes;
     *stats = fs;
   }
   return SLRF_OK;
@@ -483,7 +536,16 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   ctx->diagA = cv.take<double>(n);
   ctx->diagB = cv.take<double>(n);
   ctx->diagpos = cv.take<int>(n);
+  ctx->timer.d_counts = cv.take<int>(kTimerSlots);
   ctx->static_bytes = cv.off;
+  if (ctx->opt.profile) {
+    ctx->events.assign(2 * kTimerSlots, nullptr);
+    for (auto& e : ctx->events)
+      if (hipEventCreate(&e) != hipSuccess) return bail(SLRF_E_DEVICE, "hipEventCreate failed");
+    ctx->timer.events = ctx->events.data();
+    ctx->timer.capacity = kTimerSlots;
+    launch_fill_zero(ctx->stream, ctx->timer.d_counts, 4 * kTimerSlots);
+  }
   hipStream_t s = ctx->stream;
   auto cp = [&](void* dst, const void* src, size_t b) { return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s); };
   if (cp(ctx->rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(ctx->col, cl.data(), 4 * nnz) != hipSuccess ||
@@ -561,6 +623,7 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
   slrf_solve_stats ss{};
   std::vector<double> theta, theta2, rho(L, 0.0);
   int prev_count = -1, count = 0;
+  double iter_sum = 0;
   bool converged = false, too_small = false;
   int k = 0;
   for (k = 1; k <= std::max(1, ctx->opt.outer_maxit); ++k) {
@@ -570,6 +633,13 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
     if (st != SLRF_OK) return st;
     ss.filter_seconds += fs.seconds;
     ss.spmv_total += fs.spmv;
+    iter_sum += fs.mean_iterations;
+    ss.kernels.spmm_seconds += fs.spmm_seconds;
+    ss.kernels.spmm_launches += fs.spmm_launches;
+    ss.kernels.spmm_bytes += fs.spmm_bytes;
+    ss.kernels.update_seconds += fs.update_seconds;
+    ss.kernels.update_launches += fs.update_launches;
+    ss.kernels.update_bytes += fs.update_bytes;
     st = rr_pass(ctx, L, U, X, WA, WB, part, nch, GA, GB, Zd, theta);
     if (st != SLRF_OK) return st;
     st = rr_pass(ctx, L, X, V, WA, WB, part, nch, GA, GB, Zd, theta2);
@@ -610,6 +680,7 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
     prev_count = count;
   }
   ss.outer_iterations = std::min(k, std::max(1, ctx->opt.outer_maxit));
+  ss.inner_iterations = iter_sum / std::max(1, ss.outer_iterations);
   HIPCHK(ctx, hipMemcpyAsync(d_evecs, V, 8 * (size_t)n * L, hipMemcpyDeviceToDevice, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   int found = 0;
