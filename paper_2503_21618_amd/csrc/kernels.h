@@ -28,8 +28,8 @@ enum ColFlag : int {
 
 // Geometry of an (n, K) complex Krylov block: rows split into row blocks of
 // `rows_per_block`, columns into tiles of 64 (one column per lane).  Every
-// kernel over the block uses the same decomposition, so per-column partial
-// sums live in [nrb][K] arrays and are reduced in a fixed order.
+// kernel over the block uses the same grid of G workgroups, so per-column
+// partial sums live in [G][K] arrays and are reduced in a fixed order.
 struct KGeom {
   int n;
   int K;             // columns = poles * L, pole-major (c = j * L + l)
@@ -38,9 +38,12 @@ struct KGeom {
   int rows_per_block;
   int nrb;           // row blocks
   int nct;           // column tiles of 64
-  int64_t total;     // nrb * nct workgroups
-  int64_t padded;    // total rounded up to a multiple of 8 (XCD count)
+  int slab;          // row blocks per XCD
+  int G;             // workgroups (a multiple of 8)
+  int steps;         // row-block steps per tile per workgroup
+  const int* sched;  // sparse-product row order (a permutation of 0..n-1), or null
 };
+constexpr int kMaxGrid = 1024;  // G <= kMaxGrid
 
 KGeom make_geom(int n, int N, int L, int rows_per_block);
 

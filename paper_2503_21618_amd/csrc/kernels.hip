@@ -6,16 +6,14 @@
 // (re, im) interleaved, so one row of a 64-column tile is a contiguous
 // 64 * sizeof(cx<R>) byte segment (1 KiB in FP64).
 //
-// Work decomposition shared by all Krylov kernels: a workgroup of 256 threads
-// (4 wavefronts of 64) owns one row block x one 64-column tile; each lane owns
-// one column, each wavefront walks every 4th row of the block.  Per-column dot
-// products therefore accumulate in registers with no cross-lane traffic; the 4
-// wavefronts are combined through LDS and the row blocks by a per-column kernel
-// that sums [nrb][K] partials in a fixed order (bitwise reproducible).
-//
-// Workgroups are dispatched round-robin over the 8 XCDs; blockIdx is remapped
-// so that each XCD owns a contiguous range of row blocks of one column tile, so
-// the neighbouring rows gathered by the sparse product stay in that XCD's L2.
+// Work decomposition shared by all Krylov kernels: a grid of G workgroups of
+// 256 threads (4 wavefronts of 64) sweeps the 64-column tiles one after the
+// other; within a tile each lane owns one column and each wavefront walks every
+// 4th row of its row blocks (see WgPos for how rows are assigned per XCD).
+// Per-column dot products therefore accumulate in registers with no cross-lane
+// traffic; the 4 wavefronts are combined through LDS and the G workgroups by a
+// per-column kernel that sums [G][K] partials in a fixed order (bitwise
+// reproducible).
 #include "kernels.h"
 
 #include <algorithm>
@@ -24,6 +22,7 @@ namespace slrf {
 
 constexpr int WAVE = 64;
 constexpr int WG = 256;
+constexpr int kWgPerXcd = 128;  // workgroups per XCD in the Krylov kernels
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -61,69 +60,74 @@ KGeom make_geom(int n, int N, int L, int rows_per_block) {
   g.rows_per_block = rows_per_block;
   g.nrb = (n + rows_per_block - 1) / rows_per_block;
   g.nct = (g.K + WAVE - 1) / WAVE;
-  g.total = (int64_t)g.nrb * g.nct;
-  g.padded = (g.total + 7) / 8 * 8;
+  g.slab = (g.nrb + 7) / 8;
+  const int per_xcd = std::max(1, std::min(kWgPerXcd, g.slab));
+  g.G = 8 * per_xcd;
+  g.steps = (g.slab + per_xcd - 1) / per_xcd;
+  g.sched = nullptr;
   return g;
 }
 
-struct BlockPos {
-  int rb, ct, c, lane, w, r0, r1;
-  bool valid;
+// Workgroup b runs on XCD b % 8 (round-robin dispatch).  XCD x owns the
+// contiguous slab of row blocks [x * slab, (x + 1) * slab); its per_xcd
+// workgroups advance through the slab together, step t covering row blocks
+// x * slab + t * per_xcd + [0, per_xcd), so the rows in flight on one XCD stay
+// within about one grid plane and the neighbours gathered by the sparse product
+// are re-read from that XCD's L2 instead of HBM.
+struct WgPos {
+  int x, q, per, lane, w;
 };
 
-__device__ __forceinline__ bool block_pos(const KGeom& g, BlockPos& p) {
-  int64_t id = xcd_remap(blockIdx.x, g.padded);
-  if (id >= g.total) return false;
-  p.rb = (int)(id % g.nrb);
-  p.ct = (int)(id / g.nrb);
+__device__ __forceinline__ WgPos wg_pos(const KGeom& g) {
+  WgPos p;
+  p.x = blockIdx.x & 7;
+  p.q = blockIdx.x >> 3;
+  p.per = g.G >> 3;
   p.lane = lane_id();
   p.w = wave_id();
-  p.c = p.ct * WAVE + p.lane;
-  p.valid = p.c < g.K;
-  p.r0 = p.rb * g.rows_per_block;
-  p.r1 = min(p.r0 + g.rows_per_block, g.n);
-  return true;
+  return p;
 }
 
-// true if any column of the tile is in one of the given states
-__device__ __forceinline__ bool tile_has(const int* flags, const BlockPos& p, int s0, int s1) {
-  int f = p.valid ? flags[p.c] : -1;
+// row block of step t for this workgroup, or -1 once past the slab
+__device__ __forceinline__ int step_block(const KGeom& g, const WgPos& p, int t) {
+  const int j = t * p.per + p.q;
+  if (j >= g.slab) return -1;
+  const int rb = p.x * g.slab + j;
+  return rb < g.nrb ? rb : -1;
+}
+
+// true if any column of the 64-column tile is in one of the given states
+__device__ __forceinline__ bool tile_has(const int* flags, int c, bool valid, int s0, int s1) {
+  const int f = valid ? flags[c] : -1;
   return __any(f == s0 || f == s1);
 }
 
-// one vector atomic per processed workgroup when instrumented
+// one vector atomic per processed (workgroup, tile) when instrumented
 __device__ __forceinline__ void count_tile(int* counter) {
   if (counter && threadIdx.x == 0) atomicAdd(counter, 1);
 }
 
+// Sum of the 4 wavefronts' per-lane values in a fixed order; lane c of wave 0
+// stores it at out[c] (out points at this workgroup's slice of the tile).
 template <typename T>
-__device__ __forceinline__ void wg_store_partial(T v, const BlockPos& p, T* out, int K) {
+__device__ __forceinline__ void wg_store_partial(T v, int w, int lane, bool valid, T* out) {
   __shared__ T red[4][WAVE];
-  red[p.w][p.lane] = v;
+  red[w][lane] = v;
   __syncthreads();
-  if (p.w == 0 && p.valid) {
-    T s = red[0][p.lane];
-#pragma unroll
-    for (int q = 1; q < 4; ++q) s = s + red[q][p.lane];
-    out[(size_t)p.rb * K + p.c] = s;
-  }
+  if (w == 0 && valid) out[lane] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  __syncthreads();
 }
 
 template <typename R>
-__device__ __forceinline__ void wg_store_partial_cx(cx<R> v, const BlockPos& p, cx<R>* out, int K) {
+__device__ __forceinline__ void wg_store_partial_cx(cx<R> v, int w, int lane, bool valid, cx<R>* out) {
   __shared__ R rr[4][WAVE], ri[4][WAVE];
-  rr[p.w][p.lane] = v.re;
-  ri[p.w][p.lane] = v.im;
+  rr[w][lane] = v.re;
+  ri[w][lane] = v.im;
   __syncthreads();
-  if (p.w == 0 && p.valid) {
-    R sr = rr[0][p.lane], si = ri[0][p.lane];
-#pragma unroll
-    for (int q = 1; q < 4; ++q) {
-      sr += rr[q][p.lane];
-      si += ri[q][p.lane];
-    }
-    out[(size_t)p.rb * K + p.c] = {sr, si};
-  }
+  if (w == 0 && valid)
+    out[lane] = {rr[0][lane] + rr[1][lane] + rr[2][lane] + rr[3][lane],
+                 ri[0][lane] + ri[1][lane] + ri[2][lane] + ri[3][lane]};
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -131,80 +135,116 @@ __device__ __forceinline__ void wg_store_partial_cx(cx<R> v, const BlockPos& p, 
 //   Q[i, c] = sum_j (a_ij - sigma_c b_ij) P[j, c]
 // (A - sigma B is never formed: each (a, b) pair is read once per tile and the
 // pole of the column is applied when the row is finished.)
-template <typename R>
+// The row's entries are taken in chunks of CH: CH (col, a, b) entries are read
+// (wave-uniform, scalar loads), then CH gathers are issued back to back with no
+// branches, then the FMAs.  Entries past the row end repeat the last valid
+// column with zero coefficients, and lanes past K read column K-1 (both stay in
+// bounds; their contributions are discarded).
+template <typename R, int CH>
 __device__ __forceinline__ cx<R> shifted_row(int i, const int* __restrict__ rowptr,
                                              const int* __restrict__ col,
                                              const ab_pair<R>* __restrict__ ab,
-                                             const cx<R>* __restrict__ P, int K, int c,
-                                             bool valid, cx<R> sig) {
+                                             const cx<R>* __restrict__ Pc, int K, cx<R> sig) {
   const int k0 = rowptr[i], k1 = rowptr[i + 1];
   R apr = 0, api = 0, bpr = 0, bpi = 0;
-  const cx<R>* Pc = P + c;
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
-    const int j = col[k];
-    const ab_pair<R> m = ab[k];
-    cx<R> x = {0, 0};
-    if (valid) x = Pc[(size_t)j * K];
-    apr += m.a * x.re;
-    api += m.a * x.im;
-    bpr += m.b * x.re;
-    bpi += m.b * x.im;
+  for (int kb = k0; kb < k1; kb += CH) {
+    int jj[CH];
+    ab_pair<R> m[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = min(kb + u, k1 - 1);
+      jj[u] = col[k];
+      m[u] = ab[k];
+      if (kb + u >= k1) m[u] = ab_pair<R>{0, 0};
+    }
+    cx<R> x[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) x[u] = Pc[(size_t)jj[u] * K];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      apr += m[u].a * x[u].re;
+      api += m[u].a * x[u].im;
+      bpr += m[u].b * x[u].re;
+      bpi += m[u].b * x[u].im;
+    }
   }
   return {apr - (sig.re * bpr - sig.im * bpi), api - (sig.re * bpi + sig.im * bpr)};
 }
+
+constexpr int kChunk = 16;
 
 // v = S p_hat, partial (rhat, v)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_v(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
                                               const int* __restrict__ col,
                                               const ab_pair<R>* __restrict__ ab, int* counter) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
-  count_tile(counter);
-  const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
-  const int l = p.c % g.L;
-  R dr = 0, di = 0;
-  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-    cx<R> q = shifted_row<R>(i, rowptr, col, ab, st.ph, g.K, p.c, p.valid, sig);
-    if (p.valid) {
-      st.v[(size_t)i * g.K + p.c] = q;
-      const R rh = st.rhat[(size_t)i * g.L + l];
-      dr += rh * q.re;
-      di += rh * q.im;
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    const int cc = min(c, g.K - 1);
+    R dr = 0, di = 0;
+    if (tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) {
+      count_tile(counter);
+      const cx<R> sig = st.sigma_col[cc];
+      const int l = cc % g.L;
+      for (int t = 0; t < g.steps; ++t) {
+        const int rb = step_block(g, p, t);
+        if (rb < 0) break;
+        const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+        for (int pos = rb * g.rows_per_block + p.w; pos < r1; pos += 4) {
+          const int i = g.sched ? g.sched[pos] : pos;
+          const R rh = st.rhat[(size_t)i * g.L + l];
+          const cx<R> q = shifted_row<R, kChunk>(i, rowptr, col, ab, st.ph + cc, g.K, sig);
+          if (valid) {
+            st.v[(size_t)i * g.K + c] = q;
+            dr += rh * q.re;
+            di += rh * q.im;
+          }
+        }
+      }
     }
+    wg_store_partial_cx<R>({dr, di}, p.w, p.lane, valid, st.part_a + (size_t)blockIdx.x * g.K + ct * WAVE);
   }
-  wg_store_partial_cx<R>({dr, di}, p, st.part_a, g.K);
 }
 
-// t = S s_hat, partials (t, s) = t^H s with s = d s_hat, and (t, t)
+// t = S s_hat, partials (t, s) = t^H s and (t, t)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const int* __restrict__ rowptr,
                                               const int* __restrict__ col,
                                               const ab_pair<R>* __restrict__ ab, int* counter) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
-  count_tile(counter);
-  const cx<R> sig = p.valid ? st.sigma_col[p.c] : cx<R>{0, 0};
-  const int pole = p.c / g.L;
-  R tsr = 0, tsi = 0, tt = 0;
-  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-    cx<R> t = shifted_row<R>(i, rowptr, col, ab, st.sh, g.K, p.c, p.valid, sig);
-    if (p.valid) {
-      st.t[(size_t)i * g.K + p.c] = t;
-      const size_t e = (size_t)i * g.K + p.c;
-      const cx<R> s = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], st.sh[e]);
-      // conj(t) * s
-      tsr += t.re * s.re + t.im * s.im;
-      tsi += t.re * s.im - t.im * s.re;
-      tt += t.re * t.re + t.im * t.im;
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    const int cc = min(c, g.K - 1);
+    R tsr = 0, tsi = 0, tt = 0;
+    if (tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) {
+      count_tile(counter);
+      const cx<R> sig = st.sigma_col[cc];
+      const int pole = cc / g.L;
+      for (int t = 0; t < g.steps; ++t) {
+        const int rb = step_block(g, p, t);
+        if (rb < 0) break;
+        const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+        for (int pos = rb * g.rows_per_block + p.w; pos < r1; pos += 4) {
+          const int i = g.sched ? g.sched[pos] : pos;
+          const cx<R> tv = shifted_row<R, kChunk>(i, rowptr, col, ab, st.sh + cc, g.K, sig);
+          if (valid) {
+            const size_t e = (size_t)i * g.K + c;
+            st.t[e] = tv;
+            const cx<R> s = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], st.sh[e]);
+            tsr += tv.re * s.re + tv.im * s.im;  // conj(t) * s
+            tsi += tv.re * s.im - tv.im * s.re;
+            tt += tv.re * tv.re + tv.im * tv.im;
+          }
+        }
+      }
     }
+    const size_t o = (size_t)blockIdx.x * g.K + ct * WAVE;
+    wg_store_partial_cx<R>({tsr, tsi}, p.w, p.lane, valid, st.part_a + o);
+    wg_store_partial<R>(tt, p.w, p.lane, valid, st.part_b + o);
   }
-  wg_store_partial_cx<R>({tsr, tsi}, p, st.part_a, g.K);
-  __syncthreads();
-  wg_store_partial<R>(tt, p, st.part_b, g.K);
 }
 
 // p = r + beta (p - omega v)  (first iteration: p = r).
@@ -212,27 +252,34 @@ __global__ __launch_bounds__(WG) void k_spmm_t(KGeom g, KrylovState<R> st, const
 // General preconditioner: p is stored and p_hat is formed by the preconditioner.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int first, int* counter) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
-  count_tile(counter);
-  const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
-  if (!act) return;
-  const int pole = p.c / g.L;
-  const cx<R> beta = st.beta[p.c], omega = st.omega[p.c];
-  for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-    const size_t e = (size_t)i * g.K + p.c;
-    cx<R> pn = st.r[e];
-    if (st.p) {
-      if (!first) pn = cadd(pn, cmul(beta, csub(st.p[e], cmul(omega, st.v[e]))));
-      st.p[e] = pn;
-    } else {
-      const cx<R> di = st.dinv[(size_t)i * g.N + pole];
-      if (!first) {
-        const cx<R> dd = st.d[(size_t)i * g.N + pole];
-        pn = cadd(pn, cmul(beta, csub(cmul(dd, st.ph[e]), cmul(omega, st.v[e]))));
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) continue;
+    count_tile(counter);
+    if (!valid || st.flags[c] != COL_ACTIVE) continue;
+    const int pole = c / g.L;
+    const cx<R> beta = st.beta[c], omega = st.omega[c];
+    for (int t = 0; t < g.steps; ++t) {
+      const int rb = step_block(g, p, t);
+      if (rb < 0) break;
+      const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+      for (int i = rb * g.rows_per_block + p.w; i < r1; i += 4) {
+        const size_t e = (size_t)i * g.K + c;
+        cx<R> pn = st.r[e];
+        if (st.p) {
+          if (!first) pn = cadd(pn, cmul(beta, csub(st.p[e], cmul(omega, st.v[e]))));
+          st.p[e] = pn;
+        } else {
+          const cx<R> di = st.dinv[(size_t)i * g.N + pole];
+          if (!first) {
+            const cx<R> dd = st.d[(size_t)i * g.N + pole];
+            pn = cadd(pn, cmul(beta, csub(cmul(dd, st.ph[e]), cmul(omega, st.v[e]))));
+          }
+          st.ph[e] = cmul(pn, di);
+        }
       }
-      st.ph[e] = cmul(pn, di);
     }
   }
 }
@@ -240,65 +287,82 @@ __global__ __launch_bounds__(WG) void k_update_p(KGeom g, KrylovState<R> st, int
 // s = r - alpha v (Jacobi: s_hat = s / d is stored instead) ; partial |s|^2
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_s(KGeom g, KrylovState<R> st, int* counter) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  if (!tile_has(st.flags, p, COL_ACTIVE, COL_ACTIVE)) return;
-  count_tile(counter);
-  const bool act = p.valid && st.flags[p.c] == COL_ACTIVE;
-  const int pole = p.c / g.L;
-  const cx<R> alpha = act ? st.alpha[p.c] : cx<R>{0, 0};
-  R ss = 0;
-  if (act) {
-    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-      const size_t e = (size_t)i * g.K + p.c;
-      const cx<R> s = csub(st.r[e], cmul(alpha, st.v[e]));
-      ss += s.re * s.re + s.im * s.im;
-      if (st.s)
-        st.s[e] = s;
-      else
-        st.sh[e] = cmul(s, st.dinv[(size_t)i * g.N + pole]);
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    R ss = 0;
+    if (tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) {
+      count_tile(counter);
+      if (valid && st.flags[c] == COL_ACTIVE) {
+        const int pole = c / g.L;
+        const cx<R> alpha = st.alpha[c];
+        for (int t = 0; t < g.steps; ++t) {
+          const int rb = step_block(g, p, t);
+          if (rb < 0) break;
+          const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+          for (int i = rb * g.rows_per_block + p.w; i < r1; i += 4) {
+            const size_t e = (size_t)i * g.K + c;
+            const cx<R> s = csub(st.r[e], cmul(alpha, st.v[e]));
+            ss += s.re * s.re + s.im * s.im;
+            if (st.s)
+              st.s[e] = s;
+            else
+              st.sh[e] = cmul(s, st.dinv[(size_t)i * g.N + pole]);
+          }
+        }
+      }
     }
+    wg_store_partial<R>(ss, p.w, p.lane, valid, st.part_b + (size_t)blockIdx.x * g.K + ct * WAVE);
   }
-  wg_store_partial<R>(ss, p, st.part_b, g.K);
 }
 
 // x += alpha p_hat + omega s_hat ; r = s - omega t ; partials (rhat, r), |r|^2
 // Columns that converged at the half step take x += alpha p_hat only.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int first, int* counter) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  if (!tile_has(st.flags, p, COL_ACTIVE, COL_HALF_PENDING)) return;
-  count_tile(counter);
-  const int f = p.valid ? st.flags[p.c] : -1;
-  const bool act = f == COL_ACTIVE, half = f == COL_HALF_PENDING;
-  const int pole = p.c / g.L;
-  const int l = p.c % g.L;
-  const cx<R> alpha = (act || half) ? st.alpha[p.c] : cx<R>{0, 0};
-  const cx<R> omega = act ? st.omega[p.c] : cx<R>{0, 0};
-  R rr = 0, ri = 0, nn = 0;
-  if (act || half) {
-    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-      const size_t e = (size_t)i * g.K + p.c;
-      cx<R> x = first ? cx<R>{0, 0} : st.x[e];
-      x = cadd(x, cmul(alpha, st.ph[e]));
-      if (act) {
-        const cx<R> sh = st.sh[e];
-        x = cadd(x, cmul(omega, sh));
-        const cx<R> sv = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], sh);
-        const cx<R> r = csub(sv, cmul(omega, st.t[e]));
-        st.r[e] = r;
-        const R rh = st.rhat[(size_t)i * g.L + l];
-        rr += rh * r.re;
-        ri += rh * r.im;
-        nn += r.re * r.re + r.im * r.im;
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    R rr = 0, ri = 0, nn = 0;
+    if (tile_has(st.flags, c, valid, COL_ACTIVE, COL_HALF_PENDING)) {
+      count_tile(counter);
+      const int f = valid ? st.flags[c] : -1;
+      const bool act = f == COL_ACTIVE, half = f == COL_HALF_PENDING;
+      if (act || half) {
+        const int pole = c / g.L;
+        const int l = c % g.L;
+        const cx<R> alpha = st.alpha[c];
+        const cx<R> omega = act ? st.omega[c] : cx<R>{0, 0};
+        for (int t = 0; t < g.steps; ++t) {
+          const int rb = step_block(g, p, t);
+          if (rb < 0) break;
+          const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+          for (int i = rb * g.rows_per_block + p.w; i < r1; i += 4) {
+            const size_t e = (size_t)i * g.K + c;
+            cx<R> x = first ? cx<R>{0, 0} : st.x[e];
+            x = cadd(x, cmul(alpha, st.ph[e]));
+            if (act) {
+              const cx<R> sh = st.sh[e];
+              x = cadd(x, cmul(omega, sh));
+              const cx<R> sv = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], sh);
+              const cx<R> r = csub(sv, cmul(omega, st.t[e]));
+              st.r[e] = r;
+              const R rh = st.rhat[(size_t)i * g.L + l];
+              rr += rh * r.re;
+              ri += rh * r.im;
+              nn += r.re * r.re + r.im * r.im;
+            }
+            st.x[e] = x;
+          }
+        }
       }
-      st.x[e] = x;
     }
+    const size_t o = (size_t)blockIdx.x * g.K + ct * WAVE;
+    wg_store_partial_cx<R>({rr, ri}, p.w, p.lane, valid, st.part_a + o);
+    wg_store_partial<R>(nn, p.w, p.lane, valid, st.part_b + o);
   }
-  wg_store_partial_cx<R>({rr, ri}, p, st.part_a, g.K);
-  __syncthreads();
-  wg_store_partial<R>(nn, p, st.part_b, g.K);
 }
 
 template <typename R>
@@ -325,7 +389,7 @@ template <typename R>
 __global__ void k_sc_alpha(KGeom g, KrylovState<R> st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const cx<R> rv = sum_part_cx(st.part_a, g.nrb, g.K, c);
+  const cx<R> rv = sum_part_cx(st.part_a, g.G, g.K, c);
   const cx<R> rho = st.rho[c];
   if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
     st.flags[c] = COL_BREAKDOWN;
@@ -340,7 +404,7 @@ template <typename R>
 __global__ void k_sc_half(KGeom g, KrylovState<R> st, R tol) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const R sn = sqrt(sum_part(st.part_b, g.nrb, g.K, c));
+  const R sn = sqrt(sum_part(st.part_b, g.G, g.K, c));
   if (sn <= tol * st.fnorm[c]) {
     st.flags[c] = COL_HALF_PENDING;
     st.rnorm[c] = sn;
@@ -352,8 +416,8 @@ template <typename R>
 __global__ void k_sc_omega(KGeom g, KrylovState<R> st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const cx<R> ts = sum_part_cx(st.part_a, g.nrb, g.K, c);
-  const R tt = sum_part(st.part_b, g.nrb, g.K, c);
+  const cx<R> ts = sum_part_cx(st.part_a, g.G, g.K, c);
+  const R tt = sum_part(st.part_b, g.G, g.K, c);
   if (tt == 0 || !isfinite(tt)) {
     st.flags[c] = COL_BREAKDOWN;
     return;
@@ -372,8 +436,8 @@ __global__ void k_sc_beta(KGeom g, KrylovState<R> st, R tol, int maxit) {
     return;
   }
   if (f != COL_ACTIVE) return;
-  const cx<R> rn = sum_part_cx(st.part_a, g.nrb, g.K, c);
-  const R nn = sqrt(sum_part(st.part_b, g.nrb, g.K, c));
+  const cx<R> rn = sum_part_cx(st.part_a, g.G, g.K, c);
+  const R nn = sqrt(sum_part(st.part_b, g.G, g.K, c));
   st.rnorm[c] = nn;
   if (nn <= tol * st.fnorm[c]) {
     st.flags[c] = COL_CONVERGED;
@@ -444,7 +508,7 @@ template <typename R>
 void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const int* rowptr,
                       const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first,
                       const IluFactors<R>* ilu, LaunchTimer* tm, double matrix_bytes) {
-  const dim3 grid((unsigned)g.padded), blk(WG);
+  const dim3 grid((unsigned)g.G), blk(WG);
   const dim3 cgrid((g.K + 255) / 256), cblk(256);
   const dim3 igrid((g.K + 63) / 64), iblk(64);
   // algorithmic traffic: n x K complex passes per fully processed launch, plus
@@ -482,26 +546,34 @@ void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, c
 // x = 0, r = f (broadcast over poles); partials of (rhat, r) = ||f||^2
 template <typename R>
 __global__ __launch_bounds__(WG) void k_init(KGeom g, KrylovState<R> st, const R* __restrict__ F) {
-  BlockPos p;
-  if (!block_pos(g, p)) return;
-  const int l = p.c % g.L;
-  R nn = 0;
-  if (p.valid) {
-    for (int i = p.r0 + p.w; i < p.r1; i += 4) {
-      const R f = F[(size_t)i * g.L + l];
-      st.r[(size_t)i * g.K + p.c] = {f, 0};
-      st.x[(size_t)i * g.K + p.c] = {0, 0};
-      nn += f * f;
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    R nn = 0;
+    if (valid) {
+      const int l = c % g.L;
+      for (int t = 0; t < g.steps; ++t) {
+        const int rb = step_block(g, p, t);
+        if (rb < 0) break;
+        const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+        for (int i = rb * g.rows_per_block + p.w; i < r1; i += 4) {
+          const R f = F[(size_t)i * g.L + l];
+          st.r[(size_t)i * g.K + c] = {f, 0};
+          st.x[(size_t)i * g.K + c] = {0, 0};
+          nn += f * f;
+        }
+      }
     }
+    wg_store_partial<R>(nn, p.w, p.lane, valid, st.part_b + (size_t)blockIdx.x * g.K + ct * WAVE);
   }
-  wg_store_partial<R>(nn, p, st.part_b, g.K);
 }
 
 template <typename R>
 __global__ void k_init_scalars(KGeom g, KrylovState<R> st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.K) return;
-  const R nn = sum_part(st.part_b, g.nrb, g.K, c);
+  const R nn = sum_part(st.part_b, g.G, g.K, c);
   st.fnorm[c] = sqrt(nn);
   st.rnorm[c] = sqrt(nn);
   st.rho[c] = {nn, 0};
@@ -514,7 +586,7 @@ __global__ void k_init_scalars(KGeom g, KrylovState<R> st) {
 
 template <typename R>
 void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const R* F) {
-  k_init<R><<<dim3((unsigned)g.padded), dim3(WG), 0, s>>>(g, st, F);
+  k_init<R><<<dim3((unsigned)g.G), dim3(WG), 0, s>>>(g, st, F);
 }
 template <typename R>
 void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st) {

@@ -25,7 +25,8 @@ using namespace slrf;
 
 namespace {
 
-constexpr int kRowsPerBlock = 256;
+constexpr int kRowsPerBlock = 8;
+constexpr int kSubBand = 1024;  // rows per sub-band of the sparse-product row order
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -61,7 +62,7 @@ size_t krylov_bytes_fp64(int64_t n, int64_t nnz, int64_t L, int64_t N) {
   b += al((size_t)n * L * 8);               // rhat = B X
   b += 2 * al((size_t)n * N * 16);          // d, dinv
   b += al((size_t)N * 16) + al((size_t)K * 16) + al((size_t)2 * N * 8);  // sigma, sigma_col, w
-  b += al((size_t)nrb * K * 16) + al((size_t)nrb * K * 8);                // partials
+  b += al((size_t)kMaxGrid * K * 16) + al((size_t)kMaxGrid * K * 8);      // partials [G][K]
   b += 4 * al((size_t)K * 16) + 2 * al((size_t)K * 8) + 2 * al((size_t)K * 4) + al(256);
   return b;
 }
@@ -98,6 +99,7 @@ struct slrf_ctx_s {
   bool verbose = false;
   bool use_ilu = false;
   int* diagpos = nullptr;
+  int* sched = nullptr;     // sparse-product row order, null = natural order
   // host copy of the merged CSR, kept for the per-pole ILU(0) factorisations
   std::vector<int32_t> h_rp, h_cl, h_dpos;
   std::vector<double> h_ab;
@@ -127,7 +129,30 @@ constexpr int kTimerSlots = 512;
 
 size_t static_bytes_for(int64_t n, int64_t nnz) {
   return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8) +
-         al((size_t)n * 4) + al(kTimerSlots * 4);
+         al((size_t)n * 4) + al(kTimerSlots * 4) + al((size_t)n * 4);
+}
+
+// Row order of the sparse products.  With upper bandwidth H (max j - i), the
+// neighbours of row i lie in [i - H, i + H].  Rows are cut into chunks of H and
+// each chunk into S sub-bands of about kSubBand rows; the order visits sub-band
+// s of chunk 0, 1, 2, ... before sub-band s + 1, so consecutive rows in the
+// order have overlapping neighbourhoods (for a lexicographic 3D grid: a narrow
+// (x, y) band marching along z).  Returns false (natural order) when H is small.
+bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
+                   std::vector<int32_t>& order) {
+  int64_t H = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] > rp[i]) H = std::max<int64_t>(H, (int64_t)cl[rp[i + 1] - 1] - i);
+  if (H <= 2 * kSubBand || H >= n) return false;
+  const int64_t S = (H + kSubBand - 1) / kSubBand, band = (H + S - 1) / S, nchunk = (n + H - 1) / H;
+  order.clear();
+  order.reserve(n);
+  for (int64_t sb = 0; sb < S; ++sb)
+    for (int64_t k = 0; k < nchunk; ++k) {
+      const int64_t a = k * H + sb * band, b = std::min({k * H + (sb + 1) * band, (k + 1) * H, n});
+      for (int64_t r = a; r < b; ++r) order.push_back((int32_t)r);
+    }
+  return (int64_t)order.size() == n;
 }
 
 double merged_csr_bytes(const slrf_ctx ctx, size_t value_bytes) {
@@ -237,7 +262,8 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   const double t0 = now_s();
   hipStream_t s = ctx->stream;
   const int n = (int)ctx->n, N = poles->n_poles;
-  const KGeom g = make_geom(n, N, L, kRowsPerBlock);
+  KGeom g = make_geom(n, N, L, kRowsPerBlock);
+  g.sched = ctx->sched;
   const int K = g.K;
   KrylovState<double> st{};
   st.x = cv.take<cx<double>>((size_t)n * K);
@@ -258,8 +284,8 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   cx<double>* sig = cv.take<cx<double>>(N);
   cx<double>* sigc = cv.take<cx<double>>(K);
   double* w = cv.take<double>(2 * N);
-  st.part_a = cv.take<cx<double>>((size_t)g.nrb * K);
-  st.part_b = cv.take<double>((size_t)g.nrb * K);
+  st.part_a = cv.take<cx<double>>((size_t)g.G * K);
+  st.part_b = cv.take<double>((size_t)g.G * K);
   st.rho = cv.take<cx<double>>(K);
   st.alpha = cv.take<cx<double>>(K);
   st.omega = cv.take<cx<double>>(K);
@@ -325,7 +351,7 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
     HIPCHK(ctx, hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (tm) {
-      slrf_status hs = harvest_timer(ctx, g.total, &ks);
+      slrf_status hs = harvest_timer(ctx, (int64_t)g.G * g.nct, &ks);
       if (hs != SLRF_OK) return hs;
     }
     if (active == 0) break;
@@ -537,7 +563,10 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   ctx->diagB = cv.take<double>(n);
   ctx->diagpos = cv.take<int>(n);
   ctx->timer.d_counts = cv.take<int>(kTimerSlots);
+  int* sched_dev = cv.take<int>(n);
   ctx->static_bytes = cv.off;
+  std::vector<int32_t> order;
+  if (band_schedule(n, rp, cl, order)) ctx->sched = sched_dev;
   if (ctx->opt.profile) {
     ctx->events.assign(2 * kTimerSlots, nullptr);
     for (auto& e : ctx->events)
@@ -551,7 +580,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (cp(ctx->rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(ctx->col, cl.data(), 4 * nnz) != hipSuccess ||
       cp(ctx->ab64, ab.data(), 16 * nnz) != hipSuccess || cp(ctx->diagA, dA.data(), 8 * n) != hipSuccess ||
       cp(ctx->diagB, dB.data(), 8 * n) != hipSuccess || cp(ctx->diagpos, dpos.data(), 4 * n) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+      (ctx->sched && cp(ctx->sched, order.data(), 4 * n) != hipSuccess) || hipStreamSynchronize(s) != hipSuccess)
     return bail(SLRF_E_DEVICE, "upload of the merged CSR failed");
   if (ctx->use_ilu) {
     ctx->h_rp = std::move(rp);

