@@ -235,7 +235,7 @@ class Solver:
             X = t.as_tensor(np.ascontiguousarray(X, dtype=np.float64))
         return X.to(device=self.device, dtype=t.float64).contiguous()
 
-    def filter_apply(self, X, sigma, w):
+    def filter_apply(self, X, sigma, w):  # noqa: D401
         """U = sum_j 2 Re(w_j (A - sigma_j B)^{-1} B X); returns (U, stats dict)."""
         X = self._dev(X)
         n, L = X.shape

@@ -58,6 +58,7 @@ struct KrylovState {
   cx<R>* p;    // unpreconditioned search direction (general preconditioner only)
   cx<R>* s;    // unpreconditioned half-step residual (general preconditioner only)
   const R* rhat;       // (n, L) shared shadow residual = right-hand side
+  const cx<R>* rhat_cx;  // (n, K) per-column complex shadow residual (used when non-null)
   const cx<R>* d;      // (n, N) shifted-operator diagonal
   const cx<R>* dinv;   // (n, N) its inverse
   const cx<R>* sigma_col;  // (K) pole of each column
@@ -120,6 +121,23 @@ void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st,
                       R tol, int maxit, bool first, const IluFactors<R>* ilu,
                       LaunchTimer* timer, double matrix_bytes);
 void launch_count_active(hipStream_t s, int K, const int* flags, int* out);
+
+// ---- mixed precision (FP32 inner solves, FP64 defect correction) ----------
+// R = F - S Y over all K columns in FP64 (Y null: R = F, R not written), with
+// per-column partial sums of |R|^2 into part [G][K].
+void launch_defect(hipStream_t s, const KGeom& g, const int* rowptr, const int* col,
+                   const ab_pair<double>* ab, const cx<double>* sigma_col, const double* F,
+                   const cx<double>* Y, cx<double>* Rout, double* part);
+// scale_c = ||R_c|| if ||R_c|| > tol ||F_c|| else 0; fnorm_c = ||F_c|| on the first
+// round (first != 0); writes the number of unconverged columns to *count.
+void launch_defect_norms(hipStream_t s, const KGeom& g, const double* part, double tol, int first,
+                         double* fnorm, double* scale, double* relres, int* count);
+// r = R / scale (R null: F / scale), rhat = r, x = 0 in FP32; partial |r|^2 into part_b.
+void launch_mixed_rhs(hipStream_t s, const KGeom& g, const cx<double>* R, const double* F,
+                      const double* scale, const KrylovState<float>& st, cx<float>* rhat);
+// Y += scale x (first: Y = scale x)
+void launch_accumulate(hipStream_t s, const KGeom& g, const cx<float>* x, const double* scale,
+                       cx<double>* Y, int first);
 
 template <typename R>
 void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x,

@@ -194,12 +194,18 @@ __global__ __launch_bounds__(WG) void k_spmm_v(KGeom g, KrylovState<R> st, const
         const int r1 = min((rb + 1) * g.rows_per_block, g.n);
         for (int pos = rb * g.rows_per_block + p.w; pos < r1; pos += 4) {
           const int i = g.sched ? g.sched[pos] : pos;
-          const R rh = st.rhat[(size_t)i * g.L + l];
           const cx<R> q = shifted_row<R, kChunk>(i, rowptr, col, ab, st.ph + cc, g.K, sig);
           if (valid) {
             st.v[(size_t)i * g.K + c] = q;
-            dr += rh * q.re;
-            di += rh * q.im;
+            if (st.rhat_cx) {  // conj(rhat) * v
+              const cx<R> rh = st.rhat_cx[(size_t)i * g.K + c];
+              dr += rh.re * q.re + rh.im * q.im;
+              di += rh.re * q.im - rh.im * q.re;
+            } else {
+              const R rh = st.rhat[(size_t)i * g.L + l];
+              dr += rh * q.re;
+              di += rh * q.im;
+            }
           }
         }
       }
@@ -349,9 +355,15 @@ __global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int
               const cx<R> sv = st.s ? st.s[e] : cmul(st.d[(size_t)i * g.N + pole], sh);
               const cx<R> r = csub(sv, cmul(omega, st.t[e]));
               st.r[e] = r;
-              const R rh = st.rhat[(size_t)i * g.L + l];
-              rr += rh * r.re;
-              ri += rh * r.im;
+              if (st.rhat_cx) {
+                const cx<R> rh = st.rhat_cx[e];
+                rr += rh.re * r.re + rh.im * r.im;
+                ri += rh.re * r.im - rh.im * r.re;
+              } else {
+                const R rh = st.rhat[(size_t)i * g.L + l];
+                rr += rh * r.re;
+                ri += rh * r.im;
+              }
               nn += r.re * r.re + r.im * r.im;
             }
             st.x[e] = x;
@@ -591,6 +603,131 @@ void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const 
 template <typename R>
 void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st) {
   k_init_scalars<R><<<dim3((g.K + 255) / 256), dim3(256), 0, s>>>(g, st);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: FP64 defect R = F - S Y and the FP32 <-> FP64 transfers.
+__global__ __launch_bounds__(WG) void k_defect(KGeom g, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                              const ab_pair<double>* __restrict__ ab,
+                                              const cx<double>* __restrict__ sigma_col, const double* __restrict__ F,
+                                              const cx<double>* __restrict__ Y, cx<double>* __restrict__ Rout,
+                                              double* __restrict__ part) {
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    const int cc = min(c, g.K - 1);
+    const int l = cc % g.L;
+    const cx<double> sig = sigma_col[cc];
+    double nn = 0;
+    for (int t = 0; t < g.steps; ++t) {
+      const int rb = step_block(g, p, t);
+      if (rb < 0) break;
+      const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+      for (int pos = rb * g.rows_per_block + p.w; pos < r1; pos += 4) {
+        const int i = g.sched ? g.sched[pos] : pos;
+        const double f = F[(size_t)i * g.L + l];
+        cx<double> r = {f, 0.0};
+        if (Y) {
+          const cx<double> q = shifted_row<double, kChunk>(i, rowptr, col, ab, Y + cc, g.K, sig);
+          r = {f - q.re, -q.im};
+          if (valid) Rout[(size_t)i * g.K + c] = r;
+        }
+        nn += r.re * r.re + r.im * r.im;
+      }
+    }
+    wg_store_partial<double>(nn, p.w, p.lane, valid, part + (size_t)blockIdx.x * g.K + ct * WAVE);
+  }
+}
+
+void launch_defect(hipStream_t s, const KGeom& g, const int* rowptr, const int* col, const ab_pair<double>* ab,
+                   const cx<double>* sigma_col, const double* F, const cx<double>* Y, cx<double>* Rout,
+                   double* part) {
+  k_defect<<<dim3((unsigned)g.G), dim3(WG), 0, s>>>(g, rowptr, col, ab, sigma_col, F, Y, Rout, part);
+}
+
+__global__ void k_defect_norms(KGeom g, const double* __restrict__ part, double tol, int first,
+                               double* __restrict__ fnorm, double* __restrict__ scale, double* __restrict__ relres,
+                               int* __restrict__ count) {
+  __shared__ int cnt[256];
+  int mine = 0;
+  for (int c = threadIdx.x; c < g.K; c += blockDim.x) {
+    double sacc = 0;
+    for (int b = 0; b < g.G; ++b) sacc += part[(size_t)b * g.K + c];
+    const double r = sqrt(sacc);
+    if (first) fnorm[c] = r;
+    const double fn = fnorm[c];
+    const bool done = r <= tol * fn;
+    scale[c] = done ? 0.0 : r;
+    relres[c] = fn > 0 ? r / fn : 0.0;
+    mine += done ? 0 : 1;
+  }
+  cnt[threadIdx.x] = mine;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) cnt[threadIdx.x] += cnt[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[0] = cnt[0];
+}
+
+void launch_defect_norms(hipStream_t s, const KGeom& g, const double* part, double tol, int first, double* fnorm,
+                         double* scale, double* relres, int* count) {
+  k_defect_norms<<<1, 256, 0, s>>>(g, part, tol, first, fnorm, scale, relres, count);
+}
+
+__global__ __launch_bounds__(WG) void k_mixed_rhs(KGeom g, const cx<double>* __restrict__ R,
+                                                 const double* __restrict__ F, const double* __restrict__ scale,
+                                                 KrylovState<float> st, cx<float>* __restrict__ rhat) {
+  const WgPos p = wg_pos(g);
+  for (int ct = 0; ct < g.nct; ++ct) {
+    const int c = ct * WAVE + p.lane;
+    const bool valid = c < g.K;
+    float nn = 0;
+    if (valid) {
+      const double sc = scale[c];
+      const double inv = sc > 0 ? 1.0 / sc : 0.0;
+      const int l = c % g.L;
+      for (int t = 0; t < g.steps; ++t) {
+        const int rb = step_block(g, p, t);
+        if (rb < 0) break;
+        const int r1 = min((rb + 1) * g.rows_per_block, g.n);
+        for (int i = rb * g.rows_per_block + p.w; i < r1; i += 4) {
+          const size_t e = (size_t)i * g.K + c;
+          cx<double> v = R ? R[e] : cx<double>{F[(size_t)i * g.L + l], 0.0};
+          const cx<float> r = {(float)(v.re * inv), (float)(v.im * inv)};
+          st.r[e] = r;
+          rhat[e] = r;
+          st.x[e] = {0.f, 0.f};
+          nn += r.re * r.re + r.im * r.im;
+        }
+      }
+    }
+    wg_store_partial<float>(nn, p.w, p.lane, valid, st.part_b + (size_t)blockIdx.x * g.K + ct * WAVE);
+  }
+}
+
+void launch_mixed_rhs(hipStream_t s, const KGeom& g, const cx<double>* R, const double* F, const double* scale,
+                      const KrylovState<float>& st, cx<float>* rhat) {
+  k_mixed_rhs<<<dim3((unsigned)g.G), dim3(WG), 0, s>>>(g, R, F, scale, st, rhat);
+}
+
+__global__ void k_accumulate(int64_t total, int K, const cx<float>* __restrict__ x, const double* __restrict__ scale,
+                             cx<double>* __restrict__ Y, int first) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const double sc = scale[e % K];
+  const cx<float> v = x[e];
+  cx<double> y = first ? cx<double>{0.0, 0.0} : Y[e];
+  y.re += sc * (double)v.re;
+  y.im += sc * (double)v.im;
+  Y[e] = y;
+}
+
+void launch_accumulate(hipStream_t s, const KGeom& g, const cx<float>* x, const double* scale, cx<double>* Y,
+                       int first) {
+  const int64_t tot = (int64_t)g.n * g.K;
+  k_accumulate<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(tot, g.K, x, scale, Y, first);
 }
 
 __global__ void k_count_active(int K, const int* flags, int* out) {

@@ -67,6 +67,25 @@ size_t krylov_bytes_fp64(int64_t n, int64_t nnz, int64_t L, int64_t N) {
   return b;
 }
 
+// MIXED: FP32 Krylov state (+ per-column complex shadow residual, p and s for
+// ILU) and the FP64 accumulator Y, defect R and right-hand side F.
+size_t krylov_bytes_mixed(int64_t n, int64_t nnz, int64_t L, int64_t N) {
+  const int64_t K = N * L;
+  size_t b = 0;
+  b += 7 * al((size_t)n * K * 8);                                           // x r ph v sh t rhat (FP32)
+  if (ilu_allowed(n, nnz)) b += 2 * al((size_t)n * K * 8) + al((size_t)N * nnz * 8);
+  b += 2 * al((size_t)n * K * 16) + al((size_t)n * L * 8);                  // Y R (FP64), F
+  b += 2 * al((size_t)n * N * 8);                                           // d, dinv (FP32)
+  b += al((size_t)N * 8) + al((size_t)K * 8) + al((size_t)K * 16) + al((size_t)2 * N * 8);
+  b += al((size_t)kMaxGrid * K * 8) + al((size_t)kMaxGrid * K * 4) + al((size_t)kMaxGrid * K * 8);
+  b += 4 * al((size_t)K * 8) + 2 * al((size_t)K * 4) + 2 * al((size_t)K * 4) + 3 * al((size_t)K * 8) + al(256);
+  return b;
+}
+
+size_t krylov_bytes(int64_t n, int64_t nnz, int64_t L, int64_t N, int precision) {
+  return precision == SLRF_MIXED ? krylov_bytes_mixed(n, nnz, L, N) : krylov_bytes_fp64(n, nnz, L, N);
+}
+
 size_t outer_bytes(int64_t n, int64_t L) {
   const int nch = gram_chunks((int)n, (int)L);
   const int64_t nrr = (n + 255) / 256;
@@ -95,6 +114,9 @@ struct slrf_ctx_s {
   ab_pair<double>* ab64 = nullptr;
   double* diagA = nullptr;
   double* diagB = nullptr;
+  ab_pair<float>* ab32 = nullptr;  // FP32 copies for the mixed path
+  float* diagA32 = nullptr;
+  float* diagB32 = nullptr;
   std::string err;
   bool verbose = false;
   bool use_ilu = false;
@@ -129,7 +151,7 @@ constexpr int kTimerSlots = 512;
 
 size_t static_bytes_for(int64_t n, int64_t nnz) {
   return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8) +
-         al((size_t)n * 4) + al(kTimerSlots * 4) + al((size_t)n * 4);
+         al((size_t)n * 4) + al(kTimerSlots * 4) + al((size_t)n * 4) + al((size_t)nnz * 8) + 2 * al((size_t)n * 4);
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
@@ -392,6 +414,166 @@ slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L
   return SLRF_OK;
 }
 
+// Filter application with complex FP32 inner solves and FP64 defect correction:
+// Y = 0; repeat { R = F - S Y (FP64); stop columns with ||R|| <= target ||F||;
+// solve S D = R / ||R|| in FP32 (BiCGStab, relative tolerance inner_tol32);
+// Y += ||R|| D } ; U = sum_j 2 Re(w_j Y_j).
+constexpr double kInnerTol32 = 1e-6;
+constexpr int kMaxRounds = 6;
+
+slrf_status filter_mixed(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L, const double* X, double* U,
+                         slrf_filter_stats* stats, double target) {
+  const double t0 = now_s();
+  hipStream_t s = ctx->stream;
+  const int n = (int)ctx->n, N = poles->n_poles;
+  KGeom g = make_geom(n, N, L, kRowsPerBlock);
+  g.sched = ctx->sched;
+  const int K = g.K;
+  KrylovState<float> st{};
+  st.x = cv.take<cx<float>>((size_t)n * K);
+  st.r = cv.take<cx<float>>((size_t)n * K);
+  st.ph = cv.take<cx<float>>((size_t)n * K);
+  st.v = cv.take<cx<float>>((size_t)n * K);
+  st.sh = cv.take<cx<float>>((size_t)n * K);
+  st.t = cv.take<cx<float>>((size_t)n * K);
+  cx<float>* rhat = cv.take<cx<float>>((size_t)n * K);
+  cx<float>* fac = nullptr;
+  if (ctx->use_ilu) {
+    st.p = cv.take<cx<float>>((size_t)n * K);
+    st.s = cv.take<cx<float>>((size_t)n * K);
+    fac = cv.take<cx<float>>((size_t)N * ctx->nnz);
+  }
+  cx<double>* Y = cv.take<cx<double>>((size_t)n * K);
+  cx<double>* Rd = cv.take<cx<double>>((size_t)n * K);
+  double* F = cv.take<double>((size_t)n * L);
+  cx<float>* d = cv.take<cx<float>>((size_t)n * N);
+  cx<float>* dinv = cv.take<cx<float>>((size_t)n * N);
+  cx<float>* sig = cv.take<cx<float>>(N);
+  cx<float>* sigc = cv.take<cx<float>>(K);
+  cx<double>* sigc64 = cv.take<cx<double>>(K);
+  double* w = cv.take<double>(2 * N);
+  st.part_a = cv.take<cx<float>>((size_t)g.G * K);
+  st.part_b = cv.take<float>((size_t)g.G * K);
+  double* part64 = cv.take<double>((size_t)g.G * K);
+  st.rho = cv.take<cx<float>>(K);
+  st.alpha = cv.take<cx<float>>(K);
+  st.omega = cv.take<cx<float>>(K);
+  st.beta = cv.take<cx<float>>(K);
+  st.fnorm = cv.take<float>(K);
+  st.rnorm = cv.take<float>(K);
+  st.flags = cv.take<int>(K);
+  st.iters = cv.take<int>(K);
+  double* fnorm64 = cv.take<double>(K);
+  double* scale = cv.take<double>(K);
+  double* relres = cv.take<double>(K);
+  int* d_count = cv.take<int>(64);
+  if (cv.off > cv.cap) return fail(ctx, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
+  st.rhat = nullptr;
+  st.rhat_cx = rhat;
+  st.d = d;
+  st.dinv = dinv;
+  st.sigma_col = sigc;
+
+  std::vector<float> hsig(2 * N), hsigc(2 * (size_t)K);
+  std::vector<double> hsigc64(2 * (size_t)K);
+  for (int j = 0; j < N; ++j) {
+    hsig[2 * j] = (float)poles->sigma[2 * j];
+    hsig[2 * j + 1] = (float)poles->sigma[2 * j + 1];
+    for (int l = 0; l < L; ++l) {
+      const size_t c = (size_t)j * L + l;
+      hsigc[2 * c] = (float)poles->sigma[2 * j];
+      hsigc[2 * c + 1] = (float)poles->sigma[2 * j + 1];
+      hsigc64[2 * c] = poles->sigma[2 * j];
+      hsigc64[2 * c + 1] = poles->sigma[2 * j + 1];
+    }
+  }
+  HIPCHK(ctx, hipMemcpyAsync(sig, hsig.data(), 8 * N, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(sigc, hsigc.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(sigc64, hsigc64.data(), 16 * (size_t)K, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(w, poles->weight, 16 * N, hipMemcpyHostToDevice, s));
+  IluFactors<float> ilu{};
+  std::vector<cx<float>> hf;
+  if (ctx->use_ilu) {
+    hf.resize((size_t)N * ctx->nnz);
+    std::vector<std::complex<double>> fj;
+    for (int j = 0; j < N; ++j) {
+      if (!ilu0_factor(ctx, {poles->sigma[2 * j], poles->sigma[2 * j + 1]}, fj))
+        return fail(ctx, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
+      for (int64_t k = 0; k < ctx->nnz; ++k)
+        hf[(size_t)j * ctx->nnz + k] = {(float)fj[k].real(), (float)fj[k].imag()};
+    }
+    HIPCHK(ctx, hipMemcpyAsync(fac, hf.data(), 8 * hf.size(), hipMemcpyHostToDevice, s));
+    ilu = {ctx->rowptr, ctx->col, ctx->diagpos, fac, ctx->nnz};
+  }
+  launch_jacobi_diag<float>(s, n, N, ctx->diagA32, ctx->diagB32, sig, d, dinv);
+  launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, X, nullptr, F);
+  HIPCHK(ctx, hipGetLastError());
+
+  const int maxit = std::max(1, ctx->opt.inner_maxit);
+  const int every = std::max(1, std::min(ctx->opt.check_every, 64));
+  LaunchTimer* tm = ctx->opt.profile ? &ctx->timer : nullptr;
+  const double mbytes = merged_csr_bytes(ctx, 8);
+  slrf_filter_stats fs{};
+  double sum_it = 0;
+  int rounds = 0;
+  for (int round = 0; round <= kMaxRounds; ++round) {
+    // defect and the columns still above the target
+    launch_defect(s, g, ctx->rowptr, ctx->col, ctx->ab64, sigc64, F, round ? Y : nullptr, Rd, part64);
+    launch_defect_norms(s, g, part64, target, round == 0, fnorm64, scale, relres, d_count);
+    HIPCHK(ctx, hipGetLastError());
+    int open = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&open, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (round > 0) fs.spmv += (int64_t)K;  // one product with S per column for the defect
+    if (open == 0 || round == kMaxRounds) break;
+    ++rounds;
+    launch_mixed_rhs(s, g, round ? Rd : nullptr, F, scale, st, rhat);
+    launch_init_scalars<float>(s, g, st);
+    int it = 0;
+    while (it < maxit) {
+      const int chunk = std::min(every, maxit - it);
+      for (int q = 0; q < chunk; ++q, ++it)
+        launch_iteration<float>(s, g, st, ctx->rowptr, ctx->col, ctx->ab32, (float)kInnerTol32, maxit, it == 0,
+                                ctx->use_ilu ? &ilu : nullptr, tm, mbytes);
+      launch_count_active(s, K, st.flags, d_count);
+      HIPCHK(ctx, hipGetLastError());
+      int active = 0;
+      HIPCHK(ctx, hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      if (tm) {
+        slrf_status hs = harvest_timer(ctx, (int64_t)g.G * g.nct, &fs);
+        if (hs != SLRF_OK) return hs;
+      }
+      if (active == 0) break;
+    }
+    launch_accumulate(s, g, st.x, scale, Y, round == 0);
+    std::vector<int> fl(K), its(K);
+    HIPCHK(ctx, hipMemcpyAsync(fl.data(), st.flags, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(its.data(), st.iters, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (int c = 0; c < K; ++c) {
+      fs.max_iterations = std::max(fs.max_iterations, its[c]);
+      sum_it += its[c];
+      fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
+      if (fl[c] == COL_BREAKDOWN) fs.n_breakdown++;
+      if (fl[c] == COL_MAXIT) fs.n_maxit++;
+    }
+  }
+  launch_filter_sum<double>(s, n, L, N, Y, w, U, false);
+  HIPCHK(ctx, hipGetLastError());
+  std::vector<double> rr(K);
+  HIPCHK(ctx, hipMemcpyAsync(rr.data(), relres, 8 * (size_t)K, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (stats) {
+    for (int c = 0; c < K; ++c) fs.max_relres = std::max(fs.max_relres, rr[c]);
+    fs.mean_iterations = K ? sum_it / K : 0.0;
+    fs.refinements = rounds;
+    fs.seconds = now_s() - t0;
+    *stats = fs;
+  }
+  return SLRF_OK;
+}
+
 // One Rayleigh-Ritz pass: Y = Xin Z with (Y^T A Y, Y^T B Y) = (diag(theta), I).
 slrf_status rr_pass(slrf_ctx ctx, int L, const double* Xin, double* Y, double* WA, double* WB, double* part,
                     int nch, double* GA, double* GB, double* Zd, std::vector<double>& theta) {
@@ -470,8 +652,8 @@ slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma
 
 slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
   if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
-  if (precision != SLRF_FP64) return SLRF_E_INVALID_ARG;
-  *bytes = static_bytes_for(n, nnz) + krylov_bytes_fp64(n, nnz, L, N) + outer_bytes(n, L);
+  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  *bytes = static_bytes_for(n, nnz) + krylov_bytes(n, nnz, L, N, precision) + outer_bytes(n, L);
   return SLRF_OK;
 }
 
@@ -492,7 +674,8 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
       max_N < 1)
     return bail(SLRF_E_INVALID_ARG, "bad size or NULL argument");
   if (opt) ctx->opt = *opt; else slrf_default_options(&ctx->opt);
-  if (ctx->opt.precision != SLRF_FP64) return bail(SLRF_E_INVALID_ARG, "precision not supported by this build");
+  if (ctx->opt.precision != SLRF_FP64 && ctx->opt.precision != SLRF_MIXED)
+    return bail(SLRF_E_INVALID_ARG, "unknown precision");
   ctx->n = n;
   ctx->verbose = getenv("SLRF_VERBOSE") != nullptr;
   ctx->stream = (hipStream_t)hip_stream;
@@ -564,7 +747,16 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   ctx->diagpos = cv.take<int>(n);
   ctx->timer.d_counts = cv.take<int>(kTimerSlots);
   int* sched_dev = cv.take<int>(n);
+  ctx->ab32 = cv.take<ab_pair<float>>(nnz);
+  ctx->diagA32 = cv.take<float>(n);
+  ctx->diagB32 = cv.take<float>(n);
   ctx->static_bytes = cv.off;
+  std::vector<float> ab32(2 * (size_t)nnz), dA32(n), dB32(n);
+  for (size_t k = 0; k < 2 * (size_t)nnz; ++k) ab32[k] = (float)ab[k];
+  for (int64_t i = 0; i < n; ++i) {
+    dA32[i] = (float)dA[i];
+    dB32[i] = (float)dB[i];
+  }
   std::vector<int32_t> order;
   if (band_schedule(n, rp, cl, order)) ctx->sched = sched_dev;
   if (ctx->opt.profile) {
@@ -580,7 +772,9 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (cp(ctx->rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(ctx->col, cl.data(), 4 * nnz) != hipSuccess ||
       cp(ctx->ab64, ab.data(), 16 * nnz) != hipSuccess || cp(ctx->diagA, dA.data(), 8 * n) != hipSuccess ||
       cp(ctx->diagB, dB.data(), 8 * n) != hipSuccess || cp(ctx->diagpos, dpos.data(), 4 * n) != hipSuccess ||
-      (ctx->sched && cp(ctx->sched, order.data(), 4 * n) != hipSuccess) || hipStreamSynchronize(s) != hipSuccess)
+      (ctx->sched && cp(ctx->sched, order.data(), 4 * n) != hipSuccess) ||
+      cp(ctx->ab32, ab32.data(), 8 * nnz) != hipSuccess || cp(ctx->diagA32, dA32.data(), 4 * n) != hipSuccess ||
+      cp(ctx->diagB32, dB32.data(), 4 * n) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
     return bail(SLRF_E_DEVICE, "upload of the merged CSR failed");
   if (ctx->use_ilu) {
     ctx->h_rp = std::move(rp);
@@ -602,6 +796,7 @@ slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L, 
   slrf_status st = check_poles(ctx, poles);
   if (st != SLRF_OK) return st;
   Carver cv{ctx->ws, ctx->static_bytes, ctx->ws_bytes};
+  if (ctx->opt.precision == SLRF_MIXED) return filter_mixed(ctx, cv, poles, (int)L, d_X, d_U, stats, ctx->opt.inner_tol);
   return filter_fp64(ctx, cv, poles, (int)L, d_X, d_U, stats);
 }
 
@@ -629,7 +824,8 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
   if (st != SLRF_OK) return st;
   hipStream_t s = ctx->stream;
   // outer buffers sit after the Krylov region sized for max_L, max_N
-  Carver co{ctx->ws, ctx->static_bytes + krylov_bytes_fp64(n, ctx->nnz, ctx->max_L, ctx->max_N), ctx->ws_bytes};
+  Carver co{ctx->ws, ctx->static_bytes + krylov_bytes(n, ctx->nnz, ctx->max_L, ctx->max_N, ctx->opt.precision),
+            ctx->ws_bytes};
   const int nch = gram_chunks(n, L);
   const int nrr = (n + 255) / 256;
   double* V = co.take<double>((size_t)n * L);
@@ -652,13 +848,23 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
   slrf_solve_stats ss{};
   std::vector<double> theta, theta2, rho(L, 0.0);
   int prev_count = -1, count = 0;
-  double iter_sum = 0;
+  double iter_sum = 0, prev_maxr = INFINITY, prev_prev_maxr = INFINITY, mix_c = 1e-3;
   bool converged = false, too_small = false;
   int k = 0;
   for (k = 1; k <= std::max(1, ctx->opt.outer_maxit); ++k) {
     Carver cv{ctx->ws, ctx->static_bytes, ctx->ws_bytes};
     slrf_filter_stats fs{};
-    st = filter_fp64(ctx, cv, poles, L, V, U, &fs);
+    if (ctx->opt.precision == SLRF_MIXED) {
+      // Inner accuracy follows the outer residual: target = c * (largest residual
+      // of the previous outer iteration), within [1e-13, 1e-4].  The residual of a
+      // Ritz pair amplifies the inner error by up to ~lambda_max / theta, so when
+      // an outer iteration fails to cut the residual 3x, c shrinks 100x.
+      if (prev_prev_maxr < INFINITY && prev_maxr > 0.3 * prev_prev_maxr) mix_c = std::max(1e-9, mix_c * 1e-2);
+      const double target = std::max(1e-13, std::min(1e-4, mix_c * prev_maxr));
+      st = filter_mixed(ctx, cv, poles, L, V, U, &fs, target);
+    } else {
+      st = filter_fp64(ctx, cv, poles, L, V, U, &fs);
+    }
     if (st != SLRF_OK) return st;
     ss.filter_seconds += fs.seconds;
     ss.spmv_total += fs.spmv;
@@ -693,11 +899,13 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const s
       }
     }
     ss.max_resid = maxr;
+    prev_prev_maxr = prev_maxr;
+    prev_maxr = count ? maxr : INFINITY;
     if (ctx->verbose)
-      fprintf(stderr, "[slrf] outer %d: inner its mean %.1f max %d (maxit %d, breakdown %d, max relres %.2e) "
-                      "theta [%.6g, %.6g] count %d max rho %.3e\n",
-              k, fs.mean_iterations, fs.max_iterations, fs.n_maxit, fs.n_breakdown, fs.max_relres, theta2[0],
-              theta2[L - 1], count, maxr);
+      fprintf(stderr, "[slrf] outer %d: inner its mean %.1f max %d (rounds %d, maxit %d, breakdown %d, max relres "
+                      "%.2e) theta [%.6g, %.6g] count %d max rho %.3e\n",
+              k, fs.mean_iterations, fs.max_iterations, fs.refinements, fs.n_maxit, fs.n_breakdown, fs.max_relres,
+              theta2[0], theta2[L - 1], count, maxr);
     if (count == L) {
       too_small = true;
       break;
