@@ -377,31 +377,67 @@ __global__ __launch_bounds__(WG) void k_update_x(KGeom g, KrylovState<R> st, int
   }
 }
 
-template <typename R>
-__device__ __forceinline__ cx<R> sum_part_cx(const cx<R>* part, int nrb, int K, int c) {
-  R sr = 0, si = 0;
-  for (int b = 0; b < nrb; ++b) {
-    const cx<R> v = part[(size_t)b * K + c];
-    sr += v.re;
-    si += v.im;
+// Per-column sums of the [G][K] partials, one 256-thread block per 64-column
+// tile: wavefront w adds partials w, w + 4, w + 8, ... (independent loads, kept
+// in flight by unrolling), then the 4 wavefront sums are added in a fixed
+// order.  Every wavefront of the block receives the total.
+template <typename T>
+__device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int K, int c, bool valid) {
+  __shared__ T red[4][WAVE];
+  const int w = wave_id(), lane = lane_id();
+  T acc = 0;
+  if (valid) {
+#pragma unroll 8
+    for (int b = w; b < G; b += 4) acc += part[(size_t)b * K + c];
   }
-  return {sr, si};
+  red[w][lane] = acc;
+  __syncthreads();
+  const T tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  __syncthreads();
+  return tot;
 }
+
 template <typename R>
-__device__ __forceinline__ R sum_part(const R* part, int nrb, int K, int c) {
-  R s = 0;
-  for (int b = 0; b < nrb; ++b) s += part[(size_t)b * K + c];
-  return s;
+__device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int K, int c, bool valid) {
+  const R* p = reinterpret_cast<const R*>(part);
+  // real and imaginary parts are interleaved: sum them as two strided streams
+  __shared__ R rr[4][WAVE], ri[4][WAVE];
+  const int w = wave_id(), lane = lane_id();
+  R ar = 0, ai = 0;
+  if (valid) {
+#pragma unroll 8
+    for (int b = w; b < G; b += 4) {
+      const cx<R> v = part[(size_t)b * K + c];
+      ar += v.re;
+      ai += v.im;
+    }
+  }
+  rr[w][lane] = ar;
+  ri[w][lane] = ai;
+  __syncthreads();
+  const cx<R> tot = {rr[0][lane] + rr[1][lane] + rr[2][lane] + rr[3][lane],
+                     ri[0][lane] + ri[1][lane] + ri[2][lane] + ri[3][lane]};
+  __syncthreads();
+  (void)p;
+  return tot;
 }
+
 template <typename R>
 __device__ __forceinline__ bool cfinite(cx<R> z) { return isfinite(z.re) && isfinite(z.im); }
 
+// The per-column scalar kernels run one block per 64-column tile; wavefront 0
+// applies the update after the block-wide reduction.
+#define SC_PROLOGUE                              \
+  const int c = blockIdx.x * WAVE + lane_id();   \
+  const bool valid = c < g.K;                    \
+  const bool lead = wave_id() == 0 && valid;
+
 // alpha = rho / (rhat, v)
 template <typename R>
-__global__ void k_sc_alpha(KGeom g, KrylovState<R> st) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const cx<R> rv = sum_part_cx(st.part_a, g.G, g.K, c);
+__global__ __launch_bounds__(WG) void k_sc_alpha(KGeom g, KrylovState<R> st) {
+  SC_PROLOGUE
+  const cx<R> rv = block_col_sum_cx(st.part_a, g.G, g.K, c, valid);
+  if (!lead || st.flags[c] != COL_ACTIVE) return;
   const cx<R> rho = st.rho[c];
   if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
     st.flags[c] = COL_BREAKDOWN;
@@ -413,10 +449,10 @@ __global__ void k_sc_alpha(KGeom g, KrylovState<R> st) {
 
 // half-step test ||s|| <= tol ||f||
 template <typename R>
-__global__ void k_sc_half(KGeom g, KrylovState<R> st, R tol) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const R sn = sqrt(sum_part(st.part_b, g.G, g.K, c));
+__global__ __launch_bounds__(WG) void k_sc_half(KGeom g, KrylovState<R> st, R tol) {
+  SC_PROLOGUE
+  const R sn = sqrt(block_col_sum(st.part_b, g.G, g.K, c, valid));
+  if (!lead || st.flags[c] != COL_ACTIVE) return;
   if (sn <= tol * st.fnorm[c]) {
     st.flags[c] = COL_HALF_PENDING;
     st.rnorm[c] = sn;
@@ -425,11 +461,11 @@ __global__ void k_sc_half(KGeom g, KrylovState<R> st, R tol) {
 
 // omega = (t, s) / (t, t)
 template <typename R>
-__global__ void k_sc_omega(KGeom g, KrylovState<R> st) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.K || st.flags[c] != COL_ACTIVE) return;
-  const cx<R> ts = sum_part_cx(st.part_a, g.G, g.K, c);
-  const R tt = sum_part(st.part_b, g.G, g.K, c);
+__global__ __launch_bounds__(WG) void k_sc_omega(KGeom g, KrylovState<R> st) {
+  SC_PROLOGUE
+  const cx<R> ts = block_col_sum_cx(st.part_a, g.G, g.K, c, valid);
+  const R tt = block_col_sum(st.part_b, g.G, g.K, c, valid);
+  if (!lead || st.flags[c] != COL_ACTIVE) return;
   if (tt == 0 || !isfinite(tt)) {
     st.flags[c] = COL_BREAKDOWN;
     return;
@@ -439,17 +475,17 @@ __global__ void k_sc_omega(KGeom g, KrylovState<R> st) {
 
 // rho_new = (rhat, r); ||r|| test; beta = (rho_new / rho)(alpha / omega)
 template <typename R>
-__global__ void k_sc_beta(KGeom g, KrylovState<R> st, R tol, int maxit) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.K) return;
+__global__ __launch_bounds__(WG) void k_sc_beta(KGeom g, KrylovState<R> st, R tol, int maxit) {
+  SC_PROLOGUE
+  const cx<R> rn = block_col_sum_cx(st.part_a, g.G, g.K, c, valid);
+  const R nn = sqrt(block_col_sum(st.part_b, g.G, g.K, c, valid));
+  if (!lead) return;
   const int f = st.flags[c];
   if (f == COL_HALF_PENDING) {
     st.flags[c] = COL_HALF_CONVERGED;
     return;
   }
   if (f != COL_ACTIVE) return;
-  const cx<R> rn = sum_part_cx(st.part_a, g.G, g.K, c);
-  const R nn = sqrt(sum_part(st.part_b, g.G, g.K, c));
   st.rnorm[c] = nn;
   if (nn <= tol * st.fnorm[c]) {
     st.flags[c] = COL_CONVERGED;
@@ -521,7 +557,7 @@ void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st, c
                       const int* col, const ab_pair<R>* ab, R tol, int maxit, bool first,
                       const IluFactors<R>* ilu, LaunchTimer* tm, double matrix_bytes) {
   const dim3 grid((unsigned)g.G), blk(WG);
-  const dim3 cgrid((g.K + 255) / 256), cblk(256);
+  const dim3 cgrid((unsigned)g.nct), cblk(WG);
   const dim3 igrid((g.K + 63) / 64), iblk(64);
   // algorithmic traffic: n x K complex passes per fully processed launch, plus
   // per-launch fixed bytes (merged CSR; shared real rhat (n, L); diagonals (n, N))
@@ -582,10 +618,10 @@ __global__ __launch_bounds__(WG) void k_init(KGeom g, KrylovState<R> st, const R
 }
 
 template <typename R>
-__global__ void k_init_scalars(KGeom g, KrylovState<R> st) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.K) return;
-  const R nn = sum_part(st.part_b, g.G, g.K, c);
+__global__ __launch_bounds__(WG) void k_init_scalars(KGeom g, KrylovState<R> st) {
+  SC_PROLOGUE
+  const R nn = block_col_sum(st.part_b, g.G, g.K, c, valid);
+  if (!lead) return;
   st.fnorm[c] = sqrt(nn);
   st.rnorm[c] = sqrt(nn);
   st.rho[c] = {nn, 0};
@@ -602,7 +638,7 @@ void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const 
 }
 template <typename R>
 void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st) {
-  k_init_scalars<R><<<dim3((g.K + 255) / 256), dim3(256), 0, s>>>(g, st);
+  k_init_scalars<R><<<dim3((unsigned)g.nct), dim3(WG), 0, s>>>(g, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,34 +682,36 @@ void launch_defect(hipStream_t s, const KGeom& g, const int* rowptr, const int* 
   k_defect<<<dim3((unsigned)g.G), dim3(WG), 0, s>>>(g, rowptr, col, ab, sigma_col, F, Y, Rout, part);
 }
 
-__global__ void k_defect_norms(KGeom g, const double* __restrict__ part, double tol, int first,
-                               double* __restrict__ fnorm, double* __restrict__ scale, double* __restrict__ relres,
-                               int* __restrict__ count) {
+__global__ __launch_bounds__(WG) void k_defect_norms(KGeom g, const double* __restrict__ part, double tol, int first,
+                                                    double* __restrict__ fnorm, double* __restrict__ scale,
+                                                    double* __restrict__ relres) {
+  SC_PROLOGUE
+  const double r = sqrt(block_col_sum(part, g.G, g.K, c, valid));
+  if (!lead) return;
+  if (first) fnorm[c] = r;
+  const double fn = fnorm[c];
+  const bool done = r <= tol * fn;
+  scale[c] = done ? 0.0 : r;
+  relres[c] = fn > 0 ? r / fn : 0.0;
+}
+
+__global__ void k_count_positive(int K, const double* __restrict__ v, int* __restrict__ out) {
   __shared__ int cnt[256];
   int mine = 0;
-  for (int c = threadIdx.x; c < g.K; c += blockDim.x) {
-    double sacc = 0;
-    for (int b = 0; b < g.G; ++b) sacc += part[(size_t)b * g.K + c];
-    const double r = sqrt(sacc);
-    if (first) fnorm[c] = r;
-    const double fn = fnorm[c];
-    const bool done = r <= tol * fn;
-    scale[c] = done ? 0.0 : r;
-    relres[c] = fn > 0 ? r / fn : 0.0;
-    mine += done ? 0 : 1;
-  }
+  for (int c = threadIdx.x; c < K; c += 256) mine += v[c] > 0 ? 1 : 0;
   cnt[threadIdx.x] = mine;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) cnt[threadIdx.x] += cnt[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) count[0] = cnt[0];
+  if (threadIdx.x == 0) out[0] = cnt[0];
 }
 
 void launch_defect_norms(hipStream_t s, const KGeom& g, const double* part, double tol, int first, double* fnorm,
                          double* scale, double* relres, int* count) {
-  k_defect_norms<<<1, 256, 0, s>>>(g, part, tol, first, fnorm, scale, relres, count);
+  k_defect_norms<<<dim3((unsigned)g.nct), dim3(WG), 0, s>>>(g, part, tol, first, fnorm, scale, relres);
+  k_count_positive<<<1, 256, 0, s>>>(g.K, scale, count);
 }
 
 __global__ __launch_bounds__(WG) void k_mixed_rhs(KGeom g, const cx<double>* __restrict__ R,
