@@ -78,6 +78,9 @@ typedef struct {
   int32_t profile;     /* 1: time the sparse-product and vector-update kernels with HIP
                           events and count the column tiles each launch processes
                           (stats fields spmm_* and update_*); 0: off */
+  int32_t graph;       /* 1: capture check_every BiCGStab iterations (and the poll of the
+                          active count) once per Krylov run as a hipGraph and replay it;
+                          needs a non-NULL stream and profile = 0, else ignored.  0: off */
 } slrf_options;
 
 typedef struct {
@@ -114,7 +117,7 @@ typedef struct {
 } slrf_solve_stats;
 
 /* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
- * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0. */
+ * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0. */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance
@@ -172,6 +175,71 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slr
 void slrf_destroy(slrf_ctx ctx);
 const char* slrf_status_string(slrf_status s);
 const char* slrf_last_error(slrf_ctx ctx);
+
+/* ---- Batches: many pencils, one launch per Krylov step ---------------------
+ *
+ * A batch runs Algorithm 1 on a changing set of pencils at once.  Each outer
+ * step applies the filter to every unfinished pencil in ONE batched BiCGStab
+ * (each kernel launch covers every pole x column of every pencil; the per-
+ * pencil sizes, offsets and CSR pointers sit in a device table), then does
+ * Rayleigh-Ritz, residuals and the stopping test per pencil.  The arithmetic of
+ * each pencil is that of slrf_solve_interval with the same options, poles and
+ * start block (the per-column reductions are summed in a fixed order that does
+ * not depend on the other pencils, so a pencil's result is bitwise the same
+ * alone or in a batch when the Krylov grid is the same).
+ *
+ * Workspace (device, 256-byte aligned, caller-owned): a filter arena of
+ * arena_bytes shared by the pencils of one step, and a pool for each pencil's
+ * persistent data (merged CSR, subspace blocks).  slrf_batch_footprint gives
+ * both parts for one pencil; the arena needed by a set of pencils is at most
+ * the sum of their transient parts.  Pencils can be added between steps
+ * (continuous batching) and removed once finished, which frees their pool
+ * space.  Not thread-safe; one batch per stream. */
+typedef struct slrf_batch_s* slrf_batch;
+
+/* Bytes one pencil needs: persistent_bytes in the pool (kept from add to
+ * remove) and transient_bytes of filter arena while it is unfinished. */
+slrf_status slrf_batch_footprint(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
+                                 int32_t precision, size_t* persistent_bytes,
+                                 size_t* transient_bytes);
+
+/* d_workspace: device, 256-byte aligned, ws_bytes >= arena_bytes + 2 KiB; the
+ * rest after the arena becomes the pool.  max_poles: largest N of any pencil
+ * (1..16).  opt may be NULL.  On failure *out may hold a batch: read
+ * slrf_batch_last_error(*out), then slrf_batch_destroy(*out). */
+slrf_status slrf_batch_create(slrf_batch* out, void* d_workspace, size_t ws_bytes,
+                              size_t arena_bytes, int32_t max_poles,
+                              const slrf_options* opt, void* hip_stream);
+
+/* Adds a pencil (CSR arrays as for slrf_create, host) to find every eigenpair in
+ * (0, gamma] with an L-column subspace; poles NULL designs N = 4 as in
+ * slrf_solve_interval; d_V0 device (n, L) start block or NULL (seeded
+ * Gaussian), copied before return.  *id receives its handle.  SLRF_E_WORKSPACE
+ * if the pool or the arena (with the unfinished pencils) cannot take it: the
+ * caller may retry after a step finishes or removes pencils. */
+slrf_status slrf_batch_add(slrf_batch b, int64_t n,
+                           const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                           const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                           double gamma, int64_t L, const slrf_poles* poles,
+                           const double* d_V0, int32_t* id);
+
+/* One outer iteration for every unfinished pencil.  *n_active (may be NULL)
+ * gets the number still unfinished.  A device or breakdown error ends every
+ * pencil of the step with that status. */
+slrf_status slrf_batch_step(slrf_batch b, int32_t* n_active);
+
+/* done = 1 once the pencil has stopped (converged, too small, limit, error). */
+slrf_status slrf_batch_query(slrf_batch b, int32_t id, int32_t* done, int32_t* outer_iterations);
+
+/* Results of a finished pencil, as slrf_solve_interval returns them; the
+ * return value is that pencil's final status. */
+slrf_status slrf_batch_result(slrf_batch b, int32_t id, int64_t* n_found, double* h_evals,
+                              double* d_evecs, double* h_resid, slrf_solve_stats* stats);
+
+/* Frees the pencil's pool space; the id becomes invalid. */
+slrf_status slrf_batch_remove(slrf_batch b, int32_t id);
+void slrf_batch_destroy(slrf_batch b);
+const char* slrf_batch_last_error(slrf_batch b);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,8 @@ STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_D
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
-                ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32)]
+                ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class Poles(C.Structure):
@@ -74,8 +75,23 @@ _lib.slrf_status_string.argtypes = [C.c_int]
 _lib.slrf_status_string.restype = C.c_char_p
 _lib.slrf_last_error.argtypes = [_P]
 _lib.slrf_last_error.restype = C.c_char_p
+_lib.slrf_batch_footprint.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+_lib.slrf_batch_create.argtypes = [C.POINTER(_P), _P, C.c_size_t, C.c_size_t, C.c_int32,
+                                   C.POINTER(Options), _P]
+_lib.slrf_batch_add.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_double, C.c_int64,
+                                C.POINTER(Poles), _P, C.POINTER(C.c_int32)]
+_lib.slrf_batch_step.argtypes = [_P, C.POINTER(C.c_int32)]
+_lib.slrf_batch_query.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+_lib.slrf_batch_result.argtypes = [_P, C.c_int32, C.POINTER(C.c_int64), _P, _P, _P,
+                                   C.POINTER(SolveStats)]
+_lib.slrf_batch_remove.argtypes = [_P, C.c_int32]
+_lib.slrf_batch_destroy.argtypes = [_P]
+_lib.slrf_batch_last_error.argtypes = [_P]
+_lib.slrf_batch_last_error.restype = C.c_char_p
 for _f in ("slrf_design_poles", "slrf_workspace_bytes", "slrf_create", "slrf_filter_apply",
-           "slrf_solve_interval"):
+           "slrf_solve_interval", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
+           "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove"):
     getattr(_lib, _f).restype = C.c_int
 
 _lib.slrf_test_gram.argtypes = [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
@@ -87,7 +103,9 @@ _lib.slrf_test_gram_scratch.restype = C.c_size_t
 
 EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_workspace_bytes", "slrf_create",
             "slrf_filter_apply", "slrf_solve_interval", "slrf_destroy", "slrf_status_string",
-            "slrf_last_error"]
+            "slrf_last_error", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
+            "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove",
+            "slrf_batch_destroy", "slrf_batch_last_error"]
 TESTING_EXPORTED = ["slrf_test_gram", "slrf_test_gemm", "slrf_test_gram_scratch"]
 
 
@@ -172,6 +190,18 @@ def _union_nnz(A, B) -> int:
     return int((abs(A) + abs(B)).nnz) if (A.nnz != B.nnz or (A.indices != B.indices).any()) else int(A.nnz)
 
 
+def _csr_arrays(A, B):
+    """Sorted CSR of A and B as the six host arrays the C ABI takes, plus n and the union nnz."""
+    A = A.tocsr()
+    B = B.tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    arrs = [np.ascontiguousarray(x) for x in (
+        A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64),
+        B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64))]
+    return A.shape[0], _union_nnz(A, B), arrs
+
+
 @dataclass
 class SolveResult:
     status: int
@@ -190,21 +220,13 @@ class Solver:
                  device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
-        A = A.tocsr()
-        B = B.tocsr()
-        A.sort_indices()
-        B.sort_indices()
-        self.n = A.shape[0]
+        self.n, nnz, arrs = _csr_arrays(A, B)
         self.device = torch.device(device)
         self.options = options or default_options()
-        nnz = _union_nnz(A, B)
         self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, self.options.precision)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._h = C.c_void_p()
-        arrs = [np.ascontiguousarray(x) for x in (
-            A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64),
-            B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64))]
         st = _lib.slrf_create(C.byref(self._h), self.n, *[_ptr(a) for a in arrs],
                               C.c_void_p(self.workspace.data_ptr()), self.ws_bytes, max_L, max_poles,
                               C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
@@ -272,3 +294,114 @@ class Solver:
         if st and raise_on_error and st not in (5,):
             raise SlrfError(st, msg)
         return SolveResult(st, evals, evecs, resid, nf.value, stats.as_dict(), msg)
+
+
+def batch_footprint(n: int, nnz: int, L: int, N: int, precision: int = FP64):
+    """(persistent, transient) device bytes of one pencil in a Batch."""
+    p, t = C.c_size_t(), C.c_size_t()
+    st = _lib.slrf_batch_footprint(n, nnz, L, N, precision, C.byref(p), C.byref(t))
+    if st:
+        raise SlrfError(st, "batch footprint")
+    return p.value, t.value
+
+
+class Batch:
+    """Many pencils solved together: one batched Krylov launch per step for all
+    unfinished pencils; pencils may join between steps and leave when done."""
+
+    def __init__(self, ws_bytes: int, arena_bytes: int, max_poles: int = 4,
+                 options: Options | None = None, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.options = options or default_options()
+        self.ws_bytes = int(ws_bytes)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._h = C.c_void_p()
+        self.n_of = {}
+        self.L_of = {}
+        st = _lib.slrf_batch_create(C.byref(self._h), C.c_void_p(self.workspace.data_ptr()),
+                                    self.ws_bytes, int(arena_bytes), max_poles,
+                                    C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
+        if st:
+            msg = self.last_error()
+            self.close()
+            raise SlrfError(st, msg)
+
+    def last_error(self) -> str:
+        if not self._h:
+            return ""
+        return _lib.slrf_batch_last_error(self._h).decode()
+
+    def close(self):
+        if self._h:
+            _lib.slrf_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, A, B, gamma: float, L: int, sigma=None, w=None, V0=None, must_fit: bool = True):
+        """Adds a pencil; returns its id, or None when it does not fit and must_fit is False."""
+        t = self.torch
+        n, _, arrs = _csr_arrays(A, B)
+        pp = None
+        keep = None
+        if sigma is not None:
+            p, keep = _poles_struct(sigma, w)
+            pp = C.byref(p)
+        v0 = None
+        if V0 is not None:
+            if not isinstance(V0, t.Tensor):
+                V0 = t.as_tensor(np.ascontiguousarray(V0, dtype=np.float64))
+            v0 = V0.to(device=self.device, dtype=t.float64).contiguous()
+        pid = C.c_int32()
+        st = _lib.slrf_batch_add(self._h, n, *[_ptr(a) for a in arrs], gamma, L, pp,
+                                 C.c_void_p(v0.data_ptr()) if v0 is not None else None, C.byref(pid))
+        del keep
+        if st == 3 and not must_fit:
+            return None
+        if st:
+            raise SlrfError(st, self.last_error())
+        self.n_of[pid.value] = n
+        self.L_of[pid.value] = L
+        return pid.value
+
+    def step(self) -> int:
+        act = C.c_int32()
+        st = _lib.slrf_batch_step(self._h, C.byref(act))
+        if st:
+            raise SlrfError(st, self.last_error())
+        return act.value
+
+    def query(self, pid: int):
+        """(done, outer iterations so far)."""
+        d, k = C.c_int32(), C.c_int32()
+        st = _lib.slrf_batch_query(self._h, pid, C.byref(d), C.byref(k))
+        if st:
+            raise SlrfError(st, self.last_error())
+        return bool(d.value), k.value
+
+    def result(self, pid: int) -> SolveResult:
+        t = self.torch
+        n, L = self.n_of[pid], self.L_of[pid]
+        evecs = t.empty((n, L), dtype=t.float64, device=self.device)
+        evals = np.zeros(L)
+        resid = np.zeros(L)
+        nf = C.c_int64()
+        stats = SolveStats()
+        st = _lib.slrf_batch_result(self._h, pid, C.byref(nf), _ptr(evals), C.c_void_p(evecs.data_ptr()),
+                                    _ptr(resid), C.byref(stats))
+        msg = self.last_error() if st else ""
+        return SolveResult(st, evals, evecs, resid, nf.value, stats.as_dict(), msg)
+
+    def remove(self, pid: int):
+        st = _lib.slrf_batch_remove(self._h, pid)
+        if st:
+            raise SlrfError(st, self.last_error())
+        self.n_of.pop(pid, None)
+        self.L_of.pop(pid, None)

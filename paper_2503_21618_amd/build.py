@@ -2,6 +2,7 @@
 
     python -m paper_2503_21618_amd.build        (or build() from Python)
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -13,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 HOST_SRC = ["dense.cpp", "poles.cpp"]
-HIP_SRC = ["kernels.hip", "solver.hip"]
+HIP_SRC = ["kernels.hip", "krylov.hip", "solver.hip"]
 # packed FP32 instructions are disabled for all device code
 HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,15 +31,17 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    steps = []
     for src in HOST_SRC:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O3", "-fPIC", "-std=c++17", "-pthread", "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        steps.append((["g++", "-O3", "-fPIC", "-std=c++17", "-pthread", "-c", os.path.join(CSRC, src),
+                       "-o", obj], obj))
     for src in HIP_SRC:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        steps.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(steps), 4)) as pool:
+        list(pool.map(lambda st: _run(st[0]), steps))
+    objs = [obj for _, obj in steps]
     tmp = OUT + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, OUT)

@@ -26,27 +26,42 @@ enum ColFlag : int {
   COL_HALF_PENDING = 5,  // converged at the half step; x still takes alpha * p_hat
 };
 
-// Geometry of an (n, K) complex Krylov block: rows split into row blocks of
-// `rows_per_block`, columns into tiles of 64 (one column per lane).  Every
-// kernel over the block uses the same grid of G workgroups, so per-column
-// partial sums live in [G][K] arrays and are reduced in a fixed order.
-struct KGeom {
-  int n;
-  int K;             // columns = poles * L, pole-major (c = j * L + l)
-  int L;
-  int N;             // poles
-  int rows_per_block;
-  int nrb;           // row blocks
-  int nct;           // column tiles of 64
-  int slab;          // row blocks per XCD
-  int G;             // workgroups (a multiple of 8)
-  int steps;         // row-block steps per tile per workgroup
-  const int* sched;  // sparse-product row order (a permutation of 0..n-1), or null
+constexpr int kMaxGrid = 1024;  // workgroups of the Krylov kernels (a multiple of 8)
+
+// One pencil of a batch as the Krylov kernels see it.  Its Krylov block is a
+// row-major (n, K) complex array, K = N * L, column c = j * L + l belonging to
+// pole j and right-hand side l.  Global columns of the batch are the pencils'
+// columns one after the other; global 64-column tiles likewise.
+struct Inst {
+  int n, K, L, N;        // rows, columns, right-hand sides, poles
+  int nrb, slab, steps;  // row blocks, row blocks per XCD, steps per workgroup
+  int col0, tile0;       // first global column and first global tile
+  int nnz;
+  int64_t blk;           // element offset of the (n, K) blocks
+  int64_t rl;            // element offset of the (n, L) real blocks (rhat, F)
+  int64_t dn;            // element offset of the (n, N) diagonal blocks
+  const int* rowptr;
+  const int* col;
+  const void* ab;               // ab_pair<R> in the Krylov precision
+  const ab_pair<double>* ab64;  // FP64 values (defect of the mixed path)
+  const int* sched;             // sparse-product row order, or null
+  const int* diagpos;           // position of each row's diagonal (ILU)
+  const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
 };
-constexpr int kMaxGrid = 1024;  // G <= kMaxGrid
 
-KGeom make_geom(int n, int N, int L, int rows_per_block);
+// Kernel argument describing a whole batch (device tables).
+struct Batch {
+  const Inst* inst;       // [count]
+  const int* tile_inst;   // [n_tiles] pencil of each global tile
+  const int* col_inst;    // [Ktot] pencil of each global column
+  int n_tiles;
+  int Ktot;
+  int G;                  // grid, a multiple of 8
+  int rows_per_block;
+};
 
+// Krylov vectors: base pointers of the concatenated per-pencil blocks; per
+// column arrays are indexed by global column; partial sums are [G][Ktot].
 template <typename R>
 struct KrylovState {
   cx<R>* x;
@@ -57,14 +72,13 @@ struct KrylovState {
   cx<R>* t;
   cx<R>* p;    // unpreconditioned search direction (general preconditioner only)
   cx<R>* s;    // unpreconditioned half-step residual (general preconditioner only)
-  const R* rhat;       // (n, L) shared shadow residual = right-hand side
-  const cx<R>* rhat_cx;  // (n, K) per-column complex shadow residual (used when non-null)
-  const cx<R>* d;      // (n, N) shifted-operator diagonal
-  const cx<R>* dinv;   // (n, N) its inverse
-  const cx<R>* sigma_col;  // (K) pole of each column
-  cx<R>* part_a;       // (nrb, K) complex partial sums
-  R* part_b;           // (nrb, K) real partial sums
-  // per-column scalars
+  const R* rhat;         // real (n, L) shadow residual per pencil (at Inst::rl)
+  const cx<R>* rhat_cx;  // per-column complex shadow residual (at Inst::blk), if non-null
+  const cx<R>* d;        // (n, N) shifted-operator diagonals (at Inst::dn)
+  const cx<R>* dinv;
+  const cx<R>* sigma_col;  // [Ktot] pole of each column
+  cx<R>* part_a;
+  R* part_b;
   cx<R>* rho;
   cx<R>* alpha;
   cx<R>* omega;
@@ -75,22 +89,10 @@ struct KrylovState {
   int* iters;
 };
 
-// ILU(0) factors of A - sigma_j B on the merged pattern, one value array per pole
-// (L strictly lower with unit diagonal, U upper; the U diagonal is stored inverted).
-template <typename R>
-struct IluFactors {
-  const int* rowptr;
-  const int* col;
-  const int* diagpos;  // position of the diagonal entry in each row
-  const cx<R>* f;      // (N, nnz)
-  int64_t nnz;
-};
-
 // Optional per-launch instrumentation of the Krylov kernels: a HIP event pair
 // around each sparse-product / vector-update launch and a device counter of the
-// column tiles the launch processed (tiles whose columns are all converged exit
-// at once).  Host-side records say which kernel and how many n x K passes it
-// makes per processed tile.
+// (workgroup, tile) pairs the launch processed (tiles whose columns are all
+// converged exit at once).
 struct LaunchTimer {
   hipEvent_t* events = nullptr;  // 2 * capacity
   int* d_counts = nullptr;       // capacity
@@ -102,43 +104,47 @@ struct LaunchTimer {
     double fixed;       // bytes read once per launch whatever the tiles (merged CSR)
   };
   Rec recs[512];
-  // returns the counter for the next launch (records its start event) or nullptr
   int* begin(hipStream_t s, int kind, double tile_bytes, double fixed);
   void end(hipStream_t s);
 };
 
-// ---- launchers (stream-ordered) -----------------------------------------
+// Algorithmic byte counts of one batch iteration (for the timer).
+struct IterBytes {
+  double blk;      // one pass over every (n, K) block
+  double rhat;     // the (n, L) real blocks
+  double diag;     // the (n, N) diagonal blocks
+  double matrix;   // every merged CSR once
+};
+
+// ---- batched Krylov launchers (stream-ordered) ----------------------------
+template <typename R>
+void launch_init(hipStream_t s, const Batch& b, const KrylovState<R>& st, const R* F);
+template <typename R>
+void launch_init_scalars(hipStream_t s, const Batch& b, const KrylovState<R>& st);
+template <typename R>
+void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
+                      bool first, bool ilu, LaunchTimer* timer, const IterBytes& bytes);
+void launch_count_active(hipStream_t s, int Ktot, const int* flags, int* out);
+
+// Mixed precision (FP32 inner solves, FP64 defect correction).
+// R = F - S Y in FP64 (Y null: R = F and R is not written), partial |R|^2 in part [G][Ktot].
+void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, const double* F,
+                   const cx<double>* Y, cx<double>* Rout, double* part);
+// scale_c = ||R_c|| if ||R_c|| > tol_c ||F_c|| else 0 (tol per column); the first round
+// sets fnorm_c = ||F_c||; *count = number of columns with scale_c > 0.
+void launch_defect_norms(hipStream_t s, const Batch& b, const double* part, const double* tol,
+                         int first, double* fnorm, double* scale, double* relres, int* count);
+// r = R / scale (R null: F / scale), rhat = r, x = 0 in FP32; partial |r|^2 into part_b.
+void launch_mixed_rhs(hipStream_t s, const Batch& b, const cx<double>* R, const double* F,
+                      const double* scale, const KrylovState<float>& st, cx<float>* rhat);
+// Y += scale x (first: Y = scale x)
+void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const double* scale,
+                       cx<double>* Y, int first);
+
+// ---- per-pencil launchers -------------------------------------------------
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
                         const cx<R>* sigma, cx<R>* d, cx<R>* dinv);
-template <typename R>
-void launch_init(hipStream_t s, const KGeom& g, const KrylovState<R>& st, const R* F);
-template <typename R>
-void launch_init_scalars(hipStream_t s, const KGeom& g, const KrylovState<R>& st);
-template <typename R>
-void launch_iteration(hipStream_t s, const KGeom& g, const KrylovState<R>& st,
-                      const int* rowptr, const int* col, const ab_pair<R>* ab,
-                      R tol, int maxit, bool first, const IluFactors<R>* ilu,
-                      LaunchTimer* timer, double matrix_bytes);
-void launch_count_active(hipStream_t s, int K, const int* flags, int* out);
-
-// ---- mixed precision (FP32 inner solves, FP64 defect correction) ----------
-// R = F - S Y over all K columns in FP64 (Y null: R = F, R not written), with
-// per-column partial sums of |R|^2 into part [G][K].
-void launch_defect(hipStream_t s, const KGeom& g, const int* rowptr, const int* col,
-                   const ab_pair<double>* ab, const cx<double>* sigma_col, const double* F,
-                   const cx<double>* Y, cx<double>* Rout, double* part);
-// scale_c = ||R_c|| if ||R_c|| > tol ||F_c|| else 0; fnorm_c = ||F_c|| on the first
-// round (first != 0); writes the number of unconverged columns to *count.
-void launch_defect_norms(hipStream_t s, const KGeom& g, const double* part, double tol, int first,
-                         double* fnorm, double* scale, double* relres, int* count);
-// r = R / scale (R null: F / scale), rhat = r, x = 0 in FP32; partial |r|^2 into part_b.
-void launch_mixed_rhs(hipStream_t s, const KGeom& g, const cx<double>* R, const double* F,
-                      const double* scale, const KrylovState<float>& st, cx<float>* rhat);
-// Y += scale x (first: Y = scale x)
-void launch_accumulate(hipStream_t s, const KGeom& g, const cx<float>* x, const double* scale,
-                       cx<double>* Y, int first);
-
 template <typename R>
 void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x,
                        const double* w /* 2N */, double* U, bool accumulate);

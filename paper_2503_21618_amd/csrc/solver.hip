@@ -1,6 +1,14 @@
-// C ABI of the SLRF eigensolver: context, workspace carving, filter
-// application (Algorithm 1's shifted solves and filter sum) and the outer
-// subspace iteration with Rayleigh-Ritz and residuals.
+// C ABI of the SLRF eigensolver.
+//
+// An engine over pencils.  Each pencil's merged CSR (with its FP32 copy,
+// diagonals and sparse-product row order) is validated, built and uploaded once
+// and kept in the caller's workspace.  A filter application runs on any set of
+// (pencil, L, poles) jobs at once: the batched Krylov kernels serve every
+// pole x column of every job in one launch per step.  An outer step of
+// Algorithm 1 is one batched filter application followed by Rayleigh-Ritz,
+// residuals and the stopping test per pencil.  slrf_ctx is a batch of one
+// pencil; slrf_batch keeps a changing set of pencils (continuous batching) in
+// one workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,9 +19,11 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/slrf.h"
@@ -26,16 +36,22 @@ using namespace slrf;
 namespace {
 
 constexpr int kRowsPerBlock = 8;
-constexpr int kSubBand = 1024;  // rows per sub-band of the sparse-product row order
+constexpr int kWgPerXcd = 128;      // Krylov grid: at most 8 * 128 = kMaxGrid workgroups
+constexpr int kSubBand = 1024;      // rows per sub-band of the sparse-product row order
+constexpr int kTimerSlots = 512;
+constexpr double kInnerTol32 = 1e-6;  // relative tolerance of each FP32 correction solve
+constexpr int kMaxRounds = 6;         // defect-correction rounds per filter application
+constexpr int kDefaultPoles = 4;
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Bump allocator over a device region; with base == nullptr it only measures.
 struct Carver {
   char* base;
   size_t off = 0, cap = 0;
   template <typename T>
   T* take(size_t count) {
-    T* p = reinterpret_cast<T*>(base + off);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off = al(off + count * sizeof(T));
     return p;
   }
@@ -45,113 +61,81 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Sizes of the per-call workspace regions for (n, L, N).
-struct DynLayout {
-  size_t krylov64 = 0, outer = 0, total = 0;
-};
-
 // ILU(0) runs one thread per column over all rows: only for narrow patterns.
 bool ilu_allowed(int64_t n, int64_t nnz) { return nnz <= 5 * n; }
-
-size_t krylov_bytes_fp64(int64_t n, int64_t nnz, int64_t L, int64_t N) {
-  const int64_t K = N * L;
-  const int64_t nrb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-  size_t b = 0;
-  b += 6 * al((size_t)n * K * 16);          // x r ph v sh t
-  if (ilu_allowed(n, nnz)) b += 2 * al((size_t)n * K * 16) + al((size_t)N * nnz * 16);  // p s factors
-  b += al((size_t)n * L * 8);               // rhat = B X
-  b += 2 * al((size_t)n * N * 16);          // d, dinv
-  b += al((size_t)N * 16) + al((size_t)K * 16) + al((size_t)2 * N * 8);  // sigma, sigma_col, w
-  b += al((size_t)kMaxGrid * K * 16) + al((size_t)kMaxGrid * K * 8);      // partials [G][K]
-  b += 4 * al((size_t)K * 16) + 2 * al((size_t)K * 8) + 2 * al((size_t)K * 4) + al(256);
-  return b;
+bool use_ilu_for(int precond, int64_t n, int64_t nnz) {
+  return precond == 2 || (precond == 0 && ilu_allowed(n, nnz));
 }
 
-// MIXED: FP32 Krylov state (+ per-column complex shadow residual, p and s for
-// ILU) and the FP64 accumulator Y, defect R and right-hand side F.
-size_t krylov_bytes_mixed(int64_t n, int64_t nnz, int64_t L, int64_t N) {
-  const int64_t K = N * L;
-  size_t b = 0;
-  b += 7 * al((size_t)n * K * 8);                                           // x r ph v sh t rhat (FP32)
-  if (ilu_allowed(n, nnz)) b += 2 * al((size_t)n * K * 8) + al((size_t)N * nnz * 8);
-  b += 2 * al((size_t)n * K * 16) + al((size_t)n * L * 8);                  // Y R (FP64), F
-  b += 2 * al((size_t)n * N * 8);                                           // d, dinv (FP32)
-  b += al((size_t)N * 8) + al((size_t)K * 8) + al((size_t)K * 16) + al((size_t)2 * N * 8);
-  b += al((size_t)kMaxGrid * K * 8) + al((size_t)kMaxGrid * K * 4) + al((size_t)kMaxGrid * K * 8);
-  b += 4 * al((size_t)K * 8) + 2 * al((size_t)K * 4) + 2 * al((size_t)K * 4) + 3 * al((size_t)K * 8) + al(256);
-  return b;
-}
-
-size_t krylov_bytes(int64_t n, int64_t nnz, int64_t L, int64_t N, int precision) {
-  return precision == SLRF_MIXED ? krylov_bytes_mixed(n, nnz, L, N) : krylov_bytes_fp64(n, nnz, L, N);
-}
-
-size_t outer_bytes(int64_t n, int64_t L) {
-  const int nch = gram_chunks((int)n, (int)L);
-  const int64_t nrr = (n + 255) / 256;
-  size_t b = 0;
-  b += 5 * al((size_t)n * L * 8);                   // V U WA WB X
-  b += al((size_t)nch * 2 * L * L * 8);             // gram partials
-  b += 3 * al((size_t)L * L * 8);                   // GA GB Z
-  b += al((size_t)L * 8);                           // theta
-  b += al((size_t)(nrr * 2 * L + 2 * L) * 8);       // residual partials
-  return b;
-}
-
-}  // namespace
-
-struct slrf_ctx_s {
-  int64_t n = 0, nnz = 0;
-  hipStream_t stream = nullptr;
-  slrf_options opt{};
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  size_t static_bytes = 0;
-  int64_t max_L = 0;
-  int32_t max_N = 0;
-  int* rowptr = nullptr;
-  int* col = nullptr;
-  ab_pair<double>* ab64 = nullptr;
-  double* diagA = nullptr;
-  double* diagB = nullptr;
-  ab_pair<float>* ab32 = nullptr;  // FP32 copies for the mixed path
-  float* diagA32 = nullptr;
-  float* diagB32 = nullptr;
-  std::string err;
-  bool verbose = false;
-  bool use_ilu = false;
-  int* diagpos = nullptr;
-  int* sched = nullptr;     // sparse-product row order, null = natural order
-  // host copy of the merged CSR, kept for the per-pole ILU(0) factorisations
-  std::vector<int32_t> h_rp, h_cl, h_dpos;
-  std::vector<double> h_ab;
-  LaunchTimer timer;
-  std::vector<hipEvent_t> events;
-  ~slrf_ctx_s() {
-    for (hipEvent_t e : events)
-      if (e) (void)hipEventDestroy(e);
+// First-fit allocator over a device region (persistent data of a batch).
+struct Pool {
+  char* base = nullptr;
+  std::map<size_t, size_t> free_;  // offset -> size
+  void init(char* b, size_t s) {
+    base = b;
+    free_.clear();
+    s &= ~size_t(255);
+    if (s) free_[0] = s;
+  }
+  char* alloc(size_t bytes) {
+    bytes = al(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        return base + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(char* p, size_t bytes) {
+    if (!p) return;
+    bytes = al(bytes);
+    size_t off = (size_t)(p - base);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + bytes == nx->first) {
+      bytes += nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        bytes += pv->second;
+        free_.erase(pv);
+      }
+    }
+    free_[off] = bytes;
   }
 };
 
-namespace {
+// ---------------------------------------------------------------------------
+// Pencils
 
-slrf_status fail(slrf_ctx ctx, slrf_status s, const std::string& msg) {
-  if (ctx) ctx->err = msg;
-  return s;
-}
+struct Pencil {
+  int64_t n = 0, nnz = 0;
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  ab_pair<double>* ab64 = nullptr;
+  ab_pair<float>* ab32 = nullptr;
+  double* diagA = nullptr;
+  double* diagB = nullptr;
+  float* diagA32 = nullptr;
+  float* diagB32 = nullptr;
+  int* diagpos = nullptr;
+  int* sched = nullptr;
+  bool use_ilu = false;
+  char* mem = nullptr;  // device region holding the above
+  size_t mem_bytes = 0;
+  std::vector<int32_t> h_rp, h_cl, h_dpos;  // host copies for ILU(0)
+  std::vector<double> h_ab;
+};
 
-#define HIPCHK(ctx, call)                                                                  \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail(ctx, SLRF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-constexpr int kTimerSlots = 512;
-
-size_t static_bytes_for(int64_t n, int64_t nnz) {
-  return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + 2 * al((size_t)n * 8) +
-         al((size_t)n * 4) + al(kTimerSlots * 4) + al((size_t)n * 4) + al((size_t)nnz * 8) + 2 * al((size_t)n * 4);
+size_t pencil_bytes(int64_t n, int64_t nnz) {
+  return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + al((size_t)nnz * 8) +
+         2 * al((size_t)n * 8) + 2 * al((size_t)n * 4) + 2 * al((size_t)n * 4);
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
@@ -177,511 +161,16 @@ bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<
   return (int64_t)order.size() == n;
 }
 
-double merged_csr_bytes(const slrf_ctx ctx, size_t value_bytes) {
-  return (double)(ctx->n + 1) * 4 + (double)ctx->nnz * (4 + value_bytes);
-}
-
-// Reads back the event pairs and tile counters of the current window into the
-// kernel statistics, then clears the window.
-slrf_status harvest_timer(slrf_ctx ctx, int64_t total_tiles, slrf_filter_stats* fs) {
-  LaunchTimer& tm = ctx->timer;
-  if (tm.used == 0) return SLRF_OK;
-  std::vector<int> cnt(tm.used);
-  HIPCHK(ctx, hipMemcpyAsync(cnt.data(), tm.d_counts, 4 * (size_t)tm.used, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  for (int u = 0; u < tm.used; ++u) {
-    float ms = 0;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, tm.events[2 * u], tm.events[2 * u + 1]));
-    const LaunchTimer::Rec& r = tm.recs[u];
-    const double bytes = r.tile_bytes * (double)cnt[u] / (double)total_tiles + (cnt[u] > 0 ? r.fixed : 0.0);
-    if (r.kind == 0) {
-      fs->spmm_seconds += 1e-3 * ms;
-      fs->spmm_launches += 1;
-      fs->spmm_bytes += bytes;
-    } else {
-      fs->update_seconds += 1e-3 * ms;
-      fs->update_launches += 1;
-      fs->update_bytes += bytes;
-    }
-  }
-  tm.used = 0;
-  launch_fill_zero(ctx->stream, tm.d_counts, 4 * (size_t)tm.capacity);
-  return SLRF_OK;
-}
-
-// ILU(0) of A - sigma B on the merged pattern (row-wise IKJ elimination without
-// fill); the U diagonal is returned inverted.
-bool ilu0_factor(const slrf_ctx ctx, std::complex<double> sigma, std::vector<std::complex<double>>& f) {
-  const int64_t n = ctx->n, nnz = ctx->nnz;
-  const auto& rp = ctx->h_rp;
-  const auto& cl = ctx->h_cl;
-  const auto& dp = ctx->h_dpos;
-  f.resize(nnz);
-  for (int64_t k = 0; k < nnz; ++k) f[k] = std::complex<double>(ctx->h_ab[2 * k], 0.0) - sigma * ctx->h_ab[2 * k + 1];
-  for (int64_t i = 0; i < n; ++i) {
-    for (int32_t k = rp[i]; k < dp[i]; ++k) {
-      const int32_t c = cl[k];
-      f[k] /= f[dp[c]];
-      const std::complex<double> lik = f[k];
-      int32_t a = k + 1, b = dp[c] + 1;
-      while (a < rp[i + 1] && b < rp[c + 1]) {
-        if (cl[a] == cl[b]) {
-          f[a] -= lik * f[b];
-          ++a;
-          ++b;
-        } else if (cl[a] < cl[b]) {
-          ++a;
-        } else {
-          ++b;
-        }
-      }
-    }
-    if (std::abs(f[dp[i]]) == 0.0 || !std::isfinite(std::abs(f[dp[i]]))) return false;
-  }
-  for (int64_t i = 0; i < n; ++i) f[dp[i]] = 1.0 / f[dp[i]];
-  return true;
-}
-
-std::mutex g_design_mu;
-std::map<std::tuple<int, double, double>, std::vector<double>> g_design_cache;
-
-bool design_unit_cached(int N, double alpha, double beta, std::vector<double>& out /* 3N */) {
-  std::lock_guard<std::mutex> lk(g_design_mu);
-  auto key = std::make_tuple(N, alpha, beta);
-  auto it = g_design_cache.find(key);
-  if (it != g_design_cache.end()) {
-    out = it->second;
-    return true;
-  }
-  std::vector<double> xi(N), om(2 * N);
-  if (!design_poles_unit(N, alpha, beta, xi.data(), om.data())) return false;
-  out.assign(3 * N, 0.0);
-  for (int j = 0; j < N; ++j) {
-    out[j] = xi[j];
-    out[N + 2 * j] = om[2 * j];
-    out[N + 2 * j + 1] = om[2 * j + 1];
-  }
-  g_design_cache[key] = out;
-  return true;
-}
-
-slrf_status check_poles(slrf_ctx ctx, const slrf_poles* p) {
-  if (!p || p->n_poles < 1 || !p->sigma || !p->weight)
-    return fail(ctx, SLRF_E_INVALID_ARG, "pole set is NULL or empty");
-  if (p->n_poles > ctx->max_N) return fail(ctx, SLRF_E_INVALID_ARG, "more poles than the workspace was sized for");
-  for (int j = 0; j < p->n_poles; ++j) {
-    const double a = p->sigma[2 * j], b = p->sigma[2 * j + 1], c = p->weight[2 * j], d = p->weight[2 * j + 1];
-    if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c) || !std::isfinite(d))
-      return fail(ctx, SLRF_E_INVALID_ARG, "non-finite pole or weight");
-    if (!(b > 0)) return fail(ctx, SLRF_E_INVALID_ARG, "poles must lie in the upper half plane (Im sigma > 0)");
-  }
-  return SLRF_OK;
-}
-
-// Filter application into U (FP64 path).  Workspace carved from `cv`.
-slrf_status filter_fp64(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L, const double* X, double* U,
-                        slrf_filter_stats* stats) {
-  const double t0 = now_s();
-  hipStream_t s = ctx->stream;
-  const int n = (int)ctx->n, N = poles->n_poles;
-  KGeom g = make_geom(n, N, L, kRowsPerBlock);
-  g.sched = ctx->sched;
-  const int K = g.K;
-  KrylovState<double> st{};
-  st.x = cv.take<cx<double>>((size_t)n * K);
-  st.r = cv.take<cx<double>>((size_t)n * K);
-  st.ph = cv.take<cx<double>>((size_t)n * K);
-  st.v = cv.take<cx<double>>((size_t)n * K);
-  st.sh = cv.take<cx<double>>((size_t)n * K);
-  st.t = cv.take<cx<double>>((size_t)n * K);
-  cx<double>* fac = nullptr;
-  if (ctx->use_ilu) {
-    st.p = cv.take<cx<double>>((size_t)n * K);
-    st.s = cv.take<cx<double>>((size_t)n * K);
-    fac = cv.take<cx<double>>((size_t)N * ctx->nnz);
-  }
-  double* rhat = cv.take<double>((size_t)n * L);
-  cx<double>* d = cv.take<cx<double>>((size_t)n * N);
-  cx<double>* dinv = cv.take<cx<double>>((size_t)n * N);
-  cx<double>* sig = cv.take<cx<double>>(N);
-  cx<double>* sigc = cv.take<cx<double>>(K);
-  double* w = cv.take<double>(2 * N);
-  st.part_a = cv.take<cx<double>>((size_t)g.G * K);
-  st.part_b = cv.take<double>((size_t)g.G * K);
-  st.rho = cv.take<cx<double>>(K);
-  st.alpha = cv.take<cx<double>>(K);
-  st.omega = cv.take<cx<double>>(K);
-  st.beta = cv.take<cx<double>>(K);
-  st.fnorm = cv.take<double>(K);
-  st.rnorm = cv.take<double>(K);
-  st.flags = cv.take<int>(K);
-  st.iters = cv.take<int>(K);
-  int* d_count = cv.take<int>(64);
-  if (cv.off > cv.cap) return fail(ctx, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
-  st.rhat = rhat;
-  st.d = d;
-  st.dinv = dinv;
-  st.sigma_col = sigc;
-
-  std::vector<double> hsig(2 * N), hsigc(2 * (size_t)K);
-  for (int j = 0; j < N; ++j) {
-    hsig[2 * j] = poles->sigma[2 * j];
-    hsig[2 * j + 1] = poles->sigma[2 * j + 1];
-    for (int l = 0; l < L; ++l) {
-      hsigc[2 * ((size_t)j * L + l)] = poles->sigma[2 * j];
-      hsigc[2 * ((size_t)j * L + l) + 1] = poles->sigma[2 * j + 1];
-    }
-  }
-  HIPCHK(ctx, hipMemcpyAsync(sig, hsig.data(), 16 * N, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(sigc, hsigc.data(), 16 * (size_t)K, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(w, poles->weight, 16 * N, hipMemcpyHostToDevice, s));
-
-  IluFactors<double> ilu{};
-  std::vector<std::complex<double>> hf;
-  if (ctx->use_ilu) {
-    hf.resize((size_t)N * ctx->nnz);
-    std::vector<std::complex<double>> fj;
-    for (int j = 0; j < N; ++j) {
-      if (!ilu0_factor(ctx, {poles->sigma[2 * j], poles->sigma[2 * j + 1]}, fj))
-        return fail(ctx, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
-      std::copy(fj.begin(), fj.end(), hf.begin() + (size_t)j * ctx->nnz);
-    }
-    HIPCHK(ctx, hipMemcpyAsync(fac, hf.data(), 16 * hf.size(), hipMemcpyHostToDevice, s));
-    ilu = {ctx->rowptr, ctx->col, ctx->diagpos, fac, ctx->nnz};
-  }
-  launch_jacobi_diag<double>(s, n, N, ctx->diagA, ctx->diagB, sig, d, dinv);
-  launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, X, nullptr, rhat);
-  launch_init<double>(s, g, st, rhat);
-  launch_init_scalars<double>(s, g, st);
-  HIPCHK(ctx, hipGetLastError());
-
-  const int maxit = std::max(1, ctx->opt.inner_maxit);
-  const int every = std::max(1, std::min(ctx->opt.check_every, 64));
-  const double tol = ctx->opt.inner_tol;
-  LaunchTimer* tm = ctx->opt.profile ? &ctx->timer : nullptr;
-  const double mbytes = merged_csr_bytes(ctx, 16);
-  slrf_filter_stats ks{};
-  int it = 0;
-  while (it < maxit) {
-    const int chunk = std::min(every, maxit - it);
-    for (int q = 0; q < chunk; ++q, ++it)
-      launch_iteration<double>(s, g, st, ctx->rowptr, ctx->col, ctx->ab64, tol, maxit, it == 0,
-                               ctx->use_ilu ? &ilu : nullptr, tm, mbytes);
-    launch_count_active(s, K, st.flags, d_count);
-    HIPCHK(ctx, hipGetLastError());
-    int active = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    if (tm) {
-      slrf_status hs = harvest_timer(ctx, (int64_t)g.G * g.nct, &ks);
-      if (hs != SLRF_OK) return hs;
-    }
-    if (active == 0) break;
-  }
-  launch_filter_sum<double>(s, n, L, N, st.x, w, U, false);
-  HIPCHK(ctx, hipGetLastError());
-
-  if (stats) {
-    std::vector<int> fl(K), its(K);
-    std::vector<double> rn(K), fn(K);
-    HIPCHK(ctx, hipMemcpyAsync(fl.data(), st.flags, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(its.data(), st.iters, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(rn.data(), st.rnorm, 8 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(fn.data(), st.fnorm, 8 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    slrf_filter_stats fs{};
-    double sum_it = 0;
-    for (int c = 0; c < K; ++c) {
-      fs.max_iterations = std::max(fs.max_iterations, its[c]);
-      sum_it += its[c];
-      fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
-      if (fl[c] == COL_BREAKDOWN) fs.n_breakdown++;
-      if (fl[c] == COL_MAXIT) fs.n_maxit++;
-      const double rr = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
-      fs.max_relres = std::max(fs.max_relres, rr);
-    }
-    fs.mean_iterations = K ? sum_it / K : 0.0;
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    fs.seconds = now_s() - t0;
-    fs.spmm_seconds = ks.spmm_seconds;
-    fs.spmm_launches = ks.spmm_launches;
-    fs.spmm_bytes = ks.spmm_bytes;
-    fs.update_seconds = ks.update_seconds;
-    fs.update_launches = ks.update_launches;
-    fs.update_bytes = ks.update_bytes;
-    *stats = fs;
-  }
-  return SLRF_OK;
-}
-
-// Filter application with complex FP32 inner solves and FP64 defect correction:
-// Y = 0; repeat { R = F - S Y (FP64); stop columns with ||R|| <= target ||F||;
-// solve S D = R / ||R|| in FP32 (BiCGStab, relative tolerance inner_tol32);
-// Y += ||R|| D } ; U = sum_j 2 Re(w_j Y_j).
-constexpr double kInnerTol32 = 1e-6;
-constexpr int kMaxRounds = 6;
-
-slrf_status filter_mixed(slrf_ctx ctx, Carver& cv, const slrf_poles* poles, int L, const double* X, double* U,
-                         slrf_filter_stats* stats, double target) {
-  const double t0 = now_s();
-  hipStream_t s = ctx->stream;
-  const int n = (int)ctx->n, N = poles->n_poles;
-  KGeom g = make_geom(n, N, L, kRowsPerBlock);
-  g.sched = ctx->sched;
-  const int K = g.K;
-  KrylovState<float> st{};
-  st.x = cv.take<cx<float>>((size_t)n * K);
-  st.r = cv.take<cx<float>>((size_t)n * K);
-  st.ph = cv.take<cx<float>>((size_t)n * K);
-  st.v = cv.take<cx<float>>((size_t)n * K);
-  st.sh = cv.take<cx<float>>((size_t)n * K);
-  st.t = cv.take<cx<float>>((size_t)n * K);
-  cx<float>* rhat = cv.take<cx<float>>((size_t)n * K);
-  cx<float>* fac = nullptr;
-  if (ctx->use_ilu) {
-    st.p = cv.take<cx<float>>((size_t)n * K);
-    st.s = cv.take<cx<float>>((size_t)n * K);
-    fac = cv.take<cx<float>>((size_t)N * ctx->nnz);
-  }
-  cx<double>* Y = cv.take<cx<double>>((size_t)n * K);
-  cx<double>* Rd = cv.take<cx<double>>((size_t)n * K);
-  double* F = cv.take<double>((size_t)n * L);
-  cx<float>* d = cv.take<cx<float>>((size_t)n * N);
-  cx<float>* dinv = cv.take<cx<float>>((size_t)n * N);
-  cx<float>* sig = cv.take<cx<float>>(N);
-  cx<float>* sigc = cv.take<cx<float>>(K);
-  cx<double>* sigc64 = cv.take<cx<double>>(K);
-  double* w = cv.take<double>(2 * N);
-  st.part_a = cv.take<cx<float>>((size_t)g.G * K);
-  st.part_b = cv.take<float>((size_t)g.G * K);
-  double* part64 = cv.take<double>((size_t)g.G * K);
-  st.rho = cv.take<cx<float>>(K);
-  st.alpha = cv.take<cx<float>>(K);
-  st.omega = cv.take<cx<float>>(K);
-  st.beta = cv.take<cx<float>>(K);
-  st.fnorm = cv.take<float>(K);
-  st.rnorm = cv.take<float>(K);
-  st.flags = cv.take<int>(K);
-  st.iters = cv.take<int>(K);
-  double* fnorm64 = cv.take<double>(K);
-  double* scale = cv.take<double>(K);
-  double* relres = cv.take<double>(K);
-  int* d_count = cv.take<int>(64);
-  if (cv.off > cv.cap) return fail(ctx, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
-  st.rhat = nullptr;
-  st.rhat_cx = rhat;
-  st.d = d;
-  st.dinv = dinv;
-  st.sigma_col = sigc;
-
-  std::vector<float> hsig(2 * N), hsigc(2 * (size_t)K);
-  std::vector<double> hsigc64(2 * (size_t)K);
-  for (int j = 0; j < N; ++j) {
-    hsig[2 * j] = (float)poles->sigma[2 * j];
-    hsig[2 * j + 1] = (float)poles->sigma[2 * j + 1];
-    for (int l = 0; l < L; ++l) {
-      const size_t c = (size_t)j * L + l;
-      hsigc[2 * c] = (float)poles->sigma[2 * j];
-      hsigc[2 * c + 1] = (float)poles->sigma[2 * j + 1];
-      hsigc64[2 * c] = poles->sigma[2 * j];
-      hsigc64[2 * c + 1] = poles->sigma[2 * j + 1];
-    }
-  }
-  HIPCHK(ctx, hipMemcpyAsync(sig, hsig.data(), 8 * N, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(sigc, hsigc.data(), 8 * (size_t)K, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(sigc64, hsigc64.data(), 16 * (size_t)K, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(w, poles->weight, 16 * N, hipMemcpyHostToDevice, s));
-  IluFactors<float> ilu{};
-  std::vector<cx<float>> hf;
-  if (ctx->use_ilu) {
-    hf.resize((size_t)N * ctx->nnz);
-    std::vector<std::complex<double>> fj;
-    for (int j = 0; j < N; ++j) {
-      if (!ilu0_factor(ctx, {poles->sigma[2 * j], poles->sigma[2 * j + 1]}, fj))
-        return fail(ctx, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
-      for (int64_t k = 0; k < ctx->nnz; ++k)
-        hf[(size_t)j * ctx->nnz + k] = {(float)fj[k].real(), (float)fj[k].imag()};
-    }
-    HIPCHK(ctx, hipMemcpyAsync(fac, hf.data(), 8 * hf.size(), hipMemcpyHostToDevice, s));
-    ilu = {ctx->rowptr, ctx->col, ctx->diagpos, fac, ctx->nnz};
-  }
-  launch_jacobi_diag<float>(s, n, N, ctx->diagA32, ctx->diagB32, sig, d, dinv);
-  launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, X, nullptr, F);
-  HIPCHK(ctx, hipGetLastError());
-
-  const int maxit = std::max(1, ctx->opt.inner_maxit);
-  const int every = std::max(1, std::min(ctx->opt.check_every, 64));
-  LaunchTimer* tm = ctx->opt.profile ? &ctx->timer : nullptr;
-  const double mbytes = merged_csr_bytes(ctx, 8);
-  slrf_filter_stats fs{};
-  double sum_it = 0;
-  int rounds = 0;
-  for (int round = 0; round <= kMaxRounds; ++round) {
-    // defect and the columns still above the target
-    launch_defect(s, g, ctx->rowptr, ctx->col, ctx->ab64, sigc64, F, round ? Y : nullptr, Rd, part64);
-    launch_defect_norms(s, g, part64, target, round == 0, fnorm64, scale, relres, d_count);
-    HIPCHK(ctx, hipGetLastError());
-    int open = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&open, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    if (round > 0) fs.spmv += (int64_t)K;  // one product with S per column for the defect
-    if (open == 0 || round == kMaxRounds) break;
-    ++rounds;
-    launch_mixed_rhs(s, g, round ? Rd : nullptr, F, scale, st, rhat);
-    launch_init_scalars<float>(s, g, st);
-    int it = 0;
-    while (it < maxit) {
-      const int chunk = std::min(every, maxit - it);
-      for (int q = 0; q < chunk; ++q, ++it)
-        launch_iteration<float>(s, g, st, ctx->rowptr, ctx->col, ctx->ab32, (float)kInnerTol32, maxit, it == 0,
-                                ctx->use_ilu ? &ilu : nullptr, tm, mbytes);
-      launch_count_active(s, K, st.flags, d_count);
-      HIPCHK(ctx, hipGetLastError());
-      int active = 0;
-      HIPCHK(ctx, hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(ctx, hipStreamSynchronize(s));
-      if (tm) {
-        slrf_status hs = harvest_timer(ctx, (int64_t)g.G * g.nct, &fs);
-        if (hs != SLRF_OK) return hs;
-      }
-      if (active == 0) break;
-    }
-    launch_accumulate(s, g, st.x, scale, Y, round == 0);
-    std::vector<int> fl(K), its(K);
-    HIPCHK(ctx, hipMemcpyAsync(fl.data(), st.flags, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(its.data(), st.iters, 4 * (size_t)K, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    for (int c = 0; c < K; ++c) {
-      fs.max_iterations = std::max(fs.max_iterations, its[c]);
-      sum_it += its[c];
-      fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
-      if (fl[c] == COL_BREAKDOWN) fs.n_breakdown++;
-      if (fl[c] == COL_MAXIT) fs.n_maxit++;
-    }
-  }
-  launch_filter_sum<double>(s, n, L, N, Y, w, U, false);
-  HIPCHK(ctx, hipGetLastError());
-  std::vector<double> rr(K);
-  HIPCHK(ctx, hipMemcpyAsync(rr.data(), relres, 8 * (size_t)K, hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  if (stats) {
-    for (int c = 0; c < K; ++c) fs.max_relres = std::max(fs.max_relres, rr[c]);
-    fs.mean_iterations = K ? sum_it / K : 0.0;
-    fs.refinements = rounds;
-    fs.seconds = now_s() - t0;
-    *stats = fs;
-  }
-  return SLRF_OK;
-}
-
-// One Rayleigh-Ritz pass: Y = Xin Z with (Y^T A Y, Y^T B Y) = (diag(theta), I).
-slrf_status rr_pass(slrf_ctx ctx, int L, const double* Xin, double* Y, double* WA, double* WB, double* part,
-                    int nch, double* GA, double* GB, double* Zd, std::vector<double>& theta) {
-  hipStream_t s = ctx->stream;
-  const int n = (int)ctx->n;
-  launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, Xin, WA, WB);
-  launch_gram(s, n, L, Xin, WA, WB, part, nch, GA, GB);
-  HIPCHK(ctx, hipGetLastError());
-  std::vector<double> hA((size_t)L * L), hB((size_t)L * L), Z((size_t)L * L);
-  HIPCHK(ctx, hipMemcpyAsync(hA.data(), GA, 8 * hA.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipMemcpyAsync(hB.data(), GB, 8 * hB.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  theta.assign(L, 0.0);
-  if (!projected_pencil(L, hA.data(), hB.data(), theta.data(), Z.data()))
-    return fail(ctx, SLRF_E_BREAKDOWN, "projected pencil not solvable (non-finite or zero Gram matrix)");
-  HIPCHK(ctx, hipMemcpyAsync(Zd, Z.data(), 8 * Z.size(), hipMemcpyHostToDevice, s));
-  const double* xs[1] = {Xin};
-  double* ys[1] = {Y};
-  launch_gemm_nz(s, n, L, L, 1, xs, Zd, ys);
-  HIPCHK(ctx, hipGetLastError());
-  HIPCHK(ctx, hipStreamSynchronize(s));  // Z host buffer lifetime
-  return SLRF_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-void slrf_default_options(slrf_options* o) {
-  if (!o) return;
-  o->precision = SLRF_FP64;
-  o->inner_tol = 1e-10;
-  o->inner_maxit = 1000;
-  o->outer_tol = 1e-8;
-  o->outer_maxit = 40;
-  o->check_every = 10;
-  o->seed = 1;
-  o->precond = 0;
-}
-
-const char* slrf_status_string(slrf_status s) {
-  switch (s) {
-    case SLRF_OK: return "ok";
-    case SLRF_E_INVALID_ARG: return "invalid argument";
-    case SLRF_E_NOT_SPD: return "A or B has a non-positive or missing diagonal entry";
-    case SLRF_E_WORKSPACE: return "workspace too small or misaligned";
-    case SLRF_E_DEVICE: return "HIP runtime error";
-    case SLRF_E_NOT_CONVERGED: return "outer iteration did not converge";
-    case SLRF_E_SUBSPACE_TOO_SMALL: return "subspace too small: every Ritz value lies in the interval";
-    case SLRF_E_BREAKDOWN: return "breakdown of the projected problem";
-  }
-  return "unknown status";
-}
-
-const char* slrf_last_error(slrf_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma, double* sigma_out,
-                              double* weight_out, double* sep_out) {
-  if (N < 1 || N > 16 || !(alpha > 0) || !(beta > 0) || !(gamma > 0) || !sigma_out || !weight_out)
+// Validates A and B, merges them into one CSR of (a, b) pairs over the union
+// pattern and, with mem != nullptr, uploads it there (pencil_bytes(n, nnz)
+// bytes).  With mem == nullptr it only validates and reports nnz of the union.
+slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                         const int32_t* b_rowptr, const int32_t* b_col, const double* b_val, int precond,
+                         hipStream_t s, Pencil& P, std::string& err, char* mem, int64_t* nnz_out) {
+  if (n < 1 || n > INT32_MAX || !a_rowptr || !a_col || !a_val || !b_rowptr || !b_col || !b_val) {
+    err = "bad size or NULL argument";
     return SLRF_E_INVALID_ARG;
-  std::vector<double> u;
-  if (!design_unit_cached(N, alpha, beta, u)) return SLRF_E_INVALID_ARG;
-  std::complex<double> dphi = 0;
-  for (int j = 0; j < N; ++j) {
-    const std::complex<double> sg(gamma * u[j], gamma * u[j] * alpha);
-    const std::complex<double> wj(gamma * u[N + 2 * j], gamma * u[N + 2 * j + 1]);
-    sigma_out[2 * j] = sg.real();
-    sigma_out[2 * j + 1] = sg.imag();
-    weight_out[2 * j] = wj.real();
-    weight_out[2 * j + 1] = wj.imag();
-    dphi += -2.0 * (wj / ((gamma - sg) * (gamma - sg))).real();
   }
-  if (sep_out) *sep_out = std::abs(dphi.real());
-  return SLRF_OK;
-}
-
-slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
-  if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
-  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
-  *bytes = static_bytes_for(n, nnz) + krylov_bytes(n, nnz, L, N, precision) + outer_bytes(n, L);
-  return SLRF_OK;
-}
-
-slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
-                        const double* a_val, const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
-                        void* d_workspace, size_t ws_bytes, int64_t max_L, int32_t max_N, const slrf_options* opt,
-                        void* hip_stream) {
-  if (!out) return SLRF_E_INVALID_ARG;
-  *out = nullptr;
-  slrf_ctx ctx = new (std::nothrow) slrf_ctx_s();
-  if (!ctx) return SLRF_E_INVALID_ARG;
-  auto bail = [&](slrf_status s, const std::string& m) {
-    ctx->err = m;
-    *out = ctx;  // keep the context so the caller can read the message
-    return s;
-  };
-  if (n < 1 || n > INT32_MAX || !a_rowptr || !a_col || !a_val || !b_rowptr || !b_col || !b_val || max_L < 1 ||
-      max_N < 1)
-    return bail(SLRF_E_INVALID_ARG, "bad size or NULL argument");
-  if (opt) ctx->opt = *opt; else slrf_default_options(&ctx->opt);
-  if (ctx->opt.precision != SLRF_FP64 && ctx->opt.precision != SLRF_MIXED)
-    return bail(SLRF_E_INVALID_ARG, "unknown precision");
-  ctx->n = n;
-  ctx->verbose = getenv("SLRF_VERBOSE") != nullptr;
-  ctx->stream = (hipStream_t)hip_stream;
-  ctx->max_L = max_L;
-  ctx->max_N = max_N;
-  // validate and merge the two patterns
   auto check_csr = [&](const int32_t* rp, const int32_t* cl, const double* v, const char* name) -> std::string {
     if (rp[0] != 0) return std::string(name) + ": row_ptr[0] != 0";
     for (int64_t i = 0; i < n; ++i) {
@@ -694,10 +183,14 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
     }
     return "";
   };
-  std::string m1 = check_csr(a_rowptr, a_col, a_val, "A");
-  if (!m1.empty()) return bail(SLRF_E_INVALID_ARG, m1);
-  std::string m2 = check_csr(b_rowptr, b_col, b_val, "B");
-  if (!m2.empty()) return bail(SLRF_E_INVALID_ARG, m2);
+  err = check_csr(a_rowptr, a_col, a_val, "A");
+  if (!err.empty()) return SLRF_E_INVALID_ARG;
+  err = check_csr(b_rowptr, b_col, b_val, "B");
+  if (!err.empty()) return SLRF_E_INVALID_ARG;
+  if (precond < 0 || precond > 2) {
+    err = "unknown preconditioner";
+    return SLRF_E_INVALID_ARG;
+  }
   std::vector<int32_t> rp(n + 1, 0), cl, dpos(n, -1);
   std::vector<double> ab, dA(n, 0.0), dB(n, 0.0);
   cl.reserve(std::max(a_rowptr[n], b_rowptr[n]));
@@ -722,67 +215,1077 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
     rp[i + 1] = (int32_t)cl.size();
   }
   for (int64_t i = 0; i < n; ++i)
-    if (!(dA[i] > 0) || !(dB[i] > 0))
-      return bail(SLRF_E_NOT_SPD, "row " + std::to_string(i) + ": diagonal of A or B not positive");
+    if (!(dA[i] > 0) || !(dB[i] > 0)) {
+      err = "row " + std::to_string(i) + ": diagonal of A or B not positive";
+      return SLRF_E_NOT_SPD;
+    }
   const int64_t nnz = (int64_t)cl.size();
-  ctx->nnz = nnz;
-  if (ctx->opt.precond < 0 || ctx->opt.precond > 2) return bail(SLRF_E_INVALID_ARG, "unknown preconditioner");
-  if (ctx->opt.precond == 2 && !ilu_allowed(n, nnz))
-    return bail(SLRF_E_INVALID_ARG, "ILU(0) needs a narrow pattern (nnz <= 5 n)");
-  ctx->use_ilu = ctx->opt.precond == 2 || (ctx->opt.precond == 0 && ilu_allowed(n, nnz));
-  if (((uintptr_t)d_workspace & 255) != 0 || !d_workspace) return bail(SLRF_E_WORKSPACE, "workspace not 256-byte aligned");
-  size_t need = 0;
-  if (slrf_workspace_bytes(n, nnz, max_L, max_N, ctx->opt.precision, &need) != SLRF_OK)
-    return bail(SLRF_E_INVALID_ARG, "bad sizes");
-  if (ws_bytes < need)
-    return bail(SLRF_E_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(need));
-  ctx->ws = (char*)d_workspace;
-  ctx->ws_bytes = ws_bytes;
-  Carver cv{ctx->ws, 0, ws_bytes};
-  ctx->rowptr = cv.take<int>(n + 1);
-  ctx->col = cv.take<int>(nnz);
-  ctx->ab64 = cv.take<ab_pair<double>>(nnz);
-  ctx->diagA = cv.take<double>(n);
-  ctx->diagB = cv.take<double>(n);
-  ctx->diagpos = cv.take<int>(n);
-  ctx->timer.d_counts = cv.take<int>(kTimerSlots);
+  if (nnz_out) *nnz_out = nnz;
+  if (precond == 2 && !ilu_allowed(n, nnz)) {
+    err = "ILU(0) needs a narrow pattern (nnz <= 5 n)";
+    return SLRF_E_INVALID_ARG;
+  }
+  if (!mem) return SLRF_OK;
+  P.n = n;
+  P.nnz = nnz;
+  P.use_ilu = use_ilu_for(precond, n, nnz);
+  P.mem = mem;
+  P.mem_bytes = pencil_bytes(n, nnz);
+  Carver cv{mem, 0, P.mem_bytes};
+  P.rowptr = cv.take<int>(n + 1);
+  P.col = cv.take<int>(nnz);
+  P.ab64 = cv.take<ab_pair<double>>(nnz);
+  P.ab32 = cv.take<ab_pair<float>>(nnz);
+  P.diagA = cv.take<double>(n);
+  P.diagB = cv.take<double>(n);
+  P.diagA32 = cv.take<float>(n);
+  P.diagB32 = cv.take<float>(n);
+  P.diagpos = cv.take<int>(n);
   int* sched_dev = cv.take<int>(n);
-  ctx->ab32 = cv.take<ab_pair<float>>(nnz);
-  ctx->diagA32 = cv.take<float>(n);
-  ctx->diagB32 = cv.take<float>(n);
-  ctx->static_bytes = cv.off;
+  std::vector<int32_t> order;
+  P.sched = band_schedule(n, rp, cl, order) ? sched_dev : nullptr;
   std::vector<float> ab32(2 * (size_t)nnz), dA32(n), dB32(n);
   for (size_t k = 0; k < 2 * (size_t)nnz; ++k) ab32[k] = (float)ab[k];
   for (int64_t i = 0; i < n; ++i) {
     dA32[i] = (float)dA[i];
     dB32[i] = (float)dB[i];
   }
-  std::vector<int32_t> order;
-  if (band_schedule(n, rp, cl, order)) ctx->sched = sched_dev;
-  if (ctx->opt.profile) {
-    ctx->events.assign(2 * kTimerSlots, nullptr);
-    for (auto& e : ctx->events)
-      if (hipEventCreate(&e) != hipSuccess) return bail(SLRF_E_DEVICE, "hipEventCreate failed");
-    ctx->timer.events = ctx->events.data();
-    ctx->timer.capacity = kTimerSlots;
-    launch_fill_zero(ctx->stream, ctx->timer.d_counts, 4 * kTimerSlots);
-  }
-  hipStream_t s = ctx->stream;
   auto cp = [&](void* dst, const void* src, size_t b) { return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s); };
-  if (cp(ctx->rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(ctx->col, cl.data(), 4 * nnz) != hipSuccess ||
-      cp(ctx->ab64, ab.data(), 16 * nnz) != hipSuccess || cp(ctx->diagA, dA.data(), 8 * n) != hipSuccess ||
-      cp(ctx->diagB, dB.data(), 8 * n) != hipSuccess || cp(ctx->diagpos, dpos.data(), 4 * n) != hipSuccess ||
-      (ctx->sched && cp(ctx->sched, order.data(), 4 * n) != hipSuccess) ||
-      cp(ctx->ab32, ab32.data(), 8 * nnz) != hipSuccess || cp(ctx->diagA32, dA32.data(), 4 * n) != hipSuccess ||
-      cp(ctx->diagB32, dB32.data(), 4 * n) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-    return bail(SLRF_E_DEVICE, "upload of the merged CSR failed");
-  if (ctx->use_ilu) {
-    ctx->h_rp = std::move(rp);
-    ctx->h_cl = std::move(cl);
-    ctx->h_ab = std::move(ab);
-    ctx->h_dpos = std::move(dpos);
+  if (cp(P.rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(P.col, cl.data(), 4 * nnz) != hipSuccess ||
+      cp(P.ab64, ab.data(), 16 * nnz) != hipSuccess || cp(P.ab32, ab32.data(), 8 * nnz) != hipSuccess ||
+      cp(P.diagA, dA.data(), 8 * n) != hipSuccess || cp(P.diagB, dB.data(), 8 * n) != hipSuccess ||
+      cp(P.diagA32, dA32.data(), 4 * n) != hipSuccess || cp(P.diagB32, dB32.data(), 4 * n) != hipSuccess ||
+      cp(P.diagpos, dpos.data(), 4 * n) != hipSuccess ||
+      (P.sched && cp(P.sched, order.data(), 4 * n) != hipSuccess) || hipStreamSynchronize(s) != hipSuccess) {
+    err = "upload of the merged CSR failed";
+    return SLRF_E_DEVICE;
   }
-  *out = ctx;
+  if (P.use_ilu) {
+    P.h_rp = std::move(rp);
+    P.h_cl = std::move(cl);
+    P.h_ab = std::move(ab);
+    P.h_dpos = std::move(dpos);
+  }
+  return SLRF_OK;
+}
+
+// ILU(0) of A - sigma B on the merged pattern (row-wise IKJ elimination without
+// fill); the U diagonal is returned inverted.
+bool ilu0_factor(const Pencil& P, std::complex<double> sigma, std::vector<std::complex<double>>& f) {
+  const int64_t n = P.n, nnz = P.nnz;
+  const auto& rp = P.h_rp;
+  const auto& cl = P.h_cl;
+  const auto& dp = P.h_dpos;
+  f.resize(nnz);
+  for (int64_t k = 0; k < nnz; ++k) f[k] = std::complex<double>(P.h_ab[2 * k], 0.0) - sigma * P.h_ab[2 * k + 1];
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t k = rp[i]; k < dp[i]; ++k) {
+      const int32_t c = cl[k];
+      f[k] /= f[dp[c]];
+      const std::complex<double> lik = f[k];
+      int32_t a = k + 1, b = dp[c] + 1;
+      while (a < rp[i + 1] && b < rp[c + 1]) {
+        if (cl[a] == cl[b]) {
+          f[a] -= lik * f[b];
+          ++a;
+          ++b;
+        } else if (cl[a] < cl[b]) {
+          ++a;
+        } else {
+          ++b;
+        }
+      }
+    }
+    if (std::abs(f[dp[i]]) == 0.0 || !std::isfinite(std::abs(f[dp[i]]))) return false;
+  }
+  for (int64_t i = 0; i < n; ++i) f[dp[i]] = 1.0 / f[dp[i]];
+  return true;
+}
+
+double merged_csr_bytes(const Pencil& P, size_t value_bytes) {
+  return (double)(P.n + 1) * 4 + (double)P.nnz * (4 + value_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Pole design (cached per (N, alpha, beta) at gamma = 1)
+
+std::mutex g_design_mu;
+std::map<std::tuple<int, double, double>, std::vector<double>> g_design_cache;
+
+bool design_unit_cached(int N, double alpha, double beta, std::vector<double>& out /* 3N */) {
+  std::lock_guard<std::mutex> lk(g_design_mu);
+  auto key = std::make_tuple(N, alpha, beta);
+  auto it = g_design_cache.find(key);
+  if (it != g_design_cache.end()) {
+    out = it->second;
+    return true;
+  }
+  std::vector<double> xi(N), om(2 * N);
+  if (!design_poles_unit(N, alpha, beta, xi.data(), om.data())) return false;
+  out.assign(3 * N, 0.0);
+  for (int j = 0; j < N; ++j) {
+    out[j] = xi[j];
+    out[N + 2 * j] = om[2 * j];
+    out[N + 2 * j + 1] = om[2 * j + 1];
+  }
+  g_design_cache[key] = out;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Engine state shared by contexts and batches
+
+struct Env {
+  hipStream_t stream = nullptr;
+  slrf_options opt{};
+  bool verbose = false;
+  std::string err;
+  LaunchTimer timer;
+  std::vector<hipEvent_t> events;
+  ~Env() {
+    for (hipEvent_t e : events)
+      if (e) (void)hipEventDestroy(e);
+  }
+  bool setup_timer(int* d_counts) {
+    timer.d_counts = d_counts;
+    if (!opt.profile) return true;
+    events.assign(2 * kTimerSlots, nullptr);
+    for (auto& e : events)
+      if (hipEventCreate(&e) != hipSuccess) return false;
+    timer.events = events.data();
+    timer.capacity = kTimerSlots;
+    launch_fill_zero(stream, d_counts, 4 * kTimerSlots);
+    return hipStreamSynchronize(stream) == hipSuccess;
+  }
+};
+
+slrf_status fail(Env& env, slrf_status s, const std::string& msg) {
+  env.err = msg;
+  return s;
+}
+
+#define HIPCHK(env, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(env, SLRF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
+  if (opt)
+    env.opt = *opt;
+  else
+    slrf_default_options(&env.opt);
+  env.verbose = getenv("SLRF_VERBOSE") != nullptr;
+  env.stream = (hipStream_t)hip_stream;
+  if (env.opt.precision != SLRF_FP64 && env.opt.precision != SLRF_MIXED)
+    return fail(env, SLRF_E_INVALID_ARG, "unknown precision");
+  if (env.opt.precond < 0 || env.opt.precond > 2) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
+    return fail(env, SLRF_E_INVALID_ARG, "tolerances must be non-negative");
+  return SLRF_OK;
+}
+
+// Reads back the event pairs and tile counters of the current window into the
+// kernel statistics, then clears the window.
+slrf_status harvest_timer(Env& env, int64_t total_tiles, slrf_filter_stats* fs) {
+  LaunchTimer& tm = env.timer;
+  if (tm.used == 0) return SLRF_OK;
+  std::vector<int> cnt(tm.used);
+  HIPCHK(env, hipMemcpyAsync(cnt.data(), tm.d_counts, 4 * (size_t)tm.used, hipMemcpyDeviceToHost, env.stream));
+  HIPCHK(env, hipStreamSynchronize(env.stream));
+  for (int u = 0; u < tm.used; ++u) {
+    float ms = 0;
+    HIPCHK(env, hipEventElapsedTime(&ms, tm.events[2 * u], tm.events[2 * u + 1]));
+    const LaunchTimer::Rec& r = tm.recs[u];
+    const double bytes = r.tile_bytes * (double)cnt[u] / (double)total_tiles + (cnt[u] > 0 ? r.fixed : 0.0);
+    if (r.kind == 0) {
+      fs->spmm_seconds += 1e-3 * ms;
+      fs->spmm_launches += 1;
+      fs->spmm_bytes += bytes;
+    } else {
+      fs->update_seconds += 1e-3 * ms;
+      fs->update_launches += 1;
+      fs->update_bytes += bytes;
+    }
+  }
+  tm.used = 0;
+  launch_fill_zero(env.stream, tm.d_counts, 4 * (size_t)tm.capacity);
+  return SLRF_OK;
+}
+
+slrf_status check_poles(Env& env, const slrf_poles* p, int max_N) {
+  if (!p || p->n_poles < 1 || !p->sigma || !p->weight)
+    return fail(env, SLRF_E_INVALID_ARG, "pole set is NULL or empty");
+  if (p->n_poles > max_N) return fail(env, SLRF_E_INVALID_ARG, "more poles than the workspace was sized for");
+  for (int j = 0; j < p->n_poles; ++j) {
+    const double a = p->sigma[2 * j], b = p->sigma[2 * j + 1], c = p->weight[2 * j], d = p->weight[2 * j + 1];
+    if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c) || !std::isfinite(d))
+      return fail(env, SLRF_E_INVALID_ARG, "non-finite pole or weight");
+    if (!(b > 0)) return fail(env, SLRF_E_INVALID_ARG, "poles must lie in the upper half plane (Im sigma > 0)");
+  }
+  return SLRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched filter application
+
+struct FilterJob {
+  const Pencil* P;
+  int L, N;
+  const double* sigma;   // host, 2N
+  const double* weight;  // host, 2N
+  const double* X;       // device (n, L)
+  double* U;             // device (n, L)
+  double target;         // relative accuracy of the shifted solves
+  slrf_filter_stats stats;
+};
+
+struct JobShape {
+  int64_t n, nnz;
+  int L, N;
+  bool ilu;           // ILU(0) factors of this pencil
+  bool general = false;  // count the p and s blocks even without ILU(0) (upper bounds)
+};
+
+// Device layout of one batched filter application.  Carving with a null base
+// measures it; partial sums are sized for kMaxGrid workgroups so the size does
+// not depend on the grid a batch picks.
+struct FilterLayout {
+  int64_t EB = 0, ER = 0, ED = 0, Ktot = 0, n_tiles = 0, ilu_vals = 0;
+  bool any_ilu = false;
+  void* vec[9] = {};  // x r ph v sh t [p s] [complex shadow residual]
+  double* rhat = nullptr;
+  void* d = nullptr;
+  void* dinv = nullptr;
+  void* sigma_col = nullptr;
+  cx<double>* sigma_col64 = nullptr;
+  cx<double>* Y = nullptr;
+  cx<double>* R = nullptr;
+  double* F = nullptr;
+  double* w = nullptr;
+  void* sig_j = nullptr;
+  void* part_a = nullptr;
+  void* part_b = nullptr;
+  double* part64 = nullptr;
+  void* scal[4] = {};  // rho alpha omega beta
+  void* fnorm = nullptr;
+  void* rnorm = nullptr;
+  int* flags = nullptr;
+  int* iters = nullptr;
+  double* fnorm64 = nullptr;
+  double* scale = nullptr;
+  double* relres = nullptr;
+  double* tol64 = nullptr;
+  int* count = nullptr;
+  Inst* inst = nullptr;
+  int* tile_inst = nullptr;
+  int* col_inst = nullptr;
+  void* ilu = nullptr;
+};
+
+void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo) {
+  lo = FilterLayout{};
+  int64_t sumN = 0;
+  bool any_general = false;
+  for (const auto& j : js) {
+    const int64_t K = (int64_t)j.N * j.L;
+    lo.EB += j.n * K;
+    lo.ER += j.n * j.L;
+    lo.ED += j.n * j.N;
+    lo.Ktot += K;
+    lo.n_tiles += (K + 63) / 64;
+    sumN += j.N;
+    if (j.ilu) {
+      lo.any_ilu = true;
+      lo.ilu_vals += (int64_t)j.N * j.nnz;
+    }
+    if (j.general) any_general = true;
+  }
+  const size_t cs = mixed ? 8 : 16;  // complex size in the Krylov precision
+  const size_t rs = cs / 2;
+  // with any ILU(0) pencil in the batch, every pencil keeps p and s
+  const int nvec = 6 + (lo.any_ilu || any_general ? 2 : 0);
+  for (int v = 0; v < nvec; ++v) lo.vec[v] = cv.take<char>((size_t)lo.EB * cs);
+  if (mixed) {
+    lo.vec[8] = cv.take<char>((size_t)lo.EB * cs);
+    lo.Y = cv.take<cx<double>>(lo.EB);
+    lo.R = cv.take<cx<double>>(lo.EB);
+    lo.F = cv.take<double>(lo.ER);
+    lo.sigma_col64 = cv.take<cx<double>>(lo.Ktot);
+    lo.part64 = cv.take<double>((size_t)kMaxGrid * lo.Ktot);
+    lo.fnorm64 = cv.take<double>(lo.Ktot);
+    lo.scale = cv.take<double>(lo.Ktot);
+    lo.relres = cv.take<double>(lo.Ktot);
+    lo.tol64 = cv.take<double>(lo.Ktot);
+  } else {
+    lo.rhat = cv.take<double>(lo.ER);
+  }
+  lo.d = cv.take<char>((size_t)lo.ED * cs);
+  lo.dinv = cv.take<char>((size_t)lo.ED * cs);
+  lo.sigma_col = cv.take<char>((size_t)lo.Ktot * cs);
+  lo.sig_j = cv.take<char>((size_t)sumN * cs);
+  lo.w = cv.take<double>(2 * sumN);
+  lo.part_a = cv.take<char>((size_t)kMaxGrid * lo.Ktot * cs);
+  lo.part_b = cv.take<char>((size_t)kMaxGrid * lo.Ktot * rs);
+  for (int q = 0; q < 4; ++q) lo.scal[q] = cv.take<char>((size_t)lo.Ktot * cs);
+  lo.fnorm = cv.take<char>((size_t)lo.Ktot * rs);
+  lo.rnorm = cv.take<char>((size_t)lo.Ktot * rs);
+  lo.flags = cv.take<int>(lo.Ktot);
+  lo.iters = cv.take<int>(lo.Ktot);
+  lo.count = cv.take<int>(64);
+  lo.inst = cv.take<Inst>(js.size());
+  lo.tile_inst = cv.take<int>(lo.n_tiles);
+  lo.col_inst = cv.take<int>(lo.Ktot);
+  if (lo.any_ilu) lo.ilu = cv.take<char>((size_t)lo.ilu_vals * cs);
+}
+
+size_t filter_arena_bytes(const std::vector<JobShape>& js, bool mixed) {
+  Carver cv{nullptr, 0, 0};
+  FilterLayout lo;
+  carve_filter(cv, js, mixed, lo);
+  return cv.off;
+}
+
+template <typename R>
+KrylovState<R> make_state(const FilterLayout& lo) {
+  KrylovState<R> st{};
+  st.x = (cx<R>*)lo.vec[0];
+  st.r = (cx<R>*)lo.vec[1];
+  st.ph = (cx<R>*)lo.vec[2];
+  st.v = (cx<R>*)lo.vec[3];
+  st.sh = (cx<R>*)lo.vec[4];
+  st.t = (cx<R>*)lo.vec[5];
+  st.p = (cx<R>*)lo.vec[6];
+  st.s = (cx<R>*)lo.vec[7];
+  st.rhat = std::is_same<R, double>::value ? (const R*)lo.rhat : nullptr;
+  st.rhat_cx = (const cx<R>*)lo.vec[8];
+  st.d = (const cx<R>*)lo.d;
+  st.dinv = (const cx<R>*)lo.dinv;
+  st.sigma_col = (const cx<R>*)lo.sigma_col;
+  st.part_a = (cx<R>*)lo.part_a;
+  st.part_b = (R*)lo.part_b;
+  st.rho = (cx<R>*)lo.scal[0];
+  st.alpha = (cx<R>*)lo.scal[1];
+  st.omega = (cx<R>*)lo.scal[2];
+  st.beta = (cx<R>*)lo.scal[3];
+  st.fnorm = (R*)lo.fnorm;
+  st.rnorm = (R*)lo.rnorm;
+  st.flags = lo.flags;
+  st.iters = lo.iters;
+  return st;
+}
+
+// Builds and uploads the device tables of the batch: the Inst table, the tile
+// and column owners, per-column and per-pole shifts, weights and the ILU(0)
+// factors.  The host arrays are parked in `keep`, which the caller holds until
+// the stream has passed the copies.
+template <typename R>
+slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
+                          std::vector<std::vector<char>>& keep) {
+  const hipStream_t s = env.stream;
+  std::vector<Inst> insts(jobs.size());
+  std::vector<int> tile_inst, col_inst;
+  std::vector<cx<R>> sigc, sigj, ilu_all;
+  std::vector<double> sigc64, w;
+  int max_slab = 1;
+  for (const auto& j : jobs) {
+    const int nrb = (int)((j.P->n + kRowsPerBlock - 1) / kRowsPerBlock);
+    max_slab = std::max(max_slab, (nrb + 7) / 8);
+  }
+  const int per = std::max(1, std::min(kWgPerXcd, max_slab));
+  b.G = 8 * per;
+  b.rows_per_block = kRowsPerBlock;
+  int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0;
+  int col0 = 0, tile0 = 0;
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    const FilterJob& j = jobs[q];
+    Inst& I = insts[q];
+    I.n = (int)j.P->n;
+    I.L = j.L;
+    I.N = j.N;
+    I.K = j.N * j.L;
+    I.nrb = (I.n + kRowsPerBlock - 1) / kRowsPerBlock;
+    I.slab = (I.nrb + 7) / 8;
+    I.steps = (I.slab + per - 1) / per;
+    I.col0 = col0;
+    I.tile0 = tile0;
+    I.nnz = (int)j.P->nnz;
+    I.blk = blk;
+    I.rl = rl;
+    I.dn = dn;
+    I.rowptr = j.P->rowptr;
+    I.col = j.P->col;
+    I.ab = std::is_same<R, float>::value ? (const void*)j.P->ab32 : (const void*)j.P->ab64;
+    I.ab64 = j.P->ab64;
+    I.sched = j.P->sched;
+    I.diagpos = j.P->diagpos;
+    I.ilu = nullptr;
+    const int tiles = (I.K + 63) / 64;
+    for (int t = 0; t < tiles; ++t) tile_inst.push_back((int)q);
+    for (int c = 0; c < I.K; ++c) col_inst.push_back((int)q);
+    for (int p = 0; p < j.N; ++p) {
+      const cx<R> sg = {(R)j.sigma[2 * p], (R)j.sigma[2 * p + 1]};
+      sigj.push_back(sg);
+      w.push_back(j.weight[2 * p]);
+      w.push_back(j.weight[2 * p + 1]);
+      for (int l = 0; l < j.L; ++l) {
+        sigc.push_back(sg);
+        sigc64.push_back(j.sigma[2 * p]);
+        sigc64.push_back(j.sigma[2 * p + 1]);
+      }
+    }
+    if (j.P->use_ilu) {
+      std::vector<std::complex<double>> fj;
+      for (int p = 0; p < j.N; ++p) {
+        if (!ilu0_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, fj))
+          return fail(env, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
+        for (int64_t k = 0; k < j.P->nnz; ++k) ilu_all.push_back({(R)fj[k].real(), (R)fj[k].imag()});
+      }
+      I.ilu = (const char*)lo.ilu + ilu_off * sizeof(cx<R>);
+      ilu_off += (int64_t)j.N * j.P->nnz;
+    }
+    blk += (int64_t)I.n * I.K;
+    rl += (int64_t)I.n * I.L;
+    dn += (int64_t)I.n * I.N;
+    col0 += I.K;
+    tile0 += tiles;
+  }
+  b.inst = lo.inst;
+  b.tile_inst = lo.tile_inst;
+  b.col_inst = lo.col_inst;
+  b.n_tiles = tile0;
+  b.Ktot = col0;
+  keep.reserve(keep.size() + 8);
+  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    keep.emplace_back((const char*)src, (const char*)src + bytes);
+    return hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, s);
+  };
+  HIPCHK(env, put(lo.inst, insts.data(), insts.size() * sizeof(Inst)));
+  HIPCHK(env, put(lo.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
+  HIPCHK(env, put(lo.col_inst, col_inst.data(), 4 * col_inst.size()));
+  HIPCHK(env, put(lo.sigma_col, sigc.data(), sizeof(cx<R>) * sigc.size()));
+  HIPCHK(env, put(lo.sig_j, sigj.data(), sizeof(cx<R>) * sigj.size()));
+  HIPCHK(env, put(lo.w, w.data(), 8 * w.size()));
+  if (lo.sigma_col64) HIPCHK(env, put(lo.sigma_col64, sigc64.data(), 8 * sigc64.size()));
+  if (!ilu_all.empty()) HIPCHK(env, put(lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
+  return SLRF_OK;
+}
+
+// Runs BiCGStab iterations on the batch until no column is active or maxit is
+// reached, polling the active count every check_every iterations.  With
+// opt.graph (no profiling, a non-null stream) one chunk of check_every
+// iterations plus the count is captured once as a hipGraph and replayed.
+template <typename R>
+slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol, bool ilu, const IterBytes& by,
+                       int* d_count, slrf_filter_stats* ks) {
+  const hipStream_t s = env.stream;
+  const int maxit = std::max(1, env.opt.inner_maxit);
+  const int every = std::max(1, std::min(env.opt.check_every, 64));
+  LaunchTimer* tm = env.opt.profile ? &env.timer : nullptr;
+  const bool graph = env.opt.graph && !tm && s != nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t gr = nullptr;
+  slrf_status out = SLRF_OK;
+  int it = 0;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (gr) (void)hipGraphDestroy(gr);
+  };
+  while (it < maxit) {
+    const int chunk = std::min(every, maxit - it);
+    if (graph && it > 0 && chunk == every) {
+      if (!exec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          for (int q = 0; q < every; ++q) launch_iteration<R>(s, b, st, tol, maxit, false, ilu, nullptr, by);
+          launch_count_active(s, b.Ktot, st.flags, d_count);
+          e = hipStreamEndCapture(s, &gr);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          cleanup();
+          return fail(env, SLRF_E_DEVICE, std::string("hipGraph capture: ") + hipGetErrorString(e));
+        }
+      }
+      hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        cleanup();
+        return fail(env, SLRF_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+      }
+      it += every;
+    } else {
+      for (int q = 0; q < chunk; ++q, ++it) launch_iteration<R>(s, b, st, tol, maxit, it == 0, ilu, tm, by);
+      launch_count_active(s, b.Ktot, st.flags, d_count);
+    }
+    int active = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&active, d_count, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(env, SLRF_E_DEVICE, std::string("Krylov iteration: ") + hipGetErrorString(e));
+    }
+    if (tm) {
+      out = harvest_timer(env, (int64_t)b.G * b.n_tiles, ks);
+      if (out != SLRF_OK) break;
+    }
+    if (active == 0) break;
+  }
+  cleanup();
+  return out;
+}
+
+IterBytes iter_bytes(const std::vector<FilterJob>& jobs, const FilterLayout& lo, size_t rs, bool complex_rhat) {
+  IterBytes by{};
+  by.blk = (double)lo.EB * 2 * rs;
+  by.rhat = complex_rhat ? by.blk : (double)lo.ER * rs;
+  by.diag = (double)lo.ED * 2 * rs;
+  for (const auto& j : jobs) by.matrix += merged_csr_bytes(*j.P, 2 * rs);
+  return by;
+}
+
+// Per-column outcome of a finished BiCGStab run, summed per job.  sum_it gets
+// each job's total iteration count; with final_relres the recursive residual
+// ratio rnorm / fnorm feeds max_relres.
+template <typename R>
+slrf_status collect_stats(Env& env, std::vector<FilterJob>& jobs, const KrylovState<R>& st, int64_t Ktot,
+                          bool final_relres, std::vector<double>& sum_it) {
+  std::vector<int> fl(Ktot), its(Ktot);
+  std::vector<R> rn(Ktot), fn(Ktot);
+  HIPCHK(env, hipMemcpyAsync(fl.data(), st.flags, 4 * (size_t)Ktot, hipMemcpyDeviceToHost, env.stream));
+  HIPCHK(env, hipMemcpyAsync(its.data(), st.iters, 4 * (size_t)Ktot, hipMemcpyDeviceToHost, env.stream));
+  HIPCHK(env, hipMemcpyAsync(rn.data(), st.rnorm, sizeof(R) * (size_t)Ktot, hipMemcpyDeviceToHost, env.stream));
+  HIPCHK(env, hipMemcpyAsync(fn.data(), st.fnorm, sizeof(R) * (size_t)Ktot, hipMemcpyDeviceToHost, env.stream));
+  HIPCHK(env, hipStreamSynchronize(env.stream));
+  sum_it.assign(jobs.size(), 0.0);
+  int64_t c = 0;
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    slrf_filter_stats& fs = jobs[q].stats;
+    const int K = jobs[q].N * jobs[q].L;
+    for (int k = 0; k < K; ++k, ++c) {
+      fs.max_iterations = std::max(fs.max_iterations, its[c]);
+      sum_it[q] += its[c];
+      fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
+      if (fl[c] == COL_BREAKDOWN) fs.n_breakdown++;
+      if (fl[c] == COL_MAXIT) fs.n_maxit++;
+      if (final_relres) fs.max_relres = std::max(fs.max_relres, fn[c] > 0 ? (double)rn[c] / (double)fn[c] : 0.0);
+    }
+  }
+  return SLRF_OK;
+}
+
+void finish_stats(std::vector<FilterJob>& jobs, const std::vector<double>& sum_it, const slrf_filter_stats& ks,
+                  double seconds, int rounds) {
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    slrf_filter_stats& fs = jobs[q].stats;
+    fs.mean_iterations = sum_it[q] / std::max(1, jobs[q].N * jobs[q].L);
+    fs.refinements = rounds;
+    fs.seconds = seconds;
+    fs.spmm_seconds = ks.spmm_seconds;
+    fs.spmm_launches = ks.spmm_launches;
+    fs.spmm_bytes = ks.spmm_bytes;
+    fs.update_seconds = ks.update_seconds;
+    fs.update_launches = ks.update_launches;
+    fs.update_bytes = ks.update_bytes;
+  }
+}
+
+// FP64 filter application: every (job, pole, column) system solved by
+// BiCGStab in complex FP64 with x0 = 0 and shadow residual B X, then
+// U = sum_j 2 Re(w_j Y_j) per job.
+slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
+  const double t0 = now_s();
+  const hipStream_t s = env.stream;
+  std::vector<JobShape> js;
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu});
+  FilterLayout lo;
+  carve_filter(arena, js, false, lo);
+  if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
+  Batch b{};
+  std::vector<std::vector<char>> keep;
+  slrf_status st0 = upload_tables<double>(env, jobs, lo, b, keep);
+  if (st0 != SLRF_OK) return st0;
+  KrylovState<double> st = make_state<double>(lo);
+  int64_t dn = 0, rl = 0, pj = 0;
+  for (auto& j : jobs) {
+    launch_jacobi_diag<double>(s, (int)j.P->n, j.N, j.P->diagA, j.P->diagB, (const cx<double>*)lo.sig_j + pj,
+                               (cx<double>*)lo.d + dn, (cx<double>*)lo.dinv + dn);
+    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.rhat + rl);
+    dn += j.P->n * j.N;
+    rl += j.P->n * j.L;
+    pj += j.N;
+  }
+  launch_init<double>(s, b, st, lo.rhat);
+  launch_init_scalars<double>(s, b, st);
+  HIPCHK(env, hipGetLastError());
+  slrf_filter_stats ks{};
+  const IterBytes by = iter_bytes(jobs, lo, 8, false);
+  slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.any_ilu, by, lo.count, &ks);
+  if (rs != SLRF_OK) return rs;
+  int64_t blk = 0, wj = 0;
+  for (auto& j : jobs) {
+    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, st.x + blk, lo.w + 2 * wj, j.U, false);
+    blk += j.P->n * (int64_t)j.N * j.L;
+    wj += j.N;
+  }
+  HIPCHK(env, hipGetLastError());
+  for (auto& j : jobs) j.stats = slrf_filter_stats{};
+  std::vector<double> sum_it;
+  slrf_status cs = collect_stats<double>(env, jobs, st, lo.Ktot, true, sum_it);
+  if (cs != SLRF_OK) return cs;
+  finish_stats(jobs, sum_it, ks, now_s() - t0, 0);
+  return SLRF_OK;
+}
+
+// Filter application with complex FP32 inner solves and FP64 defect correction:
+//   Y = 0; repeat { R = F - S Y in FP64; stop the columns with
+//   ||R|| <= target ||F||; solve S D = R / ||R|| in FP32 by BiCGStab to relative
+//   residual kInnerTol32; Y += ||R|| D };  U = sum_j 2 Re(w_j Y_j).
+slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
+  const double t0 = now_s();
+  const hipStream_t s = env.stream;
+  std::vector<JobShape> js;
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu});
+  FilterLayout lo;
+  carve_filter(arena, js, true, lo);
+  if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
+  Batch b{};
+  std::vector<std::vector<char>> keep;
+  slrf_status st0 = upload_tables<float>(env, jobs, lo, b, keep);
+  if (st0 != SLRF_OK) return st0;
+  KrylovState<float> st = make_state<float>(lo);
+  std::vector<double> tol_host;
+  for (auto& j : jobs)
+    for (int c = 0; c < j.N * j.L; ++c) tol_host.push_back(j.target);
+  HIPCHK(env, hipMemcpyAsync(lo.tol64, tol_host.data(), 8 * tol_host.size(), hipMemcpyHostToDevice, s));
+  int64_t dn = 0, rl = 0, pj = 0;
+  for (auto& j : jobs) {
+    launch_jacobi_diag<float>(s, (int)j.P->n, j.N, j.P->diagA32, j.P->diagB32, (const cx<float>*)lo.sig_j + pj,
+                              (cx<float>*)lo.d + dn, (cx<float>*)lo.dinv + dn);
+    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.F + rl);
+    dn += j.P->n * j.N;
+    rl += j.P->n * j.L;
+    pj += j.N;
+  }
+  HIPCHK(env, hipGetLastError());
+  const IterBytes by = iter_bytes(jobs, lo, 4, true);
+  slrf_filter_stats ks{};
+  for (auto& j : jobs) j.stats = slrf_filter_stats{};
+  std::vector<double> sum_it(jobs.size(), 0.0), it_round;
+  int rounds = 0;
+  for (int round = 0; round <= kMaxRounds; ++round) {
+    launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64);
+    launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.count);
+    HIPCHK(env, hipGetLastError());
+    int open = 0;
+    HIPCHK(env, hipMemcpyAsync(&open, lo.count, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(env, hipStreamSynchronize(s));
+    if (round > 0)
+      for (auto& j : jobs) j.stats.spmv += (int64_t)j.N * j.L;  // the defect's product with S
+    if (open == 0 || round == kMaxRounds) break;
+    ++rounds;
+    launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
+    launch_init_scalars<float>(s, b, st);
+    slrf_status rs = run_krylov<float>(env, b, st, (float)kInnerTol32, lo.any_ilu, by, lo.count, &ks);
+    if (rs != SLRF_OK) return rs;
+    launch_accumulate(s, b, st.x, lo.scale, lo.Y, round == 0);
+    slrf_status cs = collect_stats<float>(env, jobs, st, lo.Ktot, false, it_round);
+    if (cs != SLRF_OK) return cs;
+    for (size_t q = 0; q < jobs.size(); ++q) sum_it[q] += it_round[q];
+  }
+  int64_t blk = 0, wj = 0;
+  for (auto& j : jobs) {
+    if (rounds > 0)
+      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, lo.Y + blk, lo.w + 2 * wj, j.U, false);
+    else
+      HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
+    blk += j.P->n * (int64_t)j.N * j.L;
+    wj += j.N;
+  }
+  HIPCHK(env, hipGetLastError());
+  std::vector<double> rr(lo.Ktot);
+  HIPCHK(env, hipMemcpyAsync(rr.data(), lo.relres, 8 * (size_t)lo.Ktot, hipMemcpyDeviceToHost, s));
+  HIPCHK(env, hipStreamSynchronize(s));
+  int64_t c = 0;
+  for (size_t q = 0; q < jobs.size(); ++q)
+    for (int k = 0; k < jobs[q].N * jobs[q].L; ++k, ++c)
+      jobs[q].stats.max_relres = std::max(jobs[q].stats.max_relres, rr[c]);
+  finish_stats(jobs, sum_it, ks, now_s() - t0, rounds);
+  return SLRF_OK;
+}
+
+slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
+  if (jobs.empty()) return SLRF_OK;
+  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs) : filter_batch_fp64(env, arena, jobs);
+}
+
+// ---------------------------------------------------------------------------
+// Outer iteration (Algorithm 1) per pencil
+
+size_t outer_bytes(int64_t n, int64_t L) {
+  const int nch = gram_chunks((int)n, (int)L);
+  const int64_t nrr = (n + 255) / 256;
+  size_t b = 0;
+  b += 5 * al((size_t)n * L * 8);              // V U WA WB X
+  b += al((size_t)nch * 2 * L * L * 8);        // Gram partials
+  b += 3 * al((size_t)L * L * 8);              // GA GB Z
+  b += al((size_t)L * 8);                      // theta
+  b += al((size_t)(nrr * 2 * L + 2 * L) * 8);  // residual partials
+  return b;
+}
+
+struct SolveJob {
+  Pencil* P = nullptr;
+  int L = 0, N = 0;
+  double gamma = 0;
+  std::vector<double> sig, w;  // host, 2N each
+  char* mem = nullptr;         // outer_bytes(n, L) of device buffers
+  double *V = nullptr, *U = nullptr, *WA = nullptr, *WB = nullptr, *X = nullptr, *part = nullptr, *GA = nullptr,
+         *GB = nullptr, *Zd = nullptr, *th = nullptr, *rpart = nullptr;
+  int nch = 0, nrr = 0;
+  int k = 0, prev_count = -1, count = 0;
+  double prev_maxr = INFINITY, prev_prev = INFINITY, mix_c = 1e-3, iter_sum = 0, t0 = 0;
+  bool done = false;
+  slrf_status status = SLRF_OK;
+  std::string msg;
+  std::vector<double> theta, rho;
+  slrf_solve_stats ss{};
+
+  void carve(char* m) {
+    mem = m;
+    const int64_t n = P->n;
+    nch = gram_chunks((int)n, L);
+    nrr = (int)((n + 255) / 256);
+    Carver co{m, 0, outer_bytes(n, L)};
+    V = co.take<double>((size_t)n * L);
+    U = co.take<double>((size_t)n * L);
+    WA = co.take<double>((size_t)n * L);
+    WB = co.take<double>((size_t)n * L);
+    X = co.take<double>((size_t)n * L);
+    part = co.take<double>((size_t)nch * 2 * L * L);
+    GA = co.take<double>((size_t)L * L);
+    GB = co.take<double>((size_t)L * L);
+    Zd = co.take<double>((size_t)L * L);
+    th = co.take<double>(L);
+    rpart = co.take<double>((size_t)nrr * 2 * L + 2 * L);
+  }
+};
+
+// One Rayleigh-Ritz pass (Section 3, B-orthonormalisation by the projected
+// pencil): Y = Xin Z with Z^T (Xin^T A Xin) Z = diag(theta), Z^T (Xin^T B Xin) Z = I.
+slrf_status rr_pass(Env& env, SolveJob& J, const double* Xin, double* Y, std::vector<double>& theta) {
+  const hipStream_t s = env.stream;
+  const int n = (int)J.P->n, L = J.L;
+  launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, Xin, J.WA, J.WB);
+  launch_gram(s, n, L, Xin, J.WA, J.WB, J.part, J.nch, J.GA, J.GB);
+  HIPCHK(env, hipGetLastError());
+  std::vector<double> hA((size_t)L * L), hB((size_t)L * L), Z((size_t)L * L);
+  HIPCHK(env, hipMemcpyAsync(hA.data(), J.GA, 8 * hA.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(env, hipMemcpyAsync(hB.data(), J.GB, 8 * hB.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(env, hipStreamSynchronize(s));
+  theta.assign(L, 0.0);
+  if (!projected_pencil(L, hA.data(), hB.data(), theta.data(), Z.data()))
+    return fail(env, SLRF_E_BREAKDOWN, "projected pencil not solvable (non-finite or zero Gram matrix)");
+  HIPCHK(env, hipMemcpyAsync(J.Zd, Z.data(), 8 * Z.size(), hipMemcpyHostToDevice, s));
+  const double* xs[1] = {Xin};
+  double* ys[1] = {Y};
+  launch_gemm_nz(s, n, L, L, 1, xs, J.Zd, ys);
+  HIPCHK(env, hipGetLastError());
+  HIPCHK(env, hipStreamSynchronize(s));  // Z host buffer lifetime
+  return SLRF_OK;
+}
+
+// Rayleigh-Ritz (two passes), residuals rho_i and the stopping test of one
+// outer iteration, after the filter has written U.
+slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
+  const hipStream_t s = env.stream;
+  const int n = (int)J.P->n, L = J.L;
+  J.ss.filter_seconds += fs.seconds;
+  J.ss.spmv_total += fs.spmv;
+  J.iter_sum += fs.mean_iterations;
+  slrf_filter_stats& kk = J.ss.kernels;
+  kk.spmm_seconds += fs.spmm_seconds;
+  kk.spmm_launches += fs.spmm_launches;
+  kk.spmm_bytes += fs.spmm_bytes;
+  kk.update_seconds += fs.update_seconds;
+  kk.update_launches += fs.update_launches;
+  kk.update_bytes += fs.update_bytes;
+  std::vector<double> th1;
+  slrf_status st = rr_pass(env, J, J.U, J.X, th1);
+  if (st != SLRF_OK) return st;
+  st = rr_pass(env, J, J.X, J.V, J.theta);
+  if (st != SLRF_OK) return st;
+  launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, J.V, J.WA, J.WB);
+  HIPCHK(env, hipMemcpyAsync(J.th, J.theta.data(), 8 * (size_t)L, hipMemcpyHostToDevice, s));
+  launch_resid(s, n, L, J.WA, J.WB, J.th, J.rpart, J.nrr);
+  HIPCHK(env, hipGetLastError());
+  std::vector<double> sums(2 * L);
+  HIPCHK(env, hipMemcpyAsync(sums.data(), J.rpart + (size_t)J.nrr * 2 * L, 16 * (size_t)L, hipMemcpyDeviceToHost, s));
+  HIPCHK(env, hipStreamSynchronize(s));
+  J.rho.assign(L, 0.0);
+  int count = 0;
+  bool all_ok = true;
+  double maxr = 0;
+  for (int c = 0; c < L; ++c) {
+    J.rho[c] = std::sqrt(sums[c]) / (std::fabs(J.theta[c]) * std::sqrt(sums[L + c]));
+    if (J.theta[c] > 0 && J.theta[c] <= J.gamma) {
+      ++count;
+      maxr = std::max(maxr, J.rho[c]);
+      if (!(J.rho[c] <= env.opt.outer_tol)) all_ok = false;
+    }
+  }
+  J.count = count;
+  J.ss.max_resid = maxr;
+  J.prev_prev = J.prev_maxr;
+  J.prev_maxr = count ? maxr : INFINITY;
+  if (env.verbose)
+    fprintf(stderr,
+            "[slrf] n=%d outer %d: inner its mean %.1f max %d (rounds %d, maxit %d, breakdown %d, max relres %.2e) "
+            "theta [%.6g, %.6g] count %d max rho %.3e\n",
+            n, J.k, fs.mean_iterations, fs.max_iterations, fs.refinements, fs.n_maxit, fs.n_breakdown, fs.max_relres,
+            J.theta[0], J.theta[L - 1], count, maxr);
+  if (count == L) {
+    J.done = true;
+    J.status = SLRF_E_SUBSPACE_TOO_SMALL;
+    J.msg = "all L Ritz values lie in (0, gamma]: increase L";
+  } else if (count == J.prev_count && all_ok) {
+    J.done = true;
+    J.status = SLRF_OK;
+  } else if (J.k >= std::max(1, env.opt.outer_maxit)) {
+    J.done = true;
+    J.status = SLRF_E_NOT_CONVERGED;
+    J.msg = "outer iteration limit reached";
+  }
+  J.prev_count = count;
+  if (J.done) {
+    J.ss.outer_iterations = J.k;
+    J.ss.inner_iterations = J.iter_sum / std::max(1, J.k);
+    int found = 0;
+    for (int c = 0; c < L; ++c)
+      if (J.theta[c] > 0 && J.theta[c] <= J.gamma && J.rho[c] <= env.opt.outer_tol) ++found;
+    J.ss.n_found = found;
+    J.ss.seconds = now_s() - J.t0;
+  }
+  return SLRF_OK;
+}
+
+// One outer step for every job not yet done: one batched filter application
+// over all of them, then Rayleigh-Ritz and residuals per job.  A failure marks
+// the jobs of the step done with that status.
+slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs) {
+  std::vector<FilterJob> fj;
+  std::vector<SolveJob*> act;
+  for (SolveJob* J : jobs) {
+    if (J->done) continue;
+    ++J->k;
+    double target = env.opt.inner_tol;
+    if (env.opt.precision == SLRF_MIXED) {
+      // Inner accuracy follows the outer residual: target = c * (largest
+      // residual of the previous outer iteration), within [1e-13, 1e-4].  The
+      // residual of a Ritz pair amplifies the inner error by up to about
+      // lambda_max / theta, so when an outer iteration fails to cut the
+      // residual 3x, c shrinks 100x.
+      if (J->prev_prev < INFINITY && J->prev_maxr > 0.3 * J->prev_prev) J->mix_c = std::max(1e-9, J->mix_c * 1e-2);
+      target = std::max(1e-13, std::min(1e-4, J->mix_c * J->prev_maxr));
+    }
+    fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}});
+    act.push_back(J);
+  }
+  if (act.empty()) return SLRF_OK;
+  slrf_status st = filter_batch(env, arena, fj);
+  for (size_t q = 0; q < act.size() && st == SLRF_OK; ++q) st = finish_outer(env, *act[q], fj[q].stats);
+  if (st != SLRF_OK)
+    for (SolveJob* J : act)
+      if (!J->done) {
+        J->done = true;
+        J->status = st;
+        J->msg = env.err;
+        J->ss.outer_iterations = J->k;
+        J->ss.seconds = now_s() - J->t0;
+      }
+  return st;
+}
+
+slrf_status prepare_job(Env& env, SolveJob& J, double gamma, const slrf_poles* poles_in, const double* d_V0,
+                        int max_N) {
+  J.gamma = gamma;
+  const slrf_poles* poles = poles_in;
+  slrf_poles designed{};
+  std::vector<double> ds, dw;
+  if (!poles) {
+    ds.resize(2 * kDefaultPoles);
+    dw.resize(2 * kDefaultPoles);
+    if (slrf_design_poles(kDefaultPoles, 1.0, 0.01, gamma, ds.data(), dw.data(), nullptr) != SLRF_OK)
+      return fail(env, SLRF_E_INVALID_ARG, "pole design failed");
+    designed = {kDefaultPoles, ds.data(), dw.data()};
+    poles = &designed;
+  }
+  slrf_status st = check_poles(env, poles, max_N);
+  if (st != SLRF_OK) return st;
+  J.N = poles->n_poles;
+  J.sig.assign(poles->sigma, poles->sigma + 2 * J.N);
+  J.w.assign(poles->weight, poles->weight + 2 * J.N);
+  J.t0 = now_s();
+  if (d_V0)
+    HIPCHK(env, hipMemcpyAsync(J.V, d_V0, 8 * (size_t)J.P->n * J.L, hipMemcpyDeviceToDevice, env.stream));
+  else
+    launch_gaussian(env.stream, (int64_t)J.P->n * J.L, env.opt.seed, J.V);
+  HIPCHK(env, hipGetLastError());
+  HIPCHK(env, hipStreamSynchronize(env.stream));
+  return SLRF_OK;
+}
+
+slrf_status copy_results(Env& env, const SolveJob& J, int64_t* n_found, double* h_evals, double* d_evecs,
+                         double* h_resid, slrf_solve_stats* stats) {
+  HIPCHK(env, hipMemcpyAsync(d_evecs, J.V, 8 * (size_t)J.P->n * J.L, hipMemcpyDeviceToDevice, env.stream));
+  HIPCHK(env, hipStreamSynchronize(env.stream));
+  for (int c = 0; c < J.L; ++c) {
+    h_evals[c] = c < (int)J.theta.size() ? J.theta[c] : 0.0;
+    h_resid[c] = c < (int)J.rho.size() ? J.rho[c] : 0.0;
+  }
+  *n_found = J.ss.n_found;
+  if (stats) *stats = J.ss;
+  return SLRF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single-pencil context: [pencil | timer counters | filter arena | outer buffers]
+
+struct slrf_ctx_s {
+  Env env;
+  Pencil P;
+  char* ws = nullptr;
+  int64_t max_L = 0;
+  int32_t max_N = 0;
+  size_t arena_off = 0, arena_bytes = 0, outer_off = 0;
+};
+
+// Batch of pencils: [timer counters | filter arena | pool of pencils and outer buffers]
+struct slrf_batch_s {
+  Env env;
+  Pool pool;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  int max_N = 0;
+  int next_id = 0;
+  struct Entry {
+    std::unique_ptr<Pencil> P;
+    std::unique_ptr<SolveJob> J;
+  };
+  std::map<int, Entry> entries;
+
+  std::vector<JobShape> active_shapes() const {
+    std::vector<JobShape> js;
+    for (const auto& kv : entries)
+      if (!kv.second.J->done)
+        js.push_back({kv.second.P->n, kv.second.P->nnz, kv.second.J->L, kv.second.J->N, kv.second.P->use_ilu});
+    return js;
+  }
+};
+
+extern "C" {
+
+void slrf_default_options(slrf_options* o) {
+  if (!o) return;
+  o->precision = SLRF_FP64;
+  o->inner_tol = 1e-10;
+  o->inner_maxit = 1000;
+  o->outer_tol = 1e-8;
+  o->outer_maxit = 40;
+  o->check_every = 10;
+  o->seed = 1;
+  o->precond = 0;
+  o->profile = 0;
+  o->graph = 0;
+}
+
+const char* slrf_status_string(slrf_status s) {
+  switch (s) {
+    case SLRF_OK: return "ok";
+    case SLRF_E_INVALID_ARG: return "invalid argument";
+    case SLRF_E_NOT_SPD: return "A or B has a non-positive or missing diagonal entry";
+    case SLRF_E_WORKSPACE: return "workspace too small or misaligned";
+    case SLRF_E_DEVICE: return "HIP runtime error";
+    case SLRF_E_NOT_CONVERGED: return "outer iteration did not converge";
+    case SLRF_E_SUBSPACE_TOO_SMALL: return "subspace too small: every Ritz value lies in the interval";
+    case SLRF_E_BREAKDOWN: return "breakdown of the projected problem";
+  }
+  return "unknown status";
+}
+
+const char* slrf_last_error(slrf_ctx ctx) { return ctx ? ctx->env.err.c_str() : "null context"; }
+
+slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma, double* sigma_out,
+                              double* weight_out, double* sep_out) {
+  if (N < 1 || N > 16 || !(alpha > 0) || !(beta > 0) || !(gamma > 0) || !sigma_out || !weight_out)
+    return SLRF_E_INVALID_ARG;
+  std::vector<double> u;
+  if (!design_unit_cached(N, alpha, beta, u)) return SLRF_E_INVALID_ARG;
+  std::complex<double> dphi = 0;
+  for (int j = 0; j < N; ++j) {
+    const std::complex<double> sg(gamma * u[j], gamma * u[j] * alpha);
+    const std::complex<double> wj(gamma * u[N + 2 * j], gamma * u[N + 2 * j + 1]);
+    sigma_out[2 * j] = sg.real();
+    sigma_out[2 * j + 1] = sg.imag();
+    weight_out[2 * j] = wj.real();
+    weight_out[2 * j + 1] = wj.imag();
+    dphi += -2.0 * (wj / ((gamma - sg) * (gamma - sg))).real();
+  }
+  if (sep_out) *sep_out = std::abs(dphi.real());
+  return SLRF_OK;
+}
+
+slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
+  if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
+  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  // sized for the ILU(0) vectors whenever the pattern allows them
+  const size_t arena =
+      filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz)}}, precision == SLRF_MIXED);
+  *bytes = pencil_bytes(n, nnz) + al(kTimerSlots * 4) + arena + outer_bytes(n, L);
+  return SLRF_OK;
+}
+
+slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
+                        const double* a_val, const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                        void* d_workspace, size_t ws_bytes, int64_t max_L, int32_t max_N, const slrf_options* opt,
+                        void* hip_stream) {
+  if (!out) return SLRF_E_INVALID_ARG;
+  *out = nullptr;
+  slrf_ctx ctx = new (std::nothrow) slrf_ctx_s();
+  if (!ctx) return SLRF_E_INVALID_ARG;
+  *out = ctx;  // kept on failure so the caller can read the message
+  Env& env = ctx->env;
+  slrf_status st = setup_env(env, opt, hip_stream);
+  if (st != SLRF_OK) return st;
+  if (max_L < 1 || max_N < 1) return fail(env, SLRF_E_INVALID_ARG, "bad size or NULL argument");
+  int64_t nnz = 0;
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, ctx->P, env.err,
+                    nullptr, &nnz);
+  if (st != SLRF_OK) return st;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0)
+    return fail(env, SLRF_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  size_t need = 0;
+  if (slrf_workspace_bytes(n, nnz, max_L, max_N, env.opt.precision, &need) != SLRF_OK)
+    return fail(env, SLRF_E_INVALID_ARG, "bad sizes");
+  if (ws_bytes < need)
+    return fail(env, SLRF_E_WORKSPACE,
+                "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(need));
+  ctx->max_L = max_L;
+  ctx->max_N = max_N;
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, ctx->P, env.err,
+                    (char*)d_workspace, nullptr);
+  if (st != SLRF_OK) return st;
+  const size_t poff = pencil_bytes(n, nnz);
+  if (!env.setup_timer((int*)((char*)d_workspace + poff))) return fail(env, SLRF_E_DEVICE, "timer set-up failed");
+  ctx->arena_off = poff + al(kTimerSlots * 4);
+  ctx->arena_bytes =
+      filter_arena_bytes({JobShape{n, nnz, (int)max_L, max_N, ilu_allowed(n, nnz)}}, env.opt.precision == SLRF_MIXED);
+  ctx->outer_off = ctx->arena_off + ctx->arena_bytes;
+  ctx->ws = (char*)d_workspace;
   return SLRF_OK;
 }
 
@@ -791,153 +1294,183 @@ void slrf_destroy(slrf_ctx ctx) { delete ctx; }
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L, const double* d_X, double* d_U,
                               slrf_filter_stats* stats) {
   if (!ctx || !ctx->ws) return SLRF_E_INVALID_ARG;
+  Env& env = ctx->env;
   if (L < 1 || L > ctx->max_L || !d_X || !d_U || d_X == d_U)
-    return fail(ctx, SLRF_E_INVALID_ARG, "bad L or block pointers");
-  slrf_status st = check_poles(ctx, poles);
+    return fail(env, SLRF_E_INVALID_ARG, "bad L or block pointers");
+  slrf_status st = check_poles(env, poles, ctx->max_N);
   if (st != SLRF_OK) return st;
-  Carver cv{ctx->ws, ctx->static_bytes, ctx->ws_bytes};
-  if (ctx->opt.precision == SLRF_MIXED) return filter_mixed(ctx, cv, poles, (int)L, d_X, d_U, stats, ctx->opt.inner_tol);
-  return filter_fp64(ctx, cv, poles, (int)L, d_X, d_U, stats);
-}
-
-slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L64, const slrf_poles* poles_in,
-                                const double* d_V0, int64_t* n_found, double* h_evals, double* d_evecs,
-                                double* h_resid, slrf_solve_stats* stats) {
-  const double t0 = now_s();
-  if (!ctx || !ctx->ws) return SLRF_E_INVALID_ARG;
-  if (!(gamma > 0) || L64 < 2 || L64 > ctx->max_L || !n_found || !h_evals || !d_evecs || !h_resid)
-    return fail(ctx, SLRF_E_INVALID_ARG, "bad gamma, L or output pointer");
-  const int L = (int)L64, n = (int)ctx->n;
-  if (L > n) return fail(ctx, SLRF_E_INVALID_ARG, "L exceeds n");
-  std::vector<double> psig, pw;
-  slrf_poles designed{};
-  const slrf_poles* poles = poles_in;
-  if (!poles) {
-    psig.resize(8);
-    pw.resize(8);
-    if (slrf_design_poles(4, 1.0, 0.01, gamma, psig.data(), pw.data(), nullptr) != SLRF_OK)
-      return fail(ctx, SLRF_E_INVALID_ARG, "pole design failed");
-    designed = {4, psig.data(), pw.data()};
-    poles = &designed;
-  }
-  slrf_status st = check_poles(ctx, poles);
+  std::vector<FilterJob> jobs{
+      {&ctx->P, (int)L, poles->n_poles, poles->sigma, poles->weight, d_X, d_U, env.opt.inner_tol, {}}};
+  Carver arena{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes};
+  st = filter_batch(env, arena, jobs);
   if (st != SLRF_OK) return st;
-  hipStream_t s = ctx->stream;
-  // outer buffers sit after the Krylov region sized for max_L, max_N
-  Carver co{ctx->ws, ctx->static_bytes + krylov_bytes(n, ctx->nnz, ctx->max_L, ctx->max_N, ctx->opt.precision),
-            ctx->ws_bytes};
-  const int nch = gram_chunks(n, L);
-  const int nrr = (n + 255) / 256;
-  double* V = co.take<double>((size_t)n * L);
-  double* U = co.take<double>((size_t)n * L);
-  double* WA = co.take<double>((size_t)n * L);
-  double* WB = co.take<double>((size_t)n * L);
-  double* X = co.take<double>((size_t)n * L);
-  double* part = co.take<double>((size_t)nch * 2 * L * L);
-  double* GA = co.take<double>((size_t)L * L);
-  double* GB = co.take<double>((size_t)L * L);
-  double* Zd = co.take<double>((size_t)L * L);
-  double* th_d = co.take<double>(L);
-  double* rpart = co.take<double>((size_t)nrr * 2 * L + 2 * L);
-  if (co.off > co.cap) return fail(ctx, SLRF_E_WORKSPACE, "workspace too small for the outer iteration");
-  if (d_V0)
-    HIPCHK(ctx, hipMemcpyAsync(V, d_V0, 8 * (size_t)n * L, hipMemcpyDeviceToDevice, s));
-  else
-    launch_gaussian(s, (int64_t)n * L, ctx->opt.seed, V);
-
-  slrf_solve_stats ss{};
-  std::vector<double> theta, theta2, rho(L, 0.0);
-  int prev_count = -1, count = 0;
-  double iter_sum = 0, prev_maxr = INFINITY, prev_prev_maxr = INFINITY, mix_c = 1e-3;
-  bool converged = false, too_small = false;
-  int k = 0;
-  for (k = 1; k <= std::max(1, ctx->opt.outer_maxit); ++k) {
-    Carver cv{ctx->ws, ctx->static_bytes, ctx->ws_bytes};
-    slrf_filter_stats fs{};
-    if (ctx->opt.precision == SLRF_MIXED) {
-      // Inner accuracy follows the outer residual: target = c * (largest residual
-      // of the previous outer iteration), within [1e-13, 1e-4].  The residual of a
-      // Ritz pair amplifies the inner error by up to ~lambda_max / theta, so when
-      // an outer iteration fails to cut the residual 3x, c shrinks 100x.
-      if (prev_prev_maxr < INFINITY && prev_maxr > 0.3 * prev_prev_maxr) mix_c = std::max(1e-9, mix_c * 1e-2);
-      const double target = std::max(1e-13, std::min(1e-4, mix_c * prev_maxr));
-      st = filter_mixed(ctx, cv, poles, L, V, U, &fs, target);
-    } else {
-      st = filter_fp64(ctx, cv, poles, L, V, U, &fs);
-    }
-    if (st != SLRF_OK) return st;
-    ss.filter_seconds += fs.seconds;
-    ss.spmv_total += fs.spmv;
-    iter_sum += fs.mean_iterations;
-    ss.kernels.spmm_seconds += fs.spmm_seconds;
-    ss.kernels.spmm_launches += fs.spmm_launches;
-    ss.kernels.spmm_bytes += fs.spmm_bytes;
-    ss.kernels.update_seconds += fs.update_seconds;
-    ss.kernels.update_launches += fs.update_launches;
-    ss.kernels.update_bytes += fs.update_bytes;
-    st = rr_pass(ctx, L, U, X, WA, WB, part, nch, GA, GB, Zd, theta);
-    if (st != SLRF_OK) return st;
-    st = rr_pass(ctx, L, X, V, WA, WB, part, nch, GA, GB, Zd, theta2);
-    if (st != SLRF_OK) return st;
-    // residuals of the Ritz pairs (theta2, V)
-    launch_spmm_real<double>(s, n, L, ctx->rowptr, ctx->col, ctx->ab64, V, WA, WB);
-    HIPCHK(ctx, hipMemcpyAsync(th_d, theta2.data(), 8 * (size_t)L, hipMemcpyHostToDevice, s));
-    launch_resid(s, n, L, WA, WB, th_d, rpart, nrr);
-    HIPCHK(ctx, hipGetLastError());
-    std::vector<double> sums(2 * L);
-    HIPCHK(ctx, hipMemcpyAsync(sums.data(), rpart + (size_t)nrr * 2 * L, 16 * (size_t)L, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    count = 0;
-    bool all_ok = true;
-    double maxr = 0;
-    for (int c = 0; c < L; ++c) {
-      rho[c] = std::sqrt(sums[c]) / (std::fabs(theta2[c]) * std::sqrt(sums[L + c]));
-      if (theta2[c] > 0 && theta2[c] <= gamma) {
-        ++count;
-        maxr = std::max(maxr, rho[c]);
-        if (!(rho[c] <= ctx->opt.outer_tol)) all_ok = false;
-      }
-    }
-    ss.max_resid = maxr;
-    prev_prev_maxr = prev_maxr;
-    prev_maxr = count ? maxr : INFINITY;
-    if (ctx->verbose)
-      fprintf(stderr, "[slrf] outer %d: inner its mean %.1f max %d (rounds %d, maxit %d, breakdown %d, max relres "
-                      "%.2e) theta [%.6g, %.6g] count %d max rho %.3e\n",
-              k, fs.mean_iterations, fs.max_iterations, fs.refinements, fs.n_maxit, fs.n_breakdown, fs.max_relres,
-              theta2[0], theta2[L - 1], count, maxr);
-    if (count == L) {
-      too_small = true;
-      break;
-    }
-    if (count == prev_count && all_ok) {
-      converged = true;
-      break;
-    }
-    prev_count = count;
-  }
-  ss.outer_iterations = std::min(k, std::max(1, ctx->opt.outer_maxit));
-  ss.inner_iterations = iter_sum / std::max(1, ss.outer_iterations);
-  HIPCHK(ctx, hipMemcpyAsync(d_evecs, V, 8 * (size_t)n * L, hipMemcpyDeviceToDevice, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  int found = 0;
-  for (int c = 0; c < L; ++c) {
-    h_evals[c] = theta2[c];
-    h_resid[c] = rho[c];
-    if (theta2[c] > 0 && theta2[c] <= gamma && rho[c] <= ctx->opt.outer_tol) ++found;
-  }
-  *n_found = found;
-  ss.n_found = found;
-  ss.seconds = now_s() - t0;
-  if (stats) *stats = ss;
-  if (too_small) return fail(ctx, SLRF_E_SUBSPACE_TOO_SMALL, "all L Ritz values lie in (0, gamma]: increase L");
-  if (!converged) return fail(ctx, SLRF_E_NOT_CONVERGED, "outer iteration limit reached");
+  if (stats) *stats = jobs[0].stats;
   return SLRF_OK;
 }
 
-}  // extern "C"
+slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slrf_poles* poles, const double* d_V0,
+                                int64_t* n_found, double* h_evals, double* d_evecs, double* h_resid,
+                                slrf_solve_stats* stats) {
+  if (!ctx || !ctx->ws) return SLRF_E_INVALID_ARG;
+  Env& env = ctx->env;
+  if (!(gamma > 0) || L < 2 || L > ctx->max_L || !n_found || !h_evals || !d_evecs || !h_resid)
+    return fail(env, SLRF_E_INVALID_ARG, "bad gamma, L or output pointer");
+  if (L > ctx->P.n) return fail(env, SLRF_E_INVALID_ARG, "L exceeds n");
+  SolveJob J;
+  J.P = &ctx->P;
+  J.L = (int)L;
+  J.carve(ctx->ws + ctx->outer_off);
+  slrf_status st = prepare_job(env, J, gamma, poles, d_V0, ctx->max_N);
+  if (st != SLRF_OK) return st;
+  const std::vector<SolveJob*> jobs{&J};
+  while (!J.done) {
+    st = outer_step(env, Carver{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes}, jobs);
+    if (st != SLRF_OK) return st;
+  }
+  st = copy_results(env, J, n_found, h_evals, d_evecs, h_resid, stats);
+  if (st != SLRF_OK) return st;
+  if (J.status != SLRF_OK) return fail(env, J.status, J.msg);
+  return SLRF_OK;
+}
 
-extern "C" {
+// ---- batches ------------------------------------------------------------------
+
+slrf_status slrf_batch_footprint(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision,
+                                 size_t* persistent_bytes, size_t* transient_bytes) {
+  if (n < 1 || nnz < n || L < 1 || N < 1 || n > INT32_MAX || nnz > INT32_MAX || !persistent_bytes ||
+      !transient_bytes)
+    return SLRF_E_INVALID_ARG;
+  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  *persistent_bytes = al(pencil_bytes(n, nnz)) + al(outer_bytes(n, L));
+  // counts the two blocks a batch with an ILU(0) pencil gives every pencil, so
+  // that the sum over a set of pencils bounds the arena the set needs
+  *transient_bytes = filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz), true}},
+                                        precision == SLRF_MIXED);
+  return SLRF_OK;
+}
+
+const char* slrf_batch_last_error(slrf_batch b) { return b ? b->env.err.c_str() : "null batch"; }
+
+slrf_status slrf_batch_create(slrf_batch* out, void* d_workspace, size_t ws_bytes, size_t arena_bytes,
+                              int32_t max_poles, const slrf_options* opt, void* hip_stream) {
+  if (!out) return SLRF_E_INVALID_ARG;
+  *out = nullptr;
+  slrf_batch b = new (std::nothrow) slrf_batch_s();
+  if (!b) return SLRF_E_INVALID_ARG;
+  *out = b;
+  Env& env = b->env;
+  slrf_status st = setup_env(env, opt, hip_stream);
+  if (st != SLRF_OK) return st;
+  if (max_poles < 1 || max_poles > 16) return fail(env, SLRF_E_INVALID_ARG, "max_poles must be in [1, 16]");
+  if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0)
+    return fail(env, SLRF_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  const size_t head = al(kTimerSlots * 4);
+  if (ws_bytes < head + al(arena_bytes))
+    return fail(env, SLRF_E_WORKSPACE, "workspace smaller than the arena it should hold");
+  char* ws = (char*)d_workspace;
+  if (!env.setup_timer((int*)ws)) return fail(env, SLRF_E_DEVICE, "timer set-up failed");
+  b->arena = ws + head;
+  b->arena_bytes = al(arena_bytes);
+  b->pool.init(ws + head + b->arena_bytes, ws_bytes - head - b->arena_bytes);
+  b->max_N = max_poles;
+  return SLRF_OK;
+}
+
+slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
+                           const double* a_val, const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                           double gamma, int64_t L, const slrf_poles* poles, const double* d_V0, int32_t* id) {
+  if (!b || !id) return SLRF_E_INVALID_ARG;
+  Env& env = b->env;
+  if (!(gamma > 0) || L < 2 || L > n || L > INT32_MAX) return fail(env, SLRF_E_INVALID_ARG, "bad gamma or L");
+  const int N = poles ? poles->n_poles : kDefaultPoles;
+  if (N < 1 || N > b->max_N) return fail(env, SLRF_E_INVALID_ARG, "pole count outside [1, max_poles]");
+  int64_t nnz = 0;
+  auto P = std::make_unique<Pencil>();
+  slrf_status st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, *P,
+                                env.err, nullptr, &nnz);
+  if (st != SLRF_OK) return st;
+  std::vector<JobShape> shapes = b->active_shapes();
+  shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz)});
+  if (filter_arena_bytes(shapes, env.opt.precision == SLRF_MIXED) > b->arena_bytes)
+    return fail(env, SLRF_E_WORKSPACE, "the filter arena cannot hold this pencil next to the active ones");
+  const size_t pb = pencil_bytes(n, nnz), ob = outer_bytes(n, L);
+  char* pm = b->pool.alloc(pb);
+  if (!pm) return fail(env, SLRF_E_WORKSPACE, "no room for the pencil in the workspace");
+  char* om = b->pool.alloc(ob);
+  if (!om) {
+    b->pool.release(pm, pb);
+    return fail(env, SLRF_E_WORKSPACE, "no room for the subspace blocks in the workspace");
+  }
+  auto J = std::make_unique<SolveJob>();
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, *P, env.err, pm,
+                    nullptr);
+  if (st == SLRF_OK) {
+    J->P = P.get();
+    J->L = (int)L;
+    J->carve(om);
+    st = prepare_job(env, *J, gamma, poles, d_V0, b->max_N);
+  }
+  if (st != SLRF_OK) {
+    b->pool.release(pm, pb);
+    b->pool.release(om, ob);
+    return st;
+  }
+  *id = b->next_id++;
+  b->entries[*id] = {std::move(P), std::move(J)};
+  return SLRF_OK;
+}
+
+slrf_status slrf_batch_step(slrf_batch b, int32_t* n_active) {
+  if (!b) return SLRF_E_INVALID_ARG;
+  std::vector<SolveJob*> jobs;
+  for (auto& kv : b->entries)
+    if (!kv.second.J->done) jobs.push_back(kv.second.J.get());
+  const slrf_status st = outer_step(b->env, Carver{b->arena, 0, b->arena_bytes}, jobs);
+  int act = 0;
+  for (auto& kv : b->entries)
+    if (!kv.second.J->done) ++act;
+  if (n_active) *n_active = act;
+  return st;
+}
+
+slrf_status slrf_batch_query(slrf_batch b, int32_t id, int32_t* done, int32_t* outer_iterations) {
+  if (!b) return SLRF_E_INVALID_ARG;
+  auto it = b->entries.find(id);
+  if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
+  if (done) *done = it->second.J->done ? 1 : 0;
+  if (outer_iterations) *outer_iterations = it->second.J->k;
+  return SLRF_OK;
+}
+
+slrf_status slrf_batch_result(slrf_batch b, int32_t id, int64_t* n_found, double* h_evals, double* d_evecs,
+                              double* h_resid, slrf_solve_stats* stats) {
+  if (!b) return SLRF_E_INVALID_ARG;
+  if (!n_found || !h_evals || !d_evecs || !h_resid) return fail(b->env, SLRF_E_INVALID_ARG, "NULL output pointer");
+  auto it = b->entries.find(id);
+  if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
+  const SolveJob& J = *it->second.J;
+  if (!J.done) return fail(b->env, SLRF_E_INVALID_ARG, "pencil not finished");
+  slrf_status st = copy_results(b->env, J, n_found, h_evals, d_evecs, h_resid, stats);
+  if (st != SLRF_OK) return st;
+  if (J.status != SLRF_OK) return fail(b->env, J.status, J.msg);
+  return SLRF_OK;
+}
+
+slrf_status slrf_batch_remove(slrf_batch b, int32_t id) {
+  if (!b) return SLRF_E_INVALID_ARG;
+  auto it = b->entries.find(id);
+  if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
+  const Pencil& P = *it->second.P;
+  const SolveJob& J = *it->second.J;
+  b->pool.release(P.mem, P.mem_bytes);
+  b->pool.release(J.mem, outer_bytes(P.n, J.L));
+  b->entries.erase(it);
+  return SLRF_OK;
+}
+
+void slrf_batch_destroy(slrf_batch b) { delete b; }
+
+// ---- kernel-level test hooks ----------------------------------------------
 
 size_t slrf_test_gram_scratch(int64_t n, int64_t L) {
   return (size_t)gram_chunks((int)n, (int)L) * 2 * L * L * sizeof(double);

@@ -1,0 +1,216 @@
+"""GPU tests of the batch API: many pencils in one batched Krylov launch per step.
+
+* A pencil gives bitwise the same eigenpairs alone (slrf_solve_interval) and
+  inside a batch, when the Krylov grid is the same (every pencil here has
+  n >= 8192, which fills the 1024-workgroup grid): the per-column reductions do
+  not mix pencils and converged columns are frozen.
+* Small pencils of different kinds (ILU(0) and Jacobi preconditioned in the same
+  launch, different sizes, L and gamma) agree with the dense FP64 oracle.
+* Continuous batching: admission by footprint, pencils joining between steps and
+  leaving when done, results unchanged.
+* hipGraph replay of the iteration chunks gives bitwise the eager result.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+import pencils
+from closed_forms import closed_1d
+from oracle import dense, inertia
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def slrf(torch):
+    import paper_2503_21618_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gap_gamma(ev, k):
+    """gamma halfway between the k-th and (k+1)-th eigenvalue (1-based k)."""
+    return 0.5 * (ev[k - 1] + ev[k])
+
+
+def smallest_eigs(p, k):
+    vals = sla.eigsh(p.A.tocsc(), k=k, M=p.B.tocsc(), sigma=0.0, which="LM",
+                     return_eigenvectors=False)
+    return np.sort(vals)
+
+
+def big_cases():
+    """Three pencils with n >= 8192 (full Krylov grid), different kinds and sizes."""
+    out = []
+    for (m, dim, ln, seed, nev) in [(92, 2, 0.5, 11, 18), (22, 3, 0.5, 12, 24), (22, 3, 0.0, 0, 12)]:
+        p = pencils.scalar_q1(m, dim, ln, seed)
+        ev = smallest_eigs(p, nev + 8)
+        # a gamma in a relative gap of at least 1e-3 near nev
+        k = nev
+        while (ev[k] - ev[k - 1]) / ev[k] < 1e-3:
+            k += 1
+        L = int(np.ceil(1.25 * k / 8) * 8)
+        out.append((p, gap_gamma(ev, k), L, k))
+    return out
+
+
+def ws_for(slrf, cases, prec):
+    pers = trans = 0
+    for p, _, L, _ in cases:
+        nnz = int((abs(p.A) + abs(p.B)).nnz)
+        a, b = slrf.batch_footprint(p.n, nnz, L, 4, prec)
+        pers += a + 4096
+        trans += b
+    return pers + trans + (1 << 20), trans
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_bitwise_equals_alone(slrf, torch, prec):
+    cases = big_cases()
+    opt = slrf.default_options(precision=prec)
+    alone = []
+    for i, (p, gamma, L, k) in enumerate(cases):
+        say(f"case alone prec={prec} pencil {i} n={p.n} L={L} nev={k}")
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=4, options=opt)
+        r = s.solve_interval(gamma, L, V0=torch.from_numpy(pencils.start_block(p.n, L, 40 + i)).cuda())
+        assert r.status == 0 and r.n_found == k
+        alone.append(r)
+        s.close()
+    ws, arena = ws_for(slrf, cases, prec)
+    say(f"case batch prec={prec}: {len(cases)} pencils, workspace {ws / 2**20:.1f} MiB")
+    b = slrf.Batch(ws, arena, max_poles=4, options=opt)
+    ids = [b.add(p.A, p.B, gamma, L, V0=pencils.start_block(p.n, L, 40 + i))
+           for i, (p, gamma, L, _) in enumerate(cases)]
+    steps = 0
+    while b.step() > 0:
+        steps += 1
+        assert steps < 60
+    for i, pid in enumerate(ids):
+        r = b.result(pid)
+        a = alone[i]
+        say(f"  pencil {i}: found {r.n_found} outer {r.stats['outer_iterations']} "
+            f"(alone {a.stats['outer_iterations']})")
+        assert r.status == 0 and r.n_found == a.n_found
+        assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
+        assert np.array_equal(r.evals, a.evals)
+        assert np.array_equal(r.resid, a.resid)
+        assert torch.equal(r.evecs, a.evecs)
+    b.close()
+
+
+def small_cases():
+    """Pencils below the full grid: a 1D string (ILU(0)), a 2D and a 3D
+    log-normal pencil (Jacobi), different n, L and gamma."""
+    out = []
+    lam, _ = closed_1d(2000)
+    out.append((pencils.c1_string(), gap_gamma(lam, 12), 24, 12, lam))
+    for (m, dim, ln, seed, k, L) in [(30, 2, 0.5, 3, 15, 24), (12, 3, 0.5, 31, 30, 40)]:
+        p = pencils.scalar_q1(m, dim, ln, seed)
+        ev, _ = dense.all_eigenpairs(p.A, p.B)
+        out.append((p, gap_gamma(ev, k), L, k, ev))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_mixed_kinds_match_oracle(slrf, torch, prec):
+    cases = small_cases()
+    ws, arena = ws_for(slrf, [(p, g, L, k) for p, g, L, k, _ in cases], prec)
+    say(f"case batch small kinds prec={prec}")
+    b = slrf.Batch(ws, arena, max_poles=4, options=slrf.default_options(precision=prec))
+    ids = [b.add(p.A, p.B, gamma, L) for p, gamma, L, _, _ in cases]
+    while b.step() > 0:
+        pass
+    for pid, (p, gamma, L, k, ev) in zip(ids, cases):
+        r = b.result(pid)
+        nf = r.n_found
+        rel = np.abs(r.evals[:nf] / ev[:nf] - 1).max()
+        X = r.evecs.cpu().numpy()[:, :nf]
+        orth = np.abs(X.T @ (p.B @ X) - np.eye(nf)).max()
+        say(f"  n={p.n}: found {nf} of {k}, rel eig err {rel:.2e}, max rho {r.resid[:nf].max():.2e}, "
+            f"orth {orth:.1e}")
+        assert r.status == 0 and nf == k == inertia.sparse_ldl_count(p.A, p.B, gamma)
+        assert rel < 1e-10
+        assert r.resid[:nf].max() <= 1e-8
+        assert orth < 1e-10
+    b.close()
+
+
+def test_batch_continuous_admission(slrf, torch):
+    """Arena for two pencils: the third is refused until one finishes; results
+    are those of the pencils solved alone in a batch of their own."""
+    cases = small_cases()
+    prec = 0
+    nnz = [int((abs(p.A) + abs(p.B)).nnz) for p, *_ in cases]
+    fp = [slrf.batch_footprint(p.n, z, L, 4, prec) for (p, _, L, _, _), z in zip(cases, nnz)]
+    # order: the largest transient first so that the others fit once it leaves
+    order = sorted(range(3), key=lambda i: -fp[i][1])
+    arena = fp[order[0]][1] + fp[order[1]][1]
+    assert fp[order[2]][1] <= fp[order[0]][1]
+    ws = sum(a for a, _ in fp) + 3 * 4096 + arena + (1 << 20)
+    say("case continuous admission")
+    b = slrf.Batch(ws, arena, max_poles=4, options=slrf.default_options(precision=prec))
+    ids = {}
+    for i in order[:2]:
+        p, g, L, _, _ = cases[i]
+        ids[i] = b.add(p.A, p.B, g, L)
+    p, g, L, _, _ = cases[order[2]]
+    assert b.add(p.A, p.B, g, L, must_fit=False) is None
+    pending = order[2]
+    finished = {}
+    for _ in range(80):
+        act = b.step()
+        for i, pid in list(ids.items()):
+            done, _ = b.query(pid)
+            if done and i not in finished:
+                finished[i] = b.result(pid)
+                b.remove(pid)
+                del ids[i]
+        if pending is not None:
+            p, g, L, _, _ = cases[pending]
+            pid = b.add(p.A, p.B, g, L, must_fit=False)
+            if pid is not None:
+                ids[pending] = pid
+                pending = None
+        if act == 0 and not ids and pending is None:
+            break
+    assert len(finished) == 3
+    for i, (p, gamma, L, k, ev) in enumerate(cases):
+        r = finished[i]
+        nf = r.n_found
+        say(f"  pencil {i} n={p.n}: found {nf}, outer {r.stats['outer_iterations']}")
+        assert r.status == 0 and nf == k
+        assert np.abs(r.evals[:nf] / ev[:nf] - 1).max() < 1e-10
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_bitwise_equals_eager(slrf, torch, prec):
+    cases = small_cases()
+    ws, arena = ws_for(slrf, [(p, g, L, k) for p, g, L, k, _ in cases], prec)
+    results = []
+    for graph in (0, 1):
+        stream = torch.cuda.Stream()
+        say(f"case graph={graph} prec={prec}")
+        b = slrf.Batch(ws, arena, max_poles=4,
+                       options=slrf.default_options(precision=prec, graph=graph), stream=stream)
+        ids = [b.add(p.A, p.B, g, L) for p, g, L, _, _ in cases]
+        while b.step() > 0:
+            pass
+        results.append([b.result(pid) for pid in ids])
+        torch.cuda.synchronize()
+        b.close()
+    for e, g in zip(*results):
+        assert e.status == 0 and g.status == 0
+        assert np.array_equal(e.evals, g.evals)
+        assert torch.equal(e.evecs, g.evecs)
