@@ -81,6 +81,12 @@ typedef struct {
   int32_t graph;       /* 1: capture check_every BiCGStab iterations (and the poll of the
                           active count) once per Krylov run as a hipGraph and replay it;
                           needs a non-NULL stream and profile = 0, else ignored.  0: off */
+  /* Work decomposition of the Krylov kernels (0 = default).  They change the
+   * order of floating-point sums, not the method. */
+  int32_t tile_rows;   /* rows per row block (default 8, 1..64) */
+  int32_t tile_wgs;    /* workgroups per XCD (default 128, 1..256; grid = 8 * this) */
+  int32_t band_rows;   /* rows per sub-band of the sparse-product row order (default
+                          1024; -1 = natural row order); applied when a pencil is built */
 } slrf_options;
 
 typedef struct {
@@ -117,7 +123,8 @@ typedef struct {
 } slrf_solve_stats;
 
 /* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
- * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0. */
+ * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0,
+ * tile_rows / tile_wgs / band_rows 0 (defaults). */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance

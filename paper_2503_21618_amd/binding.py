@@ -29,7 +29,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("tile_rows", C.c_int32), ("tile_wgs", C.c_int32),
+                ("band_rows", C.c_int32)]
 
 
 class Poles(C.Structure):

@@ -26,7 +26,8 @@ enum ColFlag : int {
   COL_HALF_PENDING = 5,  // converged at the half step; x still takes alpha * p_hat
 };
 
-constexpr int kMaxGrid = 1024;  // workgroups of the Krylov kernels (a multiple of 8)
+constexpr int kMaxGrid = 2048;  // largest grid of the Krylov kernels (a multiple of 8)
+constexpr int kCsrPad = 16;     // zero entries after the last CSR entry (whole-chunk reads)
 
 // One pencil of a batch as the Krylov kernels see it.  Its Krylov block is a
 // row-major (n, K) complex array, K = N * L, column c = j * L + l belonging to

@@ -78,15 +78,16 @@ __device__ __forceinline__ void wg_store_partial_cx(cx<R> v, int w, int lane, bo
 
 // Complex-shifted sparse product of one row over the merged CSR:
 //   q = sum_j (a_ij - sigma b_ij) P[j]      (A - sigma B is never formed)
-// The row's entries are taken in chunks of CH: CH (col, a, b) entries are read
-// (wave-uniform, scalar loads), then CH gathers are issued back to back with no
-// branches, then the FMAs.  Entries past the row end repeat the last valid
-// column with zero coefficients, and lanes past K read a clamped column (both
-// stay in bounds; their contributions are discarded).
+// The row's entries are taken in chunks of CH.  A chunk's CH column indices and
+// (a, b) pairs are contiguous, wave-uniform reads (wide scalar loads; the CSR
+// arrays carry kCsrPad zero entries at the end so a chunk never leaves them),
+// then CH gathers are issued back to back, then the FMAs.  Entries past the row
+// end get zero coefficients and re-read the row's own column; lanes past K read
+// a clamped column (both stay in bounds; their contributions are discarded).
 template <typename R, int CH>
-__device__ __forceinline__ cx<R> shifted_row(int i, const int* __restrict__ rowptr, const int* __restrict__ col,
-                                             const ab_pair<R>* __restrict__ ab, const cx<R>* __restrict__ Pc,
-                                             int K, cx<R> sig) {
+__device__ __forceinline__ cx<R> shifted_row(int i, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
+                                             const cx<R>* __restrict__ Pc, int K, cx<R> sig) {
+  static_assert(CH <= kCsrPad, "chunk longer than the CSR padding");
   const int k0 = rowptr[i], k1 = rowptr[i + 1];
   R apr = 0, api = 0, bpr = 0, bpi = 0;
   for (int kb = k0; kb < k1; kb += CH) {
@@ -94,10 +95,15 @@ __device__ __forceinline__ cx<R> shifted_row(int i, const int* __restrict__ rowp
     ab_pair<R> m[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int k = min(kb + u, k1 - 1);
-      jj[u] = col[k];
-      m[u] = ab[k];
-      if (kb + u >= k1) m[u] = ab_pair<R>{0, 0};
+      jj[u] = col[kb + u];
+      m[u] = ldc(ab + kb + u);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (kb + u >= k1) {
+        jj[u] = i;
+        m[u] = ab_pair<R>{0, 0};
+      }
     }
     cx<R> x[CH];
 #pragma unroll
@@ -120,7 +126,7 @@ constexpr int kChunk = 16;
 // global column.
 #define FOR_TILES(b, p)                                   \
   for (int tg = 0; tg < (b).n_tiles; ++tg) {              \
-    const Inst I = (b).inst[(b).tile_inst[tg]];           \
+    const Inst I = ldc(as_const((b).inst) + as_const((b).tile_inst)[tg]); \
     const int cl = (tg - I.tile0) * WAVE + (p).lane;      \
     const bool valid = cl < I.K;                          \
     const int cc = min(cl, I.K - 1);                      \
@@ -150,9 +156,10 @@ __global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* 
       const int l = cc % I.L;
       const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
       FOR_ROWS(b, p, I)
-        const int i = I.sched ? I.sched[pos] : pos;
+        const int i = I.sched ? as_const(I.sched)[pos] : pos;
         const size_t e = I.blk + (size_t)i * I.K + cc;
-        const cx<R> q = shifted_row<R, kChunk>(i, I.rowptr, I.col, ab, st.ph + I.blk + cc, I.K, sig);
+        const cx<R> q = shifted_row<R, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
+                                               st.ph + I.blk + cc, I.K, sig);
         if (valid) {
           st.v[e] = q;
           if (st.rhat_cx) {  // conj(rhat) * v
@@ -183,8 +190,9 @@ __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* 
       const int pole = cc / I.L;
       const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
       FOR_ROWS(b, p, I)
-        const int i = I.sched ? I.sched[pos] : pos;
-        const cx<R> tv = shifted_row<R, kChunk>(i, I.rowptr, I.col, ab, st.sh + I.blk + cc, I.K, sig);
+        const int i = I.sched ? as_const(I.sched)[pos] : pos;
+        const cx<R> tv = shifted_row<R, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
+                                                st.sh + I.blk + cc, I.K, sig);
         if (valid) {
           const size_t e = I.blk + (size_t)i * I.K + cc;
           st.t[e] = tv;
@@ -373,7 +381,7 @@ template <typename R>
 __device__ __forceinline__ bool cfinite(cx<R> z) { return isfinite(z.re) && isfinite(z.im); }
 
 #define SC_PROLOGUE                                         \
-  const Inst I = b.inst[b.tile_inst[blockIdx.x]];           \
+  const Inst I = ldc(as_const(b.inst) + as_const(b.tile_inst)[blockIdx.x]); \
   const int cl = (blockIdx.x - I.tile0) * WAVE + lane_id(); \
   const bool valid = cl < I.K;                              \
   const int c = I.col0 + min(cl, I.K - 1);                  \
@@ -589,11 +597,12 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
     const cx<double> sig = sigma_col[cg];
     double nn = 0;
     FOR_ROWS(b, p, I)
-      const int i = I.sched ? I.sched[pos] : pos;
+      const int i = I.sched ? as_const(I.sched)[pos] : pos;
       const double f = F[I.rl + (size_t)i * I.L + l];
       cx<double> r = {f, 0.0};
       if (Y) {
-        const cx<double> q = shifted_row<double, kChunk>(i, I.rowptr, I.col, I.ab64, Y + I.blk + cc, I.K, sig);
+        const cx<double> q = shifted_row<double, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(I.ab64),
+                                                         Y + I.blk + cc, I.K, sig);
         r = {f - q.re, -q.im};
         if (valid) Rout[I.blk + (size_t)i * I.K + cc] = r;
       }

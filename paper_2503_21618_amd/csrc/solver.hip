@@ -35,9 +35,9 @@ using namespace slrf;
 
 namespace {
 
-constexpr int kRowsPerBlock = 8;
-constexpr int kWgPerXcd = 128;      // Krylov grid: at most 8 * 128 = kMaxGrid workgroups
-constexpr int kSubBand = 1024;      // rows per sub-band of the sparse-product row order
+constexpr int kRowsPerBlock = 8;    // default rows per row block
+constexpr int kWgPerXcd = 128;      // default workgroups per XCD (grid 8 * 128)
+constexpr int kSubBand = 1024;      // default rows per sub-band of the sparse-product row order
 constexpr int kTimerSlots = 512;
 constexpr double kInnerTol32 = 1e-6;  // relative tolerance of each FP32 correction solve
 constexpr int kMaxRounds = 6;         // defect-correction rounds per filter application
@@ -134,23 +134,26 @@ struct Pencil {
 };
 
 size_t pencil_bytes(int64_t n, int64_t nnz) {
-  return al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + al((size_t)nnz * 16) + al((size_t)nnz * 8) +
-         2 * al((size_t)n * 8) + 2 * al((size_t)n * 4) + 2 * al((size_t)n * 4);
+  const size_t np = (size_t)nnz + kCsrPad;
+  return al((size_t)(n + 1) * 4) + al(np * 4) + al(np * 16) + al(np * 8) + 2 * al((size_t)n * 8) +
+         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4);
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
 // neighbours of row i lie in [i - H, i + H].  Rows are cut into chunks of H and
-// each chunk into S sub-bands of about kSubBand rows; the order visits sub-band
+// each chunk into S sub-bands of about `band` rows; the order visits sub-band
 // s of chunk 0, 1, 2, ... before sub-band s + 1, so consecutive rows in the
 // order have overlapping neighbourhoods (for a lexicographic 3D grid: a narrow
 // (x, y) band marching along z).  Returns false (natural order) when H is small.
-bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
+bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl, int band_rows,
                    std::vector<int32_t>& order) {
+  if (band_rows < 0) return false;
+  const int64_t target = band_rows > 0 ? band_rows : kSubBand;
   int64_t H = 0;
   for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] > rp[i]) H = std::max<int64_t>(H, (int64_t)cl[rp[i + 1] - 1] - i);
-  if (H <= 2 * kSubBand || H >= n) return false;
-  const int64_t S = (H + kSubBand - 1) / kSubBand, band = (H + S - 1) / S, nchunk = (n + H - 1) / H;
+  if (H <= 2 * target || H >= n) return false;
+  const int64_t S = (H + target - 1) / target, band = (H + S - 1) / S, nchunk = (n + H - 1) / H;
   order.clear();
   order.reserve(n);
   for (int64_t sb = 0; sb < S; ++sb)
@@ -166,7 +169,8 @@ bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<
 // bytes).  With mem == nullptr it only validates and reports nnz of the union.
 slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
                          const int32_t* b_rowptr, const int32_t* b_col, const double* b_val, int precond,
-                         hipStream_t s, Pencil& P, std::string& err, char* mem, int64_t* nnz_out) {
+                         int band_rows, hipStream_t s, Pencil& P, std::string& err, char* mem,
+                         int64_t* nnz_out) {
   if (n < 1 || n > INT32_MAX || !a_rowptr || !a_col || !a_val || !b_rowptr || !b_col || !b_val) {
     err = "bad size or NULL argument";
     return SLRF_E_INVALID_ARG;
@@ -233,9 +237,9 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.mem_bytes = pencil_bytes(n, nnz);
   Carver cv{mem, 0, P.mem_bytes};
   P.rowptr = cv.take<int>(n + 1);
-  P.col = cv.take<int>(nnz);
-  P.ab64 = cv.take<ab_pair<double>>(nnz);
-  P.ab32 = cv.take<ab_pair<float>>(nnz);
+  P.col = cv.take<int>(nnz + kCsrPad);
+  P.ab64 = cv.take<ab_pair<double>>(nnz + kCsrPad);
+  P.ab32 = cv.take<ab_pair<float>>(nnz + kCsrPad);
   P.diagA = cv.take<double>(n);
   P.diagB = cv.take<double>(n);
   P.diagA32 = cv.take<float>(n);
@@ -243,16 +247,20 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.diagpos = cv.take<int>(n);
   int* sched_dev = cv.take<int>(n);
   std::vector<int32_t> order;
-  P.sched = band_schedule(n, rp, cl, order) ? sched_dev : nullptr;
-  std::vector<float> ab32(2 * (size_t)nnz), dA32(n), dB32(n);
-  for (size_t k = 0; k < 2 * (size_t)nnz; ++k) ab32[k] = (float)ab[k];
+  P.sched = band_schedule(n, rp, cl, band_rows, order) ? sched_dev : nullptr;
+  // kCsrPad zero entries (column 0, coefficients 0) after the last entry
+  cl.resize(nnz + kCsrPad, 0);
+  ab.resize(2 * (size_t)(nnz + kCsrPad), 0.0);
+  std::vector<float> ab32(2 * (size_t)(nnz + kCsrPad)), dA32(n), dB32(n);
+  for (size_t k = 0; k < ab32.size(); ++k) ab32[k] = (float)ab[k];
   for (int64_t i = 0; i < n; ++i) {
     dA32[i] = (float)dA[i];
     dB32[i] = (float)dB[i];
   }
   auto cp = [&](void* dst, const void* src, size_t b) { return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s); };
-  if (cp(P.rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(P.col, cl.data(), 4 * nnz) != hipSuccess ||
-      cp(P.ab64, ab.data(), 16 * nnz) != hipSuccess || cp(P.ab32, ab32.data(), 8 * nnz) != hipSuccess ||
+  const size_t np = (size_t)nnz + kCsrPad;
+  if (cp(P.rowptr, rp.data(), 4 * (n + 1)) != hipSuccess || cp(P.col, cl.data(), 4 * np) != hipSuccess ||
+      cp(P.ab64, ab.data(), 16 * np) != hipSuccess || cp(P.ab32, ab32.data(), 8 * np) != hipSuccess ||
       cp(P.diagA, dA.data(), 8 * n) != hipSuccess || cp(P.diagB, dB.data(), 8 * n) != hipSuccess ||
       cp(P.diagA32, dA32.data(), 4 * n) != hipSuccess || cp(P.diagB32, dB32.data(), 4 * n) != hipSuccess ||
       cp(P.diagpos, dpos.data(), 4 * n) != hipSuccess ||
@@ -383,6 +391,9 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   if (env.opt.precond < 0 || env.opt.precond > 2) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
   if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
     return fail(env, SLRF_E_INVALID_ARG, "tolerances must be non-negative");
+  if (env.opt.tile_rows < 0 || env.opt.tile_rows > 64 || env.opt.tile_wgs < 0 ||
+      env.opt.tile_wgs * 8 > kMaxGrid || env.opt.band_rows < -1)
+    return fail(env, SLRF_E_INVALID_ARG, "tile_rows must be in [0, 64], tile_wgs in [0, 256], band_rows >= -1");
   return SLRF_OK;
 }
 
@@ -588,14 +599,16 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all;
   std::vector<double> sigc64, w;
+  const int rpb = env.opt.tile_rows > 0 ? env.opt.tile_rows : kRowsPerBlock;
+  const int wgs = env.opt.tile_wgs > 0 ? env.opt.tile_wgs : kWgPerXcd;
   int max_slab = 1;
   for (const auto& j : jobs) {
-    const int nrb = (int)((j.P->n + kRowsPerBlock - 1) / kRowsPerBlock);
+    const int nrb = (int)((j.P->n + rpb - 1) / rpb);
     max_slab = std::max(max_slab, (nrb + 7) / 8);
   }
-  const int per = std::max(1, std::min(kWgPerXcd, max_slab));
+  const int per = std::max(1, std::min(wgs, max_slab));
   b.G = 8 * per;
-  b.rows_per_block = kRowsPerBlock;
+  b.rows_per_block = rpb;
   int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
@@ -605,7 +618,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.L = j.L;
     I.N = j.N;
     I.K = j.N * j.L;
-    I.nrb = (I.n + kRowsPerBlock - 1) / kRowsPerBlock;
+    I.nrb = (I.n + rpb - 1) / rpb;
     I.slab = (I.nrb + 7) / 8;
     I.steps = (I.slab + per - 1) / per;
     I.col0 = col0;
@@ -1201,6 +1214,9 @@ void slrf_default_options(slrf_options* o) {
   o->precond = 0;
   o->profile = 0;
   o->graph = 0;
+  o->tile_rows = 0;
+  o->tile_wgs = 0;
+  o->band_rows = 0;
 }
 
 const char* slrf_status_string(slrf_status s) {
@@ -1263,7 +1279,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (st != SLRF_OK) return st;
   if (max_L < 1 || max_N < 1) return fail(env, SLRF_E_INVALID_ARG, "bad size or NULL argument");
   int64_t nnz = 0;
-  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, ctx->P, env.err,
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.opt.band_rows, env.stream, ctx->P, env.err,
                     nullptr, &nnz);
   if (st != SLRF_OK) return st;
   if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0)
@@ -1276,7 +1292,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
                 "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(need));
   ctx->max_L = max_L;
   ctx->max_N = max_N;
-  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, ctx->P, env.err,
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.opt.band_rows, env.stream, ctx->P, env.err,
                     (char*)d_workspace, nullptr);
   if (st != SLRF_OK) return st;
   const size_t poff = pencil_bytes(n, nnz);
@@ -1386,7 +1402,7 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
   if (N < 1 || N > b->max_N) return fail(env, SLRF_E_INVALID_ARG, "pole count outside [1, max_poles]");
   int64_t nnz = 0;
   auto P = std::make_unique<Pencil>();
-  slrf_status st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, *P,
+  slrf_status st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.opt.band_rows, env.stream, *P,
                                 env.err, nullptr, &nnz);
   if (st != SLRF_OK) return st;
   std::vector<JobShape> shapes = b->active_shapes();
@@ -1402,7 +1418,7 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
     return fail(env, SLRF_E_WORKSPACE, "no room for the subspace blocks in the workspace");
   }
   auto J = std::make_unique<SolveJob>();
-  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.stream, *P, env.err, pm,
+  st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.opt.band_rows, env.stream, *P, env.err, pm,
                     nullptr);
   if (st == SLRF_OK) {
     J->P = P.get();
