@@ -1,7 +1,8 @@
 """Benchmark: eigenpairs/s of the SLRF interval eigensolver on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1]
-                    [--precision both|mixed|fp64] [--no-cpu-baseline] [--calibrate-copy]
+                    [--precision both|mixed|fp64] [--no-cpu-baseline]
+    python bench.py --counters-probe | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
 
 A step is one complete slrf_solve_interval (filter application with the shifted
 BiCGStab solves over all poles and columns, filter sum, B-orthonormalising
@@ -21,10 +22,23 @@ Prints one JSON line.  `roofline` is measured live: HIP events around every
 launch of the dominant kernel (the complex-shifted sparse product) during the
 timed steps, against its algorithmic bytes (each processed column tile reads its
 input block and writes its output block once, the merged CSR once per launch).
-`cpu_baseline` times the FP64 oracle's BiCGStab on a bounded sample of the same
-workload on the host and scales it to the whole solve.
+`roofline.traffic` is the HBM bytes per launch from the rocprofv3 FETCH_SIZE and
+WRITE_SIZE passes summarised in profiles/spmm_c2_pmc.txt (each scaled by what
+the counter reads for a copy kernel of known size), scaled to the launches of
+the timed steps; it is null when the kernel sources differ from the ones the
+counters were taken with.  `cpu_baseline` times the FP64 oracle's BiCGStab on a
+bounded sample of the same workload on the host and scales it to the whole
+solve.
+
+Counter collection (the probe runs full-width launches of the sparse product):
+    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_spmm|elementwise" \
+        --output-format csv -d <dir> -o run -- python3 bench.py --counters-probe
+    (again with WRITE_SIZE)
+    python bench.py --summarize-pmc <fetch csv> <write csv>  > profiles/spmm_c2_pmc.txt
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +49,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "eigenpairs/s at rel. residual 1e-8, mixed vs FP64; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_c2_pmc.txt")
+KERNEL_SOURCES = ["krylov.hip", "device_util.h", "kernels.h"]
+COPY_BYTES = 1 << 30      # the calibration copy reads and writes 1 GiB
 
 
 def log(*a):
@@ -71,7 +88,7 @@ def cpu_baseline(wl, sig, solve_stats):
     import pencils
     from oracle import krylov
     p = wl["pencil"]
-    cols, iters = 4, 20 if p.n > 100000 else 200
+    cols, iters = 4, 100 if p.n > 100000 else 200
     F = p.B @ pencils.start_block(p.n, cols, 77)
     with threadpool_limits(1):
         t0 = time.perf_counter()
@@ -86,6 +103,137 @@ def cpu_baseline(wl, sig, solve_stats):
                        f"{iters} iterations took {dt:.1f} s on 1 host thread; scaled to the "
                        f"{col_its:.0f} column-iterations of one GPU solve (Rayleigh-Ritz excluded)"),
             "seconds_per_column_iteration": per_col_it}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_21618_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_pmc_summary():
+    """key: value lines of the committed counter summary, or None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    d = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    return d
+
+
+def hbm_traffic(dtype, avg_alg_bytes):
+    """HBM bytes per launch of the sparse product from the counter summary, scaled
+    from the probe's full-width launches to launches that average avg_alg_bytes
+    algorithmic bytes (converged tiles are skipped); None if the summary is
+    missing or the kernel sources changed since it was taken."""
+    d = read_pmc_summary()
+    if not d or d.get("source_sha256") != kernel_source_hash():
+        return None, "no counter summary for the current kernel sources"
+    full_traffic = float(d[f"full_launch_traffic_bytes {dtype}"])
+    full_alg = float(d[f"full_launch_algorithmic_bytes {dtype}"])
+    return full_traffic * avg_alg_bytes / full_alg, (
+        f"{PMC_SUMMARY.split(os.sep)[-2]}/{os.path.basename(PMC_SUMMARY)}: FETCH_SIZE + WRITE_SIZE per "
+        f"full-width launch {full_traffic / 1e9:.3f} GB vs algorithmic {full_alg / 1e9:.3f} GB, "
+        "scaled by the timed launches' mean algorithmic bytes")
+
+
+def counters_probe():
+    """Short run for the rocprofv3 counter passes: a 1 GiB copy kernel (reads and
+    writes COPY_BYTES) and full-width launches of the sparse product on the 64^3
+    scalar pencil (fixed BiCGStab iterations, no column converges)."""
+    import torch
+
+    import paper_2503_21618_amd as slrf
+    import pencils
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    log("copy kernel done")
+    wl = workload("c2")
+    p = wl["pencil"]
+    sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
+    X = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
+    for prec, dtype in ((slrf.MIXED, "float"), (slrf.FP64, "double")):
+        opt = slrf.default_options(profile=1, precision=prec, inner_tol=0.0, inner_maxit=3, check_every=3)
+        s = slrf.Solver(p.A, p.B, max_L=wl["L"], max_poles=wl["N"], options=opt)
+        U, st = s.filter_apply(X, sig, w)
+        torch.cuda.synchronize()
+        print(json.dumps({"dtype": dtype, "spmm_launches": st["spmm_launches"],
+                          "full_launch_algorithmic_bytes": st["spmm_bytes"] / st["spmm_launches"]}),
+              flush=True)
+        s.close()
+        del s, U
+        torch.cuda.empty_cache()
+
+
+def summarize_pmc(fetch_csv, write_csv, probe_log):
+    """Prints the counter summary (key: value lines) from the two rocprofv3 CSVs
+    and the probe's own output (algorithmic bytes per full launch)."""
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = ("copy" if "elementwise" in name and "neg" in name else
+                       "k_spmm_v<float>" if "k_spmm_v<float>" in name else
+                       "k_spmm_t<float>" if "k_spmm_t<float>" in name else
+                       "k_spmm_v<double>" if "k_spmm_v<double>" in name else
+                       "k_spmm_t<double>" if "k_spmm_t<double>" in name else None)
+                if key:
+                    acc.setdefault(key, []).append(float(row["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    fe = per_kernel(fetch_csv, "FETCH_SIZE")
+    wr = per_kernel(write_csv, "WRITE_SIZE")
+    alg = {}
+    with open(probe_log) as f:
+        for line in f:
+            if line.startswith("{"):
+                d = json.loads(line)
+                alg[d["dtype"]] = d["full_launch_algorithmic_bytes"]
+    kib = COPY_BYTES / 1024.0
+    ff = fe["copy"][0] / kib
+    fw = wr["copy"][0] / kib
+    print("# HBM traffic of the complex-shifted sparse product (k_spmm_v, k_spmm_t), 3D scalar")
+    print("# vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768), full-width launches.")
+    print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
+    print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|elementwise\" --output-format csv "
+          "-d R/gpurun_out/pmc_fetch -o run -- python3 R/bench.py --counters-probe")
+    print("#   rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_spmm|elementwise\" --output-format csv "
+          "-d R/gpurun_out/pmc_write -o run -- python3 R/bench.py --counters-probe")
+    print("#   python3 bench.py --summarize-pmc R/gpurun_out/pmc_fetch/run_counter_collection.csv "
+          "R/gpurun_out/pmc_write/run_counter_collection.csv <probe stdout>")
+    print("# Counter values are KiB per dispatch; each is divided by the value the same counter")
+    print("# reads for a copy kernel that reads and writes 1 GiB (torch.neg on 2^27 doubles).")
+    print(f"source_sha256: {kernel_source_hash()}")
+    print(f"copy FETCH_SIZE KiB: {fe['copy'][0]:.0f}")
+    print(f"copy WRITE_SIZE KiB: {wr['copy'][0]:.0f}")
+    print(f"copy_fetch_factor: {ff:.4f}")
+    print(f"copy_write_factor: {fw:.4f}")
+    for dtype in ("float", "double"):
+        tot = 0.0
+        for kern in (f"k_spmm_v<{dtype}>", f"k_spmm_t<{dtype}>"):
+            fk, nf = fe[kern]
+            wk, nw = wr[kern]
+            fb, wb = fk * 1024 / ff, wk * 1024 / fw
+            tot += fb + wb
+            print(f"{kern} dispatches: {nf}")
+            print(f"{kern} FETCH_SIZE KiB: {fk:.0f}")
+            print(f"{kern} WRITE_SIZE KiB: {wk:.0f}")
+            print(f"{kern} fetch bytes (calibrated): {fb:.4e}")
+            print(f"{kern} write bytes (calibrated): {wb:.4e}")
+        print(f"full_launch_traffic_bytes {dtype}: {tot / 2:.6e}")
+        print(f"full_launch_algorithmic_bytes {dtype}: {alg[dtype]:.6e}")
+        print(f"traffic_over_algorithmic {dtype}: {tot / 2 / alg[dtype]:.3f}")
 
 
 def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
@@ -133,25 +281,28 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run a 1 GiB elementwise copy first (reference for HBM byte counters)")
+    ap.add_argument("--counters-probe", action="store_true",
+                    help="short run for the rocprofv3 counter passes (see the module docstring)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
+                    help="print the counter summary from two rocprofv3 CSVs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the pole-sharded "
               "multi-GPU form is not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.counters_probe:
+        counters_probe()
+        return
 
     import torch
 
     import paper_2503_21618_amd as slrf
     import pencils
 
-    if args.calibrate_copy:
-        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        torch.neg(a, out=b)          # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del a, b
     wl = workload(args.workload)
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
@@ -169,6 +320,8 @@ def main():
     upd_gbs = ks["update_bytes"] / ks["update_seconds"] / 1e9
     prec = "complex FP32 inner solves + FP64 defect correction and Rayleigh-Ritz" if main_form == "mixed" \
         else "complex FP64 inner solves"
+    kdtype = "float" if main_form == "mixed" else "double"
+    traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]))
     out = {
         "metric": METRIC, "value": m["value"], "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * m["dt"] / args.steps,
@@ -176,11 +329,12 @@ def main():
         "dtype": "f32+f64" if main_form == "mixed" else "f64",
         "data": "synthetic", "config": {"workload": wl["desc"] + "; " + prec},
         "roofline": {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_spmm_v / k_spmm_t <{'float' if main_form == 'mixed' else 'double'}> "
-                               "(complex-shifted sparse product)",
+                     "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_spmm_v / k_spmm_t <{kdtype}> (complex-shifted sparse product)",
                      "launches": ks["spmm_launches"],
-                     "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"])},
+                     "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
+                     "algorithmic_bytes_per_launch": ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
+                     "traffic_note": traffic_note},
         "vector_updates": {"achieved_GBs": upd_gbs, "frac": upd_gbs / HBM_PEAK_GBS,
                            "avg_launch_ms": 1e3 * ks["update_seconds"] / max(1, ks["update_launches"])},
         "solve": {k: m["results"][-1].stats[k] for k in ("outer_iterations", "spmv_total", "n_found",
