@@ -1,6 +1,6 @@
 """Benchmark: eigenpairs/s of the SLRF interval eigensolver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|batched|served]
                     [--precision both|mixed|fp64] [--no-cpu-baseline]
     python bench.py --counters-probe | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
 
@@ -15,7 +15,7 @@ log-normal coefficient (sigma 0.5, seed 2), consistent mass; gamma = 421
 (87 eigenvalues below it, Sylvester count from the oracle); L = 128, N = 6 SLRF
 poles (alpha 1, beta 0.01).  `value` is the mixed-precision form (complex FP32
 BiCGStab with FP64 defect correction, FP64 Rayleigh-Ritz and residuals); the
-plain FP64 form (complex FP64 BiCGStab, point Jacobi, inner tolerance 1e-10) is
+plain FP64 form (complex FP64 BiCGStab, point Jacobi, inner tolerance 1e-13) is
 timed in the same run and reported under "fp64" for the comparison.
 
 Prints one JSON line.  `roofline` is measured live: HIP events around every
@@ -236,6 +236,184 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
         print(f"traffic_over_algorithmic {dtype}: {tot / 2 / alg[dtype]:.3f}")
 
 
+def union_nnz(p):
+    return int((abs(p.A) + abs(p.B)).nnz)
+
+
+def batch_kernel_stats(results):
+    """Batch-wide kernel statistics: every pencil's stats hold the batch launches of
+    the steps it took part in, so the pencil that ran longest holds them all."""
+    last = max(results, key=lambda r: r.stats["outer_iterations"])
+    return last.stats["kernels"]
+
+
+def serial_fp64(slrf, items):
+    """Plain FP64 solves one pencil at a time (create and pole design excluded)."""
+    import torch
+    found, secs = 0, 0.0
+    for p, gamma, L in items:
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=slrf.default_options())
+        sig, w, _ = slrf.design_poles(6, 1.0, 0.01, gamma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve_interval(gamma, L, sig, w, raise_on_error=False)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        found += r.n_found
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return found, secs
+
+
+def run_batched(slrf, args):
+    """64 independent 2D/3D scalar pencils (pencils.batch_instance) solved together:
+    mixed precision, N = 6, autotuned tiles; one batched launch per Krylov step."""
+    import torch
+
+    import pencils
+    t0 = time.perf_counter()
+    insts = [pencils.batch_instance(i) for i in range(args.instances)]
+    log(f"built {len(insts)} pencils in {time.perf_counter() - t0:.1f} s, "
+        f"sum n = {sum(p.n for p, *_ in insts)}")
+    N = 6
+    pers = trans = 0
+    for p, g, L, _ in insts:
+        a, b = slrf.batch_footprint(p.n, union_nnz(p), L, N, slrf.MIXED)
+        pers += a + 4096
+        trans += b
+    ws = pers + trans + (1 << 24)
+    log(f"workspace {ws / 2**30:.1f} GiB (filter arena {trans / 2**30:.1f} GiB)")
+    opt = slrf.default_options(precision=slrf.MIXED, profile=1, tune=1)
+    b = slrf.Batch(ws, trans, max_poles=N, options=opt)
+    ids = []
+    for p, g, L, _ in insts:
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
+        ids.append(b.add(p.A, p.B, g, L, sig, w))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        act = b.step()
+        steps += 1
+        log(f"batched step {steps}: {act} unfinished, {time.perf_counter() - t0:.1f} s")
+        if act == 0:
+            break
+    res = [b.result(pid) for pid in ids]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    bad = [i for i, r in enumerate(res) if r.status != 0]
+    found = sum(r.n_found for r in res)
+    ks = batch_kernel_stats(res)
+    out = {"value": found / dt, "seconds": dt, "found": found, "steps": steps,
+           "statuses_not_ok": bad, "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
+    if not args.no_serial:
+        log("serial FP64 solves...")
+        f2, s2 = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in insts])
+        out["serial_fp64"] = {"value": f2 / s2, "seconds": s2, "found": f2}
+    return out, insts
+
+
+def run_served(slrf, args):
+    """Poisson stream of interval eigensolves (pencils.serve_request) through the
+    continuous-batching server; the rate is 0.7 x the throughput measured on a
+    closed calibration batch of the first requests."""
+    import torch
+
+    import paper_2503_21618_amd.serve as serve
+    import pencils
+    R = args.requests
+    reqs = [pencils.serve_request(r, n_range=(args.n_min, args.n_max), nev_range=(20, args.nev_max))
+            for r in range(R)]
+    log(f"{R} requests, sum n = {sum(p.n for p, *_ in reqs)}")
+    N = 6
+    opt = slrf.default_options(precision=slrf.MIXED, profile=1)
+    fps = [slrf.batch_footprint(p.n, union_nnz(p), L, N, slrf.MIXED) for p, g, L, _ in reqs]
+    arena = int(args.arena_gb * 2**30)
+    pool = int(args.pool_gb * 2**30)
+    if max(t for _, t in fps) > arena or max(a for a, _ in fps) > pool:
+        raise SystemExit("a request does not fit the arena or pool")
+
+    def make(i, arrival):
+        p, g, L, _ = reqs[i]
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
+        return serve.Request(i, p.A, p.B, g, L, sig, w, arrival=arrival)
+
+    # calibration: the first C requests at once
+    C = min(args.calibrate, R)
+    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt)
+    for i in range(C):
+        srv.submit(make(i, 0.0))
+    t0 = time.perf_counter()
+    while not srv.idle():
+        srv.pump()
+    mu = C / (time.perf_counter() - t0)
+    rate = 0.7 * mu
+    log(f"calibration: {C} requests in {C / mu:.1f} s -> rate {rate:.3f} requests/s")
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    arr = pencils.arrival_times(R, rate)
+    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt)
+    pending = [make(i, float(arr[i])) for i in range(R)]
+    t0 = time.perf_counter()
+    srv.clock = lambda: time.perf_counter() - t0
+    last_log = 0.0
+    while pending or not srv.idle():
+        now = srv.clock()
+        while pending and pending[0].arrival <= now:
+            srv.submit(pending.pop(0))
+        if srv.idle():
+            time.sleep(min(0.05, max(0.0, pending[0].arrival - now)))
+            continue
+        srv.pump()
+        if srv.clock() - last_log > 10:
+            last_log = srv.clock()
+            log(f"served {len(srv.done)}/{R}, active {len(srv.active)}, queued {len(srv.queue)}, "
+                f"t {last_log:.0f} s")
+    makespan = max(c.finished for c in srv.done) - float(arr[0])
+    res = [c.result for c in srv.done]
+    found = sum(r.n_found for r in res)
+    lat = serve.latency_stats(srv.done)
+    ks = batch_kernel_stats(res)
+    out = {"value": found / makespan, "seconds": makespan, "found": found, "latency_s": lat,
+           "rate_per_s": rate, "peak_active": srv.peak_active, "steps": srv.steps,
+           "statuses_not_ok": [c.rid for c in srv.done if c.result.status != 0],
+           "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    if not args.no_serial:
+        log("serial FP64 solves...")
+        f2, s2 = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in reqs])
+        out["serial_fp64"] = {"value": f2 / s2, "seconds": s2, "found": f2}
+    return out, reqs
+
+
+def many_line(args, kind, out, desc):
+    ks = out.pop("ks")
+    spmm_gbs = ks["spmm_bytes"] / ks["spmm_seconds"] / 1e9
+    traffic = None
+    line = {"metric": METRIC, "value": out["value"], "unit": "eigenpairs/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": desc},
+            "roofline": {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                         "kernel": "k_spmm_v / k_spmm_t <float> (complex-shifted sparse product)",
+                         "launches": ks["spmm_launches"],
+                         "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
+                         "traffic_note": "counters are taken on the 64^3 scalar workload only"},
+            "vector_updates": {"achieved_GBs": ks["update_bytes"] / ks["update_seconds"] / 1e9}}
+    line[kind] = out
+    if "serial_fp64" in out:
+        line["over_serial_fp64"] = out["value"] / out["serial_fp64"]["value"]
+    return line
+
+
 def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
     import torch
     p = wl["pencil"]
@@ -281,6 +459,15 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
+    ap.add_argument("--requests", type=int, default=24, help="served workload: number of requests")
+    ap.add_argument("--n-min", type=float, default=1e4, help="served workload: smallest pencil")
+    ap.add_argument("--n-max", type=float, default=1e5, help="served workload: largest pencil")
+    ap.add_argument("--nev-max", type=int, default=100, help="served workload: largest NEV")
+    ap.add_argument("--calibrate", type=int, default=6, help="served workload: calibration batch")
+    ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--pool-gb", type=float, default=32.0)
+    ap.add_argument("--no-serial", action="store_true", help="skip the serial FP64 comparison")
     ap.add_argument("--counters-probe", action="store_true",
                     help="short run for the rocprofv3 counter passes (see the module docstring)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
@@ -303,6 +490,22 @@ def main():
     import paper_2503_21618_amd as slrf
     import pencils
 
+    if args.workload == "batched":
+        out, insts = run_batched(slrf, args)
+        desc = (f"{len(insts)} independent 2D/3D scalar vibration pencils (bilinear/trilinear FE, "
+                "log-normal coefficient sigma=0.5, seeds 1000+i), n log-uniform 5e3..2e5 "
+                f"(sum {sum(p.n for p, *_ in insts)}), NEV 10..80 each with its own gamma, "
+                "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles")
+        print(json.dumps(many_line(args, "batched", out, desc)), flush=True)
+        return
+    if args.workload == "served":
+        out, reqs = run_served(slrf, args)
+        desc = (f"{len(reqs)} Poisson-arriving requests (rate 0.7 x calibrated capacity), 3D scalar "
+                f"vibration pencils n log-uniform {args.n_min:.0e}..{args.n_max:.0e}, NEV log-uniform "
+                f"20..{args.nev_max}, L = ceil(1.2 NEV) to a multiple of 8, N=6, seeds 5000+r; continuous batching, "
+                "admission by HBM footprint, mixed precision")
+        print(json.dumps(many_line(args, "served", out, desc)), flush=True)
+        return
     wl = workload(args.workload)
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])

@@ -65,7 +65,8 @@ typedef struct {
 typedef struct {
   int32_t precision;   /* slrf_precision.  FP64: complex FP64 inner solves.  MIXED:
                           complex FP32 inner solves with FP64 defect correction */
-  double inner_tol;    /* relative residual ||f - S y|| / ||f|| of each shifted solve */
+  double inner_tol;    /* relative residual ||f - S y|| / ||f|| of each shifted solve
+                          (paper Section 4.2: 1e-13) */
   int32_t inner_maxit; /* BiCGStab iteration limit per solve (paper: 1000) */
   double outer_tol;    /* tau of the residual test (paper Section 4.2: 1e-8) */
   int32_t outer_maxit; /* outer (subspace) iteration limit */
@@ -87,6 +88,10 @@ typedef struct {
   int32_t tile_wgs;    /* workgroups per XCD (default 128, 1..256; grid = 8 * this) */
   int32_t band_rows;   /* rows per sub-band of the sparse-product row order (default
                           1024; -1 = natural row order); applied when a pencil is built */
+  int32_t tune;        /* 1: autotune (tile_rows, tile_wgs) per batch shape: the first
+                          filter application of a shape not seen before in the process
+                          times two BiCGStab iterations per candidate and keeps the
+                          fastest (cached per process); overrides tile_rows/tile_wgs */
 } slrf_options;
 
 typedef struct {
@@ -122,9 +127,9 @@ typedef struct {
   slrf_filter_stats kernels;/* profile = 1: spmm_* / update_* summed over the call */
 } slrf_solve_stats;
 
-/* Defaults: FP64, inner_tol 1e-10, inner_maxit 1000, outer_tol 1e-8,
+/* Defaults: FP64, inner_tol 1e-13, inner_maxit 1000, outer_tol 1e-8,
  * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0,
- * tile_rows / tile_wgs / band_rows 0 (defaults). */
+ * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0. */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance

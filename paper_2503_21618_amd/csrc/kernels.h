@@ -55,6 +55,8 @@ struct Batch {
   const Inst* inst;       // [count]
   const int* tile_inst;   // [n_tiles] pencil of each global tile
   const int* col_inst;    // [Ktot] pencil of each global column
+  int* active;            // [n_tiles] tiles that had an active column at the last poll
+  int* n_active;          // [1] length of that list
   int n_tiles;
   int Ktot;
   int G;                  // grid, a multiple of 8
@@ -78,6 +80,7 @@ struct KrylovState {
   const cx<R>* d;        // (n, N) shifted-operator diagonals (at Inst::dn)
   const cx<R>* dinv;
   const cx<R>* sigma_col;  // [Ktot] pole of each column
+  const R* tolc;           // [Ktot] relative tolerance of each column, or null (one for all)
   cx<R>* part_a;
   R* part_b;
   cx<R>* rho;
@@ -125,7 +128,8 @@ void launch_init_scalars(hipStream_t s, const Batch& b, const KrylovState<R>& st
 template <typename R>
 void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
                       bool first, bool ilu, LaunchTimer* timer, const IterBytes& bytes);
-void launch_count_active(hipStream_t s, int Ktot, const int* flags, int* out);
+// out[0] = number of active columns; rebuilds the active-tile list of the batch.
+void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* out);
 
 // Mixed precision (FP32 inner solves, FP64 defect correction).
 // R = F - S Y in FP64 (Y null: R = F and R is not written), partial |R|^2 in part [G][Ktot].

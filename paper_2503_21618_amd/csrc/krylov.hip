@@ -123,15 +123,21 @@ constexpr int kChunk = 16;
 
 // Loop header shared by the batched kernels: tile tg of pencil I; cl is the
 // lane's column within the pencil, cc that column clamped into range, cg the
-// global column.
-#define FOR_TILES(b, p)                                   \
-  for (int tg = 0; tg < (b).n_tiles; ++tg) {              \
+// global column.  FOR_TILES walks every tile; FOR_ACTIVE_TILES walks the list of
+// tiles that had an active column at the last poll (the iteration kernels).
+#define FOR_TILE_LIST(b, p, COUNT, TG)                                \
+  for (int ti_ = 0; ti_ < (COUNT); ++ti_) {                           \
+    const int tg = (TG);                                              \
     const Inst I = ldc(as_const((b).inst) + as_const((b).tile_inst)[tg]); \
-    const int cl = (tg - I.tile0) * WAVE + (p).lane;      \
-    const bool valid = cl < I.K;                          \
-    const int cc = min(cl, I.K - 1);                      \
-    const int cg = I.col0 + cc;                           \
+    const int cl = (tg - I.tile0) * WAVE + (p).lane;                  \
+    const bool valid = cl < I.K;                                      \
+    const int cc = min(cl, I.K - 1);                                  \
+    const int cg = I.col0 + cc;                                       \
     const size_t po = (size_t)blockIdx.x * (b).Ktot + I.col0 + (size_t)(tg - I.tile0) * WAVE;
+
+#define FOR_TILES(b, p) FOR_TILE_LIST(b, p, (b).n_tiles, ti_)
+#define FOR_ACTIVE_TILES(b, p) \
+  FOR_TILE_LIST(b, p, as_const((const int*)(b).n_active)[0], as_const((const int*)(b).active)[ti_])
 
 #define FOR_ROWS(b, p, I)                                               \
   for (int t_ = 0; t_ < (I).steps; ++t_) {                              \
@@ -148,7 +154,7 @@ constexpr int kChunk = 16;
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* counter) {
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p)
     R dr = 0, di = 0;
     if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* 
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* counter) {
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p)
     R tsr = 0, tsi = 0, tt = 0;
     if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* 
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int first, int* counter) {
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p)
     (void)po;
     if (!tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) continue;
     count_tile(counter);
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int* counter) {
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p)
     R ss = 0;
     if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_x(Batch b, KrylovState<R> st, int first, int* counter) {
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p)
     R rr = 0, ri = 0, nn = 0;
     if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_HALF_PENDING)) {
       count_tile(counter);
@@ -391,6 +397,7 @@ __device__ __forceinline__ bool cfinite(cx<R> z) { return isfinite(z.re) && isfi
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_alpha(Batch b, KrylovState<R> st) {
   SC_PROLOGUE
+  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
   const cx<R> rv = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
   if (!lead || st.flags[c] != COL_ACTIVE) return;
   const cx<R> rho = st.rho[c];
@@ -406,9 +413,10 @@ __global__ __launch_bounds__(WG) void k_sc_alpha(Batch b, KrylovState<R> st) {
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_half(Batch b, KrylovState<R> st, R tol) {
   SC_PROLOGUE
+  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
   const R sn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, valid));
   if (!lead || st.flags[c] != COL_ACTIVE) return;
-  if (sn <= tol * st.fnorm[c]) {
+  if (sn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
     st.flags[c] = COL_HALF_PENDING;
     st.rnorm[c] = sn;
   }
@@ -418,6 +426,7 @@ __global__ __launch_bounds__(WG) void k_sc_half(Batch b, KrylovState<R> st, R to
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_omega(Batch b, KrylovState<R> st) {
   SC_PROLOGUE
+  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
   const cx<R> ts = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
   const R tt = block_col_sum(st.part_b, b.G, b.Ktot, c, valid);
   if (!lead || st.flags[c] != COL_ACTIVE) return;
@@ -432,6 +441,7 @@ __global__ __launch_bounds__(WG) void k_sc_omega(Batch b, KrylovState<R> st) {
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_beta(Batch b, KrylovState<R> st, R tol, int maxit) {
   SC_PROLOGUE
+  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_HALF_PENDING)) return;
   const cx<R> rn = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
   const R nn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, valid));
   if (!lead) return;
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(WG) void k_sc_beta(Batch b, KrylovState<R> st, R to
   }
   if (f != COL_ACTIVE) return;
   st.rnorm[c] = nn;
-  if (nn <= tol * st.fnorm[c]) {
+  if (nn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
     st.flags[c] = COL_CONVERGED;
     return;
   }
@@ -462,6 +472,10 @@ __global__ __launch_bounds__(WG) void k_sc_beta(Batch b, KrylovState<R> st, R to
 template <typename R>
 __global__ __launch_bounds__(WG) void k_init_scalars(Batch b, KrylovState<R> st) {
   SC_PROLOGUE
+  if (threadIdx.x == 0) {  // every tile starts on the active list
+    b.active[blockIdx.x] = blockIdx.x;
+    if (blockIdx.x == 0) b.n_active[0] = b.n_tiles;
+  }
   const R nn = block_col_sum(st.part_b, b.G, b.Ktot, c, valid);
   if (!lead) return;
   st.fnorm[c] = sqrt(nn);
@@ -570,20 +584,46 @@ void launch_init_scalars(hipStream_t s, const Batch& b, const KrylovState<R>& st
   k_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(WG), 0, s>>>(b, st);
 }
 
-__global__ void k_count_active(int K, const int* flags, int* out) {
-  __shared__ int cnt[256];
-  int c0 = 0;
-  for (int c = threadIdx.x; c < K; c += 256) c0 += (flags[c] == COL_ACTIVE) ? 1 : 0;
-  cnt[threadIdx.x] = c0;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) cnt[threadIdx.x] += cnt[threadIdx.x + st];
+// Number of active columns, and the ordered list of tiles that still have an
+// active column (one block; tiles in chunks of 256 with an LDS prefix sum).
+__global__ __launch_bounds__(256) void k_count_active(Batch b, const int* __restrict__ flags,
+                                                     int* __restrict__ out) {
+  __shared__ int scan[256];
+  __shared__ int cols[256];
+  int base = 0, ncols = 0;
+  for (int t0 = 0; t0 < b.n_tiles; t0 += 256) {
+    const int t = t0 + (int)threadIdx.x;
+    int act = 0, cnt = 0;
+    if (t < b.n_tiles) {
+      const Inst I = b.inst[b.tile_inst[t]];
+      const int c0 = I.col0 + (t - I.tile0) * WAVE;
+      const int c1 = min(c0 + WAVE, I.col0 + I.K);
+      for (int c = c0; c < c1; ++c) cnt += flags[c] == COL_ACTIVE ? 1 : 0;
+      act = cnt > 0 ? 1 : 0;
+    }
+    scan[threadIdx.x] = act;
+    cols[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+      const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+      const int w = threadIdx.x >= (unsigned)off ? cols[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      cols[threadIdx.x] += w;
+      __syncthreads();
+    }
+    if (act) b.active[base + scan[threadIdx.x] - 1] = t;
+    base += scan[255];
+    ncols += cols[255];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = cnt[0];
+  if (threadIdx.x == 0) {
+    b.n_active[0] = base;
+    out[0] = ncols;
+  }
 }
-void launch_count_active(hipStream_t s, int K, const int* flags, int* out) {
-  k_count_active<<<1, 256, 0, s>>>(K, flags, out);
+void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* out) {
+  k_count_active<<<1, 256, 0, s>>>(b, flags, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <functional>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -39,7 +40,7 @@ constexpr int kRowsPerBlock = 8;    // default rows per row block
 constexpr int kWgPerXcd = 128;      // default workgroups per XCD (grid 8 * 128)
 constexpr int kSubBand = 1024;      // default rows per sub-band of the sparse-product row order
 constexpr int kTimerSlots = 512;
-constexpr double kInnerTol32 = 1e-6;  // relative tolerance of each FP32 correction solve
+constexpr double kInnerTol32 = 1e-6;  // tightest relative tolerance of an FP32 correction solve
 constexpr int kMaxRounds = 6;         // defect-correction rounds per filter application
 constexpr int kDefaultPoles = 4;
 
@@ -488,7 +489,10 @@ struct FilterLayout {
   double* scale = nullptr;
   double* relres = nullptr;
   double* tol64 = nullptr;
+  float* tol32 = nullptr;
   int* count = nullptr;
+  int* active = nullptr;
+  int* n_active = nullptr;
   Inst* inst = nullptr;
   int* tile_inst = nullptr;
   int* col_inst = nullptr;
@@ -529,6 +533,7 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
     lo.scale = cv.take<double>(lo.Ktot);
     lo.relres = cv.take<double>(lo.Ktot);
     lo.tol64 = cv.take<double>(lo.Ktot);
+    lo.tol32 = cv.take<float>(lo.Ktot);
   } else {
     lo.rhat = cv.take<double>(lo.ER);
   }
@@ -545,6 +550,8 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   lo.flags = cv.take<int>(lo.Ktot);
   lo.iters = cv.take<int>(lo.Ktot);
   lo.count = cv.take<int>(64);
+  lo.active = cv.take<int>(lo.n_tiles);
+  lo.n_active = cv.take<int>(64);
   lo.inst = cv.take<Inst>(js.size());
   lo.tile_inst = cv.take<int>(lo.n_tiles);
   lo.col_inst = cv.take<int>(lo.Ktot);
@@ -587,28 +594,52 @@ KrylovState<R> make_state(const FilterLayout& lo) {
   return st;
 }
 
-// Builds and uploads the device tables of the batch: the Inst table, the tile
-// and column owners, per-column and per-pole shifts, weights and the ILU(0)
-// factors.  The host arrays are parked in `keep`, which the caller holds until
-// the stream has passed the copies.
+struct Tiling {
+  int rpb, wgs;  // rows per row block, workgroups per XCD
+};
+
+Tiling option_tiling(const Env& env) {
+  return {env.opt.tile_rows > 0 ? env.opt.tile_rows : kRowsPerBlock,
+          env.opt.tile_wgs > 0 ? env.opt.tile_wgs : kWgPerXcd};
+}
+
+// Row-block fields of the Inst table and the grid for a tiling.  XCD x owns the
+// row blocks [x * slab, (x + 1) * slab) of each pencil; the grid gives each XCD
+// min(wgs, largest slab) workgroups.
+void apply_tiling(std::vector<Inst>& insts, Batch& b, Tiling t) {
+  int max_slab = 1;
+  for (const Inst& I : insts) max_slab = std::max(max_slab, ((I.n + t.rpb - 1) / t.rpb + 7) / 8);
+  const int per = std::max(1, std::min(t.wgs, max_slab));
+  b.G = 8 * per;
+  b.rows_per_block = t.rpb;
+  for (Inst& I : insts) {
+    I.nrb = (I.n + t.rpb - 1) / t.rpb;
+    I.slab = (I.nrb + 7) / 8;
+    I.steps = (I.slab + per - 1) / per;
+  }
+}
+
+// Copies host bytes into `keep` (alive until the stream has passed the copy)
+// and enqueues the upload.
+hipError_t put_async(hipStream_t s, std::vector<std::vector<char>>& keep, void* dst, const void* src,
+                     size_t bytes) {
+  if (!bytes) return hipSuccess;
+  keep.emplace_back((const char*)src, (const char*)src + bytes);
+  return hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, s);
+}
+
+// Builds and uploads the device tables of the batch: the Inst table (host copy
+// left in `insts`), the tile and column owners, per-column and per-pole shifts,
+// weights and the ILU(0) factors.  The host arrays are parked in `keep`, which
+// the caller holds until the stream has passed the copies.
 template <typename R>
 slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
-                          std::vector<std::vector<char>>& keep) {
+                          std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
   const hipStream_t s = env.stream;
-  std::vector<Inst> insts(jobs.size());
+  insts.assign(jobs.size(), Inst{});
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all;
   std::vector<double> sigc64, w;
-  const int rpb = env.opt.tile_rows > 0 ? env.opt.tile_rows : kRowsPerBlock;
-  const int wgs = env.opt.tile_wgs > 0 ? env.opt.tile_wgs : kWgPerXcd;
-  int max_slab = 1;
-  for (const auto& j : jobs) {
-    const int nrb = (int)((j.P->n + rpb - 1) / rpb);
-    max_slab = std::max(max_slab, (nrb + 7) / 8);
-  }
-  const int per = std::max(1, std::min(wgs, max_slab));
-  b.G = 8 * per;
-  b.rows_per_block = rpb;
   int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
@@ -618,9 +649,6 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.L = j.L;
     I.N = j.N;
     I.K = j.N * j.L;
-    I.nrb = (I.n + rpb - 1) / rpb;
-    I.slab = (I.nrb + 7) / 8;
-    I.steps = (I.slab + per - 1) / per;
     I.col0 = col0;
     I.tile0 = tile0;
     I.nnz = (int)j.P->nnz;
@@ -667,22 +695,94 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   b.inst = lo.inst;
   b.tile_inst = lo.tile_inst;
   b.col_inst = lo.col_inst;
+  b.active = lo.active;
+  b.n_active = lo.n_active;
   b.n_tiles = tile0;
   b.Ktot = col0;
-  keep.reserve(keep.size() + 8);
-  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-    if (!bytes) return hipSuccess;
-    keep.emplace_back((const char*)src, (const char*)src + bytes);
-    return hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, s);
-  };
-  HIPCHK(env, put(lo.inst, insts.data(), insts.size() * sizeof(Inst)));
-  HIPCHK(env, put(lo.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
-  HIPCHK(env, put(lo.col_inst, col_inst.data(), 4 * col_inst.size()));
-  HIPCHK(env, put(lo.sigma_col, sigc.data(), sizeof(cx<R>) * sigc.size()));
-  HIPCHK(env, put(lo.sig_j, sigj.data(), sizeof(cx<R>) * sigj.size()));
-  HIPCHK(env, put(lo.w, w.data(), 8 * w.size()));
-  if (lo.sigma_col64) HIPCHK(env, put(lo.sigma_col64, sigc64.data(), 8 * sigc64.size()));
-  if (!ilu_all.empty()) HIPCHK(env, put(lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
+  apply_tiling(insts, b, option_tiling(env));
+  HIPCHK(env, put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst)));
+  HIPCHK(env, put_async(s, keep, lo.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
+  HIPCHK(env, put_async(s, keep, lo.col_inst, col_inst.data(), 4 * col_inst.size()));
+  HIPCHK(env, put_async(s, keep, lo.sigma_col, sigc.data(), sizeof(cx<R>) * sigc.size()));
+  HIPCHK(env, put_async(s, keep, lo.sig_j, sigj.data(), sizeof(cx<R>) * sigj.size()));
+  HIPCHK(env, put_async(s, keep, lo.w, w.data(), 8 * w.size()));
+  if (lo.sigma_col64) HIPCHK(env, put_async(s, keep, lo.sigma_col64, sigc64.data(), 8 * sigc64.size()));
+  if (!ilu_all.empty()) HIPCHK(env, put_async(s, keep, lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
+  return SLRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner: for a batch shape not seen before in this process, times
+// two BiCGStab iterations for each candidate tiling and keeps the fastest.
+// The shape key is (precision, log2 of the column tiles, log2 of the rows,
+// nonzeros per row to a factor sqrt(2)).
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, Tiling> g_tune_cache;
+
+int ilog2(int64_t x) {
+  int r = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+template <typename R>
+slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo, Batch& b,
+                     const KrylovState<R>& st, R tol, bool ilu, const IterBytes& by,
+                     const std::function<void()>& restart, std::vector<std::vector<char>>& keep) {
+  const hipStream_t s = env.stream;
+  int64_t rows = 0, nnz = 0;
+  for (const Inst& I : insts) {
+    rows += I.n;
+    nnz += I.nnz;
+  }
+  const auto key = std::make_tuple((int)sizeof(R), ilog2(b.n_tiles), ilog2(rows),
+                                   (int)std::lround(2.0 * std::log2((double)nnz / (double)rows)));
+  Tiling best{0, 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) best = it->second;
+  }
+  if (best.rpb == 0) {
+    static const Tiling cands[] = {{8, 128}, {16, 128}, {32, 128}, {4, 128}, {8, 256}, {16, 64}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(env, hipEventCreate(&e0));
+    HIPCHK(env, hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    hipError_t err = hipSuccess;
+    for (const Tiling& c : cands) {
+      apply_tiling(insts, b, c);
+      err = put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst));
+      if (err != hipSuccess) break;
+      restart();
+      launch_iteration<R>(s, b, st, tol, 1 << 30, true, ilu, nullptr, by);
+      (void)hipEventRecord(e0, s);
+      for (int q = 0; q < 2; ++q) launch_iteration<R>(s, b, st, tol, 1 << 30, false, ilu, nullptr, by);
+      (void)hipEventRecord(e1, s);
+      err = hipEventSynchronize(e1);
+      float ms = 0;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (env.verbose) fprintf(stderr, "[slrf] tune rows %d wgs %d: %.3f ms\n", c.rpb, c.wgs, ms);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(env, SLRF_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  apply_tiling(insts, b, best);
+  HIPCHK(env, put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst)));
+  restart();
+  HIPCHK(env, hipGetLastError());
   return SLRF_OK;
 }
 
@@ -713,7 +813,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
           for (int q = 0; q < every; ++q) launch_iteration<R>(s, b, st, tol, maxit, false, ilu, nullptr, by);
-          launch_count_active(s, b.Ktot, st.flags, d_count);
+          launch_count_active(s, b, st.flags, d_count);
           e = hipStreamEndCapture(s, &gr);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
@@ -730,7 +830,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       it += every;
     } else {
       for (int q = 0; q < chunk; ++q, ++it) launch_iteration<R>(s, b, st, tol, maxit, it == 0, ilu, tm, by);
-      launch_count_active(s, b.Ktot, st.flags, d_count);
+      launch_count_active(s, b, st.flags, d_count);
     }
     int active = 0;
     hipError_t e = hipGetLastError();
@@ -818,7 +918,8 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
   Batch b{};
   std::vector<std::vector<char>> keep;
-  slrf_status st0 = upload_tables<double>(env, jobs, lo, b, keep);
+  std::vector<Inst> insts;
+  slrf_status st0 = upload_tables<double>(env, jobs, lo, b, insts, keep);
   if (st0 != SLRF_OK) return st0;
   KrylovState<double> st = make_state<double>(lo);
   int64_t dn = 0, rl = 0, pj = 0;
@@ -835,6 +936,13 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   HIPCHK(env, hipGetLastError());
   slrf_filter_stats ks{};
   const IterBytes by = iter_bytes(jobs, lo, 8, false);
+  if (env.opt.tune) {
+    slrf_status ts = autotune<double>(env, insts, lo, b, st, env.opt.inner_tol, lo.any_ilu, by, [&]() {
+      launch_init<double>(s, b, st, lo.rhat);
+      launch_init_scalars<double>(s, b, st);
+    }, keep);
+    if (ts != SLRF_OK) return ts;
+  }
   slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.any_ilu, by, lo.count, &ks);
   if (rs != SLRF_OK) return rs;
   int64_t blk = 0, wj = 0;
@@ -855,7 +963,8 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
 // Filter application with complex FP32 inner solves and FP64 defect correction:
 //   Y = 0; repeat { R = F - S Y in FP64; stop the columns with
 //   ||R|| <= target ||F||; solve S D = R / ||R|| in FP32 by BiCGStab to relative
-//   residual kInnerTol32; Y += ||R|| D };  U = sum_j 2 Re(w_j Y_j).
+//   residual clamp(0.1 target, 1e-6, 1e-2); Y += ||R|| D };
+//   U = sum_j 2 Re(w_j Y_j).
 slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
   const double t0 = now_s();
   const hipStream_t s = env.stream;
@@ -866,13 +975,26 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
   Batch b{};
   std::vector<std::vector<char>> keep;
-  slrf_status st0 = upload_tables<float>(env, jobs, lo, b, keep);
+  std::vector<Inst> insts;
+  slrf_status st0 = upload_tables<float>(env, jobs, lo, b, insts, keep);
   if (st0 != SLRF_OK) return st0;
   KrylovState<float> st = make_state<float>(lo);
+  // Per column: the FP64 defect target of its job, and the FP32 correction
+  // tolerance, which only has to gain a factor 10 on that target (a round ends
+  // a column once its FP64 defect meets the target).
   std::vector<double> tol_host;
-  for (auto& j : jobs)
-    for (int c = 0; c < j.N * j.L; ++c) tol_host.push_back(j.target);
-  HIPCHK(env, hipMemcpyAsync(lo.tol64, tol_host.data(), 8 * tol_host.size(), hipMemcpyHostToDevice, s));
+  std::vector<float> tol32_host;
+  for (auto& j : jobs) {
+    const float t32 = (float)std::max(kInnerTol32, std::min(1e-2, 0.1 * j.target));
+    for (int c = 0; c < j.N * j.L; ++c) {
+      tol_host.push_back(j.target);
+      tol32_host.push_back(t32);
+    }
+  }
+  const float tol32 = (float)kInnerTol32;  // unused: every column has its own
+  HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
+  HIPCHK(env, put_async(s, keep, lo.tol32, tol32_host.data(), 4 * tol32_host.size()));
+  st.tolc = lo.tol32;
   int64_t dn = 0, rl = 0, pj = 0;
   for (auto& j : jobs) {
     launch_jacobi_diag<float>(s, (int)j.P->n, j.N, j.P->diagA32, j.P->diagB32, (const cx<float>*)lo.sig_j + pj,
@@ -901,7 +1023,14 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     ++rounds;
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
     launch_init_scalars<float>(s, b, st);
-    slrf_status rs = run_krylov<float>(env, b, st, (float)kInnerTol32, lo.any_ilu, by, lo.count, &ks);
+    if (round == 0 && env.opt.tune) {
+      slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.any_ilu, by, [&]() {
+        launch_mixed_rhs(s, b, nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
+        launch_init_scalars<float>(s, b, st);
+      }, keep);
+      if (ts != SLRF_OK) return ts;
+    }
+    slrf_status rs = run_krylov<float>(env, b, st, tol32, lo.any_ilu, by, lo.count, &ks);
     if (rs != SLRF_OK) return rs;
     launch_accumulate(s, b, st.x, lo.scale, lo.Y, round == 0);
     slrf_status cs = collect_stats<float>(env, jobs, st, lo.Ktot, false, it_round);
@@ -1205,7 +1334,7 @@ extern "C" {
 void slrf_default_options(slrf_options* o) {
   if (!o) return;
   o->precision = SLRF_FP64;
-  o->inner_tol = 1e-10;
+  o->inner_tol = 1e-13;  // Section 4.2: BiCGStab stopping tolerance of the eigensolver runs
   o->inner_maxit = 1000;
   o->outer_tol = 1e-8;
   o->outer_maxit = 40;
@@ -1217,6 +1346,7 @@ void slrf_default_options(slrf_options* o) {
   o->tile_rows = 0;
   o->tile_wgs = 0;
   o->band_rows = 0;
+  o->tune = 0;
 }
 
 const char* slrf_status_string(slrf_status s) {

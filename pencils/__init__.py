@@ -274,3 +274,72 @@ def c3_elasticity(nodes: int = 48, seed: int = 3) -> Pencil:
     """3D elasticity, 48 x 47 x 47 hexes of side 1/48, 48^3 free nodes x 3 dofs."""
     return elasticity_q1(nodes, nodes - 1, nodes - 1, 1.0 / nodes, 0.7, 0.3,
                          (0.8, 1.2), seed)
+
+
+# Batched workload ----------------------------------------------------------
+
+def cc_spectrum(m: int, dim: int, count: int) -> np.ndarray:
+    """The `count` smallest eigenvalues of the constant-coefficient Q1 pencil with m
+    elements per side (Dirichlet): sums of the 1D linear-FE eigenvalues
+    mu_k = (6/h^2)(1 - cos k pi h)/(2 + cos k pi h), k = 1..m-1, one per axis
+    (stiffness and mass are Kronecker sums/products of the 1D matrices)."""
+    h = 1.0 / m
+    k = np.arange(1, m)
+    mu = (6.0 / h ** 2) * 2.0 * np.sin(0.5 * k * np.pi * h) ** 2 / (2.0 + np.cos(k * np.pi * h))
+    mu = mu[: min(len(mu), count)]
+    s = mu
+    for _ in range(dim - 1):
+        s = (s[:, None] + mu[None, :]).ravel()
+        s = np.sort(s)[:count]
+    return np.sort(s)[:count]
+
+
+def batch_instance(i: int, seed0: int = 1000, n_range=(5e3, 2e5), nev_range=(10, 80),
+                   sigma_ln: float = 0.5):
+    """Instance i of the batched workload: a 2D or 3D scalar vibration pencil.
+
+    Seed s = seed0 + i.  Uniforms u = uniform(s, 3): dimension 2 if u0 < 1/2 else 3;
+    target size n = exp(U[ln n_lo, ln n_hi]) rounded to the nearest grid (m-1)^dim;
+    NEV uniform on {nev_lo..nev_hi}; log-normal element coefficient (sigma_ln, seed s).
+    gamma lies halfway between the NEV-th eigenvalue of the constant-coefficient
+    pencil of the same grid and the next larger distinct one, so the log-normal
+    pencil has about NEV eigenvalues in (0, gamma].  L = ceil(1.2 NEV) rounded up
+    to a multiple of 8.  Returns (pencil, gamma, L, NEV)."""
+    s = seed0 + i
+    u = uniform(s, 3)
+    dim = 2 if u[0] < 0.5 else 3
+    lo, hi = math.log(n_range[0]), math.log(n_range[1])
+    n_t = math.exp(lo + (hi - lo) * u[1])
+    m = int(round(n_t ** (1.0 / dim))) + 1
+    nev = nev_range[0] + min(int(u[2] * (nev_range[1] - nev_range[0] + 1)), nev_range[1] - nev_range[0])
+    lam = cc_spectrum(m, dim, nev + 64)
+    above = lam[lam > lam[nev - 1] * (1 + 1e-12)]
+    gamma = 0.5 * (lam[nev - 1] + above[0])
+    L = int(math.ceil(math.ceil(1.2 * nev) / 8.0) * 8)
+    return scalar_q1(m, dim, sigma_ln, s), float(gamma), L, nev
+
+
+def serve_request(r: int, seed0: int = 5000, n_range=(1e4, 1e5), nev_range=(20, 100),
+                  sigma_ln: float = 0.5):
+    """Request r of the serving workload: a 3D scalar vibration pencil.
+
+    Seed s = seed0 + r; uniforms u = uniform(s, 2): size log-uniform on n_range
+    (rounded to the nearest grid (m-1)^3), NEV log-uniform on nev_range; gamma
+    from the constant-coefficient spectrum as in batch_instance; L = ceil(1.2 NEV)
+    rounded up to a multiple of 8.  Returns (pencil, gamma, L, NEV)."""
+    s = seed0 + r
+    u = uniform(s, 2)
+    lo, hi = math.log(n_range[0]), math.log(n_range[1])
+    m = int(round(math.exp(lo + (hi - lo) * u[0]) ** (1.0 / 3.0))) + 1
+    a, b = math.log(nev_range[0]), math.log(nev_range[1])
+    nev = int(round(math.exp(a + (b - a) * u[1])))
+    lam = cc_spectrum(m, 3, nev + 64)
+    above = lam[lam > lam[nev - 1] * (1 + 1e-12)]
+    gamma = 0.5 * (lam[nev - 1] + above[0])
+    L = int(math.ceil(math.ceil(1.2 * nev) / 8.0) * 8)
+    return scalar_q1(m, 3, sigma_ln, s), float(gamma), L, nev
+
+
+def arrival_times(count: int, rate: float, seed: int = 4999) -> np.ndarray:
+    """Poisson arrivals: cumulative sums of exponential gaps -ln(u)/rate."""
+    return np.cumsum(-np.log(uniform(seed, count)) / rate)

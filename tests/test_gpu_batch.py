@@ -214,3 +214,35 @@ def test_graph_replay_bitwise_equals_eager(slrf, torch, prec):
         assert e.status == 0 and g.status == 0
         assert np.array_equal(e.evals, g.evals)
         assert torch.equal(e.evecs, g.evecs)
+
+
+def test_batched_workload_recipe_with_autotune_and_graph(slrf, torch):
+    """Eight instances of the batched workload's recipe (sizes cut to 2e3..1.5e4
+    rows so the oracle's inertia count stays quick), mixed precision, autotuned
+    tiles, graph replay: every instance converges to the oracle's count and
+    agrees with its FP64 solve alone."""
+    insts = [pencils.batch_instance(i, n_range=(2e3, 1.5e4)) for i in range(8)]
+    cases = [(p, g, L, k) for p, g, L, k in insts]
+    ws, arena = ws_for(slrf, cases, 1)
+    stream = torch.cuda.Stream()
+    opt = slrf.default_options(precision=1, tune=1, graph=1)
+    say("case batched recipe, 8 instances, mixed + tune + graph")
+    b = slrf.Batch(ws, arena, max_poles=4, options=opt, stream=stream)
+    ids = [b.add(p.A, p.B, g, L) for p, g, L, _ in cases]
+    while b.step() > 0:
+        pass
+    res = [b.result(pid) for pid in ids]
+    torch.cuda.synchronize()
+    b.close()
+    for (p, gamma, L, nev), r in zip(cases, res):
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=4)
+        a = s.solve_interval(gamma, L)
+        s.close()
+        nf = r.n_found
+        cnt = inertia.sparse_ldl_count(p.A, p.B, gamma)
+        rel = np.abs(r.evals[:nf] / a.evals[:nf] - 1).max()
+        say(f"  n={p.n} dim={p.meta['dim']} nev~{nev} L={L}: found {nf} (count {cnt}), "
+            f"outer {r.stats['outer_iterations']}, rel vs FP64 alone {rel:.1e}")
+        assert r.status == 0 and nf == cnt == a.n_found
+        assert rel < 1e-9
+        assert r.resid[:nf].max() <= 1e-8

@@ -1,0 +1,89 @@
+"""GPU tests of the serving loop (continuous batching): requests that arrive
+while others run are admitted as pool and arena space frees up, their work
+shares each batched launch, and every result is the same as the request solved
+alone, within the stated tolerance (eigenvalues to 1e-9 relative, the same count
+of converged pairs, residuals <= 1e-8)."""
+import numpy as np
+import pytest
+
+import pencils
+from oracle import inertia
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def slrf(torch):
+    import paper_2503_21618_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def requests(serve):
+    """Six small requests (2D and 3D scalar pencils, different n, L, gamma) and the
+    server step at which each arrives."""
+    out = []
+    arrive = [0, 0, 1, 2, 4, 5]
+    for k, i in enumerate([1, 6, 8, 34, 42, 51]):
+        p, gamma, L, _ = pencils.batch_instance(i)
+        V0 = pencils.start_block(p.n, L, 500 + k)
+        out.append(serve.Request(k, p.A, p.B, gamma, L, V0=V0, arrival=float(arrive[k])))
+    return out
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_results_same_alone_and_in_the_mix(slrf, torch, prec):
+    import paper_2503_21618_amd.serve as serve
+    reqs = requests(serve)
+    opt = slrf.default_options(precision=prec)
+    alone = {}
+    for r in reqs:
+        s = slrf.Solver(r.A, r.B, max_L=r.L, max_poles=4, options=opt)
+        alone[r.rid] = s.solve_interval(r.gamma, r.L, V0=torch.from_numpy(r.V0).cuda())
+        s.close()
+    pers = trans = 0
+    for r in reqs:
+        nnz = int((abs(r.A) + abs(r.B)).nnz)
+        a, b = slrf.batch_footprint(r.A.shape[0], nnz, r.L, 4, prec)
+        pers += a + 4096
+        trans += b
+    # arena for about half of the requests at once: admission has to wait
+    srv = serve.Server(pers + trans // 2 + (1 << 20), trans // 2, max_poles=4, options=opt)
+    srv.clock = lambda: float(srv.steps)
+    pending = sorted(reqs, key=lambda r: r.arrival)
+    while pending or not srv.idle():
+        while pending and pending[0].arrival <= srv.steps:
+            srv.submit(pending.pop(0))
+        if srv.idle() and pending:
+            srv.steps += 1          # nothing to run until the next arrival
+            continue
+        srv.pump()
+        assert srv.steps < 200
+    say(f"case serve prec={prec}: {len(srv.done)} done in {srv.steps} steps, peak active {srv.peak_active}")
+    assert len(srv.done) == len(reqs)
+    assert 2 <= srv.peak_active < len(reqs)
+    for c in srv.done:
+        a = alone[c.rid]
+        r = c.result
+        req = reqs[c.rid]
+        nf = r.n_found
+        rel = np.abs(r.evals[:nf] / a.evals[:nf] - 1).max()
+        say(f"  request {c.rid}: n={req.A.shape[0]} found {nf} (alone {a.n_found}), rel diff {rel:.1e}, "
+            f"arrive {c.arrival:.0f} admitted {c.admitted:.0f} finished {c.finished:.0f}")
+        assert r.status == 0 and a.status == 0
+        assert nf == a.n_found == inertia.sparse_ldl_count(req.A, req.B, req.gamma)
+        assert rel < 1e-9
+        assert r.resid[:nf].max() <= 1e-8
+        assert c.admitted >= c.arrival and c.finished > c.admitted
+    srv.close()
