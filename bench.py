@@ -247,11 +247,14 @@ def batch_kernel_stats(results):
     return last.stats["kernels"]
 
 
-def serial_fp64(slrf, items):
-    """Plain FP64 solves one pencil at a time (create and pole design excluded)."""
+def serial_fp64(slrf, items, limit_s=float("inf")):
+    """Plain FP64 solves one pencil at a time (create and pole design excluded),
+    in order, until limit_s seconds of solve time have been spent."""
     import torch
-    found, secs = 0, 0.0
+    found, secs, done, not_ok = 0, 0.0, 0, 0
     for p, gamma, L in items:
+        if secs >= limit_s:
+            break
         s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=slrf.default_options())
         sig, w, _ = slrf.design_poles(6, 1.0, 0.01, gamma)
         torch.cuda.synchronize()
@@ -260,10 +263,15 @@ def serial_fp64(slrf, items):
         torch.cuda.synchronize()
         secs += time.perf_counter() - t0
         found += r.n_found
+        done += 1
+        not_ok += r.status != 0
+        log(f"serial FP64 {done}: n={p.n} found {r.n_found} status {r.status} "
+            f"outer {r.stats['outer_iterations']}, total {secs:.1f} s")
         s.close()
         del s
         torch.cuda.empty_cache()
-    return found, secs
+    return {"value": found / secs, "seconds": secs, "found": found, "pencils": done,
+            "pencils_not_converged": not_ok}
 
 
 def run_batched(slrf, args):
@@ -312,8 +320,7 @@ def run_batched(slrf, args):
            "statuses_not_ok": bad, "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
     if not args.no_serial:
         log("serial FP64 solves...")
-        f2, s2 = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in insts])
-        out["serial_fp64"] = {"value": f2 / s2, "seconds": s2, "found": f2}
+        out["serial_fp64"] = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in insts], args.serial_limit)
     return out, insts
 
 
@@ -388,8 +395,7 @@ def run_served(slrf, args):
     torch.cuda.empty_cache()
     if not args.no_serial:
         log("serial FP64 solves...")
-        f2, s2 = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in reqs])
-        out["serial_fp64"] = {"value": f2 / s2, "seconds": s2, "found": f2}
+        out["serial_fp64"] = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in reqs], args.serial_limit)
     return out, reqs
 
 
@@ -468,6 +474,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--pool-gb", type=float, default=32.0)
     ap.add_argument("--no-serial", action="store_true", help="skip the serial FP64 comparison")
+    ap.add_argument("--serial-limit", type=float, default=float("inf"),
+                    help="stop the serial FP64 comparison after this many seconds of solves")
     ap.add_argument("--counters-probe", action="store_true",
                     help="short run for the rocprofv3 counter passes (see the module docstring)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),

@@ -136,9 +136,11 @@ void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* o
 void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, const double* F,
                    const cx<double>* Y, cx<double>* Rout, double* part);
 // scale_c = ||R_c|| if ||R_c|| > tol_c ||F_c|| else 0 (tol per column); the first round
-// sets fnorm_c = ||F_c||; *count = number of columns with scale_c > 0.
+// sets fnorm_c = ||F_c||; tol32_c = clamp(0.1 tol_c ||F_c|| / ||R_c||, min32, 0.1), the
+// relative tolerance of the column's next FP32 solve; *count = columns with scale_c > 0.
 void launch_defect_norms(hipStream_t s, const Batch& b, const double* part, const double* tol,
-                         int first, double* fnorm, double* scale, double* relres, int* count);
+                         int first, double* fnorm, double* scale, double* relres, float* tol32,
+                         double min32, int* count);
 // r = R / scale (R null: F / scale), rhat = r, x = 0 in FP32; partial |r|^2 into part_b.
 void launch_mixed_rhs(hipStream_t s, const Batch& b, const cx<double>* R, const double* F,
                       const double* scale, const KrylovState<float>& st, cx<float>* rhat);

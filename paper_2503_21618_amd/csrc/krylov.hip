@@ -657,10 +657,14 @@ void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, c
   k_defect<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, sigma_col, F, Y, Rout, part);
 }
 
+// scale_c = ||R_c|| unless the defect meets its target; the next FP32 solve of
+// the column only has to reduce R_c by the remaining factor target ||F|| / ||R||,
+// so its tolerance is a tenth of that, within [min32, 1e-1].
 __global__ __launch_bounds__(WG) void k_defect_norms(Batch b, const double* __restrict__ part,
                                                     const double* __restrict__ tol, int first,
                                                     double* __restrict__ fnorm, double* __restrict__ scale,
-                                                    double* __restrict__ relres) {
+                                                    double* __restrict__ relres, float* __restrict__ tol32,
+                                                    double min32) {
   SC_PROLOGUE
   const double r = sqrt(block_col_sum(part, b.G, b.Ktot, c, valid));
   if (!lead) return;
@@ -669,6 +673,8 @@ __global__ __launch_bounds__(WG) void k_defect_norms(Batch b, const double* __re
   const bool done = r <= tol[c] * fn;
   scale[c] = done ? 0.0 : r;
   relres[c] = fn > 0 ? r / fn : 0.0;
+  const double gap = r > 0 ? tol[c] * fn / r : 1.0;
+  tol32[c] = (float)fmin(1e-1, fmax(min32, 0.1 * gap));
 }
 
 __global__ void k_count_positive(int K, const double* __restrict__ v, int* __restrict__ out) {
@@ -685,8 +691,9 @@ __global__ void k_count_positive(int K, const double* __restrict__ v, int* __res
 }
 
 void launch_defect_norms(hipStream_t s, const Batch& b, const double* part, const double* tol, int first,
-                         double* fnorm, double* scale, double* relres, int* count) {
-  k_defect_norms<<<dim3((unsigned)b.n_tiles), dim3(WG), 0, s>>>(b, part, tol, first, fnorm, scale, relres);
+                         double* fnorm, double* scale, double* relres, float* tol32, double min32, int* count) {
+  k_defect_norms<<<dim3((unsigned)b.n_tiles), dim3(WG), 0, s>>>(b, part, tol, first, fnorm, scale, relres,
+                                                                tol32, min32);
   k_count_positive<<<1, 256, 0, s>>>(b.Ktot, scale, count);
 }
 

@@ -963,7 +963,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
 // Filter application with complex FP32 inner solves and FP64 defect correction:
 //   Y = 0; repeat { R = F - S Y in FP64; stop the columns with
 //   ||R|| <= target ||F||; solve S D = R / ||R|| in FP32 by BiCGStab to relative
-//   residual clamp(0.1 target, 1e-6, 1e-2); Y += ||R|| D };
+//   residual clamp(0.1 target ||F|| / ||R||, 1e-6, 1e-1); Y += ||R|| D };
 //   U = sum_j 2 Re(w_j Y_j).
 slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
   const double t0 = now_s();
@@ -979,21 +979,14 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   slrf_status st0 = upload_tables<float>(env, jobs, lo, b, insts, keep);
   if (st0 != SLRF_OK) return st0;
   KrylovState<float> st = make_state<float>(lo);
-  // Per column: the FP64 defect target of its job, and the FP32 correction
-  // tolerance, which only has to gain a factor 10 on that target (a round ends
-  // a column once its FP64 defect meets the target).
+  // Per column: the FP64 defect target of its job.  The relative tolerance of
+  // each FP32 correction solve is set per column by the defect kernel from the
+  // gap between the current defect and that target.
   std::vector<double> tol_host;
-  std::vector<float> tol32_host;
-  for (auto& j : jobs) {
-    const float t32 = (float)std::max(kInnerTol32, std::min(1e-2, 0.1 * j.target));
-    for (int c = 0; c < j.N * j.L; ++c) {
-      tol_host.push_back(j.target);
-      tol32_host.push_back(t32);
-    }
-  }
+  for (auto& j : jobs)
+    for (int c = 0; c < j.N * j.L; ++c) tol_host.push_back(j.target);
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
-  HIPCHK(env, put_async(s, keep, lo.tol32, tol32_host.data(), 4 * tol32_host.size()));
   st.tolc = lo.tol32;
   int64_t dn = 0, rl = 0, pj = 0;
   for (auto& j : jobs) {
@@ -1012,7 +1005,8 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   int rounds = 0;
   for (int round = 0; round <= kMaxRounds; ++round) {
     launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64);
-    launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.count);
+    launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.tol32,
+                        kInnerTol32, lo.count);
     HIPCHK(env, hipGetLastError());
     int open = 0;
     HIPCHK(env, hipMemcpyAsync(&open, lo.count, sizeof(int), hipMemcpyDeviceToHost, s));
