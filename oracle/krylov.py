@@ -2,11 +2,14 @@
 
 The paper solves each shifted system (A - sigma_j B) y = f with BiCGStab
 (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992)), Sections 2 and 4.2, with an
-ILU preconditioner of the shifted operator.  Two preconditioners M_j of
-S_j = A - sigma_j B are used here, both applied on the right:
+ILU preconditioner of the shifted operator.  Three preconditioners M_j of
+S_j = A - sigma_j B are used here, all applied on the right:
   * point Jacobi, M_j = diag(A) - sigma_j diag(B);
   * ILU(0), M_j = L_j U_j with the sparsity pattern of S_j (no fill), which is
-    the exact LU factorisation when S_j is tridiagonal.
+    the exact LU factorisation when S_j is tridiagonal;
+  * node block Jacobi for vector problems with 3 unknowns per node
+    (unknowns 3k, 3k+1, 3k+2 belong to node k): M_j = blockdiag of the 3x3
+    diagonal blocks of S_j, exact when A and B are block diagonal.
 
 Readings: the initial guess is x_0 = 0, so r_0 = f, and the shadow residual is
 r_hat = f (real when f = B X is real, shared by all poles).  Inner products are
@@ -67,6 +70,27 @@ def ilu0(A, B, sigma: complex):
     return indptr, indices, vals
 
 
+def block_jacobi3(A, B, sigma: complex) -> np.ndarray:
+    """The (n/3, 3, 3) diagonal node blocks of S = A - sigma B."""
+    n = A.shape[0]
+    if n % 3:
+        raise ValueError("block Jacobi needs 3 unknowns per node")
+    S = (A.astype(np.complex128) - sigma * B).tocsr()
+    blocks = np.zeros((n // 3, 3, 3), np.complex128)
+    for r in range(3):
+        for c in range(3):
+            rows = np.arange(r, n, 3)
+            blocks[:, r, c] = np.asarray(S[rows, rows - r + c]).ravel()
+    return blocks
+
+
+def block_jacobi3_solve(blocks, Y):
+    """M^{-1} Y for M = blockdiag(blocks): one 3x3 solve per node and column."""
+    n, m = Y.shape
+    Z = np.asarray(Y, dtype=np.complex128).reshape(n // 3, 3, m)
+    return np.linalg.solve(blocks, Z).reshape(n, m)
+
+
 def ilu0_solve(fac, Y):
     """(L U)^{-1} Y by forward and backward substitution (Y is (n, m))."""
     indptr, indices, vals = fac
@@ -113,6 +137,12 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
 
         def Minv(Y):
             return np.concatenate([ilu0_solve(facs[j], Y[:, j * L:(j + 1) * L])
+                                   for j in range(N)], axis=1)
+    elif precond == "bjac3":
+        blks = [block_jacobi3(A, B, s) for s in sigmas]
+
+        def Minv(Y):
+            return np.concatenate([block_jacobi3_solve(blks[j], Y[:, j * L:(j + 1) * L])
                                    for j in range(N)], axis=1)
     else:
         raise ValueError(precond)
