@@ -247,15 +247,15 @@ def batch_kernel_stats(results):
     return last.stats["kernels"]
 
 
-def serial_fp64(slrf, items, limit_s=float("inf")):
-    """Plain FP64 solves one pencil at a time (create and pole design excluded),
+def serial_solves(slrf, items, precision, limit_s=float("inf")):
+    """The same pencils solved one at a time (create and pole design excluded),
     in order, until limit_s seconds of solve time have been spent."""
     import torch
     found, secs, done, not_ok = 0, 0.0, 0, 0
     for p, gamma, L in items:
         if secs >= limit_s:
             break
-        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=slrf.default_options())
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=slrf.default_options(precision=precision))
         sig, w, _ = slrf.design_poles(6, 1.0, 0.01, gamma)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -265,13 +265,14 @@ def serial_fp64(slrf, items, limit_s=float("inf")):
         found += r.n_found
         done += 1
         not_ok += r.status != 0
-        log(f"serial FP64 {done}: n={p.n} found {r.n_found} status {r.status} "
+        log(f"serial {done}: n={p.n} found {r.n_found} status {r.status} "
             f"outer {r.stats['outer_iterations']}, total {secs:.1f} s")
         s.close()
         del s
         torch.cuda.empty_cache()
-    return {"value": found / secs, "seconds": secs, "found": found, "pencils": done,
-            "pencils_not_converged": not_ok}
+    return {"precision": "mixed" if precision == slrf.MIXED else "fp64",
+            "value": found / secs if secs > 0 else 0.0, "seconds": secs, "found": found,
+            "pencils": done, "pencils_not_converged": not_ok}
 
 
 def run_batched(slrf, args):
@@ -319,8 +320,10 @@ def run_batched(slrf, args):
     out = {"value": found / dt, "seconds": dt, "found": found, "steps": steps,
            "statuses_not_ok": bad, "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
     if not args.no_serial:
-        log("serial FP64 solves...")
-        out["serial_fp64"] = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in insts], args.serial_limit)
+        log("serial solves...")
+        out["serial"] = serial_solves(slrf, [(p, g, L) for p, g, L, _ in insts],
+                                      slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
+                                      args.serial_limit)
     return out, insts
 
 
@@ -394,8 +397,10 @@ def run_served(slrf, args):
     del srv
     torch.cuda.empty_cache()
     if not args.no_serial:
-        log("serial FP64 solves...")
-        out["serial_fp64"] = serial_fp64(slrf, [(p, g, L) for p, g, L, _ in reqs], args.serial_limit)
+        log("serial solves...")
+        out["serial"] = serial_solves(slrf, [(p, g, L) for p, g, L, _ in reqs],
+                                      slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
+                                      args.serial_limit)
     return out, reqs
 
 
@@ -415,8 +420,9 @@ def many_line(args, kind, out, desc):
                          "traffic_note": "counters are taken on the 64^3 scalar workload only"},
             "vector_updates": {"achieved_GBs": ks["update_bytes"] / ks["update_seconds"] / 1e9}}
     line[kind] = out
-    if "serial_fp64" in out:
-        line["over_serial_fp64"] = out["value"] / out["serial_fp64"]["value"]
+    ser = out.get("serial")
+    if ser and ser["value"] > 0:
+        line[f"over_serial_{ser['precision']}"] = out["value"] / ser["value"]
     return line
 
 
@@ -473,9 +479,11 @@ def main():
     ap.add_argument("--calibrate", type=int, default=6, help="served workload: calibration batch")
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--pool-gb", type=float, default=32.0)
-    ap.add_argument("--no-serial", action="store_true", help="skip the serial FP64 comparison")
+    ap.add_argument("--no-serial", action="store_true", help="skip the one-pencil-at-a-time comparison")
     ap.add_argument("--serial-limit", type=float, default=float("inf"),
-                    help="stop the serial FP64 comparison after this many seconds of solves")
+                    help="stop the serial comparison after this many seconds of solves")
+    ap.add_argument("--serial-precision", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the one-pencil-at-a-time comparison")
     ap.add_argument("--counters-probe", action="store_true",
                     help="short run for the rocprofv3 counter passes (see the module docstring)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),

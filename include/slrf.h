@@ -75,7 +75,10 @@ typedef struct {
   int32_t precond;     /* preconditioner M_j of the shifted operator A - sigma_j B:
                           0 auto: ILU(0) if the merged pattern has nnz <= 5 n, else Jacobi
                           1 point Jacobi, M_j = diag(A) - sigma_j diag(B)
-                          2 ILU(0) on the merged pattern (requires nnz <= 5 n) */
+                          2 ILU(0) on the merged pattern (requires nnz <= 5 n)
+                          3 node block Jacobi for three unknowns per node (unknowns
+                            3k, 3k+1, 3k+2 form node k; requires n divisible by 3):
+                            M_j = blockdiag of the 3x3 node blocks of A - sigma_j B */
   int32_t profile;     /* 1: time the sparse-product and vector-update kernels with HIP
                           events and count the column tiles each launch processes
                           (stats fields spmm_* and update_*); 0: off */
@@ -146,15 +149,20 @@ slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma
 
 /* Bytes of device workspace slrf_create needs for a pencil with n rows and
  * nnz_union entries in the union of the patterns of A and B, subspace size up
- * to L and up to N poles, at the given precision. */
+ * to L and up to N poles, at the given precision, with the automatic
+ * preconditioner choice (precond = 0). */
 slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
                                  int32_t precision, size_t* bytes);
+
+/* The same for the precision and preconditioner of opt (NULL: defaults). */
+slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
+                                     const slrf_options* opt, size_t* bytes);
 
 /* Validates A and B (square, sorted in-range columns, finite values, symmetric
  * pattern sizes, positive diagonals), merges them into one CSR over the union
  * pattern with (a_ij, b_ij) value pairs, and uploads it into the workspace.
- * d_workspace: device, 256-byte aligned, ws_bytes from slrf_workspace_bytes
- * with the largest L and N that later calls use.  hip_stream: a hipStream_t
+ * d_workspace: device, 256-byte aligned, ws_bytes from slrf_workspace_bytes_for
+ * with the largest L and N that later calls use and the same options.  hip_stream: a hipStream_t
  * (NULL = default stream).  opt may be NULL (defaults).  On failure *out may
  * still hold a context: read slrf_last_error(*out), then slrf_destroy(*out). */
 slrf_status slrf_create(slrf_ctx* out, int64_t n,

@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 FP64, MIXED = 0, 1
-PRECOND_AUTO, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
+PRECOND_AUTO, PRECOND_JACOBI, PRECOND_ILU0, PRECOND_BLOCK3 = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_DEVICE",
           5: "E_NOT_CONVERGED", 6: "E_SUBSPACE_TOO_SMALL", 7: "E_BREAKDOWN"}
 
@@ -66,6 +66,8 @@ _lib.slrf_default_options.argtypes = [C.POINTER(Options)]
 _lib.slrf_design_poles.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _P, _P, _P]
 _lib.slrf_workspace_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_size_t)]
+_lib.slrf_workspace_bytes_for.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.POINTER(Options),
+                                          C.POINTER(C.c_size_t)]
 _lib.slrf_create.argtypes = [C.POINTER(_P), C.c_int64, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
                              C.c_int64, C.c_int32, C.POINTER(Options), _P]
 _lib.slrf_filter_apply.argtypes = [_P, C.POINTER(Poles), C.c_int64, _P, _P, C.POINTER(FilterStats)]
@@ -90,7 +92,8 @@ _lib.slrf_batch_remove.argtypes = [_P, C.c_int32]
 _lib.slrf_batch_destroy.argtypes = [_P]
 _lib.slrf_batch_last_error.argtypes = [_P]
 _lib.slrf_batch_last_error.restype = C.c_char_p
-for _f in ("slrf_design_poles", "slrf_workspace_bytes", "slrf_create", "slrf_filter_apply",
+for _f in ("slrf_design_poles", "slrf_workspace_bytes", "slrf_workspace_bytes_for", "slrf_create",
+           "slrf_filter_apply",
            "slrf_solve_interval", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
            "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove"):
     getattr(_lib, _f).restype = C.c_int
@@ -102,7 +105,8 @@ _lib.slrf_test_gemm.restype = C.c_int
 _lib.slrf_test_gram_scratch.argtypes = [C.c_int64, C.c_int64]
 _lib.slrf_test_gram_scratch.restype = C.c_size_t
 
-EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_workspace_bytes", "slrf_create",
+EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_workspace_bytes", "slrf_workspace_bytes_for",
+            "slrf_create",
             "slrf_filter_apply", "slrf_solve_interval", "slrf_destroy", "slrf_status_string",
             "slrf_last_error", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
             "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove",
@@ -167,9 +171,13 @@ def design_poles(N: int, alpha: float = 1.0, beta: float = 0.01, gamma: float = 
     return s[0::2] + 1j * s[1::2], w[0::2] + 1j * w[1::2], float(sep[0])
 
 
-def workspace_bytes(n: int, nnz: int, L: int, N: int, precision: int = FP64) -> int:
+def workspace_bytes(n: int, nnz: int, L: int, N: int, precision: int = FP64, options: Options | None = None) -> int:
+    """Workspace bytes of a Solver; with options, for their precision and preconditioner."""
     b = C.c_size_t()
-    st = _lib.slrf_workspace_bytes(n, nnz, L, N, precision, C.byref(b))
+    if options is None:
+        st = _lib.slrf_workspace_bytes(n, nnz, L, N, precision, C.byref(b))
+    else:
+        st = _lib.slrf_workspace_bytes_for(n, nnz, L, N, C.byref(options), C.byref(b))
     if st:
         raise SlrfError(st, "workspace size")
     return b.value
@@ -224,7 +232,7 @@ class Solver:
         self.n, nnz, arrs = _csr_arrays(A, B)
         self.device = torch.device(device)
         self.options = options or default_options()
-        self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, self.options.precision)
+        self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, options=self.options)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._h = C.c_void_p()

@@ -30,11 +30,13 @@ constexpr int kMaxGrid = 2048;  // largest grid of the Krylov kernels (a multipl
 constexpr int kCsrPad = 16;     // zero entries after the last CSR entry (whole-chunk reads)
 
 // One pencil of a batch as the Krylov kernels see it.  Its Krylov block is a
-// row-major (n, K) complex array, K = N * L, column c = j * L + l belonging to
-// pole j and right-hand side l.  Global columns of the batch are the pencils'
-// columns one after the other; global 64-column tiles likewise.
+// row-major (n, Kp) complex array, K = N * L, column c = j * L + l belonging to
+// pole j and right-hand side l (columns K..Kp-1 are padding).  Global columns of
+// the batch are the pencils' Kp columns one after the other; global tiles of
+// 64 V columns likewise.
 struct Inst {
   int n, K, L, N;        // rows, columns, right-hand sides, poles
+  int Kp;                // leading dimension of the (n, Kp) blocks: K rounded up to the lane width
   int nrb, slab, steps;  // row blocks, row blocks per XCD, steps per workgroup
   int col0, tile0;       // first global column and first global tile
   int nnz;
@@ -48,6 +50,7 @@ struct Inst {
   const int* sched;             // sparse-product row order, or null
   const int* diagpos;           // position of each row's diagonal (ILU)
   const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
+  const void* bjac;             // (N, n/3, 3, 3) cx<R> inverted node blocks, or null
 };
 
 // Kernel argument describing a whole batch (device tables).
@@ -58,9 +61,10 @@ struct Batch {
   int* active;            // [n_tiles] tiles that had an active column at the last poll
   int* n_active;          // [1] length of that list
   int n_tiles;
-  int Ktot;
+  int Ktot;               // global columns, each pencil padded to Kp
   int G;                  // grid, a multiple of 8
   int rows_per_block;
+  int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
 };
 
 // Krylov vectors: base pointers of the concatenated per-pencil blocks; per
@@ -126,8 +130,9 @@ void launch_init(hipStream_t s, const Batch& b, const KrylovState<R>& st, const 
 template <typename R>
 void launch_init_scalars(hipStream_t s, const Batch& b, const KrylovState<R>& st);
 template <typename R>
+// precs: 1 if some pencil uses ILU(0), 2 if some pencil uses node block Jacobi (or both)
 void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
-                      bool first, bool ilu, LaunchTimer* timer, const IterBytes& bytes);
+                      bool first, int precs, LaunchTimer* timer, const IterBytes& bytes);
 // out[0] = number of active columns; rebuilds the active-tile list of the batch.
 void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* out);
 
@@ -152,8 +157,9 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
                         const cx<R>* sigma, cx<R>* d, cx<R>* dinv);
+// U = sum_j 2 Re(w_j x[:, j L .. j L + L)), x row-major (n, ld)
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x,
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int ld, const cx<R>* x,
                        const double* w /* 2N */, double* U, bool accumulate);
 
 // real products with the merged pencil: AX = A X, BX = B X (either may be null)

@@ -30,13 +30,13 @@ void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* di
 
 // U[i, l] (+)= sum_j 2 Re(w_j x[i, j L + l])
 template <typename R>
-__global__ void k_filter_sum(int n, int L, int N, const cx<R>* __restrict__ x, const double* __restrict__ w,
-                             double* __restrict__ U, int accumulate) {
+__global__ void k_filter_sum(int n, int L, int N, int ld, const cx<R>* __restrict__ x,
+                             const double* __restrict__ w, double* __restrict__ U, int accumulate) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * L) return;
   const int64_t i = e / L;
   const int l = (int)(e % L);
-  const int64_t K = (int64_t)N * L;
+  const int64_t K = ld;
   double s = accumulate ? U[e] : 0.0;
   for (int j = 0; j < N; ++j) {
     const cx<R> y = x[i * K + (int64_t)j * L + l];
@@ -45,10 +45,11 @@ __global__ void k_filter_sum(int n, int L, int N, const cx<R>* __restrict__ x, c
   U[e] = s;
 }
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, const cx<R>* x, const double* w, double* U,
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int ld, const cx<R>* x, const double* w, double* U,
                        bool accumulate) {
   const int64_t tot = (int64_t)n * L;
-  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, x, w, U, accumulate ? 1 : 0);
+  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, ld, x, w, U,
+                                                                             accumulate ? 1 : 0);
 }
 
 // Real products of the merged pencil with a real block: one wavefront per row.
@@ -318,7 +319,7 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
 #define SLRF_INST(R)                                                                                          \
   template void launch_jacobi_diag<R>(hipStream_t, int, int, const R*, const R*, const cx<R>*, cx<R>*,     \
                                       cx<R>*);                                                              \
-  template void launch_filter_sum<R>(hipStream_t, int, int, int, const cx<R>*, const double*, double*,     \
+  template void launch_filter_sum<R>(hipStream_t, int, int, int, int, const cx<R>*, const double*, double*, \
                                      bool);                                                                 \
   template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \
                                     const double*, double*, double*);

@@ -1,24 +1,50 @@
 // Batched complex-shifted BiCGStab kernels (gfx950).
 //
 // One launch serves every pole x column of every pencil of a batch.  The
-// columns of the batch form a list of 64-column tiles, each tagged with its
-// pencil (Batch::tile_inst); the per-pencil sizes, block offsets and CSR
-// pointers live in a small device table (Inst).
+// columns of the batch form a list of tiles, each tagged with its pencil
+// (Batch::tile_inst); the per-pencil sizes, block offsets and CSR pointers live
+// in a small device table (Inst).
+//
+// Lane width.  A lane owns V adjacent columns: V = 1 for complex FP64 (16 B per
+// element), V = 2 for complex FP32, so that every gather and vector access moves
+// 16 B per lane in both precisions.  A tile is 64 V columns.  A pencil's blocks
+// are row-major (n, Kp) with Kp = K rounded up to a multiple of V; the padding
+// column has a zero right-hand side and is never active.
 //
 // Work decomposition: a grid of G workgroups of 256 threads (4 wavefronts of
-// 64) walks the tiles in order.  Within a tile each lane owns one column and
-// each wavefront walks every 4th row of its row blocks, so per-column dot
-// products accumulate in registers with no cross-lane traffic.  Workgroup b runs
-// on XCD b % 8 (round-robin dispatch).  XCD x owns the contiguous slab of row
-// blocks [x * slab, (x + 1) * slab) of the pencil, and its G / 8 workgroups
-// advance through the slab together (step t covers x * slab + t * G/8 + [0, G/8)),
-// so the rows in flight on one XCD stay close and the neighbours gathered by
-// the sparse product are re-read from that XCD's L2.  The 4 wavefronts are
-// combined through LDS and the G workgroups by per-column kernels that sum the
-// [G][Ktot] partials in a fixed order (bitwise reproducible).
+// 64) walks the tiles in order.  Within a tile each wavefront walks every 4th
+// row of its row blocks, so per-column dot products accumulate in registers with
+// no cross-lane traffic.  Workgroup b runs on XCD b % 8 (round-robin dispatch).
+// XCD x owns the contiguous slab of row blocks [x * slab, (x + 1) * slab) of the
+// pencil, and its G / 8 workgroups advance through the slab together (step t
+// covers x * slab + t * G/8 + [0, G/8)), so the rows in flight on one XCD stay
+// close and the neighbours gathered by the sparse product are re-read from that
+// XCD's L2.  The 4 wavefronts are combined through LDS and the G workgroups by
+// per-column kernels that sum the [G][Ktot] partials in a fixed order (bitwise
+// reproducible).
 #include "device_util.h"
 
 namespace slrf {
+
+template <typename R>
+struct LaneWidth {
+  static constexpr int V = sizeof(R) == 4 ? 2 : 1;
+};
+
+// V adjacent complex values of one row, loaded and stored as one 16 B access.
+template <typename R, int V>
+struct alignas(V * sizeof(cx<R>)) cvec {
+  cx<R> c[V];
+};
+
+template <typename R, int V>
+__device__ __forceinline__ cvec<R, V> ldv(const cx<R>* p) {
+  return *reinterpret_cast<const cvec<R, V>*>(p);
+}
+template <typename R, int V>
+__device__ __forceinline__ void stv(cx<R>* p, const cvec<R, V>& v) {
+  *reinterpret_cast<cvec<R, V>*>(p) = v;
+}
 
 struct WgPos {
   int x, q, per, lane, w;
@@ -42,10 +68,22 @@ __device__ __forceinline__ int step_block(const Inst& I, const WgPos& p, int t) 
   return rb < I.nrb ? rb : -1;
 }
 
+// Flags of the lane's V columns (-1 for columns past K).
+template <int V>
+__device__ __forceinline__ void lane_flags(const int* flags, int cg0, int cl0, int K, int (&f)[V]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) f[v] = cl0 + v < K ? flags[cg0 + v] : -1;
+}
+
 // true if any column of the tile is in one of the given states
-__device__ __forceinline__ bool tile_has(const int* flags, int cg, bool valid, int s0, int s1) {
-  const int f = valid ? flags[cg] : -1;
-  return __any(f == s0 || f == s1);
+template <int V>
+__device__ __forceinline__ bool tile_has(const int* flags, int cg0, int cl0, int K, int s0, int s1) {
+  int f[V];
+  lane_flags<V>(flags, cg0, cl0, K, f);
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < V; ++v) any |= f[v] == s0 || f[v] == s1;
+  return __any(any);
 }
 
 // one vector atomic per processed (workgroup, tile) when instrumented
@@ -53,43 +91,61 @@ __device__ __forceinline__ void count_tile(int* counter) {
   if (counter && threadIdx.x == 0) atomicAdd(counter, 1);
 }
 
-// Sum of the 4 wavefronts' per-lane values in a fixed order; lane l of wave 0
-// stores it at out[l] (out points at this workgroup's slice of the tile).
-template <typename T>
-__device__ __forceinline__ void wg_store_partial(T v, int w, int lane, bool valid, T* out) {
-  __shared__ T red[4][WAVE];
-  red[w][lane] = v;
+// Sums of the 4 wavefronts' per-lane values in a fixed order; lane l of wave 0
+// stores column v's sum at out[V l + v] (out points at this workgroup's slice of
+// the tile), for the columns before K.
+template <typename T, int V>
+__device__ __forceinline__ void wg_store_partial(const T (&v)[V], int w, int lane, int cl0, int K, T* out) {
+  __shared__ T red[4][V * WAVE];
+#pragma unroll
+  for (int u = 0; u < V; ++u) red[w][V * lane + u] = v[u];
   __syncthreads();
-  if (w == 0 && valid) out[lane] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-  __syncthreads();
-}
-
-template <typename R>
-__device__ __forceinline__ void wg_store_partial_cx(cx<R> v, int w, int lane, bool valid, cx<R>* out) {
-  __shared__ R rr[4][WAVE], ri[4][WAVE];
-  rr[w][lane] = v.re;
-  ri[w][lane] = v.im;
-  __syncthreads();
-  if (w == 0 && valid)
-    out[lane] = {rr[0][lane] + rr[1][lane] + rr[2][lane] + rr[3][lane],
-                 ri[0][lane] + ri[1][lane] + ri[2][lane] + ri[3][lane]};
+  if (w == 0) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = V * lane + u;
+      if (cl0 + u < K) out[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    }
+  }
   __syncthreads();
 }
 
-// Complex-shifted sparse product of one row over the merged CSR:
-//   q = sum_j (a_ij - sigma b_ij) P[j]      (A - sigma B is never formed)
-// The row's entries are taken in chunks of CH.  A chunk's CH column indices and
-// (a, b) pairs are contiguous, wave-uniform reads (wide scalar loads; the CSR
-// arrays carry kCsrPad zero entries at the end so a chunk never leaves them),
-// then CH gathers are issued back to back, then the FMAs.  Entries past the row
-// end get zero coefficients and re-read the row's own column; lanes past K read
-// a clamped column (both stay in bounds; their contributions are discarded).
-template <typename R, int CH>
-__device__ __forceinline__ cx<R> shifted_row(int i, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
-                                             const cx<R>* __restrict__ Pc, int K, cx<R> sig) {
+template <typename R, int V>
+__device__ __forceinline__ void wg_store_partial_cx(const cx<R> (&v)[V], int w, int lane, int cl0, int K,
+                                                    cx<R>* out) {
+  __shared__ R rr[4][V * WAVE], ri[4][V * WAVE];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    rr[w][V * lane + u] = v[u].re;
+    ri[w][V * lane + u] = v[u].im;
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = V * lane + u;
+      if (cl0 + u < K)
+        out[k] = {rr[0][k] + rr[1][k] + rr[2][k] + rr[3][k], ri[0][k] + ri[1][k] + ri[2][k] + ri[3][k]};
+    }
+  }
+  __syncthreads();
+}
+
+// Complex-shifted sparse product of one row over the merged CSR, for the lane's
+// V columns:  q_v = sum_j (a_ij - sigma_v b_ij) P[j][v]   (A - sigma B is never
+// formed).  The row's entries are taken in chunks of CH.  A chunk's CH column
+// indices and (a, b) pairs are contiguous, wave-uniform reads (wide scalar
+// loads; the CSR arrays carry kCsrPad zero entries at the end so a chunk never
+// leaves them), then CH gathers of 16 B per lane are issued back to back, then
+// the FMAs.  Entries past the row end get zero coefficients and re-read the
+// row's own column; lanes past K read a clamped column (both stay in bounds;
+// their contributions are discarded).
+template <typename R, int V, int CH>
+__device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
+                                                  const cx<R>* __restrict__ Pc, int Kp, const cx<R> (&sig)[V]) {
   static_assert(CH <= kCsrPad, "chunk longer than the CSR padding");
   const int k0 = rowptr[i], k1 = rowptr[i + 1];
-  R apr = 0, api = 0, bpr = 0, bpi = 0;
+  R apr[V] = {}, api[V] = {}, bpr[V] = {}, bpi[V] = {};
   for (int kb = k0; kb < k1; kb += CH) {
     int jj[CH];
     ab_pair<R> m[CH];
@@ -105,39 +161,48 @@ __device__ __forceinline__ cx<R> shifted_row(int i, cptr<int> rowptr, cptr<int> 
         m[u] = ab_pair<R>{0, 0};
       }
     }
-    cx<R> x[CH];
+    cvec<R, V> x[CH];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) x[u] = Pc[(size_t)jj[u] * K];
+    for (int u = 0; u < CH; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * Kp);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      apr += m[u].a * x[u].re;
-      api += m[u].a * x[u].im;
-      bpr += m[u].b * x[u].re;
-      bpi += m[u].b * x[u].im;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        apr[v] += m[u].a * x[u].c[v].re;
+        api[v] += m[u].a * x[u].c[v].im;
+        bpr[v] += m[u].b * x[u].c[v].re;
+        bpi[v] += m[u].b * x[u].c[v].im;
+      }
     }
   }
-  return {apr - (sig.re * bpr - sig.im * bpi), api - (sig.re * bpi + sig.im * bpr)};
+  cvec<R, V> q;
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    q.c[v] = {apr[v] - (sig[v].re * bpr[v] - sig[v].im * bpi[v]),
+              api[v] - (sig[v].re * bpi[v] + sig[v].im * bpr[v])};
+  return q;
 }
 
 constexpr int kChunk = 16;
 
-// Loop header shared by the batched kernels: tile tg of pencil I; cl is the
-// lane's column within the pencil, cc that column clamped into range, cg the
-// global column.  FOR_TILES walks every tile; FOR_ACTIVE_TILES walks the list of
-// tiles that had an active column at the last poll (the iteration kernels).
-#define FOR_TILE_LIST(b, p, COUNT, TG)                                \
-  for (int ti_ = 0; ti_ < (COUNT); ++ti_) {                           \
-    const int tg = (TG);                                              \
-    const Inst I = ldc(as_const((b).inst) + as_const((b).tile_inst)[tg]); \
-    const int cl = (tg - I.tile0) * WAVE + (p).lane;                  \
-    const bool valid = cl < I.K;                                      \
-    const int cc = min(cl, I.K - 1);                                  \
-    const int cg = I.col0 + cc;                                       \
-    const size_t po = (size_t)blockIdx.x * (b).Ktot + I.col0 + (size_t)(tg - I.tile0) * WAVE;
+// Loop header shared by the batched kernels: tile tg of pencil I.  cl0 is the
+// lane's first column within the pencil (a multiple of V), cc0 that column
+// clamped into the padded range, cg0 its global column; column v of the lane is
+// real if cl0 + v < I.K.  FOR_TILES walks every tile; FOR_ACTIVE_TILES walks the
+// list of tiles that had an active column at the last poll (iteration kernels).
+#define FOR_TILE_LIST(b, p, V, COUNT, TG)                                    \
+  for (int ti_ = 0; ti_ < (COUNT); ++ti_) {                                  \
+    const int tg = (TG);                                                     \
+    const Inst I = ldc(as_const((b).inst) + as_const((b).tile_inst)[tg]);    \
+    const int cl0 = (tg - I.tile0) * (WAVE * (V)) + (p).lane * (V);          \
+    const bool valid = cl0 < I.K;                                            \
+    const int cc0 = min(cl0, I.Kp - (V));                                    \
+    const int cg0 = I.col0 + cc0;                                            \
+    const size_t po = (size_t)blockIdx.x * (b).Ktot + I.col0 + (size_t)(tg - I.tile0) * (WAVE * (V));
 
-#define FOR_TILES(b, p) FOR_TILE_LIST(b, p, (b).n_tiles, ti_)
-#define FOR_ACTIVE_TILES(b, p) \
-  FOR_TILE_LIST(b, p, as_const((const int*)(b).n_active)[0], as_const((const int*)(b).active)[ti_])
+#define FOR_TILES(b, p, V) FOR_TILE_LIST(b, p, V, (b).n_tiles, ti_)
+#define FOR_ACTIVE_TILES(b, p, V) \
+  FOR_TILE_LIST(b, p, V, as_const((const int*)(b).n_active)[0], as_const((const int*)(b).active)[ti_])
 
 #define FOR_ROWS(b, p, I)                                               \
   for (int t_ = 0; t_ < (I).steps; ++t_) {                              \
@@ -153,122 +218,206 @@ constexpr int kChunk = 16;
 // v = S p_hat, partial (rhat, v)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_ACTIVE_TILES(b, p)
-    R dr = 0, di = 0;
-    if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
+  FOR_ACTIVE_TILES(b, p, V)
+    cx<R> d[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
-      const cx<R> sig = st.sigma_col[cg];
-      const int l = cc % I.L;
+      cx<R> sig[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
       const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
       FOR_ROWS(b, p, I)
         const int i = I.sched ? as_const(I.sched)[pos] : pos;
-        const size_t e = I.blk + (size_t)i * I.K + cc;
-        const cx<R> q = shifted_row<R, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
-                                               st.ph + I.blk + cc, I.K, sig);
+        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        const cvec<R, V> q = shifted_row<R, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
+                                                       st.ph + I.blk + cc0, I.Kp, sig);
         if (valid) {
-          st.v[e] = q;
+          stv<R, V>(st.v + e, q);
           if (st.rhat_cx) {  // conj(rhat) * v
-            const cx<R> rh = st.rhat_cx[e];
-            dr += rh.re * q.re + rh.im * q.im;
-            di += rh.re * q.im - rh.im * q.re;
+            const cvec<R, V> rh = ldv<R, V>(st.rhat_cx + e);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              d[v].re += rh.c[v].re * q.c[v].re + rh.c[v].im * q.c[v].im;
+              d[v].im += rh.c[v].re * q.c[v].im - rh.c[v].im * q.c[v].re;
+            }
           } else {
-            const R rh = st.rhat[I.rl + (size_t)i * I.L + l];
-            dr += rh * q.re;
-            di += rh * q.im;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              const R rh = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
+              d[v].re += rh * q.c[v].re;
+              d[v].im += rh * q.c[v].im;
+            }
           }
         }
       END_ROWS
     }
-    wg_store_partial_cx<R>({dr, di}, p.w, p.lane, valid, st.part_a + po);
+    wg_store_partial_cx<R, V>(d, p.w, p.lane, cl0, I.K, st.part_a + po);
   }
 }
 
 // t = S s_hat, partials (t, s) = t^H s and (t, t)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_ACTIVE_TILES(b, p)
-    R tsr = 0, tsi = 0, tt = 0;
-    if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
+  FOR_ACTIVE_TILES(b, p, V)
+    cx<R> ts[V] = {};
+    R tt[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
-      const cx<R> sig = st.sigma_col[cg];
-      const int pole = cc / I.L;
+      cx<R> sig[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
       const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
       FOR_ROWS(b, p, I)
         const int i = I.sched ? as_const(I.sched)[pos] : pos;
-        const cx<R> tv = shifted_row<R, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
-                                                st.sh + I.blk + cc, I.K, sig);
+        const cvec<R, V> tv = shifted_row<R, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
+                                                        st.sh + I.blk + cc0, I.Kp, sig);
         if (valid) {
-          const size_t e = I.blk + (size_t)i * I.K + cc;
-          st.t[e] = tv;
-          const cx<R> s = st.s ? st.s[e] : cmul(st.d[I.dn + (size_t)i * I.N + pole], st.sh[e]);
-          tsr += tv.re * s.re + tv.im * s.im;  // conj(t) * s
-          tsi += tv.re * s.im - tv.im * s.re;
-          tt += tv.re * tv.re + tv.im * tv.im;
+          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+          stv<R, V>(st.t + e, tv);
+          cvec<R, V> sv;
+          if (st.s) {
+            sv = ldv<R, V>(st.s + e);
+          } else {
+            const cvec<R, V> shv = ldv<R, V>(st.sh + e);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+              sv.c[v] = cmul(st.d[I.dn + (size_t)i * I.N + min((cc0 + v) / I.L, I.N - 1)], shv.c[v]);
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const cx<R> t = tv.c[v], s = sv.c[v];
+            ts[v].re += t.re * s.re + t.im * s.im;  // conj(t) * s
+            ts[v].im += t.re * s.im - t.im * s.re;
+            tt[v] += t.re * t.re + t.im * t.im;
+          }
         }
       END_ROWS
     }
-    wg_store_partial_cx<R>({tsr, tsi}, p.w, p.lane, valid, st.part_a + po);
-    wg_store_partial<R>(tt, p.w, p.lane, valid, st.part_b + po);
+    wg_store_partial_cx<R, V>(ts, p.w, p.lane, cl0, I.K, st.part_a + po);
+    wg_store_partial<R, V>(tt, p.w, p.lane, cl0, I.K, st.part_b + po);
   }
 }
 
 // p = r + beta (p - omega v)  (first iteration: p = r).
 // Jacobi batch: p itself is not stored; p_hat = p / d with p = d p_hat.
-// Batch with ILU(0) pencils: p is stored; the ILU kernel forms p_hat for those
-// pencils, and Jacobi pencils of the same batch form p_hat = p / d here.
+// Batch with ILU(0) or block-Jacobi pencils: p is stored; their kernels form
+// p_hat for those pencils, and Jacobi pencils of the same batch form
+// p_hat = p / d here.  Columns that are not active keep their values.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int first, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_ACTIVE_TILES(b, p)
+  FOR_ACTIVE_TILES(b, p, V)
     (void)po;
-    if (!tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) continue;
+    if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) continue;
     count_tile(counter);
-    if (!valid || st.flags[cg] != COL_ACTIVE) continue;
-    const int pole = cc / I.L;
-    const cx<R> beta = st.beta[cg], omega = st.omega[cg];
+    int f[V];
+    lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+    bool any = false;
+    int pole[V];
+    cx<R> beta[V], omega[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      any |= f[v] == COL_ACTIVE;
+      pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      beta[v] = st.beta[cg0 + v];
+      omega[v] = st.omega[cg0 + v];
+    }
+    if (!any) continue;
+    bool keep = false;  // some column of the lane is not updated: its old values are stored back
+#pragma unroll
+    for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
+    const bool jac_here = !I.ilu && !I.bjac;
     FOR_ROWS(b, p, I)
       const int i = pos;
-      const size_t e = I.blk + (size_t)i * I.K + cc;
-      cx<R> pn = st.r[e];
+      const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+      const size_t de = I.dn + (size_t)i * I.N;
+      const cvec<R, V> r = ldv<R, V>(st.r + e);
       if (st.p) {
-        if (!first) pn = cadd(pn, cmul(beta, csub(st.p[e], cmul(omega, st.v[e]))));
-        st.p[e] = pn;
-        if (!I.ilu) st.ph[e] = cmul(pn, st.dinv[I.dn + (size_t)i * I.N + pole]);
+        cvec<R, V> pv, vv, ph;
+        if (!first || keep) pv = ldv<R, V>(st.p + e);
+        if (!first) vv = ldv<R, V>(st.v + e);
+        if (jac_here && keep) ph = ldv<R, V>(st.ph + e);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (f[v] != COL_ACTIVE) continue;
+          cx<R> pn = r.c[v];
+          if (!first) pn = cadd(pn, cmul(beta[v], csub(pv.c[v], cmul(omega[v], vv.c[v]))));
+          pv.c[v] = pn;
+          if (jac_here) ph.c[v] = cmul(pn, st.dinv[de + pole[v]]);
+        }
+        stv<R, V>(st.p + e, pv);
+        if (jac_here) stv<R, V>(st.ph + e, ph);
       } else {
-        const size_t de = I.dn + (size_t)i * I.N + pole;
-        if (!first) pn = cadd(pn, cmul(beta, csub(cmul(st.d[de], st.ph[e]), cmul(omega, st.v[e]))));
-        st.ph[e] = cmul(pn, st.dinv[de]);
+        cvec<R, V> ph, vv;
+        if (!first || keep) ph = ldv<R, V>(st.ph + e);
+        if (!first) vv = ldv<R, V>(st.v + e);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (f[v] != COL_ACTIVE) continue;
+          cx<R> pn = r.c[v];
+          if (!first) pn = cadd(pn, cmul(beta[v], csub(cmul(st.d[de + pole[v]], ph.c[v]), cmul(omega[v], vv.c[v]))));
+          ph.c[v] = cmul(pn, st.dinv[de + pole[v]]);
+        }
+        stv<R, V>(st.ph + e, ph);
       }
     END_ROWS
   }
 }
 
 // s = r - alpha v (Jacobi batch: s_hat = s / d is stored instead; in a batch
-// with ILU(0) pencils s is stored, plus s_hat = s / d for its Jacobi pencils) ;
-// partial |s|^2
+// with ILU(0) or block-Jacobi pencils s is stored, plus s_hat = s / d for its
+// Jacobi pencils) ; partial |s|^2
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_ACTIVE_TILES(b, p)
-    R ss = 0;
-    if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_ACTIVE)) {
+  FOR_ACTIVE_TILES(b, p, V)
+    R ss[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
       count_tile(counter);
-      if (valid && st.flags[cg] == COL_ACTIVE) {
-        const int pole = cc / I.L;
-        const cx<R> alpha = st.alpha[cg];
+      int f[V];
+      lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+      bool any = false;
+      int pole[V];
+      cx<R> alpha[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        any |= f[v] == COL_ACTIVE;
+        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        alpha[v] = st.alpha[cg0 + v];
+      }
+      if (any) {
+        bool keep = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
+        const bool jac_here = !st.s || (!I.ilu && !I.bjac);
         FOR_ROWS(b, p, I)
           const int i = pos;
-          const size_t e = I.blk + (size_t)i * I.K + cc;
-          const cx<R> s = csub(st.r[e], cmul(alpha, st.v[e]));
-          ss += s.re * s.re + s.im * s.im;
-          if (st.s) st.s[e] = s;
-          if (!st.s || !I.ilu) st.sh[e] = cmul(s, st.dinv[I.dn + (size_t)i * I.N + pole]);
+          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+          const size_t de = I.dn + (size_t)i * I.N;
+          const cvec<R, V> r = ldv<R, V>(st.r + e), vv = ldv<R, V>(st.v + e);
+          cvec<R, V> sv, sh;
+          if (st.s && keep) sv = ldv<R, V>(st.s + e);
+          if (jac_here && keep) sh = ldv<R, V>(st.sh + e);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (f[v] != COL_ACTIVE) continue;
+            const cx<R> s = csub(r.c[v], cmul(alpha[v], vv.c[v]));
+            ss[v] += s.re * s.re + s.im * s.im;
+            sv.c[v] = s;
+            if (jac_here) sh.c[v] = cmul(s, st.dinv[de + pole[v]]);
+          }
+          if (st.s) stv<R, V>(st.s + e, sv);
+          if (jac_here) stv<R, V>(st.sh + e, sh);
         END_ROWS
       }
     }
-    wg_store_partial<R>(ss, p.w, p.lane, valid, st.part_b + po);
+    wg_store_partial<R, V>(ss, p.w, p.lane, cl0, I.K, st.part_b + po);
   }
 }
 
@@ -276,75 +425,121 @@ __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int
 // Columns that converged at the half step take x += alpha p_hat only.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_update_x(Batch b, KrylovState<R> st, int first, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_ACTIVE_TILES(b, p)
-    R rr = 0, ri = 0, nn = 0;
-    if (tile_has(st.flags, cg, valid, COL_ACTIVE, COL_HALF_PENDING)) {
+  FOR_ACTIVE_TILES(b, p, V)
+    cx<R> rd[V] = {};
+    R nn[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_HALF_PENDING)) {
       count_tile(counter);
-      const int f = valid ? st.flags[cg] : -1;
-      const bool act = f == COL_ACTIVE, half = f == COL_HALF_PENDING;
-      if (act || half) {
-        const int pole = cc / I.L;
-        const int l = cc % I.L;
-        const cx<R> alpha = st.alpha[cg];
-        const cx<R> omega = act ? st.omega[cg] : cx<R>{0, 0};
+      int f[V];
+      lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+      bool act[V], half[V], any = false;
+      int pole[V];
+      cx<R> alpha[V], omega[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        act[v] = f[v] == COL_ACTIVE;
+        half[v] = f[v] == COL_HALF_PENDING;
+        any |= act[v] || half[v];
+        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        alpha[v] = st.alpha[cg0 + v];
+        omega[v] = act[v] ? st.omega[cg0 + v] : cx<R>{0, 0};
+      }
+      if (any) {
+        bool keep_x = false, keep_r = false, any_act = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          keep_x |= !act[v] && !half[v];
+          keep_r |= !act[v];
+          any_act |= act[v];
+        }
         FOR_ROWS(b, p, I)
           const int i = pos;
-          const size_t e = I.blk + (size_t)i * I.K + cc;
-          cx<R> x = first ? cx<R>{0, 0} : st.x[e];
-          x = cadd(x, cmul(alpha, st.ph[e]));
-          if (act) {
-            const cx<R> sh = st.sh[e];
-            x = cadd(x, cmul(omega, sh));
-            const cx<R> sv = st.s ? st.s[e] : cmul(st.d[I.dn + (size_t)i * I.N + pole], sh);
-            const cx<R> r = csub(sv, cmul(omega, st.t[e]));
-            st.r[e] = r;
-            if (st.rhat_cx) {
-              const cx<R> rh = st.rhat_cx[e];
-              rr += rh.re * r.re + rh.im * r.im;
-              ri += rh.re * r.im - rh.im * r.re;
-            } else {
-              const R rh = st.rhat[I.rl + (size_t)i * I.L + l];
-              rr += rh * r.re;
-              ri += rh * r.im;
+          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+          const size_t de = I.dn + (size_t)i * I.N;
+          cvec<R, V> x;
+          if (first && !keep_x) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x.c[v] = {0, 0};
+          } else {
+            x = ldv<R, V>(st.x + e);
+            if (first) {
+#pragma unroll
+              for (int v = 0; v < V; ++v)
+                if (act[v] || half[v]) x.c[v] = {0, 0};
             }
-            nn += r.re * r.re + r.im * r.im;
           }
-          st.x[e] = x;
+          const cvec<R, V> ph = ldv<R, V>(st.ph + e);
+          cvec<R, V> sh, t, r, sv, rh;
+          if (any_act) {
+            sh = ldv<R, V>(st.sh + e);
+            t = ldv<R, V>(st.t + e);
+            if (st.s) sv = ldv<R, V>(st.s + e);
+            if (st.rhat_cx) rh = ldv<R, V>(st.rhat_cx + e);
+          }
+          if (keep_r) r = ldv<R, V>(st.r + e);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (!act[v] && !half[v]) continue;
+            x.c[v] = cadd(x.c[v], cmul(alpha[v], ph.c[v]));
+            if (!act[v]) continue;
+            x.c[v] = cadd(x.c[v], cmul(omega[v], sh.c[v]));
+            const cx<R> s = st.s ? sv.c[v] : cmul(st.d[de + pole[v]], sh.c[v]);
+            const cx<R> rv = csub(s, cmul(omega[v], t.c[v]));
+            r.c[v] = rv;
+            if (st.rhat_cx) {
+              rd[v].re += rh.c[v].re * rv.re + rh.c[v].im * rv.im;
+              rd[v].im += rh.c[v].re * rv.im - rh.c[v].im * rv.re;
+            } else {
+              const R rr = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
+              rd[v].re += rr * rv.re;
+              rd[v].im += rr * rv.im;
+            }
+            nn[v] += rv.re * rv.re + rv.im * rv.im;
+          }
+          if (any_act) stv<R, V>(st.r + e, r);
+          stv<R, V>(st.x + e, x);
         END_ROWS
       }
     }
-    wg_store_partial_cx<R>({rr, ri}, p.w, p.lane, valid, st.part_a + po);
-    wg_store_partial<R>(nn, p.w, p.lane, valid, st.part_b + po);
+    wg_store_partial_cx<R, V>(rd, p.w, p.lane, cl0, I.K, st.part_a + po);
+    wg_store_partial<R, V>(nn, p.w, p.lane, cl0, I.K, st.part_b + po);
   }
 }
 
 // x = 0, r = f (broadcast over poles); partials of ||f||^2
 template <typename R>
 __global__ __launch_bounds__(WG) void k_init(Batch b, KrylovState<R> st, const R* __restrict__ F) {
+  constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
-    R nn = 0;
+  FOR_TILES(b, p, V)
+    R nn[V] = {};
     if (valid) {
-      const int l = cc % I.L;
       FOR_ROWS(b, p, I)
         const int i = pos;
-        const R f = F[I.rl + (size_t)i * I.L + l];
-        const size_t e = I.blk + (size_t)i * I.K + cc;
-        st.r[e] = {f, 0};
-        st.x[e] = {0, 0};
-        nn += f * f;
+        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        cvec<R, V> r, x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const R fv = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L] : R(0);
+          r.c[v] = {fv, 0};
+          x.c[v] = {0, 0};
+          nn[v] += fv * fv;
+        }
+        stv<R, V>(st.r + e, r);
+        stv<R, V>(st.x + e, x);
       END_ROWS
     }
-    wg_store_partial<R>(nn, p.w, p.lane, valid, st.part_b + po);
+    wg_store_partial<R, V>(nn, p.w, p.lane, cl0, I.K, st.part_b + po);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Per-column scalar kernels: one 256-thread block per global tile.  The sum
-// over the G partials is split across the 4 wavefronts (partials w, w + 4, ...,
-// loads kept in flight by unrolling) and combined in a fixed order; wavefront 0
-// then applies the update.
+// Per-column scalar kernels: one 256-thread block per global tile, each lane
+// handling V columns.  The sum over the G partials is split across the 4
+// wavefronts (partials w, w + 4, ..., loads kept in flight by unrolling) and
+// combined in a fixed order; wavefront 0 then applies the update.
 template <typename T>
 __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int Ktot, int c, bool valid) {
   __shared__ T red[4][WAVE];
@@ -386,106 +581,138 @@ __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int 
 template <typename R>
 __device__ __forceinline__ bool cfinite(cx<R> z) { return isfinite(z.re) && isfinite(z.im); }
 
-#define SC_PROLOGUE                                         \
-  const Inst I = ldc(as_const(b.inst) + as_const(b.tile_inst)[blockIdx.x]); \
-  const int cl = (blockIdx.x - I.tile0) * WAVE + lane_id(); \
-  const bool valid = cl < I.K;                              \
-  const int c = I.col0 + min(cl, I.K - 1);                  \
-  const bool lead = wave_id() == 0 && valid;
+// lane's first column (cl0), its global column (cg0), and the wavefront that
+// applies the per-column updates
+#define SC_PROLOGUE(V)                                                        \
+  const Inst I = ldc(as_const(b.inst) + as_const(b.tile_inst)[blockIdx.x]);   \
+  const int cl0 = (blockIdx.x - I.tile0) * (WAVE * (V)) + lane_id() * (V);    \
+  const int cg0 = I.col0 + min(cl0, I.Kp - (V));                              \
+  const bool lead = wave_id() == 0;
 
 // alpha = rho / (rhat, v)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_alpha(Batch b, KrylovState<R> st) {
-  SC_PROLOGUE
-  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
-  const cx<R> rv = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
-  if (!lead || st.flags[c] != COL_ACTIVE) return;
-  const cx<R> rho = st.rho[c];
-  if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
-    st.flags[c] = COL_BREAKDOWN;
-    return;
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const cx<R> rv = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
+    if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
+    const cx<R> rho = st.rho[c];
+    if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
+      st.flags[c] = COL_BREAKDOWN;
+      continue;
+    }
+    st.alpha[c] = cdiv(rho, rv);
+    st.iters[c] += 1;
   }
-  st.alpha[c] = cdiv(rho, rv);
-  st.iters[c] += 1;
 }
 
 // half-step test ||s|| <= tol ||f||
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_half(Batch b, KrylovState<R> st, R tol) {
-  SC_PROLOGUE
-  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
-  const R sn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, valid));
-  if (!lead || st.flags[c] != COL_ACTIVE) return;
-  if (sn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
-    st.flags[c] = COL_HALF_PENDING;
-    st.rnorm[c] = sn;
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const R sn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, ok));
+    if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
+    if (sn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
+      st.flags[c] = COL_HALF_PENDING;
+      st.rnorm[c] = sn;
+    }
   }
 }
 
 // omega = (t, s) / (t, t)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_omega(Batch b, KrylovState<R> st) {
-  SC_PROLOGUE
-  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_ACTIVE)) return;
-  const cx<R> ts = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
-  const R tt = block_col_sum(st.part_b, b.G, b.Ktot, c, valid);
-  if (!lead || st.flags[c] != COL_ACTIVE) return;
-  if (tt == 0 || !isfinite(tt)) {
-    st.flags[c] = COL_BREAKDOWN;
-    return;
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const cx<R> ts = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
+    const R tt = block_col_sum(st.part_b, b.G, b.Ktot, c, ok);
+    if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
+    if (tt == 0 || !isfinite(tt)) {
+      st.flags[c] = COL_BREAKDOWN;
+      continue;
+    }
+    st.omega[c] = {ts.re / tt, ts.im / tt};
   }
-  st.omega[c] = {ts.re / tt, ts.im / tt};
 }
 
 // rho_new = (rhat, r); ||r|| test; beta = (rho_new / rho)(alpha / omega)
 template <typename R>
 __global__ __launch_bounds__(WG) void k_sc_beta(Batch b, KrylovState<R> st, R tol, int maxit) {
-  SC_PROLOGUE
-  if (!tile_has(st.flags, c, valid, COL_ACTIVE, COL_HALF_PENDING)) return;
-  const cx<R> rn = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, valid);
-  const R nn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, valid));
-  if (!lead) return;
-  const int f = st.flags[c];
-  if (f == COL_HALF_PENDING) {
-    st.flags[c] = COL_HALF_CONVERGED;
-    return;
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_HALF_PENDING)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const cx<R> rn = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
+    const R nn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, ok));
+    if (!lead || !ok) continue;
+    const int f = st.flags[c];
+    if (f == COL_HALF_PENDING) {
+      st.flags[c] = COL_HALF_CONVERGED;
+      continue;
+    }
+    if (f != COL_ACTIVE) continue;
+    st.rnorm[c] = nn;
+    if (nn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
+      st.flags[c] = COL_CONVERGED;
+      continue;
+    }
+    if (st.iters[c] >= maxit) {
+      st.flags[c] = COL_MAXIT;
+      continue;
+    }
+    const cx<R> om = st.omega[c];
+    if ((om.re == 0 && om.im == 0) || !cfinite(rn)) {
+      st.flags[c] = COL_BREAKDOWN;
+      continue;
+    }
+    st.beta[c] = cmul(cdiv(rn, st.rho[c]), cdiv(st.alpha[c], om));
+    st.rho[c] = rn;
   }
-  if (f != COL_ACTIVE) return;
-  st.rnorm[c] = nn;
-  if (nn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
-    st.flags[c] = COL_CONVERGED;
-    return;
-  }
-  if (st.iters[c] >= maxit) {
-    st.flags[c] = COL_MAXIT;
-    return;
-  }
-  const cx<R> om = st.omega[c];
-  if ((om.re == 0 && om.im == 0) || !cfinite(rn)) {
-    st.flags[c] = COL_BREAKDOWN;
-    return;
-  }
-  st.beta[c] = cmul(cdiv(rn, st.rho[c]), cdiv(st.alpha[c], om));
-  st.rho[c] = rn;
 }
 
+// Per-column start values; padding columns (past K) are marked converged.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_init_scalars(Batch b, KrylovState<R> st) {
-  SC_PROLOGUE
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
   if (threadIdx.x == 0) {  // every tile starts on the active list
     b.active[blockIdx.x] = blockIdx.x;
     if (blockIdx.x == 0) b.n_active[0] = b.n_tiles;
   }
-  const R nn = block_col_sum(st.part_b, b.G, b.Ktot, c, valid);
-  if (!lead) return;
-  st.fnorm[c] = sqrt(nn);
-  st.rnorm[c] = sqrt(nn);
-  st.rho[c] = {nn, 0};
-  st.alpha[c] = {1, 0};
-  st.omega[c] = {1, 0};
-  st.beta[c] = {0, 0};
-  st.iters[c] = 0;
-  st.flags[c] = nn == 0 ? COL_CONVERGED : COL_ACTIVE;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const R nn = block_col_sum(st.part_b, b.G, b.Ktot, c, ok);
+    if (!lead || cl0 + v >= I.Kp) continue;
+    st.fnorm[c] = sqrt(nn);
+    st.rnorm[c] = sqrt(nn);
+    st.rho[c] = {nn, 0};
+    st.alpha[c] = {1, 0};
+    st.omega[c] = {1, 0};
+    st.beta[c] = {0, 0};
+    st.iters[c] = 0;
+    st.flags[c] = (nn == 0 || !ok) ? COL_CONVERGED : COL_ACTIVE;
+  }
 }
 
 // out = (L U)^{-1} in, one thread per global column: forward then backward
@@ -500,33 +727,79 @@ __global__ __launch_bounds__(64) void k_ilu_apply(Batch b, const int* __restrict
   const Inst I = b.inst[b.col_inst[cg]];
   if (!I.ilu) return;
   const int c = cg - I.col0;
+  if (c >= I.K) return;
   const cx<R>* f = static_cast<const cx<R>*>(I.ilu) + (size_t)(c / I.L) * I.nnz;
   const cx<R>* src = in + I.blk + c;
   cx<R>* dst = out + I.blk + c;
+  const size_t ld = (size_t)I.Kp;
   cx<R> prev = {0, 0};
   for (int i = 0; i < I.n; ++i) {
-    cx<R> y = src[(size_t)i * I.K];
+    cx<R> y = src[(size_t)i * ld];
     const int kd = I.diagpos[i];
     for (int k = I.rowptr[i]; k < kd; ++k) {
       const int j = I.col[k];
-      const cx<R> yj = (j == i - 1) ? prev : dst[(size_t)j * I.K];
+      const cx<R> yj = (j == i - 1) ? prev : dst[(size_t)j * ld];
       y = csub(y, cmul(f[k], yj));
     }
-    dst[(size_t)i * I.K] = y;
+    dst[(size_t)i * ld] = y;
     prev = y;
   }
   prev = {0, 0};
   for (int i = I.n - 1; i >= 0; --i) {
-    cx<R> z = dst[(size_t)i * I.K];
+    cx<R> z = dst[(size_t)i * ld];
     const int kd = I.diagpos[i];
     for (int k = kd + 1; k < I.rowptr[i + 1]; ++k) {
       const int j = I.col[k];
-      const cx<R> zj = (j == i + 1) ? prev : dst[(size_t)j * I.K];
+      const cx<R> zj = (j == i + 1) ? prev : dst[(size_t)j * ld];
       z = csub(z, cmul(f[k], zj));
     }
     z = cmul(z, f[kd]);
-    dst[(size_t)i * I.K] = z;
+    dst[(size_t)i * ld] = z;
     prev = z;
+  }
+}
+
+// out = M^{-1} in for node block Jacobi: unknowns 3k, 3k+1, 3k+2 form node k and
+// M_k^{-1} (3x3, per pole) multiplies them.  One thread per (node, V columns);
+// only active columns of pencils that use block Jacobi are written.
+template <typename R>
+__global__ __launch_bounds__(WG) void k_bjac_apply(Batch b, const int* __restrict__ flags,
+                                                  const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+  constexpr int V = LaneWidth<R>::V;
+  const WgPos p = wg_pos(b.G);
+  FOR_ACTIVE_TILES(b, p, V)
+    (void)po;
+    if (!I.bjac || !valid) continue;
+    int f[V];
+    lane_flags<V>(flags, cg0, cl0, I.K, f);
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) any |= f[v] == COL_ACTIVE;
+    if (!any) continue;
+    bool keep = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
+    const int nodes = I.n / 3;
+    const size_t stride = (size_t)I.Kp;
+    for (int k = blockIdx.x * 4 + p.w; k < nodes; k += b.G * 4) {
+      const size_t e0 = I.blk + (size_t)(3 * k) * stride + cc0;
+      const cvec<R, V> x0 = ldv<R, V>(in + e0), x1 = ldv<R, V>(in + e0 + stride), x2 = ldv<R, V>(in + e0 + 2 * stride);
+      cvec<R, V> y[3];
+      if (keep)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) y[r] = ldv<R, V>(out + e0 + r * stride);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (f[v] != COL_ACTIVE) continue;
+        const cx<R>* m = static_cast<const cx<R>*>(I.bjac) +
+                         ((size_t)((cc0 + v) / I.L) * nodes + (size_t)k) * 9;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          y[r].c[v] = cadd(cadd(cmul(m[3 * r], x0.c[v]), cmul(m[3 * r + 1], x1.c[v])), cmul(m[3 * r + 2], x2.c[v]));
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) stv<R, V>(out + e0 + r * stride, y[r]);
+    }
   }
 }
 
@@ -543,7 +816,8 @@ void LaunchTimer::end(hipStream_t s) {
 
 template <typename R>
 void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit, bool first,
-                      bool ilu, LaunchTimer* tm, const IterBytes& by) {
+                      int precs, LaunchTimer* tm, const IterBytes& by) {
+  const bool ilu = precs & 1, bjac = precs & 2;
   const dim3 grid((unsigned)b.G), blk(WG);
   const dim3 cgrid((unsigned)b.n_tiles), cblk(WG);
   const dim3 igrid((unsigned)((b.Ktot + 63) / 64)), iblk(64);
@@ -554,6 +828,7 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   k_update_p<R><<<grid, blk, 0, s>>>(b, st, first ? 1 : 0, c);
   if (c) tm->end(s);
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(b, st.flags, st.p, st.ph);
+  if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.p, st.ph);
   // v = S p_hat: gather p_hat once, write v, read rhat; the merged CSR once per launch
   c = tm ? tm->begin(s, 0, 2 * by.blk + by.rhat, by.matrix) : nullptr;
   k_spmm_v<R><<<grid, blk, 0, s>>>(b, st, c);
@@ -564,6 +839,7 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   if (c) tm->end(s);
   k_sc_half<R><<<cgrid, cblk, 0, s>>>(b, st, tol);
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(b, st.flags, st.s, st.sh);
+  if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.s, st.sh);
   c = tm ? tm->begin(s, 0, (jac ? 2 : 3) * by.blk + (jac ? by.diag : 0), by.matrix) : nullptr;
   k_spmm_t<R><<<grid, blk, 0, s>>>(b, st, c);
   if (c) tm->end(s);
@@ -590,14 +866,15 @@ __global__ __launch_bounds__(256) void k_count_active(Batch b, const int* __rest
                                                      int* __restrict__ out) {
   __shared__ int scan[256];
   __shared__ int cols[256];
+  const int tw = WAVE * b.V;
   int base = 0, ncols = 0;
   for (int t0 = 0; t0 < b.n_tiles; t0 += 256) {
     const int t = t0 + (int)threadIdx.x;
     int act = 0, cnt = 0;
     if (t < b.n_tiles) {
       const Inst I = b.inst[b.tile_inst[t]];
-      const int c0 = I.col0 + (t - I.tile0) * WAVE;
-      const int c1 = min(c0 + WAVE, I.col0 + I.K);
+      const int c0 = I.col0 + (t - I.tile0) * tw;
+      const int c1 = min(c0 + tw, I.col0 + I.K);
       for (int c = c0; c < c1; ++c) cnt += flags[c] == COL_ACTIVE ? 1 : 0;
       act = cnt > 0 ? 1 : 0;
     }
@@ -627,28 +904,41 @@ void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* o
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision: FP64 defect R = F - S Y and the FP32 <-> FP64 transfers.
+// Mixed precision: FP64 defect R = F - S Y and the FP32 <-> FP64 transfers.  The
+// batch is the FP32 one, so a lane owns kMixedV adjacent columns.
+constexpr int kMixedV = LaneWidth<float>::V;
+
 __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __restrict__ sigma_col,
                                               const double* __restrict__ F, const cx<double>* __restrict__ Y,
                                               cx<double>* __restrict__ Rout, double* __restrict__ part) {
+  constexpr int V = kMixedV;
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
-    const int l = cc % I.L;
-    const cx<double> sig = sigma_col[cg];
-    double nn = 0;
+  FOR_TILES(b, p, V)
+    cx<double> sig[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) sig[v] = sigma_col[cg0 + v];
+    double nn[V] = {};
     FOR_ROWS(b, p, I)
       const int i = I.sched ? as_const(I.sched)[pos] : pos;
-      const double f = F[I.rl + (size_t)i * I.L + l];
-      cx<double> r = {f, 0.0};
-      if (Y) {
-        const cx<double> q = shifted_row<double, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(I.ab64),
-                                                         Y + I.blk + cc, I.K, sig);
-        r = {f - q.re, -q.im};
-        if (valid) Rout[I.blk + (size_t)i * I.K + cc] = r;
+      cvec<double, V> q;
+      if (Y)
+        q = shifted_row<double, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(I.ab64),
+                                           Y + I.blk + cc0, I.Kp, sig);
+      cvec<double, V> r;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double f = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L] : 0.0;
+        r.c[v] = Y ? cx<double>{f - q.c[v].re, -q.c[v].im} : cx<double>{f, 0.0};
+        if (cl0 + v >= I.K) r.c[v] = {0.0, 0.0};
+        nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
       }
-      nn += r.re * r.re + r.im * r.im;
+      if (Y && valid) {
+        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) Rout[e + v] = r.c[v];
+      }
     END_ROWS
-    wg_store_partial<double>(nn, p.w, p.lane, valid, part + po);
+    wg_store_partial<double, V>(nn, p.w, p.lane, cl0, I.K, part + po);
   }
 }
 
@@ -665,16 +955,22 @@ __global__ __launch_bounds__(WG) void k_defect_norms(Batch b, const double* __re
                                                     double* __restrict__ fnorm, double* __restrict__ scale,
                                                     double* __restrict__ relres, float* __restrict__ tol32,
                                                     double min32) {
-  SC_PROLOGUE
-  const double r = sqrt(block_col_sum(part, b.G, b.Ktot, c, valid));
-  if (!lead) return;
-  if (first) fnorm[c] = r;
-  const double fn = fnorm[c];
-  const bool done = r <= tol[c] * fn;
-  scale[c] = done ? 0.0 : r;
-  relres[c] = fn > 0 ? r / fn : 0.0;
-  const double gap = r > 0 ? tol[c] * fn / r : 1.0;
-  tol32[c] = (float)fmin(1e-1, fmax(min32, 0.1 * gap));
+  constexpr int V = kMixedV;
+  SC_PROLOGUE(V)
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const double r = sqrt(block_col_sum(part, b.G, b.Ktot, c, ok));
+    if (!lead || cl0 + v >= I.Kp) continue;
+    if (first) fnorm[c] = r;
+    const double fn = fnorm[c];
+    const bool done = !ok || r <= tol[c] * fn;
+    scale[c] = done ? 0.0 : r;
+    relres[c] = fn > 0 ? r / fn : 0.0;
+    const double gap = r > 0 ? tol[c] * fn / r : 1.0;
+    tol32[c] = (float)fmin(1e-1, fmax(min32, 0.1 * gap));
+  }
 }
 
 __global__ void k_count_positive(int K, const double* __restrict__ v, int* __restrict__ out) {
@@ -697,28 +993,38 @@ void launch_defect_norms(hipStream_t s, const Batch& b, const double* part, cons
   k_count_positive<<<1, 256, 0, s>>>(b.Ktot, scale, count);
 }
 
+// r = R / scale (R null: F / scale), rhat = r, x = 0 in FP32; partial |r|^2
 __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __restrict__ R,
                                                  const double* __restrict__ F, const double* __restrict__ scale,
                                                  KrylovState<float> st, cx<float>* __restrict__ rhat) {
+  constexpr int V = kMixedV;
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
-    float nn = 0;
+  FOR_TILES(b, p, V)
+    float nn[V] = {};
     if (valid) {
-      const double sc = scale[cg];
-      const double inv = sc > 0 ? 1.0 / sc : 0.0;
-      const int l = cc % I.L;
+      double inv[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double sc = scale[cg0 + v];
+        inv[v] = (cl0 + v < I.K && sc > 0) ? 1.0 / sc : 0.0;
+      }
       FOR_ROWS(b, p, I)
         const int i = pos;
-        const size_t e = I.blk + (size_t)i * I.K + cc;
-        const cx<double> v = R ? R[e] : cx<double>{F[I.rl + (size_t)i * I.L + l], 0.0};
-        const cx<float> r = {(float)(v.re * inv), (float)(v.im * inv)};
-        st.r[e] = r;
-        rhat[e] = r;
-        st.x[e] = {0.f, 0.f};
-        nn += r.re * r.re + r.im * r.im;
+        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        cvec<float, V> r, x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const cx<double> d = R ? R[e + v] : cx<double>{F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L], 0.0};
+          r.c[v] = {(float)(d.re * inv[v]), (float)(d.im * inv[v])};
+          x.c[v] = {0.f, 0.f};
+          nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
+        }
+        stv<float, V>(st.r + e, r);
+        stv<float, V>(rhat + e, r);
+        stv<float, V>(st.x + e, x);
       END_ROWS
     }
-    wg_store_partial<float>(nn, p.w, p.lane, valid, st.part_b + po);
+    wg_store_partial<float, V>(nn, p.w, p.lane, cl0, I.K, st.part_b + po);
   }
 }
 
@@ -727,21 +1033,28 @@ void launch_mixed_rhs(hipStream_t s, const Batch& b, const cx<double>* R, const 
   k_mixed_rhs<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, R, F, scale, st, rhat);
 }
 
+// Y += scale x (first: Y = scale x)
 __global__ __launch_bounds__(WG) void k_accumulate(Batch b, const cx<float>* __restrict__ x,
                                                   const double* __restrict__ scale, cx<double>* __restrict__ Y,
                                                   int first) {
+  constexpr int V = kMixedV;
   const WgPos p = wg_pos(b.G);
-  FOR_TILES(b, p)
+  FOR_TILES(b, p, V)
     (void)po;
     if (!valid) continue;
-    const double sc = scale[cg];
+    double sc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) sc[v] = cl0 + v < I.K ? scale[cg0 + v] : 0.0;
     FOR_ROWS(b, p, I)
-      const size_t e = I.blk + (size_t)pos * I.K + cc;
-      const cx<float> v = x[e];
-      cx<double> y = first ? cx<double>{0.0, 0.0} : Y[e];
-      y.re += sc * (double)v.re;
-      y.im += sc * (double)v.im;
-      Y[e] = y;
+      const size_t e = I.blk + (size_t)pos * I.Kp + cc0;
+      const cvec<float, V> xv = ldv<float, V>(x + e);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        cx<double> y = first ? cx<double>{0.0, 0.0} : Y[e + v];
+        y.re += sc[v] * (double)xv.c[v].re;
+        y.im += sc[v] * (double)xv.c[v].im;
+        Y[e + v] = y;
+      }
     END_ROWS
   }
 }
@@ -755,7 +1068,7 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
   template void launch_init<R>(hipStream_t, const Batch&, const KrylovState<R>&, const R*);        \
   template void launch_init_scalars<R>(hipStream_t, const Batch&, const KrylovState<R>&);          \
   template void launch_iteration<R>(hipStream_t, const Batch&, const KrylovState<R>&, R, int, bool, \
-                                    bool, LaunchTimer*, const IterBytes&);
+                                    int, LaunchTimer*, const IterBytes&);
 SLRF_INST(double)
 SLRF_INST(float)
 

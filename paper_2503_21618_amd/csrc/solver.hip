@@ -67,6 +67,7 @@ bool ilu_allowed(int64_t n, int64_t nnz) { return nnz <= 5 * n; }
 bool use_ilu_for(int precond, int64_t n, int64_t nnz) {
   return precond == 2 || (precond == 0 && ilu_allowed(n, nnz));
 }
+bool use_bjac_for(int precond) { return precond == 3; }
 
 // First-fit allocator over a device region (persistent data of a batch).
 struct Pool {
@@ -128,9 +129,10 @@ struct Pencil {
   int* diagpos = nullptr;
   int* sched = nullptr;
   bool use_ilu = false;
+  bool use_bjac = false;  // node 3x3 block Jacobi
   char* mem = nullptr;  // device region holding the above
   size_t mem_bytes = 0;
-  std::vector<int32_t> h_rp, h_cl, h_dpos;  // host copies for ILU(0)
+  std::vector<int32_t> h_rp, h_cl, h_dpos;  // host copies for ILU(0) / block Jacobi
   std::vector<double> h_ab;
 };
 
@@ -192,8 +194,12 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   if (!err.empty()) return SLRF_E_INVALID_ARG;
   err = check_csr(b_rowptr, b_col, b_val, "B");
   if (!err.empty()) return SLRF_E_INVALID_ARG;
-  if (precond < 0 || precond > 2) {
+  if (precond < 0 || precond > 3) {
     err = "unknown preconditioner";
+    return SLRF_E_INVALID_ARG;
+  }
+  if (precond == 3 && n % 3 != 0) {
+    err = "node block Jacobi needs three unknowns per node (n divisible by 3)";
     return SLRF_E_INVALID_ARG;
   }
   std::vector<int32_t> rp(n + 1, 0), cl, dpos(n, -1);
@@ -234,6 +240,7 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.n = n;
   P.nnz = nnz;
   P.use_ilu = use_ilu_for(precond, n, nnz);
+  P.use_bjac = use_bjac_for(precond);
   P.mem = mem;
   P.mem_bytes = pencil_bytes(n, nnz);
   Carver cv{mem, 0, P.mem_bytes};
@@ -269,7 +276,7 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
     err = "upload of the merged CSR failed";
     return SLRF_E_DEVICE;
   }
-  if (P.use_ilu) {
+  if (P.use_ilu || P.use_bjac) {
     P.h_rp = std::move(rp);
     P.h_cl = std::move(cl);
     P.h_ab = std::move(ab);
@@ -308,6 +315,43 @@ bool ilu0_factor(const Pencil& P, std::complex<double> sigma, std::vector<std::c
     if (std::abs(f[dp[i]]) == 0.0 || !std::isfinite(std::abs(f[dp[i]]))) return false;
   }
   for (int64_t i = 0; i < n; ++i) f[dp[i]] = 1.0 / f[dp[i]];
+  return true;
+}
+
+// Inverted 3x3 node blocks of A - sigma B (node k: unknowns 3k..3k+2), row-major,
+// by Gauss-Jordan elimination with partial pivoting.  False if a block is singular.
+bool bjac3_factor(const Pencil& P, std::complex<double> sigma, std::vector<std::complex<double>>& f) {
+  using C = std::complex<double>;
+  const int64_t nodes = P.n / 3;
+  f.assign(nodes * 9, C(0.0));
+  for (int64_t k = 0; k < nodes; ++k) {
+    C m[3][6] = {};
+    for (int r = 0; r < 3; ++r) {
+      const int64_t i = 3 * k + r;
+      for (int32_t q = P.h_rp[i]; q < P.h_rp[i + 1]; ++q) {
+        const int64_t c = P.h_cl[q] - 3 * k;
+        if (c >= 0 && c < 3) m[r][c] = C(P.h_ab[2 * q], 0.0) - sigma * P.h_ab[2 * q + 1];
+      }
+      m[r][3 + r] = 1.0;
+    }
+    for (int col = 0; col < 3; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < 3; ++r)
+        if (std::abs(m[r][col]) > std::abs(m[piv][col])) piv = r;
+      if (!(std::abs(m[piv][col]) > 0.0) || !std::isfinite(std::abs(m[piv][col]))) return false;
+      if (piv != col)
+        for (int q = 0; q < 6; ++q) std::swap(m[piv][q], m[col][q]);
+      const C inv = 1.0 / m[col][col];
+      for (int q = 0; q < 6; ++q) m[col][q] *= inv;
+      for (int r = 0; r < 3; ++r)
+        if (r != col) {
+          const C fr = m[r][col];
+          for (int q = 0; q < 6; ++q) m[r][q] -= fr * m[col][q];
+        }
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) f[k * 9 + 3 * r + c] = m[r][3 + c];
+  }
   return true;
 }
 
@@ -389,7 +433,7 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   env.stream = (hipStream_t)hip_stream;
   if (env.opt.precision != SLRF_FP64 && env.opt.precision != SLRF_MIXED)
     return fail(env, SLRF_E_INVALID_ARG, "unknown precision");
-  if (env.opt.precond < 0 || env.opt.precond > 2) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (env.opt.precond < 0 || env.opt.precond > 3) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
   if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
     return fail(env, SLRF_E_INVALID_ARG, "tolerances must be non-negative");
   if (env.opt.tile_rows < 0 || env.opt.tile_rows > 64 || env.opt.tile_wgs < 0 ||
@@ -456,16 +500,17 @@ struct FilterJob {
 struct JobShape {
   int64_t n, nnz;
   int L, N;
-  bool ilu;           // ILU(0) factors of this pencil
-  bool general = false;  // count the p and s blocks even without ILU(0) (upper bounds)
+  bool ilu;              // ILU(0) factors of this pencil
+  bool general = false;  // count the p and s blocks even without another preconditioner (bounds)
+  bool bjac = false;     // node block-Jacobi inverses of this pencil
 };
 
 // Device layout of one batched filter application.  Carving with a null base
 // measures it; partial sums are sized for kMaxGrid workgroups so the size does
 // not depend on the grid a batch picks.
 struct FilterLayout {
-  int64_t EB = 0, ER = 0, ED = 0, Ktot = 0, n_tiles = 0, ilu_vals = 0;
-  bool any_ilu = false;
+  int64_t EB = 0, ER = 0, ED = 0, Ktot = 0, n_tiles = 0, ilu_vals = 0, bjac_vals = 0;
+  bool any_ilu = false, any_bjac = false;
   void* vec[9] = {};  // x r ph v sh t [p s] [complex shadow residual]
   double* rhat = nullptr;
   void* d = nullptr;
@@ -497,30 +542,43 @@ struct FilterLayout {
   int* tile_inst = nullptr;
   int* col_inst = nullptr;
   void* ilu = nullptr;
+  void* bjac = nullptr;
+  int precs() const { return (any_ilu ? 1 : 0) | (any_bjac ? 2 : 0); }
 };
+
+// Columns per lane of the Krylov kernels: 2 adjacent complex FP32 values or one
+// complex FP64 value (16 B either way).  A pencil's blocks have leading
+// dimension Kp = K rounded up to that width; a tile is 64 lanes wide.
+int lane_width(bool mixed) { return mixed ? 2 : 1; }
+int64_t padded_k(int64_t K, int V) { return (K + V - 1) / V * V; }
 
 void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo) {
   lo = FilterLayout{};
   int64_t sumN = 0;
   bool any_general = false;
+  const int V = lane_width(mixed);
   for (const auto& j : js) {
-    const int64_t K = (int64_t)j.N * j.L;
-    lo.EB += j.n * K;
+    const int64_t Kp = padded_k((int64_t)j.N * j.L, V);
+    lo.EB += j.n * Kp;
     lo.ER += j.n * j.L;
     lo.ED += j.n * j.N;
-    lo.Ktot += K;
-    lo.n_tiles += (K + 63) / 64;
+    lo.Ktot += Kp;
+    lo.n_tiles += (Kp + 64 * V - 1) / (64 * V);
     sumN += j.N;
     if (j.ilu) {
       lo.any_ilu = true;
       lo.ilu_vals += (int64_t)j.N * j.nnz;
     }
+    if (j.bjac) {
+      lo.any_bjac = true;
+      lo.bjac_vals += (int64_t)j.N * (j.n / 3) * 9;
+    }
     if (j.general) any_general = true;
   }
   const size_t cs = mixed ? 8 : 16;  // complex size in the Krylov precision
   const size_t rs = cs / 2;
-  // with any ILU(0) pencil in the batch, every pencil keeps p and s
-  const int nvec = 6 + (lo.any_ilu || any_general ? 2 : 0);
+  // with any ILU(0) or block-Jacobi pencil in the batch, every pencil keeps p and s
+  const int nvec = 6 + (lo.any_ilu || lo.any_bjac || any_general ? 2 : 0);
   for (int v = 0; v < nvec; ++v) lo.vec[v] = cv.take<char>((size_t)lo.EB * cs);
   if (mixed) {
     lo.vec[8] = cv.take<char>((size_t)lo.EB * cs);
@@ -556,6 +614,7 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   lo.tile_inst = cv.take<int>(lo.n_tiles);
   lo.col_inst = cv.take<int>(lo.Ktot);
   if (lo.any_ilu) lo.ilu = cv.take<char>((size_t)lo.ilu_vals * cs);
+  if (lo.any_bjac) lo.bjac = cv.take<char>((size_t)lo.bjac_vals * cs);
 }
 
 size_t filter_arena_bytes(const std::vector<JobShape>& js, bool mixed) {
@@ -637,10 +696,11 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
                           std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
   const hipStream_t s = env.stream;
   insts.assign(jobs.size(), Inst{});
+  b.V = std::is_same<R, float>::value ? 2 : 1;
   std::vector<int> tile_inst, col_inst;
-  std::vector<cx<R>> sigc, sigj, ilu_all;
+  std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all;
   std::vector<double> sigc64, w;
-  int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0;
+  int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0, bjac_off = 0;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
     const FilterJob& j = jobs[q];
@@ -649,6 +709,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.L = j.L;
     I.N = j.N;
     I.K = j.N * j.L;
+    I.Kp = (int)padded_k(I.K, b.V);
     I.col0 = col0;
     I.tile0 = tile0;
     I.nnz = (int)j.P->nnz;
@@ -662,9 +723,10 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.sched = j.P->sched;
     I.diagpos = j.P->diagpos;
     I.ilu = nullptr;
-    const int tiles = (I.K + 63) / 64;
+    I.bjac = nullptr;
+    const int tiles = (I.Kp + 64 * b.V - 1) / (64 * b.V);
     for (int t = 0; t < tiles; ++t) tile_inst.push_back((int)q);
-    for (int c = 0; c < I.K; ++c) col_inst.push_back((int)q);
+    for (int c = 0; c < I.Kp; ++c) col_inst.push_back((int)q);
     for (int p = 0; p < j.N; ++p) {
       const cx<R> sg = {(R)j.sigma[2 * p], (R)j.sigma[2 * p + 1]};
       sigj.push_back(sg);
@@ -676,6 +738,11 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
         sigc64.push_back(j.sigma[2 * p + 1]);
       }
     }
+    for (int c = I.K; c < I.Kp; ++c) {  // padding columns take the last pole (never active)
+      sigc.push_back(sigc.back());
+      sigc64.push_back(sigc64[sigc64.size() - 2]);
+      sigc64.push_back(sigc64[sigc64.size() - 2]);
+    }
     if (j.P->use_ilu) {
       std::vector<std::complex<double>> fj;
       for (int p = 0; p < j.N; ++p) {
@@ -686,10 +753,20 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
       I.ilu = (const char*)lo.ilu + ilu_off * sizeof(cx<R>);
       ilu_off += (int64_t)j.N * j.P->nnz;
     }
-    blk += (int64_t)I.n * I.K;
+    if (j.P->use_bjac) {
+      std::vector<std::complex<double>> fj;
+      for (int p = 0; p < j.N; ++p) {
+        if (!bjac3_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, fj))
+          return fail(env, SLRF_E_BREAKDOWN, "singular node block of the shifted operator");
+        for (const auto& v : fj) bjac_all.push_back({(R)v.real(), (R)v.imag()});
+      }
+      I.bjac = (const char*)lo.bjac + bjac_off * sizeof(cx<R>);
+      bjac_off += (int64_t)j.N * (j.P->n / 3) * 9;
+    }
+    blk += (int64_t)I.n * I.Kp;
     rl += (int64_t)I.n * I.L;
     dn += (int64_t)I.n * I.N;
-    col0 += I.K;
+    col0 += I.Kp;
     tile0 += tiles;
   }
   b.inst = lo.inst;
@@ -708,6 +785,8 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   HIPCHK(env, put_async(s, keep, lo.w, w.data(), 8 * w.size()));
   if (lo.sigma_col64) HIPCHK(env, put_async(s, keep, lo.sigma_col64, sigc64.data(), 8 * sigc64.size()));
   if (!ilu_all.empty()) HIPCHK(env, put_async(s, keep, lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
+  if (!bjac_all.empty())
+    HIPCHK(env, put_async(s, keep, lo.bjac, bjac_all.data(), sizeof(cx<R>) * bjac_all.size()));
   return SLRF_OK;
 }
 
@@ -731,7 +810,7 @@ int ilog2(int64_t x) {
 
 template <typename R>
 slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo, Batch& b,
-                     const KrylovState<R>& st, R tol, bool ilu, const IterBytes& by,
+                     const KrylovState<R>& st, R tol, int precs, const IterBytes& by,
                      const std::function<void()>& restart, std::vector<std::vector<char>>& keep) {
   const hipStream_t s = env.stream;
   int64_t rows = 0, nnz = 0;
@@ -759,9 +838,9 @@ slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo,
       err = put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst));
       if (err != hipSuccess) break;
       restart();
-      launch_iteration<R>(s, b, st, tol, 1 << 30, true, ilu, nullptr, by);
+      launch_iteration<R>(s, b, st, tol, 1 << 30, true, precs, nullptr, by);
       (void)hipEventRecord(e0, s);
-      for (int q = 0; q < 2; ++q) launch_iteration<R>(s, b, st, tol, 1 << 30, false, ilu, nullptr, by);
+      for (int q = 0; q < 2; ++q) launch_iteration<R>(s, b, st, tol, 1 << 30, false, precs, nullptr, by);
       (void)hipEventRecord(e1, s);
       err = hipEventSynchronize(e1);
       float ms = 0;
@@ -791,7 +870,7 @@ slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo,
 // opt.graph (no profiling, a non-null stream) one chunk of check_every
 // iterations plus the count is captured once as a hipGraph and replayed.
 template <typename R>
-slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol, bool ilu, const IterBytes& by,
+slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol, int precs, const IterBytes& by,
                        int* d_count, slrf_filter_stats* ks) {
   const hipStream_t s = env.stream;
   const int maxit = std::max(1, env.opt.inner_maxit);
@@ -812,7 +891,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       if (!exec) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-          for (int q = 0; q < every; ++q) launch_iteration<R>(s, b, st, tol, maxit, false, ilu, nullptr, by);
+          for (int q = 0; q < every; ++q) launch_iteration<R>(s, b, st, tol, maxit, false, precs, nullptr, by);
           launch_count_active(s, b, st.flags, d_count);
           e = hipStreamEndCapture(s, &gr);
         }
@@ -829,7 +908,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       }
       it += every;
     } else {
-      for (int q = 0; q < chunk; ++q, ++it) launch_iteration<R>(s, b, st, tol, maxit, it == 0, ilu, tm, by);
+      for (int q = 0; q < chunk; ++q, ++it) launch_iteration<R>(s, b, st, tol, maxit, it == 0, precs, tm, by);
       launch_count_active(s, b, st.flags, d_count);
     }
     int active = 0;
@@ -852,7 +931,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
 
 IterBytes iter_bytes(const std::vector<FilterJob>& jobs, const FilterLayout& lo, size_t rs, bool complex_rhat) {
   IterBytes by{};
-  by.blk = (double)lo.EB * 2 * rs;
+  for (const auto& j : jobs) by.blk += (double)j.P->n * j.N * j.L * 2 * rs;  // padding excluded
   by.rhat = complex_rhat ? by.blk : (double)lo.ER * rs;
   by.diag = (double)lo.ED * 2 * rs;
   for (const auto& j : jobs) by.matrix += merged_csr_bytes(*j.P, 2 * rs);
@@ -877,7 +956,9 @@ slrf_status collect_stats(Env& env, std::vector<FilterJob>& jobs, const KrylovSt
   for (size_t q = 0; q < jobs.size(); ++q) {
     slrf_filter_stats& fs = jobs[q].stats;
     const int K = jobs[q].N * jobs[q].L;
-    for (int k = 0; k < K; ++k, ++c) {
+    const int Kp = (int)padded_k(K, sizeof(R) == 4 ? 2 : 1);
+    for (int k = 0; k < Kp; ++k, ++c) {
+      if (k >= K) continue;
       fs.max_iterations = std::max(fs.max_iterations, its[c]);
       sum_it[q] += its[c];
       fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
@@ -912,7 +993,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
-  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu});
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
   FilterLayout lo;
   carve_filter(arena, js, false, lo);
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
@@ -937,17 +1018,17 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   slrf_filter_stats ks{};
   const IterBytes by = iter_bytes(jobs, lo, 8, false);
   if (env.opt.tune) {
-    slrf_status ts = autotune<double>(env, insts, lo, b, st, env.opt.inner_tol, lo.any_ilu, by, [&]() {
+    slrf_status ts = autotune<double>(env, insts, lo, b, st, env.opt.inner_tol, lo.precs(), by, [&]() {
       launch_init<double>(s, b, st, lo.rhat);
       launch_init_scalars<double>(s, b, st);
     }, keep);
     if (ts != SLRF_OK) return ts;
   }
-  slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.any_ilu, by, lo.count, &ks);
+  slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.precs(), by, lo.count, &ks);
   if (rs != SLRF_OK) return rs;
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
-    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, st.x + blk, lo.w + 2 * wj, j.U, false);
+    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, j.N * j.L, st.x + blk, lo.w + 2 * wj, j.U, false);
     blk += j.P->n * (int64_t)j.N * j.L;
     wj += j.N;
   }
@@ -969,7 +1050,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
-  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu});
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
   FilterLayout lo;
   carve_filter(arena, js, true, lo);
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
@@ -984,7 +1065,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   // gap between the current defect and that target.
   std::vector<double> tol_host;
   for (auto& j : jobs)
-    for (int c = 0; c < j.N * j.L; ++c) tol_host.push_back(j.target);
+    for (int64_t c = 0; c < padded_k(j.N * j.L, 2); ++c) tol_host.push_back(j.target);
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
   st.tolc = lo.tol32;
@@ -1018,13 +1099,13 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
     launch_init_scalars<float>(s, b, st);
     if (round == 0 && env.opt.tune) {
-      slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.any_ilu, by, [&]() {
+      slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.precs(), by, [&]() {
         launch_mixed_rhs(s, b, nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
         launch_init_scalars<float>(s, b, st);
       }, keep);
       if (ts != SLRF_OK) return ts;
     }
-    slrf_status rs = run_krylov<float>(env, b, st, tol32, lo.any_ilu, by, lo.count, &ks);
+    slrf_status rs = run_krylov<float>(env, b, st, tol32, lo.precs(), by, lo.count, &ks);
     if (rs != SLRF_OK) return rs;
     launch_accumulate(s, b, st.x, lo.scale, lo.Y, round == 0);
     slrf_status cs = collect_stats<float>(env, jobs, st, lo.Ktot, false, it_round);
@@ -1034,10 +1115,11 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
     if (rounds > 0)
-      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, lo.Y + blk, lo.w + 2 * wj, j.U, false);
+      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, (int)padded_k(j.N * j.L, 2), lo.Y + blk,
+                                lo.w + 2 * wj, j.U, false);
     else
       HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
-    blk += j.P->n * (int64_t)j.N * j.L;
+    blk += j.P->n * padded_k(j.N * j.L, 2);
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1045,9 +1127,11 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   HIPCHK(env, hipMemcpyAsync(rr.data(), lo.relres, 8 * (size_t)lo.Ktot, hipMemcpyDeviceToHost, s));
   HIPCHK(env, hipStreamSynchronize(s));
   int64_t c = 0;
-  for (size_t q = 0; q < jobs.size(); ++q)
-    for (int k = 0; k < jobs[q].N * jobs[q].L; ++k, ++c)
-      jobs[q].stats.max_relres = std::max(jobs[q].stats.max_relres, rr[c]);
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    const int K = jobs[q].N * jobs[q].L;
+    for (int k = 0; k < padded_k(K, 2); ++k, ++c)
+      if (k < K) jobs[q].stats.max_relres = std::max(jobs[q].stats.max_relres, rr[c]);
+  }
   finish_stats(jobs, sum_it, ks, now_s() - t0, rounds);
   return SLRF_OK;
 }
@@ -1318,7 +1402,8 @@ struct slrf_batch_s {
     std::vector<JobShape> js;
     for (const auto& kv : entries)
       if (!kv.second.J->done)
-        js.push_back({kv.second.P->n, kv.second.P->nnz, kv.second.J->L, kv.second.J->N, kv.second.P->use_ilu});
+        js.push_back({kv.second.P->n, kv.second.P->nnz, kv.second.J->L, kv.second.J->N, kv.second.P->use_ilu, false,
+                      kv.second.P->use_bjac});
     return js;
   }
 };
@@ -1379,14 +1464,28 @@ slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma
   return SLRF_OK;
 }
 
-slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
+slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz, int64_t L, int32_t N, const slrf_options* opt,
+                                     size_t* bytes) {
+  slrf_options o;
+  if (opt)
+    o = *opt;
+  else
+    slrf_default_options(&o);
   if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
-  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
-  // sized for the ILU(0) vectors whenever the pattern allows them
-  const size_t arena =
-      filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz)}}, precision == SLRF_MIXED);
+  if (o.precision != SLRF_FP64 && o.precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  if (o.precond < 0 || o.precond > 3) return SLRF_E_INVALID_ARG;
+  const size_t arena = filter_arena_bytes(
+      {JobShape{n, nnz, (int)L, (int)N, use_ilu_for(o.precond, n, nnz), false, use_bjac_for(o.precond)}},
+      o.precision == SLRF_MIXED);
   *bytes = pencil_bytes(n, nnz) + al(kTimerSlots * 4) + arena + outer_bytes(n, L);
   return SLRF_OK;
+}
+
+slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision, size_t* bytes) {
+  slrf_options o;
+  slrf_default_options(&o);  // automatic preconditioner choice
+  o.precision = precision;
+  return slrf_workspace_bytes_for(n, nnz, L, N, &o, bytes);
 }
 
 slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
@@ -1409,7 +1508,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0)
     return fail(env, SLRF_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
   size_t need = 0;
-  if (slrf_workspace_bytes(n, nnz, max_L, max_N, env.opt.precision, &need) != SLRF_OK)
+  if (slrf_workspace_bytes_for(n, nnz, max_L, max_N, &env.opt, &need) != SLRF_OK)
     return fail(env, SLRF_E_INVALID_ARG, "bad sizes");
   if (ws_bytes < need)
     return fail(env, SLRF_E_WORKSPACE,
@@ -1423,7 +1522,8 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   if (!env.setup_timer((int*)((char*)d_workspace + poff))) return fail(env, SLRF_E_DEVICE, "timer set-up failed");
   ctx->arena_off = poff + al(kTimerSlots * 4);
   ctx->arena_bytes =
-      filter_arena_bytes({JobShape{n, nnz, (int)max_L, max_N, ilu_allowed(n, nnz)}}, env.opt.precision == SLRF_MIXED);
+      filter_arena_bytes({JobShape{n, nnz, (int)max_L, max_N, ctx->P.use_ilu, false, ctx->P.use_bjac}},
+                         env.opt.precision == SLRF_MIXED);
   ctx->outer_off = ctx->arena_off + ctx->arena_bytes;
   ctx->ws = (char*)d_workspace;
   return SLRF_OK;
@@ -1482,9 +1582,10 @@ slrf_status slrf_batch_footprint(int64_t n, int64_t nnz, int64_t L, int32_t N, i
     return SLRF_E_INVALID_ARG;
   if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
   *persistent_bytes = al(pencil_bytes(n, nnz)) + al(outer_bytes(n, L));
-  // counts the two blocks a batch with an ILU(0) pencil gives every pencil, so
-  // that the sum over a set of pencils bounds the arena the set needs
-  *transient_bytes = filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz), true}},
+  // counts the two blocks a batch with an ILU(0) or block-Jacobi pencil gives
+  // every pencil (and block-Jacobi inverses when n is a multiple of 3), so that
+  // the sum over a set of pencils bounds the arena the set needs
+  *transient_bytes = filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz), true, n % 3 == 0}},
                                         precision == SLRF_MIXED);
   return SLRF_OK;
 }
@@ -1530,7 +1631,7 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
                                 env.err, nullptr, &nnz);
   if (st != SLRF_OK) return st;
   std::vector<JobShape> shapes = b->active_shapes();
-  shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz)});
+  shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz), false, use_bjac_for(env.opt.precond)});
   if (filter_arena_bytes(shapes, env.opt.precision == SLRF_MIXED) > b->arena_bytes)
     return fail(env, SLRF_E_WORKSPACE, "the filter arena cannot hold this pencil next to the active ones");
   const size_t pb = pencil_bytes(n, nnz), ob = outer_bytes(n, L);
