@@ -1,6 +1,6 @@
 """Benchmark: eigenpairs/s of the SLRF interval eigensolver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|batched|served]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|batched|served]
                     [--precision both|mixed|fp64] [--no-cpu-baseline]
     python bench.py --counters-probe | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
 
@@ -41,6 +41,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -67,6 +68,14 @@ def workload(name):
                           "log-normal coefficient sigma=0.5 seed 2, consistent mass "
                           f"(n={p.n}, nnz={p.A.nnz}); gamma=421 (87 eigenvalues); L=128; "
                           "N=6 SLRF poles alpha=1 beta=0.01; point-Jacobi BiCGStab"))
+    if name == "c3":
+        p = pencils.c3_elasticity()
+        return dict(pencil=p, gamma=101.0, L=256, N=8, expect=None, precond=3,
+                    desc=("3D linear elasticity, trilinear hex, 48^3 free nodes x 3 dofs, clamped x=0 face, "
+                          "Young's modulus log-normal sigma=0.7 seed 3, nu=0.3, density U[0.8,1.2] "
+                          f"(n={p.n}, nnz={p.A.nnz}); gamma=101 (about 200 eigenvalues: the 200th "
+                          "eigenvalue of the 12^3 and 16^3 meshes extrapolated in h^2); L=256; N=8 SLRF poles "
+                          "alpha=1 beta=0.01; node 3x3 block-Jacobi BiCGStab"))
     if name == "c1":
         import numpy as np
         p = pencils.c1_string()
@@ -80,26 +89,30 @@ def workload(name):
 
 
 def cpu_baseline(wl, sig, solve_stats):
-    """Oracle BiCGStab (point Jacobi, FP64) on 1 pole x 4 columns for a fixed number
-    of iterations, single thread; scaled by the column-iterations of the GPU solve."""
+    """Oracle BiCGStab (FP64, the workload's preconditioner) on 1 pole x 4 columns for
+    a fixed number of iterations, single thread; scaled by the column-iterations of
+    the GPU solve."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import pencils
     from oracle import krylov
     p = wl["pencil"]
-    cols, iters = 4, 100 if p.n > 100000 else 200
+    # about 15 s of host work: 100 iterations on the 64^3 scalar pencil, scaled by nnz
+    cols = 4
+    iters = max(10, min(200, int(100 * 6.5e6 / max(p.A.nnz, 1))))
+    pc = "bjac3" if wl.get("precond", 0) == 3 else "jacobi"
     F = p.B @ pencils.start_block(p.n, cols, 77)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        krylov.bicgstab(p.A, p.B, sig[:1], F, 0.0, iters, fixed_iters=iters)
+        krylov.bicgstab(p.A, p.B, sig[:1], F, 0.0, iters, fixed_iters=iters, precond=pc)
         dt = time.perf_counter() - t0
     per_col_it = dt / (cols * iters)
     col_its = solve_stats["spmv_total"] / 2.0
     est = per_col_it * col_its
     return {"value": solve_stats["n_found"] / est, "unit": "eigenpairs/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"oracle.krylov.bicgstab (FP64, point Jacobi) on 1 pole x {cols} columns for "
+            "sample": (f"oracle.krylov.bicgstab (FP64, {pc}) on 1 pole x {cols} columns for "
                        f"{iters} iterations took {dt:.1f} s on 1 host thread; scaled to the "
                        f"{col_its:.0f} column-iterations of one GPU solve (Rayleigh-Ritz excluded)"),
             "seconds_per_column_iteration": per_col_it}
@@ -184,11 +197,9 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
                 if row["Counter_Name"] != counter:
                     continue
                 name = row["Kernel_Name"]
+                m = re.search(r"k_spmm_([vt])<(float|double)", name)
                 key = ("copy" if "elementwise" in name and "neg" in name else
-                       "k_spmm_v<float>" if "k_spmm_v<float>" in name else
-                       "k_spmm_t<float>" if "k_spmm_t<float>" in name else
-                       "k_spmm_v<double>" if "k_spmm_v<double>" in name else
-                       "k_spmm_t<double>" if "k_spmm_t<double>" in name else None)
+                       f"k_spmm_{m.group(1)}<{m.group(2)}>" if m else None)
                 if key:
                     acc.setdefault(key, []).append(float(row["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
@@ -430,14 +441,14 @@ def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
     import torch
     p = wl["pencil"]
     L, N, gamma = wl["L"], wl["N"], wl["gamma"]
-    opt = slrf.default_options(profile=1, precision=precision)
+    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0))
     solver = slrf.Solver(p.A, p.B, max_L=L, max_poles=N, options=opt)
     tag = "mixed" if precision == slrf.MIXED else "fp64"
     log(f"{tag}: n={p.n} L={L} N={N} workspace {solver.ws_bytes / 2**30:.2f} GiB")
 
     def step():
         r = solver.solve_interval(gamma, L, sig, w, V0=V0)
-        if r.status != 0 or r.n_found != wl["expect"]:
+        if r.status != 0 or (wl["expect"] is not None and r.n_found != wl["expect"]):
             raise SystemExit(f"{tag} solve failed: status {r.status} found {r.n_found} ({r.message})")
         return r
 

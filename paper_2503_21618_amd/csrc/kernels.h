@@ -48,6 +48,7 @@ struct Inst {
   const void* ab;               // ab_pair<R> in the Krylov precision
   const ab_pair<double>* ab64;  // FP64 values (defect of the mixed path)
   const int* sched;             // sparse-product row order, or null
+  const int* groups;            // stencil-group flags per kGroup rows, or null
   const int* diagpos;           // position of each row's diagonal (ILU)
   const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
   const void* bjac;             // (N, n/3, 3, 3) cx<R> inverted node blocks, or null
@@ -65,6 +66,7 @@ struct Batch {
   int G;                  // grid, a multiple of 8
   int rows_per_block;
   int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
+  int groups;             // 1 if some pencil has stencil groups (selects the sparse-product variant)
 };
 
 // Krylov vectors: base pointers of the concatenated per-pencil blocks; per

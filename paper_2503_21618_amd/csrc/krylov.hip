@@ -184,6 +184,51 @@ __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<
 }
 
 constexpr int kChunk = 16;
+constexpr int kGroupRows = 4;  // rows of a stencil group (flags built on the host)
+
+// Complex-shifted sparse product of a stencil group: rows i0 .. i0 + 3 whose
+// entries have the same offsets col - row, in runs of three consecutive columns
+// (checked on the host).  Run j of row r covers columns c_j + r .. c_j + r + 2,
+// so the six input rows c_j .. c_j + 5 are gathered once for the four rows:
+// 6 gathers per run instead of 12.  Each row's entries are summed in entry
+// order, as in shifted_row.
+template <typename R, int V>
+__device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
+                                              const cx<R>* __restrict__ Pc, int Kp, const cx<R> (&sig)[V],
+                                              cvec<R, V> (&q)[kGroupRows]) {
+  int kb[kGroupRows];
+#pragma unroll
+  for (int r = 0; r < kGroupRows; ++r) kb[r] = rowptr[i0 + r];
+  const int m = rowptr[i0 + 1] - kb[0];
+  R apr[kGroupRows][V] = {}, api[kGroupRows][V] = {}, bpr[kGroupRows][V] = {}, bpi[kGroupRows][V] = {};
+#pragma unroll 1
+  for (int j = 0; j < m; j += 3) {
+    const int c0 = col[kb[0] + j];
+    cvec<R, V> w[kGroupRows + 2];
+#pragma unroll
+    for (int t = 0; t < kGroupRows + 2; ++t) w[t] = ldv<R, V>(Pc + (size_t)(c0 + t) * Kp);
+#pragma unroll
+    for (int r = 0; r < kGroupRows; ++r) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const ab_pair<R> ce = ldc(ab + kb[r] + j + e);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          apr[r][v] += ce.a * w[r + e].c[v].re;
+          api[r][v] += ce.a * w[r + e].c[v].im;
+          bpr[r][v] += ce.b * w[r + e].c[v].re;
+          bpi[r][v] += ce.b * w[r + e].c[v].im;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kGroupRows; ++r)
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      q[r].c[v] = {apr[r][v] - (sig[v].re * bpr[r][v] - sig[v].im * bpi[r][v]),
+                   api[r][v] - (sig[v].re * bpi[r][v] + sig[v].im * bpr[r][v])};
+}
 
 // Loop header shared by the batched kernels: tile tg of pencil I.  cl0 is the
 // lane's first column within the pencil (a multiple of V), cc0 that column
@@ -215,9 +260,61 @@ constexpr int kChunk = 16;
   }              \
   }
 
+// Row loop of the sparse products for one tile: the workgroup's row blocks of
+// pencil I; emit(i, q) receives row i's product.  When the row block is a
+// multiple of 16 rows and the pencil has stencil groups, wavefront w takes the
+// four consecutive positions rb * rows_per_block + 4 w + 16 k; if they hold one
+// stencil group the shared-gather path serves them, else each is a generic row.
+// Otherwise wavefront w takes every 4th position as in FOR_ROWS.
+template <typename R, int V, bool GRP, typename Emit>
+__device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const Inst& I, const void* abv,
+                                          const cx<R>* __restrict__ Pc, const cx<R> (&sig)[V], Emit&& emit) {
+  const cptr<int> rowptr = as_const(I.rowptr), col = as_const(I.col);
+  const cptr<ab_pair<R>> ab = as_const(static_cast<const ab_pair<R>*>(abv));
+  const bool quads = GRP && I.groups && b.rows_per_block % (4 * kGroupRows) == 0;
+  for (int t = 0; t < I.steps; ++t) {
+    const int rb = step_block(I, p, t);
+    if (rb < 0) break;
+    const int r0 = rb * b.rows_per_block, r1 = min(r0 + b.rows_per_block, I.n);
+    if (quads) {
+      for (int q0 = r0 + kGroupRows * p.w; q0 < r1; q0 += 4 * kGroupRows) {
+        const int cnt = min(kGroupRows, r1 - q0);
+        const int i0 = I.sched ? as_const(I.sched)[q0] : q0;
+        bool grp = cnt == kGroupRows && i0 % kGroupRows == 0 && as_const(I.groups)[i0 / kGroupRows] != 0;
+        if (grp && I.sched) {
+#pragma unroll
+          for (int u = 1; u < kGroupRows; ++u) grp = grp && as_const(I.sched)[q0 + u] == i0 + u;
+        }
+        if constexpr (GRP) {
+          if (grp) {
+            cvec<R, V> q[kGroupRows];
+            shifted_group<R, V>(i0, rowptr, col, ab, Pc, I.Kp, sig, q);
+#pragma unroll
+            for (int u = 0; u < kGroupRows; ++u) emit(i0 + u, q[u]);
+            continue;
+          }
+        }
+        {
+          for (int u = 0; u < cnt; ++u) {
+            const int i = I.sched ? as_const(I.sched)[q0 + u] : q0 + u;
+            emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, I.Kp, sig));
+          }
+        }
+      }
+    } else {
+      for (int pos = r0 + p.w; pos < r1; pos += 4) {
+        const int i = I.sched ? as_const(I.sched)[pos] : pos;
+        emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, I.Kp, sig));
+      }
+    }
+  }
+}
+
+// The sparse-product kernels declare 4 wavefronts per SIMD (<= 128 VGPRs): the
+// grid puts at most 4 workgroups of 4 wavefronts on a CU.
 // v = S p_hat, partial (rhat, v)
-template <typename R>
-__global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* counter) {
+template <typename R, bool GRP>
+__global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
@@ -227,39 +324,34 @@ __global__ __launch_bounds__(WG) void k_spmm_v(Batch b, KrylovState<R> st, int* 
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
-      FOR_ROWS(b, p, I)
-        const int i = I.sched ? as_const(I.sched)[pos] : pos;
+      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.ph + I.blk + cc0, sig, [&](int i, const cvec<R, V>& q) {
+        if (!valid) return;
         const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-        const cvec<R, V> q = shifted_row<R, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
-                                                       st.ph + I.blk + cc0, I.Kp, sig);
-        if (valid) {
-          stv<R, V>(st.v + e, q);
-          if (st.rhat_cx) {  // conj(rhat) * v
-            const cvec<R, V> rh = ldv<R, V>(st.rhat_cx + e);
+        stv<R, V>(st.v + e, q);
+        if (st.rhat_cx) {  // conj(rhat) * v
+          const cvec<R, V> rh = ldv<R, V>(st.rhat_cx + e);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              d[v].re += rh.c[v].re * q.c[v].re + rh.c[v].im * q.c[v].im;
-              d[v].im += rh.c[v].re * q.c[v].im - rh.c[v].im * q.c[v].re;
-            }
-          } else {
+          for (int v = 0; v < V; ++v) {
+            d[v].re += rh.c[v].re * q.c[v].re + rh.c[v].im * q.c[v].im;
+            d[v].im += rh.c[v].re * q.c[v].im - rh.c[v].im * q.c[v].re;
+          }
+        } else {
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              const R rh = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
-              d[v].re += rh * q.c[v].re;
-              d[v].im += rh * q.c[v].im;
-            }
+          for (int v = 0; v < V; ++v) {
+            const R rh = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
+            d[v].re += rh * q.c[v].re;
+            d[v].im += rh * q.c[v].im;
           }
         }
-      END_ROWS
+      });
     }
     wg_store_partial_cx<R, V>(d, p.w, p.lane, cl0, I.K, st.part_a + po);
   }
 }
 
 // t = S s_hat, partials (t, s) = t^H s and (t, t)
-template <typename R>
-__global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* counter) {
+template <typename R, bool GRP>
+__global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
@@ -270,11 +362,7 @@ __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* 
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      const ab_pair<R>* ab = static_cast<const ab_pair<R>*>(I.ab);
-      FOR_ROWS(b, p, I)
-        const int i = I.sched ? as_const(I.sched)[pos] : pos;
-        const cvec<R, V> tv = shifted_row<R, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(ab),
-                                                        st.sh + I.blk + cc0, I.Kp, sig);
+      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.sh + I.blk + cc0, sig, [&](int i, const cvec<R, V>& tv) {
         if (valid) {
           const size_t e = I.blk + (size_t)i * I.Kp + cc0;
           stv<R, V>(st.t + e, tv);
@@ -295,7 +383,7 @@ __global__ __launch_bounds__(WG) void k_spmm_t(Batch b, KrylovState<R> st, int* 
             tt[v] += t.re * t.re + t.im * t.im;
           }
         }
-      END_ROWS
+      });
     }
     wg_store_partial_cx<R, V>(ts, p.w, p.lane, cl0, I.K, st.part_a + po);
     wg_store_partial<R, V>(tt, p.w, p.lane, cl0, I.K, st.part_b + po);
@@ -831,7 +919,10 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.p, st.ph);
   // v = S p_hat: gather p_hat once, write v, read rhat; the merged CSR once per launch
   c = tm ? tm->begin(s, 0, 2 * by.blk + by.rhat, by.matrix) : nullptr;
-  k_spmm_v<R><<<grid, blk, 0, s>>>(b, st, c);
+  if (b.groups)
+    k_spmm_v<R, true><<<grid, blk, 0, s>>>(b, st, c);
+  else
+    k_spmm_v<R, false><<<grid, blk, 0, s>>>(b, st, c);
   if (c) tm->end(s);
   k_sc_alpha<R><<<cgrid, cblk, 0, s>>>(b, st);
   c = tm ? tm->begin(s, 1, 3 * by.blk + (jac ? by.diag : 0), 0) : nullptr;
@@ -841,7 +932,10 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(b, st.flags, st.s, st.sh);
   if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.s, st.sh);
   c = tm ? tm->begin(s, 0, (jac ? 2 : 3) * by.blk + (jac ? by.diag : 0), by.matrix) : nullptr;
-  k_spmm_t<R><<<grid, blk, 0, s>>>(b, st, c);
+  if (b.groups)
+    k_spmm_t<R, true><<<grid, blk, 0, s>>>(b, st, c);
+  else
+    k_spmm_t<R, false><<<grid, blk, 0, s>>>(b, st, c);
   if (c) tm->end(s);
   k_sc_omega<R><<<cgrid, cblk, 0, s>>>(b, st);
   c = tm ? tm->begin(s, 1, (first ? 5 : 6) * by.blk + (jac ? 0 : by.blk) + by.rhat + (jac ? by.diag : 0), 0)
@@ -918,12 +1012,7 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
 #pragma unroll
     for (int v = 0; v < V; ++v) sig[v] = sigma_col[cg0 + v];
     double nn[V] = {};
-    FOR_ROWS(b, p, I)
-      const int i = I.sched ? as_const(I.sched)[pos] : pos;
-      cvec<double, V> q;
-      if (Y)
-        q = shifted_row<double, V, kChunk>(i, as_const(I.rowptr), as_const(I.col), as_const(I.ab64),
-                                           Y + I.blk + cc0, I.Kp, sig);
+    auto emit = [&](int i, const cvec<double, V>& q) {
       cvec<double, V> r;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -937,7 +1026,15 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
 #pragma unroll
         for (int v = 0; v < V; ++v) Rout[e + v] = r.c[v];
       }
-    END_ROWS
+    };
+    if (Y) {
+      spmm_rows<double, V, true>(b, p, I, I.ab64, Y + I.blk + cc0, sig, emit);
+    } else {
+      const cvec<double, V> zero{};
+      FOR_ROWS(b, p, I)
+        emit(I.sched ? as_const(I.sched)[pos] : pos, zero);
+      END_ROWS
+    }
     wg_store_partial<double, V>(nn, p.w, p.lane, cl0, I.K, part + po);
   }
 }

@@ -36,7 +36,8 @@ using namespace slrf;
 
 namespace {
 
-constexpr int kRowsPerBlock = 8;    // default rows per row block
+constexpr int kRowsPerBlock = 16;   // default rows per row block (4 wavefronts x one row group)
+constexpr int kGroup = 4;           // rows of a stencil group (see stencil_groups)
 constexpr int kWgPerXcd = 128;      // default workgroups per XCD (grid 8 * 128)
 constexpr int kSubBand = 1024;      // default rows per sub-band of the sparse-product row order
 constexpr int kTimerSlots = 512;
@@ -128,6 +129,7 @@ struct Pencil {
   float* diagB32 = nullptr;
   int* diagpos = nullptr;
   int* sched = nullptr;
+  int* groups = nullptr;  // stencil-group flags (n / kGroup), or null
   bool use_ilu = false;
   bool use_bjac = false;  // node 3x3 block Jacobi
   char* mem = nullptr;  // device region holding the above
@@ -139,7 +141,7 @@ struct Pencil {
 size_t pencil_bytes(int64_t n, int64_t nnz) {
   const size_t np = (size_t)nnz + kCsrPad;
   return al((size_t)(n + 1) * 4) + al(np * 4) + al(np * 16) + al(np * 8) + 2 * al((size_t)n * 8) +
-         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4);
+         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4) + al((size_t)(n / kGroup + 1) * 4);
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
@@ -156,7 +158,9 @@ bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<
   for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] > rp[i]) H = std::max<int64_t>(H, (int64_t)cl[rp[i + 1] - 1] - i);
   if (H <= 2 * target || H >= n) return false;
-  const int64_t S = (H + target - 1) / target, band = (H + S - 1) / S, nchunk = (n + H - 1) / H;
+  H = (H + kGroup - 1) / kGroup * kGroup;  // chunk and sub-band starts stay multiples of kGroup
+  const int64_t S = (H + target - 1) / target;
+  const int64_t band = ((H + S - 1) / S + kGroup - 1) / kGroup * kGroup, nchunk = (n + H - 1) / H;
   order.clear();
   order.reserve(n);
   for (int64_t sb = 0; sb < S; ++sb)
@@ -165,6 +169,32 @@ bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<
       for (int64_t r = a; r < b; ++r) order.push_back((int32_t)r);
     }
   return (int64_t)order.size() == n;
+}
+
+// Stencil groups: kGroup consecutive rows i0 .. i0 + 3 (i0 a multiple of kGroup)
+// whose entries have the same offsets col - row, in runs of three consecutive
+// columns (interior rows of bilinear and trilinear finite-element pencils).  For
+// such a group, run j of row r covers columns c_j + r .. c_j + r + 2, so the
+// sparse product gathers the six rows c_j .. c_j + 5 once for all four rows.
+// Returns one flag per group.
+std::vector<int32_t> stencil_groups(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl) {
+  const int64_t ng = n / kGroup;
+  std::vector<int32_t> g(ng > 0 ? ng : 1, 0);
+  for (int64_t q = 0; q < ng; ++q) {
+    const int64_t i0 = q * kGroup;
+    const int32_t k0 = rp[i0], m = rp[i0 + 1] - rp[i0];
+    if (m <= 0 || m % 3 != 0) continue;
+    bool ok = true;
+    for (int r = 1; r < kGroup && ok; ++r) {
+      if (rp[i0 + r + 1] - rp[i0 + r] != m) ok = false;
+      for (int32_t k = 0; k < m && ok; ++k)
+        if (cl[rp[i0 + r] + k] != cl[k0 + k] + r) ok = false;
+    }
+    for (int32_t j = 0; j < m && ok; j += 3)
+      if (cl[k0 + j + 1] != cl[k0 + j] + 1 || cl[k0 + j + 2] != cl[k0 + j] + 2) ok = false;
+    g[q] = ok ? 1 : 0;
+  }
+  return g;
 }
 
 // Validates A and B, merges them into one CSR of (a, b) pairs over the union
@@ -254,8 +284,13 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.diagB32 = cv.take<float>(n);
   P.diagpos = cv.take<int>(n);
   int* sched_dev = cv.take<int>(n);
+  int* groups_dev = cv.take<int>(n / kGroup + 1);
   std::vector<int32_t> order;
   P.sched = band_schedule(n, rp, cl, band_rows, order) ? sched_dev : nullptr;
+  const std::vector<int32_t> groups = stencil_groups(n, rp, cl);
+  bool any_group = false;
+  for (int32_t f : groups) any_group |= f != 0;
+  P.groups = any_group ? groups_dev : nullptr;
   // kCsrPad zero entries (column 0, coefficients 0) after the last entry
   cl.resize(nnz + kCsrPad, 0);
   ab.resize(2 * (size_t)(nnz + kCsrPad), 0.0);
@@ -272,7 +307,9 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
       cp(P.diagA, dA.data(), 8 * n) != hipSuccess || cp(P.diagB, dB.data(), 8 * n) != hipSuccess ||
       cp(P.diagA32, dA32.data(), 4 * n) != hipSuccess || cp(P.diagB32, dB32.data(), 4 * n) != hipSuccess ||
       cp(P.diagpos, dpos.data(), 4 * n) != hipSuccess ||
-      (P.sched && cp(P.sched, order.data(), 4 * n) != hipSuccess) || hipStreamSynchronize(s) != hipSuccess) {
+      (P.sched && cp(P.sched, order.data(), 4 * n) != hipSuccess) ||
+      (P.groups && cp(P.groups, groups.data(), 4 * groups.size()) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess) {
     err = "upload of the merged CSR failed";
     return SLRF_E_DEVICE;
   }
@@ -697,6 +734,8 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   const hipStream_t s = env.stream;
   insts.assign(jobs.size(), Inst{});
   b.V = std::is_same<R, float>::value ? 2 : 1;
+  b.groups = 0;
+  for (const auto& j : jobs) b.groups |= j.P->groups ? 1 : 0;
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all;
   std::vector<double> sigc64, w;
@@ -721,6 +760,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.ab = std::is_same<R, float>::value ? (const void*)j.P->ab32 : (const void*)j.P->ab64;
     I.ab64 = j.P->ab64;
     I.sched = j.P->sched;
+    I.groups = j.P->groups;
     I.diagpos = j.P->diagpos;
     I.ilu = nullptr;
     I.bjac = nullptr;
@@ -827,7 +867,7 @@ slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo,
     if (it != g_tune_cache.end()) best = it->second;
   }
   if (best.rpb == 0) {
-    static const Tiling cands[] = {{8, 128}, {16, 128}, {32, 128}, {4, 128}, {8, 256}, {16, 64}};
+    static const Tiling cands[] = {{16, 128}, {32, 128}, {8, 128}, {16, 256}, {32, 256}, {16, 64}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(env, hipEventCreate(&e0));
     HIPCHK(env, hipEventCreate(&e1));
