@@ -38,6 +38,7 @@ struct Inst {
   int n, K, L, N;        // rows, columns, right-hand sides, poles
   int Kp;                // leading dimension of the (n, Kp) blocks: K rounded up to the lane width
   int nrb, slab, steps;  // row blocks, row blocks per XCD, steps per workgroup
+  int rot;               // rotation of the pencil's row blocks over an XCD's workgroups
   int col0, tile0;       // first global column and first global tile
   int nnz;
   int64_t blk;           // element offset of the (n, K) blocks
@@ -140,8 +141,9 @@ void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* o
 
 // Mixed precision (FP32 inner solves, FP64 defect correction).
 // R = F - S Y in FP64 (Y null: R = F and R is not written), partial |R|^2 in part [G][Ktot].
+// With Y, tiles whose columns all have scale 0 (met their target earlier) are skipped.
 void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, const double* F,
-                   const cx<double>* Y, cx<double>* Rout, double* part);
+                   const cx<double>* Y, cx<double>* Rout, double* part, const double* scale);
 // scale_c = ||R_c|| if ||R_c|| > tol_c ||F_c|| else 0 (tol per column); the first round
 // sets fnorm_c = ||F_c||; tol32_c = clamp(0.1 tol_c ||F_c|| / ||R_c||, min32, 0.1), the
 // relative tolerance of the column's next FP32 solve; *count = columns with scale_c > 0.

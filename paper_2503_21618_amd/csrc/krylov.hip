@@ -46,6 +46,29 @@ __device__ __forceinline__ void stv(cx<R>* p, const cvec<R, V>& v) {
   *reinterpret_cast<cvec<R, V>*>(p) = v;
 }
 
+// Streamed blocks (written or read once per launch): non-temporal accesses, so
+// that they do not evict the gathered input rows from L2.
+template <typename R, int V>
+__device__ __forceinline__ cvec<R, V> ldv_nt(const cx<R>* p) {
+  using W = R __attribute__((ext_vector_type(2 * V)));
+  const W w = __builtin_nontemporal_load(reinterpret_cast<const W*>(p));
+  cvec<R, V> out;
+#pragma unroll
+  for (int v = 0; v < V; ++v) out.c[v] = {w[2 * v], w[2 * v + 1]};
+  return out;
+}
+template <typename R, int V>
+__device__ __forceinline__ void stv_nt(cx<R>* p, const cvec<R, V>& v) {
+  using W = R __attribute__((ext_vector_type(2 * V)));
+  W w;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    w[2 * u] = v.c[u].re;
+    w[2 * u + 1] = v.c[u].im;
+  }
+  __builtin_nontemporal_store(w, reinterpret_cast<W*>(p));
+}
+
 struct WgPos {
   int x, q, per, lane, w;
 };
@@ -62,7 +85,7 @@ __device__ __forceinline__ WgPos wg_pos(int G) {
 
 // row block of step t for this workgroup in pencil I, or -1 once past its slab
 __device__ __forceinline__ int step_block(const Inst& I, const WgPos& p, int t) {
-  const int j = t * p.per + p.q;
+  const int j = t * p.per + (p.q + I.rot) % p.per;
   if (j >= I.slab) return -1;
   const int rb = p.x * I.slab + j;
   return rb < I.nrb ? rb : -1;
@@ -260,6 +283,23 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
   }              \
   }
 
+// Row loop of the vector updates: a wavefront takes U of its rows at a time
+// (positions q, q + 4, ..., in the order FOR_ROWS visits them), so that all
+// their loads are issued before the first store.  ic[u] is row u's index clamped
+// into the block (in bounds for loads); ok[u] says whether row u exists.
+#define FOR_ROW_BATCH(b, p, I, U)                                             \
+  for (int t_ = 0; t_ < (I).steps; ++t_) {                                    \
+    const int rb_ = step_block((I), (p), t_);                                 \
+    if (rb_ < 0) break;                                                       \
+    const int r1_ = min((rb_ + 1) * (b).rows_per_block, (I).n);               \
+    for (int q_ = rb_ * (b).rows_per_block + (p).w; q_ < r1_; q_ += 4 * (U)) { \
+      int ic[U];                                                              \
+      bool ok[U];                                                             \
+      _Pragma("unroll") for (int u = 0; u < (U); ++u) {                       \
+        ok[u] = q_ + 4 * u < r1_;                                             \
+        ic[u] = ok[u] ? q_ + 4 * u : r1_ - 1;                                 \
+      }
+
 // Row loop of the sparse products for one tile: the workgroup's row blocks of
 // pencil I; emit(i, q) receives row i's product.  When the row block is a
 // multiple of 16 rows and the pencil has stencil groups, wavefront w takes the
@@ -327,9 +367,9 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, in
       spmm_rows<R, V, GRP>(b, p, I, I.ab, st.ph + I.blk + cc0, sig, [&](int i, const cvec<R, V>& q) {
         if (!valid) return;
         const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-        stv<R, V>(st.v + e, q);
+        stv_nt<R, V>(st.v + e, q);
         if (st.rhat_cx) {  // conj(rhat) * v
-          const cvec<R, V> rh = ldv<R, V>(st.rhat_cx + e);
+          const cvec<R, V> rh = ldv_nt<R, V>(st.rhat_cx + e);
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             d[v].re += rh.c[v].re * q.c[v].re + rh.c[v].im * q.c[v].im;
@@ -365,10 +405,10 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, in
       spmm_rows<R, V, GRP>(b, p, I, I.ab, st.sh + I.blk + cc0, sig, [&](int i, const cvec<R, V>& tv) {
         if (valid) {
           const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-          stv<R, V>(st.t + e, tv);
+          stv_nt<R, V>(st.t + e, tv);
           cvec<R, V> sv;
           if (st.s) {
-            sv = ldv<R, V>(st.s + e);
+            sv = ldv_nt<R, V>(st.s + e);
           } else {
             const cvec<R, V> shv = ldv<R, V>(st.sh + e);
 #pragma unroll
@@ -396,7 +436,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, in
 // p_hat for those pencils, and Jacobi pencils of the same batch form
 // p_hat = p / d here.  Columns that are not active keep their values.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int first, int* counter) {
+__global__ __launch_bounds__(WG, 4) void k_update_p(Batch b, KrylovState<R> st, int first, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
@@ -420,38 +460,44 @@ __global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int
 #pragma unroll
     for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
     const bool jac_here = !I.ilu && !I.bjac;
-    FOR_ROWS(b, p, I)
-      const int i = pos;
-      const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-      const size_t de = I.dn + (size_t)i * I.N;
-      const cvec<R, V> r = ldv<R, V>(st.r + e);
-      if (st.p) {
-        cvec<R, V> pv, vv, ph;
-        if (!first || keep) pv = ldv<R, V>(st.p + e);
-        if (!first) vv = ldv<R, V>(st.v + e);
-        if (jac_here && keep) ph = ldv<R, V>(st.ph + e);
+    constexpr int kRowBatch = 4;
+    FOR_ROW_BATCH(b, p, I, kRowBatch)
+      size_t e[kRowBatch];
+      cvec<R, V> r[kRowBatch], pv[kRowBatch], vv[kRowBatch], ph[kRowBatch];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          if (f[v] != COL_ACTIVE) continue;
-          cx<R> pn = r.c[v];
-          if (!first) pn = cadd(pn, cmul(beta[v], csub(pv.c[v], cmul(omega[v], vv.c[v]))));
-          pv.c[v] = pn;
-          if (jac_here) ph.c[v] = cmul(pn, st.dinv[de + pole[v]]);
-        }
-        stv<R, V>(st.p + e, pv);
-        if (jac_here) stv<R, V>(st.ph + e, ph);
-      } else {
-        cvec<R, V> ph, vv;
-        if (!first || keep) ph = ldv<R, V>(st.ph + e);
-        if (!first) vv = ldv<R, V>(st.v + e);
+      for (int u = 0; u < kRowBatch; ++u) {
+        e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+        r[u] = ldv<R, V>(st.r + e[u]);
+        if (!first || keep) pv[u] = ldv<R, V>(st.p ? st.p + e[u] : st.ph + e[u]);
+        if (!first) vv[u] = ldv<R, V>(st.v + e[u]);
+        if (st.p && jac_here && keep) ph[u] = ldv<R, V>(st.ph + e[u]);
+      }
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          if (f[v] != COL_ACTIVE) continue;
-          cx<R> pn = r.c[v];
-          if (!first) pn = cadd(pn, cmul(beta[v], csub(cmul(st.d[de + pole[v]], ph.c[v]), cmul(omega[v], vv.c[v]))));
-          ph.c[v] = cmul(pn, st.dinv[de + pole[v]]);
+      for (int u = 0; u < kRowBatch; ++u) {
+        if (!ok[u]) continue;
+        const size_t de = I.dn + (size_t)ic[u] * I.N;
+        if (st.p) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (f[v] != COL_ACTIVE) continue;
+            cx<R> pn = r[u].c[v];
+            if (!first) pn = cadd(pn, cmul(beta[v], csub(pv[u].c[v], cmul(omega[v], vv[u].c[v]))));
+            pv[u].c[v] = pn;
+            if (jac_here) ph[u].c[v] = cmul(pn, st.dinv[de + pole[v]]);
+          }
+          stv<R, V>(st.p + e[u], pv[u]);
+          if (jac_here) stv<R, V>(st.ph + e[u], ph[u]);
+        } else {  // pv holds p_hat
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (f[v] != COL_ACTIVE) continue;
+            cx<R> pn = r[u].c[v];
+            if (!first)
+              pn = cadd(pn, cmul(beta[v], csub(cmul(st.d[de + pole[v]], pv[u].c[v]), cmul(omega[v], vv[u].c[v]))));
+            pv[u].c[v] = cmul(pn, st.dinv[de + pole[v]]);
+          }
+          stv<R, V>(st.ph + e[u], pv[u]);
         }
-        stv<R, V>(st.ph + e, ph);
       }
     END_ROWS
   }
@@ -461,7 +507,7 @@ __global__ __launch_bounds__(WG) void k_update_p(Batch b, KrylovState<R> st, int
 // with ILU(0) or block-Jacobi pencils s is stored, plus s_hat = s / d for its
 // Jacobi pencils) ; partial |s|^2
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int* counter) {
+__global__ __launch_bounds__(WG, 4) void k_update_s(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
@@ -484,24 +530,33 @@ __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int
 #pragma unroll
         for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
         const bool jac_here = !st.s || (!I.ilu && !I.bjac);
-        FOR_ROWS(b, p, I)
-          const int i = pos;
-          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-          const size_t de = I.dn + (size_t)i * I.N;
-          const cvec<R, V> r = ldv<R, V>(st.r + e), vv = ldv<R, V>(st.v + e);
-          cvec<R, V> sv, sh;
-          if (st.s && keep) sv = ldv<R, V>(st.s + e);
-          if (jac_here && keep) sh = ldv<R, V>(st.sh + e);
+        constexpr int kRowBatch = 4;
+        FOR_ROW_BATCH(b, p, I, kRowBatch)
+          size_t e[kRowBatch];
+          cvec<R, V> r[kRowBatch], vv[kRowBatch], sv[kRowBatch], sh[kRowBatch];
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            if (f[v] != COL_ACTIVE) continue;
-            const cx<R> s = csub(r.c[v], cmul(alpha[v], vv.c[v]));
-            ss[v] += s.re * s.re + s.im * s.im;
-            sv.c[v] = s;
-            if (jac_here) sh.c[v] = cmul(s, st.dinv[de + pole[v]]);
+          for (int u = 0; u < kRowBatch; ++u) {
+            e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+            r[u] = ldv<R, V>(st.r + e[u]);
+            vv[u] = ldv<R, V>(st.v + e[u]);
+            if (st.s && keep) sv[u] = ldv<R, V>(st.s + e[u]);
+            if (jac_here && keep) sh[u] = ldv<R, V>(st.sh + e[u]);
           }
-          if (st.s) stv<R, V>(st.s + e, sv);
-          if (jac_here) stv<R, V>(st.sh + e, sh);
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) {
+            if (!ok[u]) continue;
+            const size_t de = I.dn + (size_t)ic[u] * I.N;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              if (f[v] != COL_ACTIVE) continue;
+              const cx<R> s = csub(r[u].c[v], cmul(alpha[v], vv[u].c[v]));
+              ss[v] += s.re * s.re + s.im * s.im;
+              sv[u].c[v] = s;
+              if (jac_here) sh[u].c[v] = cmul(s, st.dinv[de + pole[v]]);
+            }
+            if (st.s) stv<R, V>(st.s + e[u], sv[u]);
+            if (jac_here) stv<R, V>(st.sh + e[u], sh[u]);
+          }
         END_ROWS
       }
     }
@@ -512,7 +567,7 @@ __global__ __launch_bounds__(WG) void k_update_s(Batch b, KrylovState<R> st, int
 // x += alpha p_hat + omega s_hat ; r = s - omega t ; partials (rhat, r), |r|^2
 // Columns that converged at the half step take x += alpha p_hat only.
 template <typename R>
-__global__ __launch_bounds__(WG) void k_update_x(Batch b, KrylovState<R> st, int first, int* counter) {
+__global__ __launch_bounds__(WG, 4) void k_update_x(Batch b, KrylovState<R> st, int first, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
@@ -542,52 +597,62 @@ __global__ __launch_bounds__(WG) void k_update_x(Batch b, KrylovState<R> st, int
           keep_r |= !act[v];
           any_act |= act[v];
         }
-        FOR_ROWS(b, p, I)
-          const int i = pos;
-          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
-          const size_t de = I.dn + (size_t)i * I.N;
-          cvec<R, V> x;
-          if (first && !keep_x) {
+        constexpr int kRowBatch = 2;
+        FOR_ROW_BATCH(b, p, I, kRowBatch)
+          size_t e[kRowBatch];
+          cvec<R, V> x[kRowBatch], ph[kRowBatch], sh[kRowBatch], t[kRowBatch], r[kRowBatch], sv[kRowBatch],
+              rh[kRowBatch];
+          cx<R> dg[kRowBatch][V];
+          R rr[kRowBatch][V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) x.c[v] = {0, 0};
-          } else {
-            x = ldv<R, V>(st.x + e);
-            if (first) {
+          for (int u = 0; u < kRowBatch; ++u) {
+            e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+            if (!first || keep_x) x[u] = ldv<R, V>(st.x + e[u]);
+            ph[u] = ldv<R, V>(st.ph + e[u]);
+            if (any_act) {
+              sh[u] = ldv<R, V>(st.sh + e[u]);
+              t[u] = ldv<R, V>(st.t + e[u]);
+              if (st.s) {
+                sv[u] = ldv<R, V>(st.s + e[u]);
+              } else {
+                const size_t de = I.dn + (size_t)ic[u] * I.N;
 #pragma unroll
-              for (int v = 0; v < V; ++v)
-                if (act[v] || half[v]) x.c[v] = {0, 0};
+                for (int v = 0; v < V; ++v) dg[u][v] = st.d[de + pole[v]];
+              }
+              if (st.rhat_cx) {
+                rh[u] = ldv<R, V>(st.rhat_cx + e[u]);
+              } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) rr[u][v] = st.rhat[I.rl + (size_t)ic[u] * I.L + (cc0 + v) % I.L];
+              }
             }
+            if (keep_r) r[u] = ldv<R, V>(st.r + e[u]);
           }
-          const cvec<R, V> ph = ldv<R, V>(st.ph + e);
-          cvec<R, V> sh, t, r, sv, rh;
-          if (any_act) {
-            sh = ldv<R, V>(st.sh + e);
-            t = ldv<R, V>(st.t + e);
-            if (st.s) sv = ldv<R, V>(st.s + e);
-            if (st.rhat_cx) rh = ldv<R, V>(st.rhat_cx + e);
-          }
-          if (keep_r) r = ldv<R, V>(st.r + e);
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            if (!act[v] && !half[v]) continue;
-            x.c[v] = cadd(x.c[v], cmul(alpha[v], ph.c[v]));
-            if (!act[v]) continue;
-            x.c[v] = cadd(x.c[v], cmul(omega[v], sh.c[v]));
-            const cx<R> s = st.s ? sv.c[v] : cmul(st.d[de + pole[v]], sh.c[v]);
-            const cx<R> rv = csub(s, cmul(omega[v], t.c[v]));
-            r.c[v] = rv;
-            if (st.rhat_cx) {
-              rd[v].re += rh.c[v].re * rv.re + rh.c[v].im * rv.im;
-              rd[v].im += rh.c[v].re * rv.im - rh.c[v].im * rv.re;
-            } else {
-              const R rr = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
-              rd[v].re += rr * rv.re;
-              rd[v].im += rr * rv.im;
+          for (int u = 0; u < kRowBatch; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              if (first && (act[v] || half[v] || !keep_x)) x[u].c[v] = {0, 0};
+              if (!act[v] && !half[v]) continue;
+              x[u].c[v] = cadd(x[u].c[v], cmul(alpha[v], ph[u].c[v]));
+              if (!act[v]) continue;
+              x[u].c[v] = cadd(x[u].c[v], cmul(omega[v], sh[u].c[v]));
+              const cx<R> s = st.s ? sv[u].c[v] : cmul(dg[u][v], sh[u].c[v]);
+              const cx<R> rv = csub(s, cmul(omega[v], t[u].c[v]));
+              r[u].c[v] = rv;
+              if (st.rhat_cx) {
+                rd[v].re += rh[u].c[v].re * rv.re + rh[u].c[v].im * rv.im;
+                rd[v].im += rh[u].c[v].re * rv.im - rh[u].c[v].im * rv.re;
+              } else {
+                rd[v].re += rr[u][v] * rv.re;
+                rd[v].im += rr[u][v] * rv.im;
+              }
+              nn[v] += rv.re * rv.re + rv.im * rv.im;
             }
-            nn[v] += rv.re * rv.re + rv.im * rv.im;
+            if (any_act) stv<R, V>(st.r + e[u], r[u]);
+            stv<R, V>(st.x + e[u], x[u]);
           }
-          if (any_act) stv<R, V>(st.r + e, r);
-          stv<R, V>(st.x + e, x);
         END_ROWS
       }
     }
@@ -626,16 +691,27 @@ __global__ __launch_bounds__(WG) void k_init(Batch b, KrylovState<R> st, const R
 // ---------------------------------------------------------------------------
 // Per-column scalar kernels: one 256-thread block per global tile, each lane
 // handling V columns.  The sum over the G partials is split across the 4
-// wavefronts (partials w, w + 4, ..., loads kept in flight by unrolling) and
-// combined in a fixed order; wavefront 0 then applies the update.
+// wavefronts (slots k = w, w + 4, ..., loads kept in flight by unrolling) and
+// combined in a fixed order; wavefront 0 then applies the update.  Slot k is row
+// block slot k >> 3 of XCD k & 7; its partial sits in the row of the workgroup
+// that the pencil's rotation gave that slot.  Summing in slot order makes the
+// result independent of the grid size and of the rotation: a pencil's sums are
+// the same alone and in a batch (a larger grid only appends zero partials).
+__device__ __forceinline__ size_t slot_partial(int k, int per, int rot) {
+  int q = (k >> 3) - rot;
+  if (q < 0) q += per;
+  return (size_t)(8 * q + (k & 7));
+}
+
 template <typename T>
-__device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int Ktot, int c, bool valid) {
+__device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int rot, int Ktot, int c,
+                                           bool valid) {
   __shared__ T red[4][WAVE];
-  const int w = wave_id(), lane = lane_id();
+  const int w = wave_id(), lane = lane_id(), per = G >> 3;
   T acc = 0;
   if (valid) {
 #pragma unroll 8
-    for (int g = w; g < G; g += 4) acc += part[(size_t)g * Ktot + c];
+    for (int k = w; k < G; k += 4) acc += part[slot_partial(k, per, rot) * Ktot + c];
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -645,14 +721,15 @@ __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, in
 }
 
 template <typename R>
-__device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int Ktot, int c, bool valid) {
+__device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int rot, int Ktot, int c,
+                                                  bool valid) {
   __shared__ R rr[4][WAVE], ri[4][WAVE];
-  const int w = wave_id(), lane = lane_id();
+  const int w = wave_id(), lane = lane_id(), per = G >> 3;
   R ar = 0, ai = 0;
   if (valid) {
 #pragma unroll 8
-    for (int g = w; g < G; g += 4) {
-      const cx<R> v = part[(size_t)g * Ktot + c];
+    for (int k = w; k < G; k += 4) {
+      const cx<R> v = part[slot_partial(k, per, rot) * Ktot + c];
       ar += v.re;
       ai += v.im;
     }
@@ -687,7 +764,7 @@ __global__ __launch_bounds__(WG) void k_sc_alpha(Batch b, KrylovState<R> st) {
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const cx<R> rv = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
+    const cx<R> rv = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
     if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
     const cx<R> rho = st.rho[c];
     if ((rv.re == 0 && rv.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(rv)) {
@@ -709,7 +786,7 @@ __global__ __launch_bounds__(WG) void k_sc_half(Batch b, KrylovState<R> st, R to
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const R sn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, ok));
+    const R sn = sqrt(block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok));
     if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
     if (sn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
       st.flags[c] = COL_HALF_PENDING;
@@ -728,8 +805,8 @@ __global__ __launch_bounds__(WG) void k_sc_omega(Batch b, KrylovState<R> st) {
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const cx<R> ts = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
-    const R tt = block_col_sum(st.part_b, b.G, b.Ktot, c, ok);
+    const cx<R> ts = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    const R tt = block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok);
     if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
     if (tt == 0 || !isfinite(tt)) {
       st.flags[c] = COL_BREAKDOWN;
@@ -749,8 +826,8 @@ __global__ __launch_bounds__(WG) void k_sc_beta(Batch b, KrylovState<R> st, R to
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const cx<R> rn = block_col_sum_cx(st.part_a, b.G, b.Ktot, c, ok);
-    const R nn = sqrt(block_col_sum(st.part_b, b.G, b.Ktot, c, ok));
+    const cx<R> rn = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    const R nn = sqrt(block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok));
     if (!lead || !ok) continue;
     const int f = st.flags[c];
     if (f == COL_HALF_PENDING) {
@@ -790,7 +867,7 @@ __global__ __launch_bounds__(WG) void k_init_scalars(Batch b, KrylovState<R> st)
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const R nn = block_col_sum(st.part_b, b.G, b.Ktot, c, ok);
+    const R nn = block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok);
     if (!lead || cl0 + v >= I.Kp) continue;
     st.fnorm[c] = sqrt(nn);
     st.rnorm[c] = sqrt(nn);
@@ -1002,12 +1079,23 @@ void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* o
 // batch is the FP32 one, so a lane owns kMixedV adjacent columns.
 constexpr int kMixedV = LaneWidth<float>::V;
 
+// true if some column of the tile has scale > 0 (has not met its target)
+template <int V>
+__device__ __forceinline__ bool tile_open(const double* scale, int cg0, int cl0, int K) {
+  bool open = false;
+#pragma unroll
+  for (int v = 0; v < V; ++v) open |= cl0 + v < K && scale[cg0 + v] > 0;
+  return __any(open);
+}
+
 __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __restrict__ sigma_col,
                                               const double* __restrict__ F, const cx<double>* __restrict__ Y,
-                                              cx<double>* __restrict__ Rout, double* __restrict__ part) {
+                                              cx<double>* __restrict__ Rout, double* __restrict__ part,
+                                              const double* __restrict__ scale) {
   constexpr int V = kMixedV;
   const WgPos p = wg_pos(b.G);
   FOR_TILES(b, p, V)
+    if (Y && !tile_open<V>(scale, cg0, cl0, I.K)) continue;  // every column already met its target
     cx<double> sig[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) sig[v] = sigma_col[cg0 + v];
@@ -1040,8 +1128,8 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
 }
 
 void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, const double* F,
-                   const cx<double>* Y, cx<double>* Rout, double* part) {
-  k_defect<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, sigma_col, F, Y, Rout, part);
+                   const cx<double>* Y, cx<double>* Rout, double* part, const double* scale) {
+  k_defect<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, sigma_col, F, Y, Rout, part, scale);
 }
 
 // scale_c = ||R_c|| unless the defect meets its target; the next FP32 solve of
@@ -1058,8 +1146,10 @@ __global__ __launch_bounds__(WG) void k_defect_norms(Batch b, const double* __re
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const double r = sqrt(block_col_sum(part, b.G, b.Ktot, c, ok));
-    if (!lead || cl0 + v >= I.Kp) continue;
+    // a column that met its target keeps its values (its Y no longer changes)
+    const bool fresh = ok && (first || scale[c] > 0);
+    const double r = sqrt(block_col_sum(part, b.G, I.rot, b.Ktot, c, fresh));
+    if (!lead || cl0 + v >= I.Kp || (ok && !fresh)) continue;
     if (first) fnorm[c] = r;
     const double fn = fnorm[c];
     const bool done = !ok || r <= tol[c] * fn;
@@ -1098,7 +1188,7 @@ __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __r
   const WgPos p = wg_pos(b.G);
   FOR_TILES(b, p, V)
     float nn[V] = {};
-    if (valid) {
+    if (valid && tile_open<V>(scale, cg0, cl0, I.K)) {
       double inv[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -1138,7 +1228,7 @@ __global__ __launch_bounds__(WG) void k_accumulate(Batch b, const cx<float>* __r
   const WgPos p = wg_pos(b.G);
   FOR_TILES(b, p, V)
     (void)po;
-    if (!valid) continue;
+    if (!valid || (!first && !tile_open<V>(scale, cg0, cl0, I.K))) continue;
     double sc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) sc[v] = cl0 + v < I.K ? scale[cg0 + v] : 0.0;
@@ -1147,10 +1237,14 @@ __global__ __launch_bounds__(WG) void k_accumulate(Batch b, const cx<float>* __r
       const cvec<float, V> xv = ldv<float, V>(x + e);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        cx<double> y = first ? cx<double>{0.0, 0.0} : Y[e + v];
-        y.re += sc[v] * (double)xv.c[v].re;
-        y.im += sc[v] * (double)xv.c[v].im;
-        Y[e + v] = y;
+        if (sc[v] > 0) {
+          cx<double> y = first ? cx<double>{0.0, 0.0} : Y[e + v];
+          y.re += sc[v] * (double)xv.c[v].re;
+          y.im += sc[v] * (double)xv.c[v].im;
+          Y[e + v] = y;
+        } else if (first) {
+          Y[e + v] = {0.0, 0.0};
+        }
       }
     END_ROWS
   }

@@ -584,10 +584,14 @@ struct FilterLayout {
 };
 
 // Columns per lane of the Krylov kernels: 2 adjacent complex FP32 values or one
-// complex FP64 value (16 B either way).  A pencil's blocks have leading
-// dimension Kp = K rounded up to that width; a tile is 64 lanes wide.
+// complex FP64 value (16 B either way); a tile is 64 lanes wide.  A pencil's
+// blocks have leading dimension Kp = K rounded up to 16 columns, so that every
+// row of a tile starts on a 128 B cache line (rows that straddle lines cost the
+// gathers of the sparse product about 15%).  16 divides the tile widths, so the
+// padding never adds a tile.
+constexpr int kColAlign = 16;
 int lane_width(bool mixed) { return mixed ? 2 : 1; }
-int64_t padded_k(int64_t K, int V) { return (K + V - 1) / V * V; }
+int64_t padded_k(int64_t K) { return (K + kColAlign - 1) / kColAlign * kColAlign; }
 
 void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo) {
   lo = FilterLayout{};
@@ -595,7 +599,7 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   bool any_general = false;
   const int V = lane_width(mixed);
   for (const auto& j : js) {
-    const int64_t Kp = padded_k((int64_t)j.N * j.L, V);
+    const int64_t Kp = padded_k((int64_t)j.N * j.L);
     lo.EB += j.n * Kp;
     lo.ER += j.n * j.L;
     lo.ED += j.n * j.N;
@@ -712,6 +716,9 @@ void apply_tiling(std::vector<Inst>& insts, Batch& b, Tiling t) {
     I.nrb = (I.n + t.rpb - 1) / t.rpb;
     I.slab = (I.nrb + 7) / 8;
     I.steps = (I.slab + per - 1) / per;
+    // spreads pencils smaller than the grid over the workgroups; depends on the
+    // pencil and the grid only, so a pencil computes the same alone and in a batch
+    I.rot = (int)((uint32_t)I.n * 2654435761u % (uint32_t)per);
   }
 }
 
@@ -748,7 +755,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.L = j.L;
     I.N = j.N;
     I.K = j.N * j.L;
-    I.Kp = (int)padded_k(I.K, b.V);
+    I.Kp = (int)padded_k(I.K);
     I.col0 = col0;
     I.tile0 = tile0;
     I.nnz = (int)j.P->nnz;
@@ -996,7 +1003,7 @@ slrf_status collect_stats(Env& env, std::vector<FilterJob>& jobs, const KrylovSt
   for (size_t q = 0; q < jobs.size(); ++q) {
     slrf_filter_stats& fs = jobs[q].stats;
     const int K = jobs[q].N * jobs[q].L;
-    const int Kp = (int)padded_k(K, sizeof(R) == 4 ? 2 : 1);
+    const int Kp = (int)padded_k(K);
     for (int k = 0; k < Kp; ++k, ++c) {
       if (k >= K) continue;
       fs.max_iterations = std::max(fs.max_iterations, its[c]);
@@ -1068,8 +1075,9 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   if (rs != SLRF_OK) return rs;
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
-    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, j.N * j.L, st.x + blk, lo.w + 2 * wj, j.U, false);
-    blk += j.P->n * (int64_t)j.N * j.L;
+    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, (int)padded_k(j.N * j.L), st.x + blk, lo.w + 2 * wj, j.U,
+                              false);
+    blk += j.P->n * padded_k(j.N * j.L);
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1105,7 +1113,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   // gap between the current defect and that target.
   std::vector<double> tol_host;
   for (auto& j : jobs)
-    for (int64_t c = 0; c < padded_k(j.N * j.L, 2); ++c) tol_host.push_back(j.target);
+    for (int64_t c = 0; c < padded_k(j.N * j.L); ++c) tol_host.push_back(j.target);
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
   st.tolc = lo.tol32;
@@ -1125,7 +1133,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   std::vector<double> sum_it(jobs.size(), 0.0), it_round;
   int rounds = 0;
   for (int round = 0; round <= kMaxRounds; ++round) {
-    launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64);
+    launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64, lo.scale);
     launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.tol32,
                         kInnerTol32, lo.count);
     HIPCHK(env, hipGetLastError());
@@ -1155,11 +1163,11 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
     if (rounds > 0)
-      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, (int)padded_k(j.N * j.L, 2), lo.Y + blk,
+      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, (int)padded_k(j.N * j.L), lo.Y + blk,
                                 lo.w + 2 * wj, j.U, false);
     else
       HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
-    blk += j.P->n * padded_k(j.N * j.L, 2);
+    blk += j.P->n * padded_k(j.N * j.L);
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1169,7 +1177,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   int64_t c = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
     const int K = jobs[q].N * jobs[q].L;
-    for (int k = 0; k < padded_k(K, 2); ++k, ++c)
+    for (int k = 0; k < padded_k(K); ++k, ++c)
       if (k < K) jobs[q].stats.max_relres = std::max(jobs[q].stats.max_relres, rr[c]);
   }
   finish_stats(jobs, sum_it, ks, now_s() - t0, rounds);
