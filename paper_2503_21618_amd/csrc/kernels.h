@@ -161,9 +161,10 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
                         const cx<R>* sigma, cx<R>* d, cx<R>* dinv);
-// U = sum_j 2 Re(w_j x[:, j L .. j L + L)), x row-major (n, ld)
+// U = sum_j 2 Re(w_j x[:, j L .. j L + L)), x a tile-major block (tiles of W
+// columns, each an n x W row-major panel)
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, int ld, const cx<R>* x,
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, const cx<R>* x,
                        const double* w /* 2N */, double* U, bool accumulate);
 
 // real products with the merged pencil: AX = A X, BX = B X (either may be null)

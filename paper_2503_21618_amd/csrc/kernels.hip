@@ -30,25 +30,25 @@ void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* di
 
 // U[i, l] (+)= sum_j 2 Re(w_j x[i, j L + l])
 template <typename R>
-__global__ void k_filter_sum(int n, int L, int N, int ld, const cx<R>* __restrict__ x,
+__global__ void k_filter_sum(int n, int L, int N, int W, const cx<R>* __restrict__ x,
                              const double* __restrict__ w, double* __restrict__ U, int accumulate) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * L) return;
   const int64_t i = e / L;
   const int l = (int)(e % L);
-  const int64_t K = ld;
   double s = accumulate ? U[e] : 0.0;
   for (int j = 0; j < N; ++j) {
-    const cx<R> y = x[i * K + (int64_t)j * L + l];
+    const int c = j * L + l;  // tile-major block: tile c / W is an n x W panel
+    const cx<R> y = x[(int64_t)(c / W) * n * W + i * W + c % W];
     s += 2.0 * (w[2 * j] * (double)y.re - w[2 * j + 1] * (double)y.im);
   }
   U[e] = s;
 }
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, int ld, const cx<R>* x, const double* w, double* U,
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, const cx<R>* x, const double* w, double* U,
                        bool accumulate) {
   const int64_t tot = (int64_t)n * L;
-  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, ld, x, w, U,
+  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, x, w, U,
                                                                              accumulate ? 1 : 0);
 }
 

@@ -7,9 +7,11 @@
 //
 // Lane width.  A lane owns V adjacent columns: V = 1 for complex FP64 (16 B per
 // element), V = 2 for complex FP32, so that every gather and vector access moves
-// 16 B per lane in both precisions.  A tile is 64 V columns.  A pencil's blocks
-// are row-major (n, Kp) with Kp = K rounded up to a multiple of V; the padding
-// column has a zero right-hand side and is never active.
+// 16 B per lane in both precisions.  A tile is W = 64 V columns.  A pencil has
+// Kp = K rounded up to a multiple of W columns; the padding columns have a zero
+// right-hand side and are never active.  Its blocks are stored tile-major: tile
+// t is an n x W row-major panel (see tile_base), so each row of a tile is one
+// 1 KB line-aligned slice and the panel of a tile is contiguous.
 //
 // Work decomposition: a grid of G workgroups of 256 threads (4 wavefronts of
 // 64) walks the tiles in order.  Within a tile each wavefront walks every 4th
@@ -21,7 +23,8 @@
 // close and the neighbours gathered by the sparse product are re-read from that
 // XCD's L2.  The 4 wavefronts are combined through LDS and the G workgroups by
 // per-column kernels that sum the [G][Ktot] partials in a fixed order (bitwise
-// reproducible).
+// reproducible).  A pencil's row-block slots are rotated over the XCD's
+// workgroups by Inst::rot, so a batch of small pencils loads them evenly.
 #include "device_util.h"
 
 namespace slrf {
@@ -165,7 +168,7 @@ __device__ __forceinline__ void wg_store_partial_cx(const cx<R> (&v)[V], int w, 
 // their contributions are discarded).
 template <typename R, int V, int CH>
 __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
-                                                  const cx<R>* __restrict__ Pc, int Kp, const cx<R> (&sig)[V]) {
+                                                  const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V]) {
   static_assert(CH <= kCsrPad, "chunk longer than the CSR padding");
   const int k0 = rowptr[i], k1 = rowptr[i + 1];
   R apr[V] = {}, api[V] = {}, bpr[V] = {}, bpi[V] = {};
@@ -186,7 +189,7 @@ __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<
     }
     cvec<R, V> x[CH];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * Kp);
+    for (int u = 0; u < CH; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
 #pragma unroll
@@ -217,7 +220,7 @@ constexpr int kGroupRows = 4;  // rows of a stencil group (flags built on the ho
 // order, as in shifted_row.
 template <typename R, int V>
 __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
-                                              const cx<R>* __restrict__ Pc, int Kp, const cx<R> (&sig)[V],
+                                              const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V],
                                               cvec<R, V> (&q)[kGroupRows]) {
   int kb[kGroupRows];
 #pragma unroll
@@ -229,7 +232,7 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
     const int c0 = col[kb[0] + j];
     cvec<R, V> w[kGroupRows + 2];
 #pragma unroll
-    for (int t = 0; t < kGroupRows + 2; ++t) w[t] = ldv<R, V>(Pc + (size_t)(c0 + t) * Kp);
+    for (int t = 0; t < kGroupRows + 2; ++t) w[t] = ldv<R, V>(Pc + (size_t)(c0 + t) * ld);
 #pragma unroll
     for (int r = 0; r < kGroupRows; ++r) {
 #pragma unroll
@@ -253,6 +256,14 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
                    api[r][v] - (sig[v].re * bpi[r][v] + sig[v].im * bpr[r][v])};
 }
 
+// Block layout: a pencil's n x Kp block is stored tile by tile.  Tile t holds
+// columns [t W, (t + 1) W) (W = 64 V, Kp a multiple of W) as an n x W row-major
+// panel, so the rows a tile's kernels gather are W * 8 or W * 16 bytes apart
+// whatever the number of columns.
+__device__ __forceinline__ size_t tile_base(const Inst& I, int t, int V) {
+  return I.blk + (size_t)t * (size_t)I.n * (WAVE * V);
+}
+
 // Loop header shared by the batched kernels: tile tg of pencil I.  cl0 is the
 // lane's first column within the pencil (a multiple of V), cc0 that column
 // clamped into the padded range, cg0 its global column; column v of the lane is
@@ -266,6 +277,7 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
     const bool valid = cl0 < I.K;                                            \
     const int cc0 = min(cl0, I.Kp - (V));                                    \
     const int cg0 = I.col0 + cc0;                                            \
+    const size_t tb = tile_base(I, tg - I.tile0, (V)) + (size_t)(p).lane * (V); \
     const size_t po = (size_t)blockIdx.x * (b).Ktot + I.col0 + (size_t)(tg - I.tile0) * (WAVE * (V));
 
 #define FOR_TILES(b, p, V) FOR_TILE_LIST(b, p, V, (b).n_tiles, ti_)
@@ -328,7 +340,7 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
         if constexpr (GRP) {
           if (grp) {
             cvec<R, V> q[kGroupRows];
-            shifted_group<R, V>(i0, rowptr, col, ab, Pc, I.Kp, sig, q);
+            shifted_group<R, V>(i0, rowptr, col, ab, Pc, WAVE * V, sig, q);
 #pragma unroll
             for (int u = 0; u < kGroupRows; ++u) emit(i0 + u, q[u]);
             continue;
@@ -337,14 +349,14 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
         {
           for (int u = 0; u < cnt; ++u) {
             const int i = I.sched ? as_const(I.sched)[q0 + u] : q0 + u;
-            emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, I.Kp, sig));
+            emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, WAVE * V, sig));
           }
         }
       }
     } else {
       for (int pos = r0 + p.w; pos < r1; pos += 4) {
         const int i = I.sched ? as_const(I.sched)[pos] : pos;
-        emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, I.Kp, sig));
+        emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, WAVE * V, sig));
       }
     }
   }
@@ -364,9 +376,9 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, in
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.ph + I.blk + cc0, sig, [&](int i, const cvec<R, V>& q) {
+      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.ph + tb, sig, [&](int i, const cvec<R, V>& q) {
         if (!valid) return;
-        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        const size_t e = tb + (size_t)i * (WAVE * V);
         stv_nt<R, V>(st.v + e, q);
         if (st.rhat_cx) {  // conj(rhat) * v
           const cvec<R, V> rh = ldv_nt<R, V>(st.rhat_cx + e);
@@ -402,9 +414,9 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, in
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.sh + I.blk + cc0, sig, [&](int i, const cvec<R, V>& tv) {
+      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.sh + tb, sig, [&](int i, const cvec<R, V>& tv) {
         if (valid) {
-          const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+          const size_t e = tb + (size_t)i * (WAVE * V);
           stv_nt<R, V>(st.t + e, tv);
           cvec<R, V> sv;
           if (st.s) {
@@ -466,7 +478,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_p(Batch b, KrylovState<R> st, 
       cvec<R, V> r[kRowBatch], pv[kRowBatch], vv[kRowBatch], ph[kRowBatch];
 #pragma unroll
       for (int u = 0; u < kRowBatch; ++u) {
-        e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+        e[u] = tb + (size_t)ic[u] * (WAVE * V);
         r[u] = ldv<R, V>(st.r + e[u]);
         if (!first || keep) pv[u] = ldv<R, V>(st.p ? st.p + e[u] : st.ph + e[u]);
         if (!first) vv[u] = ldv<R, V>(st.v + e[u]);
@@ -536,7 +548,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_s(Batch b, KrylovState<R> st, 
           cvec<R, V> r[kRowBatch], vv[kRowBatch], sv[kRowBatch], sh[kRowBatch];
 #pragma unroll
           for (int u = 0; u < kRowBatch; ++u) {
-            e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+            e[u] = tb + (size_t)ic[u] * (WAVE * V);
             r[u] = ldv<R, V>(st.r + e[u]);
             vv[u] = ldv<R, V>(st.v + e[u]);
             if (st.s && keep) sv[u] = ldv<R, V>(st.s + e[u]);
@@ -606,7 +618,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_x(Batch b, KrylovState<R> st, 
           R rr[kRowBatch][V];
 #pragma unroll
           for (int u = 0; u < kRowBatch; ++u) {
-            e[u] = I.blk + (size_t)ic[u] * I.Kp + cc0;
+            e[u] = tb + (size_t)ic[u] * (WAVE * V);
             if (!first || keep_x) x[u] = ldv<R, V>(st.x + e[u]);
             ph[u] = ldv<R, V>(st.ph + e[u]);
             if (any_act) {
@@ -671,7 +683,7 @@ __global__ __launch_bounds__(WG) void k_init(Batch b, KrylovState<R> st, const R
     if (valid) {
       FOR_ROWS(b, p, I)
         const int i = pos;
-        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        const size_t e = tb + (size_t)i * (WAVE * V);
         cvec<R, V> r, x;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -894,9 +906,11 @@ __global__ __launch_bounds__(64) void k_ilu_apply(Batch b, const int* __restrict
   const int c = cg - I.col0;
   if (c >= I.K) return;
   const cx<R>* f = static_cast<const cx<R>*>(I.ilu) + (size_t)(c / I.L) * I.nnz;
-  const cx<R>* src = in + I.blk + c;
-  cx<R>* dst = out + I.blk + c;
-  const size_t ld = (size_t)I.Kp;
+  constexpr int W = WAVE * LaneWidth<R>::V;
+  const size_t col_base = tile_base(I, c / W, LaneWidth<R>::V) + c % W;
+  const cx<R>* src = in + col_base;
+  cx<R>* dst = out + col_base;
+  const size_t ld = W;
   cx<R> prev = {0, 0};
   for (int i = 0; i < I.n; ++i) {
     cx<R> y = src[(size_t)i * ld];
@@ -945,9 +959,9 @@ __global__ __launch_bounds__(WG) void k_bjac_apply(Batch b, const int* __restric
 #pragma unroll
     for (int v = 0; v < V; ++v) keep |= f[v] != COL_ACTIVE;
     const int nodes = I.n / 3;
-    const size_t stride = (size_t)I.Kp;
+    const size_t stride = WAVE * V;
     for (int k = blockIdx.x * 4 + p.w; k < nodes; k += b.G * 4) {
-      const size_t e0 = I.blk + (size_t)(3 * k) * stride + cc0;
+      const size_t e0 = tb + (size_t)(3 * k) * stride;
       const cvec<R, V> x0 = ldv<R, V>(in + e0), x1 = ldv<R, V>(in + e0 + stride), x2 = ldv<R, V>(in + e0 + 2 * stride);
       cvec<R, V> y[3];
       if (keep)
@@ -1110,13 +1124,13 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
         nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
       }
       if (Y && valid) {
-        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        const size_t e = tb + (size_t)i * (WAVE * V);
 #pragma unroll
         for (int v = 0; v < V; ++v) Rout[e + v] = r.c[v];
       }
     };
     if (Y) {
-      spmm_rows<double, V, true>(b, p, I, I.ab64, Y + I.blk + cc0, sig, emit);
+      spmm_rows<double, V, true>(b, p, I, I.ab64, Y + tb, sig, emit);
     } else {
       const cvec<double, V> zero{};
       FOR_ROWS(b, p, I)
@@ -1197,7 +1211,7 @@ __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __r
       }
       FOR_ROWS(b, p, I)
         const int i = pos;
-        const size_t e = I.blk + (size_t)i * I.Kp + cc0;
+        const size_t e = tb + (size_t)i * (WAVE * V);
         cvec<float, V> r, x;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1233,7 +1247,7 @@ __global__ __launch_bounds__(WG) void k_accumulate(Batch b, const cx<float>* __r
 #pragma unroll
     for (int v = 0; v < V; ++v) sc[v] = cl0 + v < I.K ? scale[cg0 + v] : 0.0;
     FOR_ROWS(b, p, I)
-      const size_t e = I.blk + (size_t)pos * I.Kp + cc0;
+      const size_t e = tb + (size_t)pos * (WAVE * V);
       const cvec<float, V> xv = ldv<float, V>(x + e);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
