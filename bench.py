@@ -70,7 +70,7 @@ def workload(name):
                           "N=6 SLRF poles alpha=1 beta=0.01; point-Jacobi BiCGStab"))
     if name == "c3":
         p = pencils.c3_elasticity()
-        return dict(pencil=p, gamma=101.0, L=256, N=8, expect=None, precond=3,
+        return dict(pencil=p, gamma=101.0, L=256, N=8, expect=None, precond=3, stepwise=True,
                     desc=("3D linear elasticity, trilinear hex, 48^3 free nodes x 3 dofs, clamped x=0 face, "
                           "Young's modulus log-normal sigma=0.7 seed 3, nu=0.3, density U[0.8,1.2] "
                           f"(n={p.n}, nnz={p.A.nnz}); gamma=101 (about 200 eigenvalues: the 200th "
@@ -437,8 +437,56 @@ def many_line(args, kind, out, desc):
     return line
 
 
+def run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0):
+    """As run_form, through the batch API with the one pencil, so that every outer
+    iteration reports (a solve of the elasticity workload takes minutes)."""
+    import torch
+    p = wl["pencil"]
+    L, N, gamma = wl["L"], wl["N"], wl["gamma"]
+    tag = "mixed" if precision == slrf.MIXED else "fp64"
+    pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, precision)
+    ws = pers + trans + (1 << 24)
+    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0))
+    log(f"{tag}: n={p.n} L={L} N={N} workspace {ws / 2**30:.2f} GiB (one-pencil batch)")
+
+    def solve():
+        b = slrf.Batch(ws, trans, max_poles=N, options=opt)
+        pid = b.add(p.A, p.B, gamma, L, sig, w, V0=V0)
+        t0, k = time.perf_counter(), 0
+        while b.step() > 0:
+            k += 1
+            done, outer = b.query(pid)
+            log(f"{tag} outer step {k}: {time.perf_counter() - t0:.1f} s")
+        r = b.result(pid)
+        b.close()
+        if r.status != 0 or (wl["expect"] is not None and r.n_found != wl["expect"]):
+            raise SystemExit(f"{tag} solve failed: status {r.status} found {r.n_found} ({r.message})")
+        return r
+
+    for i in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    found, results = 0, []
+    for i in range(steps):
+        r = solve()
+        found += r.n_found
+        results.append(r)
+        log(f"{tag} step {i}: outer {r.stats['outer_iterations']}, found {r.n_found}, "
+            f"max rho {r.stats['max_resid']:.2e}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    ks = {k: sum(r.stats["kernels"][k] for r in results) for k in
+          ("spmm_seconds", "spmm_launches", "spmm_bytes", "update_seconds", "update_launches",
+           "update_bytes")}
+    return dict(value=found / dt, dt=dt, results=results, ks=ks)
+
+
 def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
     import torch
+    if wl.get("stepwise"):
+        return run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0)
     p = wl["pencil"]
     L, N, gamma = wl["L"], wl["N"], wl["gamma"]
     opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0))

@@ -36,7 +36,7 @@ constexpr int kCsrPad = 16;     // zero entries after the last CSR entry (whole-
 // 64 V columns likewise.
 struct Inst {
   int n, K, L, N;        // rows, columns, right-hand sides, poles
-  int Kp;                // leading dimension of the (n, Kp) blocks: K rounded up to the lane width
+  int Kp;                // padded columns: K rounded up to a whole tile (blocks are tile-major)
   int nrb, slab, steps;  // row blocks, row blocks per XCD, steps per workgroup
   int rot;               // rotation of the pencil's row blocks over an XCD's workgroups
   int col0, tile0;       // first global column and first global tile
@@ -50,6 +50,7 @@ struct Inst {
   const ab_pair<double>* ab64;  // FP64 values (defect of the mixed path)
   const int* sched;             // sparse-product row order, or null
   const int* groups;            // stencil-group flags per kGroup rows, or null
+  const int* nodes;             // node-triple flags per 3 rows, or null
   const int* diagpos;           // position of each row's diagonal (ILU)
   const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
   const void* bjac;             // (N, n/3, 3, 3) cx<R> inverted node blocks, or null
@@ -67,7 +68,7 @@ struct Batch {
   int G;                  // grid, a multiple of 8
   int rows_per_block;
   int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
-  int groups;             // 1 if some pencil has stencil groups (selects the sparse-product variant)
+  int groups;             // sparse-product row mode: 1 stencil groups, 2 node triples, 0 neither
 };
 
 // Krylov vectors: base pointers of the concatenated per-pencil blocks; per

@@ -256,6 +256,57 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
                    api[r][v] - (sig[v].re * bpi[r][v] + sig[v].im * bpr[r][v])};
 }
 
+constexpr int kNodeRows = 3;  // rows of a node triple (flags built on the host)
+constexpr int kNodeChunk = 8;
+
+// Complex-shifted sparse product of a node triple: rows i0 .. i0 + 2 with the
+// same column list (checked on the host), so each input row is gathered once
+// for the three rows: a third of the gathers of three generic rows.  Entries
+// are taken in chunks of kNodeChunk (the CSR padding covers the overrun of the
+// last chunk; entries past the row end get zero coefficients and re-read row
+// i0); each row's entries are summed in entry order, as in shifted_row.
+template <typename R, int V>
+__device__ __forceinline__ void shifted_node(int i0, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
+                                             const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V],
+                                             cvec<R, V> (&q)[kNodeRows]) {
+  static_assert(kNodeChunk <= kCsrPad, "chunk longer than the CSR padding");
+  int kb[kNodeRows];
+#pragma unroll
+  for (int r = 0; r < kNodeRows; ++r) kb[r] = rowptr[i0 + r];
+  const int m = rowptr[i0 + 1] - kb[0];
+  R apr[kNodeRows][V] = {}, api[kNodeRows][V] = {}, bpr[kNodeRows][V] = {}, bpi[kNodeRows][V] = {};
+#pragma unroll 1
+  for (int j = 0; j < m; j += kNodeChunk) {
+    int jj[kNodeChunk];
+#pragma unroll
+    for (int u = 0; u < kNodeChunk; ++u) jj[u] = j + u < m ? col[kb[0] + j + u] : i0;
+    cvec<R, V> x[kNodeChunk];
+#pragma unroll
+    for (int u = 0; u < kNodeChunk; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
+#pragma unroll
+    for (int r = 0; r < kNodeRows; ++r) {
+#pragma unroll
+      for (int u = 0; u < kNodeChunk; ++u) {
+        ab_pair<R> ce = ldc(ab + kb[r] + j + u);
+        if (j + u >= m) ce = ab_pair<R>{0, 0};
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          apr[r][v] += ce.a * x[u].c[v].re;
+          api[r][v] += ce.a * x[u].c[v].im;
+          bpr[r][v] += ce.b * x[u].c[v].re;
+          bpi[r][v] += ce.b * x[u].c[v].im;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kNodeRows; ++r)
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      q[r].c[v] = {apr[r][v] - (sig[v].re * bpr[r][v] - sig[v].im * bpi[r][v]),
+                   api[r][v] - (sig[v].re * bpi[r][v] + sig[v].im * bpr[r][v])};
+}
+
 // Block layout: a pencil's n x Kp block is stored tile by tile.  Tile t holds
 // columns [t W, (t + 1) W) (W = 64 V, Kp a multiple of W) as an n x W row-major
 // panel, so the rows a tile's kernels gather are W * 8 or W * 16 bytes apart
@@ -317,18 +368,47 @@ __device__ __forceinline__ size_t tile_base(const Inst& I, int t, int V) {
 // multiple of 16 rows and the pencil has stencil groups, wavefront w takes the
 // four consecutive positions rb * rows_per_block + 4 w + 16 k; if they hold one
 // stencil group the shared-gather path serves them, else each is a generic row.
-// Otherwise wavefront w takes every 4th position as in FOR_ROWS.
-template <typename R, int V, bool GRP, typename Emit>
+// Likewise with node triples and a multiple of 12 rows: wavefront w takes the
+// three positions rb * rows_per_block + 3 w + 12 k.  Otherwise wavefront w takes
+// every 4th position as in FOR_ROWS.
+// MODE selects the shared-gather path compiled in (each adds registers to the
+// kernel): kRowsGeneric none, kRowsQuads stencil groups, kRowsTriples node
+// triples.  A pencil without that kind of row sets takes the generic rows.
+constexpr int kRowsGeneric = 0, kRowsQuads = 1, kRowsTriples = 2;
+
+template <typename R, int V, int MODE, typename Emit>
 __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const Inst& I, const void* abv,
                                           const cx<R>* __restrict__ Pc, const cx<R> (&sig)[V], Emit&& emit) {
   const cptr<int> rowptr = as_const(I.rowptr), col = as_const(I.col);
   const cptr<ab_pair<R>> ab = as_const(static_cast<const ab_pair<R>*>(abv));
-  const bool quads = GRP && I.groups && b.rows_per_block % (4 * kGroupRows) == 0;
+  const bool quads = MODE == kRowsQuads && I.groups && b.rows_per_block % (4 * kGroupRows) == 0;
+  const bool triples = MODE == kRowsTriples && I.nodes && b.rows_per_block % (4 * kNodeRows) == 0;
   for (int t = 0; t < I.steps; ++t) {
     const int rb = step_block(I, p, t);
     if (rb < 0) break;
     const int r0 = rb * b.rows_per_block, r1 = min(r0 + b.rows_per_block, I.n);
-    if (quads) {
+    if (MODE == kRowsTriples && triples) {
+      for (int q0 = r0 + kNodeRows * p.w; q0 < r1; q0 += 4 * kNodeRows) {
+        const int cnt = min(kNodeRows, r1 - q0);
+        const int i0 = I.sched ? as_const(I.sched)[q0] : q0;
+        bool node = cnt == kNodeRows && i0 % kNodeRows == 0 && as_const(I.nodes)[i0 / kNodeRows] != 0;
+        if (node && I.sched) {
+#pragma unroll
+          for (int u = 1; u < kNodeRows; ++u) node = node && as_const(I.sched)[q0 + u] == i0 + u;
+        }
+        if (node) {
+          cvec<R, V> q[kNodeRows];
+          shifted_node<R, V>(i0, rowptr, col, ab, Pc, WAVE * V, sig, q);
+#pragma unroll
+          for (int u = 0; u < kNodeRows; ++u) emit(i0 + u, q[u]);
+          continue;
+        }
+        for (int u = 0; u < cnt; ++u) {
+          const int i = I.sched ? as_const(I.sched)[q0 + u] : q0 + u;
+          emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, WAVE * V, sig));
+        }
+      }
+    } else if (MODE == kRowsQuads && quads) {
       for (int q0 = r0 + kGroupRows * p.w; q0 < r1; q0 += 4 * kGroupRows) {
         const int cnt = min(kGroupRows, r1 - q0);
         const int i0 = I.sched ? as_const(I.sched)[q0] : q0;
@@ -337,14 +417,12 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
 #pragma unroll
           for (int u = 1; u < kGroupRows; ++u) grp = grp && as_const(I.sched)[q0 + u] == i0 + u;
         }
-        if constexpr (GRP) {
-          if (grp) {
-            cvec<R, V> q[kGroupRows];
-            shifted_group<R, V>(i0, rowptr, col, ab, Pc, WAVE * V, sig, q);
+        if (grp) {
+          cvec<R, V> q[kGroupRows];
+          shifted_group<R, V>(i0, rowptr, col, ab, Pc, WAVE * V, sig, q);
 #pragma unroll
-            for (int u = 0; u < kGroupRows; ++u) emit(i0 + u, q[u]);
-            continue;
-          }
+          for (int u = 0; u < kGroupRows; ++u) emit(i0 + u, q[u]);
+          continue;
         }
         {
           for (int u = 0; u < cnt; ++u) {
@@ -365,7 +443,7 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
 // The sparse-product kernels declare 4 wavefronts per SIMD (<= 128 VGPRs): the
 // grid puts at most 4 workgroups of 4 wavefronts on a CU.
 // v = S p_hat, partial (rhat, v)
-template <typename R, bool GRP>
+template <typename R, int MODE>
 __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
@@ -376,7 +454,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, in
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.ph + tb, sig, [&](int i, const cvec<R, V>& q) {
+      spmm_rows<R, V, MODE>(b, p, I, I.ab, st.ph + tb, sig, [&](int i, const cvec<R, V>& q) {
         if (!valid) return;
         const size_t e = tb + (size_t)i * (WAVE * V);
         stv_nt<R, V>(st.v + e, q);
@@ -402,7 +480,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, in
 }
 
 // t = S s_hat, partials (t, s) = t^H s and (t, t)
-template <typename R, bool GRP>
+template <typename R, int MODE>
 __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
@@ -414,7 +492,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, in
       cx<R> sig[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
-      spmm_rows<R, V, GRP>(b, p, I, I.ab, st.sh + tb, sig, [&](int i, const cvec<R, V>& tv) {
+      spmm_rows<R, V, MODE>(b, p, I, I.ab, st.sh + tb, sig, [&](int i, const cvec<R, V>& tv) {
         if (valid) {
           const size_t e = tb + (size_t)i * (WAVE * V);
           stv_nt<R, V>(st.t + e, tv);
@@ -1010,10 +1088,12 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.p, st.ph);
   // v = S p_hat: gather p_hat once, write v, read rhat; the merged CSR once per launch
   c = tm ? tm->begin(s, 0, 2 * by.blk + by.rhat, by.matrix) : nullptr;
-  if (b.groups)
-    k_spmm_v<R, true><<<grid, blk, 0, s>>>(b, st, c);
+  if (b.groups == kRowsQuads)
+    k_spmm_v<R, kRowsQuads><<<grid, blk, 0, s>>>(b, st, c);
+  else if (b.groups == kRowsTriples)
+    k_spmm_v<R, kRowsTriples><<<grid, blk, 0, s>>>(b, st, c);
   else
-    k_spmm_v<R, false><<<grid, blk, 0, s>>>(b, st, c);
+    k_spmm_v<R, kRowsGeneric><<<grid, blk, 0, s>>>(b, st, c);
   if (c) tm->end(s);
   k_sc_alpha<R><<<cgrid, cblk, 0, s>>>(b, st);
   c = tm ? tm->begin(s, 1, 3 * by.blk + (jac ? by.diag : 0), 0) : nullptr;
@@ -1023,10 +1103,12 @@ void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R
   if (ilu) k_ilu_apply<R><<<igrid, iblk, 0, s>>>(b, st.flags, st.s, st.sh);
   if (bjac) k_bjac_apply<R><<<grid, blk, 0, s>>>(b, st.flags, st.s, st.sh);
   c = tm ? tm->begin(s, 0, (jac ? 2 : 3) * by.blk + (jac ? by.diag : 0), by.matrix) : nullptr;
-  if (b.groups)
-    k_spmm_t<R, true><<<grid, blk, 0, s>>>(b, st, c);
+  if (b.groups == kRowsQuads)
+    k_spmm_t<R, kRowsQuads><<<grid, blk, 0, s>>>(b, st, c);
+  else if (b.groups == kRowsTriples)
+    k_spmm_t<R, kRowsTriples><<<grid, blk, 0, s>>>(b, st, c);
   else
-    k_spmm_t<R, false><<<grid, blk, 0, s>>>(b, st, c);
+    k_spmm_t<R, kRowsGeneric><<<grid, blk, 0, s>>>(b, st, c);
   if (c) tm->end(s);
   k_sc_omega<R><<<cgrid, cblk, 0, s>>>(b, st);
   c = tm ? tm->begin(s, 1, (first ? 5 : 6) * by.blk + (jac ? 0 : by.blk) + by.rhat + (jac ? by.diag : 0), 0)
@@ -1102,6 +1184,7 @@ __device__ __forceinline__ bool tile_open(const double* scale, int cg0, int cl0,
   return __any(open);
 }
 
+template <int MODE>
 __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __restrict__ sigma_col,
                                               const double* __restrict__ F, const cx<double>* __restrict__ Y,
                                               cx<double>* __restrict__ Rout, double* __restrict__ part,
@@ -1130,7 +1213,7 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
       }
     };
     if (Y) {
-      spmm_rows<double, V, true>(b, p, I, I.ab64, Y + tb, sig, emit);
+      spmm_rows<double, V, MODE>(b, p, I, I.ab64, Y + tb, sig, emit);
     } else {
       const cvec<double, V> zero{};
       FOR_ROWS(b, p, I)
@@ -1143,7 +1226,13 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
 
 void launch_defect(hipStream_t s, const Batch& b, const cx<double>* sigma_col, const double* F,
                    const cx<double>* Y, cx<double>* Rout, double* part, const double* scale) {
-  k_defect<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, sigma_col, F, Y, Rout, part, scale);
+  const dim3 grid((unsigned)b.G), blk(WG);
+  if (b.groups == kRowsQuads)
+    k_defect<kRowsQuads><<<grid, blk, 0, s>>>(b, sigma_col, F, Y, Rout, part, scale);
+  else if (b.groups == kRowsTriples)
+    k_defect<kRowsTriples><<<grid, blk, 0, s>>>(b, sigma_col, F, Y, Rout, part, scale);
+  else
+    k_defect<kRowsGeneric><<<grid, blk, 0, s>>>(b, sigma_col, F, Y, Rout, part, scale);
 }
 
 // scale_c = ||R_c|| unless the defect meets its target; the next FP32 solve of

@@ -38,6 +38,9 @@ namespace {
 
 constexpr int kRowsPerBlock = 16;   // default rows per row block (4 wavefronts x one row group)
 constexpr int kGroup = 4;           // rows of a stencil group (see stencil_groups)
+constexpr int kNode = 3;            // rows of a node triple (see node_triples)
+constexpr int kRowAlign = 12;       // row-order chunks keep groups and triples whole
+constexpr int kRowsPerNodeBlock = 24;  // default rows per block for node-triple pencils
 constexpr int kWgPerXcd = 128;      // default workgroups per XCD (grid 8 * 128)
 constexpr int kSubBand = 1024;      // default rows per sub-band of the sparse-product row order
 constexpr int kTimerSlots = 512;
@@ -130,6 +133,7 @@ struct Pencil {
   int* diagpos = nullptr;
   int* sched = nullptr;
   int* groups = nullptr;  // stencil-group flags (n / kGroup), or null
+  int* nodes = nullptr;   // node-triple flags (n / kNode), or null (never both)
   bool use_ilu = false;
   bool use_bjac = false;  // node 3x3 block Jacobi
   char* mem = nullptr;  // device region holding the above
@@ -141,7 +145,8 @@ struct Pencil {
 size_t pencil_bytes(int64_t n, int64_t nnz) {
   const size_t np = (size_t)nnz + kCsrPad;
   return al((size_t)(n + 1) * 4) + al(np * 4) + al(np * 16) + al(np * 8) + 2 * al((size_t)n * 8) +
-         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4) + al((size_t)(n / kGroup + 1) * 4);
+         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4) + al((size_t)(n / kGroup + 1) * 4) +
+         al((size_t)(n / kNode + 1) * 4);
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
@@ -158,9 +163,9 @@ bool band_schedule(int64_t n, const std::vector<int32_t>& rp, const std::vector<
   for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] > rp[i]) H = std::max<int64_t>(H, (int64_t)cl[rp[i + 1] - 1] - i);
   if (H <= 2 * target || H >= n) return false;
-  H = (H + kGroup - 1) / kGroup * kGroup;  // chunk and sub-band starts stay multiples of kGroup
+  H = (H + kRowAlign - 1) / kRowAlign * kRowAlign;  // chunk and sub-band starts keep groups and triples whole
   const int64_t S = (H + target - 1) / target;
-  const int64_t band = ((H + S - 1) / S + kGroup - 1) / kGroup * kGroup, nchunk = (n + H - 1) / H;
+  const int64_t band = ((H + S - 1) / S + kRowAlign - 1) / kRowAlign * kRowAlign, nchunk = (n + H - 1) / H;
   order.clear();
   order.reserve(n);
   for (int64_t sb = 0; sb < S; ++sb)
@@ -192,6 +197,28 @@ std::vector<int32_t> stencil_groups(int64_t n, const std::vector<int32_t>& rp, c
     }
     for (int32_t j = 0; j < m && ok; j += 3)
       if (cl[k0 + j + 1] != cl[k0 + j] + 1 || cl[k0 + j + 2] != cl[k0 + j] + 2) ok = false;
+    g[q] = ok ? 1 : 0;
+  }
+  return g;
+}
+
+// Node triples: rows 3k, 3k + 1, 3k + 2 with the same column list (the three
+// displacement components of a node in vector-valued finite elements: every
+// row couples to all components of the same neighbour nodes).  The sparse
+// product gathers each column once for the three rows.  Returns one flag per
+// triple.
+std::vector<int32_t> node_triples(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl) {
+  const int64_t nt = n / kNode;
+  std::vector<int32_t> g(nt > 0 ? nt : 1, 0);
+  for (int64_t q = 0; q < nt; ++q) {
+    const int64_t i0 = q * kNode;
+    const int32_t k0 = rp[i0], m = rp[i0 + 1] - rp[i0];
+    bool ok = m > 0;
+    for (int r = 1; r < kNode && ok; ++r) {
+      if (rp[i0 + r + 1] - rp[i0 + r] != m) ok = false;
+      for (int32_t k = 0; k < m && ok; ++k)
+        if (cl[rp[i0 + r] + k] != cl[k0 + k]) ok = false;
+    }
     g[q] = ok ? 1 : 0;
   }
   return g;
@@ -285,12 +312,16 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.diagpos = cv.take<int>(n);
   int* sched_dev = cv.take<int>(n);
   int* groups_dev = cv.take<int>(n / kGroup + 1);
+  int* nodes_dev = cv.take<int>(n / kNode + 1);
   std::vector<int32_t> order;
   P.sched = band_schedule(n, rp, cl, band_rows, order) ? sched_dev : nullptr;
-  const std::vector<int32_t> groups = stencil_groups(n, rp, cl);
-  bool any_group = false;
-  for (int32_t f : groups) any_group |= f != 0;
-  P.groups = any_group ? groups_dev : nullptr;
+  const std::vector<int32_t> groups = stencil_groups(n, rp, cl), nodes = node_triples(n, rp, cl);
+  int64_t n_group = 0, n_node = 0;
+  for (int32_t f : groups) n_group += f != 0;
+  for (int32_t f : nodes) n_node += f != 0;
+  // one kind per pencil: the one that covers more rows
+  P.nodes = n_node > 0 && kNode * n_node >= kGroup * n_group ? nodes_dev : nullptr;
+  P.groups = n_group > 0 && !P.nodes ? groups_dev : nullptr;
   // kCsrPad zero entries (column 0, coefficients 0) after the last entry
   cl.resize(nnz + kCsrPad, 0);
   ab.resize(2 * (size_t)(nnz + kCsrPad), 0.0);
@@ -309,6 +340,7 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
       cp(P.diagpos, dpos.data(), 4 * n) != hipSuccess ||
       (P.sched && cp(P.sched, order.data(), 4 * n) != hipSuccess) ||
       (P.groups && cp(P.groups, groups.data(), 4 * groups.size()) != hipSuccess) ||
+      (P.nodes && cp(P.nodes, nodes.data(), 4 * nodes.size()) != hipSuccess) ||
       hipStreamSynchronize(s) != hipSuccess) {
     err = "upload of the merged CSR failed";
     return SLRF_E_DEVICE;
@@ -702,9 +734,17 @@ struct Tiling {
   int rpb, wgs;  // rows per row block, workgroups per XCD
 };
 
-Tiling option_tiling(const Env& env) {
-  return {env.opt.tile_rows > 0 ? env.opt.tile_rows : kRowsPerBlock,
-          env.opt.tile_wgs > 0 ? env.opt.tile_wgs : kWgPerXcd};
+// Default rows per block: 16 (four stencil groups per workgroup), or 24 (two
+// node triples per wavefront) when the batch's pencils have node triples and no
+// stencil groups.
+Tiling option_tiling(const Env& env, const std::vector<FilterJob>& jobs) {
+  bool any_group = false, any_node = false;
+  for (const auto& j : jobs) {
+    any_group |= j.P->groups != nullptr;
+    any_node |= j.P->nodes != nullptr;
+  }
+  const int rows = any_node && !any_group ? kRowsPerNodeBlock : kRowsPerBlock;
+  return {env.opt.tile_rows > 0 ? env.opt.tile_rows : rows, env.opt.tile_wgs > 0 ? env.opt.tile_wgs : kWgPerXcd};
 }
 
 // Row-block fields of the Inst table and the grid for a tiling.  XCD x owns the
@@ -745,8 +785,14 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   const hipStream_t s = env.stream;
   insts.assign(jobs.size(), Inst{});
   b.V = std::is_same<R, float>::value ? 2 : 1;
-  b.groups = 0;
-  for (const auto& j : jobs) b.groups |= j.P->groups ? 1 : 0;
+  // sparse-product variant: stencil groups if some pencil has them, else node
+  // triples if some pencil has those (1 and 2, the kernels' row modes)
+  bool any_group = false, any_node = false;
+  for (const auto& j : jobs) {
+    any_group |= j.P->groups != nullptr;
+    any_node |= j.P->nodes != nullptr;
+  }
+  b.groups = any_group ? 1 : any_node ? 2 : 0;
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all;
   std::vector<double> sigc64, w;
@@ -772,6 +818,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.ab64 = j.P->ab64;
     I.sched = j.P->sched;
     I.groups = j.P->groups;
+    I.nodes = j.P->nodes;
     I.diagpos = j.P->diagpos;
     I.ilu = nullptr;
     I.bjac = nullptr;
@@ -827,7 +874,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   b.n_active = lo.n_active;
   b.n_tiles = tile0;
   b.Ktot = col0;
-  apply_tiling(insts, b, option_tiling(env));
+  apply_tiling(insts, b, option_tiling(env, jobs));
   HIPCHK(env, put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst)));
   HIPCHK(env, put_async(s, keep, lo.tile_inst, tile_inst.data(), 4 * tile_inst.size()));
   HIPCHK(env, put_async(s, keep, lo.col_inst, col_inst.data(), 4 * col_inst.size()));
@@ -878,7 +925,8 @@ slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo,
     if (it != g_tune_cache.end()) best = it->second;
   }
   if (best.rpb == 0) {
-    static const Tiling cands[] = {{16, 128}, {32, 128}, {8, 128}, {16, 256}, {32, 256}, {16, 64}};
+    static const Tiling cands[] = {{16, 128}, {32, 128}, {8, 128}, {16, 256}, {32, 256}, {16, 64}, {24, 128},
+                                   {48, 128}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(env, hipEventCreate(&e0));
     HIPCHK(env, hipEventCreate(&e1));
