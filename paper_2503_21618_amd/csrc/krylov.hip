@@ -210,6 +210,10 @@ __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<
 }
 
 constexpr int kChunk = 16;
+// Chunk of the generic rows inside the shared-gather variants: 8 entries in
+// FP32 keeps those kernels within 128 VGPRs (16 spilled registers otherwise).
+template <typename R>
+constexpr int kChunkShared = sizeof(R) == 4 ? 8 : kChunk;
 constexpr int kGroupRows = 4;  // rows of a stencil group (flags built on the host)
 
 // Complex-shifted sparse product of a stencil group: rows i0 .. i0 + 3 whose
@@ -405,7 +409,7 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
         }
         for (int u = 0; u < cnt; ++u) {
           const int i = I.sched ? as_const(I.sched)[q0 + u] : q0 + u;
-          emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, WAVE * V, sig));
+          emit(i, shifted_row<R, V, kChunkShared<R>>(i, rowptr, col, ab, Pc, WAVE * V, sig));
         }
       }
     } else if (MODE == kRowsQuads && quads) {
@@ -427,7 +431,7 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
         {
           for (int u = 0; u < cnt; ++u) {
             const int i = I.sched ? as_const(I.sched)[q0 + u] : q0 + u;
-            emit(i, shifted_row<R, V, kChunk>(i, rowptr, col, ab, Pc, WAVE * V, sig));
+            emit(i, shifted_row<R, V, kChunkShared<R>>(i, rowptr, col, ab, Pc, WAVE * V, sig));
           }
         }
       }
