@@ -198,3 +198,81 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
         flags = np.where(flags == ACTIVE, MAXIT, flags)
     relres = np.sqrt((np.abs(f - S(x)) ** 2).sum(0)) / np.where(fn == 0, 1, fn)
     return x, iters, flags, relres
+
+
+def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None,
+         precond: str = "jacobi"):
+    """Conjugate orthogonal conjugate gradients (COCG; van der Vorst and Melissen,
+    IEEE Trans. Magn. 26 (1990)) for every pole and column, an alternative to
+    BiCGStab for the shifted systems of Section 3.
+
+    With A and B real symmetric, S_j = A - sigma_j B is complex symmetric
+    (S_j^T = S_j), and CG with the bilinear form [u, v] = u^T v (no conjugation)
+    in place of the inner product applies; it needs one product with S_j per
+    iteration.  The preconditioner must be complex symmetric as well: point
+    Jacobi or node block Jacobi (ILU(0) is not symmetric and is not offered).
+    Same interface and conventions as ``bicgstab``: x_0 = 0, columns pole-major,
+    convergence on the recursively updated residual ||r||_2 <= tol ||f||_2.
+
+    Steps per iteration, each column with its own scalars:
+        q = S p ;  alpha = rho / [p, q]
+        x = x + alpha p ;  r = r - alpha q        -> stop if ||r|| <= tol ||f||
+        z = M^{-1} r ;  rho' = [r, z] ;  beta = rho' / rho ;  p = z + beta p
+    starting from r = f, z = M^{-1} f, p = z, rho = [r, z].
+    """
+    n, L = F.shape
+    N = len(sigmas)
+    K = N * L
+    sig = np.repeat(np.asarray(sigmas, dtype=np.complex128), L)
+    if precond == "jacobi":
+        D = np.stack([jacobi_diagonal(A, B, s) for s in sigmas], axis=1)
+        Dc = np.repeat(D, L, axis=1)
+
+        def Minv(Y):
+            return Y / Dc
+    elif precond == "bjac3":
+        blks = [block_jacobi3(A, B, s) for s in sigmas]
+
+        def Minv(Y):
+            return np.concatenate([block_jacobi3_solve(blks[j], Y[:, j * L:(j + 1) * L])
+                                   for j in range(N)], axis=1)
+    else:
+        raise ValueError(f"COCG needs a symmetric preconditioner, not {precond}")
+    f = np.tile(F, (1, N)).astype(np.complex128)
+
+    def S(Y):
+        return (A @ Y) - sig[None, :] * (B @ Y)
+
+    fn = np.sqrt((np.abs(f) ** 2).sum(0))
+    x = np.zeros((n, K), np.complex128)
+    r = f.copy()
+    p = Minv(r)
+    rho = (r * p).sum(0)
+    flags = np.where(fn == 0.0, CONVERGED, ACTIVE)
+    iters = np.zeros(K, np.int64)
+    nsteps = fixed_iters if fixed_iters is not None else maxit
+    for it in range(nsteps):
+        act = flags == ACTIVE
+        if not act.any():
+            break
+        q = S(p)
+        pq = (p * q).sum(0)
+        bad = act & ((pq == 0) | (rho == 0))
+        ok = act & ~bad
+        alpha = np.where(ok, rho / np.where(pq == 0, 1, pq), 0)
+        x = np.where(ok, x + alpha * p, x)
+        r = np.where(ok, r - alpha * q, r)
+        iters = np.where(ok, iters + 1, iters)
+        rn = np.sqrt((np.abs(r) ** 2).sum(0))
+        conv = ok & (rn <= tol * fn) & (fixed_iters is None)
+        flags = np.where(conv, CONVERGED, np.where(bad, BREAKDOWN, flags))
+        act = flags == ACTIVE
+        z = Minv(r)
+        rho_new = (r * z).sum(0)
+        beta = np.where(act, rho_new / np.where(rho == 0, 1, rho), 0)
+        p = np.where(act, z + beta * p, p)
+        rho = np.where(act, rho_new, rho)
+    if fixed_iters is None:
+        flags = np.where(flags == ACTIVE, MAXIT, flags)
+    relres = np.sqrt((np.abs(f - S(x)) ** 2).sum(0)) / np.where(fn == 0, 1, fn)
+    return x, iters, flags, relres

@@ -177,6 +177,66 @@ def test_bicgstab_closed_form_rhs():
     assert np.abs(x - expect).max() < 1e-9 * np.abs(expect).max()
 
 
+def test_cocg_real_shift_is_preconditioned_cg():
+    """For a real shift sigma = -g the shifted operator A + g B is symmetric
+    positive definite and COCG is Jacobi-preconditioned CG: its iterates equal
+    scipy's preconditioned CG iterates step by step."""
+    import scipy.sparse.linalg as sla
+    q = pencils.scalar_q1(8, 3, 0.5, 7)
+    F = q.B @ pencils.start_block(q.n, 1, 3)
+    g = 60.0
+    S = (q.A + g * q.B).tocsr()
+    d = S.diagonal()
+    M = sla.LinearOperator(S.shape, matvec=lambda v: v / d)
+    for k in (1, 3, 10):
+        xs = []
+        sla.cg(S, F[:, 0], x0=np.zeros(q.n), rtol=1e-30, atol=0.0, maxiter=k, M=M,
+               callback=lambda xk: xs.append(xk.copy()))
+        x, it, fl, _ = krylov.cocg(q.A, q.B, [-g + 0j], F, 0.0, k, fixed_iters=k)
+        assert len(xs) == k and it[0] == k
+        assert np.abs(x[:, 0].imag).max() == 0.0
+        assert np.abs(x[:, 0].real - xs[-1]).max() < 1e-13 * np.abs(xs[-1]).max()
+
+
+def test_cocg_matches_exact_solve_complex_symmetric():
+    q = pencils.scalar_q1(7, 3, 0.5, 5)
+    rng = np.random.default_rng(1)
+    F = rng.standard_normal((q.n, 3))
+    sig = np.array([40.0 * (1 + 1j), 150.0 * (1 + 1j)])
+    for pc, P in (("jacobi", q), ):
+        x, it, fl, rr = krylov.cocg(P.A, P.B, sig, F, 1e-12, 2000, precond=pc)
+        assert set(fl.tolist()) == {krylov.CONVERGED}
+        for j, s in enumerate(sig):
+            y = oflt.shifted_solve(P.A, P.B, s, F)
+            e = np.abs(x[:, j * 3:(j + 1) * 3] - y).max() / np.abs(y).max()
+            assert e < 1e-9
+        assert rr.max() < 1e-11
+
+
+def test_cocg_block_jacobi_on_elasticity():
+    e = pencils.elasticity_q1(3, 3, 3, 1.0 / 3, 0.7, 0.3, (0.8, 1.2), 5)
+    F = e.B @ pencils.start_block(e.n, 2, 4)
+    sig = np.array([30.0 * (1 + 1j)])
+    x, it, fl, rr = krylov.cocg(e.A, e.B, sig, F, 1e-12, 3000, precond="bjac3")
+    y = oflt.shifted_solve(e.A, e.B, sig[0], F)
+    assert np.abs(x - y).max() < 1e-9 * np.abs(y).max()
+    with pytest.raises(ValueError):
+        krylov.cocg(e.A, e.B, sig, F, 1e-12, 10, precond="ilu0")
+
+
+def test_cocg_finite_termination():
+    """In exact arithmetic COCG ends after at most n steps; on an 8-unknown
+    pencil the 8th iterate is the solution to rounding."""
+    q = pencils.string_1d(8)
+    F = q.B @ pencils.start_block(q.n, 2, 5)
+    sig = np.array([400.0 * (1 + 0.7j)])
+    x, it, fl, _ = krylov.cocg(q.A, q.B, sig, F, 0.0, 8, fixed_iters=8)
+    y = oflt.shifted_solve(q.A, q.B, sig[0], F)
+    assert np.abs(x - y).max() < 1e-9 * np.abs(y).max()
+    x4, *_ = krylov.cocg(q.A, q.B, sig, F, 0.0, 4, fixed_iters=4)
+    assert np.abs(x4 - y).max() > 1e-6 * np.abs(y).max()
+
+
 def test_ilu0_defining_property_and_exactness():
     """ILU(0): (L U)_ij = S_ij on the pattern of S; exact LU for a tridiagonal S."""
     q = pencils.scalar_q1(5, 3, 0.5, 3)
