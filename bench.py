@@ -67,7 +67,7 @@ def workload(name):
                     desc=("3D scalar vibration, trilinear hex 64^3 unit cube, Dirichlet, "
                           "log-normal coefficient sigma=0.5 seed 2, consistent mass "
                           f"(n={p.n}, nnz={p.A.nnz}); gamma=421 (87 eigenvalues); L=128; "
-                          "N=6 SLRF poles alpha=1 beta=0.01; point-Jacobi BiCGStab"))
+                          "N=6 SLRF poles alpha=1 beta=0.01; point Jacobi"))
     if name == "c3":
         p = pencils.c3_elasticity()
         return dict(pencil=p, gamma=101.0, L=256, N=8, expect=None, precond=3, stepwise=True,
@@ -75,7 +75,7 @@ def workload(name):
                           "Young's modulus log-normal sigma=0.7 seed 3, nu=0.3, density U[0.8,1.2] "
                           f"(n={p.n}, nnz={p.A.nnz}); gamma=101 (about 200 eigenvalues: the 200th "
                           "eigenvalue of the 12^3 and 16^3 meshes extrapolated in h^2); L=256; N=8 SLRF poles "
-                          "alpha=1 beta=0.01; node 3x3 block-Jacobi BiCGStab"))
+                          "alpha=1 beta=0.01; node 3x3 block Jacobi"))
     if name == "c1":
         import numpy as np
         p = pencils.c1_string()
@@ -84,14 +84,14 @@ def workload(name):
         k = np.arange(20, 22)
         lam = (6 / h ** 2) * 2 * np.sin(0.5 * k * np.pi * h) ** 2 / (2 + np.cos(k * np.pi * h))
         return dict(pencil=p, gamma=0.5 * (lam[0] + lam[1]), L=32, N=4, expect=20,
-                    desc="1D linear-FE string n=2000, 20 eigenvalues; L=32; N=4; ILU(0) BiCGStab")
+                    desc="1D linear-FE string n=2000, 20 eigenvalues; L=32; N=4; ILU(0)")
     raise SystemExit(f"unknown workload {name}")
 
 
 def cpu_baseline(wl, sig, solve_stats):
-    """Oracle BiCGStab (FP64, the workload's preconditioner) on 1 pole x 4 columns for
-    a fixed number of iterations, single thread; scaled by the column-iterations of
-    the GPU solve."""
+    """Oracle inner solver of the workload (BiCGStab or COCG, FP64, the workload's
+    preconditioner) on 1 pole x 4 columns for a fixed number of iterations, single
+    thread; scaled by the column-iterations of the GPU solve."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -103,16 +103,18 @@ def cpu_baseline(wl, sig, solve_stats):
     iters = max(10, min(200, int(100 * 6.5e6 / max(p.A.nnz, 1))))
     pc = "bjac3" if wl.get("precond", 0) == 3 else "jacobi"
     F = p.B @ pencils.start_block(p.n, cols, 77)
+    cocg = wl.get("solver", 0) == 1
+    solve = krylov.cocg if cocg else krylov.bicgstab
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        krylov.bicgstab(p.A, p.B, sig[:1], F, 0.0, iters, fixed_iters=iters, precond=pc)
+        solve(p.A, p.B, sig[:1], F, 0.0, iters, fixed_iters=iters, precond=pc)
         dt = time.perf_counter() - t0
     per_col_it = dt / (cols * iters)
-    col_its = solve_stats["spmv_total"] / 2.0
+    col_its = solve_stats["spmv_total"] / (1.0 if cocg else 2.0)   # products per iteration
     est = per_col_it * col_its
     return {"value": solve_stats["n_found"] / est, "unit": "eigenpairs/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"oracle.krylov.bicgstab (FP64, {pc}) on 1 pole x {cols} columns for "
+            "sample": (f"oracle.krylov.{solve.__name__} (FP64, {pc}) on 1 pole x {cols} columns for "
                        f"{iters} iterations took {dt:.1f} s on 1 host thread; scaled to the "
                        f"{col_its:.0f} column-iterations of one GPU solve (Rayleigh-Ritz excluded)"),
             "seconds_per_column_iteration": per_col_it}
@@ -258,15 +260,27 @@ def batch_kernel_stats(results):
     return last.stats["kernels"]
 
 
-def serial_solves(slrf, items, precision, limit_s=float("inf")):
+def many_options(slrf, args, precision, **kw):
+    """Options of the batched, served and serial runs: with --graph (the default)
+    the Krylov iteration chunks replay as hipGraphs and the per-launch kernel
+    timers are off; with --no-graph the kernels are timed (roofline fields)."""
+    if args.graph:
+        return slrf.default_options(precision=precision, graph=1, profile=0, **kw)
+    return slrf.default_options(precision=precision, profile=1, **kw)
+
+
+def serial_solves(slrf, args, items, precision, limit_s=float("inf")):
     """The same pencils solved one at a time (create and pole design excluded),
-    in order, until limit_s seconds of solve time have been spent."""
+    in order, until limit_s seconds of solve time have been spent; same graph
+    setting as the batch."""
     import torch
     found, secs, done, not_ok = 0, 0.0, 0, 0
+    stream = torch.cuda.Stream()
     for p, gamma, L in items:
         if secs >= limit_s:
             break
-        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=slrf.default_options(precision=precision))
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=6, options=many_options(slrf, args, precision),
+                        stream=stream)
         sig, w, _ = slrf.design_poles(6, 1.0, 0.01, gamma)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -304,8 +318,8 @@ def run_batched(slrf, args):
         trans += b
     ws = pers + trans + (1 << 24)
     log(f"workspace {ws / 2**30:.1f} GiB (filter arena {trans / 2**30:.1f} GiB)")
-    opt = slrf.default_options(precision=slrf.MIXED, profile=1, tune=1)
-    b = slrf.Batch(ws, trans, max_poles=N, options=opt)
+    opt = many_options(slrf, args, slrf.MIXED, tune=1)
+    b = slrf.Batch(ws, trans, max_poles=N, options=opt, stream=torch.cuda.Stream())
     ids = []
     for p, g, L, _ in insts:
         sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
@@ -332,7 +346,7 @@ def run_batched(slrf, args):
            "statuses_not_ok": bad, "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
     if not args.no_serial:
         log("serial solves...")
-        out["serial"] = serial_solves(slrf, [(p, g, L) for p, g, L, _ in insts],
+        out["serial"] = serial_solves(slrf, args, [(p, g, L) for p, g, L, _ in insts],
                                       slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
                                       args.serial_limit)
     return out, insts
@@ -351,7 +365,8 @@ def run_served(slrf, args):
             for r in range(R)]
     log(f"{R} requests, sum n = {sum(p.n for p, *_ in reqs)}")
     N = 6
-    opt = slrf.default_options(precision=slrf.MIXED, profile=1)
+    opt = many_options(slrf, args, slrf.MIXED)
+    stream = torch.cuda.Stream()
     fps = [slrf.batch_footprint(p.n, union_nnz(p), L, N, slrf.MIXED) for p, g, L, _ in reqs]
     arena = int(args.arena_gb * 2**30)
     pool = int(args.pool_gb * 2**30)
@@ -365,7 +380,7 @@ def run_served(slrf, args):
 
     # calibration: the first C requests at once
     C = min(args.calibrate, R)
-    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt)
+    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt, stream=stream)
     for i in range(C):
         srv.submit(make(i, 0.0))
     t0 = time.perf_counter()
@@ -378,7 +393,7 @@ def run_served(slrf, args):
     del srv
     torch.cuda.empty_cache()
     arr = pencils.arrival_times(R, rate)
-    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt)
+    srv = serve.Server(pool + arena, arena, max_poles=N, options=opt, stream=stream)
     pending = [make(i, float(arr[i])) for i in range(R)]
     t0 = time.perf_counter()
     srv.clock = lambda: time.perf_counter() - t0
@@ -409,7 +424,7 @@ def run_served(slrf, args):
     torch.cuda.empty_cache()
     if not args.no_serial:
         log("serial solves...")
-        out["serial"] = serial_solves(slrf, [(p, g, L) for p, g, L, _ in reqs],
+        out["serial"] = serial_solves(slrf, args, [(p, g, L) for p, g, L, _ in reqs],
                                       slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
                                       args.serial_limit)
     return out, reqs
@@ -417,19 +432,23 @@ def run_served(slrf, args):
 
 def many_line(args, kind, out, desc):
     ks = out.pop("ks")
-    spmm_gbs = ks["spmm_bytes"] / ks["spmm_seconds"] / 1e9
-    traffic = None
     line = {"metric": METRIC, "value": out["value"], "unit": "eigenpairs/s", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["seconds"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-            "config": {"workload": desc},
-            "roofline": {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                         "kernel": "k_spmm_v / k_spmm_t <float> (complex-shifted sparse product)",
-                         "launches": ks["spmm_launches"],
-                         "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
-                         "traffic_note": "counters are taken on the 64^3 scalar workload only"},
-            "vector_updates": {"achieved_GBs": ks["update_bytes"] / ks["update_seconds"] / 1e9}}
+            "config": {"workload": desc, "graph": bool(args.graph)}}
+    if ks["spmm_seconds"] > 0:
+        spmm_gbs = ks["spmm_bytes"] / ks["spmm_seconds"] / 1e9
+        line["roofline"] = {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": "k_spmm_v / k_spmm_t <float> (complex-shifted sparse product)",
+                            "launches": ks["spmm_launches"],
+                            "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
+                            "traffic_note": "counters are taken on the 64^3 scalar workload only"}
+        line["vector_updates"] = {"achieved_GBs": ks["update_bytes"] / ks["update_seconds"] / 1e9}
+    else:
+        line["roofline"] = None
+        line["roofline_note"] = ("hipGraph replay with kernel timers off; bench.py --no-graph times the "
+                                 "kernels of this workload")
     line[kind] = out
     ser = out.get("serial")
     if ser and ser["value"] > 0:
@@ -446,7 +465,8 @@ def run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0):
     tag = "mixed" if precision == slrf.MIXED else "fp64"
     pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, precision)
     ws = pers + trans + (1 << 24)
-    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0))
+    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
+                               solver=wl.get("solver", 0))
     log(f"{tag}: n={p.n} L={L} N={N} workspace {ws / 2**30:.2f} GiB (one-pencil batch)")
 
     def solve():
@@ -489,7 +509,8 @@ def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
         return run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0)
     p = wl["pencil"]
     L, N, gamma = wl["L"], wl["N"], wl["gamma"]
-    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0))
+    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
+                               solver=wl.get("solver", 0))
     solver = slrf.Solver(p.A, p.B, max_L=L, max_poles=N, options=opt)
     tag = "mixed" if precision == slrf.MIXED else "fp64"
     log(f"{tag}: n={p.n} L={L} N={N} workspace {solver.ws_bytes / 2**30:.2f} GiB")
@@ -529,6 +550,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cocg"],
+                    help="inner solver of the shifted systems (COCG: point-Jacobi workloads only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
     ap.add_argument("--requests", type=int, default=24, help="served workload: number of requests")
@@ -539,6 +562,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--pool-gb", type=float, default=32.0)
     ap.add_argument("--no-serial", action="store_true", help="skip the one-pencil-at-a-time comparison")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="batched/served: time every kernel launch instead of replaying hipGraphs")
     ap.add_argument("--serial-limit", type=float, default=float("inf"),
                     help="stop the serial comparison after this many seconds of solves")
     ap.add_argument("--serial-precision", default="fp64", choices=["fp64", "mixed"],
@@ -582,6 +607,7 @@ def main():
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
     wl = workload(args.workload)
+    wl["solver"] = 1 if args.solver == "cocg" else 0
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
@@ -598,8 +624,13 @@ def main():
     upd_gbs = ks["update_bytes"] / ks["update_seconds"] / 1e9
     prec = "complex FP32 inner solves + FP64 defect correction and Rayleigh-Ritz" if main_form == "mixed" \
         else "complex FP64 inner solves"
+    prec += "; inner solver " + ("COCG" if wl["solver"] == 1 else "BiCGStab")
     kdtype = "float" if main_form == "mixed" else "double"
-    traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]))
+    if wl["solver"] == 1:
+        traffic, traffic_note = None, "counters are taken for the BiCGStab sparse products (k_spmm_v / k_spmm_t)"
+    else:
+        traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]))
+    kname = "k_cocg_spmm" if wl["solver"] == 1 else "k_spmm_v / k_spmm_t"
     out = {
         "metric": METRIC, "value": m["value"], "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * m["dt"] / args.steps,
@@ -608,7 +639,7 @@ def main():
         "data": "synthetic", "config": {"workload": wl["desc"] + "; " + prec},
         "roofline": {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_spmm_v / k_spmm_t <{kdtype}> (complex-shifted sparse product)",
+                     "kernel": f"{kname} <{kdtype}> (complex-shifted sparse product)",
                      "launches": ks["spmm_launches"],
                      "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
                      "algorithmic_bytes_per_launch": ks["spmm_bytes"] / max(1, ks["spmm_launches"]),

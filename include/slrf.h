@@ -95,6 +95,12 @@ typedef struct {
                           filter application of a shape not seen before in the process
                           times two BiCGStab iterations per candidate and keeps the
                           fastest (cached per process); overrides tile_rows/tile_wgs */
+  int32_t solver;      /* inner solver of the shifted systems: 0 BiCGStab (Section 2,
+                          the paper's choice), 1 COCG, conjugate gradients with the
+                          bilinear form u^T v for the complex-symmetric A - sigma_j B
+                          (one sparse product per iteration; point Jacobi only:
+                          precond 0 then selects Jacobi, precond 2 and 3 are
+                          rejected with SLRF_E_INVALID_ARG) */
 } slrf_options;
 
 typedef struct {
@@ -132,7 +138,7 @@ typedef struct {
 
 /* Defaults: FP64, inner_tol 1e-13, inner_maxit 1000, outer_tol 1e-8,
  * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0,
- * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0. */
+ * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0, solver 0 (BiCGStab). */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance
@@ -174,7 +180,8 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n,
 /* One filter application (Algorithm 1, the "Solve" loop and "Compute U"):
  *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
  * every (pole, column) system solved by right-preconditioned BiCGStab (the
- * preconditioner of slrf_options.precond), x_0 = 0 and shadow residual B X.  d_X, d_U: device (n, L) row-major float64
+ * preconditioner of slrf_options.precond), x_0 = 0 and shadow residual B X, or by
+ * Jacobi-preconditioned COCG (slrf_options.solver = 1).  d_X, d_U: device (n, L) row-major float64
  * (may not alias).  stats may be NULL.  Returns SLRF_OK even if some columns hit
  * inner_maxit or broke down; stats reports them. */
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L,

@@ -21,6 +21,7 @@ _lib = C.CDLL(LIB_PATH)
 
 FP64, MIXED = 0, 1
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_ILU0, PRECOND_BLOCK3 = 0, 1, 2, 3
+SOLVER_BICGSTAB, SOLVER_COCG = 0, 1
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_DEVICE",
           5: "E_NOT_CONVERGED", 6: "E_SUBSPACE_TOO_SMALL", 7: "E_BREAKDOWN"}
 
@@ -30,7 +31,7 @@ class Options(C.Structure):
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32),
                 ("graph", C.c_int32), ("tile_rows", C.c_int32), ("tile_wgs", C.c_int32),
-                ("band_rows", C.c_int32), ("tune", C.c_int32)]
+                ("band_rows", C.c_int32), ("tune", C.c_int32), ("solver", C.c_int32)]
 
 
 class Poles(C.Structure):

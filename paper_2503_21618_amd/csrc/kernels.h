@@ -137,6 +137,14 @@ template <typename R>
 // precs: 1 if some pencil uses ILU(0), 2 if some pencil uses node block Jacobi (or both)
 void launch_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
                       bool first, int precs, LaunchTimer* timer, const IterBytes& bytes);
+// COCG (point Jacobi only): p = M^{-1} r and the per-column start values, after
+// launch_init or launch_mixed_rhs has written r and the partial ||r||^2; then
+// one COCG iteration per call.
+template <typename R>
+void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st);
+template <typename R>
+void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
+                           LaunchTimer* timer, const IterBytes& bytes);
 // out[0] = number of active columns; rebuilds the active-tile list of the batch.
 void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* out);
 

@@ -1362,11 +1362,293 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
   k_accumulate<<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, x, scale, Y, first);
 }
 
+// ---- COCG (conjugate orthogonal CG) for the complex-symmetric shifted systems ----
+// S = A - sigma B is complex symmetric, so CG with the bilinear form [u, v] = u^T v
+// applies (van der Vorst and Melissen 1990): one sparse product per iteration.
+// Point Jacobi only (M = diag(S), symmetric); z = M^{-1} r is never stored.
+// Storage: p in ph (the gathered direction), q = S p in v.
+//   start:  p = M^{-1} r, rho = [r, p]           (after k_init / k_mixed_rhs)
+//   q = S p, alpha = rho / [p, q]
+//   x += alpha p, r -= alpha q                    -> stop if ||r|| <= tol ||f||
+//   rho' = [r, M^{-1} r], beta = rho' / rho, p = M^{-1} r + beta p
+
+// p = M^{-1} r over every tile; partial [r, p] in part_a
+template <typename R>
+__global__ __launch_bounds__(WG, 4) void k_cocg_start(Batch b, KrylovState<R> st) {
+  constexpr int V = LaneWidth<R>::V;
+  const WgPos p = wg_pos(b.G);
+  FOR_TILES(b, p, V)
+    cx<R> rz[V] = {};
+    if (valid) {
+      int pole[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      FOR_ROWS(b, p, I)
+        const size_t e = tb + (size_t)pos * (WAVE * V);
+        const size_t de = I.dn + (size_t)pos * I.N;
+        const cvec<R, V> r = ldv<R, V>(st.r + e);
+        cvec<R, V> z;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          z.c[v] = cl0 + v < I.K ? cmul(st.dinv[de + pole[v]], r.c[v]) : cx<R>{0, 0};
+          const cx<R> t = cmul(r.c[v], z.c[v]);
+          rz[v].re += t.re;
+          rz[v].im += t.im;
+        }
+        stv<R, V>(st.ph + e, z);
+      END_ROWS
+    }
+    wg_store_partial_cx<R, V>(rz, p.w, p.lane, cl0, I.K, st.part_a + po);
+  }
+}
+
+// start values: ||f|| from part_b (written by the right-hand-side kernel), rho
+// from part_a; every tile starts on the active list, padding columns converged
+template <typename R>
+__global__ __launch_bounds__(WG) void k_cocg_init_scalars(Batch b, KrylovState<R> st) {
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (threadIdx.x == 0) {
+    b.active[blockIdx.x] = blockIdx.x;
+    if (blockIdx.x == 0) b.n_active[0] = b.n_tiles;
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const R nn = block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok);
+    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    if (!lead || cl0 + v >= I.Kp) continue;
+    st.fnorm[c] = sqrt(nn);
+    st.rnorm[c] = sqrt(nn);
+    st.rho[c] = rz;
+    st.alpha[c] = {0, 0};
+    st.beta[c] = {0, 0};
+    st.iters[c] = 0;
+    st.flags[c] = (nn == 0 || !ok) ? COL_CONVERGED : COL_ACTIVE;
+  }
+}
+
+// q = S p; partial [p, q]
+template <typename R, int MODE>
+__global__ __launch_bounds__(WG, 4) void k_cocg_spmm(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
+  const WgPos p = wg_pos(b.G);
+  FOR_ACTIVE_TILES(b, p, V)
+    cx<R> d[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
+      count_tile(counter);
+      cx<R> sig[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) sig[v] = st.sigma_col[cg0 + v];
+      spmm_rows<R, V, MODE>(b, p, I, I.ab, st.ph + tb, sig, [&](int i, const cvec<R, V>& q) {
+        if (!valid) return;
+        const size_t e = tb + (size_t)i * (WAVE * V);
+        stv_nt<R, V>(st.v + e, q);
+        const cvec<R, V> pv = ldv<R, V>(st.ph + e);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const cx<R> t = cmul(pv.c[v], q.c[v]);
+          d[v].re += t.re;
+          d[v].im += t.im;
+        }
+      });
+    }
+    wg_store_partial_cx<R, V>(d, p.w, p.lane, cl0, I.K, st.part_a + po);
+  }
+}
+
+// alpha = rho / [p, q]
+template <typename R>
+__global__ __launch_bounds__(WG) void k_cocg_alpha(Batch b, KrylovState<R> st) {
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const cx<R> pq = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
+    const cx<R> rho = st.rho[c];
+    if ((pq.re == 0 && pq.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(pq)) {
+      st.flags[c] = COL_BREAKDOWN;
+      continue;
+    }
+    st.alpha[c] = cdiv(rho, pq);
+    st.iters[c] += 1;
+  }
+}
+
+// x += alpha p, r -= alpha q for active columns; partials [r, M^{-1} r] and ||r||^2
+template <typename R>
+__global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
+  const WgPos p = wg_pos(b.G);
+  FOR_ACTIVE_TILES(b, p, V)
+    cx<R> rz[V] = {};
+    R nn[V] = {};
+    if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
+      count_tile(counter);
+      int f[V], pole[V];
+      lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+      cx<R> alpha[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        alpha[v] = f[v] == COL_ACTIVE ? st.alpha[cg0 + v] : cx<R>{0, 0};
+      }
+      constexpr int kRowBatch = 2;
+      FOR_ROW_BATCH(b, p, I, kRowBatch)
+        size_t e[kRowBatch];
+        cvec<R, V> x[kRowBatch], r[kRowBatch], pv[kRowBatch], q[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          e[u] = tb + (size_t)ic[u] * (WAVE * V);
+          x[u] = ldv<R, V>(st.x + e[u]);
+          r[u] = ldv<R, V>(st.r + e[u]);
+          pv[u] = ldv<R, V>(st.ph + e[u]);
+          q[u] = ldv<R, V>(st.v + e[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          if (!ok[u]) continue;
+          const size_t de = I.dn + (size_t)ic[u] * I.N;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (f[v] != COL_ACTIVE) continue;
+            x[u].c[v] = cadd(x[u].c[v], cmul(alpha[v], pv[u].c[v]));
+            const cx<R> rv = csub(r[u].c[v], cmul(alpha[v], q[u].c[v]));
+            r[u].c[v] = rv;
+            const cx<R> t = cmul(rv, cmul(st.dinv[de + pole[v]], rv));
+            rz[v].re += t.re;
+            rz[v].im += t.im;
+            nn[v] += rv.re * rv.re + rv.im * rv.im;
+          }
+          stv<R, V>(st.x + e[u], x[u]);
+          stv<R, V>(st.r + e[u], r[u]);
+        }
+      END_ROWS
+    }
+    wg_store_partial_cx<R, V>(rz, p.w, p.lane, cl0, I.K, st.part_a + po);
+    wg_store_partial<R, V>(nn, p.w, p.lane, cl0, I.K, st.part_b + po);
+  }
+}
+
+// ||r|| test; beta = rho' / rho
+template <typename R>
+__global__ __launch_bounds__(WG) void k_cocg_beta(Batch b, KrylovState<R> st, R tol, int maxit) {
+  constexpr int V = LaneWidth<R>::V;
+  SC_PROLOGUE(V)
+  if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = cg0 + v;
+    const bool ok = cl0 + v < I.K;
+    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    const R nn = sqrt(block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok));
+    if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
+    st.rnorm[c] = nn;
+    if (nn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
+      st.flags[c] = COL_CONVERGED;
+      continue;
+    }
+    if (st.iters[c] >= maxit) {
+      st.flags[c] = COL_MAXIT;
+      continue;
+    }
+    if (!cfinite(rz)) {
+      st.flags[c] = COL_BREAKDOWN;
+      continue;
+    }
+    st.beta[c] = cdiv(rz, st.rho[c]);
+    st.rho[c] = rz;
+  }
+}
+
+// p = M^{-1} r + beta p for active columns
+template <typename R>
+__global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R> st, int* counter) {
+  constexpr int V = LaneWidth<R>::V;
+  const WgPos p = wg_pos(b.G);
+  FOR_ACTIVE_TILES(b, p, V)
+    (void)po;
+    if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) continue;
+    count_tile(counter);
+    int f[V], pole[V];
+    lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+    cx<R> beta[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      beta[v] = st.beta[cg0 + v];
+    }
+    constexpr int kRowBatch = 4;
+    FOR_ROW_BATCH(b, p, I, kRowBatch)
+      size_t e[kRowBatch];
+      cvec<R, V> r[kRowBatch], pv[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        e[u] = tb + (size_t)ic[u] * (WAVE * V);
+        r[u] = ldv<R, V>(st.r + e[u]);
+        pv[u] = ldv<R, V>(st.ph + e[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        if (!ok[u]) continue;
+        const size_t de = I.dn + (size_t)ic[u] * I.N;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (f[v] != COL_ACTIVE) continue;
+          pv[u].c[v] = cadd(cmul(st.dinv[de + pole[v]], r[u].c[v]), cmul(beta[v], pv[u].c[v]));
+        }
+        stv<R, V>(st.ph + e[u], pv[u]);
+      }
+    END_ROWS
+  }
+}
+
+template <typename R>
+void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
+  k_cocg_start<R><<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, st);
+  k_cocg_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(WG), 0, s>>>(b, st);
+}
+
+template <typename R>
+void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
+                           LaunchTimer* tm, const IterBytes& by) {
+  const dim3 grid((unsigned)b.G), blk(WG);
+  const dim3 cgrid((unsigned)b.n_tiles), cblk(WG);
+  int* c;
+  // q = S p: gather p once, write q, read p's own rows; the merged CSR once
+  c = tm ? tm->begin(s, 0, 2 * by.blk, by.matrix) : nullptr;
+  if (b.groups == kRowsQuads)
+    k_cocg_spmm<R, kRowsQuads><<<grid, blk, 0, s>>>(b, st, c);
+  else if (b.groups == kRowsTriples)
+    k_cocg_spmm<R, kRowsTriples><<<grid, blk, 0, s>>>(b, st, c);
+  else
+    k_cocg_spmm<R, kRowsGeneric><<<grid, blk, 0, s>>>(b, st, c);
+  if (c) tm->end(s);
+  k_cocg_alpha<R><<<cgrid, cblk, 0, s>>>(b, st);
+  // x, r update: read x, r, p, q, write x, r; 1/d
+  c = tm ? tm->begin(s, 1, 6 * by.blk + by.diag, 0) : nullptr;
+  k_cocg_update_xr<R><<<grid, blk, 0, s>>>(b, st, c);
+  if (c) tm->end(s);
+  k_cocg_beta<R><<<cgrid, cblk, 0, s>>>(b, st, tol, maxit);
+  // p update: read r, p, write p; 1/d
+  c = tm ? tm->begin(s, 1, 3 * by.blk + by.diag, 0) : nullptr;
+  k_cocg_update_p<R><<<grid, blk, 0, s>>>(b, st, c);
+  if (c) tm->end(s);
+}
+
 #define SLRF_INST(R)                                                                                  \
   template void launch_init<R>(hipStream_t, const Batch&, const KrylovState<R>&, const R*);        \
   template void launch_init_scalars<R>(hipStream_t, const Batch&, const KrylovState<R>&);          \
   template void launch_iteration<R>(hipStream_t, const Batch&, const KrylovState<R>&, R, int, bool, \
-                                    int, LaunchTimer*, const IterBytes&);
+                                    int, LaunchTimer*, const IterBytes&);                              \
+  template void launch_cocg_start<R>(hipStream_t, const Batch&, const KrylovState<R>&);            \
+  template void launch_cocg_iteration<R>(hipStream_t, const Batch&, const KrylovState<R>&, R, int, \
+                                         LaunchTimer*, const IterBytes&);
 SLRF_INST(double)
 SLRF_INST(float)
 

@@ -503,6 +503,13 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   if (env.opt.precision != SLRF_FP64 && env.opt.precision != SLRF_MIXED)
     return fail(env, SLRF_E_INVALID_ARG, "unknown precision");
   if (env.opt.precond < 0 || env.opt.precond > 3) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (env.opt.solver != 0 && env.opt.solver != 1) return fail(env, SLRF_E_INVALID_ARG, "unknown inner solver");
+  if (env.opt.solver == 1) {
+    // COCG needs a complex-symmetric preconditioner: point Jacobi
+    if (env.opt.precond == 2 || env.opt.precond == 3)
+      return fail(env, SLRF_E_INVALID_ARG, "COCG takes point Jacobi only (precond 0 or 1)");
+    env.opt.precond = 1;
+  }
   if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
     return fail(env, SLRF_E_INVALID_ARG, "tolerances must be non-negative");
   if (env.opt.tile_rows < 0 || env.opt.tile_rows > 64 || env.opt.tile_wgs < 0 ||
@@ -906,6 +913,25 @@ int ilog2(int64_t x) {
   return r;
 }
 
+// Inner-solver dispatch: start values after the right-hand side is in r, and one
+// iteration (BiCGStab of the paper, or COCG with options.solver = 1).
+template <typename R>
+void krylov_start(const Env& env, const Batch& b, const KrylovState<R>& st) {
+  if (env.opt.solver == 1)
+    launch_cocg_start<R>(env.stream, b, st);
+  else
+    launch_init_scalars<R>(env.stream, b, st);
+}
+
+template <typename R>
+void krylov_iteration(const Env& env, const Batch& b, const KrylovState<R>& st, R tol, int maxit, bool first,
+                      int precs, LaunchTimer* tm, const IterBytes& by) {
+  if (env.opt.solver == 1)
+    launch_cocg_iteration<R>(env.stream, b, st, tol, maxit, tm, by);
+  else
+    launch_iteration<R>(env.stream, b, st, tol, maxit, first, precs, tm, by);
+}
+
 template <typename R>
 slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo, Batch& b,
                      const KrylovState<R>& st, R tol, int precs, const IterBytes& by,
@@ -937,9 +963,9 @@ slrf_status autotune(Env& env, std::vector<Inst>& insts, const FilterLayout& lo,
       err = put_async(s, keep, lo.inst, insts.data(), insts.size() * sizeof(Inst));
       if (err != hipSuccess) break;
       restart();
-      launch_iteration<R>(s, b, st, tol, 1 << 30, true, precs, nullptr, by);
+      krylov_iteration<R>(env, b, st, tol, 1 << 30, true, precs, nullptr, by);
       (void)hipEventRecord(e0, s);
-      for (int q = 0; q < 2; ++q) launch_iteration<R>(s, b, st, tol, 1 << 30, false, precs, nullptr, by);
+      for (int q = 0; q < 2; ++q) krylov_iteration<R>(env, b, st, tol, 1 << 30, false, precs, nullptr, by);
       (void)hipEventRecord(e1, s);
       err = hipEventSynchronize(e1);
       float ms = 0;
@@ -990,7 +1016,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       if (!exec) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-          for (int q = 0; q < every; ++q) launch_iteration<R>(s, b, st, tol, maxit, false, precs, nullptr, by);
+          for (int q = 0; q < every; ++q) krylov_iteration<R>(env, b, st, tol, maxit, false, precs, nullptr, by);
           launch_count_active(s, b, st.flags, d_count);
           e = hipStreamEndCapture(s, &gr);
         }
@@ -1007,7 +1033,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       }
       it += every;
     } else {
-      for (int q = 0; q < chunk; ++q, ++it) launch_iteration<R>(s, b, st, tol, maxit, it == 0, precs, tm, by);
+      for (int q = 0; q < chunk; ++q, ++it) krylov_iteration<R>(env, b, st, tol, maxit, it == 0, precs, tm, by);
       launch_count_active(s, b, st.flags, d_count);
     }
     int active = 0;
@@ -1060,7 +1086,8 @@ slrf_status collect_stats(Env& env, std::vector<FilterJob>& jobs, const KrylovSt
       if (k >= K) continue;
       fs.max_iterations = std::max(fs.max_iterations, its[c]);
       sum_it[q] += its[c];
-      fs.spmv += 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
+      // BiCGStab: two products per iteration (one at a half-step exit); COCG: one
+      fs.spmv += env.opt.solver == 1 ? (int64_t)its[c] : 2 * (int64_t)its[c] - (fl[c] == COL_HALF_CONVERGED ? 1 : 0);
       if (fl[c] == COL_BREAKDOWN) fs.n_breakdown++;
       if (fl[c] == COL_MAXIT) fs.n_maxit++;
       if (final_relres) fs.max_relres = std::max(fs.max_relres, fn[c] > 0 ? (double)rn[c] / (double)fn[c] : 0.0);
@@ -1112,14 +1139,14 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
     pj += j.N;
   }
   launch_init<double>(s, b, st, lo.rhat);
-  launch_init_scalars<double>(s, b, st);
+  krylov_start<double>(env, b, st);
   HIPCHK(env, hipGetLastError());
   slrf_filter_stats ks{};
   const IterBytes by = iter_bytes(jobs, lo, 8, false);
   if (env.opt.tune) {
     slrf_status ts = autotune<double>(env, insts, lo, b, st, env.opt.inner_tol, lo.precs(), by, [&]() {
       launch_init<double>(s, b, st, lo.rhat);
-      launch_init_scalars<double>(s, b, st);
+      krylov_start<double>(env, b, st);
     }, keep);
     if (ts != SLRF_OK) return ts;
   }
@@ -1196,11 +1223,11 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     if (open == 0 || round == kMaxRounds) break;
     ++rounds;
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
-    launch_init_scalars<float>(s, b, st);
+    krylov_start<float>(env, b, st);
     if (round == 0 && env.opt.tune) {
       slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.precs(), by, [&]() {
         launch_mixed_rhs(s, b, nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
-        launch_init_scalars<float>(s, b, st);
+        krylov_start<float>(env, b, st);
       }, keep);
       if (ts != SLRF_OK) return ts;
     }
@@ -1525,6 +1552,7 @@ void slrf_default_options(slrf_options* o) {
   o->tile_wgs = 0;
   o->band_rows = 0;
   o->tune = 0;
+  o->solver = 0;
 }
 
 const char* slrf_status_string(slrf_status s) {
@@ -1573,6 +1601,7 @@ slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz, int64_t L, int32_t 
   if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
   if (o.precision != SLRF_FP64 && o.precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
   if (o.precond < 0 || o.precond > 3) return SLRF_E_INVALID_ARG;
+  if (o.solver == 1 && o.precond == 0) o.precond = 1;  // COCG runs with point Jacobi
   const size_t arena = filter_arena_bytes(
       {JobShape{n, nnz, (int)L, (int)N, use_ilu_for(o.precond, n, nnz), false, use_bjac_for(o.precond)}},
       o.precision == SLRF_MIXED);
