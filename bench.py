@@ -31,7 +31,7 @@ bounded sample of the same workload on the host and scales it to the whole
 solve.
 
 Counter collection (the probe runs full-width launches of the sparse product):
-    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_spmm|elementwise" \
+    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_spmm|k_cocg_spmm|elementwise" \
         --output-format csv -d <dir> -o run -- python3 bench.py --counters-probe
     (again with WRITE_SIZE)
     python bench.py --summarize-pmc <fetch csv> <write csv>  > profiles/spmm_c2_pmc.txt
@@ -142,7 +142,7 @@ def read_pmc_summary():
     return d
 
 
-def hbm_traffic(dtype, avg_alg_bytes):
+def hbm_traffic(dtype, avg_alg_bytes, family="bicgstab"):
     """HBM bytes per launch of the sparse product from the counter summary, scaled
     from the probe's full-width launches to launches that average avg_alg_bytes
     algorithmic bytes (converged tiles are skipped); None if the summary is
@@ -150,8 +150,11 @@ def hbm_traffic(dtype, avg_alg_bytes):
     d = read_pmc_summary()
     if not d or d.get("source_sha256") != kernel_source_hash():
         return None, "no counter summary for the current kernel sources"
-    full_traffic = float(d[f"full_launch_traffic_bytes {dtype}"])
-    full_alg = float(d[f"full_launch_algorithmic_bytes {dtype}"])
+    key = dtype if family == "bicgstab" else f"{family} {dtype}"
+    if f"full_launch_traffic_bytes {key}" not in d:
+        return None, f"no counter summary for the {family} sparse product"
+    full_traffic = float(d[f"full_launch_traffic_bytes {key}"])
+    full_alg = float(d[f"full_launch_algorithmic_bytes {key}"])
     return full_traffic * avg_alg_bytes / full_alg, (
         f"{PMC_SUMMARY.split(os.sep)[-2]}/{os.path.basename(PMC_SUMMARY)}: FETCH_SIZE + WRITE_SIZE per "
         f"full-width launch {full_traffic / 1e9:.3f} GB vs algorithmic {full_alg / 1e9:.3f} GB, "
@@ -176,14 +179,16 @@ def counters_probe():
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     X = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
-    for prec, dtype in ((slrf.MIXED, "float"), (slrf.FP64, "double")):
-        opt = slrf.default_options(profile=1, precision=prec, inner_tol=0.0, inner_maxit=3, check_every=3)
-        s = slrf.Solver(p.A, p.B, max_L=wl["L"], max_poles=wl["N"], options=opt)
-        U, st = s.filter_apply(X, sig, w)
-        torch.cuda.synchronize()
-        print(json.dumps({"dtype": dtype, "spmm_launches": st["spmm_launches"],
-                          "full_launch_algorithmic_bytes": st["spmm_bytes"] / st["spmm_launches"]}),
-              flush=True)
+    for solver, family in ((slrf.SOLVER_BICGSTAB, "bicgstab"), (slrf.SOLVER_COCG, "cocg")):
+        for prec, dtype in ((slrf.MIXED, "float"), (slrf.FP64, "double")):
+            opt = slrf.default_options(profile=1, precision=prec, inner_tol=0.0, inner_maxit=3, check_every=3,
+                                       solver=solver)
+            s = slrf.Solver(p.A, p.B, max_L=wl["L"], max_poles=wl["N"], options=opt)
+            U, st = s.filter_apply(X, sig, w)
+            torch.cuda.synchronize()
+            print(json.dumps({"family": family, "dtype": dtype, "spmm_launches": st["spmm_launches"],
+                              "full_launch_algorithmic_bytes": st["spmm_bytes"] / st["spmm_launches"]}),
+                  flush=True)
         s.close()
         del s, U
         torch.cuda.empty_cache()
@@ -200,8 +205,10 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
                     continue
                 name = row["Kernel_Name"]
                 m = re.search(r"k_spmm_([vt])<(float|double)", name)
+                mc = re.search(r"k_cocg_spmm<(float|double)", name)
                 key = ("copy" if "elementwise" in name and "neg" in name else
-                       f"k_spmm_{m.group(1)}<{m.group(2)}>" if m else None)
+                       f"k_spmm_{m.group(1)}<{m.group(2)}>" if m else
+                       f"k_cocg_spmm<{mc.group(1)}>" if mc else None)
                 if key:
                     acc.setdefault(key, []).append(float(row["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
@@ -212,16 +219,17 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
         for line in f:
             if line.startswith("{"):
                 d = json.loads(line)
-                alg[d["dtype"]] = d["full_launch_algorithmic_bytes"]
+                alg[(d.get("family", "bicgstab"), d["dtype"])] = d["full_launch_algorithmic_bytes"]
     kib = COPY_BYTES / 1024.0
     ff = fe["copy"][0] / kib
     fw = wr["copy"][0] / kib
-    print("# HBM traffic of the complex-shifted sparse product (k_spmm_v, k_spmm_t), 3D scalar")
-    print("# vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768), full-width launches.")
+    print("# HBM traffic of the complex-shifted sparse products (BiCGStab: k_spmm_v, k_spmm_t; COCG:")
+    print("# k_cocg_spmm), 3D scalar vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768),")
+    print("# full-width launches.")
     print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
-    print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|elementwise\" --output-format csv "
+    print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|elementwise\" --output-format csv "
           "-d R/gpurun_out/pmc_fetch -o run -- python3 R/bench.py --counters-probe")
-    print("#   rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_spmm|elementwise\" --output-format csv "
+    print("#   rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|elementwise\" --output-format csv "
           "-d R/gpurun_out/pmc_write -o run -- python3 R/bench.py --counters-probe")
     print("#   python3 bench.py --summarize-pmc R/gpurun_out/pmc_fetch/run_counter_collection.csv "
           "R/gpurun_out/pmc_write/run_counter_collection.csv <probe stdout>")
@@ -232,21 +240,26 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
     print(f"copy WRITE_SIZE KiB: {wr['copy'][0]:.0f}")
     print(f"copy_fetch_factor: {ff:.4f}")
     print(f"copy_write_factor: {fw:.4f}")
-    for dtype in ("float", "double"):
-        tot = 0.0
-        for kern in (f"k_spmm_v<{dtype}>", f"k_spmm_t<{dtype}>"):
-            fk, nf = fe[kern]
-            wk, nw = wr[kern]
-            fb, wb = fk * 1024 / ff, wk * 1024 / fw
-            tot += fb + wb
-            print(f"{kern} dispatches: {nf}")
-            print(f"{kern} FETCH_SIZE KiB: {fk:.0f}")
-            print(f"{kern} WRITE_SIZE KiB: {wk:.0f}")
-            print(f"{kern} fetch bytes (calibrated): {fb:.4e}")
-            print(f"{kern} write bytes (calibrated): {wb:.4e}")
-        print(f"full_launch_traffic_bytes {dtype}: {tot / 2:.6e}")
-        print(f"full_launch_algorithmic_bytes {dtype}: {alg[dtype]:.6e}")
-        print(f"traffic_over_algorithmic {dtype}: {tot / 2 / alg[dtype]:.3f}")
+    for family, kerns in (("bicgstab", ("k_spmm_v<{}>", "k_spmm_t<{}>")), ("cocg", ("k_cocg_spmm<{}>",))):
+        for dtype in ("float", "double"):
+            if (family, dtype) not in alg or any(k.format(dtype) not in fe for k in kerns):
+                continue
+            tot = 0.0
+            for kern in (k.format(dtype) for k in kerns):
+                fk, nf = fe[kern]
+                wk, nw = wr[kern]
+                fb, wb = fk * 1024 / ff, wk * 1024 / fw
+                tot += fb + wb
+                print(f"{kern} dispatches: {nf}")
+                print(f"{kern} FETCH_SIZE KiB: {fk:.0f}")
+                print(f"{kern} WRITE_SIZE KiB: {wk:.0f}")
+                print(f"{kern} fetch bytes (calibrated): {fb:.4e}")
+                print(f"{kern} write bytes (calibrated): {wb:.4e}")
+            key = dtype if family == "bicgstab" else f"{family} {dtype}"
+            a = alg[(family, dtype)]
+            print(f"full_launch_traffic_bytes {key}: {tot / len(kerns):.6e}")
+            print(f"full_launch_algorithmic_bytes {key}: {a:.6e}")
+            print(f"traffic_over_algorithmic {key}: {tot / len(kerns) / a:.3f}")
 
 
 def union_nnz(p):
@@ -261,9 +274,11 @@ def batch_kernel_stats(results):
 
 
 def many_options(slrf, args, precision, **kw):
-    """Options of the batched, served and serial runs: with --graph (the default)
-    the Krylov iteration chunks replay as hipGraphs and the per-launch kernel
-    timers are off; with --no-graph the kernels are timed (roofline fields)."""
+    """Options of the batched, served and serial runs (scalar pencils, point
+    Jacobi: COCG unless --solver bicgstab): with --graph (the default) the Krylov
+    iteration chunks replay as hipGraphs and the per-launch kernel timers are
+    off; with --no-graph the kernels are timed (roofline fields)."""
+    kw.setdefault("solver", slrf.SOLVER_BICGSTAB if args.solver == "bicgstab" else slrf.SOLVER_COCG)
     if args.graph:
         return slrf.default_options(precision=precision, graph=1, profile=0, **kw)
     return slrf.default_options(precision=precision, profile=1, **kw)
@@ -550,8 +565,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
-    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cocg"],
-                    help="inner solver of the shifted systems (COCG: point-Jacobi workloads only)")
+    ap.add_argument("--solver", default="auto", choices=["auto", "bicgstab", "cocg"],
+                    help="inner solver of the shifted systems; auto: COCG for point-Jacobi workloads "
+                         "(BiCGStab timed beside it), BiCGStab for ILU(0) and block-Jacobi ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
     ap.add_argument("--requests", type=int, default=24, help="served workload: number of requests")
@@ -595,7 +611,8 @@ def main():
         desc = (f"{len(insts)} independent 2D/3D scalar vibration pencils (bilinear/trilinear FE, "
                 "log-normal coefficient sigma=0.5, seeds 1000+i), n log-uniform 5e3..2e5 "
                 f"(sum {sum(p.n for p, *_ in insts)}), NEV 10..80 each with its own gamma, "
-                "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles")
+                "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles; "
+                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}")
         print(json.dumps(many_line(args, "batched", out, desc)), flush=True)
         return
     if args.workload == "served":
@@ -603,11 +620,13 @@ def main():
         desc = (f"{len(reqs)} Poisson-arriving requests (rate 0.7 x calibrated capacity), 3D scalar "
                 f"vibration pencils n log-uniform {args.n_min:.0e}..{args.n_max:.0e}, NEV log-uniform "
                 f"20..{args.nev_max}, L = ceil(1.2 NEV) to a multiple of 8, N=6, seeds 5000+r; continuous batching, "
-                "admission by HBM footprint, mixed precision")
+                "admission by HBM footprint, mixed precision; "
+                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}")
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
     wl = workload(args.workload)
-    wl["solver"] = 1 if args.solver == "cocg" else 0
+    jacobi = wl.get("precond", 0) in (0, 1) and args.workload != "c1"
+    wl["solver"] = 1 if args.solver == "cocg" or (args.solver == "auto" and jacobi) else 0
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
@@ -617,6 +636,9 @@ def main():
     if args.precision in ("both", "fp64"):
         fp_steps, fp_warm = (1, 0) if args.precision == "both" else (args.steps, args.warmup)
         forms["fp64"] = run_form(slrf, wl, slrf.FP64, fp_steps, fp_warm, sig, w, V0)
+    if args.solver == "auto" and wl["solver"] == 1 and args.precision in ("both", "mixed"):
+        # the paper's inner solver on the same workload, for comparison
+        forms["bicgstab"] = run_form(slrf, dict(wl, solver=0), slrf.MIXED, 1, 0, sig, w, V0)
     main_form = "mixed" if "mixed" in forms else "fp64"
     m = forms[main_form]
     ks = m["ks"]
@@ -626,10 +648,8 @@ def main():
         else "complex FP64 inner solves"
     prec += "; inner solver " + ("COCG" if wl["solver"] == 1 else "BiCGStab")
     kdtype = "float" if main_form == "mixed" else "double"
-    if wl["solver"] == 1:
-        traffic, traffic_note = None, "counters are taken for the BiCGStab sparse products (k_spmm_v / k_spmm_t)"
-    else:
-        traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]))
+    traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
+                                        "cocg" if wl["solver"] == 1 else "bicgstab")
     kname = "k_cocg_spmm" if wl["solver"] == 1 else "k_spmm_v / k_spmm_t"
     out = {
         "metric": METRIC, "value": m["value"], "unit": "eigenpairs/s", "n_gpus": 1,
@@ -659,6 +679,16 @@ def main():
                        "outer_iterations": f["results"][-1].stats["outer_iterations"],
                        "max_resid": f["results"][-1].stats["max_resid"]}
         out["mixed_over_fp64"] = m["value"] / f["value"]
+    if "bicgstab" in forms:
+        f = forms["bicgstab"]
+        fk = f["ks"]
+        out["bicgstab_mixed"] = {"value": f["value"], "ms_per_step": 1e3 * f["dt"],
+                                 "spmm_GBs": fk["spmm_bytes"] / fk["spmm_seconds"] / 1e9,
+                                 "update_GBs": fk["update_bytes"] / fk["update_seconds"] / 1e9,
+                                 "outer_iterations": f["results"][-1].stats["outer_iterations"],
+                                 "spmv_total": f["results"][-1].stats["spmv_total"],
+                                 "max_resid": f["results"][-1].stats["max_resid"]}
+        out["cocg_over_bicgstab"] = m["value"] / f["value"]
     if not args.no_cpu_baseline:
         log("cpu baseline sample...")
         ref = forms.get("fp64", m)
