@@ -566,8 +566,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--solver", default="auto", choices=["auto", "bicgstab", "cocg"],
-                    help="inner solver of the shifted systems; auto: COCG for point-Jacobi workloads "
-                         "(BiCGStab timed beside it), BiCGStab for ILU(0) and block-Jacobi ones")
+                    help="inner solver of the shifted systems; auto: COCG (BiCGStab timed beside it on "
+                         "the 64^3 workload), BiCGStab for the ILU(0) string")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
     ap.add_argument("--requests", type=int, default=24, help="served workload: number of requests")
@@ -625,8 +625,8 @@ def main():
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
     wl = workload(args.workload)
-    jacobi = wl.get("precond", 0) in (0, 1) and args.workload != "c1"
-    wl["solver"] = 1 if args.solver == "cocg" or (args.solver == "auto" and jacobi) else 0
+    symmetric = args.workload != "c1"          # C1 runs ILU(0), which COCG does not take
+    wl["solver"] = 1 if args.solver == "cocg" or (args.solver == "auto" and symmetric) else 0
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
@@ -636,7 +636,8 @@ def main():
     if args.precision in ("both", "fp64"):
         fp_steps, fp_warm = (1, 0) if args.precision == "both" else (args.steps, args.warmup)
         forms["fp64"] = run_form(slrf, wl, slrf.FP64, fp_steps, fp_warm, sig, w, V0)
-    if args.solver == "auto" and wl["solver"] == 1 and args.precision in ("both", "mixed"):
+    if (args.solver == "auto" and wl["solver"] == 1 and args.precision in ("both", "mixed")
+            and not wl.get("stepwise")):
         # the paper's inner solver on the same workload, for comparison
         forms["bicgstab"] = run_form(slrf, dict(wl, solver=0), slrf.MIXED, 1, 0, sig, w, V0)
     main_form = "mixed" if "mixed" in forms else "fp64"

@@ -98,9 +98,10 @@ typedef struct {
   int32_t solver;      /* inner solver of the shifted systems: 0 BiCGStab (Section 2,
                           the paper's choice), 1 COCG, conjugate gradients with the
                           bilinear form u^T v for the complex-symmetric A - sigma_j B
-                          (one sparse product per iteration; point Jacobi only:
-                          precond 0 then selects Jacobi, precond 2 and 3 are
-                          rejected with SLRF_E_INVALID_ARG) */
+                          (one sparse product per iteration; symmetric
+                          preconditioners only: precond 0 then selects point
+                          Jacobi, 3 node block Jacobi, and 2 (ILU(0)) is rejected
+                          with SLRF_E_INVALID_ARG) */
 } slrf_options;
 
 typedef struct {
@@ -181,7 +182,7 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n,
  *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
  * every (pole, column) system solved by right-preconditioned BiCGStab (the
  * preconditioner of slrf_options.precond), x_0 = 0 and shadow residual B X, or by
- * Jacobi-preconditioned COCG (slrf_options.solver = 1).  d_X, d_U: device (n, L) row-major float64
+ * COCG with point or node block Jacobi (slrf_options.solver = 1).  d_X, d_U: device (n, L) row-major float64
  * (may not alias).  stats may be NULL.  Returns SLRF_OK even if some columns hit
  * inner_maxit or broke down; stats reports them. */
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L,

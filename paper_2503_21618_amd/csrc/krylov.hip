@@ -1365,12 +1365,35 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
 // ---- COCG (conjugate orthogonal CG) for the complex-symmetric shifted systems ----
 // S = A - sigma B is complex symmetric, so CG with the bilinear form [u, v] = u^T v
 // applies (van der Vorst and Melissen 1990): one sparse product per iteration.
-// Point Jacobi only (M = diag(S), symmetric); z = M^{-1} r is never stored.
+// Point Jacobi (M = diag(S)) or node block Jacobi (M = the 3x3 node blocks of S,
+// complex symmetric; the vector kernels then walk nodes); z = M^{-1} r is never
+// stored.
 // Storage: p in ph (the gathered direction), q = S p in v.
 //   start:  p = M^{-1} r, rho = [r, p]           (after k_init / k_mixed_rhs)
 //   q = S p, alpha = rho / [p, q]
 //   x += alpha p, r -= alpha q                    -> stop if ||r|| <= tol ||f||
 //   rho' = [r, M^{-1} r], beta = rho' / rho, p = M^{-1} r + beta p
+
+// Node block Jacobi inside the COCG kernels: z = M_k^{-1} r for node k (rows
+// 3k .. 3k + 2) of the lane's columns; M_k^{-1} is the (pole, node) 3x3 inverse
+// (row-major, complex symmetric).  Columns past K take z = 0.
+template <typename R, int V>
+__device__ __forceinline__ void node_apply(const Inst& I, int k, int cl0, int cc0, const cvec<R, V> (&r)[3],
+                                           cvec<R, V> (&z)[3]) {
+  const int nodes = I.n / 3;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    if (cl0 + v >= I.K) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) z[i].c[v] = {0, 0};
+      continue;
+    }
+    const cx<R>* m = static_cast<const cx<R>*>(I.bjac) + ((size_t)((cc0 + v) / I.L) * nodes + (size_t)k) * 9;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      z[i].c[v] = cadd(cadd(cmul(m[3 * i], r[0].c[v]), cmul(m[3 * i + 1], r[1].c[v])), cmul(m[3 * i + 2], r[2].c[v]));
+  }
+}
 
 // p = M^{-1} r over every tile; partial [r, p] in part_a
 template <typename R>
@@ -1379,7 +1402,25 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_start(Batch b, KrylovState<R> st
   const WgPos p = wg_pos(b.G);
   FOR_TILES(b, p, V)
     cx<R> rz[V] = {};
-    if (valid) {
+    if (valid && I.bjac) {  // node block Jacobi: one node (three rows) per wavefront step
+      for (int k = blockIdx.x * 4 + p.w; k < I.n / 3; k += b.G * 4) {
+        const size_t e0 = tb + (size_t)(3 * k) * (WAVE * V);
+        cvec<R, V> r[3], z[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = ldv<R, V>(st.r + e0 + (size_t)i * (WAVE * V));
+        node_apply<R, V>(I, k, cl0, cc0, r, z);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const cx<R> t = cmul(r[i].c[v], z[i].c[v]);
+            rz[v].re += t.re;
+            rz[v].im += t.im;
+          }
+          stv<R, V>(st.ph + e0 + (size_t)i * (WAVE * V), z[i]);
+        }
+      }
+    } else if (valid) {
       int pole[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) pole[v] = min((cc0 + v) / I.L, I.N - 1);
@@ -1498,6 +1539,43 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
         pole[v] = min((cc0 + v) / I.L, I.N - 1);
         alpha[v] = f[v] == COL_ACTIVE ? st.alpha[cg0 + v] : cx<R>{0, 0};
       }
+      if (I.bjac) {  // node block Jacobi: one node per wavefront step
+        for (int k = blockIdx.x * 4 + p.w; k < I.n / 3; k += b.G * 4) {
+          const size_t e0 = tb + (size_t)(3 * k) * (WAVE * V);
+          cvec<R, V> x[3], r[3], pv[3], q[3], z[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            const size_t e = e0 + (size_t)i * (WAVE * V);
+            x[i] = ldv<R, V>(st.x + e);
+            r[i] = ldv<R, V>(st.r + e);
+            pv[i] = ldv<R, V>(st.ph + e);
+            q[i] = ldv<R, V>(st.v + e);
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              if (f[v] != COL_ACTIVE) continue;
+              x[i].c[v] = cadd(x[i].c[v], cmul(alpha[v], pv[i].c[v]));
+              r[i].c[v] = csub(r[i].c[v], cmul(alpha[v], q[i].c[v]));
+            }
+          node_apply<R, V>(I, k, cl0, cc0, r, z);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              if (f[v] != COL_ACTIVE) continue;
+              const cx<R> rv = r[i].c[v];
+              const cx<R> t = cmul(rv, z[i].c[v]);
+              rz[v].re += t.re;
+              rz[v].im += t.im;
+              nn[v] += rv.re * rv.re + rv.im * rv.im;
+            }
+            stv<R, V>(st.x + e0 + (size_t)i * (WAVE * V), x[i]);
+            stv<R, V>(st.r + e0 + (size_t)i * (WAVE * V), r[i]);
+          }
+        }
+      } else {
       constexpr int kRowBatch = 2;
       FOR_ROW_BATCH(b, p, I, kRowBatch)
         size_t e[kRowBatch];
@@ -1529,6 +1607,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
           stv<R, V>(st.r + e[u], r[u]);
         }
       END_ROWS
+      }
     }
     wg_store_partial_cx<R, V>(rz, p.w, p.lane, cl0, I.K, st.part_a + po);
     wg_store_partial<R, V>(nn, p.w, p.lane, cl0, I.K, st.part_b + po);
@@ -1582,6 +1661,26 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R>
     for (int v = 0; v < V; ++v) {
       pole[v] = min((cc0 + v) / I.L, I.N - 1);
       beta[v] = st.beta[cg0 + v];
+    }
+    if (I.bjac) {  // node block Jacobi: one node per wavefront step
+      for (int k = blockIdx.x * 4 + p.w; k < I.n / 3; k += b.G * 4) {
+        const size_t e0 = tb + (size_t)(3 * k) * (WAVE * V);
+        cvec<R, V> r[3], pv[3], z[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          r[i] = ldv<R, V>(st.r + e0 + (size_t)i * (WAVE * V));
+          pv[i] = ldv<R, V>(st.ph + e0 + (size_t)i * (WAVE * V));
+        }
+        node_apply<R, V>(I, k, cl0, cc0, r, z);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (f[v] == COL_ACTIVE) pv[i].c[v] = cadd(z[i].c[v], cmul(beta[v], pv[i].c[v]));
+          stv<R, V>(st.ph + e0 + (size_t)i * (WAVE * V), pv[i]);
+        }
+      }
+      continue;
     }
     constexpr int kRowBatch = 4;
     FOR_ROW_BATCH(b, p, I, kRowBatch)

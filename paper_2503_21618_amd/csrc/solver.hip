@@ -505,10 +505,10 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   if (env.opt.precond < 0 || env.opt.precond > 3) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
   if (env.opt.solver != 0 && env.opt.solver != 1) return fail(env, SLRF_E_INVALID_ARG, "unknown inner solver");
   if (env.opt.solver == 1) {
-    // COCG needs a complex-symmetric preconditioner: point Jacobi
-    if (env.opt.precond == 2 || env.opt.precond == 3)
-      return fail(env, SLRF_E_INVALID_ARG, "COCG takes point Jacobi only (precond 0 or 1)");
-    env.opt.precond = 1;
+    // COCG needs a complex-symmetric preconditioner: point or node block Jacobi
+    if (env.opt.precond == 2)
+      return fail(env, SLRF_E_INVALID_ARG, "COCG takes point or node block Jacobi (ILU(0) is not symmetric)");
+    if (env.opt.precond == 0) env.opt.precond = 1;
   }
   if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
     return fail(env, SLRF_E_INVALID_ARG, "tolerances must be non-negative");
