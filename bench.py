@@ -1,6 +1,6 @@
 """Benchmark: eigenpairs/s of the SLRF interval eigensolver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|batched|served]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|batched|served|filters]
                     [--precision both|mixed|fp64] [--no-cpu-baseline]
     python bench.py --counters-probe | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
 
@@ -445,6 +445,60 @@ def run_served(slrf, args):
     return out, reqs
 
 
+def run_filters(slrf, args):
+    """Section 3.2's filter comparison on a synthetic stand-in for its 2D model:
+    N = 3 poles from the SLRF design (alpha = 0.5, beta = 0.01) and from the
+    midpoint, Gauss-Legendre and Gauss-Chebyshev rules, on a 2D scalar pencil
+    with gamma between its 20th and 21st eigenvalues.  Per pole: mean inner
+    iterations of the FP64 solves (tol 1e-10, at most 5000 iterations, L = 24
+    columns) with BiCGStab and
+    with COCG; per filter: a complete mixed-precision interval solve (COCG)."""
+    import numpy as np
+    import scipy.sparse.linalg as sla
+    import torch
+
+    import pencils
+    p = pencils.scalar_q1(100, 2, 0.5, 7)
+    ev = np.sort(sla.eigsh(p.A.tocsc(), k=22, M=p.B.tocsc(), sigma=0.0, which="LM",
+                           return_eigenvectors=False))
+    gamma = 0.5 * (ev[19] + ev[20])
+    L = 24
+    X = torch.from_numpy(pencils.start_block(p.n, L, 1)).cuda()
+    filters = {"SLRF": slrf.design_poles(3, 0.5, 0.01, gamma)[:2]}
+    for rule, name in ((slrf.QUAD_MIDPOINT, "midpoint"), (slrf.QUAD_GAUSS_LEGENDRE, "gauss-legendre"),
+                       (slrf.QUAD_GAUSS_CHEBYSHEV, "gauss-chebyshev")):
+        filters[name] = slrf.quadrature_poles(rule, 3, gamma)
+    log(f"2D pencil n={p.n}, gamma={gamma:.4f} (20 eigenvalues below)")
+    out = {"pencil": f"2D scalar Q1 99^2 (n={p.n}), log-normal sigma=0.5 seed 7, gamma={gamma:.6g}",
+           "inner": {}, "solve": {}}
+    for fname, (sig, w) in filters.items():
+        row = {"poles": [[float(z.real), float(z.imag)] for z in sig]}
+        for solver, sname in ((slrf.SOLVER_BICGSTAB, "bicgstab"), (slrf.SOLVER_COCG, "cocg")):
+            its = []
+            for j in range(len(sig)):
+                opt = slrf.default_options(precision=slrf.FP64, inner_tol=1e-10, inner_maxit=5000, solver=solver)
+                s = slrf.Solver(p.A, p.B, max_L=L, max_poles=1, options=opt)
+                _, st = s.filter_apply(X, sig[j:j + 1], w[j:j + 1])
+                its.append(st["mean_iterations"])
+                s.close()
+            row[sname] = [round(v, 1) for v in its]
+        out["inner"][fname] = row
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=3,
+                        options=slrf.default_options(precision=slrf.MIXED, inner_maxit=5000,
+                                                     solver=slrf.SOLVER_COCG))
+        t0 = time.perf_counter()
+        r = s.solve_interval(gamma, L, sig, w, V0=X, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out["solve"][fname] = {"status": r.status, "found": r.n_found, "outer": r.stats["outer_iterations"],
+                               "spmv_total": r.stats["spmv_total"], "seconds": dt,
+                               "max_resid": r.stats["max_resid"]}
+        log(f"{fname}: inner its BiCGStab {row['bicgstab']}, COCG {row['cocg']}; solve found {r.n_found}, "
+            f"outer {r.stats['outer_iterations']}, spmv {r.stats['spmv_total']}")
+    return out
+
+
 def many_line(args, kind, out, desc):
     ks = out.pop("ks")
     line = {"metric": METRIC, "value": out["value"], "unit": "eigenpairs/s", "n_gpus": 1,
@@ -614,6 +668,10 @@ def main():
                 "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles; "
                 f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}")
         print(json.dumps(many_line(args, "batched", out, desc)), flush=True)
+        return
+    if args.workload == "filters":
+        print(json.dumps({"metric": "mean inner iterations per pole (Section 3.2 filter comparison)",
+                          "data": "synthetic", "filters": run_filters(slrf, args)}), flush=True)
         return
     if args.workload == "served":
         out, reqs = run_served(slrf, args)

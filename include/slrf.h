@@ -154,6 +154,17 @@ void slrf_default_options(slrf_options* opt);
 slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma,
                               double* sigma_out, double* weight_out, double* sep_factor_out);
 
+/* Quadrature-rule filters of Section 3.2 (the filters the SLRF is compared
+ * with): N nodes in the upper half-plane on the circle with centre gamma/2 and
+ * radius gamma/2, from the midpoint (rule 0), Gauss-Legendre (rule 1) or
+ * Gauss-Chebyshev (rule 2) rule in the angle; weights of the contour integral
+ * of the spectral projector, so that Phi(x) = sum_j 2 Re(w_j/(x - sigma_j)) is
+ * close to 1 inside [0, gamma] and to 0 outside.  Host-only.  Outputs as for
+ * slrf_design_poles (2N doubles each, sorted by Re(sigma)); usable as the
+ * slrf_poles of slrf_filter_apply and slrf_solve_interval.
+ * Errors: INVALID_ARG for an unknown rule, N < 1 or N > 64, gamma <= 0. */
+slrf_status slrf_quadrature_poles(int32_t rule, int32_t N, double gamma, double* sigma_out, double* weight_out);
+
 /* Bytes of device workspace slrf_create needs for a pencil with n rows and
  * nnz_union entries in the union of the patterns of A and B, subspace size up
  * to L and up to N poles, at the given precision, with the automatic

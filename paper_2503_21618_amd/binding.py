@@ -65,6 +65,7 @@ class SolveStats(C.Structure):
 _P = C.c_void_p
 _lib.slrf_default_options.argtypes = [C.POINTER(Options)]
 _lib.slrf_design_poles.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, _P, _P, _P]
+_lib.slrf_quadrature_poles.argtypes = [C.c_int32, C.c_int32, C.c_double, _P, _P]
 _lib.slrf_workspace_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_size_t)]
 _lib.slrf_workspace_bytes_for.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.POINTER(Options),
@@ -106,7 +107,8 @@ _lib.slrf_test_gemm.restype = C.c_int
 _lib.slrf_test_gram_scratch.argtypes = [C.c_int64, C.c_int64]
 _lib.slrf_test_gram_scratch.restype = C.c_size_t
 
-EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_workspace_bytes", "slrf_workspace_bytes_for",
+EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_quadrature_poles", "slrf_workspace_bytes",
+            "slrf_workspace_bytes_for",
             "slrf_create",
             "slrf_filter_apply", "slrf_solve_interval", "slrf_destroy", "slrf_status_string",
             "slrf_last_error", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
@@ -170,6 +172,20 @@ def design_poles(N: int, alpha: float = 1.0, beta: float = 0.01, gamma: float = 
     if st:
         raise SlrfError(st, "pole design")
     return s[0::2] + 1j * s[1::2], w[0::2] + 1j * w[1::2], float(sep[0])
+
+
+QUAD_MIDPOINT, QUAD_GAUSS_LEGENDRE, QUAD_GAUSS_CHEBYSHEV = 0, 1, 2
+
+
+def quadrature_poles(rule: int, N: int, gamma: float = 1.0):
+    """Section 3.2 quadrature-rule filter on the circle over [0, gamma]: upper
+    half-plane poles and weights (complex arrays, sorted by real part)."""
+    s = np.zeros(2 * N)
+    w = np.zeros(2 * N)
+    st = _lib.slrf_quadrature_poles(rule, N, gamma, _ptr(s), _ptr(w))
+    if st:
+        raise SlrfError(st, "quadrature poles")
+    return s[0::2] + 1j * s[1::2], w[0::2] + 1j * w[1::2]
 
 
 def workspace_bytes(n: int, nnz: int, L: int, N: int, precision: int = FP64, options: Options | None = None) -> int:

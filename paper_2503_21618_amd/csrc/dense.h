@@ -14,4 +14,8 @@ bool projected_pencil(int L, const double* GA, const double* GB, double* theta, 
 // SLRF design at gamma = 1 (see slrf.h): xi[N] sorted, omega[2N] (re, im).
 bool design_poles_unit(int N, double alpha, double beta, double* xi, double* omega);
 
+// Quadrature-rule filter of Section 3.2 (rule 0 midpoint, 1 Gauss-Legendre,
+// 2 Gauss-Chebyshev): sigma[2N], weight[2N] (re, im), sorted by Re(sigma).
+bool quadrature_poles(int rule, int N, double gamma, double* sigma, double* weight);
+
 }  // namespace slrf

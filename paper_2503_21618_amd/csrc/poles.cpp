@@ -14,6 +14,7 @@
 // best result is kept.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <thread>
 #include <vector>
 
@@ -266,6 +267,81 @@ bool design_poles_unit(int N, double alpha, double beta, double* xi_out, double*
     xi_out[j] = xi[j];
     omega_out[2 * j] = coef[j];
     omega_out[2 * j + 1] = coef[N + j];
+  }
+  return true;
+}
+
+// Quadrature-rule filters of Section 3.2 (the comparison systems of its filter
+// study): nodes on the circle with centre gamma/2 and radius gamma/2, at angles
+// theta_j in (0, pi) from a rule for the integral over theta of the contour
+// integral of the spectral projector, z_j = c + r e^{i theta_j}, weights
+// w_j = -(r e^{i theta_j} q_j) / (2 pi) for the rule's angle weights q_j (the
+// lower half-plane follows by conjugation, Phi(x) = sum_j 2 Re(w_j/(x - z_j))).
+// Gauss-Legendre nodes by Newton's method on the three-term recurrence of P_N.
+bool quadrature_poles(int rule, int N, double gamma, double* sigma, double* weight) {
+  if (N < 1 || N > 64 || !(gamma > 0)) return false;
+  const double pi = 3.14159265358979323846;
+  std::vector<double> th(N), q(N);
+  if (rule == 0) {  // midpoint
+    for (int j = 0; j < N; ++j) {
+      th[j] = (j + 0.5) * pi / N;
+      q[j] = pi / N;
+    }
+  } else if (rule == 1) {  // Gauss-Legendre on [-1, 1] mapped to (0, pi)
+    for (int j = 0; j < N; ++j) {
+      double x = std::cos(pi * (j + 0.75) / (N + 0.5));
+      double dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= N; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        const double pn = N == 1 ? x : p1, pm = N == 1 ? 1.0 : p0;
+        dp = N * (x * pn - pm) / (x * x - 1.0);
+        const double dx = pn / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      {  // derivative at the converged node
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= N; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        const double pn = N == 1 ? x : p1, pm = N == 1 ? 1.0 : p0;
+        dp = N * (x * pn - pm) / (x * x - 1.0);
+      }
+      th[j] = (x + 1.0) * pi / 2.0;
+      q[j] = 2.0 / ((1.0 - x * x) * dp * dp) * pi / 2.0;
+    }
+  } else if (rule == 2) {  // Gauss-Chebyshev (first kind) for a smooth integrand on [-1, 1]
+    for (int j = 0; j < N; ++j) {
+      const double x = std::cos((2.0 * (j + 1) - 1.0) * pi / (2.0 * N));
+      th[j] = (x + 1.0) * pi / 2.0;
+      q[j] = (pi / N) * std::sqrt(1.0 - x * x) * pi / 2.0;
+    }
+  } else {
+    return false;
+  }
+  const double c = gamma / 2.0, r = gamma / 2.0;
+  std::vector<std::pair<double, int>> ord(N);
+  std::vector<std::complex<double>> z(N), w(N);
+  for (int j = 0; j < N; ++j) {
+    const std::complex<double> e = std::polar(1.0, th[j]);
+    z[j] = c + r * e;
+    w[j] = -(r * e) * q[j] / (2.0 * pi);
+    ord[j] = {z[j].real(), j};
+  }
+  std::sort(ord.begin(), ord.end());
+  for (int j = 0; j < N; ++j) {
+    const int k = ord[j].second;
+    sigma[2 * j] = z[k].real();
+    sigma[2 * j + 1] = z[k].imag();
+    weight[2 * j] = w[k].real();
+    weight[2 * j + 1] = w[k].imag();
   }
   return true;
 }

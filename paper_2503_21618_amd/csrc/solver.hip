@@ -1591,6 +1591,12 @@ slrf_status slrf_design_poles(int32_t N, double alpha, double beta, double gamma
   return SLRF_OK;
 }
 
+slrf_status slrf_quadrature_poles(int32_t rule, int32_t N, double gamma, double* sigma_out, double* weight_out) {
+  if (!sigma_out || !weight_out || !quadrature_poles(rule, N, gamma, sigma_out, weight_out))
+    return SLRF_E_INVALID_ARG;
+  return SLRF_OK;
+}
+
 slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz, int64_t L, int32_t N, const slrf_options* opt,
                                      size_t* bytes) {
   slrf_options o;

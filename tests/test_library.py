@@ -44,6 +44,23 @@ def test_default_options(lib):
     assert o.solver == lib.SOLVER_BICGSTAB
 
 
+@pytest.mark.parametrize("rule", [0, 1, 2])
+def test_quadrature_poles_match_oracle(lib, rule):
+    """Section 3.2 quadrature filters: the library's host rule (Newton iteration
+    for the Gauss-Legendre nodes) against the oracle's (numpy's leggauss)."""
+    from oracle import poles
+    name = {0: "midpoint", 1: "gauss-legendre", 2: "gauss-chebyshev"}[rule]
+    for N in (1, 3, 4, 8, 16):
+        s, w = lib.quadrature_poles(rule, N, 2.5)
+        so, wo = poles.circle_quadrature(N, name, 2.5)
+        assert np.abs(s - so).max() < 1e-14 * 2.5
+        assert np.abs(w - wo).max() < 1e-14 * 2.5
+    with pytest.raises(lib.SlrfError):
+        lib.quadrature_poles(3, 4, 1.0)
+    with pytest.raises(lib.SlrfError):
+        lib.quadrature_poles(rule, 0, 1.0)
+
+
 @pytest.mark.parametrize("N", [4, 6])
 def test_design_matches_oracle_tables(lib, N):
     """Product pole design (host C++) vs the oracle's design (stored tables)."""
