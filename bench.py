@@ -279,6 +279,7 @@ def many_options(slrf, args, precision, **kw):
     iteration chunks replay as hipGraphs and the per-launch kernel timers are
     off; with --no-graph the kernels are timed (roofline fields)."""
     kw.setdefault("solver", slrf.SOLVER_BICGSTAB if args.solver == "bicgstab" else slrf.SOLVER_COCG)
+    kw.setdefault("recycle", 1 if args.recycle == "1" or (args.recycle == "auto" and kw["solver"] == 1) else 0)
     if args.graph:
         return slrf.default_options(precision=precision, graph=1, profile=0, **kw)
     return slrf.default_options(precision=precision, profile=1, **kw)
@@ -535,7 +536,7 @@ def run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0):
     pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, precision)
     ws = pers + trans + (1 << 24)
     opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
-                               solver=wl.get("solver", 0))
+                               solver=wl.get("solver", 0), recycle=wl.get("recycle", 0))
     log(f"{tag}: n={p.n} L={L} N={N} workspace {ws / 2**30:.2f} GiB (one-pencil batch)")
 
     def solve():
@@ -579,7 +580,7 @@ def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
     p = wl["pencil"]
     L, N, gamma = wl["L"], wl["N"], wl["gamma"]
     opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
-                               solver=wl.get("solver", 0))
+                               solver=wl.get("solver", 0), recycle=wl.get("recycle", 0))
     solver = slrf.Solver(p.A, p.B, max_L=L, max_poles=N, options=opt)
     tag = "mixed" if precision == slrf.MIXED else "fp64"
     log(f"{tag}: n={p.n} L={L} N={N} workspace {solver.ws_bytes / 2**30:.2f} GiB")
@@ -619,6 +620,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--recycle", default="auto", choices=["auto", "0", "1"],
+                    help="warm starts across outer iterations (mixed precision); auto: with COCG")
     ap.add_argument("--solver", default="auto", choices=["auto", "bicgstab", "cocg"],
                     help="inner solver of the shifted systems; auto: COCG (BiCGStab timed beside it on "
                          "the 64^3 workload), BiCGStab for the ILU(0) string")
@@ -666,7 +669,8 @@ def main():
                 "log-normal coefficient sigma=0.5, seeds 1000+i), n log-uniform 5e3..2e5 "
                 f"(sum {sum(p.n for p, *_ in insts)}), NEV 10..80 each with its own gamma, "
                 "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles; "
-                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}")
+                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}"
+                f"{', warm starts' if args.recycle != '0' and args.solver != 'bicgstab' else ''}")
         print(json.dumps(many_line(args, "batched", out, desc)), flush=True)
         return
     if args.workload == "filters":
@@ -679,12 +683,14 @@ def main():
                 f"vibration pencils n log-uniform {args.n_min:.0e}..{args.n_max:.0e}, NEV log-uniform "
                 f"20..{args.nev_max}, L = ceil(1.2 NEV) to a multiple of 8, N=6, seeds 5000+r; continuous batching, "
                 "admission by HBM footprint, mixed precision; "
-                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}")
+                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}"
+                f"{', warm starts' if args.recycle != '0' and args.solver != 'bicgstab' else ''}")
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
     wl = workload(args.workload)
     symmetric = args.workload != "c1"          # C1 runs ILU(0), which COCG does not take
     wl["solver"] = 1 if args.solver == "cocg" or (args.solver == "auto" and symmetric) else 0
+    wl["recycle"] = 1 if args.recycle == "1" or (args.recycle == "auto" and wl["solver"] == 1) else 0
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
@@ -697,7 +703,7 @@ def main():
     if (args.solver == "auto" and wl["solver"] == 1 and args.precision in ("both", "mixed")
             and not wl.get("stepwise")):
         # the paper's inner solver on the same workload, for comparison
-        forms["bicgstab"] = run_form(slrf, dict(wl, solver=0), slrf.MIXED, 1, 0, sig, w, V0)
+        forms["bicgstab"] = run_form(slrf, dict(wl, solver=0, recycle=0), slrf.MIXED, 1, 0, sig, w, V0)
     main_form = "mixed" if "mixed" in forms else "fp64"
     m = forms[main_form]
     ks = m["ks"]
@@ -706,6 +712,8 @@ def main():
     prec = "complex FP32 inner solves + FP64 defect correction and Rayleigh-Ritz" if main_form == "mixed" \
         else "complex FP64 inner solves"
     prec += "; inner solver " + ("COCG" if wl["solver"] == 1 else "BiCGStab")
+    if wl["recycle"] and main_form == "mixed":
+        prec += ", warm starts across outer iterations"
     kdtype = "float" if main_form == "mixed" else "double"
     traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
                                         "cocg" if wl["solver"] == 1 else "bicgstab")

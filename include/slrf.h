@@ -102,6 +102,13 @@ typedef struct {
                           preconditioners only: precond 0 then selects point
                           Jacobi, 3 node block Jacobi, and 2 (ILU(0)) is rejected
                           with SLRF_E_INVALID_ARG) */
+  int32_t recycle;     /* 1 (mixed precision): each filter application after the first
+                          starts its shifted solves from the previous one's solutions
+                          carried to the new block, Y0 = Y_prev (X_prev^T B X_new)
+                          (exact when X_new lies in span(X_prev)); needs the same
+                          pencils in the same order as the previous application (in
+                          a batch: the same unfinished pencils), else starts cold.
+                          Default 0 (cold starts, x_0 = 0) */
 } slrf_options;
 
 typedef struct {
@@ -139,7 +146,7 @@ typedef struct {
 
 /* Defaults: FP64, inner_tol 1e-13, inner_maxit 1000, outer_tol 1e-8,
  * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0,
- * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0, solver 0 (BiCGStab). */
+ * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0, solver 0 (BiCGStab), recycle 0. */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance

@@ -39,6 +39,7 @@ struct Inst {
   int Kp;                // padded columns: K rounded up to a whole tile (blocks are tile-major)
   int nrb, slab, steps;  // row blocks, row blocks per XCD, steps per workgroup
   int rot;               // rotation of the pencil's row blocks over an XCD's workgroups
+  int rmaj;              // column order: 0 pole-major, 1 right-hand-side-major (col_pole)
   int col0, tile0;       // first global column and first global tile
   int nnz;
   int64_t blk;           // element offset of the (n, K) blocks
@@ -55,6 +56,21 @@ struct Inst {
   const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
   const void* bjac;             // (N, n/3, 3, 3) cx<R> inverted node blocks, or null
 };
+
+// Column order of a pencil's blocks.  Pole-major (rmaj = 0): column c = j L + l
+// holds right-hand side l (column l of B X) for pole j, so a tile belongs to
+// one pole and the tiles of fast poles retire early.  Right-hand-side-major
+// (rmaj = 1, used with warm starts): c = l N + j, so a tile covers a few
+// right-hand sides for every pole and right-hand sides that start close to
+// their solutions retire whole tiles.  Padding columns (c >= N L) map to the
+// last pole and right-hand side.
+__host__ __device__ inline int col_pole(int c, int L, int N, int rmaj) {
+  return rmaj ? c % N : (c / L < N ? c / L : N - 1);
+}
+__host__ __device__ inline int col_rhs(int c, int L, int N, int rmaj) {
+  return rmaj ? (c / N < L ? c / N : L - 1) : c % L;
+}
+__host__ __device__ inline int col_of(int j, int l, int L, int N, int rmaj) { return rmaj ? l * N + j : j * L + l; }
 
 // Kernel argument describing a whole batch (device tables).
 struct Batch {
@@ -173,8 +189,13 @@ void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* di
 // U = sum_j 2 Re(w_j x[:, j L .. j L + L)), x a tile-major block (tiles of W
 // columns, each an n x W row-major panel)
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, const cx<R>* x,
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, const cx<R>* x,
                        const double* w /* 2N */, double* U, bool accumulate);
+
+// Y0 = Y_prev C per pole (C real L x L row-major), tile-major complex FP64
+// blocks with tiles of W columns and Kp padded columns (padding set to zero)
+void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
+                    const double* C, cx<double>* Y0);
 
 // real products with the merged pencil: AX = A X, BX = B X (either may be null)
 template <typename R>

@@ -28,9 +28,9 @@ void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* di
   k_jacobi<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, N, diagA, diagB, sigma, d, dinv);
 }
 
-// U[i, l] (+)= sum_j 2 Re(w_j x[i, j L + l])
+// U[i, l] (+)= sum_j 2 Re(w_j x[i, col_of(j, l)])
 template <typename R>
-__global__ void k_filter_sum(int n, int L, int N, int W, const cx<R>* __restrict__ x,
+__global__ void k_filter_sum(int n, int L, int N, int W, int rmaj, const cx<R>* __restrict__ x,
                              const double* __restrict__ w, double* __restrict__ U, int accumulate) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * L) return;
@@ -38,18 +38,49 @@ __global__ void k_filter_sum(int n, int L, int N, int W, const cx<R>* __restrict
   const int l = (int)(e % L);
   double s = accumulate ? U[e] : 0.0;
   for (int j = 0; j < N; ++j) {
-    const int c = j * L + l;  // tile-major block: tile c / W is an n x W panel
+    const int c = col_of(j, l, L, N, rmaj);  // tile c / W is an n x W panel
     const cx<R> y = x[(int64_t)(c / W) * n * W + i * W + c % W];
     s += 2.0 * (w[2 * j] * (double)y.re - w[2 * j + 1] * (double)y.im);
   }
   U[e] = s;
 }
 template <typename R>
-void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, const cx<R>* x, const double* w, double* U,
-                       bool accumulate) {
+void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, const cx<R>* x, const double* w,
+                       double* U, bool accumulate) {
   const int64_t tot = (int64_t)n * L;
-  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, x, w, U,
+  k_filter_sum<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, rmaj, x, w, U,
                                                                              accumulate ? 1 : 0);
+}
+
+// Warm start of the shifted solves: Y0 = Y_prev C per pole, with the real L x L
+// C = X_prev^T B X_new (row-major, C[l * L + l']).  Y_prev, Y0: tile-major
+// complex FP64 blocks (tiles of W columns) in column order rmaj, K = N L
+// columns padded to Kp; the padding columns of Y0 are zero.  One thread per
+// output element.
+__global__ void k_recycle(int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* __restrict__ Yp,
+                          const double* __restrict__ C, cx<double>* __restrict__ Y0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * Kp) return;
+  const int64_t i = e / Kp;
+  const int c = (int)(e % Kp);
+  cx<double> y = {0.0, 0.0};
+  if (c < N * L) {
+    const int j = col_pole(c, L, N, rmaj), lp = col_rhs(c, L, N, rmaj);
+    for (int l = 0; l < L; ++l) {
+      const int cs = col_of(j, l, L, N, rmaj);
+      const cx<double> v = Yp[(int64_t)(cs / W) * n * W + i * W + cs % W];
+      const double g = C[(int64_t)l * L + lp];
+      y.re += g * v.re;
+      y.im += g * v.im;
+    }
+  }
+  Y0[(int64_t)(c / W) * n * W + i * W + c % W] = y;
+}
+
+void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
+                    const double* C, cx<double>* Y0) {
+  const int64_t tot = (int64_t)n * Kp;
+  k_recycle<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, Kp, rmaj, Yp, C, Y0);
 }
 
 // Real products of the merged pencil with a real block: one wavefront per row.
@@ -319,8 +350,8 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
 #define SLRF_INST(R)                                                                                          \
   template void launch_jacobi_diag<R>(hipStream_t, int, int, const R*, const R*, const cx<R>*, cx<R>*,     \
                                       cx<R>*);                                                              \
-  template void launch_filter_sum<R>(hipStream_t, int, int, int, int, const cx<R>*, const double*, double*, \
-                                     bool);                                                                 \
+  template void launch_filter_sum<R>(hipStream_t, int, int, int, int, int, const cx<R>*, const double*,   \
+                                     double*, bool);                                                        \
   template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \
                                     const double*, double*, double*);
 SLRF_INST(double)

@@ -472,7 +472,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_v(Batch b, KrylovState<R> st, in
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) {
-            const R rh = st.rhat[I.rl + (size_t)i * I.L + (cc0 + v) % I.L];
+            const R rh = st.rhat[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)];
             d[v].re += rh * q.c[v].re;
             d[v].im += rh * q.c[v].im;
           }
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(WG, 4) void k_spmm_t(Batch b, KrylovState<R> st, in
             const cvec<R, V> shv = ldv<R, V>(st.sh + e);
 #pragma unroll
             for (int v = 0; v < V; ++v)
-              sv.c[v] = cmul(st.d[I.dn + (size_t)i * I.N + min((cc0 + v) / I.L, I.N - 1)], shv.c[v]);
+              sv.c[v] = cmul(st.d[I.dn + (size_t)i * I.N + col_pole(cc0 + v, I.L, I.N, I.rmaj)], shv.c[v]);
           }
 #pragma unroll
           for (int v = 0; v < V; ++v) {
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_p(Batch b, KrylovState<R> st, 
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       any |= f[v] == COL_ACTIVE;
-      pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
       beta[v] = st.beta[cg0 + v];
       omega[v] = st.omega[cg0 + v];
     }
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_s(Batch b, KrylovState<R> st, 
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         any |= f[v] == COL_ACTIVE;
-        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
         alpha[v] = st.alpha[cg0 + v];
       }
       if (any) {
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_x(Batch b, KrylovState<R> st, 
         act[v] = f[v] == COL_ACTIVE;
         half[v] = f[v] == COL_HALF_PENDING;
         any |= act[v] || half[v];
-        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
         alpha[v] = st.alpha[cg0 + v];
         omega[v] = act[v] ? st.omega[cg0 + v] : cx<R>{0, 0};
       }
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_x(Batch b, KrylovState<R> st, 
                 rh[u] = ldv<R, V>(st.rhat_cx + e[u]);
               } else {
 #pragma unroll
-                for (int v = 0; v < V; ++v) rr[u][v] = st.rhat[I.rl + (size_t)ic[u] * I.L + (cc0 + v) % I.L];
+                for (int v = 0; v < V; ++v) rr[u][v] = st.rhat[I.rl + (size_t)ic[u] * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)];
               }
             }
             if (keep_r) r[u] = ldv<R, V>(st.r + e[u]);
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(WG) void k_init(Batch b, KrylovState<R> st, const R
         cvec<R, V> r, x;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const R fv = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L] : R(0);
+          const R fv = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)] : R(0);
           r.c[v] = {fv, 0};
           x.c[v] = {0, 0};
           nn[v] += fv * fv;
@@ -987,7 +987,7 @@ __global__ __launch_bounds__(64) void k_ilu_apply(Batch b, const int* __restrict
   if (!I.ilu) return;
   const int c = cg - I.col0;
   if (c >= I.K) return;
-  const cx<R>* f = static_cast<const cx<R>*>(I.ilu) + (size_t)(c / I.L) * I.nnz;
+  const cx<R>* f = static_cast<const cx<R>*>(I.ilu) + (size_t)col_pole(c, I.L, I.N, I.rmaj) * I.nnz;
   constexpr int W = WAVE * LaneWidth<R>::V;
   const size_t col_base = tile_base(I, c / W, LaneWidth<R>::V) + c % W;
   const cx<R>* src = in + col_base;
@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(WG) void k_bjac_apply(Batch b, const int* __restric
       for (int v = 0; v < V; ++v) {
         if (f[v] != COL_ACTIVE) continue;
         const cx<R>* m = static_cast<const cx<R>*>(I.bjac) +
-                         ((size_t)((cc0 + v) / I.L) * nodes + (size_t)k) * 9;
+                         ((size_t)col_pole(cc0 + v, I.L, I.N, I.rmaj) * nodes + (size_t)k) * 9;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           y[r].c[v] = cadd(cadd(cmul(m[3 * r], x0.c[v]), cmul(m[3 * r + 1], x1.c[v])), cmul(m[3 * r + 2], x2.c[v]));
@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
       cvec<double, V> r;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double f = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L] : 0.0;
+        const double f = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)] : 0.0;
         r.c[v] = Y ? cx<double>{f - q.c[v].re, -q.c[v].im} : cx<double>{f, 0.0};
         if (cl0 + v >= I.K) r.c[v] = {0.0, 0.0};
         nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
@@ -1308,7 +1308,7 @@ __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __r
         cvec<float, V> r, x;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const cx<double> d = R ? R[e + v] : cx<double>{F[I.rl + (size_t)i * I.L + (cc0 + v) % I.L], 0.0};
+          const cx<double> d = R ? R[e + v] : cx<double>{F[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)], 0.0};
           r.c[v] = {(float)(d.re * inv[v]), (float)(d.im * inv[v])};
           x.c[v] = {0.f, 0.f};
           nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
@@ -1388,7 +1388,7 @@ __device__ __forceinline__ void node_apply(const Inst& I, int k, int cl0, int cc
       for (int i = 0; i < 3; ++i) z[i].c[v] = {0, 0};
       continue;
     }
-    const cx<R>* m = static_cast<const cx<R>*>(I.bjac) + ((size_t)((cc0 + v) / I.L) * nodes + (size_t)k) * 9;
+    const cx<R>* m = static_cast<const cx<R>*>(I.bjac) + ((size_t)col_pole(cc0 + v, I.L, I.N, I.rmaj) * nodes + (size_t)k) * 9;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       z[i].c[v] = cadd(cadd(cmul(m[3 * i], r[0].c[v]), cmul(m[3 * i + 1], r[1].c[v])), cmul(m[3 * i + 2], r[2].c[v]));
@@ -1423,7 +1423,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_start(Batch b, KrylovState<R> st
     } else if (valid) {
       int pole[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      for (int v = 0; v < V; ++v) pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
       FOR_ROWS(b, p, I)
         const size_t e = tb + (size_t)pos * (WAVE * V);
         const size_t de = I.dn + (size_t)pos * I.N;
@@ -1536,7 +1536,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
       cx<R> alpha[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        pole[v] = min((cc0 + v) / I.L, I.N - 1);
+        pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
         alpha[v] = f[v] == COL_ACTIVE ? st.alpha[cg0 + v] : cx<R>{0, 0};
       }
       if (I.bjac) {  // node block Jacobi: one node per wavefront step
@@ -1659,7 +1659,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R>
     cx<R> beta[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      pole[v] = min((cc0 + v) / I.L, I.N - 1);
+      pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
       beta[v] = st.beta[cg0 + v];
     }
     if (I.bjac) {  // node block Jacobi: one node per wavefront step

@@ -504,6 +504,7 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
     return fail(env, SLRF_E_INVALID_ARG, "unknown precision");
   if (env.opt.precond < 0 || env.opt.precond > 3) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
   if (env.opt.solver != 0 && env.opt.solver != 1) return fail(env, SLRF_E_INVALID_ARG, "unknown inner solver");
+  if (env.opt.recycle != 0 && env.opt.recycle != 1) return fail(env, SLRF_E_INVALID_ARG, "recycle must be 0 or 1");
   if (env.opt.solver == 1) {
     // COCG needs a complex-symmetric preconditioner: point or node block Jacobi
     if (env.opt.precond == 2)
@@ -571,6 +572,11 @@ struct FilterJob {
   double* U;             // device (n, L)
   double target;         // relative accuracy of the shifted solves
   slrf_filter_stats stats;
+  // warm start (mixed precision): scratch for C = X_prev^T B X_new
+  double* gpart = nullptr;  // gram_chunks(n, L) * 2 * L * L
+  double* C = nullptr;      // L * L
+  double* Cb = nullptr;     // L * L
+  int nch = 0;
 };
 
 struct JobShape {
@@ -786,6 +792,10 @@ hipError_t put_async(hipStream_t s, std::vector<std::vector<char>>& keep, void* 
 // left in `insts`), the tile and column owners, per-column and per-pole shifts,
 // weights and the ILU(0) factors.  The host arrays are parked in `keep`, which
 // the caller holds until the stream has passed the copies.
+// Column order (col_pole): right-hand-side-major with warm starts (mixed
+// precision, options.recycle), pole-major otherwise.
+int column_order(const Env& env) { return env.opt.precision == SLRF_MIXED && env.opt.recycle ? 1 : 0; }
+
 template <typename R>
 slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
                           std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
@@ -833,15 +843,16 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     for (int t = 0; t < tiles; ++t) tile_inst.push_back((int)q);
     for (int c = 0; c < I.Kp; ++c) col_inst.push_back((int)q);
     for (int p = 0; p < j.N; ++p) {
-      const cx<R> sg = {(R)j.sigma[2 * p], (R)j.sigma[2 * p + 1]};
-      sigj.push_back(sg);
+      sigj.push_back({(R)j.sigma[2 * p], (R)j.sigma[2 * p + 1]});
       w.push_back(j.weight[2 * p]);
       w.push_back(j.weight[2 * p + 1]);
-      for (int l = 0; l < j.L; ++l) {
-        sigc.push_back(sg);
-        sigc64.push_back(j.sigma[2 * p]);
-        sigc64.push_back(j.sigma[2 * p + 1]);
-      }
+    }
+    I.rmaj = column_order(env);
+    for (int c = 0; c < I.K; ++c) {  // pole of column c in the pencil's column order
+      const int p = col_pole(c, j.L, j.N, I.rmaj);
+      sigc.push_back({(R)j.sigma[2 * p], (R)j.sigma[2 * p + 1]});
+      sigc64.push_back(j.sigma[2 * p]);
+      sigc64.push_back(j.sigma[2 * p + 1]);
     }
     for (int c = I.K; c < I.Kp; ++c) {  // padding columns take the last pole (never active)
       sigc.push_back(sigc.back());
@@ -1154,7 +1165,8 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   if (rs != SLRF_OK) return rs;
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
-    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(false), st.x + blk, lo.w + 2 * wj, j.U, false);
+    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(false), column_order(env), st.x + blk,
+                              lo.w + 2 * wj, j.U, false);
     blk += j.P->n * padded_k(j.N * j.L, false);
     wj += j.N;
   }
@@ -1172,7 +1184,11 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
 //   ||R|| <= target ||F||; solve S D = R / ||R|| in FP32 by BiCGStab to relative
 //   residual clamp(0.1 target ||F|| / ||R||, 1e-6, 1e-1); Y += ||R|| D };
 //   U = sum_j 2 Re(w_j Y_j).
-slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
+// warm_region >= 0: the arena holds the previous application of the same jobs
+// (same layout): B X_prev in F and Y_prev in region warm_region (0: Y, 1: R).
+// *final_region: the region that holds this application's Y.
+slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region,
+                               int* final_region) {
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
@@ -1195,6 +1211,26 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
   st.tolc = lo.tol32;
+  const bool warm = warm_region >= 0;
+  *final_region = 0;
+  if (warm) {
+    // Y0 = Y_prev C, C = X_prev^T B X_new = F_prev^T X_new, before F is overwritten
+    cx<double>* Yp = warm_region ? lo.R : lo.Y;
+    cx<double>* Y0 = warm_region ? lo.Y : lo.R;
+    int64_t blk = 0, rl0 = 0;
+    for (auto& j : jobs) {
+      const int n = (int)j.P->n;
+      launch_gram(s, n, j.L, lo.F + rl0, j.X, j.X, j.gpart, j.nch, j.C, j.Cb);
+      launch_recycle(s, n, j.L, j.N, tile_width(true), (int)padded_k(j.N * j.L, true), column_order(env), Yp + blk,
+                     j.C, Y0 + blk);
+      blk += j.P->n * padded_k(j.N * j.L, true);
+      rl0 += j.P->n * j.L;
+    }
+    HIPCHK(env, hipGetLastError());
+    lo.Y = Y0;
+    lo.R = Yp;
+    *final_region = warm_region ? 0 : 1;
+  }
   int64_t dn = 0, rl = 0, pj = 0;
   for (auto& j : jobs) {
     launch_jacobi_diag<float>(s, (int)j.P->n, j.N, j.P->diagA32, j.P->diagB32, (const cx<float>*)lo.sig_j + pj,
@@ -1210,7 +1246,15 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   for (auto& j : jobs) j.stats = slrf_filter_stats{};
   std::vector<double> sum_it(jobs.size(), 0.0), it_round;
   int rounds = 0;
-  for (int round = 0; round <= kMaxRounds; ++round) {
+  if (warm) {
+    // ||F|| of every column (the targets are relative to it); the rounds then
+    // start from the defect of the warm start
+    launch_defect(s, b, lo.sigma_col64, lo.F, nullptr, lo.R, lo.part64, lo.scale);
+    launch_defect_norms(s, b, lo.part64, lo.tol64, 1, lo.fnorm64, lo.scale, lo.relres, lo.tol32, kInnerTol32,
+                        lo.count);
+  }
+  const int round0 = warm ? 1 : 0;
+  for (int round = round0; round <= kMaxRounds; ++round) {
     launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64, lo.scale);
     launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.tol32,
                         kInnerTol32, lo.count);
@@ -1224,7 +1268,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     ++rounds;
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
     krylov_start<float>(env, b, st);
-    if (round == 0 && env.opt.tune) {
+    if (round == round0 && env.opt.tune) {
       slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.precs(), by, [&]() {
         launch_mixed_rhs(s, b, nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
         krylov_start<float>(env, b, st);
@@ -1240,8 +1284,8 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   }
   int64_t blk = 0, wj = 0;
   for (auto& j : jobs) {
-    if (rounds > 0)
-      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(true), lo.Y + blk,
+    if (rounds > 0 || warm)
+      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(true), column_order(env), lo.Y + blk,
                                 lo.w + 2 * wj, j.U, false);
     else
       HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
@@ -1262,9 +1306,14 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   return SLRF_OK;
 }
 
-slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
+slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region = -1,
+                         int* final_region = nullptr) {
+  int fr = 0;
+  if (!final_region) final_region = &fr;
+  *final_region = 0;
   if (jobs.empty()) return SLRF_OK;
-  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs) : filter_batch_fp64(env, arena, jobs);
+  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs, warm_region, final_region)
+                                         : filter_batch_fp64(env, arena, jobs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1420,7 +1469,15 @@ slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
 // One outer step for every job not yet done: one batched filter application
 // over all of them, then Rayleigh-Ritz and residuals per job.  A failure marks
 // the jobs of the step done with that status.
-slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs) {
+// Warm starts across outer steps (options.recycle, mixed precision): the arena
+// keeps B X and Y of the last filter application; the next one may start from
+// them when it serves the same jobs in the same order (same arena layout).
+struct RecycleState {
+  std::vector<SolveJob*> last;
+  int y_region = 0;
+};
+
+slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs, RecycleState* rs) {
   std::vector<FilterJob> fj;
   std::vector<SolveJob*> act;
   for (SolveJob* J : jobs) {
@@ -1436,11 +1493,18 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
       if (J->prev_prev < INFINITY && J->prev_maxr > 0.3 * J->prev_prev) J->mix_c = std::max(1e-9, J->mix_c * 1e-2);
       target = std::max(1e-13, std::min(1e-4, J->mix_c * J->prev_maxr));
     }
-    fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}});
+    fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}, J->part, J->GA, J->GB,
+                  J->nch});
     act.push_back(J);
   }
   if (act.empty()) return SLRF_OK;
-  slrf_status st = filter_batch(env, arena, fj);
+  const bool warm = rs && env.opt.recycle && env.opt.precision == SLRF_MIXED && act == rs->last;
+  int region = 0;
+  slrf_status st = filter_batch(env, arena, fj, warm ? rs->y_region : -1, &region);
+  if (rs) {
+    rs->last = st == SLRF_OK ? act : std::vector<SolveJob*>{};
+    rs->y_region = region;
+  }
   for (size_t q = 0; q < act.size() && st == SLRF_OK; ++q) st = finish_outer(env, *act[q], fj[q].stats);
   if (st != SLRF_OK)
     for (SolveJob* J : act)
@@ -1523,6 +1587,7 @@ struct slrf_batch_s {
     std::unique_ptr<SolveJob> J;
   };
   std::map<int, Entry> entries;
+  RecycleState recycle;  // warm starts between steps that serve the same pencils
 
   std::vector<JobShape> active_shapes() const {
     std::vector<JobShape> js;
@@ -1553,6 +1618,7 @@ void slrf_default_options(slrf_options* o) {
   o->band_rows = 0;
   o->tune = 0;
   o->solver = 0;
+  o->recycle = 0;
 }
 
 const char* slrf_status_string(slrf_status s) {
@@ -1697,8 +1763,9 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slr
   slrf_status st = prepare_job(env, J, gamma, poles, d_V0, ctx->max_N);
   if (st != SLRF_OK) return st;
   const std::vector<SolveJob*> jobs{&J};
+  RecycleState rs;
   while (!J.done) {
-    st = outer_step(env, Carver{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes}, jobs);
+    st = outer_step(env, Carver{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes}, jobs, &rs);
     if (st != SLRF_OK) return st;
   }
   st = copy_results(env, J, n_found, h_evals, d_evecs, h_resid, stats);
@@ -1800,7 +1867,7 @@ slrf_status slrf_batch_step(slrf_batch b, int32_t* n_active) {
   std::vector<SolveJob*> jobs;
   for (auto& kv : b->entries)
     if (!kv.second.J->done) jobs.push_back(kv.second.J.get());
-  const slrf_status st = outer_step(b->env, Carver{b->arena, 0, b->arena_bytes}, jobs);
+  const slrf_status st = outer_step(b->env, Carver{b->arena, 0, b->arena_bytes}, jobs, &b->recycle);
   int act = 0;
   for (auto& kv : b->entries)
     if (!kv.second.J->done) ++act;
@@ -1840,6 +1907,7 @@ slrf_status slrf_batch_remove(slrf_batch b, int32_t id) {
   b->pool.release(P.mem, P.mem_bytes);
   b->pool.release(J.mem, outer_bytes(P.n, J.L));
   b->entries.erase(it);
+  b->recycle.last.clear();  // a new job may reuse this one's address
   return SLRF_OK;
 }
 

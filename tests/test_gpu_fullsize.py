@@ -85,12 +85,14 @@ def test_c2_full_bicgstab_sampled_columns(slrf, torch, c2):
     assert err < 1e-11
 
 
-@pytest.mark.parametrize("prec", [1, 0])
-def test_c2_full_solve_properties(slrf, torch, c2, prec):
+@pytest.mark.parametrize("prec,solver,recycle", [(1, 0, 0), (0, 0, 0), (1, 1, 1)])
+def test_c2_full_solve_properties(slrf, torch, c2, prec, solver, recycle):
+    """(1, 1, 1) is the benchmark's configuration: mixed precision, COCG, warm starts."""
     p = c2
     sig, w = golden_poles(N, GAMMA)
-    say(f"case full-size interval solve prec={prec} n={p.n} L={L} N={N}")
-    s = slrf.Solver(p.A, p.B, max_L=L, max_poles=N, options=slrf.default_options(precision=prec))
+    say(f"case full-size interval solve prec={prec} solver={solver} recycle={recycle} n={p.n} L={L} N={N}")
+    s = slrf.Solver(p.A, p.B, max_L=L, max_poles=N,
+                    options=slrf.default_options(precision=prec, solver=solver, recycle=recycle))
     r = s.solve_interval(GAMMA, L, sig, w, V0=torch.from_numpy(pencils.start_block(p.n, L, 1)).cuda())
     s.close()
     nf = r.n_found

@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_default_options(lib):
     o = lib.default_options()
     assert o.precision == lib.FP64 and o.inner_maxit == 1000 and o.outer_tol == 1e-8
-    assert o.solver == lib.SOLVER_BICGSTAB
+    assert o.solver == lib.SOLVER_BICGSTAB and o.recycle == 0
 
 
 @pytest.mark.parametrize("rule", [0, 1, 2])
