@@ -715,8 +715,11 @@ def main():
     if wl["recycle"] and main_form == "mixed":
         prec += ", warm starts across outer iterations"
     kdtype = "float" if main_form == "mixed" else "double"
-    traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
-                                        "cocg" if wl["solver"] == 1 else "bicgstab")
+    if args.workload == "c2":
+        traffic, traffic_note = hbm_traffic(kdtype, ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
+                                            "cocg" if wl["solver"] == 1 else "bicgstab")
+    else:
+        traffic, traffic_note = None, "counters are taken on the 64^3 scalar workload only"
     kname = "k_cocg_spmm" if wl["solver"] == 1 else "k_spmm_v / k_spmm_t"
     out = {
         "metric": METRIC, "value": m["value"], "unit": "eigenpairs/s", "n_gpus": 1,
