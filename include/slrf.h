@@ -67,7 +67,7 @@ typedef struct {
                           complex FP32 inner solves with FP64 defect correction */
   double inner_tol;    /* relative residual ||f - S y|| / ||f|| of each shifted solve
                           (paper Section 4.2: 1e-13) */
-  int32_t inner_maxit; /* BiCGStab iteration limit per solve (paper: 1000) */
+  int32_t inner_maxit; /* inner-solver iteration limit per solve (paper: 1000) */
   double outer_tol;    /* tau of the residual test (paper Section 4.2: 1e-8) */
   int32_t outer_maxit; /* outer (subspace) iteration limit */
   int32_t check_every; /* inner iterations between host polls of the convergence count */
@@ -82,7 +82,7 @@ typedef struct {
   int32_t profile;     /* 1: time the sparse-product and vector-update kernels with HIP
                           events and count the column tiles each launch processes
                           (stats fields spmm_* and update_*); 0: off */
-  int32_t graph;       /* 1: capture check_every BiCGStab iterations (and the poll of the
+  int32_t graph;       /* 1: capture check_every inner iterations (and the poll of the
                           active count) once per Krylov run as a hipGraph and replay it;
                           needs a non-NULL stream and profile = 0, else ignored.  0: off */
   /* Work decomposition of the Krylov kernels (0 = default).  They change the
@@ -93,7 +93,7 @@ typedef struct {
                           1024; -1 = natural row order); applied when a pencil is built */
   int32_t tune;        /* 1: autotune (tile_rows, tile_wgs) per batch shape: the first
                           filter application of a shape not seen before in the process
-                          times two BiCGStab iterations per candidate and keeps the
+                          times two inner iterations per candidate and keeps the
                           fastest (cached per process); overrides tile_rows/tile_wgs */
   int32_t solver;      /* inner solver of the shifted systems: 0 BiCGStab (Section 2,
                           the paper's choice), 1 COCG, conjugate gradients with the
@@ -112,8 +112,8 @@ typedef struct {
 } slrf_options;
 
 typedef struct {
-  int32_t max_iterations;   /* largest BiCGStab iteration count over the columns */
-  double mean_iterations;   /* mean BiCGStab iterations per (pole, column) */
+  int32_t max_iterations;   /* largest inner-solver iteration count over the columns */
+  double mean_iterations;   /* mean inner-solver iterations per (pole, column) */
   int64_t spmv;             /* single-vector products with A - sigma_j B (2 per full
                                iteration, 1 when a solve stops at the half step) */
   int32_t n_breakdown;      /* columns stopped by a zero denominator */
@@ -140,7 +140,7 @@ typedef struct {
   double max_resid;         /* largest rho_i over those pairs */
   double seconds;           /* wall time of the call */
   double filter_seconds;    /* of which in filter application */
-  double inner_iterations;  /* mean BiCGStab iterations per (pole, column), all outer its */
+  double inner_iterations;  /* mean inner-solver iterations per (pole, column), all outer its */
   slrf_filter_stats kernels;/* profile = 1: spmm_* / update_* summed over the call */
 } slrf_solve_stats;
 
@@ -225,14 +225,18 @@ const char* slrf_last_error(slrf_ctx ctx);
 /* ---- Batches: many pencils, one launch per Krylov step ---------------------
  *
  * A batch runs Algorithm 1 on a changing set of pencils at once.  Each outer
- * step applies the filter to every unfinished pencil in ONE batched BiCGStab
+ * step applies the filter to every unfinished pencil in ONE batched Krylov solve
  * (each kernel launch covers every pole x column of every pencil; the per-
  * pencil sizes, offsets and CSR pointers sit in a device table), then does
  * Rayleigh-Ritz, residuals and the stopping test per pencil.  The arithmetic of
  * each pencil is that of slrf_solve_interval with the same options, poles and
  * start block (the per-column reductions are summed in a fixed order that does
- * not depend on the other pencils, so a pencil's result is bitwise the same
- * alone or in a batch when the Krylov grid is the same).
+ * not depend on the other pencils or the grid size, so a pencil's result is
+ * bitwise the same alone or in a batch).  With recycle = 1 every pencil keeps
+ * its place in the arena while others finish or leave, and warm-starts from
+ * its previous step as it would alone; a step in which a new pencil joins
+ * starts every pencil cold, so a pencil that shares steps with later arrivals
+ * agrees with its solve alone to the tolerance only.
  *
  * Workspace (device, 256-byte aligned, caller-owned): a filter arena of
  * arena_bytes shared by the pencils of one step, and a pool for each pencil's

@@ -577,7 +577,11 @@ struct FilterJob {
   double* C = nullptr;      // L * L
   double* Cb = nullptr;     // L * L
   int nch = 0;
+  // element offsets of the job's (n, Kp) blocks and (n, L) real blocks in the
+  // layout (-1: after the previous job, see place_jobs)
+  int64_t blk = -1, rl = -1;
 };
+
 
 struct JobShape {
   int64_t n, nnz;
@@ -642,10 +646,26 @@ int64_t padded_k(int64_t K, bool mixed) {
   return (K + W - 1) / W * W;
 }
 
-void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo) {
-  lo = FilterLayout{};
-  int64_t sumN = 0;
-  bool any_general = false;
+// Give every job without explicit offsets the next free ones (jobs one after
+// the other in the layout).
+void place_jobs(std::vector<FilterJob>& jobs, bool mixed) {
+  int64_t blk = 0, rl = 0;
+  for (auto& j : jobs) {
+    if (j.blk < 0) j.blk = blk;
+    if (j.rl < 0) j.rl = rl;
+    blk = j.blk + j.P->n * padded_k((int64_t)j.N * j.L, mixed);
+    rl = j.rl + j.P->n * j.L;
+  }
+}
+
+// Sizes of a set of jobs: the block, real-block and diagonal-block elements,
+// padded columns and tiles, and which preconditioner tables the set needs.
+void shape_totals(const std::vector<JobShape>& js, bool mixed, FilterLayout& lo, int64_t& sumN,
+                  bool& any_general) {
+  lo.EB = lo.ER = lo.ED = lo.Ktot = lo.n_tiles = lo.ilu_vals = lo.bjac_vals = 0;
+  lo.any_ilu = lo.any_bjac = false;
+  sumN = 0;
+  any_general = false;
   const int V = lane_width(mixed);
   for (const auto& j : js) {
     const int64_t Kp = padded_k((int64_t)j.N * j.L, mixed);
@@ -665,6 +685,18 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
     }
     if (j.general) any_general = true;
   }
+}
+
+// span (optional): carve for this wider set of jobs, the previous step's, so
+// that every region starts where it did then and the jobs of js keep the
+// block offsets they had (warm starts read the previous blocks in place); the
+// totals of the layout are those of js.
+void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo,
+                  const std::vector<JobShape>* span = nullptr) {
+  lo = FilterLayout{};
+  int64_t sumN = 0;
+  bool any_general = false;
+  shape_totals(span ? *span : js, mixed, lo, sumN, any_general);
   const size_t cs = mixed ? 8 : 16;  // complex size in the Krylov precision
   const size_t rs = cs / 2;
   // with any ILU(0) or block-Jacobi pencil in the batch, every pencil keeps p and s
@@ -700,11 +732,12 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   lo.count = cv.take<int>(64);
   lo.active = cv.take<int>(lo.n_tiles);
   lo.n_active = cv.take<int>(64);
-  lo.inst = cv.take<Inst>(js.size());
+  lo.inst = cv.take<Inst>((span ? *span : js).size());
   lo.tile_inst = cv.take<int>(lo.n_tiles);
   lo.col_inst = cv.take<int>(lo.Ktot);
   if (lo.any_ilu) lo.ilu = cv.take<char>((size_t)lo.ilu_vals * cs);
   if (lo.any_bjac) lo.bjac = cv.take<char>((size_t)lo.bjac_vals * cs);
+  if (span) shape_totals(js, mixed, lo, sumN, any_general);  // js is a subset of the span
 }
 
 size_t filter_arena_bytes(const std::vector<JobShape>& js, bool mixed) {
@@ -813,7 +846,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all;
   std::vector<double> sigc64, w;
-  int64_t blk = 0, rl = 0, dn = 0, ilu_off = 0, bjac_off = 0;
+  int64_t dn = 0, ilu_off = 0, bjac_off = 0;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
     const FilterJob& j = jobs[q];
@@ -826,8 +859,8 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.col0 = col0;
     I.tile0 = tile0;
     I.nnz = (int)j.P->nnz;
-    I.blk = blk;
-    I.rl = rl;
+    I.blk = j.blk;
+    I.rl = j.rl;
     I.dn = dn;
     I.rowptr = j.P->rowptr;
     I.col = j.P->col;
@@ -879,8 +912,6 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
       I.bjac = (const char*)lo.bjac + bjac_off * sizeof(cx<R>);
       bjac_off += (int64_t)j.N * (j.P->n / 3) * 9;
     }
-    blk += (int64_t)I.n * I.Kp;
-    rl += (int64_t)I.n * I.L;
     dn += (int64_t)I.n * I.N;
     col0 += I.Kp;
     tile0 += tiles;
@@ -1133,6 +1164,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
   FilterLayout lo;
   carve_filter(arena, js, false, lo);
+  place_jobs(jobs, false);
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
   Batch b{};
   std::vector<std::vector<char>> keep;
@@ -1140,13 +1172,12 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   slrf_status st0 = upload_tables<double>(env, jobs, lo, b, insts, keep);
   if (st0 != SLRF_OK) return st0;
   KrylovState<double> st = make_state<double>(lo);
-  int64_t dn = 0, rl = 0, pj = 0;
+  int64_t dn = 0, pj = 0;
   for (auto& j : jobs) {
     launch_jacobi_diag<double>(s, (int)j.P->n, j.N, j.P->diagA, j.P->diagB, (const cx<double>*)lo.sig_j + pj,
                                (cx<double>*)lo.d + dn, (cx<double>*)lo.dinv + dn);
-    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.rhat + rl);
+    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.rhat + j.rl);
     dn += j.P->n * j.N;
-    rl += j.P->n * j.L;
     pj += j.N;
   }
   launch_init<double>(s, b, st, lo.rhat);
@@ -1163,11 +1194,10 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   }
   slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.precs(), by, lo.count, &ks);
   if (rs != SLRF_OK) return rs;
-  int64_t blk = 0, wj = 0;
+  int64_t wj = 0;
   for (auto& j : jobs) {
-    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(false), column_order(env), st.x + blk,
+    launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(false), column_order(env), st.x + j.blk,
                               lo.w + 2 * wj, j.U, false);
-    blk += j.P->n * padded_k(j.N * j.L, false);
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1188,13 +1218,14 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
 // (same layout): B X_prev in F and Y_prev in region warm_region (0: Y, 1: R).
 // *final_region: the region that holds this application's Y.
 slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region,
-                               int* final_region) {
+                               int* final_region, const std::vector<JobShape>* span) {
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
   for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
   FilterLayout lo;
-  carve_filter(arena, js, true, lo);
+  carve_filter(arena, js, true, lo, span);
+  place_jobs(jobs, true);
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
   Batch b{};
   std::vector<std::vector<char>> keep;
@@ -1217,27 +1248,23 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     // Y0 = Y_prev C, C = X_prev^T B X_new = F_prev^T X_new, before F is overwritten
     cx<double>* Yp = warm_region ? lo.R : lo.Y;
     cx<double>* Y0 = warm_region ? lo.Y : lo.R;
-    int64_t blk = 0, rl0 = 0;
     for (auto& j : jobs) {
       const int n = (int)j.P->n;
-      launch_gram(s, n, j.L, lo.F + rl0, j.X, j.X, j.gpart, j.nch, j.C, j.Cb);
-      launch_recycle(s, n, j.L, j.N, tile_width(true), (int)padded_k(j.N * j.L, true), column_order(env), Yp + blk,
-                     j.C, Y0 + blk);
-      blk += j.P->n * padded_k(j.N * j.L, true);
-      rl0 += j.P->n * j.L;
+      launch_gram(s, n, j.L, lo.F + j.rl, j.X, j.X, j.gpart, j.nch, j.C, j.Cb);
+      launch_recycle(s, n, j.L, j.N, tile_width(true), (int)padded_k(j.N * j.L, true), column_order(env),
+                     Yp + j.blk, j.C, Y0 + j.blk);
     }
     HIPCHK(env, hipGetLastError());
     lo.Y = Y0;
     lo.R = Yp;
     *final_region = warm_region ? 0 : 1;
   }
-  int64_t dn = 0, rl = 0, pj = 0;
+  int64_t dn = 0, pj = 0;
   for (auto& j : jobs) {
     launch_jacobi_diag<float>(s, (int)j.P->n, j.N, j.P->diagA32, j.P->diagB32, (const cx<float>*)lo.sig_j + pj,
                               (cx<float>*)lo.d + dn, (cx<float>*)lo.dinv + dn);
-    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.F + rl);
+    launch_spmm_real<double>(s, (int)j.P->n, j.L, j.P->rowptr, j.P->col, j.P->ab64, j.X, nullptr, lo.F + j.rl);
     dn += j.P->n * j.N;
-    rl += j.P->n * j.L;
     pj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1270,7 +1297,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     krylov_start<float>(env, b, st);
     if (round == round0 && env.opt.tune) {
       slrf_status ts = autotune<float>(env, insts, lo, b, st, tol32, lo.precs(), by, [&]() {
-        launch_mixed_rhs(s, b, nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
+        launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
         krylov_start<float>(env, b, st);
       }, keep);
       if (ts != SLRF_OK) return ts;
@@ -1282,14 +1309,13 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     if (cs != SLRF_OK) return cs;
     for (size_t q = 0; q < jobs.size(); ++q) sum_it[q] += it_round[q];
   }
-  int64_t blk = 0, wj = 0;
+  int64_t wj = 0;
   for (auto& j : jobs) {
     if (rounds > 0 || warm)
-      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(true), column_order(env), lo.Y + blk,
+      launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(true), column_order(env), lo.Y + j.blk,
                                 lo.w + 2 * wj, j.U, false);
     else
       HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
-    blk += j.P->n * padded_k(j.N * j.L, true);
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1306,13 +1332,14 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   return SLRF_OK;
 }
 
+// span: see carve_filter (mixed precision only)
 slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region = -1,
-                         int* final_region = nullptr) {
+                         int* final_region = nullptr, const std::vector<JobShape>* span = nullptr) {
   int fr = 0;
   if (!final_region) final_region = &fr;
   *final_region = 0;
   if (jobs.empty()) return SLRF_OK;
-  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs, warm_region, final_region)
+  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs, warm_region, final_region, span)
                                          : filter_batch_fp64(env, arena, jobs);
 }
 
@@ -1472,9 +1499,31 @@ slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
 // Warm starts across outer steps (options.recycle, mixed precision): the arena
 // keeps B X and Y of the last filter application; the next one may start from
 // them when it serves the same jobs in the same order (same arena layout).
+// What a warm start needs of the previous step: its jobs with their block
+// offsets, the set of shapes its layout was carved for, and the region that
+// holds its Y.  A step whose jobs are a subset of the previous step's (pencils
+// only finished) warm-starts every job in place; a step with a new pencil
+// starts every job cold, in a fresh layout.
 struct RecycleState {
   std::vector<SolveJob*> last;
+  std::vector<int64_t> blk, rl;
+  std::vector<JobShape> span;
   int y_region = 0;
+  void clear() {
+    last.clear();
+    blk.clear();
+    rl.clear();
+    span.clear();
+  }
+  void forget(const SolveJob* J) {  // J leaves the batch; the others keep their places
+    for (size_t q = 0; q < last.size(); ++q)
+      if (last[q] == J) {
+        last.erase(last.begin() + q);
+        blk.erase(blk.begin() + q);
+        rl.erase(rl.begin() + q);
+        return;
+      }
+  }
 };
 
 slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs, RecycleState* rs) {
@@ -1498,12 +1547,41 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
     act.push_back(J);
   }
   if (act.empty()) return SLRF_OK;
-  const bool warm = rs && env.opt.recycle && env.opt.precision == SLRF_MIXED && act == rs->last;
+  bool warm = rs && env.opt.recycle && env.opt.precision == SLRF_MIXED && !rs->last.empty();
+  if (warm) {
+    // every job was in the previous step (in the same order): it keeps its offsets
+    size_t q = 0;
+    for (size_t a = 0; a < act.size() && warm; ++a) {
+      while (q < rs->last.size() && rs->last[q] != act[a]) ++q;
+      if (q == rs->last.size() || act[a]->N > kRecycleMaxPoles) {
+        warm = false;
+      } else {
+        fj[a].blk = rs->blk[q];
+        fj[a].rl = rs->rl[q];
+      }
+    }
+    if (!warm)
+      for (auto& f : fj) f.blk = f.rl = -1;
+  }
+  std::vector<JobShape> span;
+  if (warm) {
+    span = rs->span;
+  } else {
+    for (auto& f : fj) span.push_back({f.P->n, f.P->nnz, f.L, f.N, f.P->use_ilu, false, f.P->use_bjac});
+  }
   int region = 0;
-  slrf_status st = filter_batch(env, arena, fj, warm ? rs->y_region : -1, &region);
+  slrf_status st = filter_batch(env, arena, fj, warm ? rs->y_region : -1, &region, &span);
   if (rs) {
-    rs->last = st == SLRF_OK ? act : std::vector<SolveJob*>{};
-    rs->y_region = region;
+    rs->clear();
+    if (st == SLRF_OK && env.opt.precision == SLRF_MIXED) {
+      rs->last = act;
+      for (auto& f : fj) {
+        rs->blk.push_back(f.blk);
+        rs->rl.push_back(f.rl);
+      }
+      rs->span = std::move(span);
+      rs->y_region = region;
+    }
   }
   for (size_t q = 0; q < act.size() && st == SLRF_OK; ++q) st = finish_outer(env, *act[q], fj[q].stats);
   if (st != SLRF_OK)
@@ -1904,10 +1982,10 @@ slrf_status slrf_batch_remove(slrf_batch b, int32_t id) {
   if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
   const Pencil& P = *it->second.P;
   const SolveJob& J = *it->second.J;
+  b->recycle.forget(&J);  // before a new job may reuse its address
   b->pool.release(P.mem, P.mem_bytes);
   b->pool.release(J.mem, outer_bytes(P.n, J.L));
   b->entries.erase(it);
-  b->recycle.last.clear();  // a new job may reuse this one's address
   return SLRF_OK;
 }
 

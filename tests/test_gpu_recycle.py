@@ -82,3 +82,71 @@ def test_recycle_batch_matches_dense(slrf, torch):
         assert r.status == 0 and nf == k == inertia.sparse_ldl_count(p.A, p.B, g)
         assert rel < 1e-8 and r.resid[:nf].max() <= 1e-8
     b.close()
+
+
+def test_recycle_batch_bitwise_equals_alone(slrf, torch):
+    """Warm starts in a batch whose pencils finish at different steps and are
+    removed as they finish: the others keep their places and warm-start as they
+    would alone, so every result is bitwise the solve alone and takes the same
+    number of sparse products (fixed tiling: the autotuner may pick another
+    row-block size for the batch than for a pencil alone, which rounds
+    differently)."""
+    from test_gpu_batch import big_cases, ws_for
+    cases = big_cases()
+    opt = slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG, recycle=1)
+    alone = []
+    for i, (p, gamma, L, k) in enumerate(cases):
+        say(f"case recycle alone pencil {i} n={p.n} L={L} nev={k}")
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=4, options=opt)
+        r = s.solve_interval(gamma, L, V0=torch.from_numpy(pencils.start_block(p.n, L, 40 + i)).cuda())
+        assert r.status == 0 and r.n_found == k
+        alone.append(r)
+        s.close()
+    ws, arena = ws_for(slrf, cases, slrf.MIXED)
+    say(f"case recycle batch: {len(cases)} pencils")
+    b = slrf.Batch(ws, arena, max_poles=4, options=opt)
+    ids = [b.add(p.A, p.B, gamma, L, V0=pencils.start_block(p.n, L, 40 + i))
+           for i, (p, gamma, L, _) in enumerate(cases)]
+    out, steps = {}, 0
+    while len(out) < len(ids):
+        b.step()
+        steps += 1
+        assert steps < 60
+        for i, pid in enumerate(ids):
+            if i not in out and b.query(pid)[0]:
+                out[i] = b.result(pid)
+                b.remove(pid)
+    assert len({out[i].stats["outer_iterations"] for i in out}) > 1   # pencils left at different steps
+    for i, a in enumerate(alone):
+        r = out[i]
+        say(f"  pencil {i}: found {r.n_found} outer {r.stats['outer_iterations']} "
+            f"(alone {a.stats['outer_iterations']}), spmv {r.stats['spmv_total']} (alone {a.stats['spmv_total']})")
+        assert r.status == 0 and r.n_found == a.n_found
+        assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
+        assert r.stats["spmv_total"] == a.stats["spmv_total"]
+        assert np.array_equal(r.evals, a.evals)
+        assert np.array_equal(r.resid, a.resid)
+        assert torch.equal(r.evecs, a.evecs)
+    b.close()
+
+
+def test_recycle_autotune_same_work(slrf, torch):
+    """With warm starts, the tile autotuner must leave the first correction
+    round solving for the warm start's defect: the autotuned solve takes about
+    the sparse products of the default tiling (the tilings round differently,
+    so the counts need not match exactly) and finds the same eigenvalues."""
+    from test_gpu_batch import big_cases
+    p, gamma, L, k = big_cases()[0]
+    V0 = torch.from_numpy(pencils.start_block(p.n, L, 40)).cuda()
+    out = {}
+    for tune in (0, 1):
+        opt = slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG, recycle=1, tune=tune)
+        s = slrf.Solver(p.A, p.B, max_L=L, max_poles=4, options=opt)
+        r = s.solve_interval(gamma, L, V0=V0)
+        s.close()
+        say(f"case recycle tune={tune}: found {r.n_found}, outer {r.stats['outer_iterations']}, "
+            f"spmv {r.stats['spmv_total']}")
+        assert r.status == 0 and r.n_found == k
+        out[tune] = r
+    assert abs(out[1].stats["spmv_total"] / out[0].stats["spmv_total"] - 1) < 0.15
+    assert np.abs(out[1].evals[:k] / out[0].evals[:k] - 1).max() < 1e-9
