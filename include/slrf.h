@@ -118,7 +118,8 @@ typedef struct {
                                iteration, 1 when a solve stops at the half step) */
   int32_t n_breakdown;      /* columns stopped by a zero denominator */
   int32_t n_maxit;          /* columns that hit inner_maxit */
-  int32_t refinements;      /* MIXED: defect-correction rounds used */
+  int32_t refinements;      /* MIXED: defect-correction rounds in which this pencil had an
+                               open column */
   double max_relres;        /* largest final relative residual over the columns */
   double seconds;           /* wall time of the call */
   /* profile = 1 only (else 0): kernel time from HIP events, launches, and the

@@ -1138,12 +1138,14 @@ slrf_status collect_stats(Env& env, std::vector<FilterJob>& jobs, const KrylovSt
   return SLRF_OK;
 }
 
+// job_rounds (mixed precision): the correction rounds in which each job had
+// an open column
 void finish_stats(std::vector<FilterJob>& jobs, const std::vector<double>& sum_it, const slrf_filter_stats& ks,
-                  double seconds, int rounds) {
+                  double seconds, const std::vector<int>* job_rounds) {
   for (size_t q = 0; q < jobs.size(); ++q) {
     slrf_filter_stats& fs = jobs[q].stats;
     fs.mean_iterations = sum_it[q] / std::max(1, jobs[q].N * jobs[q].L);
-    fs.refinements = rounds;
+    fs.refinements = job_rounds ? (*job_rounds)[q] : 0;
     fs.seconds = seconds;
     fs.spmm_seconds = ks.spmm_seconds;
     fs.spmm_launches = ks.spmm_launches;
@@ -1205,7 +1207,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   std::vector<double> sum_it;
   slrf_status cs = collect_stats<double>(env, jobs, st, lo.Ktot, true, sum_it);
   if (cs != SLRF_OK) return cs;
-  finish_stats(jobs, sum_it, ks, now_s() - t0, 0);
+  finish_stats(jobs, sum_it, ks, now_s() - t0, nullptr);
   return SLRF_OK;
 }
 
@@ -1281,6 +1283,11 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
                         lo.count);
   }
   const int round0 = warm ? 1 : 0;
+  // per job: an open column entering the round (the defect then computes its
+  // product with S; the counts match the job's solve alone)
+  std::vector<char> job_open(jobs.size(), 1);
+  std::vector<int> job_rounds(jobs.size(), 0);
+  std::vector<double> scale_h(lo.Ktot);
   for (int round = round0; round <= kMaxRounds; ++round) {
     launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64, lo.scale);
     launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.tol32,
@@ -1288,11 +1295,20 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     HIPCHK(env, hipGetLastError());
     int open = 0;
     HIPCHK(env, hipMemcpyAsync(&open, lo.count, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(env, hipMemcpyAsync(scale_h.data(), lo.scale, 8 * (size_t)lo.Ktot, hipMemcpyDeviceToHost, s));
     HIPCHK(env, hipStreamSynchronize(s));
-    if (round > 0)
-      for (auto& j : jobs) j.stats.spmv += (int64_t)j.N * j.L;  // the defect's product with S
+    int64_t c0 = 0;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      const int K = jobs[q].N * jobs[q].L;
+      if (round > 0 && job_open[q]) jobs[q].stats.spmv += K;  // the defect's product with S
+      bool any = false;
+      for (int k = 0; k < K && !any; ++k) any = scale_h[c0 + k] > 0;
+      job_open[q] = any;
+      c0 += padded_k(K, true);
+    }
     if (open == 0 || round == kMaxRounds) break;
     ++rounds;
+    for (size_t q = 0; q < jobs.size(); ++q) job_rounds[q] += job_open[q];
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
     krylov_start<float>(env, b, st);
     if (round == round0 && env.opt.tune) {
@@ -1328,7 +1344,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     for (int k = 0; k < padded_k(K, true); ++k, ++c)
       if (k < K) jobs[q].stats.max_relres = std::max(jobs[q].stats.max_relres, rr[c]);
   }
-  finish_stats(jobs, sum_it, ks, now_s() - t0, rounds);
+  finish_stats(jobs, sum_it, ks, now_s() - t0, &job_rounds);
   return SLRF_OK;
 }
 
@@ -1368,7 +1384,7 @@ struct SolveJob {
          *GB = nullptr, *Zd = nullptr, *th = nullptr, *rpart = nullptr;
   int nch = 0, nrr = 0;
   int k = 0, prev_count = -1, count = 0;
-  double prev_maxr = INFINITY, prev_prev = INFINITY, mix_c = 1e-3, iter_sum = 0, t0 = 0;
+  double prev_maxr = INFINITY, prev_prev = INFINITY, mix_c = 3e-3, iter_sum = 0, t0 = 0;
   bool done = false;
   slrf_status status = SLRF_OK;
   std::string msg;
@@ -1535,12 +1551,12 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
     double target = env.opt.inner_tol;
     if (env.opt.precision == SLRF_MIXED) {
       // Inner accuracy follows the outer residual: target = c * (largest
-      // residual of the previous outer iteration), within [1e-13, 1e-4].  The
-      // residual of a Ritz pair amplifies the inner error by up to about
-      // lambda_max / theta, so when an outer iteration fails to cut the
-      // residual 3x, c shrinks 100x.
+      // residual of the previous outer iteration), within [1e-13, 1e-3]
+      // (c = 3e-3 at first).  The residual of a Ritz pair amplifies the inner
+      // error by up to about lambda_max / theta, so when an outer iteration
+      // fails to cut the residual 3x, c shrinks 100x.
       if (J->prev_prev < INFINITY && J->prev_maxr > 0.3 * J->prev_prev) J->mix_c = std::max(1e-9, J->mix_c * 1e-2);
-      target = std::max(1e-13, std::min(1e-4, J->mix_c * J->prev_maxr));
+      target = std::max(1e-13, std::min(1e-3, J->mix_c * J->prev_maxr));
     }
     fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}, J->part, J->GA, J->GB,
                   J->nch});
