@@ -193,9 +193,7 @@ void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, cons
                        const double* w /* 2N */, double* U, bool accumulate);
 
 // Y0 = Y_prev C per pole (C real L x L row-major), tile-major complex FP64
-// blocks with tiles of W columns and Kp padded columns (padding set to zero);
-// N <= kRecycleMaxPoles
-constexpr int kRecycleMaxPoles = 16;
+// blocks with tiles of W columns and Kp padded columns (padding set to zero)
 void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
                     const double* C, cx<double>* Y0);
 

@@ -56,42 +56,30 @@ void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, cons
 // C = X_prev^T B X_new (row-major, C[l * L + l']).  Y_prev, Y0: tile-major
 // complex FP64 blocks (tiles of W columns) in column order rmaj, K = N L
 // columns padded to Kp; the padding columns of Y0 are zero.  One thread per
-// (row, right-hand side) computes that right-hand side for every pole, so each
-// C entry is loaded once for the N poles (N <= kRecycleMaxPoles).
-constexpr int kMaxPoles = kRecycleMaxPoles;
-
-__global__ __launch_bounds__(256) void k_recycle(int n, int L, int N, int W, int Kp, int rmaj,
-                                                 const cx<double>* __restrict__ Yp, const double* __restrict__ C,
-                                                 cx<double>* __restrict__ Y0) {
+// output element.
+__global__ void k_recycle(int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* __restrict__ Yp,
+                          const double* __restrict__ C, cx<double>* __restrict__ Y0) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * L) return;
-  const int64_t i = e / L;
-  const int lp = (int)(e % L);
-  auto off = [&](int c) { return (int64_t)(c / W) * n * W + i * W + c % W; };
-  cx<double> acc[kMaxPoles];
-#pragma unroll
-  for (int j = 0; j < kMaxPoles; ++j) acc[j] = {0.0, 0.0};
-  for (int l = 0; l < L; ++l) {
-    const double g = C[(int64_t)l * L + lp];
-#pragma unroll
-    for (int j = 0; j < kMaxPoles; ++j) {
-      if (j >= N) break;
-      const cx<double> v = Yp[off(col_of(j, l, L, N, rmaj))];
-      acc[j].re += g * v.re;
-      acc[j].im += g * v.im;
+  if (e >= (int64_t)n * Kp) return;
+  const int64_t i = e / Kp;
+  const int c = (int)(e % Kp);
+  cx<double> y = {0.0, 0.0};
+  if (c < N * L) {
+    const int j = col_pole(c, L, N, rmaj), lp = col_rhs(c, L, N, rmaj);
+    for (int l = 0; l < L; ++l) {
+      const int cs = col_of(j, l, L, N, rmaj);
+      const cx<double> v = Yp[(int64_t)(cs / W) * n * W + i * W + cs % W];
+      const double g = C[(int64_t)l * L + lp];
+      y.re += g * v.re;
+      y.im += g * v.im;
     }
   }
-#pragma unroll
-  for (int j = 0; j < kMaxPoles; ++j) {
-    if (j >= N) break;
-    Y0[off(col_of(j, lp, L, N, rmaj))] = acc[j];
-  }
-  for (int c = N * L + lp; c < Kp; c += L) Y0[off(c)] = {0.0, 0.0};
+  Y0[(int64_t)(c / W) * n * W + i * W + c % W] = y;
 }
 
 void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
                     const double* C, cx<double>* Y0) {
-  const int64_t tot = (int64_t)n * L;
+  const int64_t tot = (int64_t)n * Kp;
   k_recycle<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, Kp, rmaj, Yp, C, Y0);
 }
 

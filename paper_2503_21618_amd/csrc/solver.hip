@@ -1569,7 +1569,7 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
     size_t q = 0;
     for (size_t a = 0; a < act.size() && warm; ++a) {
       while (q < rs->last.size() && rs->last[q] != act[a]) ++q;
-      if (q == rs->last.size() || act[a]->N > kRecycleMaxPoles) {
+      if (q == rs->last.size()) {
         warm = false;
       } else {
         fj[a].blk = rs->blk[q];
