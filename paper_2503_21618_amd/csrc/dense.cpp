@@ -20,10 +20,12 @@
 
 namespace slrf {
 
-static void tridiagonalize(int n, double* A, double* Q, double* d, double* e) {
+// QT holds the transpose of the accumulated orthogonal factor, so that the
+// reflections and rotations update contiguous rows.
+static void tridiagonalize(int n, double* A, double* QT, double* d, double* e) {
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) Q[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
-  std::vector<double> v(n), p(n), w(n);
+    for (int j = 0; j < n; ++j) QT[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+  std::vector<double> v(n), p(n), w(n), sr(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double xn = 0;
@@ -57,21 +59,27 @@ static void tridiagonalize(int n, double* A, double* Q, double* d, double* e) {
     }
     A[(size_t)(k + 1) * n + k] = A[(size_t)k * n + (k + 1)] = alpha;
     for (int i = 1; i < m; ++i) A[(size_t)(k + 1 + i) * n + k] = A[(size_t)k * n + (k + 1 + i)] = 0;
-    // Q <- Q H
-    for (int r = 0; r < n; ++r) {
-      double* qr = Q + (size_t)r * n + (k + 1);
-      double s = 0;
-      for (int i = 0; i < m; ++i) s += qr[i] * v[i];
-      s *= beta;
-      for (int i = 0; i < m; ++i) qr[i] -= s * v[i];
+    // Q <- Q H: with s_r = beta sum_i Q[r][k+1+i] v_i, Q[r][k+1+i] -= s_r v_i
+    std::fill(sr.begin(), sr.end(), 0.0);
+    for (int i = 0; i < m; ++i) {
+      const double* q = QT + (size_t)(k + 1 + i) * n;
+      const double vi = v[i];
+      for (int r = 0; r < n; ++r) sr[r] += q[r] * vi;
+    }
+    for (int r = 0; r < n; ++r) sr[r] *= beta;
+    for (int i = 0; i < m; ++i) {
+      double* q = QT + (size_t)(k + 1 + i) * n;
+      const double vi = v[i];
+      for (int r = 0; r < n; ++r) q[r] -= sr[r] * vi;
     }
   }
   for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
   for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
 }
 
-// Implicit symmetric QR on (d, e), rotations applied to the columns of Q.
-static bool tridiag_qr(int n, double* d, double* e, double* Q) {
+// Implicit symmetric QR on (d, e), rotations applied to the columns of Q (rows
+// of QT).
+static bool tridiag_qr(int n, double* d, double* e, double* QT) {
   const double eps = 2.220446049250313e-16;
   int hi = n - 1;
   long guard = 0;
@@ -109,11 +117,12 @@ static bool tridiag_qr(int n, double* d, double* e, double* Q) {
         e[k + 1] = c * e[k + 1];
       }
       x = e[k];
+      double* qa = QT + (size_t)k * n;
+      double* qb = QT + (size_t)(k + 1) * n;
       for (int i = 0; i < n; ++i) {
-        double* qi = Q + (size_t)i * n;
-        const double a = qi[k], b = qi[k + 1];
-        qi[k] = c * a - s * b;
-        qi[k + 1] = s * a + c * b;
+        const double a = qa[i], b = qb[i];
+        qa[i] = c * a - s * b;
+        qb[i] = s * a + c * b;
       }
     }
   }
@@ -126,15 +135,15 @@ bool sym_eig(int n, double* A, double* w, double* V) {
     V[0] = 1;
     return true;
   }
-  std::vector<double> Q((size_t)n * n), d(n), e(n);
-  tridiagonalize(n, A, Q.data(), d.data(), e.data());
-  if (!tridiag_qr(n, d.data(), e.data(), Q.data())) return false;
+  std::vector<double> QT((size_t)n * n), d(n), e(n);
+  tridiagonalize(n, A, QT.data(), d.data(), e.data());
+  if (!tridiag_qr(n, d.data(), e.data(), QT.data())) return false;
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
   for (int j = 0; j < n; ++j) {
     w[j] = d[idx[j]];
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Q[(size_t)i * n + idx[j]];
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = QT[(size_t)idx[j] * n + i];
   }
   return true;
 }
