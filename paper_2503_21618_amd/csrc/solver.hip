@@ -582,7 +582,6 @@ struct FilterJob {
   int64_t blk = -1, rl = -1;
 };
 
-
 struct JobShape {
   int64_t n, nnz;
   int L, N;
