@@ -56,30 +56,40 @@ void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, cons
 // C = X_prev^T B X_new (row-major, C[l * L + l']).  Y_prev, Y0: tile-major
 // complex FP64 blocks (tiles of W columns) in column order rmaj, K = N L
 // columns padded to Kp; the padding columns of Y0 are zero.  One thread per
-// output element.
+// (row, pole, kRecycleCols consecutive right-hand sides), poles varying fastest
+// across the lanes: each Y_prev value read serves kRecycleCols outputs.
+constexpr int kRecycleCols = 4;
+
 __global__ void k_recycle(int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* __restrict__ Yp,
                           const double* __restrict__ C, cx<double>* __restrict__ Y0) {
+  const int per_row = (L + kRecycleCols - 1) / kRecycleCols * N;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * Kp) return;
-  const int64_t i = e / Kp;
-  const int c = (int)(e % Kp);
-  cx<double> y = {0.0, 0.0};
-  if (c < N * L) {
-    const int j = col_pole(c, L, N, rmaj), lp = col_rhs(c, L, N, rmaj);
-    for (int l = 0; l < L; ++l) {
-      const int cs = col_of(j, l, L, N, rmaj);
-      const cx<double> v = Yp[(int64_t)(cs / W) * n * W + i * W + cs % W];
-      const double g = C[(int64_t)l * L + lp];
-      y.re += g * v.re;
-      y.im += g * v.im;
+  if (e >= (int64_t)n * per_row) return;
+  const int64_t i = e / per_row;
+  const int g = (int)(e % per_row);
+  const int j = g % N, lp0 = g / N * kRecycleCols, cnt = min(kRecycleCols, L - lp0);
+  auto off = [&](int c) { return (int64_t)(c / W) * n * W + i * W + c % W; };
+  cx<double> y[kRecycleCols] = {};
+  for (int l = 0; l < L; ++l) {
+    const cx<double> v = Yp[off(col_of(j, l, L, N, rmaj))];
+    const double* cr = C + (int64_t)l * L + lp0;
+#pragma unroll
+    for (int u = 0; u < kRecycleCols; ++u) {
+      const double gu = u < cnt ? cr[u] : 0.0;
+      y[u].re += gu * v.re;
+      y[u].im += gu * v.im;
     }
   }
-  Y0[(int64_t)(c / W) * n * W + i * W + c % W] = y;
+#pragma unroll
+  for (int u = 0; u < kRecycleCols; ++u)
+    if (u < cnt) Y0[off(col_of(j, lp0 + u, L, N, rmaj))] = y[u];
+  if (g == 0)
+    for (int c = N * L; c < Kp; ++c) Y0[off(c)] = {0.0, 0.0};
 }
 
 void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
                     const double* C, cx<double>* Y0) {
-  const int64_t tot = (int64_t)n * Kp;
+  const int64_t tot = (int64_t)n * ((L + kRecycleCols - 1) / kRecycleCols * N);
   k_recycle<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, Kp, rmaj, Yp, C, Y0);
 }
 
