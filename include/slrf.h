@@ -102,13 +102,13 @@ typedef struct {
                           preconditioners only: precond 0 then selects point
                           Jacobi, 3 node block Jacobi, and 2 (ILU(0)) is rejected
                           with SLRF_E_INVALID_ARG) */
-  int32_t recycle;     /* 1 (mixed precision): each filter application after the first
-                          starts its shifted solves from the previous one's solutions
-                          carried to the new block, Y0 = Y_prev (X_prev^T B X_new)
-                          (exact when X_new lies in span(X_prev)); needs the same
-                          pencils in the same order as the previous application (in
-                          a batch: the same unfinished pencils), else starts cold.
-                          Default 0 (cold starts, x_0 = 0) */
+  int32_t recycle;     /* 1 (mixed precision): each outer iteration after a pencil's
+                          first starts its shifted solves from the previous one's
+                          solutions carried to the new block, Y0 = Y_prev (X_prev^T B
+                          X_new) (exact when X_new lies in span(X_prev)).  Each pencil
+                          keeps Y_prev and B X_prev (n x N L complex and n x L real
+                          FP64) with its own buffers, which the workspace sizes
+                          include.  Default 0 (cold starts, x_0 = 0) */
 } slrf_options;
 
 typedef struct {
@@ -180,7 +180,8 @@ slrf_status slrf_quadrature_poles(int32_t rule, int32_t N, double gamma, double*
 slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
                                  int32_t precision, size_t* bytes);
 
-/* The same for the precision and preconditioner of opt (NULL: defaults). */
+/* The same for the precision, preconditioner and warm starts (recycle) of opt
+ * (NULL: defaults). */
 slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
                                      const slrf_options* opt, size_t* bytes);
 
@@ -233,11 +234,12 @@ const char* slrf_last_error(slrf_ctx ctx);
  * each pencil is that of slrf_solve_interval with the same options, poles and
  * start block (the per-column reductions are summed in a fixed order that does
  * not depend on the other pencils or the grid size, so a pencil's result is
- * bitwise the same alone or in a batch).  With recycle = 1 every pencil keeps
- * its place in the arena while others finish or leave, and warm-starts from
- * its previous step as it would alone; a step in which a new pencil joins
- * starts every pencil cold, so a pencil that shares steps with later arrivals
- * agrees with its solve alone to the tolerance only.
+ * bitwise the same alone or in a batch).  With recycle = 1 every pencil
+ * warm-starts from its own previous step, as it would alone, whichever pencils
+ * join or leave the batch; a pencil whose first step shares a filter
+ * application with warm-started pencils starts from Y = 0 through the warm
+ * path, which rounds differently from a cold start, so it agrees with its
+ * solve alone to the solver's accuracy rather than bitwise.
  *
  * Workspace (device, 256-byte aligned, caller-owned): a filter arena of
  * arena_bytes shared by the pencils of one step, and a pool for each pencil's
@@ -249,7 +251,9 @@ const char* slrf_last_error(slrf_ctx ctx);
 typedef struct slrf_batch_s* slrf_batch;
 
 /* Bytes one pencil needs: persistent_bytes in the pool (kept from add to
- * remove) and transient_bytes of filter arena while it is unfinished. */
+ * remove; in mixed precision with room for the warm-start blocks of
+ * options.recycle) and transient_bytes of filter arena while it is
+ * unfinished. */
 slrf_status slrf_batch_footprint(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
                                  int32_t precision, size_t* persistent_bytes,
                                  size_t* transient_bytes);

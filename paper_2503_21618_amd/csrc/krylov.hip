@@ -444,6 +444,25 @@ __device__ __forceinline__ void spmm_rows(const Batch& b, const WgPos& p, const 
   }
 }
 
+// The rows of spmm_rows in the same order, each with a zero product (the
+// defect of a zero start sums its norms in the order of the product's rows).
+template <typename R, int V, int MODE, typename Emit>
+__device__ __forceinline__ void zero_rows(const Batch& b, const WgPos& p, const Inst& I, Emit&& emit) {
+  const bool quads = MODE == kRowsQuads && I.groups && b.rows_per_block % (4 * kGroupRows) == 0;
+  const bool triples = MODE == kRowsTriples && I.nodes && b.rows_per_block % (4 * kNodeRows) == 0;
+  const int per = quads ? kGroupRows : triples ? kNodeRows : 1;
+  const cvec<R, V> zero{};
+  for (int t = 0; t < I.steps; ++t) {
+    const int rb = step_block(I, p, t);
+    if (rb < 0) break;
+    const int r0 = rb * b.rows_per_block, r1 = min(r0 + b.rows_per_block, I.n);
+    for (int q0 = r0 + per * p.w; q0 < r1; q0 += 4 * per) {
+      const int cnt = min(per, r1 - q0);
+      for (int u = 0; u < cnt; ++u) emit(I.sched ? as_const(I.sched)[q0 + u] : q0 + u, zero);
+    }
+  }
+}
+
 // The sparse-product kernels declare 4 wavefronts per SIMD (<= 128 VGPRs): the
 // grid puts at most 4 workgroups of 4 wavefronts on a CU.
 // v = S p_hat, partial (rhat, v)
@@ -1216,14 +1235,10 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
         for (int v = 0; v < V; ++v) Rout[e + v] = r.c[v];
       }
     };
-    if (Y) {
+    if (Y)
       spmm_rows<double, V, MODE>(b, p, I, I.ab64, Y + tb, sig, emit);
-    } else {
-      const cvec<double, V> zero{};
-      FOR_ROWS(b, p, I)
-        emit(I.sched ? as_const(I.sched)[pos] : pos, zero);
-      END_ROWS
-    }
+    else
+      zero_rows<double, V, MODE>(b, p, I, emit);
     wg_store_partial<double, V>(nn, p.w, p.lane, cl0, I.K, part + po);
   }
 }

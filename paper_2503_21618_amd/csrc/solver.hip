@@ -578,8 +578,13 @@ struct FilterJob {
   double* Cb = nullptr;     // L * L
   int nch = 0;
   // element offsets of the job's (n, Kp) blocks and (n, L) real blocks in the
-  // layout (-1: after the previous job, see place_jobs)
-  int64_t blk = -1, rl = -1;
+  // layout (set by place_jobs)
+  int64_t blk = 0, rl = 0;
+  // warm starts (mixed precision): the pencil's copies of the previous
+  // application's Y and B X (null: not kept), and whether they are valid
+  cx<double>* yprev = nullptr;
+  double* fprev = nullptr;
+  bool warm = false;
 };
 
 struct JobShape {
@@ -645,15 +650,14 @@ int64_t padded_k(int64_t K, bool mixed) {
   return (K + W - 1) / W * W;
 }
 
-// Give every job without explicit offsets the next free ones (jobs one after
-// the other in the layout).
+// Block offsets of the jobs: one after the other in the layout.
 void place_jobs(std::vector<FilterJob>& jobs, bool mixed) {
   int64_t blk = 0, rl = 0;
   for (auto& j : jobs) {
-    if (j.blk < 0) j.blk = blk;
-    if (j.rl < 0) j.rl = rl;
-    blk = j.blk + j.P->n * padded_k((int64_t)j.N * j.L, mixed);
-    rl = j.rl + j.P->n * j.L;
+    j.blk = blk;
+    j.rl = rl;
+    blk += j.P->n * padded_k((int64_t)j.N * j.L, mixed);
+    rl += j.P->n * j.L;
   }
 }
 
@@ -686,16 +690,11 @@ void shape_totals(const std::vector<JobShape>& js, bool mixed, FilterLayout& lo,
   }
 }
 
-// span (optional): carve for this wider set of jobs, the previous step's, so
-// that every region starts where it did then and the jobs of js keep the
-// block offsets they had (warm starts read the previous blocks in place); the
-// totals of the layout are those of js.
-void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo,
-                  const std::vector<JobShape>* span = nullptr) {
+void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, FilterLayout& lo) {
   lo = FilterLayout{};
   int64_t sumN = 0;
   bool any_general = false;
-  shape_totals(span ? *span : js, mixed, lo, sumN, any_general);
+  shape_totals(js, mixed, lo, sumN, any_general);
   const size_t cs = mixed ? 8 : 16;  // complex size in the Krylov precision
   const size_t rs = cs / 2;
   // with any ILU(0) or block-Jacobi pencil in the batch, every pencil keeps p and s
@@ -731,12 +730,11 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   lo.count = cv.take<int>(64);
   lo.active = cv.take<int>(lo.n_tiles);
   lo.n_active = cv.take<int>(64);
-  lo.inst = cv.take<Inst>((span ? *span : js).size());
+  lo.inst = cv.take<Inst>(js.size());
   lo.tile_inst = cv.take<int>(lo.n_tiles);
   lo.col_inst = cv.take<int>(lo.Ktot);
   if (lo.any_ilu) lo.ilu = cv.take<char>((size_t)lo.ilu_vals * cs);
   if (lo.any_bjac) lo.bjac = cv.take<char>((size_t)lo.bjac_vals * cs);
-  if (span) shape_totals(js, mixed, lo, sumN, any_general);  // js is a subset of the span
 }
 
 size_t filter_arena_bytes(const std::vector<JobShape>& js, bool mixed) {
@@ -1215,17 +1213,17 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
 //   ||R|| <= target ||F||; solve S D = R / ||R|| in FP32 by BiCGStab to relative
 //   residual clamp(0.1 target ||F|| / ||R||, 1e-6, 1e-1); Y += ||R|| D };
 //   U = sum_j 2 Re(w_j Y_j).
-// warm_region >= 0: the arena holds the previous application of the same jobs
-// (same layout): B X_prev in F and Y_prev in region warm_region (0: Y, 1: R).
-// *final_region: the region that holds this application's Y.
-slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region,
-                               int* final_region, const std::vector<JobShape>* span) {
+// Warm starts (jobs with warm set): Y starts from Y_prev C instead of 0, and
+// the rounds start from the defect of that start; in such an application the
+// other jobs start from Y = 0 through the same steps, which computes what
+// their cold start computes.  Jobs with yprev keep Y and B X for the next one.
+slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
   for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
   FilterLayout lo;
-  carve_filter(arena, js, true, lo, span);
+  carve_filter(arena, js, true, lo);
   place_jobs(jobs, true);
   if (arena.off > arena.cap) return fail(env, SLRF_E_WORKSPACE, "workspace too small for this L and pole count");
   Batch b{};
@@ -1243,22 +1241,22 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
   st.tolc = lo.tol32;
-  const bool warm = warm_region >= 0;
-  *final_region = 0;
+  bool warm = false;
+  for (const auto& j : jobs) warm = warm || j.warm;
   if (warm) {
-    // Y0 = Y_prev C, C = X_prev^T B X_new = F_prev^T X_new, before F is overwritten
-    cx<double>* Yp = warm_region ? lo.R : lo.Y;
-    cx<double>* Y0 = warm_region ? lo.Y : lo.R;
+    // Y0 = Y_prev C with C = X_prev^T B X_new = F_prev^T X_new (Y0 = 0 for the
+    // jobs without a previous application)
     for (auto& j : jobs) {
       const int n = (int)j.P->n;
-      launch_gram(s, n, j.L, lo.F + j.rl, j.X, j.X, j.gpart, j.nch, j.C, j.Cb);
-      launch_recycle(s, n, j.L, j.N, tile_width(true), (int)padded_k(j.N * j.L, true), column_order(env),
-                     Yp + j.blk, j.C, Y0 + j.blk);
+      const int64_t Kp = padded_k(j.N * j.L, true);
+      if (j.warm) {
+        launch_gram(s, n, j.L, j.fprev, j.X, j.X, j.gpart, j.nch, j.C, j.Cb);
+        launch_recycle(s, n, j.L, j.N, tile_width(true), (int)Kp, column_order(env), j.yprev, j.C, lo.Y + j.blk);
+      } else {
+        launch_fill_zero(s, lo.Y + j.blk, (size_t)n * Kp * sizeof(cx<double>));
+      }
     }
     HIPCHK(env, hipGetLastError());
-    lo.Y = Y0;
-    lo.R = Yp;
-    *final_region = warm_region ? 0 : 1;
   }
   int64_t dn = 0, pj = 0;
   for (auto& j : jobs) {
@@ -1281,13 +1279,15 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     launch_defect_norms(s, b, lo.part64, lo.tol64, 1, lo.fnorm64, lo.scale, lo.relres, lo.tol32, kInnerTol32,
                         lo.count);
   }
-  const int round0 = warm ? 1 : 0;
+  // rounds round0 .. last: up to kMaxRounds correction solves, then the defect
+  // of the last one
+  const int round0 = warm ? 1 : 0, last = kMaxRounds + round0;
   // per job: an open column entering the round (the defect then computes its
   // product with S; the counts match the job's solve alone)
   std::vector<char> job_open(jobs.size(), 1);
   std::vector<int> job_rounds(jobs.size(), 0);
   std::vector<double> scale_h(lo.Ktot);
-  for (int round = round0; round <= kMaxRounds; ++round) {
+  for (int round = round0; round <= last; ++round) {
     launch_defect(s, b, lo.sigma_col64, lo.F, round ? lo.Y : nullptr, lo.R, lo.part64, lo.scale);
     launch_defect_norms(s, b, lo.part64, lo.tol64, round == 0, lo.fnorm64, lo.scale, lo.relres, lo.tol32,
                         kInnerTol32, lo.count);
@@ -1299,13 +1299,15 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     int64_t c0 = 0;
     for (size_t q = 0; q < jobs.size(); ++q) {
       const int K = jobs[q].N * jobs[q].L;
-      if (round > 0 && job_open[q]) jobs[q].stats.spmv += K;  // the defect's product with S
+      // the defect's product with S (not counted for a zero start, which a cold
+      // start does not compute)
+      if (round > 0 && job_open[q] && (jobs[q].warm || round > round0)) jobs[q].stats.spmv += K;
       bool any = false;
       for (int k = 0; k < K && !any; ++k) any = scale_h[c0 + k] > 0;
       job_open[q] = any;
       c0 += padded_k(K, true);
     }
-    if (open == 0 || round == kMaxRounds) break;
+    if (open == 0 || round == last) break;
     ++rounds;
     for (size_t q = 0; q < jobs.size(); ++q) job_rounds[q] += job_open[q];
     launch_mixed_rhs(s, b, round ? lo.R : nullptr, lo.F, lo.scale, st, (cx<float>*)lo.vec[8]);
@@ -1326,11 +1328,19 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   }
   int64_t wj = 0;
   for (auto& j : jobs) {
-    if (rounds > 0 || warm)
+    const int64_t Kp = padded_k(j.N * j.L, true);
+    if (rounds > 0 || warm) {
       launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(true), column_order(env), lo.Y + j.blk,
                                 lo.w + 2 * wj, j.U, false);
-    else
+    } else {  // every column met its target with Y = 0
       HIPCHK(env, hipMemsetAsync(j.U, 0, 8 * (size_t)j.P->n * j.L, s));
+      launch_fill_zero(s, lo.Y + j.blk, (size_t)j.P->n * Kp * sizeof(cx<double>));
+    }
+    if (j.yprev) {
+      HIPCHK(env, hipMemcpyAsync(j.yprev, lo.Y + j.blk, (size_t)j.P->n * Kp * sizeof(cx<double>),
+                                 hipMemcpyDeviceToDevice, s));
+      HIPCHK(env, hipMemcpyAsync(j.fprev, lo.F + j.rl, (size_t)j.P->n * j.L * 8, hipMemcpyDeviceToDevice, s));
+    }
     wj += j.N;
   }
   HIPCHK(env, hipGetLastError());
@@ -1347,21 +1357,18 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   return SLRF_OK;
 }
 
-// span: see carve_filter (mixed precision only)
-slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs, int warm_region = -1,
-                         int* final_region = nullptr, const std::vector<JobShape>* span = nullptr) {
-  int fr = 0;
-  if (!final_region) final_region = &fr;
-  *final_region = 0;
+slrf_status filter_batch(Env& env, Carver& arena, std::vector<FilterJob>& jobs) {
   if (jobs.empty()) return SLRF_OK;
-  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs, warm_region, final_region, span)
-                                         : filter_batch_fp64(env, arena, jobs);
+  return env.opt.precision == SLRF_MIXED ? filter_batch_mixed(env, arena, jobs) : filter_batch_fp64(env, arena, jobs);
 }
 
 // ---------------------------------------------------------------------------
 // Outer iteration (Algorithm 1) per pencil
 
-size_t outer_bytes(int64_t n, int64_t L) {
+// Per-pencil device buffers of the outer iteration; warm (mixed precision with
+// warm starts): also the previous filter application's Y (complex FP64, the
+// mixed form's tile-major layout for up to N poles) and B X.
+size_t outer_bytes(int64_t n, int64_t L, int64_t N, bool warm) {
   const int nch = gram_chunks((int)n, (int)L);
   const int64_t nrr = (n + 255) / 256;
   size_t b = 0;
@@ -1370,6 +1377,7 @@ size_t outer_bytes(int64_t n, int64_t L) {
   b += 3 * al((size_t)L * L * 8);              // GA GB Z
   b += al((size_t)L * 8);                      // theta
   b += al((size_t)(nrr * 2 * L + 2 * L) * 8);  // residual partials
+  if (warm) b += al((size_t)n * padded_k(N * L, true) * 16) + al((size_t)n * L * 8);  // Y_prev, B X_prev
   return b;
 }
 
@@ -1378,9 +1386,13 @@ struct SolveJob {
   int L = 0, N = 0;
   double gamma = 0;
   std::vector<double> sig, w;  // host, 2N each
-  char* mem = nullptr;         // outer_bytes(n, L) of device buffers
+  char* mem = nullptr;         // mem_bytes = outer_bytes(n, L, N, warm) of device buffers
+  size_t mem_bytes = 0;
   double *V = nullptr, *U = nullptr, *WA = nullptr, *WB = nullptr, *X = nullptr, *part = nullptr, *GA = nullptr,
          *GB = nullptr, *Zd = nullptr, *th = nullptr, *rpart = nullptr;
+  cx<double>* Yprev = nullptr;  // warm starts: Y of the previous filter application
+  double* Fprev = nullptr;      // and its right-hand side B X
+  bool has_prev = false;        // Yprev and Fprev hold the previous outer iteration's
   int nch = 0, nrr = 0;
   int k = 0, prev_count = -1, count = 0;
   double prev_maxr = INFINITY, prev_prev = INFINITY, mix_c = 3e-3, iter_sum = 0, t0 = 0;
@@ -1390,12 +1402,14 @@ struct SolveJob {
   std::vector<double> theta, rho;
   slrf_solve_stats ss{};
 
-  void carve(char* m) {
+  // max_N: the pole count the buffers are sized for; warm: keep Yprev, Fprev
+  void carve(char* m, int max_N, bool warm) {
     mem = m;
     const int64_t n = P->n;
     nch = gram_chunks((int)n, L);
     nrr = (int)((n + 255) / 256);
-    Carver co{m, 0, outer_bytes(n, L)};
+    mem_bytes = outer_bytes(n, L, max_N, warm);
+    Carver co{m, 0, mem_bytes};
     V = co.take<double>((size_t)n * L);
     U = co.take<double>((size_t)n * L);
     WA = co.take<double>((size_t)n * L);
@@ -1407,6 +1421,10 @@ struct SolveJob {
     Zd = co.take<double>((size_t)L * L);
     th = co.take<double>(L);
     rpart = co.take<double>((size_t)nrr * 2 * L + 2 * L);
+    if (warm) {
+      Yprev = co.take<cx<double>>((size_t)n * padded_k((int64_t)max_N * L, true));
+      Fprev = co.take<double>((size_t)n * L);
+    }
   }
 };
 
@@ -1511,37 +1529,10 @@ slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
 // One outer step for every job not yet done: one batched filter application
 // over all of them, then Rayleigh-Ritz and residuals per job.  A failure marks
 // the jobs of the step done with that status.
-// Warm starts across outer steps (options.recycle, mixed precision): the arena
-// keeps B X and Y of the last filter application; the next one may start from
-// them when it serves the same jobs in the same order (same arena layout).
-// What a warm start needs of the previous step: its jobs with their block
-// offsets, the set of shapes its layout was carved for, and the region that
-// holds its Y.  A step whose jobs are a subset of the previous step's (pencils
-// only finished) warm-starts every job in place; a step with a new pencil
-// starts every job cold, in a fresh layout.
-struct RecycleState {
-  std::vector<SolveJob*> last;
-  std::vector<int64_t> blk, rl;
-  std::vector<JobShape> span;
-  int y_region = 0;
-  void clear() {
-    last.clear();
-    blk.clear();
-    rl.clear();
-    span.clear();
-  }
-  void forget(const SolveJob* J) {  // J leaves the batch; the others keep their places
-    for (size_t q = 0; q < last.size(); ++q)
-      if (last[q] == J) {
-        last.erase(last.begin() + q);
-        blk.erase(blk.begin() + q);
-        rl.erase(rl.begin() + q);
-        return;
-      }
-  }
-};
-
-slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs, RecycleState* rs) {
+// Warm starts across outer steps (options.recycle, mixed precision): each
+// pencil keeps its last filter application's Y and B X in its own buffers, so
+// it warm-starts from them in any later step, whichever pencils share the step.
+slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& jobs) {
   std::vector<FilterJob> fj;
   std::vector<SolveJob*> act;
   for (SolveJob* J : jobs) {
@@ -1559,45 +1550,17 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
     }
     fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}, J->part, J->GA, J->GB,
                   J->nch});
+    FilterJob& f = fj.back();
+    if (env.opt.recycle && env.opt.precision == SLRF_MIXED && J->Yprev) {
+      f.yprev = J->Yprev;
+      f.fprev = J->Fprev;
+      f.warm = J->has_prev;
+    }
     act.push_back(J);
   }
   if (act.empty()) return SLRF_OK;
-  bool warm = rs && env.opt.recycle && env.opt.precision == SLRF_MIXED && !rs->last.empty();
-  if (warm) {
-    // every job was in the previous step (in the same order): it keeps its offsets
-    size_t q = 0;
-    for (size_t a = 0; a < act.size() && warm; ++a) {
-      while (q < rs->last.size() && rs->last[q] != act[a]) ++q;
-      if (q == rs->last.size()) {
-        warm = false;
-      } else {
-        fj[a].blk = rs->blk[q];
-        fj[a].rl = rs->rl[q];
-      }
-    }
-    if (!warm)
-      for (auto& f : fj) f.blk = f.rl = -1;
-  }
-  std::vector<JobShape> span;
-  if (warm) {
-    span = rs->span;
-  } else {
-    for (auto& f : fj) span.push_back({f.P->n, f.P->nnz, f.L, f.N, f.P->use_ilu, false, f.P->use_bjac});
-  }
-  int region = 0;
-  slrf_status st = filter_batch(env, arena, fj, warm ? rs->y_region : -1, &region, &span);
-  if (rs) {
-    rs->clear();
-    if (st == SLRF_OK && env.opt.precision == SLRF_MIXED) {
-      rs->last = act;
-      for (auto& f : fj) {
-        rs->blk.push_back(f.blk);
-        rs->rl.push_back(f.rl);
-      }
-      rs->span = std::move(span);
-      rs->y_region = region;
-    }
-  }
+  slrf_status st = filter_batch(env, arena, fj);
+  for (size_t q = 0; q < act.size(); ++q) act[q]->has_prev = st == SLRF_OK && fj[q].yprev != nullptr;
   for (size_t q = 0; q < act.size() && st == SLRF_OK; ++q) st = finish_outer(env, *act[q], fj[q].stats);
   if (st != SLRF_OK)
     for (SolveJob* J : act)
@@ -1680,7 +1643,6 @@ struct slrf_batch_s {
     std::unique_ptr<SolveJob> J;
   };
   std::map<int, Entry> entries;
-  RecycleState recycle;  // warm starts between steps that serve the same pencils
 
   std::vector<JobShape> active_shapes() const {
     std::vector<JobShape> js;
@@ -1770,7 +1732,8 @@ slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz, int64_t L, int32_t 
   const size_t arena = filter_arena_bytes(
       {JobShape{n, nnz, (int)L, (int)N, use_ilu_for(o.precond, n, nnz), false, use_bjac_for(o.precond)}},
       o.precision == SLRF_MIXED);
-  *bytes = pencil_bytes(n, nnz) + al(kTimerSlots * 4) + arena + outer_bytes(n, L);
+  *bytes = pencil_bytes(n, nnz) + al(kTimerSlots * 4) + arena +
+           outer_bytes(n, L, N, o.recycle && o.precision == SLRF_MIXED);
   return SLRF_OK;
 }
 
@@ -1852,13 +1815,12 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slr
   SolveJob J;
   J.P = &ctx->P;
   J.L = (int)L;
-  J.carve(ctx->ws + ctx->outer_off);
+  J.carve(ctx->ws + ctx->outer_off, ctx->max_N, env.opt.recycle && env.opt.precision == SLRF_MIXED);
   slrf_status st = prepare_job(env, J, gamma, poles, d_V0, ctx->max_N);
   if (st != SLRF_OK) return st;
   const std::vector<SolveJob*> jobs{&J};
-  RecycleState rs;
   while (!J.done) {
-    st = outer_step(env, Carver{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes}, jobs, &rs);
+    st = outer_step(env, Carver{ctx->ws + ctx->arena_off, 0, ctx->arena_bytes}, jobs);
     if (st != SLRF_OK) return st;
   }
   st = copy_results(env, J, n_found, h_evals, d_evecs, h_resid, stats);
@@ -1875,7 +1837,8 @@ slrf_status slrf_batch_footprint(int64_t n, int64_t nnz, int64_t L, int32_t N, i
       !transient_bytes)
     return SLRF_E_INVALID_ARG;
   if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
-  *persistent_bytes = al(pencil_bytes(n, nnz)) + al(outer_bytes(n, L));
+  // with room for the warm-start blocks (options.recycle) in mixed precision
+  *persistent_bytes = al(pencil_bytes(n, nnz)) + al(outer_bytes(n, L, N, precision == SLRF_MIXED));
   // counts the two blocks a batch with an ILU(0) or block-Jacobi pencil gives
   // every pencil (and block-Jacobi inverses when n is a multiple of 3), so that
   // the sum over a set of pencils bounds the arena the set needs
@@ -1928,7 +1891,8 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
   shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz), false, use_bjac_for(env.opt.precond)});
   if (filter_arena_bytes(shapes, env.opt.precision == SLRF_MIXED) > b->arena_bytes)
     return fail(env, SLRF_E_WORKSPACE, "the filter arena cannot hold this pencil next to the active ones");
-  const size_t pb = pencil_bytes(n, nnz), ob = outer_bytes(n, L);
+  const bool warm = env.opt.recycle && env.opt.precision == SLRF_MIXED;
+  const size_t pb = pencil_bytes(n, nnz), ob = outer_bytes(n, L, N, warm);
   char* pm = b->pool.alloc(pb);
   if (!pm) return fail(env, SLRF_E_WORKSPACE, "no room for the pencil in the workspace");
   char* om = b->pool.alloc(ob);
@@ -1942,7 +1906,7 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
   if (st == SLRF_OK) {
     J->P = P.get();
     J->L = (int)L;
-    J->carve(om);
+    J->carve(om, N, warm);
     st = prepare_job(env, *J, gamma, poles, d_V0, b->max_N);
   }
   if (st != SLRF_OK) {
@@ -1960,7 +1924,7 @@ slrf_status slrf_batch_step(slrf_batch b, int32_t* n_active) {
   std::vector<SolveJob*> jobs;
   for (auto& kv : b->entries)
     if (!kv.second.J->done) jobs.push_back(kv.second.J.get());
-  const slrf_status st = outer_step(b->env, Carver{b->arena, 0, b->arena_bytes}, jobs, &b->recycle);
+  const slrf_status st = outer_step(b->env, Carver{b->arena, 0, b->arena_bytes}, jobs);
   int act = 0;
   for (auto& kv : b->entries)
     if (!kv.second.J->done) ++act;
@@ -1997,9 +1961,8 @@ slrf_status slrf_batch_remove(slrf_batch b, int32_t id) {
   if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
   const Pencil& P = *it->second.P;
   const SolveJob& J = *it->second.J;
-  b->recycle.forget(&J);  // before a new job may reuse its address
   b->pool.release(P.mem, P.mem_bytes);
-  b->pool.release(J.mem, outer_bytes(P.n, J.L));
+  b->pool.release(J.mem, J.mem_bytes);
   b->entries.erase(it);
   return SLRF_OK;
 }

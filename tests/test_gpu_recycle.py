@@ -85,12 +85,15 @@ def test_recycle_batch_matches_dense(slrf, torch):
 
 
 def test_recycle_batch_bitwise_equals_alone(slrf, torch):
-    """Warm starts in a batch whose pencils finish at different steps and are
-    removed as they finish: the others keep their places and warm-start as they
-    would alone, so every result is bitwise the solve alone and takes the same
-    number of sparse products (fixed tiling: the autotuner may pick another
-    row-block size for the batch than for a pencil alone, which rounds
-    differently)."""
+    """Warm starts in a batch whose pencils arrive at different steps and are
+    removed as they finish: each pencil warm-starts from its own previous
+    step, as it would alone.  The pencils present from the first step give
+    bitwise the solve alone and take the same number of sparse products
+    (fixed tiling: the autotuner may pick another row-block size for the batch
+    than for a pencil alone, which rounds differently).  The last pencil joins
+    after the first step; its first filter application runs from Y = 0 inside
+    an application that warm-starts the others, which rounds differently from
+    a cold start, so it agrees with its solve alone to the solver's accuracy."""
     from test_gpu_batch import big_cases, ws_for
     cases = big_cases()
     opt = slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG, recycle=1)
@@ -103,30 +106,42 @@ def test_recycle_batch_bitwise_equals_alone(slrf, torch):
         alone.append(r)
         s.close()
     ws, arena = ws_for(slrf, cases, slrf.MIXED)
-    say(f"case recycle batch: {len(cases)} pencils")
+    say(f"case recycle batch: {len(cases)} pencils, the last one joining after the first step")
     b = slrf.Batch(ws, arena, max_poles=4, options=opt)
-    ids = [b.add(p.A, p.B, gamma, L, V0=pencils.start_block(p.n, L, 40 + i))
-           for i, (p, gamma, L, _) in enumerate(cases)]
+
+    def add(i):
+        p, gamma, L, _ = cases[i]
+        return b.add(p.A, p.B, gamma, L, V0=pencils.start_block(p.n, L, 40 + i))
+
+    ids = {i: add(i) for i in range(len(cases) - 1)}
     out, steps = {}, 0
-    while len(out) < len(ids):
+    while len(out) < len(cases):
         b.step()
         steps += 1
         assert steps < 60
-        for i, pid in enumerate(ids):
+        if steps == 1:
+            ids[len(cases) - 1] = add(len(cases) - 1)
+        for i, pid in ids.items():
             if i not in out and b.query(pid)[0]:
                 out[i] = b.result(pid)
                 b.remove(pid)
     assert len({out[i].stats["outer_iterations"] for i in out}) > 1   # pencils left at different steps
     for i, a in enumerate(alone):
         r = out[i]
-        say(f"  pencil {i}: found {r.n_found} outer {r.stats['outer_iterations']} "
+        nf = r.n_found
+        say(f"  pencil {i}: found {nf} outer {r.stats['outer_iterations']} "
             f"(alone {a.stats['outer_iterations']}), spmv {r.stats['spmv_total']} (alone {a.stats['spmv_total']})")
-        assert r.status == 0 and r.n_found == a.n_found
-        assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
-        assert r.stats["spmv_total"] == a.stats["spmv_total"]
-        assert np.array_equal(r.evals, a.evals)
-        assert np.array_equal(r.resid, a.resid)
-        assert torch.equal(r.evecs, a.evecs)
+        assert r.status == 0 and nf == a.n_found
+        if i < len(cases) - 1:
+            assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
+            assert r.stats["spmv_total"] == a.stats["spmv_total"]
+            assert np.array_equal(r.evals, a.evals)
+            assert np.array_equal(r.resid, a.resid)
+            assert torch.equal(r.evecs, a.evecs)
+        else:
+            assert np.abs(r.evals[:nf] / a.evals[:nf] - 1).max() < 1e-10
+            assert r.resid[:nf].max() <= 1e-8
+            assert abs(r.stats["spmv_total"] / a.stats["spmv_total"] - 1) < 0.1
     b.close()
 
 
