@@ -107,6 +107,22 @@ def test_workspace_bytes_monotone(lib):
         lib.workspace_bytes(0, 3000, 16, 2)
 
 
+def test_warm_start_blocks_in_the_sizes(lib):
+    """Warm starts keep each pencil's previous Y (n x N L complex FP64, the mixed
+    form's columns padded to whole tiles of 128) and B X (n x L real FP64): the
+    workspace with recycle = 1 and the mixed batch footprint hold at least that
+    much more than without."""
+    n, nnz, L, N = 5000, 5000 * 27, 40, 6
+    kp = -(-N * L // 128) * 128
+    need = n * kp * 16 + n * L * 8
+    cold = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(precision=lib.MIXED, recycle=0))
+    warm = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(precision=lib.MIXED, recycle=1))
+    assert need <= warm - cold <= need + 4096
+    f64, _ = lib.batch_footprint(n, nnz, L, N, lib.FP64)
+    mixed, _ = lib.batch_footprint(n, nnz, L, N, lib.MIXED)
+    assert need <= mixed - f64 <= need + 4096
+
+
 def _create(lib, A, B, ws_ptr=0x100000, ws_bytes=1 << 40):
     """slrf_create with a fake device pointer: validation runs before any device use."""
     arrs = [np.ascontiguousarray(x) for x in (
