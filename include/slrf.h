@@ -114,8 +114,10 @@ typedef struct {
 typedef struct {
   int32_t max_iterations;   /* largest inner-solver iteration count over the columns */
   double mean_iterations;   /* mean inner-solver iterations per (pole, column) */
-  int64_t spmv;             /* single-vector products with A - sigma_j B (2 per full
-                               iteration, 1 when a solve stops at the half step) */
+  int64_t spmv;             /* single-vector products with A - sigma_j B (BiCGStab: 2 per
+                               full iteration, 1 when a solve stops at the half step;
+                               COCG: 1 per iteration; MIXED adds the FP64 defect's
+                               product per column and correction round) */
   int32_t n_breakdown;      /* columns stopped by a zero denominator */
   int32_t n_maxit;          /* columns that hit inner_maxit */
   int32_t refinements;      /* MIXED: defect-correction rounds in which this pencil had an
