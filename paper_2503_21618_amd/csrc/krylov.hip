@@ -816,19 +816,27 @@ __device__ __forceinline__ size_t slot_partial(int k, int per, int rot) {
   return (size_t)(8 * q + (k & 7));
 }
 
+// Column sums of the partials: wavefront w of the block's nw (up to 16) adds
+// slots w, w + nw, ... in slot order, then the nw sums are added in wavefront
+// order (the order depends only on the block size).
+constexpr int kMaxScWaves = 16;
+// threads of the COCG scalar kernels (one block per column tile: the G partials
+// of each column are read by 16 wavefronts)
+constexpr int kScWG = kMaxScWaves * WAVE;
 template <typename T>
 __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int rot, int Ktot, int c,
                                            bool valid) {
-  __shared__ T red[4][WAVE];
-  const int w = wave_id(), lane = lane_id(), per = G >> 3;
+  __shared__ T red[kMaxScWaves][WAVE];
+  const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
   T acc = 0;
   if (valid) {
 #pragma unroll 8
-    for (int k = w; k < G; k += 4) acc += part[slot_partial(k, per, rot) * Ktot + c];
+    for (int k = w; k < G; k += nw) acc += part[slot_partial(k, per, rot) * Ktot + c];
   }
   red[w][lane] = acc;
   __syncthreads();
-  const T tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  T tot = red[0][lane];
+  for (int i = 1; i < nw; ++i) tot += red[i][lane];
   __syncthreads();
   return tot;
 }
@@ -836,12 +844,12 @@ __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, in
 template <typename R>
 __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int rot, int Ktot, int c,
                                                   bool valid) {
-  __shared__ R rr[4][WAVE], ri[4][WAVE];
-  const int w = wave_id(), lane = lane_id(), per = G >> 3;
+  __shared__ R rr[kMaxScWaves][WAVE], ri[kMaxScWaves][WAVE];
+  const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
   R ar = 0, ai = 0;
   if (valid) {
 #pragma unroll 8
-    for (int k = w; k < G; k += 4) {
+    for (int k = w; k < G; k += nw) {
       const cx<R> v = part[slot_partial(k, per, rot) * Ktot + c];
       ar += v.re;
       ai += v.im;
@@ -850,8 +858,11 @@ __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int 
   rr[w][lane] = ar;
   ri[w][lane] = ai;
   __syncthreads();
-  const cx<R> tot = {rr[0][lane] + rr[1][lane] + rr[2][lane] + rr[3][lane],
-                     ri[0][lane] + ri[1][lane] + ri[2][lane] + ri[3][lane]};
+  cx<R> tot = {rr[0][lane], ri[0][lane]};
+  for (int i = 1; i < nw; ++i) {
+    tot.re += rr[i][lane];
+    tot.im += ri[i][lane];
+  }
   __syncthreads();
   return tot;
 }
@@ -1461,7 +1472,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_start(Batch b, KrylovState<R> st
 // start values: ||f|| from part_b (written by the right-hand-side kernel), rho
 // from part_a; every tile starts on the active list, padding columns converged
 template <typename R>
-__global__ __launch_bounds__(WG) void k_cocg_init_scalars(Batch b, KrylovState<R> st) {
+__global__ __launch_bounds__(kScWG) void k_cocg_init_scalars(Batch b, KrylovState<R> st) {
   constexpr int V = LaneWidth<R>::V;
   SC_PROLOGUE(V)
   if (threadIdx.x == 0) {
@@ -1516,7 +1527,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_spmm(Batch b, KrylovState<R> st,
 
 // alpha = rho / [p, q]
 template <typename R>
-__global__ __launch_bounds__(WG) void k_cocg_alpha(Batch b, KrylovState<R> st) {
+__global__ __launch_bounds__(kScWG) void k_cocg_alpha(Batch b, KrylovState<R> st) {
   constexpr int V = LaneWidth<R>::V;
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
@@ -1631,7 +1642,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
 
 // ||r|| test; beta = rho' / rho
 template <typename R>
-__global__ __launch_bounds__(WG) void k_cocg_beta(Batch b, KrylovState<R> st, R tol, int maxit) {
+__global__ __launch_bounds__(kScWG) void k_cocg_beta(Batch b, KrylovState<R> st, R tol, int maxit) {
   constexpr int V = LaneWidth<R>::V;
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
@@ -1725,14 +1736,14 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R>
 template <typename R>
 void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
   k_cocg_start<R><<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, st);
-  k_cocg_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(WG), 0, s>>>(b, st);
+  k_cocg_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(kScWG), 0, s>>>(b, st);
 }
 
 template <typename R>
 void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
                            LaunchTimer* tm, const IterBytes& by) {
   const dim3 grid((unsigned)b.G), blk(WG);
-  const dim3 cgrid((unsigned)b.n_tiles), cblk(WG);
+  const dim3 cgrid((unsigned)b.n_tiles), cblk(kScWG);
   int* c;
   // q = S p: gather p once, write q, read p's own rows; the merged CSR once
   c = tm ? tm->begin(s, 0, 2 * by.blk, by.matrix) : nullptr;
