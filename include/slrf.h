@@ -240,8 +240,8 @@ const char* slrf_last_error(slrf_ctx ctx);
  * warm-starts from its own previous step, as it would alone, whichever pencils
  * join or leave the batch; a pencil whose first step shares a filter
  * application with warm-started pencils starts from Y = 0 through the warm
- * path, which rounds differently from a cold start, so it agrees with its
- * solve alone to the solver's accuracy rather than bitwise.
+ * path, which computes what its cold start computes, so its result too is
+ * bitwise the solve alone.
  *
  * Workspace (device, 256-byte aligned, caller-owned): a filter arena of
  * arena_bytes shared by the pencils of one step, and a pool for each pencil's

@@ -1238,7 +1238,9 @@ __global__ __launch_bounds__(WG) void k_defect(Batch b, const cx<double>* __rest
         const double f = cl0 + v < I.K ? F[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)] : 0.0;
         r.c[v] = Y ? cx<double>{f - q.c[v].re, -q.c[v].im} : cx<double>{f, 0.0};
         if (cl0 + v >= I.K) r.c[v] = {0.0, 0.0};
-        nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
+        // explicit fused steps: the zero-product copy of this code (zero_rows)
+        // and the product copy then round |r|^2 alike (no contraction choice)
+        nn[v] = fma(r.c[v].re, r.c[v].re, fma(r.c[v].im, r.c[v].im, nn[v]));
       }
       if (Y && valid) {
         const size_t e = tb + (size_t)i * (WAVE * V);
@@ -1337,7 +1339,8 @@ __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __r
           const cx<double> d = R ? R[e + v] : cx<double>{F[I.rl + (size_t)i * I.L + col_rhs(cc0 + v, I.L, I.N, I.rmaj)], 0.0};
           r.c[v] = {(float)(d.re * inv[v]), (float)(d.im * inv[v])};
           x.c[v] = {0.f, 0.f};
-          nn[v] += r.c[v].re * r.c[v].re + r.c[v].im * r.c[v].im;
+          // explicit fused steps: the F and the R copies round |r|^2 alike
+          nn[v] = fmaf(r.c[v].re, r.c[v].re, fmaf(r.c[v].im, r.c[v].im, nn[v]));
         }
         stv<float, V>(st.r + e, r);
         stv<float, V>(rhat + e, r);

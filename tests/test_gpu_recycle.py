@@ -87,13 +87,12 @@ def test_recycle_batch_matches_dense(slrf, torch):
 def test_recycle_batch_bitwise_equals_alone(slrf, torch):
     """Warm starts in a batch whose pencils arrive at different steps and are
     removed as they finish: each pencil warm-starts from its own previous
-    step, as it would alone.  The pencils present from the first step give
-    bitwise the solve alone and take the same number of sparse products
-    (fixed tiling: the autotuner may pick another row-block size for the batch
-    than for a pencil alone, which rounds differently).  The last pencil joins
-    after the first step; its first filter application runs from Y = 0 inside
-    an application that warm-starts the others, which rounds differently from
-    a cold start, so it agrees with its solve alone to the solver's accuracy."""
+    step, as it would alone, so every result is bitwise the solve alone and
+    takes the same number of sparse products (fixed tiling: the autotuner may
+    pick another row-block size for the batch than for a pencil alone, which
+    rounds differently).  The last pencil joins after the first step: its first
+    filter application runs from Y = 0 inside an application that warm-starts
+    the others, which computes what its cold start computes."""
     from test_gpu_batch import big_cases, ws_for
     cases = big_cases()
     opt = slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG, recycle=1)
@@ -132,16 +131,11 @@ def test_recycle_batch_bitwise_equals_alone(slrf, torch):
         say(f"  pencil {i}: found {nf} outer {r.stats['outer_iterations']} "
             f"(alone {a.stats['outer_iterations']}), spmv {r.stats['spmv_total']} (alone {a.stats['spmv_total']})")
         assert r.status == 0 and nf == a.n_found
-        if i < len(cases) - 1:
-            assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
-            assert r.stats["spmv_total"] == a.stats["spmv_total"]
-            assert np.array_equal(r.evals, a.evals)
-            assert np.array_equal(r.resid, a.resid)
-            assert torch.equal(r.evecs, a.evecs)
-        else:
-            assert np.abs(r.evals[:nf] / a.evals[:nf] - 1).max() < 1e-10
-            assert r.resid[:nf].max() <= 1e-8
-            assert abs(r.stats["spmv_total"] / a.stats["spmv_total"] - 1) < 0.1
+        assert r.stats["outer_iterations"] == a.stats["outer_iterations"]
+        assert r.stats["spmv_total"] == a.stats["spmv_total"]
+        assert np.array_equal(r.evals, a.evals)
+        assert np.array_equal(r.resid, a.resid)
+        assert torch.equal(r.evecs, a.evecs)
     b.close()
 
 
