@@ -113,6 +113,105 @@ def ilu0_solve(fac, Y):
     return Z
 
 
+def node_graph(A, B, block: int):
+    """Adjacency of the nodes (block = 1: every unknown is a node; block = 3:
+    unknowns 3k, 3k+1, 3k+2 form node k) in the union pattern of A and B, as a
+    list of neighbour sets (without the node itself)."""
+    indptr, indices = union_pattern(A, B)
+    n = A.shape[0]
+    nodes = n // block
+    nb = [set() for _ in range(nodes)]
+    for i in range(n):
+        k = i // block
+        for j in indices[indptr[i]:indptr[i + 1]]:
+            m = int(j) // block
+            if m != k:
+                nb[k].add(m)
+    return nb
+
+
+def greedy_colouring(A, B, block: int = 1) -> np.ndarray:
+    """Colour of every node such that coupled nodes differ: nodes are taken in
+    increasing index and each gets the smallest colour none of its already
+    coloured neighbours has (greedy colouring)."""
+    nb = node_graph(A, B, block)
+    col = -np.ones(len(nb), np.int64)
+    for k in range(len(nb)):
+        used = {int(col[m]) for m in nb[k] if col[m] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[k] = c
+    return col
+
+
+class MulticolourSGS:
+    """Symmetric Gauss-Seidel preconditioner of S = A - sigma B in a multicolour
+    order (the shifted-operator preconditioner of Section 4.2 is an ILU; this is a
+    symmetric one with parallel colour sweeps, usable inside COCG):
+
+        M = (D + L) D^{-1} (D + U),
+
+    D the block diagonal of S (1x1 or 3x3 node blocks), L (U) the couplings of a
+    node to nodes of lower (higher) colour.  Nodes of one colour are not coupled,
+    so M^{-1} r is a forward sweep over the colours, (D + L) y = r, i.e.
+    y_k = D_k^{-1} (r_k - sum_{colour(m) < colour(k)} S_km y_m), then a backward
+    sweep, (D + U) z = D y, i.e. z_k = y_k - D_k^{-1} sum_{colour(m) > colour(k)} S_km z_m.
+    With S complex symmetric, U = L^T and M is complex symmetric too."""
+
+    def __init__(self, A, B, sigma: complex, block: int = 1, colour=None):
+        n = A.shape[0]
+        if block not in (1, 3) or n % block:
+            raise ValueError("block must be 1, or 3 with n divisible by 3")
+        self.n, self.block = n, block
+        self.colour = greedy_colouring(A, B, block) if colour is None else np.asarray(colour)
+        S = (A.astype(np.complex128) - sigma * B).tocoo()
+        cr = self.colour[S.row // block]
+        cc = self.colour[S.col // block]
+        import scipy.sparse as sp
+        low, up, dia = cr > cc, cr < cc, cr == cc
+        mk = lambda m: sp.csr_matrix((S.data[m], (S.row[m], S.col[m])), shape=(n, n))
+        self.L, self.U, self.D = mk(low), mk(up), mk(dia)
+        # same-colour entries can only be the node's own block
+        if np.any((S.row[dia] // block) != (S.col[dia] // block)):
+            raise ValueError("colouring couples two nodes of one colour")
+        nodes = n // block
+        blocks = np.zeros((nodes, block, block), np.complex128)
+        Dc = self.D.tocoo()
+        blocks[Dc.row // block, Dc.row % block, Dc.col % block] = Dc.data
+        self.blocks = blocks
+        self.order = [np.flatnonzero(self.colour == c) for c in range(int(self.colour.max()) + 1)]
+
+    def _rows(self, nodes):
+        return (nodes[:, None] * self.block + np.arange(self.block)[None, :]).ravel()
+
+    def _dsolve(self, nodes, Y):
+        m = Y.shape[1]
+        Z = np.linalg.solve(self.blocks[nodes], Y.reshape(len(nodes), self.block, m))
+        return Z.reshape(len(nodes) * self.block, m)
+
+    def apply(self, R):
+        """M^{-1} R for an (n, m) block."""
+        R = np.asarray(R, dtype=np.complex128)
+        Y = np.zeros_like(R)
+        for nodes in self.order:
+            rows = self._rows(nodes)
+            Y[rows] = self._dsolve(nodes, R[rows] - self.L[rows] @ Y)
+        Z = np.zeros_like(R)
+        for nodes in reversed(self.order):
+            rows = self._rows(nodes)
+            Z[rows] = Y[rows] - self._dsolve(nodes, self.U[rows] @ Z)
+        return Z
+
+    def matrix(self):
+        """M itself, formed from its factors (for checks on small pencils)."""
+        import scipy.sparse as sp
+        n = self.n
+        Db = sp.block_diag(list(self.blocks), format="csr")
+        Dinv = sp.block_diag([np.linalg.inv(b) for b in self.blocks], format="csr")
+        return ((Db + self.L) @ Dinv @ (Db + self.U)).toarray() if n <= 4000 else None
+
+
 def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None,
              precond: str = "jacobi"):
     """Solve (A - sigma_c B) x_c = F[:, l(c)] for every pole and column.
@@ -210,7 +309,9 @@ def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None
     (S_j^T = S_j), and CG with the bilinear form [u, v] = u^T v (no conjugation)
     in place of the inner product applies; it needs one product with S_j per
     iteration.  The preconditioner must be complex symmetric as well: point
-    Jacobi or node block Jacobi (ILU(0) is not symmetric and is not offered).
+    Jacobi, node block Jacobi, or multicolour symmetric Gauss-Seidel with point
+    ("mcsgs") or node ("mcsgs3") blocks (ILU(0) is not symmetric and is not
+    offered).
     Same interface and conventions as ``bicgstab``: x_0 = 0, columns pole-major,
     convergence on the recursively updated residual ||r||_2 <= tol ||f||_2.
 
@@ -236,6 +337,11 @@ def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None
         def Minv(Y):
             return np.concatenate([block_jacobi3_solve(blks[j], Y[:, j * L:(j + 1) * L])
                                    for j in range(N)], axis=1)
+    elif precond in ("mcsgs", "mcsgs3"):
+        sgs = [MulticolourSGS(A, B, s, 3 if precond == "mcsgs3" else 1) for s in sigmas]
+
+        def Minv(Y):
+            return np.concatenate([sgs[j].apply(Y[:, j * L:(j + 1) * L]) for j in range(N)], axis=1)
     else:
         raise ValueError(f"COCG needs a symmetric preconditioner, not {precond}")
     f = np.tile(F, (1, N)).astype(np.complex128)

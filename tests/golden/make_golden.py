@@ -3,11 +3,17 @@ and the shared input generator ``pencils``.
 
     python tests/golden/make_golden.py poles     # SLRF pole tables, N = 4, 6, 8
     python tests/golden/make_golden.py count_c2  # inertia count of the 64^3 scalar pencil
+    python tests/golden/make_golden.py eig_c2    # eigenvalues of the 64^3 scalar pencil in (0, 421]
+    python tests/golden/make_golden.py eig_c3    # eigenvalues of the 48^3-node elasticity pencil
 
 Pole tables: the oracle's SLRF design (ridge-regularised least squares, see
 oracle/poles.py) at gamma = 1, alpha = 1, beta = 0.01 (the paper's Section 4.2
 setting).  Count: Sylvester inertia of A - gamma B for the 64^3 log-normal
 scalar pencil at gamma = 421 (sparse symmetric factorisation; several minutes).
+Eigenvalues: shift-invert subspace iteration with one banded Cholesky factor of
+A (oracle/shift_invert.py; minutes for the 64^3 pencil, about an hour for the
+elasticity pencil), with the Sylvester count of A - gamma B by banded block
+elimination at three block sizes beside it.
 """
 import json
 import os
@@ -20,7 +26,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import numpy as np  # noqa: E402
 
 import pencils  # noqa: E402
-from oracle import inertia, poles  # noqa: E402
+from oracle import banded, inertia, poles, shift_invert  # noqa: E402
 
 
 def make_poles():
@@ -49,9 +55,82 @@ def make_count_c2():
     print(out, flush=True)
 
 
+def _log(msg):
+    print(time.strftime("%H:%M:%S"), msg, flush=True)
+
+
+def _block_counts(p, gamma):
+    """Sylvester counts at three block sizes; unpivoted elimination of an
+    indefinite matrix can lose accuracy, so disagreeing counts are recorded as
+    such rather than trusted."""
+    out = {}
+    for nb in (512, 1024, 1536):
+        try:
+            out[str(nb)] = banded.inertia_count(p.A, p.B, gamma, nb=nb)
+        except RuntimeError as e:
+            out[str(nb)] = str(e)
+        _log(f"inertia nb={nb}: {out[str(nb)]}")
+    return out
+
+
+def _large_eigs(p, gamma_run, nsub, seed, tol):
+    t = time.time()
+    F = banded.band_cholesky(p.A)
+    _log(f"banded Cholesky of A: n={p.n}, kd={F.kd}, {time.time() - t:.0f} s")
+    V0 = pencils.start_block(p.n, nsub, seed)
+    r = shift_invert.subspace_iteration(p.A, p.B, gamma_run, V0, tol=tol, factor=F, log=_log)
+    return r, time.time() - t
+
+
+def make_eig_c2():
+    """All eigenvalues of the 64^3 log-normal scalar pencil in (0, 421]."""
+    p = pencils.c2_scalar3d()
+    gamma = 421.0
+    r, secs = _large_eigs(p, gamma, 240, 11, 1e-10)
+    out = {"pencil": p.name, "n": p.n, "gamma": gamma, "count": len(r.theta),
+           "eigenvalues": r.theta.tolist(), "max_rho": float(r.rho.max()),
+           "next_ritz_value": float(r.theta_all[len(r.theta)]),
+           "subspace": 240, "iterations": r.iterations, "converged": bool(r.converged),
+           "inertia_counts": _block_counts(p, gamma),
+           "source": "oracle.shift_invert.subspace_iteration (shift 0, banded Cholesky)",
+           "seconds": secs}
+    with open(os.path.join(HERE, "eig_scalar3d_m64_ln0.5_s2_g421.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    _log(f"c2: {out['count']} eigenvalues, max rho {out['max_rho']:.2e}")
+
+
+def make_eig_c3():
+    """Eigenvalues of the elasticity pencil below 112, then gamma in the middle of
+    the widest gap (relative width >= 1e-4) that leaves 195..205 below it."""
+    p = pencils.c3_elasticity()
+    r, secs = _large_eigs(p, 112.0, 520, 13, 1e-10)
+    th = r.theta
+    best = None
+    for k in range(195, min(206, len(th))):
+        gap = (th[k] - th[k - 1]) / th[k]
+        if best is None or gap > best[1]:
+            best = (k, gap)
+    k, gap = best
+    gamma = float(0.5 * (th[k - 1] + th[k]))
+    out = {"pencil": p.name, "n": p.n, "gamma": gamma, "count": k,
+           "relative_gap": gap, "eigenvalues": th[:k].tolist(),
+           "next_eigenvalue": float(th[k]), "max_rho": float(r.rho[:k].max()),
+           "subspace": 520, "iterations": r.iterations, "converged": bool(r.converged),
+           "inertia_counts": _block_counts(p, gamma),
+           "source": "oracle.shift_invert.subspace_iteration (shift 0, banded Cholesky)",
+           "seconds": secs}
+    with open(os.path.join(HERE, "eig_elast3d_48_s3.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    _log(f"c3: gamma {gamma}, {k} eigenvalues, gap {gap:.2e}, max rho {out['max_rho']:.2e}")
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["poles", "count_c2"]
     if "poles" in what:
         make_poles()
     if "count_c2" in what:
         make_count_c2()
+    if "eig_c2" in what:
+        make_eig_c2()
+    if "eig_c3" in what:
+        make_eig_c3()

@@ -466,3 +466,300 @@ def test_quadrature_rule_poles():
     s, w = poles.circle_quadrature(8, "gauss-legendre", 1.0)
     assert abs(poles.filter_value(0.5, s, w) - 1) < 1e-3
     assert abs(poles.filter_value(2.0, s, w)) < 1e-3
+
+
+# ---- filter derivative, separation factor and quadrature filters by value ----
+
+def test_separation_factor_is_the_slope_at_gamma():
+    """Definition 3.1: the separation factor is |Phi'(gamma)|.  Pinned against a
+    central difference of Phi itself (step 1e-5 gamma; the O(h^2) error of the
+    difference is far below the tolerance), for a designed and a quadrature
+    filter and at two scales of gamma."""
+    for gamma in (1.0, 421.0):
+        s, w, _ = golden_poles(4, gamma)
+        z, q = poles.circle_quadrature(5, "gauss-legendre", gamma)
+        for sig, wt in ((s, w), (z, q)):
+            h = 1e-5 * gamma
+            fd = (poles.filter_value(gamma + h, sig, wt) - poles.filter_value(gamma - h, sig, wt)) / (2 * h)
+            assert abs(poles.filter_derivative(gamma, sig, wt) - fd) < 1e-7 * abs(fd)
+            assert abs(poles.separation_factor(sig, wt, gamma) - abs(fd)) < 1e-7 * abs(fd)
+            # and at interior points, where a dropped square or factor 2 would show
+            for x in (0.1 * gamma, 0.5 * gamma, 2.0 * gamma):
+                fd = (poles.filter_value(x + h, sig, wt) - poles.filter_value(x - h, sig, wt)) / (2 * h)
+                assert abs(poles.filter_derivative(x, sig, wt) - fd) < 1e-6 * max(abs(fd), 1e-3 / gamma)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 8])
+def test_midpoint_filter_closed_form(N):
+    """Section 3.2, midpoint rule: the 2N equispaced nodes z_k = c + r w_k with
+    w_k^(2N) = -1 sum (1/2N) w_k/(w_k - t) = 1/(1 + t^(2N)), t = (x - c)/r
+    (partial fractions of 1/(1 + t^(2N))).  So the midpoint filter is the
+    Butterworth-type function 1/(1 + ((x - c)/r)^(2N)) on the real axis."""
+    gamma = 3.7
+    c = r = gamma / 2
+    z, w = poles.circle_quadrature(N, "midpoint", gamma)
+    x = np.linspace(-2 * gamma, 3 * gamma, 1001)
+    x = x[np.abs(np.abs(x - c) - r) > 1e-3 * r]
+    expect = 1.0 / (1.0 + ((x - c) / r) ** (2 * N))
+    assert np.abs(poles.filter_value(x, z, w) - expect).max() < 1e-13
+
+
+def _angles_and_weights(z, w, gamma):
+    """Recover the angle rule (theta_j, q_j) on (0, pi) from nodes and weights
+    z_j = c + r e^{i theta_j}, w_j = -(r e^{i theta_j}) q_j / (2 pi)."""
+    c = r = gamma / 2
+    e = (z - c) / r
+    th = np.angle(e)
+    q = (-2 * np.pi * w / (r * e))
+    return th, q
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6, 8])
+def test_gauss_legendre_angle_rule_exactness(N):
+    """The Gauss-Legendre rule in theta on (0, pi) integrates theta^k exactly for
+    k <= 2N - 1 (and not k = 2N), with real positive weights and unit-modulus
+    node offsets on the circle."""
+    gamma = 2.0
+    z, w = poles.circle_quadrature(N, "gauss-legendre", gamma)
+    assert np.abs(np.abs(z - gamma / 2) - gamma / 2).max() < 1e-15
+    th, q = _angles_and_weights(z, w, gamma)
+    assert np.abs(q.imag).max() < 1e-14 and (q.real > 0).all()
+    q = q.real
+    assert np.all((th > 0) & (th < np.pi))
+    for k in range(2 * N):
+        assert abs((q * th ** k).sum() - np.pi ** (k + 1) / (k + 1)) < 1e-12 * np.pi ** (k + 1)
+    if N <= 4:  # the first inexact degree (the error shrinks fast with N)
+        assert abs((q * th ** (2 * N)).sum() - np.pi ** (2 * N + 1) / (2 * N + 1)) > 1e-8 * np.pi ** (2 * N + 1)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6, 8])
+def test_gauss_chebyshev_angle_rule_exactness(N):
+    """The Gauss-Chebyshev rule: with theta = (x + 1) pi / 2 the angle weights are
+    q_j = (pi/2)(pi/N) sqrt(1 - x_j^2), so sum_j q_j p(x_j)/sqrt(1 - x_j^2) =
+    (pi/2) int_{-1}^{1} p(x)/sqrt(1 - x^2) dx exactly for deg p <= 2N - 1.
+    With p = x^(2m): int = pi (2m)! / (4^m (m!)^2); odd powers give 0."""
+    gamma = 2.0
+    z, w = poles.circle_quadrature(N, "gauss-chebyshev", gamma)
+    th, q = _angles_and_weights(z, w, gamma)
+    assert np.abs(q.imag).max() < 1e-14
+    q = q.real
+    x = 2 * th / np.pi - 1
+    for k in range(2 * N):
+        exact = 0.0 if k % 2 else math.pi * math.factorial(k) / (4 ** (k // 2) * math.factorial(k // 2) ** 2)
+        got = (q * x ** k / np.sqrt(1 - x * x)).sum()
+        assert abs(got - 0.5 * math.pi * exact) < 1e-12
+    k = 2 * N
+    exact = math.pi * math.factorial(k) / (4 ** (k // 2) * math.factorial(k // 2) ** 2)
+    assert abs((q * x ** k / np.sqrt(1 - x * x)).sum() - 0.5 * math.pi * exact) > 1e-8
+
+
+# ---- large-pencil path: banded Cholesky, inertia by block elimination, shift-invert ----
+
+def _random_band_spd(n, kd, seed):
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    for k in range(1, kd + 1):
+        v = rng.standard_normal(n - k)
+        A += np.diag(v, k) + np.diag(v, -k)
+    A += np.diag(np.abs(A).sum(1) + 1.0 + rng.random(n))   # diagonally dominant: SPD
+    return sp.csr_matrix(A)
+
+
+@pytest.mark.parametrize("n,kd,nb", [(200, 7, 16), (203, 31, 64), (150, 12, 500), (97, 96, 10)])
+def test_band_cholesky_solve_matches_lapack(n, kd, nb):
+    """A Z = R by the block-column factor against LAPACK's banded Cholesky
+    (dpbtrf/dpbtrs through scipy) and a dense solve."""
+    import scipy.linalg as sl
+    from oracle import banded
+    A = _random_band_spd(n, kd, n + kd)
+    assert banded.bandwidth(A) == kd
+    R = np.random.default_rng(1).standard_normal((n, 5))
+    F = banded.band_cholesky(A, nb=nb)
+    Z = banded.band_solve(F, R)
+    Ad = A.toarray()
+    ab = np.zeros((kd + 1, n))
+    for k in range(kd + 1):
+        ab[kd - k, k:] = np.diag(Ad, k)
+    Zl = sl.cho_solve_banded((sl.cholesky_banded(ab), False), R)
+    assert np.abs(Z - Zl).max() < 1e-12 * np.abs(Zl).max()
+    assert np.abs(Ad @ Z - R).max() < 1e-12 * np.abs(R).max()
+    # the factor itself: L L^T = A
+    L = np.zeros((n, n))
+    for j0, b, Ljj, Lb in F.panels:
+        L[j0:j0 + b, j0:j0 + b] = Ljj
+        L[j0 + b:j0 + b + Lb.shape[0], j0:j0 + b] = Lb
+    assert np.abs(L @ L.T - Ad).max() < 1e-12 * np.abs(Ad).max()
+    assert np.abs(np.triu(L, 1)).max() == 0.0 and np.abs(np.tril(L, -kd - 1)).max() == 0.0
+
+
+def test_band_inertia_counts():
+    """#{lambda < gamma} by block elimination against the Sturm count of the 1D
+    string, against the eigenvalues of small 2D/3D pencils (gamma low in the
+    spectrum, where the pencils of the workloads put it), and a singular block is
+    refused.  Several block sizes, so the block boundaries move."""
+    from oracle import banded
+    n = 400
+    p = pencils.string_1d(n)
+    lam, _ = closed_1d(n)
+    for k in (1, 7, 40):
+        g = 0.5 * (lam[k - 1] + lam[k])
+        assert inertia.sturm_count_tridiagonal(p.A, p.B, g) == k
+        for nb in (1, 3, 64):
+            assert banded.inertia_count(p.A, p.B, g, nb=nb) == k
+    for q in (pencils.scalar_q1(20, 2, 0.5, 3), pencils.scalar_q1(9, 3, 0.5, 4),
+              pencils.elasticity_q1(4, 3, 3, 0.25, 0.7, 0.3, (0.8, 1.2), 5)):
+        ev = dense.all_eigenpairs(q.A, q.B)[0]
+        for k in (3, 12):
+            g = 0.5 * (ev[k - 1] + ev[k])
+            for nb in (16, 64, 1000):
+                assert banded.inertia_count(q.A, q.B, g, nb=nb) == k
+    M = sp.csr_matrix(np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 1.0], [0.0, 1.0, 2.0]]))
+    with pytest.raises(RuntimeError):
+        banded.band_inertia(M, nb=2)
+
+
+def test_shift_invert_matches_dense_and_closed_form():
+    """Eigenpairs in (0, gamma] of the shift-invert subspace iteration against the
+    dense oracle (log-normal 3D pencil) and against the Kronecker-sum closed form
+    of the constant-coefficient 16^3 pencil (n = 3375), with B-orthonormal
+    vectors and residuals from explicit products."""
+    from closed_forms import closed_3d_cc
+    from oracle import shift_invert
+    q = pencils.scalar_q1(9, 3, 0.5, 4)
+    ev, Xd = dense.all_eigenpairs(q.A, q.B)
+    gamma = 0.5 * (ev[15] + ev[16])
+    r = shift_invert.subspace_iteration(q.A, q.B, gamma, pencils.start_block(q.n, 40, 3), tol=1e-11)
+    assert r.converged and len(r.theta) == 16
+    assert np.abs(r.theta / ev[:16] - 1).max() < 1e-12
+    assert np.abs(r.X.T @ (q.B @ r.X) - np.eye(16)).max() < 1e-12
+    assert r.rho.max() < 1e-10
+    ov = np.abs(np.sum(r.X * (q.B @ Xd[:, :16]), axis=0))
+    assert np.abs(ov - 1).max() < 1e-8
+    c = pencils.scalar_q1(16, 3)
+    lam = closed_3d_cc(16)
+    gamma = 0.5 * (lam[29] + lam[30]) if lam[30] > lam[29] * (1 + 1e-9) else None
+    k = 30
+    while gamma is None:   # next gap in the multiplet structure
+        k += 1
+        if lam[k] > lam[k - 1] * (1 + 1e-9):
+            gamma = 0.5 * (lam[k - 1] + lam[k])
+    r = shift_invert.subspace_iteration(c.A, c.B, gamma, pencils.start_block(c.n, 80, 4), tol=1e-11)
+    assert r.converged and len(r.theta) == k
+    assert np.abs(r.theta / lam[:k] - 1).max() < 1e-12
+
+
+# ---- multicolour symmetric Gauss-Seidel (the shifted-operator preconditioner of COCG) ----
+
+def _parity_colours_scalar(m, dim):
+    mi = m - 1
+    idx = np.arange(mi ** dim)
+    c = np.zeros_like(idx)
+    for a in range(dim):
+        c += ((idx // mi ** a) % mi % 2) << a
+    return c
+
+
+def test_greedy_colouring_is_the_parity_colouring():
+    """On structured grids (27-point 3D, 9-point 2D, elasticity nodes) the greedy
+    colouring in natural order is the parity colouring x%2 + 2 (y%2) + 4 (z%2):
+    8 (3D) or 4 (2D) colours, no two coupled nodes alike."""
+    for m, dim in ((7, 3), (6, 3), (9, 2)):
+        q = pencils.scalar_q1(m, dim, 0.5, 3)
+        c = krylov.greedy_colouring(q.A, q.B, 1)
+        assert np.array_equal(c, _parity_colours_scalar(m, dim))
+        C = q.A.tocoo()
+        off = C.row != C.col
+        assert np.all(c[C.row[off]] != c[C.col[off]])
+    nx = 4
+    e = pencils.elasticity_q1(nx, 3, 3, 0.25, 0.7, 0.3, (0.8, 1.2), 5)
+    c3 = krylov.greedy_colouring(e.A, e.B, 3)
+    k = np.arange(e.n // 3)
+    assert np.array_equal(c3, (k % nx) % 2 + 2 * ((k // nx) % 4 % 2) + 4 * ((k // (nx * 4)) % 2))
+
+
+@pytest.mark.parametrize("block", [1, 3])
+def test_multicolour_sgs_defining_product(block):
+    """M^{-1} r from the colour sweeps against the definition M = (D + L) D^{-1}
+    (D + U), formed densely here from S = A - sigma B and the parity colours (D:
+    couplings within a node, L / U: to lower / higher colours).  M is complex
+    symmetric; the sweeps' result solves M z = r."""
+    if block == 1:
+        q = pencils.scalar_q1(6, 3, 0.5, 3)
+        col = _parity_colours_scalar(6, 3)
+    else:
+        q = pencils.elasticity_q1(4, 3, 3, 0.25, 0.7, 0.3, (0.8, 1.2), 5)
+        k = np.arange(q.n // 3)
+        col = (k % 4) % 2 + 2 * ((k // 4) % 4 % 2) + 4 * ((k // 16) % 2)
+    sig = 40.0 * (1 + 1j)
+    S = (q.A - sig * q.B).toarray()
+    node = np.arange(q.n) // block
+    cr, cc = col[node][:, None], col[node][None, :]
+    same = node[:, None] == node[None, :]
+    D, L, U = np.where(same, S, 0), np.where(cr > cc, S, 0), np.where(cr < cc, S, 0)
+    assert np.abs(S - D - L - U).max() == 0.0     # coupled nodes never share a colour
+    M = (D + L) @ np.linalg.solve(D, D + U)
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    R = np.random.default_rng(2).standard_normal((q.n, 3)) + 1j * np.random.default_rng(3).standard_normal((q.n, 3))
+    sgs = krylov.MulticolourSGS(q.A, q.B, sig, block)
+    assert np.array_equal(sgs.colour, col)
+    Z = sgs.apply(R)
+    assert np.abs(Z - np.linalg.solve(M, R)).max() < 1e-11 * np.abs(Z).max()
+
+
+def test_multicolour_sgs_on_uncoupled_nodes_is_block_jacobi():
+    """With no coupling between nodes (block-diagonal pencil) one colour holds every
+    node, L = U = 0 and M = D: the sweeps reduce to node block Jacobi."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(5)
+    Ab = rng.standard_normal((20, 3, 3))
+    Ab = np.einsum("kij,klj->kil", Ab, Ab) + 3 * np.eye(3)
+    Bb = rng.standard_normal((20, 3, 3))
+    Bb = np.einsum("kij,klj->kil", Bb, Bb) + np.eye(3)
+    A, B = sp.block_diag(list(Ab), format="csr"), sp.block_diag(list(Bb), format="csr")
+    sig = 0.8 * (1 + 1j)
+    sgs = krylov.MulticolourSGS(A, B, sig, 3)
+    assert len(sgs.order) == 1
+    R = rng.standard_normal((60, 2)) + 0j
+    ref = krylov.block_jacobi3_solve(krylov.block_jacobi3(A, B, sig), R)
+    assert np.abs(sgs.apply(R) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_cocg_sgs_real_shift_is_preconditioned_cg():
+    """With a real negative shift S is SPD and M = (D+L) D^{-1} (D+U) is SPD: COCG
+    with the multicolour SGS preconditioner is preconditioned CG, and its
+    iterates equal SciPy's CG with the same preconditioner (given here as the
+    dense inverse of M built from the definition)."""
+    import scipy.sparse.linalg as sla
+    q = pencils.scalar_q1(6, 3, 0.5, 7)
+    F = q.B @ pencils.start_block(q.n, 1, 3)
+    g = 60.0
+    S = (q.A + g * q.B).toarray()
+    col = _parity_colours_scalar(6, 3)
+    cr, cc = col[:, None], col[None, :]
+    D = np.diag(np.diag(S))
+    M = (D + np.where(cr > cc, S, 0)) @ np.linalg.solve(D, D + np.where(cr < cc, S, 0))
+    Minv = np.linalg.inv(M)
+    P = sla.LinearOperator(S.shape, matvec=lambda v: Minv @ v)
+    for k in (1, 4, 9):
+        xs = []
+        sla.cg(S, F[:, 0], x0=np.zeros(q.n), rtol=1e-30, atol=0.0, maxiter=k, M=P,
+               callback=lambda xk: xs.append(xk.copy()))
+        x, it, fl, _ = krylov.cocg(q.A, q.B, [-g + 0j], F, 0.0, k, fixed_iters=k, precond="mcsgs")
+        assert len(xs) == k
+        assert np.abs(x[:, 0] - xs[-1]).max() < 1e-11 * np.abs(xs[-1]).max()
+
+
+@pytest.mark.parametrize("pc,make", [("mcsgs", lambda: pencils.scalar_q1(8, 3, 0.5, 5)),
+                                     ("mcsgs3", lambda: pencils.elasticity_q1(4, 3, 3, 0.25, 0.7, 0.3,
+                                                                             (0.8, 1.2), 5))])
+def test_cocg_sgs_converges_to_direct_solution_in_fewer_iterations(pc, make):
+    q = make()
+    F = q.B @ pencils.start_block(q.n, 2, 4)
+    sig = np.array([30.0 * (1 + 1j), 90.0 * (1 + 1j)])
+    x, it, fl, rr = krylov.cocg(q.A, q.B, sig, F, 1e-12, 3000, precond=pc)
+    assert set(fl.tolist()) == {krylov.CONVERGED}
+    for j, s in enumerate(sig):
+        y = oflt.shifted_solve(q.A, q.B, s, F)
+        assert np.abs(x[:, 2 * j:2 * j + 2] - y).max() < 1e-9 * np.abs(y).max()
+    _, itj, _, _ = krylov.cocg(q.A, q.B, sig, F, 1e-12, 3000, precond="jacobi" if pc == "mcsgs" else "bjac3")
+    assert it.mean() < itj.mean()
