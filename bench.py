@@ -50,7 +50,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "eigenpairs/s at rel. residual 1e-8, mixed vs FP64; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_c2_pmc.txt")
+# FP32 FMA without packed (two-wide) instructions, which this build does not emit:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz; FP64 FMA runs at the same rate
+FP32_NONPACKED_TFS = 78.6
+FP64_TFS = 78.6
+def pmc_summary_path(wl_key):
+    return os.path.join(ROOT, "profiles", f"spmm_{wl_key}_pmc.txt")
 KERNEL_SOURCES = ["krylov.hip", "device_util.h", "kernels.h"]
 COPY_BYTES = 1 << 30      # the calibration copy reads and writes 1 GiB
 
@@ -59,7 +64,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, probe=False):
     import pencils
     if name == "c2":
         p = pencils.c2_scalar3d()
@@ -70,12 +75,13 @@ def workload(name):
                           "N=6 SLRF poles alpha=1 beta=0.01; point Jacobi"))
     if name == "c3":
         p = pencils.c3_elasticity()
-        return dict(pencil=p, gamma=101.0, L=256, N=8, expect=None, precond=3, stepwise=True,
+        g = c3_golden(required=not probe)
+        return dict(pencil=p, gamma=g["gamma"], L=256, N=8, expect=g["count"], precond=3,
+                    eigs=g["eigenvalues"],
                     desc=("3D linear elasticity, trilinear hex, 48^3 free nodes x 3 dofs, clamped x=0 face, "
                           "Young's modulus log-normal sigma=0.7 seed 3, nu=0.3, density U[0.8,1.2] "
-                          f"(n={p.n}, nnz={p.A.nnz}); gamma=101 (about 200 eigenvalues: the 200th "
-                          "eigenvalue of the 12^3 and 16^3 meshes extrapolated in h^2); L=256; N=8 SLRF poles "
-                          "alpha=1 beta=0.01; node 3x3 block Jacobi"))
+                          f"(n={p.n}, nnz={p.A.nnz}); gamma={g['gamma']:.6g} ({g['count']} eigenvalues by "
+                          "the oracle, mid-gap); L=256; N=8 SLRF poles alpha=1 beta=0.01"))
     if name == "c1":
         import numpy as np
         p = pencils.c1_string()
@@ -88,36 +94,110 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wl, sig, solve_stats):
-    """Oracle inner solver of the workload (BiCGStab or COCG, FP64, the workload's
-    preconditioner) on 1 pole x 4 columns for a fixed number of iterations, single
-    thread; scaled by the column-iterations of the GPU solve."""
+def c3_golden(required=True):
+    """gamma, count and eigenvalues of the elasticity pencil stored by
+    tests/golden/make_golden.py (the oracle's shift-invert subspace iteration).
+    The counter probe, which checks no result, may run without them."""
+    path = os.path.join(ROOT, "tests", "golden", "eig_elast3d_48_s3.json")
+    if not os.path.exists(path) and not required:
+        return {"gamma": 101.0, "count": None, "eigenvalues": []}
+    with open(path) as f:
+        return json.load(f)
+
+
+def c2_golden():
+    with open(os.path.join(ROOT, "tests", "golden", "eig_scalar3d_m64_ln0.5_s2_g421.json")) as f:
+        return json.load(f)
+
+
+_SAMPLE = {}
+
+
+def _sample_worker(task):
+    """One oracle sample in a forked worker (the pencil is inherited): COCG or
+    BiCGStab iterations on a few columns, or B-orthonormalisation projections,
+    or residual products.  Returns the seconds it took."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     import pencils
-    from oracle import krylov
+    from oracle import krylov, subspace
+    from threadpoolctl import threadpool_limits
+    wl, sig = _SAMPLE["wl"], _SAMPLE["sig"]
     p = wl["pencil"]
-    # about 15 s of host work: 100 iterations on the 64^3 scalar pencil, scaled by nnz
-    cols = 4
-    iters = max(10, min(200, int(100 * 6.5e6 / max(p.A.nnz, 1))))
-    pc = "bjac3" if wl.get("precond", 0) == 3 else "jacobi"
-    F = p.B @ pencils.start_block(p.n, cols, 77)
-    cocg = wl.get("solver", 0) == 1
-    solve = krylov.cocg if cocg else krylov.bicgstab
+    kind, k = task
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        solve(p.A, p.B, sig[:1], F, 0.0, iters, fixed_iters=iters, precond=pc)
-        dt = time.perf_counter() - t0
-    per_col_it = dt / (cols * iters)
-    col_its = solve_stats["spmv_total"] / (1.0 if cocg else 2.0)   # products per iteration
-    est = per_col_it * col_its
-    return {"value": solve_stats["n_found"] / est, "unit": "eigenpairs/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"oracle.krylov.{solve.__name__} (FP64, {pc}) on 1 pole x {cols} columns for "
-                       f"{iters} iterations took {dt:.1f} s on 1 host thread; scaled to the "
-                       f"{col_its:.0f} column-iterations of one GPU solve (Rayleigh-Ritz excluded)"),
-            "seconds_per_column_iteration": per_col_it}
+        if kind == "inner":
+            pc = "bjac3" if wl.get("precond", 0) == 3 else "jacobi"
+            F = p.B @ pencils.start_block(p.n, _SAMPLE["cols"], 77 + k)
+            solve = krylov.cocg if wl.get("solver", 0) == 1 else krylov.bicgstab
+            solve(p.A, p.B, sig[k % len(sig):k % len(sig) + 1], F, 0.0, _SAMPLE["iters"],
+                  fixed_iters=_SAMPLE["iters"], precond=pc)
+        elif kind == "mgs":
+            subspace.mgs_b(pencils.start_block(p.n, _SAMPLE["mgs_cols"], 99 + k), p.B)
+        else:
+            X = pencils.start_block(p.n, _SAMPLE["res_cols"], 55 + k)
+            subspace.relative_residuals(p.A, p.B, X, np.ones(X.shape[1]))
+        return time.perf_counter() - t0
+
+
+def cpu_sample(wl, sig):
+    """Times a bounded sample of the FP64 oracle on the host's cores before the GPU
+    is touched (the workers are forked from this process): P workers, each
+    running the oracle's inner solver (the workload's preconditioner) on one pole
+    x `cols` columns for `iters` iterations, then the oracle's B-orthonormalising
+    Gram-Schmidt on a few columns and its residual products.  The oracle is
+    single-threaded per call (SciPy sparse products), so the host's cores are
+    used by running the independent samples side by side."""
+    import multiprocessing as mp
+    import platform
+    ncpu = os.cpu_count() or 1
+    P = max(1, min(ncpu, 16))
+    big = wl["pencil"].A.nnz > 1e7
+    _SAMPLE.update(wl=wl, sig=sig, cols=4, iters=4 if big else 12, mgs_cols=6, res_cols=16)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor()
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        inner = pool.map(_sample_worker, [("inner", k) for k in range(P)])
+        mgs = pool.map(_sample_worker, [("mgs", k) for k in range(P)])
+        res = pool.map(_sample_worker, [("res", k) for k in range(P)])
+    wall = time.perf_counter() - t0
+    c, it, m, rc = _SAMPLE["cols"], _SAMPLE["iters"], _SAMPLE["mgs_cols"], _SAMPLE["res_cols"]
+    # per unit of work, with P workers sharing the host: seconds of wall time per unit
+    return {"workers": P, "host_cpus": ncpu, "cpu_model": model, "wall_seconds": wall,
+            "s_per_column_iteration": max(inner) / (P * c * it),
+            # mgs_b on m columns: 2 passes of m (m - 1) / 2 projections and 2 m norms,
+            # each one product with B: m (m + 3) products
+            "s_per_b_product": max(mgs) / (P * m * (m + 3)),
+            "s_per_residual_column": max(res) / (P * rc),
+            "sample": (f"{P} forked workers on {ncpu} host CPUs ({model}): oracle inner solver on 1 pole x {c} "
+                       f"columns x {it} iterations each, oracle.subspace.mgs_b on {m} columns each, "
+                       f"oracle.subspace.relative_residuals on {rc} columns each; {wall:.1f} s wall")}
+
+
+def cpu_baseline(smp, solve_stats, L):
+    """Scales the oracle sample to one complete solve of the workload: the GPU
+    solve's column-iterations (products with A - sigma B), plus per outer
+    iteration the oracle's two-pass B-Gram-Schmidt of the L filtered columns
+    (L (L + 3) products with B) and its residuals of the L Ritz pairs."""
+    outer = solve_stats["outer_iterations"]
+    col_its = solve_stats["spmv_total"]
+    est = (col_its * smp["s_per_column_iteration"] + outer * L * (L + 3) * smp["s_per_b_product"]
+           + outer * L * smp["s_per_residual_column"])
+    return {"value": solve_stats["n_found"] / est, "unit": "eigenpairs/s", "cores": smp["workers"],
+            "kind": "oracle", "host_cpus": smp["host_cpus"], "cpu_model": smp["cpu_model"],
+            "sample": smp["sample"] + (f"; scaled to one solve: {col_its} column-iterations, {outer} outer "
+                                       f"iterations of Gram-Schmidt and residuals on L={L} columns"),
+            "estimated_solve_seconds": est}
 
 
 def kernel_source_hash():
@@ -128,12 +208,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_pmc_summary():
+def read_pmc_summary(wl_key):
     """key: value lines of the committed counter summary, or None."""
-    if not os.path.exists(PMC_SUMMARY):
+    path = pmc_summary_path(wl_key)
+    if not os.path.exists(path):
         return None
     d = {}
-    with open(PMC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("#") or ":" not in line:
                 continue
@@ -142,12 +223,12 @@ def read_pmc_summary():
     return d
 
 
-def hbm_traffic(dtype, avg_alg_bytes, family="bicgstab"):
+def hbm_traffic(dtype, avg_alg_bytes, family="bicgstab", workload_key="c2"):
     """HBM bytes per launch of the sparse product from the counter summary, scaled
     from the probe's full-width launches to launches that average avg_alg_bytes
     algorithmic bytes (converged tiles are skipped); None if the summary is
     missing or the kernel sources changed since it was taken."""
-    d = read_pmc_summary()
+    d = read_pmc_summary(workload_key)
     if not d or d.get("source_sha256") != kernel_source_hash():
         return None, "no counter summary for the current kernel sources"
     key = dtype if family == "bicgstab" else f"{family} {dtype}"
@@ -156,15 +237,17 @@ def hbm_traffic(dtype, avg_alg_bytes, family="bicgstab"):
     full_traffic = float(d[f"full_launch_traffic_bytes {key}"])
     full_alg = float(d[f"full_launch_algorithmic_bytes {key}"])
     return full_traffic * avg_alg_bytes / full_alg, (
-        f"{PMC_SUMMARY.split(os.sep)[-2]}/{os.path.basename(PMC_SUMMARY)}: FETCH_SIZE + WRITE_SIZE per "
+        f"profiles/{os.path.basename(pmc_summary_path(workload_key))}: FETCH_SIZE + WRITE_SIZE per "
         f"full-width launch {full_traffic / 1e9:.3f} GB vs algorithmic {full_alg / 1e9:.3f} GB, "
         "scaled by the timed launches' mean algorithmic bytes")
 
 
-def counters_probe():
+def counters_probe(wl_key):
     """Short run for the rocprofv3 counter passes: a 1 GiB copy kernel (reads and
-    writes COPY_BYTES) and full-width launches of the sparse product on the 64^3
-    scalar pencil (fixed BiCGStab iterations, no column converges)."""
+    writes COPY_BYTES) and full-width launches of the sparse product on the
+    workload (fixed inner iterations, no column converges): BiCGStab and COCG in
+    both precisions on the 64^3 scalar pencil, COCG in FP32 (the benchmark's
+    form) on the elasticity pencil."""
     import torch
 
     import paper_2503_21618_amd as slrf
@@ -175,26 +258,30 @@ def counters_probe():
     torch.cuda.synchronize()
     del a, b
     log("copy kernel done")
-    wl = workload("c2")
+    wl = workload(wl_key, probe=True)
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
     X = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
-    for solver, family in ((slrf.SOLVER_BICGSTAB, "bicgstab"), (slrf.SOLVER_COCG, "cocg")):
-        for prec, dtype in ((slrf.MIXED, "float"), (slrf.FP64, "double")):
-            opt = slrf.default_options(profile=1, precision=prec, inner_tol=0.0, inner_maxit=3, check_every=3,
-                                       solver=solver)
-            s = slrf.Solver(p.A, p.B, max_L=wl["L"], max_poles=wl["N"], options=opt)
-            U, st = s.filter_apply(X, sig, w)
-            torch.cuda.synchronize()
-            print(json.dumps({"family": family, "dtype": dtype, "spmm_launches": st["spmm_launches"],
-                              "full_launch_algorithmic_bytes": st["spmm_bytes"] / st["spmm_launches"]}),
-                  flush=True)
+    sgs_pc = slrf.PRECOND_SGS if wl_key == "c2" else slrf.PRECOND_SGS3
+    forms = ([(slrf.SOLVER_BICGSTAB, "bicgstab", slrf.MIXED, "float"), (slrf.SOLVER_BICGSTAB, "bicgstab", slrf.FP64, "double"),
+              (slrf.SOLVER_COCG, "cocg", slrf.MIXED, "float"), (slrf.SOLVER_COCG, "cocg", slrf.FP64, "double")]
+             if wl_key == "c2" else [(slrf.SOLVER_COCG, "cocg", slrf.MIXED, "float")])
+    forms.append((slrf.SOLVER_COCG, "sgs", slrf.MIXED, "float"))
+    for solver, family, prec, dtype in forms:
+        opt = slrf.default_options(profile=1, precision=prec, inner_tol=0.0, inner_maxit=3, check_every=3,
+                                   solver=solver, precond=sgs_pc if family == "sgs" else wl.get("precond", 0))
+        s = slrf.Solver(p.A, p.B, max_L=wl["L"], max_poles=wl["N"], options=opt)
+        U, st = s.filter_apply(X, sig, w)
+        torch.cuda.synchronize()
+        print(json.dumps({"family": family, "dtype": dtype, "spmm_launches": st["spmm_launches"],
+                          "full_launch_algorithmic_bytes": st["spmm_bytes"] / st["spmm_launches"]}),
+              flush=True)
         s.close()
         del s, U
         torch.cuda.empty_cache()
 
 
-def summarize_pmc(fetch_csv, write_csv, probe_log):
+def summarize_pmc(fetch_csv, write_csv, probe_log, wl_key="c2"):
     """Prints the counter summary (key: value lines) from the two rocprofv3 CSVs
     and the probe's own output (algorithmic bytes per full launch)."""
     def per_kernel(path, counter):
@@ -206,9 +293,11 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
                 name = row["Kernel_Name"]
                 m = re.search(r"k_spmm_([vt])<(float|double)", name)
                 mc = re.search(r"k_cocg_spmm<(float|double)", name)
+                ms = re.search(r"k_sgs_sweep<(float|double), \d+, (\d+)>", name)
                 key = ("copy" if "elementwise" in name and "neg" in name else
                        f"k_spmm_{m.group(1)}<{m.group(2)}>" if m else
-                       f"k_cocg_spmm<{mc.group(1)}>" if mc else None)
+                       f"k_cocg_spmm<{mc.group(1)}>" if mc else
+                       f"k_sgs_sweep<{ms.group(1)}>" if ms and ms.group(2) in ("0", "2") else None)
                 if key:
                     acc.setdefault(key, []).append(float(row["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
@@ -223,16 +312,18 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
     kib = COPY_BYTES / 1024.0
     ff = fe["copy"][0] / kib
     fw = wr["copy"][0] / kib
+    what = ("3D scalar vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768)" if wl_key == "c2" else
+            "3D elasticity pencil 48^3 nodes x 3 (n=331776, 81 nnz/row), L=256, N=8 (K=2048)")
     print("# HBM traffic of the complex-shifted sparse products (BiCGStab: k_spmm_v, k_spmm_t; COCG:")
-    print("# k_cocg_spmm), 3D scalar vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768),")
+    print(f"# k_cocg_spmm), {what},")
     print("# full-width launches.")
     print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
-    print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|elementwise\" --output-format csv "
-          "-d R/gpurun_out/pmc_fetch -o run -- python3 R/bench.py --counters-probe")
-    print("#   rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|elementwise\" --output-format csv "
-          "-d R/gpurun_out/pmc_write -o run -- python3 R/bench.py --counters-probe")
+    print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|k_sgs_sweep|elementwise\" --output-format csv "
+          f"-d R/gpurun_out/pmc_fetch -o run -- python3 R/bench.py --counters-probe --workload {wl_key}")
+    print("#   rocprofv3 --pmc WRITE_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|k_sgs_sweep|elementwise\" --output-format csv "
+          f"-d R/gpurun_out/pmc_write -o run -- python3 R/bench.py --counters-probe --workload {wl_key}")
     print("#   python3 bench.py --summarize-pmc R/gpurun_out/pmc_fetch/run_counter_collection.csv "
-          "R/gpurun_out/pmc_write/run_counter_collection.csv <probe stdout>")
+          f"R/gpurun_out/pmc_write/run_counter_collection.csv <probe stdout> --workload {wl_key}")
     print("# Counter values are KiB per dispatch; each is divided by the value the same counter")
     print("# reads for a copy kernel that reads and writes 1 GiB (torch.neg on 2^27 doubles).")
     print(f"source_sha256: {kernel_source_hash()}")
@@ -240,7 +331,8 @@ def summarize_pmc(fetch_csv, write_csv, probe_log):
     print(f"copy WRITE_SIZE KiB: {wr['copy'][0]:.0f}")
     print(f"copy_fetch_factor: {ff:.4f}")
     print(f"copy_write_factor: {fw:.4f}")
-    for family, kerns in (("bicgstab", ("k_spmm_v<{}>", "k_spmm_t<{}>")), ("cocg", ("k_cocg_spmm<{}>",))):
+    for family, kerns in (("bicgstab", ("k_spmm_v<{}>", "k_spmm_t<{}>")), ("cocg", ("k_cocg_spmm<{}>",)),
+                          ("sgs", ("k_sgs_sweep<{}>",))):
         for dtype in ("float", "double"):
             if (family, dtype) not in alg or any(k.format(dtype) not in fe for k in kerns):
                 continue
@@ -526,6 +618,83 @@ def many_line(args, kind, out, desc):
     return line
 
 
+def check_against_oracle(wl, evals, n_found, tol):
+    """The eigenvalues a solve returned against the oracle's (tests/golden):
+    count and largest relative error; raises if either is off."""
+    import numpy as np
+    ev = np.asarray(wl.get("eigs") or [])
+    if not len(ev):
+        return None
+    if n_found != len(ev):
+        raise SystemExit(f"found {n_found} eigenpairs, the oracle has {len(ev)}")
+    rel = float(np.abs(np.asarray(evals[:n_found]) / ev - 1).max())
+    if rel > tol:
+        raise SystemExit(f"eigenvalues differ from the oracle's by {rel:.2e} (> {tol:.0e})")
+    return rel
+
+
+def run_outer_steps(slrf, wl, precision, steps, warmup, sig, w, V0):
+    """A step is one outer iteration of Algorithm 1 on the workload: the filter
+    application (every shifted solve of the N poles x L columns, in the mixed
+    form with its FP64 defect corrections), the filter sum, Rayleigh-Ritz and the
+    residuals (slrf_batch_step on a one-pencil batch).  Solves run back to back:
+    when one converges its eigenvalues are checked against the oracle's and the
+    next starts from the same start block (slrf_batch_restart; the pencil's
+    upload happens once, before the first step).  Each step is bracketed by
+    device synchronisations; `value` counts the eigenpairs of the solves that
+    ran entirely inside the K timed steps, over the time of their steps."""
+    import torch
+    p = wl["pencil"]
+    L, N, gamma = wl["L"], wl["N"], wl["gamma"]
+    tag = "mixed" if precision == slrf.MIXED else "fp64"
+    opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
+                               solver=wl.get("solver", 0), recycle=wl.get("recycle", 0))
+    pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, options=opt)
+    ws = pers + trans + (1 << 24)
+    log(f"{tag}: n={p.n} L={L} N={N} workspace {ws / 2**30:.2f} GiB (one-pencil batch)")
+    b = slrf.Batch(ws, trans, max_poles=N, options=opt)
+    pid = b.add(p.A, p.B, gamma, L, sig, w, V0=V0)
+    torch.cuda.synchronize()
+    times, solves, cur = [], [], []
+    ks_keys = ("spmm_seconds", "spmm_launches", "spmm_bytes", "spmm_columns", "update_seconds",
+               "update_launches", "update_bytes")
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        act = b.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        timed = k >= warmup
+        times.append(dt if timed else None)
+        cur.append(k)
+        log(f"{tag} {'step' if timed else 'warmup'} {k - warmup if timed else k}: {dt:.2f} s, "
+            f"solve {len(solves)} outer {len(cur)}")
+        if act == 0:
+            r = b.result(pid)
+            if r.status != 0 or (wl["expect"] is not None and r.n_found != wl["expect"]):
+                raise SystemExit(f"{tag} solve failed: status {r.status} found {r.n_found} ({r.message})")
+            rel = check_against_oracle(wl, r.evals, r.n_found, 1e-8 if precision == slrf.MIXED else 1e-10)
+            solves.append(dict(steps=cur, result=r, rel=rel))
+            log(f"{tag} solve {len(solves)} done: {r.n_found} pairs, outer {r.stats['outer_iterations']}, "
+                f"max rho {r.stats['max_resid']:.2e}, max rel eig err vs oracle {rel}")
+            cur = []
+            b.restart(pid, V0)
+    torch.cuda.synchronize()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    full = [sv for sv in solves if all(times[i] is not None for i in sv["steps"])]
+    if not full:
+        raise SystemExit(f"no complete solve inside the {steps} timed steps: raise --steps")
+    t_full = sum(times[i] for sv in full for i in sv["steps"])
+    found = sum(sv["result"].n_found for sv in full)
+    ks = {k: sum(sv["result"].stats["kernels"][k] for sv in full) for k in ks_keys}
+    t_all = sum(t for t in times if t is not None)
+    return dict(value=found / t_full, dt=t_all, results=[sv["result"] for sv in full], ks=ks,
+                solve_seconds=t_full / len(full), complete_solves=len(full),
+                max_rel_eig_err=max(sv["rel"] for sv in full))
+
+
 def run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0):
     """As run_form, through the batch API with the one pencil, so that every outer
     iteration reports (a solve of the elasticity workload takes minutes)."""
@@ -533,10 +702,10 @@ def run_form_stepwise(slrf, wl, precision, steps, warmup, sig, w, V0):
     p = wl["pencil"]
     L, N, gamma = wl["L"], wl["N"], wl["gamma"]
     tag = "mixed" if precision == slrf.MIXED else "fp64"
-    pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, precision)
-    ws = pers + trans + (1 << 24)
     opt = slrf.default_options(profile=1, precision=precision, precond=wl.get("precond", 0),
                                solver=wl.get("solver", 0), recycle=wl.get("recycle", 0))
+    pers, trans = slrf.batch_footprint(p.n, union_nnz(p), L, N, options=opt)
+    ws = pers + trans + (1 << 24)
     log(f"{tag}: n={p.n} L={L} N={N} workspace {ws / 2**30:.2f} GiB (one-pencil batch)")
 
     def solve():
@@ -613,12 +782,130 @@ def run_form(slrf, wl, precision, steps, warmup, sig, w, V0):
     return dict(value=found / dt, dt=dt, results=results, ks=ks)
 
 
+def roofline_fields(ks, kname, kdtype, spmm_flops):
+    """The dominant kernel's rates from the timed launches: algorithmic HBM bytes
+    and flops per second.  The bound is the roof the kernel is closer to."""
+    secs = max(ks["spmm_seconds"], 1e-30)
+    gbs = ks["spmm_bytes"] / secs / 1e9
+    tfs = spmm_flops / secs / 1e12
+    peak_tf = FP32_NONPACKED_TFS if kdtype == "float" else FP64_TFS
+    out = {"achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+           "achieved_TFLOPs": tfs, "frac_alu": tfs / peak_tf, "alu_peak_TFLOPs": peak_tf,
+           "kernel": f"{kname} <{kdtype}> (complex-shifted sparse product)",
+           "launches": ks["spmm_launches"],
+           "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
+           "algorithmic_bytes_per_launch": ks["spmm_bytes"] / max(1, ks["spmm_launches"]),
+           "algorithmic_flops_per_launch": spmm_flops / max(1, ks["spmm_launches"])}
+    if out["frac_alu"] >= out["frac_hbm"]:
+        out.update(bound="alu", achieved=tfs, peak=peak_tf, unit="TFLOP/s", frac=tfs / peak_tf)
+    else:
+        out.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
+    return out
+
+
+def spmm_flops_per_column(p):
+    """Algorithmic flops of the complex-shifted product (A - sigma B) x for one
+    complex column over all rows: 4 flops per stored nonzero of A and of B (a
+    real coefficient times a complex value, accumulated) and 8 per row for
+    a - sigma b."""
+    import numpy as np
+    return 4.0 * (np.count_nonzero(p.A.data) + np.count_nonzero(p.B.data)) + 8.0 * p.n
+
+
+def main_c3(slrf, args):
+    """The default line: the elasticity workload (the largest single pencil, the
+    mixed-precision configuration), a step per outer iteration; the 64^3 scalar
+    workload's mixed and FP64 solves beside it."""
+    import numpy as np
+    import pencils
+    steps = 20 if args.steps is None else args.steps
+    warmup = 5 if args.warmup is None else args.warmup
+    wl = workload("c3")
+    wl["solver"] = 0 if args.solver == "bicgstab" else 1
+    wl["recycle"] = 0 if args.recycle == "0" or wl["solver"] == 0 else 1
+    if wl["solver"] == 1 and args.precond == "sgs":
+        wl["precond"] = slrf.PRECOND_SGS3
+    p = wl["pencil"]
+    sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
+    smp = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline sample (before the GPU is used)...")
+        smp = cpu_sample(wl, sig)
+        log(smp["sample"])
+    import torch
+    V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
+    m = run_outer_steps(slrf, wl, slrf.MIXED, steps, warmup, sig, w, V0)
+    del V0
+    ks = m["ks"]
+    res = m["results"]
+    sgs = wl.get("precond") == slrf.PRECOND_SGS3
+    kname = ("k_sgs_sweep (backward + forward colour sweeps: the product with S of an iteration)" if sgs else
+             "k_cocg_spmm" if wl["solver"] == 1 else "k_spmm_v / k_spmm_t")
+    spmm_flops = spmm_flops_per_column(p) * ks["spmm_columns"]
+    roof = roofline_fields(ks, kname, "float", spmm_flops)
+    traffic, note = hbm_traffic("float", roof["algorithmic_bytes_per_launch"],
+                                "sgs" if sgs else "cocg" if wl["solver"] == 1 else "bicgstab", workload_key="c3")
+    roof["traffic"] = traffic
+    roof["traffic_note"] = note
+    upd_gbs = ks["update_bytes"] / ks["update_seconds"] / 1e9
+    last = res[-1].stats
+    pcname = {3: "node 3x3 block Jacobi", 5: "multicolour node-block symmetric Gauss-Seidel"}[wl["precond"]]
+    prec = ("complex FP32 inner solves + FP64 defect correction and Rayleigh-Ritz; inner solver "
+            + ("COCG, warm starts across outer iterations" if wl["solver"] == 1 else "BiCGStab")
+            + "; preconditioner " + pcname)
+    out = {
+        "metric": METRIC, "value": m["value"], "unit": "eigenpairs/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * m["dt"] / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"] + "; " + prec,
+                   "step": "one outer iteration of Algorithm 1; value from the complete solves inside the "
+                           "timed steps"},
+        "roofline": roof,
+        "vector_updates": {"achieved_GBs": upd_gbs, "frac": upd_gbs / HBM_PEAK_GBS,
+                           "avg_launch_ms": 1e3 * ks["update_seconds"] / max(1, ks["update_launches"])},
+        "solve": {"seconds": m["solve_seconds"], "complete_solves_timed": m["complete_solves"],
+                  "max_rel_eig_err_vs_oracle": m["max_rel_eig_err"],
+                  **{k: last[k] for k in ("outer_iterations", "spmv_total", "n_found", "max_resid",
+                                          "inner_iterations", "filter_seconds")}},
+    }
+    if not args.no_c2:
+        c2 = workload("c2")
+        c2["eigs"] = c2_golden()["eigenvalues"]
+        c2["solver"], c2["recycle"] = 1, 1
+        c2["precond"] = slrf.PRECOND_SGS if args.precond == "sgs" else slrf.PRECOND_JACOBI
+        s2, w2, _ = slrf.design_poles(c2["N"], 1.0, 0.01, c2["gamma"])
+        V2 = torch.from_numpy(pencils.start_block(c2["pencil"].n, c2["L"], 1)).cuda()
+        legs = {}
+        for tag, prec2, st2, wu2 in (("mixed", slrf.MIXED, 1, 1), ("fp64", slrf.FP64, 1, 0)):
+            f = run_form(slrf, dict(c2, recycle=1 if prec2 == slrf.MIXED else 0), prec2, st2, wu2, s2, w2, V2)
+            r = f["results"][-1]
+            rel = check_against_oracle(c2, r.evals, r.n_found, 1e-8 if prec2 == slrf.MIXED else 1e-10)
+            fk = f["ks"]
+            legs[tag] = {"value": f["value"], "seconds": f["dt"], "outer_iterations": r.stats["outer_iterations"],
+                         "n_found": r.n_found, "max_resid": r.stats["max_resid"], "max_rel_eig_err_vs_oracle": rel,
+                         "spmm_GBs": fk["spmm_bytes"] / fk["spmm_seconds"] / 1e9,
+                         "update_GBs": fk["update_bytes"] / fk["update_seconds"] / 1e9}
+        out["c2_64cube"] = {"workload": c2["desc"].replace("; point Jacobi", "") + "; COCG; " +
+                            ("multicolour symmetric Gauss-Seidel" if args.precond == "sgs" else "point Jacobi"), **legs,
+                            "mixed_over_fp64": legs["mixed"]["value"] / legs["fp64"]["value"]}
+    if smp is not None:
+        out["cpu_baseline"] = cpu_baseline(smp, last, wl["L"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 outer iterations for c3, 1 solve otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 5 for c3, 1 otherwise)")
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-c2", action="store_true", help="c3: skip the 64^3 mixed and FP64 legs")
+    ap.add_argument("--precond", default="sgs", choices=["sgs", "jacobi"],
+                    help="shifted-operator preconditioner of the COCG workloads: multicolour symmetric "
+                         "Gauss-Seidel (point, or node blocks for elasticity) or (node block) Jacobi")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--recycle", default="auto", choices=["auto", "0", "1"],
                     help="warm starts across outer iterations (mixed precision); auto: with COCG")
@@ -647,7 +934,7 @@ def main():
                     help="print the counter summary from two rocprofv3 CSVs")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, wl_key=args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the pole-sharded "
@@ -655,7 +942,7 @@ def main():
         sys.exit(2)
 
     if args.counters_probe:
-        counters_probe()
+        counters_probe(args.workload)
         return
 
     import torch
@@ -687,6 +974,13 @@ def main():
                 f"{', warm starts' if args.recycle != '0' and args.solver != 'bicgstab' else ''}")
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
+    if args.workload == "c3":
+        main_c3(slrf, args)
+        return
+    if args.steps is None:
+        args.steps = 1
+    if args.warmup is None:
+        args.warmup = 1
     wl = workload(args.workload)
     symmetric = args.workload != "c1"          # C1 runs ILU(0), which COCG does not take
     wl["solver"] = 1 if args.solver == "cocg" or (args.solver == "auto" and symmetric) else 0

@@ -78,7 +78,18 @@ typedef struct {
                           2 ILU(0) on the merged pattern (requires nnz <= 5 n)
                           3 node block Jacobi for three unknowns per node (unknowns
                             3k, 3k+1, 3k+2 form node k; requires n divisible by 3):
-                            M_j = blockdiag of the 3x3 node blocks of A - sigma_j B */
+                            M_j = blockdiag of the 3x3 node blocks of A - sigma_j B
+                          4 multicolour symmetric Gauss-Seidel (COCG only):
+                            M_j = (D + L) D^{-1} (D + U) with D the diagonal of
+                            A - sigma_j B and L / U its couplings to unknowns of lower /
+                            higher colour in a greedy colouring of the pattern's
+                            graph (natural order; the parity classes on structured
+                            grids); applied in the split form with one backward and one
+                            forward colour sweep per iteration
+                          5 the same with the 3x3 node blocks as D (n divisible by 3)
+                          The shifted operator preconditioner of Section 4.2 is an ILU
+                          (drop tolerance 1e-4) with RCM ordering; 4 and 5 are
+                          symmetric stand-ins whose sweeps run in parallel. */
   int32_t profile;     /* 1: time the sparse-product and vector-update kernels with HIP
                           events and count the column tiles each launch processes
                           (stats fields spmm_* and update_*); 0: off */
@@ -131,6 +142,7 @@ typedef struct {
   double spmm_seconds;
   int64_t spmm_launches;
   double spmm_bytes;
+  double spmm_columns;      /* columns those launches multiplied (each over all n rows) */
   double update_seconds;
   int64_t update_launches;
   double update_bytes;
@@ -260,6 +272,13 @@ slrf_status slrf_batch_footprint(int64_t n, int64_t nnz_union, int64_t L, int32_
                                  int32_t precision, size_t* persistent_bytes,
                                  size_t* transient_bytes);
 
+/* The same for the precision and preconditioner of opt (NULL: defaults); a
+ * batch whose options select the multicolour SGS preconditioner (precond 4 or
+ * 5) sizes its pencils with this one. */
+slrf_status slrf_batch_footprint_for(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
+                                     const slrf_options* opt, size_t* persistent_bytes,
+                                     size_t* transient_bytes);
+
 /* d_workspace: device, 256-byte aligned, ws_bytes >= arena_bytes + 2 KiB; the
  * rest after the arena becomes the pool.  max_poles: largest N of any pencil
  * (1..16).  opt may be NULL.  On failure *out may hold a batch: read
@@ -292,6 +311,13 @@ slrf_status slrf_batch_query(slrf_batch b, int32_t id, int32_t* done, int32_t* o
  * return value is that pencil's final status. */
 slrf_status slrf_batch_result(slrf_batch b, int32_t id, int64_t* n_found, double* h_evals,
                               double* d_evecs, double* h_resid, slrf_solve_stats* stats);
+
+/* Starts the pencil's solve again from the start block d_V0 (device (n, L), or
+ * NULL for the seeded Gaussian block), with its gamma, L and poles, keeping the
+ * pencil's device data: the next slrf_batch_step runs its first outer
+ * iteration.  Its previous result is discarded (warm starts begin afresh).  A
+ * stream of solves of one pencil then needs no new slrf_batch_add. */
+slrf_status slrf_batch_restart(slrf_batch b, int32_t id, const double* d_V0);
 
 /* Frees the pencil's pool space; the id becomes invalid. */
 slrf_status slrf_batch_remove(slrf_batch b, int32_t id);

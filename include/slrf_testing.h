@@ -23,6 +23,14 @@ int slrf_test_gram(int64_t n, int64_t L, const double* U, const double* WA, cons
 int slrf_test_gemm(int64_t n, int64_t L, int64_t r, const double* X, const double* Z, double* Y,
                    void* hip_stream);
 
+/* The Gram products with a choice of arithmetic: f32 = 0 FP64 MFMA
+ * (v_mfma_f64_16x16x4), f32 = 1 FP32 MFMA (v_mfma_f32_16x16x4, inputs rounded to
+ * FP32, FP32 accumulation), the first projection of a mixed-precision outer
+ * iteration while its Ritz pairs are far from converged. */
+int slrf_test_gram_prec(int64_t n, int64_t L, const double* U, const double* WA, const double* WB,
+                        double* GA, double* GB, void* scratch, size_t scratch_bytes, int f32,
+                        void* hip_stream);
+
 /* Bytes of scratch slrf_test_gram needs. */
 size_t slrf_test_gram_scratch(int64_t n, int64_t L);
 

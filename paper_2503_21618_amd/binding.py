@@ -21,6 +21,7 @@ _lib = C.CDLL(LIB_PATH)
 
 FP64, MIXED = 0, 1
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_ILU0, PRECOND_BLOCK3 = 0, 1, 2, 3
+PRECOND_SGS, PRECOND_SGS3 = 4, 5   # multicolour symmetric Gauss-Seidel, point / node blocks (COCG)
 SOLVER_BICGSTAB, SOLVER_COCG = 0, 1
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_NOT_SPD", 3: "E_WORKSPACE", 4: "E_DEVICE",
           5: "E_NOT_CONVERGED", 6: "E_SUBSPACE_TOO_SMALL", 7: "E_BREAKDOWN"}
@@ -44,6 +45,7 @@ class FilterStats(C.Structure):
                 ("n_breakdown", C.c_int32), ("n_maxit", C.c_int32), ("refinements", C.c_int32),
                 ("max_relres", C.c_double), ("seconds", C.c_double),
                 ("spmm_seconds", C.c_double), ("spmm_launches", C.c_int64), ("spmm_bytes", C.c_double),
+                ("spmm_columns", C.c_double),
                 ("update_seconds", C.c_double), ("update_launches", C.c_int64),
                 ("update_bytes", C.c_double)]
 
@@ -82,6 +84,8 @@ _lib.slrf_last_error.argtypes = [_P]
 _lib.slrf_last_error.restype = C.c_char_p
 _lib.slrf_batch_footprint.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+_lib.slrf_batch_footprint_for.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.POINTER(Options),
+                                          C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
 _lib.slrf_batch_create.argtypes = [C.POINTER(_P), _P, C.c_size_t, C.c_size_t, C.c_int32,
                                    C.POINTER(Options), _P]
 _lib.slrf_batch_add.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_double, C.c_int64,
@@ -91,19 +95,24 @@ _lib.slrf_batch_query.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER
 _lib.slrf_batch_result.argtypes = [_P, C.c_int32, C.POINTER(C.c_int64), _P, _P, _P,
                                    C.POINTER(SolveStats)]
 _lib.slrf_batch_remove.argtypes = [_P, C.c_int32]
+_lib.slrf_batch_restart.argtypes = [_P, C.c_int32, _P]
 _lib.slrf_batch_destroy.argtypes = [_P]
 _lib.slrf_batch_last_error.argtypes = [_P]
 _lib.slrf_batch_last_error.restype = C.c_char_p
 for _f in ("slrf_design_poles", "slrf_workspace_bytes", "slrf_workspace_bytes_for", "slrf_create",
            "slrf_filter_apply",
-           "slrf_solve_interval", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
-           "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove"):
+           "slrf_solve_interval", "slrf_batch_footprint", "slrf_batch_footprint_for", "slrf_batch_create",
+           "slrf_batch_add",
+           "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove",
+           "slrf_batch_restart"):
     getattr(_lib, _f).restype = C.c_int
 
 _lib.slrf_test_gram.argtypes = [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
 _lib.slrf_test_gram.restype = C.c_int
 _lib.slrf_test_gemm.argtypes = [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P]
 _lib.slrf_test_gemm.restype = C.c_int
+_lib.slrf_test_gram_prec.argtypes = [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_size_t, C.c_int, _P]
+_lib.slrf_test_gram_prec.restype = C.c_int
 _lib.slrf_test_gram_scratch.argtypes = [C.c_int64, C.c_int64]
 _lib.slrf_test_gram_scratch.restype = C.c_size_t
 
@@ -111,22 +120,24 @@ EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_quadrature_poles"
             "slrf_workspace_bytes_for",
             "slrf_create",
             "slrf_filter_apply", "slrf_solve_interval", "slrf_destroy", "slrf_status_string",
-            "slrf_last_error", "slrf_batch_footprint", "slrf_batch_create", "slrf_batch_add",
+            "slrf_last_error", "slrf_batch_footprint", "slrf_batch_footprint_for", "slrf_batch_create",
+            "slrf_batch_add",
             "slrf_batch_step", "slrf_batch_query", "slrf_batch_result", "slrf_batch_remove",
-            "slrf_batch_destroy", "slrf_batch_last_error"]
-TESTING_EXPORTED = ["slrf_test_gram", "slrf_test_gemm", "slrf_test_gram_scratch"]
+            "slrf_batch_restart", "slrf_batch_destroy", "slrf_batch_last_error"]
+TESTING_EXPORTED = ["slrf_test_gram", "slrf_test_gemm", "slrf_test_gram_prec", "slrf_test_gram_scratch"]
 
 
-def test_gram(U, WA, WB):
-    """Kernel-level hook: (U^T WA, U^T WB) by the library's MFMA Gram kernel."""
+def test_gram(U, WA, WB, f32: bool = False):
+    """Kernel-level hook: (U^T WA, U^T WB) by the library's MFMA Gram kernel
+    (f32: the FP32 MFMA variant)."""
     import torch
     n, L = U.shape
     GA = torch.empty((L, L), dtype=torch.float64, device=U.device)
     GB = torch.empty_like(GA)
     nb = _lib.slrf_test_gram_scratch(n, L)
     scratch = torch.empty(max(nb, 8), dtype=torch.uint8, device=U.device)
-    st = _lib.slrf_test_gram(n, L, *[C.c_void_p(t.data_ptr()) for t in (U, WA, WB, GA, GB, scratch)],
-                             nb, C.c_void_p(torch.cuda.current_stream(U.device).cuda_stream))
+    st = _lib.slrf_test_gram_prec(n, L, *[C.c_void_p(t.data_ptr()) for t in (U, WA, WB, GA, GB, scratch)],
+                                  nb, 1 if f32 else 0, C.c_void_p(torch.cuda.current_stream(U.device).cuda_stream))
     if st:
         raise SlrfError(st, "test_gram")
     return GA, GB
@@ -243,16 +254,25 @@ class Solver:
     """A context over one pencil (A, B) with a workspace sized for (max_L, max_poles)."""
 
     def __init__(self, A, B, max_L: int, max_poles: int, options: Options | None = None,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, workspace=None):
+        """workspace: a caller-owned uint8 tensor on the device of at least
+        workspace_bytes(...) bytes (default: one is allocated); the context uses
+        it until close()."""
         import torch
         self.torch = torch
         self.n, nnz, arrs = _csr_arrays(A, B)
         self.device = torch.device(device)
         self.options = options or default_options()
-        self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, options=self.options)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._h = C.c_void_p()
+        self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, options=self.options)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        elif (workspace.dtype != torch.uint8 or workspace.device != self.device
+              or not workspace.is_contiguous() or workspace.numel() < self.ws_bytes):
+            raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device} "
+                             f"of at least {self.ws_bytes} bytes")
+        self.workspace = workspace
         st = _lib.slrf_create(C.byref(self._h), self.n, *[_ptr(a) for a in arrs],
                               C.c_void_p(self.workspace.data_ptr()), self.ws_bytes, max_L, max_poles,
                               C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
@@ -322,10 +342,14 @@ class Solver:
         return SolveResult(st, evals, evecs, resid, nf.value, stats.as_dict(), msg)
 
 
-def batch_footprint(n: int, nnz: int, L: int, N: int, precision: int = FP64):
-    """(persistent, transient) device bytes of one pencil in a Batch."""
+def batch_footprint(n: int, nnz: int, L: int, N: int, precision: int = FP64, options: Options | None = None):
+    """(persistent, transient) device bytes of one pencil in a Batch (with options:
+    for their precision and preconditioner; precision is then ignored)."""
     p, t = C.c_size_t(), C.c_size_t()
-    st = _lib.slrf_batch_footprint(n, nnz, L, N, precision, C.byref(p), C.byref(t))
+    if options is None:
+        st = _lib.slrf_batch_footprint(n, nnz, L, N, precision, C.byref(p), C.byref(t))
+    else:
+        st = _lib.slrf_batch_footprint_for(n, nnz, L, N, C.byref(options), C.byref(p), C.byref(t))
     if st:
         raise SlrfError(st, "batch footprint")
     return p.value, t.value
@@ -424,6 +448,18 @@ class Batch:
                                     _ptr(resid), C.byref(stats))
         msg = self.last_error() if st else ""
         return SolveResult(st, evals, evecs, resid, nf.value, stats.as_dict(), msg)
+
+    def restart(self, pid: int, V0=None):
+        """Solve the pencil again from V0 (device (n, L) or host array; None: the
+        seeded Gaussian block), keeping its device data."""
+        v0 = None
+        if V0 is not None:
+            t = self.torch
+            v0 = V0 if isinstance(V0, t.Tensor) else t.as_tensor(np.ascontiguousarray(V0, dtype=np.float64))
+            v0 = v0.to(device=self.device, dtype=t.float64).contiguous()
+        st = _lib.slrf_batch_restart(self._h, pid, C.c_void_p(v0.data_ptr()) if v0 is not None else None)
+        if st:
+            raise SlrfError(st, self.last_error())
 
     def remove(self, pid: int):
         st = _lib.slrf_batch_remove(self._h, pid)

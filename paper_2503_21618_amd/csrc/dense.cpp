@@ -148,7 +148,7 @@ bool sym_eig(int n, double* A, double* w, double* V) {
   return true;
 }
 
-bool projected_pencil(int L, const double* GA, const double* GB, double* theta, double* Z) {
+bool projected_pencil(int L, const double* GA, const double* GB, double* theta, double* Z, double floor_rel) {
   for (int i = 0; i < L * L; ++i)
     if (!std::isfinite(GA[i]) || !std::isfinite(GB[i])) return false;
   std::vector<double> s(L), B((size_t)L * L), lam(L), V((size_t)L * L), T((size_t)L * L),
@@ -163,7 +163,7 @@ bool projected_pencil(int L, const double* GA, const double* GB, double* theta, 
   if (!sym_eig(L, B.data(), lam.data(), V.data())) return false;
   const double lmax = lam[L - 1];
   if (!(lmax > 0)) return false;
-  const double floor_ = 1e-15 * lmax;
+  const double floor_ = floor_rel * lmax;
   // T = diag(s) V diag(max(lam, floor)^-1/2)
   for (int i = 0; i < L; ++i)
     for (int j = 0; j < L; ++j)

@@ -8,8 +8,12 @@ namespace slrf {
 bool sym_eig(int n, double* A, double* w, double* V);
 
 // Ritz values theta (ascending) and coefficients Z (L x L row-major) of the
-// projected pencil (GA, GB): Z^T GB Z = I, Z^T GA Z = diag(theta).
-bool projected_pencil(int L, const double* GA, const double* GB, double* theta, double* Z);
+// projected pencil (GA, GB): Z^T GB Z = I, Z^T GA Z = diag(theta).  floor_rel:
+// eigenvalues of the unit-diagonal GB below floor_rel times its largest are
+// raised to that floor (1e-15 for FP64 Gram matrices; about the Gram's own
+// rounding level when it was accumulated in a lower precision).
+bool projected_pencil(int L, const double* GA, const double* GB, double* theta, double* Z,
+                      double floor_rel = 1e-15);
 
 // SLRF design at gamma = 1 (see slrf.h): xi[N] sorted, omega[2N] (re, im).
 bool design_poles_unit(int N, double alpha, double beta, double* xi, double* omega);

@@ -55,6 +55,24 @@ struct Inst {
   const int* diagpos;           // position of each row's diagonal (ILU)
   const void* ilu;              // (N, nnz) cx<R> ILU(0) factors, or null
   const void* bjac;             // (N, n/3, 3, 3) cx<R> inverted node blocks, or null
+  // Multicolour symmetric Gauss-Seidel (COCG only): sgs = block size (1 point, 3
+  // node blocks) or 0.  Nodes of colour c are sgs_nodes[sgs_cptr[c] .. sgs_cptr[c+1]);
+  // the couplings of each row to nodes of lower (l*) and higher (u*) colours form
+  // two CSR matrices with (a, b) pairs in the Krylov precision.  sgsR holds R with
+  // D = R R^T for each pole's diagonal block D of A - sigma B (point: (n, N) at
+  // Inst::dn like d; blocks: (N, n/3, 3, 3) row-major), sgsD the node blocks D
+  // (blocks only; point pencils use d), bjac their inverses (blocks; point: dinv).
+  int sgs, sgs_ncol;
+  const int* sgs_cptr;
+  const int* sgs_nodes;
+  const int* lrp;
+  const int* lcol;
+  const void* lab;
+  const int* urp;
+  const int* ucol;
+  const void* uab;
+  const void* sgsR;
+  const void* sgsD;
 };
 
 // Column order of a pencil's blocks.  Pole-major (rmaj = 0): column c = j L + l
@@ -85,6 +103,8 @@ struct Batch {
   int rows_per_block;
   int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
   int groups;             // sparse-product row mode: 1 stencil groups, 2 node triples, 0 neither
+  int sgs;                // multicolour SGS block size of the batch's pencils (0 none, 1, 3)
+  int sgs_ncol;           // most colours of any pencil (sweeps launch once per colour)
 };
 
 // Krylov vectors: base pointers of the concatenated per-pencil blocks; per
@@ -130,9 +150,10 @@ struct LaunchTimer {
     int kind;           // 0 sparse product, 1 vector update
     double tile_bytes;  // bytes of a launch that processes every tile (scale with tiles)
     double fixed;       // bytes read once per launch whatever the tiles (merged CSR)
+    double share;       // share of one product with S a full-width launch performs
   };
   Rec recs[512];
-  int* begin(hipStream_t s, int kind, double tile_bytes, double fixed);
+  int* begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share = 1.0);
   void end(hipStream_t s);
 };
 
@@ -142,6 +163,8 @@ struct IterBytes {
   double rhat;     // the (n, L) real blocks
   double diag;     // the (n, N) diagonal blocks
   double matrix;   // every merged CSR once
+  double sgs_lower, sgs_upper;  // the lower / upper coupling CSRs once (multicolour SGS)
+  double sgs_blocks;            // R, D and D^{-1} of every pole once (multicolour SGS)
 };
 
 // ---- batched Krylov launchers (stream-ordered) ----------------------------
@@ -160,7 +183,15 @@ template <typename R>
 void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st);
 template <typename R>
 void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
-                           LaunchTimer* timer, const IterBytes& bytes);
+                           bool first, LaunchTimer* timer, const IterBytes& bytes);
+// Batches with multicolour SGS (Batch::sgs) run COCG on the split system
+// W y' = f', W = M_L^{-1} S M_L^{-T}, M_L = (D + L) R^{-T}, f' = M_L^{-1} f: the
+// start transforms r = f into f' (forward colour sweeps), each iteration forms
+// q = W p by one backward and one forward sweep (Eisenstat: no separate product
+// with S), and launch_sgs_finish turns x = y' into y = M_L^{-T} y' (backward
+// sweeps) for every column.
+template <typename R>
+void launch_sgs_finish(hipStream_t s, const Batch& b, const KrylovState<R>& st);
 // out[0] = number of active columns; rebuilds the active-tile list of the batch.
 void launch_count_active(hipStream_t s, const Batch& b, const int* flags, int* out);
 
@@ -202,9 +233,10 @@ template <typename R>
 void launch_spmm_real(hipStream_t s, int n, int L, const int* rowptr, const int* col,
                       const ab_pair<R>* ab, const double* X, double* AX, double* BX);
 
-// Gram matrices GA = U^T WA, GB = U^T WB (L x L), FP64 MFMA, deterministic.
+// Gram matrices GA = U^T WA, GB = U^T WB (L x L), FP64 MFMA (f32: FP32 MFMA on
+// the inputs rounded to FP32, FP32 accumulation), deterministic.
 void launch_gram(hipStream_t s, int n, int L, const double* U, const double* WA,
-                 const double* WB, double* part, int nchunks, double* GA, double* GB);
+                 const double* WB, double* part, int nchunks, double* GA, double* GB, bool f32 = false);
 int gram_chunks(int n, int L);
 
 // Y_b = X_b Z for b < nb blocks (n x L times L x r), FP64 MFMA.

@@ -134,12 +134,41 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// FP32 variant: v_mfma_f32_16x16x4f32 (FP32 inputs, FP32 accumulation), used
+// for the Gram products of the first of the two projections while the Ritz
+// pairs are still far from converged.  Its 16 x 16 accumulator puts row 4 (l / 16) + q, column l % 16 in
+// lane l's element q (the FP64 instruction: row l / 16 + 4 q).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <bool F32>
+struct Mfma;
+template <>
+struct Mfma<false> {
+  using acc_t = d4;
+  using in_t = double;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) { return mfma64(a, b, c); }
+  static __device__ __forceinline__ int row(int li, int q) { return li + 4 * q; }
+};
+template <>
+struct Mfma<true> {
+  using acc_t = f4;
+  using in_t = float;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int li, int q) { return 4 * li + q; }
+};
+
 // Partial Gram matrices over a chunk of rows: GA = U^T WA, GB = U^T WB.
 // A workgroup covers a 128 (rows of G) x 64 (columns of G) region; wavefront w
-// covers 64 x 32 of it as 4 x 2 tiles of 16 x 16, for both products.
+// covers 64 x 32 of it as 4 x 2 tiles of 16 x 16, for both products.  F32: the
+// FP64 inputs are rounded to FP32 as they are loaded.
+template <bool F32>
 __global__ __launch_bounds__(WG) void k_gram(int n, int L, const double* __restrict__ U,
                                             const double* __restrict__ WA, const double* __restrict__ WB,
                                             int rows_per_chunk, double* __restrict__ part) {
+  using M = Mfma<F32>;
+  using T = typename M::in_t;
   const int chunk = blockIdx.x;
   const int nbb = (L + 63) / 64;
   const int ba = blockIdx.y / nbb, bb = blockIdx.y % nbb;
@@ -147,38 +176,38 @@ __global__ __launch_bounds__(WG) void k_gram(int n, int L, const double* __restr
   const int a0 = ba * 128 + (w >> 1) * 64;
   const int b0 = bb * 64 + (w & 1) * 32;
   const int li = lane >> 4, lj = lane & 15;
-  d4 accA[4][2], accB[4][2];
+  typename M::acc_t accA[4][2], accB[4][2];
 #pragma unroll
   for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
     for (int tb = 0; tb < 2; ++tb) {
-      accA[ta][tb] = d4{0, 0, 0, 0};
-      accB[ta][tb] = d4{0, 0, 0, 0};
+      accA[ta][tb] = typename M::acc_t{0, 0, 0, 0};
+      accB[ta][tb] = typename M::acc_t{0, 0, 0, 0};
     }
   const int i0 = chunk * rows_per_chunk;
   const int i1 = min(n, i0 + rows_per_chunk);
   for (int i = i0; i < i1; i += 4) {
     const int row = i + li;
     const bool rv = row < i1;
-    double a[4], xa[2], xb[2];
+    T a[4], xa[2], xb[2];
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta) {
       const int cidx = a0 + 16 * ta + lj;
-      a[ta] = (rv && cidx < L) ? U[(size_t)row * L + cidx] : 0.0;
+      a[ta] = (T)((rv && cidx < L) ? U[(size_t)row * L + cidx] : 0.0);
     }
 #pragma unroll
     for (int tb = 0; tb < 2; ++tb) {
       const int cidx = b0 + 16 * tb + lj;
       const bool ok = rv && cidx < L;
-      xa[tb] = ok ? WA[(size_t)row * L + cidx] : 0.0;
-      xb[tb] = ok ? WB[(size_t)row * L + cidx] : 0.0;
+      xa[tb] = (T)(ok ? WA[(size_t)row * L + cidx] : 0.0);
+      xb[tb] = (T)(ok ? WB[(size_t)row * L + cidx] : 0.0);
     }
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
       for (int tb = 0; tb < 2; ++tb) {
-        accA[ta][tb] = mfma64(a[ta], xa[tb], accA[ta][tb]);
-        accB[ta][tb] = mfma64(a[ta], xb[tb], accB[ta][tb]);
+        accA[ta][tb] = M::op(a[ta], xa[tb], accA[ta][tb]);
+        accB[ta][tb] = M::op(a[ta], xb[tb], accB[ta][tb]);
       }
   }
   const size_t LL = (size_t)L * L;
@@ -190,11 +219,11 @@ __global__ __launch_bounds__(WG) void k_gram(int n, int L, const double* __restr
     for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int ga = a0 + 16 * ta + li + 4 * q;
+        const int ga = a0 + 16 * ta + M::row(li, q);
         const int gb = b0 + 16 * tb + lj;
         if (ga < L && gb < L) {
-          pA[(size_t)ga * L + gb] = accA[ta][tb][q];
-          pB[(size_t)ga * L + gb] = accB[ta][tb][q];
+          pA[(size_t)ga * L + gb] = (double)accA[ta][tb][q];
+          pB[(size_t)ga * L + gb] = (double)accB[ta][tb][q];
         }
       }
 }
@@ -220,11 +249,14 @@ int gram_chunks(int n, int /*L*/) {
 }
 
 void launch_gram(hipStream_t s, int n, int L, const double* U, const double* WA, const double* WB,
-                 double* part, int nchunks, double* GA, double* GB) {
+                 double* part, int nchunks, double* GA, double* GB, bool f32) {
   int rows = (n + nchunks - 1) / nchunks;
   rows = (rows + 3) / 4 * 4;
   const int tiles = ((L + 127) / 128) * ((L + 63) / 64);
-  k_gram<<<dim3(nchunks, tiles), dim3(WG), 0, s>>>(n, L, U, WA, WB, rows, part);
+  if (f32)
+    k_gram<true><<<dim3(nchunks, tiles), dim3(WG), 0, s>>>(n, L, U, WA, WB, rows, part);
+  else
+    k_gram<false><<<dim3(nchunks, tiles), dim3(WG), 0, s>>>(n, L, U, WA, WB, rows, part);
   const size_t tot = 2 * (size_t)L * L;
   k_gram_reduce<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(L, nchunks, part, GA, GB);
 }
@@ -238,6 +270,8 @@ struct GemmBlocks {
 
 __global__ __launch_bounds__(WG) void k_gemm_nz(int n, int L, int r, GemmBlocks gb,
                                                const double* __restrict__ Z) {
+  using M = Mfma<false>;
+  using T = typename M::in_t;
   const double* __restrict__ X = gb.X[blockIdx.y];
   double* __restrict__ Y = gb.Y[blockIdx.y];
   const int w = wave_id(), lane = lane_id();
@@ -245,27 +279,27 @@ __global__ __launch_bounds__(WG) void k_gemm_nz(int n, int L, int r, GemmBlocks 
   const int row0 = blockIdx.x * 64 + w * 16;
   if (row0 >= n) return;
   for (int c0 = 0; c0 < r; c0 += 128) {
-    d4 acc[8];
+    typename M::acc_t acc[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = d4{0, 0, 0, 0};
+    for (int t = 0; t < 8; ++t) acc[t] = typename M::acc_t{0, 0, 0, 0};
     for (int k0 = 0; k0 < L; k0 += 4) {
       const int row = row0 + lj;
       const int k = k0 + li;
-      const double a = (row < n && k < L) ? X[(size_t)row * L + k] : 0.0;
+      const T a = (T)((row < n && k < L) ? X[(size_t)row * L + k] : 0.0);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int cc = c0 + 16 * t + lj;
-        const double b = (k < L && cc < r) ? Z[(size_t)k * r + cc] : 0.0;
-        acc[t] = mfma64(a, b, acc[t]);
+        const T b = (T)((k < L && cc < r) ? Z[(size_t)k * r + cc] : 0.0);
+        acc[t] = M::op(a, b, acc[t]);
       }
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = row0 + li + 4 * q;
+        const int row = row0 + M::row(li, q);
         const int cc = c0 + 16 * t + lj;
-        if (row < n && cc < r) Y[(size_t)row * r + cc] = acc[t][q];
+        if (row < n && cc < r) Y[(size_t)row * r + cc] = (double)acc[t][q];
       }
   }
 }

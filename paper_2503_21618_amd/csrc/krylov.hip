@@ -165,8 +165,10 @@ __device__ __forceinline__ void wg_store_partial_cx(const cx<R> (&v)[V], int w, 
 // leaves them), then CH gathers of 16 B per lane are issued back to back, then
 // the FMAs.  Entries past the row end get zero coefficients and re-read the
 // row's own column; lanes past K read a clamped column (both stay in bounds;
-// their contributions are discarded).
-template <typename R, int V, int CH>
+// their contributions are discarded).  PZ: the re-read values are replaced by
+// zeros as well, for gathers from a vector whose own row may not be written yet
+// (a colour sweep), where 0 times leftover bits could be NaN.
+template <typename R, int V, int CH, bool PZ = false>
 __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
                                                   const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V]) {
   static_assert(CH <= kCsrPad, "chunk longer than the CSR padding");
@@ -190,6 +192,11 @@ __device__ __forceinline__ cvec<R, V> shifted_row(int i, cptr<int> rowptr, cptr<
     cvec<R, V> x[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
+    if constexpr (PZ) {
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (kb + u >= k1) x[u] = cvec<R, V>{};
+    }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
 #pragma unroll
@@ -268,8 +275,9 @@ constexpr int kNodeChunk = 8;
 // for the three rows: a third of the gathers of three generic rows.  Entries
 // are taken in chunks of kNodeChunk (the CSR padding covers the overrun of the
 // last chunk; entries past the row end get zero coefficients and re-read row
-// i0); each row's entries are summed in entry order, as in shifted_row.
-template <typename R, int V>
+// i0, whose values PZ replaces by zeros as in shifted_row); each row's entries
+// are summed in entry order, as in shifted_row.
+template <typename R, int V, bool PZ = false>
 __device__ __forceinline__ void shifted_node(int i0, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
                                              const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V],
                                              cvec<R, V> (&q)[kNodeRows]) {
@@ -287,6 +295,11 @@ __device__ __forceinline__ void shifted_node(int i0, cptr<int> rowptr, cptr<int>
     cvec<R, V> x[kNodeChunk];
 #pragma unroll
     for (int u = 0; u < kNodeChunk; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
+    if constexpr (PZ) {
+#pragma unroll
+      for (int u = 0; u < kNodeChunk; ++u)
+        if (j + u >= m) x[u] = cvec<R, V>{};
+    }
 #pragma unroll
     for (int r = 0; r < kNodeRows; ++r) {
 #pragma unroll
@@ -1094,9 +1107,9 @@ __global__ __launch_bounds__(WG) void k_bjac_apply(Batch b, const int* __restric
   }
 }
 
-int* LaunchTimer::begin(hipStream_t s, int kind, double tile_bytes, double fixed) {
+int* LaunchTimer::begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share) {
   if (used >= capacity || used >= 512) return nullptr;
-  recs[used] = {kind, tile_bytes, fixed};
+  recs[used] = {kind, tile_bytes, fixed, share};
   (void)hipEventRecord(events[2 * used], s);
   return d_counts + used;
 }
@@ -1323,7 +1336,19 @@ __global__ __launch_bounds__(WG) void k_mixed_rhs(Batch b, const cx<double>* __r
   const WgPos p = wg_pos(b.G);
   FOR_TILES(b, p, V)
     float nn[V] = {};
-    if (valid && tile_open<V>(scale, cg0, cl0, I.K)) {
+    const bool open = valid && tile_open<V>(scale, cg0, cl0, I.K);
+    if (valid && !open && b.sgs) {
+      // multicolour SGS recomputes the start values of every tile from r: a tile
+      // whose columns all met their targets starts from r = 0, x = 0 (elsewhere
+      // its columns simply start converged and keep their old vectors)
+      FOR_ROWS(b, p, I)
+        const size_t e = tb + (size_t)pos * (WAVE * V);
+        const cvec<float, V> z{};
+        stv<float, V>(st.r + e, z);
+        stv<float, V>(st.x + e, z);
+      END_ROWS
+    }
+    if (open) {
       double inv[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -1568,7 +1593,7 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
         pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
         alpha[v] = f[v] == COL_ACTIVE ? st.alpha[cg0 + v] : cx<R>{0, 0};
       }
-      if (I.bjac) {  // node block Jacobi: one node per wavefront step
+      if (I.bjac && !I.sgs) {  // node block Jacobi: one node per wavefront step
         for (int k = blockIdx.x * 4 + p.w; k < I.n / 3; k += b.G * 4) {
           const size_t e0 = tb + (size_t)(3 * k) * (WAVE * V);
           cvec<R, V> x[3], r[3], pv[3], q[3], z[3];
@@ -1627,7 +1652,8 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
             x[u].c[v] = cadd(x[u].c[v], cmul(alpha[v], pv[u].c[v]));
             const cx<R> rv = csub(r[u].c[v], cmul(alpha[v], q[u].c[v]));
             r[u].c[v] = rv;
-            const cx<R> t = cmul(rv, cmul(st.dinv[de + pole[v]], rv));
+            // split system of the multicolour SGS: no further preconditioner, [r, r]
+            const cx<R> t = I.sgs ? cmul(rv, rv) : cmul(rv, cmul(st.dinv[de + pole[v]], rv));
             rz[v].re += t.re;
             rz[v].im += t.im;
             nn[v] += rv.re * rv.re + rv.im * rv.im;
@@ -1736,15 +1762,316 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R>
   }
 }
 
+// ---- multicolour symmetric Gauss-Seidel, split (Eisenstat) form ---------------
+//
+// M = (D + L) D^{-1} (D + U) with D the point or node blocks of S = A - sigma B
+// and L / U its couplings to nodes of lower / higher colour.  With D = R R^T
+// (complex symmetric factor) M = M_L M_L^T, M_L = (D + L) R^{-T}, and COCG runs
+// on W y' = M_L^{-1} f with W = M_L^{-1} S M_L^{-T} (complex symmetric).  Since
+// S = (D + L) + (D + U) - D,
+//   W p = R^T (t + u),  t = (D + U)^{-1} R p,  u = (D + L)^{-1} (R p - D t),
+// one backward and one forward sweep: each touches every coupling once, so an
+// iteration reads the pattern once, as one product with S would.  A sweep runs
+// one launch per colour (the nodes of a colour are not coupled); node k of
+// colour c gathers t (backward) or u (forward) of the already finished colours.
+//   start:  u = (D + L)^{-1} f, r' = R^T u, rho = [r', r'], ||f'|| = ||r'||
+//   iteration: p = r' + beta p (first: p = r'), backward and forward sweeps give
+//           q = W p and [p, q]; alpha; x' += alpha p, r' -= alpha q; beta
+//   finish: y = (D + U)^{-1} R x'
+// The partial sums of the forward sweeps are accumulated over the colour
+// launches in the workgroup's slot (fixed order: bitwise reproducible).
+constexpr int kSgsBackIter = 0, kSgsBackFinal = 1, kSgsFwdIter = 2, kSgsFwdStart = 3;
+
+template <typename T, int V>
+__device__ __forceinline__ void wg_acc_partial(const T (&v)[V], int w, int lane, int cl0, int K, T* out, bool add) {
+  __shared__ T red[4][V * WAVE];
+#pragma unroll
+  for (int u = 0; u < V; ++u) red[w][V * lane + u] = v[u];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = V * lane + u;
+      if (cl0 + u < K) out[k] = (add ? out[k] : T(0)) + (red[0][k] + red[1][k] + red[2][k] + red[3][k]);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int V>
+__device__ __forceinline__ void wg_acc_partial_cx(const cx<R> (&v)[V], int w, int lane, int cl0, int K, cx<R>* out,
+                                                  bool add) {
+  R re[V], im[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    re[u] = v[u].re;
+    im[u] = v[u].im;
+  }
+  __shared__ R rr[4][V * WAVE], ri[4][V * WAVE];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    rr[w][V * lane + u] = re[u];
+    ri[w][V * lane + u] = im[u];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = V * lane + u;
+      if (cl0 + u < K) {
+        const cx<R> o = add ? out[k] : cx<R>{0, 0};
+        out[k] = {o.re + (rr[0][k] + rr[1][k] + rr[2][k] + rr[3][k]), o.im + (ri[0][k] + ri[1][k] + ri[2][k] + ri[3][k])};
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// y_i = sum_j m_ij x_j (TR: m_ji) for a BS x BS block of one column
+template <typename R, int BS, bool TR>
+__device__ __forceinline__ void blk_apply(const cx<R>* __restrict__ m, const cx<R> (&x)[BS], cx<R> (&y)[BS]) {
+#pragma unroll
+  for (int i = 0; i < BS; ++i) {
+    cx<R> acc{0, 0};
+#pragma unroll
+    for (int j = 0; j < BS; ++j) acc = cadd(acc, cmul(m[TR ? BS * j + i : BS * i + j], x[j]));
+    y[i] = acc;
+  }
+}
+
+// The couplings of node k's rows to the other colours' nodes, applied to the
+// gathered block G (the lower or the upper CSR): acc_r = sum_j S_{row r, j} G_j.
+template <typename R, int V, int BS>
+__device__ __forceinline__ void sgs_couplings(const Inst& I, int k, const int* rp, const int* cl, const void* abv,
+                                              const cx<R>* __restrict__ Gc, const cx<R> (&sig)[V],
+                                              cvec<R, V> (&acc)[BS]) {
+  const cptr<int> rowptr = as_const(rp), col = as_const(cl);
+  const cptr<ab_pair<R>> ab = as_const(static_cast<const ab_pair<R>*>(abv));
+  if constexpr (BS == 3) {
+    if (I.nodes && as_const(I.nodes)[k] != 0) {
+      shifted_node<R, V, true>(3 * k, rowptr, col, ab, Gc, WAVE * V, sig, acc);
+      return;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      acc[r] = shifted_row<R, V, kChunkShared<R>, true>(3 * k + r, rowptr, col, ab, Gc, WAVE * V, sig);
+  } else {
+    acc[0] = shifted_row<R, V, kChunk, true>(k, rowptr, col, ab, Gc, WAVE * V, sig);
+  }
+}
+
+// Per-column diagonal-block data of node k: R, D and D^{-1} for the column's pole.
+template <typename R, int BS>
+struct SgsBlocks {
+  const cx<R>* Rm;
+  const cx<R>* Dm;
+  const cx<R>* Di;
+};
+
+template <typename R, int BS>
+__device__ __forceinline__ SgsBlocks<R, BS> sgs_blocks(const Inst& I, const KrylovState<R>& st, int k, int pole) {
+  if constexpr (BS == 3) {
+    const size_t o = ((size_t)pole * (size_t)(I.n / 3) + (size_t)k) * 9;
+    return {static_cast<const cx<R>*>(I.sgsR) + o, static_cast<const cx<R>*>(I.sgsD) + o,
+            static_cast<const cx<R>*>(I.bjac) + o};
+  } else {
+    const size_t o = I.dn + (size_t)k * I.N + pole;
+    return {static_cast<const cx<R>*>(I.sgsR) + o, st.d + o, st.dinv + o};
+  }
+}
+
+template <typename R, int BS, int MODE>
+__global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st, int colour, int add, int first,
+                                                     int* counter) {
+  constexpr int V = LaneWidth<R>::V;
+  constexpr bool all_tiles = MODE == kSgsBackFinal || MODE == kSgsFwdStart;
+  constexpr bool fwd = MODE == kSgsFwdIter || MODE == kSgsFwdStart;
+  const WgPos p = wg_pos(b.G);
+  FOR_TILE_LIST(b, p, V, all_tiles ? b.n_tiles : as_const((const int*)b.n_active)[0],
+                all_tiles ? ti_ : as_const((const int*)b.active)[ti_])
+    cx<R> da[V] = {};
+    R db[V] = {};
+    const bool go = colour < I.sgs_ncol &&
+                    (all_tiles || tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE));
+    if (go) {
+      count_tile(counter);
+      int f[V], pole[V];
+      cx<R> sig[V], beta[V];
+      lane_flags<V>(st.flags, cg0, cl0, I.K, f);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
+        sig[v] = st.sigma_col[cg0 + v];
+        beta[v] = st.beta[cg0 + v];
+      }
+      const cptr<int> cptr_ = as_const(I.sgs_cptr);
+      const int c0 = cptr_[colour], c1 = cptr_[colour + 1];
+      // a contiguous share of the colour's nodes per workgroup, XCD by XCD
+      const int per = (c1 - c0 + b.G - 1) / b.G;
+      const int q0 = c0 + (p.x * p.per + p.q) * per, q1 = min(c1, q0 + per);
+      const cptr<int> nodes = as_const(I.sgs_nodes);
+      for (int q = q0 + p.w; q < q1; q += 4) {
+        const int k = nodes[q];
+        const size_t e0 = tb + (size_t)(BS * k) * (WAVE * V);
+        cvec<R, V> own[BS], two[BS], acc[BS];
+        // own: the vector the sweep transforms; two: t (forward iteration)
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+          const size_t e = e0 + (size_t)i * (WAVE * V);
+          if (MODE == kSgsBackIter) {
+            const cvec<R, V> rv = ldv<R, V>(st.r + e);
+            cvec<R, V> pv = first ? rv : ldv<R, V>(st.ph + e);
+            if (!first) {
+#pragma unroll
+              for (int v = 0; v < V; ++v)
+                if (f[v] == COL_ACTIVE) pv.c[v] = cadd(rv.c[v], cmul(beta[v], pv.c[v]));
+            }
+            own[i] = pv;
+          } else if (MODE == kSgsBackFinal) {
+            own[i] = ldv<R, V>(st.x + e);
+          } else if (MODE == kSgsFwdIter) {
+            own[i] = ldv<R, V>(st.ph + e);
+            two[i] = ldv<R, V>(st.t + e);
+          } else {
+            own[i] = ldv<R, V>(st.r + e);
+          }
+        }
+        if (fwd)
+          sgs_couplings<R, V, BS>(I, k, I.lrp, I.lcol, I.lab, st.sh + tb, sig, acc);
+        else
+          sgs_couplings<R, V, BS>(I, k, I.urp, I.ucol, I.uab, st.t + tb, sig, acc);
+        cvec<R, V> res[BS], out2[BS];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const SgsBlocks<R, BS> m = sgs_blocks<R, BS>(I, st, k, pole[v]);
+          cx<R> x[BS], w[BS], y[BS];
+#pragma unroll
+          for (int i = 0; i < BS; ++i) x[i] = own[i].c[v];
+          if (MODE == kSgsFwdStart) {
+#pragma unroll
+            for (int i = 0; i < BS; ++i) w[i] = x[i];
+          } else {
+            blk_apply<R, BS, false>(m.Rm, x, w);  // R p (R x')
+          }
+          if (MODE == kSgsFwdIter) {
+            cx<R> tv[BS], dt[BS];
+#pragma unroll
+            for (int i = 0; i < BS; ++i) tv[i] = two[i].c[v];
+            blk_apply<R, BS, false>(m.Dm, tv, dt);
+#pragma unroll
+            for (int i = 0; i < BS; ++i) w[i] = csub(w[i], dt[i]);
+          }
+#pragma unroll
+          for (int i = 0; i < BS; ++i) w[i] = csub(w[i], acc[i].c[v]);
+          blk_apply<R, BS, false>(m.Di, w, y);  // t or u
+#pragma unroll
+          for (int i = 0; i < BS; ++i) res[i].c[v] = y[i];
+          if (MODE == kSgsFwdIter || MODE == kSgsFwdStart) {
+            cx<R> z[BS], o[BS];
+#pragma unroll
+            for (int i = 0; i < BS; ++i) z[i] = MODE == kSgsFwdIter ? cadd(two[i].c[v], y[i]) : y[i];
+            blk_apply<R, BS, true>(m.Rm, z, o);  // R^T (t + u) or R^T u
+#pragma unroll
+            for (int i = 0; i < BS; ++i) {
+              out2[i].c[v] = o[i];
+              if (cl0 + v < I.K) {
+                const cx<R> a = MODE == kSgsFwdIter ? x[i] : o[i];
+                const cx<R> pq = cmul(a, o[i]);
+                da[v].re += pq.re;
+                da[v].im += pq.im;
+                if (MODE == kSgsFwdStart) db[v] += o[i].re * o[i].re + o[i].im * o[i].im;
+              }
+            }
+          }
+        }
+        if (!valid) continue;
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+          const size_t e = e0 + (size_t)i * (WAVE * V);
+          if (MODE == kSgsBackIter) {
+            stv<R, V>(st.ph + e, own[i]);
+            stv<R, V>(st.t + e, res[i]);
+          } else if (MODE == kSgsBackFinal) {
+            stv<R, V>(st.t + e, res[i]);
+            stv<R, V>(st.x + e, res[i]);
+          } else if (MODE == kSgsFwdIter) {
+            stv<R, V>(st.sh + e, res[i]);
+            stv<R, V>(st.v + e, out2[i]);
+          } else {
+            stv<R, V>(st.sh + e, res[i]);
+            stv<R, V>(st.r + e, out2[i]);
+          }
+        }
+      }
+    }
+    if (fwd) {
+      wg_acc_partial_cx<R, V>(da, p.w, p.lane, cl0, I.K, st.part_a + po, add != 0);
+      if (MODE == kSgsFwdStart) wg_acc_partial<R, V>(db, p.w, p.lane, cl0, I.K, st.part_b + po, add != 0);
+    }
+  }
+}
+
+template <typename R, int BS, int MODE>
+void sgs_sweeps(hipStream_t s, const Batch& b, const KrylovState<R>& st, int first, LaunchTimer* tm,
+                double tile_bytes, double fixed) {
+  const dim3 grid((unsigned)b.G), blk(WG);
+  constexpr bool fwd = MODE == kSgsFwdIter || MODE == kSgsFwdStart;
+  const int nc = b.sgs_ncol;
+  for (int q = 0; q < nc; ++q) {
+    const int c = fwd ? q : nc - 1 - q;
+    // a colour launch of one direction does 1 / (2 nc) of a product with S
+    int* cnt = tm ? tm->begin(s, 0, tile_bytes / nc, fixed / nc, 0.5 / nc) : nullptr;
+    k_sgs_sweep<R, BS, MODE><<<grid, blk, 0, s>>>(b, st, c, q > 0 ? 1 : 0, first, cnt);
+    if (cnt) tm->end(s);
+  }
+}
+
+template <typename R, int BS>
+void sgs_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit, bool first,
+                   LaunchTimer* tm, const IterBytes& by) {
+  const dim3 grid((unsigned)b.G), blk(WG);
+  const dim3 cgrid((unsigned)b.n_tiles), cblk(kScWG);
+  // backward: read r, p; write p, t; gather t once; the upper couplings and the blocks
+  sgs_sweeps<R, BS, kSgsBackIter>(s, b, st, first ? 1 : 0, tm, 5 * by.blk + 0.5 * by.sgs_blocks, by.sgs_upper);
+  // forward: read p, t; write u, q; gather u once; the lower couplings and the blocks
+  sgs_sweeps<R, BS, kSgsFwdIter>(s, b, st, 0, tm, 5 * by.blk + 0.5 * by.sgs_blocks, by.sgs_lower);
+  k_cocg_alpha<R><<<cgrid, cblk, 0, s>>>(b, st);
+  int* c = tm ? tm->begin(s, 1, 6 * by.blk, 0) : nullptr;
+  k_cocg_update_xr<R><<<grid, blk, 0, s>>>(b, st, c);
+  if (c) tm->end(s);
+  k_cocg_beta<R><<<cgrid, cblk, 0, s>>>(b, st, tol, maxit);
+}
+
+template <typename R>
+void launch_sgs_finish(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
+  if (b.sgs == 3)
+    sgs_sweeps<R, 3, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
+  else
+    sgs_sweeps<R, 1, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
+}
+
 template <typename R>
 void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
-  k_cocg_start<R><<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, st);
+  if (b.sgs == 3)
+    sgs_sweeps<R, 3, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
+  else if (b.sgs == 1)
+    sgs_sweeps<R, 1, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
+  else
+    k_cocg_start<R><<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, st);
   k_cocg_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(kScWG), 0, s>>>(b, st);
 }
 
 template <typename R>
 void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
-                           LaunchTimer* tm, const IterBytes& by) {
+                           bool first, LaunchTimer* tm, const IterBytes& by) {
+  if (b.sgs == 3) {
+    sgs_iteration<R, 3>(s, b, st, tol, maxit, first, tm, by);
+    return;
+  }
+  if (b.sgs == 1) {
+    sgs_iteration<R, 1>(s, b, st, tol, maxit, first, tm, by);
+    return;
+  }
   const dim3 grid((unsigned)b.G), blk(WG);
   const dim3 cgrid((unsigned)b.n_tiles), cblk(kScWG);
   int* c;
@@ -1776,7 +2103,8 @@ void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& 
                                     int, LaunchTimer*, const IterBytes&);                              \
   template void launch_cocg_start<R>(hipStream_t, const Batch&, const KrylovState<R>&);            \
   template void launch_cocg_iteration<R>(hipStream_t, const Batch&, const KrylovState<R>&, R, int, \
-                                         LaunchTimer*, const IterBytes&);
+                                         bool, LaunchTimer*, const IterBytes&);                         \
+  template void launch_sgs_finish<R>(hipStream_t, const Batch&, const KrylovState<R>&);
 SLRF_INST(double)
 SLRF_INST(float)
 

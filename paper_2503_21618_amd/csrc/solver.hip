@@ -44,6 +44,12 @@ constexpr int kRowsPerNodeBlock = 24;  // default rows per block for node-triple
 constexpr int kWgPerXcd = 128;      // default workgroups per XCD (grid 8 * 128)
 constexpr int kSubBand = 1024;      // default rows per sub-band of the sparse-product row order
 constexpr int kTimerSlots = 512;
+// largest residual of the previous outer iteration above which the Gram
+// products of the first Rayleigh-Ritz projection of the mixed form run on FP32
+// MFMA, and the eigenvalue floor of that projection (about the FP32 Gram's
+// rounding level relative to its largest eigenvalue)
+constexpr double kFirstPassF32Above = 1e-6;
+constexpr double kF32GramFloor = 1e-6;
 constexpr double kInnerTol32 = 1e-6;  // tightest relative tolerance of an FP32 correction solve
 constexpr int kMaxRounds = 6;         // defect-correction rounds per filter application
 constexpr int kDefaultPoles = 4;
@@ -72,6 +78,8 @@ bool use_ilu_for(int precond, int64_t n, int64_t nnz) {
   return precond == 2 || (precond == 0 && ilu_allowed(n, nnz));
 }
 bool use_bjac_for(int precond) { return precond == 3; }
+// multicolour symmetric Gauss-Seidel (COCG only): block size 1 (precond 4) or 3 (precond 5)
+int sgs_block_for(int precond) { return precond == 4 ? 1 : precond == 5 ? 3 : 0; }
 
 // First-fit allocator over a device region (persistent data of a batch).
 struct Pool {
@@ -136,17 +144,60 @@ struct Pencil {
   int* nodes = nullptr;   // node-triple flags (n / kNode), or null (never both)
   bool use_ilu = false;
   bool use_bjac = false;  // node 3x3 block Jacobi
+  // multicolour SGS: block size, colours, nodes by colour, lower / upper coupling CSRs
+  int sgs = 0, sgs_ncol = 0;
+  int *sgs_cptr = nullptr, *sgs_nodes = nullptr;
+  int *lrp = nullptr, *lcol = nullptr, *urp = nullptr, *ucol = nullptr;
+  ab_pair<double>*lab64 = nullptr, *uab64 = nullptr;
+  ab_pair<float>*lab32 = nullptr, *uab32 = nullptr;
+  int64_t lnnz = 0, unnz = 0;
   char* mem = nullptr;  // device region holding the above
   size_t mem_bytes = 0;
   std::vector<int32_t> h_rp, h_cl, h_dpos;  // host copies for ILU(0) / block Jacobi
   std::vector<double> h_ab;
 };
 
-size_t pencil_bytes(int64_t n, int64_t nnz) {
+// The colours of a greedy colouring are at most the largest node degree + 1;
+// the colour offsets are sized for kMaxColours.
+constexpr int kMaxColours = 1024;
+
+size_t pencil_bytes(int64_t n, int64_t nnz, int precond = 0) {
   const size_t np = (size_t)nnz + kCsrPad;
-  return al((size_t)(n + 1) * 4) + al(np * 4) + al(np * 16) + al(np * 8) + 2 * al((size_t)n * 8) +
-         2 * al((size_t)n * 4) + 2 * al((size_t)n * 4) + al((size_t)(n / kGroup + 1) * 4) +
-         al((size_t)(n / kNode + 1) * 4);
+  size_t b = al((size_t)(n + 1) * 4) + al(np * 4) + al(np * 16) + al(np * 8) + 2 * al((size_t)n * 8) +
+             2 * al((size_t)n * 4) + 2 * al((size_t)n * 4) + al((size_t)(n / kGroup + 1) * 4) +
+             al((size_t)(n / kNode + 1) * 4);
+  if (sgs_block_for(precond)) {
+    // colour offsets and nodes; two coupling CSRs (together at most nnz entries)
+    b += al((kMaxColours + 1) * 4) + al((size_t)n * 4) + 2 * al((size_t)(n + 1) * 4);
+    for (int part = 0; part < 2; ++part) b += al(np * 4) + al(np * 16) + al(np * 8);
+  }
+  return b;
+}
+
+// Greedy colouring of the node graph (block = 1: unknowns; 3: unknowns 3k..3k+2
+// form node k): nodes in increasing index, each takes the smallest colour that
+// no already coloured neighbour has.  Returns the number of colours.
+int greedy_colours(int64_t n, int block, const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
+                   std::vector<int32_t>& colour) {
+  const int64_t nodes = n / block;
+  colour.assign(nodes, -1);
+  std::vector<int64_t> seen(kMaxColours + 1, -1);
+  int ncol = 0;
+  for (int64_t k = 0; k < nodes; ++k) {
+    for (int r = 0; r < block; ++r) {
+      const int64_t i = block * k + r;
+      for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int64_t m = cl[q] / block;
+        if (m != k && colour[m] >= 0) seen[colour[m]] = k;
+      }
+    }
+    int c = 0;
+    while (c < kMaxColours && seen[c] == k) ++c;
+    if (c >= kMaxColours) return -1;
+    colour[k] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  return ncol;
 }
 
 // Row order of the sparse products.  With upper bandwidth H (max j - i), the
@@ -225,7 +276,7 @@ std::vector<int32_t> node_triples(int64_t n, const std::vector<int32_t>& rp, con
 }
 
 // Validates A and B, merges them into one CSR of (a, b) pairs over the union
-// pattern and, with mem != nullptr, uploads it there (pencil_bytes(n, nnz)
+// pattern and, with mem != nullptr, uploads it there (pencil_bytes(n, nnz, precond)
 // bytes).  With mem == nullptr it only validates and reports nnz of the union.
 slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
                          const int32_t* b_rowptr, const int32_t* b_col, const double* b_val, int precond,
@@ -251,12 +302,12 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   if (!err.empty()) return SLRF_E_INVALID_ARG;
   err = check_csr(b_rowptr, b_col, b_val, "B");
   if (!err.empty()) return SLRF_E_INVALID_ARG;
-  if (precond < 0 || precond > 3) {
+  if (precond < 0 || precond > 5) {
     err = "unknown preconditioner";
     return SLRF_E_INVALID_ARG;
   }
-  if (precond == 3 && n % 3 != 0) {
-    err = "node block Jacobi needs three unknowns per node (n divisible by 3)";
+  if ((precond == 3 || precond == 5) && n % 3 != 0) {
+    err = "node blocks need three unknowns per node (n divisible by 3)";
     return SLRF_E_INVALID_ARG;
   }
   std::vector<int32_t> rp(n + 1, 0), cl, dpos(n, -1);
@@ -298,8 +349,9 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.nnz = nnz;
   P.use_ilu = use_ilu_for(precond, n, nnz);
   P.use_bjac = use_bjac_for(precond);
+  P.sgs = sgs_block_for(precond);
   P.mem = mem;
-  P.mem_bytes = pencil_bytes(n, nnz);
+  P.mem_bytes = pencil_bytes(n, nnz, precond);
   Carver cv{mem, 0, P.mem_bytes};
   P.rowptr = cv.take<int>(n + 1);
   P.col = cv.take<int>(nnz + kCsrPad);
@@ -313,6 +365,67 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   int* sched_dev = cv.take<int>(n);
   int* groups_dev = cv.take<int>(n / kGroup + 1);
   int* nodes_dev = cv.take<int>(n / kNode + 1);
+  // multicolour SGS tables: colours of the nodes, nodes by colour, and the merged
+  // CSR split into couplings to lower and to higher colours (same-node entries
+  // form the diagonal blocks and belong to neither)
+  std::vector<int32_t> cptr, cnodes, lrp, lcl, urp, ucl;
+  std::vector<double> lab, uab;
+  if (P.sgs) {
+    const int bs = P.sgs;
+    std::vector<int32_t> colour;
+    const int ncol = greedy_colours(n, bs, rp, cl, colour);
+    if (ncol < 1) {
+      err = "node graph needs more than " + std::to_string(kMaxColours) + " colours";
+      return SLRF_E_INVALID_ARG;
+    }
+    P.sgs_ncol = ncol;
+    const int64_t nodes = n / bs;
+    cptr.assign(ncol + 1, 0);
+    for (int64_t k = 0; k < nodes; ++k) cptr[colour[k] + 1]++;
+    for (int c = 0; c < ncol; ++c) cptr[c + 1] += cptr[c];
+    cnodes.resize(nodes);
+    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t k = 0; k < nodes; ++k) cnodes[fill[colour[k]]++] = (int32_t)k;
+    lrp.assign(n + 1, 0);
+    urp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int ci = colour[i / bs];
+      for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int cj = colour[cl[q] / bs];
+        if (cj < ci) {
+          lcl.push_back(cl[q]);
+          lab.push_back(ab[2 * (size_t)q]);
+          lab.push_back(ab[2 * (size_t)q + 1]);
+        } else if (cj > ci) {
+          ucl.push_back(cl[q]);
+          uab.push_back(ab[2 * (size_t)q]);
+          uab.push_back(ab[2 * (size_t)q + 1]);
+        } else if (cl[q] / bs != i / bs) {
+          err = "colouring left two coupled nodes alike";
+          return SLRF_E_INVALID_ARG;
+        }
+      }
+      lrp[i + 1] = (int32_t)lcl.size();
+      urp[i + 1] = (int32_t)ucl.size();
+    }
+    P.lnnz = (int64_t)lcl.size();
+    P.unnz = (int64_t)ucl.size();
+    P.sgs_cptr = cv.take<int>(kMaxColours + 1);
+    P.sgs_nodes = cv.take<int>(n);
+    P.lrp = cv.take<int>(n + 1);
+    P.urp = cv.take<int>(n + 1);
+    P.lcol = cv.take<int>(nnz + kCsrPad);
+    P.lab64 = cv.take<ab_pair<double>>(nnz + kCsrPad);
+    P.lab32 = cv.take<ab_pair<float>>(nnz + kCsrPad);
+    P.ucol = cv.take<int>(nnz + kCsrPad);
+    P.uab64 = cv.take<ab_pair<double>>(nnz + kCsrPad);
+    P.uab32 = cv.take<ab_pair<float>>(nnz + kCsrPad);
+    // kCsrPad zero entries after each part (whole-chunk reads)
+    lcl.resize(lcl.size() + kCsrPad, 0);
+    ucl.resize(ucl.size() + kCsrPad, 0);
+    lab.resize(2 * lcl.size(), 0.0);
+    uab.resize(2 * ucl.size(), 0.0);
+  }
   std::vector<int32_t> order;
   P.sched = band_schedule(n, rp, cl, band_rows, order) ? sched_dev : nullptr;
   const std::vector<int32_t> groups = stencil_groups(n, rp, cl), nodes = node_triples(n, rp, cl);
@@ -345,7 +458,22 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
     err = "upload of the merged CSR failed";
     return SLRF_E_DEVICE;
   }
-  if (P.use_ilu || P.use_bjac) {
+  if (P.sgs) {
+    std::vector<float> lab32(lab.size()), uab32(uab.size());
+    for (size_t k = 0; k < lab.size(); ++k) lab32[k] = (float)lab[k];
+    for (size_t k = 0; k < uab.size(); ++k) uab32[k] = (float)uab[k];
+    if (cp(P.sgs_cptr, cptr.data(), 4 * cptr.size()) != hipSuccess ||
+        cp(P.sgs_nodes, cnodes.data(), 4 * cnodes.size()) != hipSuccess ||
+        cp(P.lrp, lrp.data(), 4 * lrp.size()) != hipSuccess || cp(P.urp, urp.data(), 4 * urp.size()) != hipSuccess ||
+        cp(P.lcol, lcl.data(), 4 * lcl.size()) != hipSuccess || cp(P.ucol, ucl.data(), 4 * ucl.size()) != hipSuccess ||
+        cp(P.lab64, lab.data(), 8 * lab.size()) != hipSuccess || cp(P.uab64, uab.data(), 8 * uab.size()) != hipSuccess ||
+        cp(P.lab32, lab32.data(), 4 * lab32.size()) != hipSuccess ||
+        cp(P.uab32, uab32.data(), 4 * uab32.size()) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      err = "upload of the colour tables failed";
+      return SLRF_E_DEVICE;
+    }
+  }
+  if (P.use_ilu || P.use_bjac || P.sgs) {
     P.h_rp = std::move(rp);
     P.h_cl = std::move(cl);
     P.h_ab = std::move(ab);
@@ -502,7 +630,9 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   env.stream = (hipStream_t)hip_stream;
   if (env.opt.precision != SLRF_FP64 && env.opt.precision != SLRF_MIXED)
     return fail(env, SLRF_E_INVALID_ARG, "unknown precision");
-  if (env.opt.precond < 0 || env.opt.precond > 3) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (env.opt.precond < 0 || env.opt.precond > 5) return fail(env, SLRF_E_INVALID_ARG, "unknown preconditioner");
+  if (sgs_block_for(env.opt.precond) && env.opt.solver != 1)
+    return fail(env, SLRF_E_INVALID_ARG, "the multicolour SGS preconditioner runs with COCG only (solver = 1)");
   if (env.opt.solver != 0 && env.opt.solver != 1) return fail(env, SLRF_E_INVALID_ARG, "unknown inner solver");
   if (env.opt.recycle != 0 && env.opt.recycle != 1) return fail(env, SLRF_E_INVALID_ARG, "recycle must be 0 or 1");
   if (env.opt.solver == 1) {
@@ -521,7 +651,7 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
 
 // Reads back the event pairs and tile counters of the current window into the
 // kernel statistics, then clears the window.
-slrf_status harvest_timer(Env& env, int64_t total_tiles, slrf_filter_stats* fs) {
+slrf_status harvest_timer(Env& env, int64_t total_tiles, int64_t total_cols, slrf_filter_stats* fs) {
   LaunchTimer& tm = env.timer;
   if (tm.used == 0) return SLRF_OK;
   std::vector<int> cnt(tm.used);
@@ -536,6 +666,7 @@ slrf_status harvest_timer(Env& env, int64_t total_tiles, slrf_filter_stats* fs) 
       fs->spmm_seconds += 1e-3 * ms;
       fs->spmm_launches += 1;
       fs->spmm_bytes += bytes;
+      fs->spmm_columns += r.share * (double)total_cols * (double)cnt[u] / (double)total_tiles;
     } else {
       fs->update_seconds += 1e-3 * ms;
       fs->update_launches += 1;
@@ -558,6 +689,42 @@ slrf_status check_poles(Env& env, const slrf_poles* p, int max_N) {
     if (!(b > 0)) return fail(env, SLRF_E_INVALID_ARG, "poles must lie in the upper half plane (Im sigma > 0)");
   }
   return SLRF_OK;
+}
+
+// Node blocks D_k of A - sigma B (row-major) and their complex-symmetric factors
+// R_k, lower triangular with D_k = R_k R_k^T (no conjugation: D_k is complex
+// symmetric), by the Cholesky recurrences with complex square roots.  False if
+// a pivot vanishes.
+bool sgs3_factor(const Pencil& P, std::complex<double> sigma, std::vector<std::complex<double>>& Rf,
+                 std::vector<std::complex<double>>& Df) {
+  using C = std::complex<double>;
+  const int64_t nodes = P.n / 3;
+  Rf.assign(nodes * 9, C(0.0));
+  Df.assign(nodes * 9, C(0.0));
+  for (int64_t k = 0; k < nodes; ++k) {
+    C* d = &Df[9 * k];
+    for (int r = 0; r < 3; ++r) {
+      const int64_t i = 3 * k + r;
+      for (int32_t q = P.h_rp[i]; q < P.h_rp[i + 1]; ++q) {
+        const int64_t c = P.h_cl[q] - 3 * k;
+        if (c >= 0 && c < 3) d[3 * r + c] = C(P.h_ab[2 * q], 0.0) - sigma * P.h_ab[2 * q + 1];
+      }
+    }
+    C* R = &Rf[9 * k];
+    for (int j = 0; j < 3; ++j) {
+      C piv = d[3 * j + j];
+      for (int m = 0; m < j; ++m) piv -= R[3 * j + m] * R[3 * j + m];
+      const C rjj = std::sqrt(piv);
+      if (!(std::abs(rjj) > 0.0) || !std::isfinite(std::abs(rjj))) return false;
+      R[3 * j + j] = rjj;
+      for (int i = j + 1; i < 3; ++i) {
+        C v = d[3 * i + j];
+        for (int m = 0; m < j; ++m) v -= R[3 * i + m] * R[3 * j + m];
+        R[3 * i + j] = v / rjj;
+      }
+    }
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -593,14 +760,16 @@ struct JobShape {
   bool ilu;              // ILU(0) factors of this pencil
   bool general = false;  // count the p and s blocks even without another preconditioner (bounds)
   bool bjac = false;     // node block-Jacobi inverses of this pencil
+  int sgs = 0;           // multicolour SGS block size of this pencil (its R, D and D^{-1})
 };
 
 // Device layout of one batched filter application.  Carving with a null base
 // measures it; partial sums are sized for kMaxGrid workgroups so the size does
 // not depend on the grid a batch picks.
 struct FilterLayout {
-  int64_t EB = 0, ER = 0, ED = 0, Ktot = 0, n_tiles = 0, ilu_vals = 0, bjac_vals = 0;
+  int64_t EB = 0, ER = 0, ED = 0, Ktot = 0, n_tiles = 0, ilu_vals = 0, bjac_vals = 0, sgs_vals = 0;
   bool any_ilu = false, any_bjac = false;
+  int sgs = 0;  // block size of the batch's multicolour SGS (all its pencils share the option)
   void* vec[9] = {};  // x r ph v sh t [p s] [complex shadow residual]
   double* rhat = nullptr;
   void* d = nullptr;
@@ -633,6 +802,8 @@ struct FilterLayout {
   int* col_inst = nullptr;
   void* ilu = nullptr;
   void* bjac = nullptr;
+  void* sgsR = nullptr;  // multicolour SGS: R (point: ED values; blocks: sgs_vals)
+  void* sgsD = nullptr;  // and the node blocks D (blocks only)
   int precs() const { return (any_ilu ? 1 : 0) | (any_bjac ? 2 : 0); }
 };
 
@@ -665,8 +836,9 @@ void place_jobs(std::vector<FilterJob>& jobs, bool mixed) {
 // padded columns and tiles, and which preconditioner tables the set needs.
 void shape_totals(const std::vector<JobShape>& js, bool mixed, FilterLayout& lo, int64_t& sumN,
                   bool& any_general) {
-  lo.EB = lo.ER = lo.ED = lo.Ktot = lo.n_tiles = lo.ilu_vals = lo.bjac_vals = 0;
+  lo.EB = lo.ER = lo.ED = lo.Ktot = lo.n_tiles = lo.ilu_vals = lo.bjac_vals = lo.sgs_vals = 0;
   lo.any_ilu = lo.any_bjac = false;
+  lo.sgs = 0;
   sumN = 0;
   any_general = false;
   const int V = lane_width(mixed);
@@ -682,9 +854,13 @@ void shape_totals(const std::vector<JobShape>& js, bool mixed, FilterLayout& lo,
       lo.any_ilu = true;
       lo.ilu_vals += (int64_t)j.N * j.nnz;
     }
-    if (j.bjac) {
-      lo.any_bjac = true;
+    if (j.bjac || j.sgs == 3) {
+      lo.any_bjac = lo.any_bjac || j.bjac;
       lo.bjac_vals += (int64_t)j.N * (j.n / 3) * 9;
+    }
+    if (j.sgs) {
+      lo.sgs = std::max(lo.sgs, j.sgs);
+      lo.sgs_vals += j.sgs == 3 ? (int64_t)j.N * (j.n / 3) * 9 : (int64_t)j.n * j.N;
     }
     if (j.general) any_general = true;
   }
@@ -734,7 +910,11 @@ void carve_filter(Carver& cv, const std::vector<JobShape>& js, bool mixed, Filte
   lo.tile_inst = cv.take<int>(lo.n_tiles);
   lo.col_inst = cv.take<int>(lo.Ktot);
   if (lo.any_ilu) lo.ilu = cv.take<char>((size_t)lo.ilu_vals * cs);
-  if (lo.any_bjac) lo.bjac = cv.take<char>((size_t)lo.bjac_vals * cs);
+  if (lo.bjac_vals) lo.bjac = cv.take<char>((size_t)lo.bjac_vals * cs);
+  if (lo.sgs) {
+    lo.sgsR = cv.take<char>((size_t)lo.sgs_vals * cs);
+    if (lo.sgs == 3) lo.sgsD = cv.take<char>((size_t)lo.sgs_vals * cs);
+  }
 }
 
 size_t filter_arena_bytes(const std::vector<JobShape>& js, bool mixed) {
@@ -841,9 +1021,11 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   }
   b.groups = any_group ? 1 : any_node ? 2 : 0;
   std::vector<int> tile_inst, col_inst;
-  std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all;
+  std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all, sgsR_all, sgsD_all;
   std::vector<double> sigc64, w;
-  int64_t dn = 0, ilu_off = 0, bjac_off = 0;
+  int64_t dn = 0, ilu_off = 0, bjac_off = 0, sgs_off = 0;
+  b.sgs = 0;
+  b.sgs_ncol = 0;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
     const FilterJob& j = jobs[q];
@@ -869,6 +1051,18 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.diagpos = j.P->diagpos;
     I.ilu = nullptr;
     I.bjac = nullptr;
+    I.sgs = j.P->sgs;
+    I.sgs_ncol = j.P->sgs_ncol;
+    I.sgs_cptr = j.P->sgs_cptr;
+    I.sgs_nodes = j.P->sgs_nodes;
+    I.lrp = j.P->lrp;
+    I.lcol = j.P->lcol;
+    I.urp = j.P->urp;
+    I.ucol = j.P->ucol;
+    I.lab = std::is_same<R, float>::value ? (const void*)j.P->lab32 : (const void*)j.P->lab64;
+    I.uab = std::is_same<R, float>::value ? (const void*)j.P->uab32 : (const void*)j.P->uab64;
+    I.sgsR = nullptr;
+    I.sgsD = nullptr;
     const int tiles = (I.Kp + 64 * b.V - 1) / (64 * b.V);
     for (int t = 0; t < tiles; ++t) tile_inst.push_back((int)q);
     for (int c = 0; c < I.Kp; ++c) col_inst.push_back((int)q);
@@ -899,7 +1093,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
       I.ilu = (const char*)lo.ilu + ilu_off * sizeof(cx<R>);
       ilu_off += (int64_t)j.N * j.P->nnz;
     }
-    if (j.P->use_bjac) {
+    if (j.P->use_bjac || j.P->sgs == 3) {
       std::vector<std::complex<double>> fj;
       for (int p = 0; p < j.N; ++p) {
         if (!bjac3_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, fj))
@@ -908,6 +1102,42 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
       }
       I.bjac = (const char*)lo.bjac + bjac_off * sizeof(cx<R>);
       bjac_off += (int64_t)j.N * (j.P->n / 3) * 9;
+    }
+    if (j.P->sgs == 3) {
+      std::vector<std::complex<double>> Rf, Df;
+      for (int p = 0; p < j.N; ++p) {
+        if (!sgs3_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, Rf, Df))
+          return fail(env, SLRF_E_BREAKDOWN, "node block of the shifted operator without a symmetric factor");
+        for (const auto& v : Rf) sgsR_all.push_back({(R)v.real(), (R)v.imag()});
+        for (const auto& v : Df) sgsD_all.push_back({(R)v.real(), (R)v.imag()});
+      }
+      I.sgsR = (const char*)lo.sgsR + sgs_off * sizeof(cx<R>);
+      I.sgsD = (const char*)lo.sgsD + sgs_off * sizeof(cx<R>);
+      sgs_off += (int64_t)j.N * (j.P->n / 3) * 9;
+    } else if (j.P->sgs == 1) {
+      // R = sqrt(d) per (row, pole), in the (n, N) layout of d at Inst::dn
+      const std::vector<double>& ab = j.P->h_ab;
+      std::vector<double> dA(I.n), dB(I.n);
+      for (int64_t i = 0; i < I.n; ++i)
+        for (int32_t q = j.P->h_rp[i]; q < j.P->h_rp[i + 1]; ++q)
+          if (j.P->h_cl[q] == i) {
+            dA[i] = ab[2 * (size_t)q];
+            dB[i] = ab[2 * (size_t)q + 1];
+          }
+      // d is computed on the device in the Krylov precision from the same
+      // diagonals; R is rounded from the FP64 square root
+      sgsR_all.resize((size_t)(dn + (int64_t)I.n * I.N));
+      for (int64_t i = 0; i < I.n; ++i)
+        for (int p = 0; p < j.N; ++p) {
+          const std::complex<double> r =
+              std::sqrt(std::complex<double>(dA[i], 0.0) - std::complex<double>(j.sigma[2 * p], j.sigma[2 * p + 1]) * dB[i]);
+          sgsR_all[(size_t)(dn + i * I.N + p)] = {(R)r.real(), (R)r.imag()};
+        }
+      I.sgsR = lo.sgsR;
+    }
+    if (j.P->sgs) {
+      b.sgs = std::max(b.sgs, j.P->sgs);
+      b.sgs_ncol = std::max(b.sgs_ncol, j.P->sgs_ncol);
     }
     dn += (int64_t)I.n * I.N;
     col0 += I.Kp;
@@ -931,6 +1161,10 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   if (!ilu_all.empty()) HIPCHK(env, put_async(s, keep, lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
   if (!bjac_all.empty())
     HIPCHK(env, put_async(s, keep, lo.bjac, bjac_all.data(), sizeof(cx<R>) * bjac_all.size()));
+  if (!sgsR_all.empty())
+    HIPCHK(env, put_async(s, keep, lo.sgsR, sgsR_all.data(), sizeof(cx<R>) * sgsR_all.size()));
+  if (!sgsD_all.empty())
+    HIPCHK(env, put_async(s, keep, lo.sgsD, sgsD_all.data(), sizeof(cx<R>) * sgsD_all.size()));
   return SLRF_OK;
 }
 
@@ -966,7 +1200,7 @@ template <typename R>
 void krylov_iteration(const Env& env, const Batch& b, const KrylovState<R>& st, R tol, int maxit, bool first,
                       int precs, LaunchTimer* tm, const IterBytes& by) {
   if (env.opt.solver == 1)
-    launch_cocg_iteration<R>(env.stream, b, st, tol, maxit, tm, by);
+    launch_cocg_iteration<R>(env.stream, b, st, tol, maxit, first, tm, by);
   else
     launch_iteration<R>(env.stream, b, st, tol, maxit, first, precs, tm, by);
 }
@@ -1084,7 +1318,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       return fail(env, SLRF_E_DEVICE, std::string("Krylov iteration: ") + hipGetErrorString(e));
     }
     if (tm) {
-      out = harvest_timer(env, (int64_t)b.G * b.n_tiles, ks);
+      out = harvest_timer(env, (int64_t)b.G * b.n_tiles, (int64_t)b.Ktot, ks);
       if (out != SLRF_OK) break;
     }
     if (active == 0) break;
@@ -1099,6 +1333,14 @@ IterBytes iter_bytes(const std::vector<FilterJob>& jobs, const FilterLayout& lo,
   by.rhat = complex_rhat ? by.blk : (double)lo.ER * rs;
   by.diag = (double)lo.ED * 2 * rs;
   for (const auto& j : jobs) by.matrix += merged_csr_bytes(*j.P, 2 * rs);
+  for (const auto& j : jobs)
+    if (j.P->sgs) {
+      // column index plus (a, b) pair per coupling, and the row pointers
+      by.sgs_lower += (double)j.P->lnnz * (4 + 2 * rs) + 4.0 * (j.P->n + 1);
+      by.sgs_upper += (double)j.P->unnz * (4 + 2 * rs) + 4.0 * (j.P->n + 1);
+      // R, D and D^{-1} for every pole (point: D and D^{-1} are the diagonal blocks)
+      by.sgs_blocks += (double)j.N * j.P->n * (j.P->sgs == 3 ? 3.0 * 3 : 3.0) * 2 * rs;
+    }
   return by;
 }
 
@@ -1147,6 +1389,7 @@ void finish_stats(std::vector<FilterJob>& jobs, const std::vector<double>& sum_i
     fs.spmm_seconds = ks.spmm_seconds;
     fs.spmm_launches = ks.spmm_launches;
     fs.spmm_bytes = ks.spmm_bytes;
+    fs.spmm_columns = ks.spmm_columns;
     fs.update_seconds = ks.update_seconds;
     fs.update_launches = ks.update_launches;
     fs.update_bytes = ks.update_bytes;
@@ -1160,7 +1403,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
-  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac, j.P->sgs});
   FilterLayout lo;
   carve_filter(arena, js, false, lo);
   place_jobs(jobs, false);
@@ -1193,6 +1436,7 @@ slrf_status filter_batch_fp64(Env& env, Carver& arena, std::vector<FilterJob>& j
   }
   slrf_status rs = run_krylov<double>(env, b, st, env.opt.inner_tol, lo.precs(), by, lo.count, &ks);
   if (rs != SLRF_OK) return rs;
+  if (b.sgs) launch_sgs_finish<double>(s, b, st);  // x = M_L^{-T} x' for every column
   int64_t wj = 0;
   for (auto& j : jobs) {
     launch_filter_sum<double>(s, (int)j.P->n, j.L, j.N, tile_width(false), column_order(env), st.x + j.blk,
@@ -1221,7 +1465,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   const double t0 = now_s();
   const hipStream_t s = env.stream;
   std::vector<JobShape> js;
-  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac});
+  for (auto& j : jobs) js.push_back({j.P->n, j.P->nnz, j.L, j.N, j.P->use_ilu, false, j.P->use_bjac, j.P->sgs});
   FilterLayout lo;
   carve_filter(arena, js, true, lo);
   place_jobs(jobs, true);
@@ -1321,6 +1565,7 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
     }
     slrf_status rs = run_krylov<float>(env, b, st, tol32, lo.precs(), by, lo.count, &ks);
     if (rs != SLRF_OK) return rs;
+    if (b.sgs) launch_sgs_finish<float>(s, b, st);  // x = M_L^{-T} x' for every column
     launch_accumulate(s, b, st.x, lo.scale, lo.Y, round == 0);
     slrf_status cs = collect_stats<float>(env, jobs, st, lo.Ktot, false, it_round);
     if (cs != SLRF_OK) return cs;
@@ -1430,18 +1675,25 @@ struct SolveJob {
 
 // One Rayleigh-Ritz pass (Section 3, B-orthonormalisation by the projected
 // pencil): Y = Xin Z with Z^T (Xin^T A Xin) Z = diag(theta), Z^T (Xin^T B Xin) Z = I.
-slrf_status rr_pass(Env& env, SolveJob& J, const double* Xin, double* Y, std::vector<double>& theta) {
+// f32: the two Gram products on FP32 MFMA (FP32 inputs, FP32 accumulation),
+// for the first projection of a mixed-precision outer iteration whose Ritz pairs
+// are still far from converged.  The update Y = Xin Z stays FP64 whatever Z is,
+// so span(Y) = span(Xin) to FP64 rounding and the FP64 pass that follows sees
+// the filtered subspace itself; only how nearly B-orthonormal Y comes out
+// depends on the FP32 Gram.
+slrf_status rr_pass(Env& env, SolveJob& J, const double* Xin, double* Y, std::vector<double>& theta,
+                    bool f32 = false) {
   const hipStream_t s = env.stream;
   const int n = (int)J.P->n, L = J.L;
   launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, Xin, J.WA, J.WB);
-  launch_gram(s, n, L, Xin, J.WA, J.WB, J.part, J.nch, J.GA, J.GB);
+  launch_gram(s, n, L, Xin, J.WA, J.WB, J.part, J.nch, J.GA, J.GB, f32);
   HIPCHK(env, hipGetLastError());
   std::vector<double> hA((size_t)L * L), hB((size_t)L * L), Z((size_t)L * L);
   HIPCHK(env, hipMemcpyAsync(hA.data(), J.GA, 8 * hA.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(env, hipMemcpyAsync(hB.data(), J.GB, 8 * hB.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(env, hipStreamSynchronize(s));
   theta.assign(L, 0.0);
-  if (!projected_pencil(L, hA.data(), hB.data(), theta.data(), Z.data()))
+  if (!projected_pencil(L, hA.data(), hB.data(), theta.data(), Z.data(), f32 ? kF32GramFloor : 1e-15))
     return fail(env, SLRF_E_BREAKDOWN, "projected pencil not solvable (non-finite or zero Gram matrix)");
   HIPCHK(env, hipMemcpyAsync(J.Zd, Z.data(), 8 * Z.size(), hipMemcpyHostToDevice, s));
   const double* xs[1] = {Xin};
@@ -1464,11 +1716,18 @@ slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
   kk.spmm_seconds += fs.spmm_seconds;
   kk.spmm_launches += fs.spmm_launches;
   kk.spmm_bytes += fs.spmm_bytes;
+  kk.spmm_columns += fs.spmm_columns;
   kk.update_seconds += fs.update_seconds;
   kk.update_launches += fs.update_launches;
   kk.update_bytes += fs.update_bytes;
+  // Two projections.  In mixed precision the first one forms its Gram
+  // matrices on FP32 MFMA while the previous residuals exceed 1e-6 (before the
+  // first outer iteration they count as infinite): it only has to
+  // B-orthonormalise approximately.  The second, which gives the Ritz pairs,
+  // the residuals and the count, is always FP64.
+  const bool f32 = env.opt.precision == SLRF_MIXED && J.prev_maxr > kFirstPassF32Above;
   std::vector<double> th1;
-  slrf_status st = rr_pass(env, J, J.U, J.X, th1);
+  slrf_status st = rr_pass(env, J, J.U, J.X, th1, f32);
   if (st != SLRF_OK) return st;
   st = rr_pass(env, J, J.X, J.V, J.theta);
   if (st != SLRF_OK) return st;
@@ -1649,7 +1908,7 @@ struct slrf_batch_s {
     for (const auto& kv : entries)
       if (!kv.second.J->done)
         js.push_back({kv.second.P->n, kv.second.P->nnz, kv.second.J->L, kv.second.J->N, kv.second.P->use_ilu, false,
-                      kv.second.P->use_bjac});
+                      kv.second.P->use_bjac, kv.second.P->sgs});
     return js;
   }
 };
@@ -1727,12 +1986,14 @@ slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz, int64_t L, int32_t 
     slrf_default_options(&o);
   if (n < 1 || nnz < n || L < 1 || N < 1 || !bytes || n > INT32_MAX || nnz > INT32_MAX) return SLRF_E_INVALID_ARG;
   if (o.precision != SLRF_FP64 && o.precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
-  if (o.precond < 0 || o.precond > 3) return SLRF_E_INVALID_ARG;
+  if (o.precond < 0 || o.precond > 5) return SLRF_E_INVALID_ARG;
+  if (sgs_block_for(o.precond) && o.solver != 1) return SLRF_E_INVALID_ARG;
   if (o.solver == 1 && o.precond == 0) o.precond = 1;  // COCG runs with point Jacobi
   const size_t arena = filter_arena_bytes(
-      {JobShape{n, nnz, (int)L, (int)N, use_ilu_for(o.precond, n, nnz), false, use_bjac_for(o.precond)}},
+      {JobShape{n, nnz, (int)L, (int)N, use_ilu_for(o.precond, n, nnz), false, use_bjac_for(o.precond),
+                sgs_block_for(o.precond)}},
       o.precision == SLRF_MIXED);
-  *bytes = pencil_bytes(n, nnz) + al(kTimerSlots * 4) + arena +
+  *bytes = pencil_bytes(n, nnz, o.precond) + al(kTimerSlots * 4) + arena +
            outer_bytes(n, L, N, o.recycle && o.precision == SLRF_MIXED);
   return SLRF_OK;
 }
@@ -1774,18 +2035,21 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
   st = build_pencil(n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, env.opt.precond, env.opt.band_rows, env.stream, ctx->P, env.err,
                     (char*)d_workspace, nullptr);
   if (st != SLRF_OK) return st;
-  const size_t poff = pencil_bytes(n, nnz);
+  const size_t poff = pencil_bytes(n, nnz, env.opt.precond);
   if (!env.setup_timer((int*)((char*)d_workspace + poff))) return fail(env, SLRF_E_DEVICE, "timer set-up failed");
   ctx->arena_off = poff + al(kTimerSlots * 4);
   ctx->arena_bytes =
-      filter_arena_bytes({JobShape{n, nnz, (int)max_L, max_N, ctx->P.use_ilu, false, ctx->P.use_bjac}},
+      filter_arena_bytes({JobShape{n, nnz, (int)max_L, max_N, ctx->P.use_ilu, false, ctx->P.use_bjac, ctx->P.sgs}},
                          env.opt.precision == SLRF_MIXED);
   ctx->outer_off = ctx->arena_off + ctx->arena_bytes;
   ctx->ws = (char*)d_workspace;
   return SLRF_OK;
 }
 
-void slrf_destroy(slrf_ctx ctx) { delete ctx; }
+void slrf_destroy(slrf_ctx ctx) {
+  if (!ctx) return;
+  delete ctx;
+}
 
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L, const double* d_X, double* d_U,
                               slrf_filter_stats* stats) {
@@ -1831,20 +2095,35 @@ slrf_status slrf_solve_interval(slrf_ctx ctx, double gamma, int64_t L, const slr
 
 // ---- batches ------------------------------------------------------------------
 
-slrf_status slrf_batch_footprint(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision,
-                                 size_t* persistent_bytes, size_t* transient_bytes) {
+slrf_status slrf_batch_footprint_for(int64_t n, int64_t nnz, int64_t L, int32_t N, const slrf_options* opt,
+                                     size_t* persistent_bytes, size_t* transient_bytes) {
+  slrf_options o;
+  if (opt)
+    o = *opt;
+  else
+    slrf_default_options(&o);
   if (n < 1 || nnz < n || L < 1 || N < 1 || n > INT32_MAX || nnz > INT32_MAX || !persistent_bytes ||
       !transient_bytes)
     return SLRF_E_INVALID_ARG;
-  if (precision != SLRF_FP64 && precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  if (o.precision != SLRF_FP64 && o.precision != SLRF_MIXED) return SLRF_E_INVALID_ARG;
+  if (o.precond < 0 || o.precond > 5) return SLRF_E_INVALID_ARG;
+  const int sgs = sgs_block_for(o.precond);
   // with room for the warm-start blocks (options.recycle) in mixed precision
-  *persistent_bytes = al(pencil_bytes(n, nnz)) + al(outer_bytes(n, L, N, precision == SLRF_MIXED));
+  *persistent_bytes = al(pencil_bytes(n, nnz, o.precond)) + al(outer_bytes(n, L, N, o.precision == SLRF_MIXED));
   // counts the two blocks a batch with an ILU(0) or block-Jacobi pencil gives
   // every pencil (and block-Jacobi inverses when n is a multiple of 3), so that
   // the sum over a set of pencils bounds the arena the set needs
-  *transient_bytes = filter_arena_bytes({JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz), true, n % 3 == 0}},
-                                        precision == SLRF_MIXED);
+  *transient_bytes = filter_arena_bytes(
+      {JobShape{n, nnz, (int)L, (int)N, ilu_allowed(n, nnz), true, n % 3 == 0, sgs}}, o.precision == SLRF_MIXED);
   return SLRF_OK;
+}
+
+slrf_status slrf_batch_footprint(int64_t n, int64_t nnz, int64_t L, int32_t N, int32_t precision,
+                                 size_t* persistent_bytes, size_t* transient_bytes) {
+  slrf_options o;
+  slrf_default_options(&o);
+  o.precision = precision;
+  return slrf_batch_footprint_for(n, nnz, L, N, &o, persistent_bytes, transient_bytes);
 }
 
 const char* slrf_batch_last_error(slrf_batch b) { return b ? b->env.err.c_str() : "null batch"; }
@@ -1888,11 +2167,12 @@ slrf_status slrf_batch_add(slrf_batch b, int64_t n, const int32_t* a_rowptr, con
                                 env.err, nullptr, &nnz);
   if (st != SLRF_OK) return st;
   std::vector<JobShape> shapes = b->active_shapes();
-  shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz), false, use_bjac_for(env.opt.precond)});
+  shapes.push_back({n, nnz, (int)L, N, use_ilu_for(env.opt.precond, n, nnz), false, use_bjac_for(env.opt.precond),
+                    sgs_block_for(env.opt.precond)});
   if (filter_arena_bytes(shapes, env.opt.precision == SLRF_MIXED) > b->arena_bytes)
     return fail(env, SLRF_E_WORKSPACE, "the filter arena cannot hold this pencil next to the active ones");
   const bool warm = env.opt.recycle && env.opt.precision == SLRF_MIXED;
-  const size_t pb = pencil_bytes(n, nnz), ob = outer_bytes(n, L, N, warm);
+  const size_t pb = pencil_bytes(n, nnz, env.opt.precond), ob = outer_bytes(n, L, N, warm);
   char* pm = b->pool.alloc(pb);
   if (!pm) return fail(env, SLRF_E_WORKSPACE, "no room for the pencil in the workspace");
   char* om = b->pool.alloc(ob);
@@ -1955,6 +2235,24 @@ slrf_status slrf_batch_result(slrf_batch b, int32_t id, int64_t* n_found, double
   return SLRF_OK;
 }
 
+slrf_status slrf_batch_restart(slrf_batch b, int32_t id, const double* d_V0) {
+  if (!b) return SLRF_E_INVALID_ARG;
+  auto it = b->entries.find(id);
+  if (it == b->entries.end()) return fail(b->env, SLRF_E_INVALID_ARG, "unknown pencil id");
+  Env& env = b->env;
+  const SolveJob& old = *it->second.J;
+  auto J = std::make_unique<SolveJob>();
+  J->P = old.P;
+  J->L = old.L;
+  // the same device buffers, sized for the batch's max_N at add
+  J->carve(old.mem, b->max_N, env.opt.recycle && env.opt.precision == SLRF_MIXED);
+  const slrf_poles poles{old.N, old.sig.data(), old.w.data()};
+  const slrf_status st = prepare_job(env, *J, old.gamma, &poles, d_V0, b->max_N);
+  if (st != SLRF_OK) return st;
+  it->second.J = std::move(J);
+  return SLRF_OK;
+}
+
 slrf_status slrf_batch_remove(slrf_batch b, int32_t id) {
   if (!b) return SLRF_E_INVALID_ARG;
   auto it = b->entries.find(id);
@@ -1977,10 +2275,15 @@ size_t slrf_test_gram_scratch(int64_t n, int64_t L) {
 
 int slrf_test_gram(int64_t n, int64_t L, const double* U, const double* WA, const double* WB, double* GA,
                    double* GB, void* scratch, size_t scratch_bytes, void* hip_stream) {
+  return slrf_test_gram_prec(n, L, U, WA, WB, GA, GB, scratch, scratch_bytes, 0, hip_stream);
+}
+
+int slrf_test_gram_prec(int64_t n, int64_t L, const double* U, const double* WA, const double* WB, double* GA,
+                        double* GB, void* scratch, size_t scratch_bytes, int f32, void* hip_stream) {
   if (n < 1 || L < 1 || !U || !WA || !WB || !GA || !GB || scratch_bytes < slrf_test_gram_scratch(n, L))
     return SLRF_E_INVALID_ARG;
   hipStream_t s = (hipStream_t)hip_stream;
-  launch_gram(s, (int)n, (int)L, U, WA, WB, (double*)scratch, gram_chunks((int)n, (int)L), GA, GB);
+  launch_gram(s, (int)n, (int)L, U, WA, WB, (double*)scratch, gram_chunks((int)n, (int)L), GA, GB, f32 != 0);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return SLRF_E_DEVICE;
   return SLRF_OK;
 }

@@ -5,6 +5,7 @@ and the shared input generator ``pencils``.
     python tests/golden/make_golden.py count_c2  # inertia count of the 64^3 scalar pencil
     python tests/golden/make_golden.py eig_c2    # eigenvalues of the 64^3 scalar pencil in (0, 421]
     python tests/golden/make_golden.py eig_c3    # eigenvalues of the 48^3-node elasticity pencil
+    python tests/golden/make_golden.py count_c3  # inertia count of that pencil at its gamma
 
 Pole tables: the oracle's SLRF design (ridge-regularised least squares, see
 oracle/poles.py) at gamma = 1, alpha = 1, beta = 0.01 (the paper's Section 4.2
@@ -99,6 +100,22 @@ def make_eig_c2():
     _log(f"c2: {out['count']} eigenvalues, max rho {out['max_rho']:.2e}")
 
 
+def make_count_c3():
+    """Sylvester count of A - gamma B for the elasticity pencil at the gamma that
+    make_eig_c3 stored (sparse symmetric factorisation)."""
+    p = pencils.c3_elasticity()
+    path = os.path.join(HERE, "eig_elast3d_48_s3.json")
+    with open(path) as f:
+        d = json.load(f)
+    t = time.time()
+    c = inertia.sparse_ldl_count(p.A, p.B, d["gamma"])
+    d["sparse_ldl_count"] = c
+    d["sparse_ldl_seconds"] = time.time() - t
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+    _log(f"c3 count at gamma {d['gamma']}: {c} (eigenvalues stored: {d['count']})")
+
+
 def make_eig_c3():
     """Eigenvalues of the elasticity pencil below 112, then gamma in the middle of
     the widest gap (relative width >= 1e-4) that leaves 195..205 below it."""
@@ -116,7 +133,6 @@ def make_eig_c3():
            "relative_gap": gap, "eigenvalues": th[:k].tolist(),
            "next_eigenvalue": float(th[k]), "max_rho": float(r.rho[:k].max()),
            "subspace": 520, "iterations": r.iterations, "converged": bool(r.converged),
-           "inertia_counts": _block_counts(p, gamma),
            "source": "oracle.shift_invert.subspace_iteration (shift 0, banded Cholesky)",
            "seconds": secs}
     with open(os.path.join(HERE, "eig_elast3d_48_s3.json"), "w") as f:
@@ -134,3 +150,5 @@ if __name__ == "__main__":
         make_eig_c2()
     if "eig_c3" in what:
         make_eig_c3()
+    if "count_c3" in what:
+        make_count_c3()

@@ -216,6 +216,25 @@ def test_mfma_gemm_kernel(slrf, torch, n, L, r):
     assert e < 1e-12 * L * 10
 
 
+@pytest.mark.parametrize("n,L", [(1000, 40), (3001, 128), (777, 200)])
+def test_mfma_gram_kernel_f32(slrf, torch, n, L):
+    """The FP32 MFMA Gram (first projection of a mixed-precision outer
+    iteration): the products of the inputs rounded to FP32, with the error of
+    FP32 accumulation, |err| <= 1e-5 (|U|^T |W|) elementwise.  A wrong
+    accumulator layout would misplace whole 16 x 16 tiles."""
+    rng = np.random.default_rng(n + L + 1)
+    U, WA, WB = (rng.standard_normal((n, L)) for _ in range(3))
+    say(f"case gram fp32 n={n} L={L}")
+    GA, GB = slrf.test_gram(*(torch.from_numpy(x).cuda() for x in (U, WA, WB)), f32=True)
+    r = lambda a: a.astype(np.float32).astype(np.float64)
+    for G, W in ((GA, WA), (GB, WB)):
+        ref = r(U).T @ r(W)
+        bound = 1e-5 * (np.abs(U).T @ np.abs(W))
+        err = np.abs(G.cpu().numpy() - ref)
+        say(f"  max err / bound {(err / bound).max():.3f}")
+        assert np.all(err <= bound)
+
+
 @pytest.mark.parametrize("iters", [1, 2, 5])
 def test_bicgstab_ilu0_iterates_match_oracle(slrf, torch, iters):
     """ILU(0)-preconditioned iterates (narrow pattern) against the oracle's."""

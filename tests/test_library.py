@@ -63,7 +63,15 @@ def test_quadrature_poles_match_oracle(lib, rule):
 
 @pytest.mark.parametrize("N", [4, 6])
 def test_design_matches_oracle_tables(lib, N):
-    """Product pole design (host C++) vs the oracle's design (stored tables)."""
+    """Product pole design (host C++) vs the oracle's design (stored tables).
+
+    Section 3.1 admits abscissae x_j in (0, gamma], closed at gamma.  The N = 4
+    optimum is interior and both designers reach it: tight tolerances.  For
+    N = 6 the fit is flat along the largest abscissa near x = gamma: the
+    product's Levenberg-Marquardt reaches x = gamma to rounding while SciPy's
+    stops just inside; there the product's objective must be no worse than the
+    oracle's and close to it, with the same arrangement of poles and the same
+    separation factor."""
     with open(os.path.join(GOLDEN, f"poles_N{N}_a1_b0.01.json")) as f:
         d = json.load(f)
     s_or = np.array(d["sigma_re"]) + 1j * np.array(d["sigma_im"])
@@ -73,15 +81,16 @@ def test_design_matches_oracle_tables(lib, N):
     rows = poles.trapezoid_rows(0.01)
     J_prod = poles.objective(s.real, 1.0, rows)
     J_or = poles.objective(s_or.real, 1.0, rows)
-    # The fit of Section 3.1 is non-convex and flat near its minimum: the two LM
-    # implementations may stop at neighbouring stationary points (for N = 6 the
-    # product's largest pole sits on the end x = gamma of the admissible range).
-    # The product must be no worse than the oracle, with the same arrangement of
-    # poles and the same separation factor.
     assert J_prod <= J_or * (1 + 1e-9)
-    assert np.abs(s - s_or).max() < 5e-3
-    assert np.abs(w - w_or).max() < 0.1 * np.abs(w_or).max()
     assert abs(sep - d["separation_factor"]) < 1e-3 * d["separation_factor"]
+    if N == 4:
+        assert np.abs(s - s_or).max() < 2e-5
+        assert np.abs(w - w_or).max() < 1e-4 * np.abs(w_or).max()
+    else:
+        assert J_prod >= J_or * (1 - 1e-4)
+        assert s.real.max() > 0.995 and s_or.real.max() > 0.995   # the end of the admissible range
+        assert np.abs(s - s_or).max() < 5e-3
+        assert np.abs(w - w_or).max() < 0.1 * np.abs(w_or).max()
 
 
 def test_design_gamma_scaling(lib):
@@ -215,3 +224,18 @@ def test_batch_create_and_add_validate_before_device_use(lib):
     assert st == 0
     assert lib._lib.slrf_batch_remove(h, 7) == 1
     lib._lib.slrf_batch_destroy(h)
+
+
+def test_sgs_options_validated_on_the_host(lib):
+    """The multicolour SGS preconditioner (4 point, 5 node blocks) runs with COCG
+    only; the size query refuses it with BiCGStab and counts its colour tables."""
+    n, nnz, L, N = 3000, 3000 * 27, 32, 4
+    with pytest.raises(lib.SlrfError):
+        lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_BICGSTAB, precond=4))
+    with pytest.raises(lib.SlrfError):
+        lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=6))
+    jac = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=1))
+    sgs = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=4))
+    # two coupling CSRs ((a, b) in FP64 and FP32, column index) within the merged pattern's
+    # size, their row pointers, the colour tables, and R = sqrt(d) per (row, pole)
+    assert 0 < sgs - jac < 2 * (nnz + 16) * 28 + 4 * (n + 1) * 4 + 1025 * 4 + n * N * 16 + 2 ** 16
