@@ -212,6 +212,30 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n,
                         void* d_workspace, size_t ws_bytes, int64_t max_L, int32_t max_poles,
                         const slrf_options* opt, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc, harnesses without an
+ * allocator): slrf_create without a workspace argument.  The context lives in a
+ * file-scope device array of SLRF_STATIC_SCRATCH_BYTES (64 MiB) that the
+ * library holds on every device it runs on until the process ends; the device
+ * is the current one at this call.  The call and every later call on the
+ * context allocate no device memory.  Arguments, validation and the returned
+ * context are those of slrf_create; the caller still passes the dense blocks.
+ * Limits and errors:
+ *  - SLRF_E_WORKSPACE if the pencil needs more than SLRF_STATIC_SCRATCH_BYTES
+ *    (slrf_workspace_bytes_for gives the need), or if another context made by
+ *    this call still holds the device's array: one such context per device at
+ *    a time; slrf_destroy releases it (after waiting for its stream).
+ *  - SLRF_E_DEVICE if the array's device address cannot be obtained.
+ * The array keeps the last call's contents; the library clears what it needs
+ * cleared on each call.  Work on the context is queued on its stream, as for
+ * any context: overlapping calls on it from several threads race. */
+#define SLRF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+slrf_status slrf_create_static(slrf_ctx* out, int64_t n,
+                               const int32_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                               const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                               int64_t max_L, int32_t max_poles, const slrf_options* opt,
+                               void* hip_stream);
+
 /* One filter application (Algorithm 1, the "Solve" loop and "Compute U"):
  *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
  * every (pole, column) system solved by right-preconditioned BiCGStab (the

@@ -74,6 +74,8 @@ _lib.slrf_workspace_bytes_for.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_i
                                           C.POINTER(C.c_size_t)]
 _lib.slrf_create.argtypes = [C.POINTER(_P), C.c_int64, _P, _P, _P, _P, _P, _P, _P, C.c_size_t,
                              C.c_int64, C.c_int32, C.POINTER(Options), _P]
+_lib.slrf_create_static.argtypes = [C.POINTER(_P), C.c_int64, _P, _P, _P, _P, _P, _P,
+                                    C.c_int64, C.c_int32, C.POINTER(Options), _P]
 _lib.slrf_filter_apply.argtypes = [_P, C.POINTER(Poles), C.c_int64, _P, _P, C.POINTER(FilterStats)]
 _lib.slrf_solve_interval.argtypes = [_P, C.c_double, C.c_int64, C.POINTER(Poles), _P,
                                      C.POINTER(C.c_int64), _P, _P, _P, C.POINTER(SolveStats)]
@@ -100,6 +102,7 @@ _lib.slrf_batch_destroy.argtypes = [_P]
 _lib.slrf_batch_last_error.argtypes = [_P]
 _lib.slrf_batch_last_error.restype = C.c_char_p
 for _f in ("slrf_design_poles", "slrf_workspace_bytes", "slrf_workspace_bytes_for", "slrf_create",
+           "slrf_create_static",
            "slrf_filter_apply",
            "slrf_solve_interval", "slrf_batch_footprint", "slrf_batch_footprint_for", "slrf_batch_create",
            "slrf_batch_add",
@@ -118,7 +121,7 @@ _lib.slrf_test_gram_scratch.restype = C.c_size_t
 
 EXPORTED = ["slrf_default_options", "slrf_design_poles", "slrf_quadrature_poles", "slrf_workspace_bytes",
             "slrf_workspace_bytes_for",
-            "slrf_create",
+            "slrf_create", "slrf_create_static",
             "slrf_filter_apply", "slrf_solve_interval", "slrf_destroy", "slrf_status_string",
             "slrf_last_error", "slrf_batch_footprint", "slrf_batch_footprint_for", "slrf_batch_create",
             "slrf_batch_add",
@@ -254,10 +257,11 @@ class Solver:
     """A context over one pencil (A, B) with a workspace sized for (max_L, max_poles)."""
 
     def __init__(self, A, B, max_L: int, max_poles: int, options: Options | None = None,
-                 device: str = "cuda:0", stream=None, workspace=None):
-        """workspace: a caller-owned uint8 tensor on the device of at least
-        workspace_bytes(...) bytes (default: one is allocated); the context uses
-        it until close()."""
+                 device: str = "cuda:0", stream=None, static_scratch: bool = False, workspace=None):
+        """static_scratch: build the context with slrf_create_static (no workspace
+        tensor; the library's per-device static array instead).  workspace: a
+        caller-owned uint8 tensor on the device of at least workspace_bytes(...)
+        bytes (default: one is allocated); the context uses it until close()."""
         import torch
         self.torch = torch
         self.n, nnz, arrs = _csr_arrays(A, B)
@@ -265,17 +269,24 @@ class Solver:
         self.options = options or default_options()
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._h = C.c_void_p()
-        self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, options=self.options)
-        if workspace is None:
-            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        elif (workspace.dtype != torch.uint8 or workspace.device != self.device
-              or not workspace.is_contiguous() or workspace.numel() < self.ws_bytes):
-            raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device} "
-                             f"of at least {self.ws_bytes} bytes")
-        self.workspace = workspace
-        st = _lib.slrf_create(C.byref(self._h), self.n, *[_ptr(a) for a in arrs],
-                              C.c_void_p(self.workspace.data_ptr()), self.ws_bytes, max_L, max_poles,
-                              C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
+        if static_scratch:
+            self.ws_bytes, self.workspace = 0, None
+            with torch.cuda.device(self.device):
+                st = _lib.slrf_create_static(C.byref(self._h), self.n, *[_ptr(a) for a in arrs], max_L,
+                                             max_poles, C.byref(self.options),
+                                             C.c_void_p(self.stream.cuda_stream))
+        else:
+            self.ws_bytes = workspace_bytes(self.n, nnz, max_L, max_poles, options=self.options)
+            if workspace is None:
+                workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            elif (workspace.dtype != torch.uint8 or workspace.device != self.device
+                  or not workspace.is_contiguous() or workspace.numel() < self.ws_bytes):
+                raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device} "
+                                 f"of at least {self.ws_bytes} bytes")
+            self.workspace = workspace
+            st = _lib.slrf_create(C.byref(self._h), self.n, *[_ptr(a) for a in arrs],
+                                  C.c_void_p(self.workspace.data_ptr()), self.ws_bytes, max_L, max_poles,
+                                  C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
         if st:
             msg = self.last_error()
             self.close()

@@ -1887,7 +1887,26 @@ struct slrf_ctx_s {
   int64_t max_L = 0;
   int32_t max_N = 0;
   size_t arena_off = 0, arena_bytes = 0, outer_off = 0;
+  int static_dev = -1;  // device whose static scratch this context holds (slrf_create_static)
 };
+
+// ---- static scratch for callers that cannot allocate ---------------------------
+//
+// slrf_create_static runs a context inside this file-scope array instead of a
+// caller workspace.  Each device the library runs on holds its own copy until
+// the process ends.  Host code never uses the array's name as an address: the
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and kept in g_scratch_ptr.  One context at a time may hold a
+// device's array; the library clears whatever it needs zeroed on every call, so
+// what an earlier context left there does not matter.
+static __device__ __align__(256) unsigned char scratch[SLRF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_held[kMaxDevices] = {};
+}  // namespace
 
 // Batch of pencils: [timer counters | filter arena | pool of pencils and outer buffers]
 struct slrf_batch_s {
@@ -2005,6 +2024,42 @@ slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz, int64_t L, int32_t N, i
   return slrf_workspace_bytes_for(n, nnz, L, N, &o, bytes);
 }
 
+slrf_status slrf_create_static(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
+                               const double* a_val, const int32_t* b_rowptr, const int32_t* b_col,
+                               const double* b_val, int64_t max_L, int32_t max_N, const slrf_options* opt,
+                               void* hip_stream) {
+  if (!out) return SLRF_E_INVALID_ARG;
+  *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SLRF_E_DEVICE;
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SLRF_E_DEVICE;
+      g_scratch_ptr[dev] = ptr;
+    }
+    ptr = g_scratch_ptr[dev];
+    if (g_scratch_held[dev]) {
+      slrf_ctx c = new (std::nothrow) slrf_ctx_s();
+      if (!c) return SLRF_E_WORKSPACE;
+      c->env.err = "the static scratch of device " + std::to_string(dev) + " is held by another context";
+      *out = c;
+      return SLRF_E_WORKSPACE;
+    }
+    g_scratch_held[dev] = true;
+  }
+  const slrf_status st = slrf_create(out, n, a_rowptr, a_col, a_val, b_rowptr, b_col, b_val, ptr,
+                                     SLRF_STATIC_SCRATCH_BYTES, max_L, max_N, opt, hip_stream);
+  if (*out) {
+    (*out)->static_dev = dev;  // released by slrf_destroy, also after a failed create
+  } else {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch_held[dev] = false;
+  }
+  return st;
+}
+
 slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const int32_t* a_col,
                         const double* a_val, const int32_t* b_rowptr, const int32_t* b_col, const double* b_val,
                         void* d_workspace, size_t ws_bytes, int64_t max_L, int32_t max_N, const slrf_options* opt,
@@ -2048,6 +2103,12 @@ slrf_status slrf_create(slrf_ctx* out, int64_t n, const int32_t* a_rowptr, const
 
 void slrf_destroy(slrf_ctx ctx) {
   if (!ctx) return;
+  if (ctx->static_dev >= 0) {
+    // work queued in the static scratch must finish before another context may use it
+    (void)hipStreamSynchronize(ctx->env.stream);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch_held[ctx->static_dev] = false;
+  }
   delete ctx;
 }
 
