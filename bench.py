@@ -1,40 +1,41 @@
 """Benchmark: eigenpairs/s of the SLRF interval eigensolver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|batched|served|filters]
-                    [--precision both|mixed|fp64] [--no-cpu-baseline]
-    python bench.py --counters-probe | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|batched|served|filters]
+                    [--precond sgs|jacobi] [--no-c2] [--no-cpu-baseline]
+    python bench.py --counters-probe [--workload c3] | --summarize-pmc FETCH_CSV WRITE_CSV PROBE_LOG
+    python bench.py --mfma-probe | --summarize-mfma PMC_CSV TRACE_CSV
 
-A step is one complete slrf_solve_interval (filter application with the shifted
-BiCGStab solves over all poles and columns, filter sum, B-orthonormalising
-Rayleigh-Ritz and residuals, repeated until every Ritz pair in (0, gamma] has
-relative residual <= 1e-8) on synthetic, seeded input resident in HBM.
+Default workload c3: 3D linear elasticity on trilinear hexahedra, 48^3 free
+nodes x 3 unknowns (n = 331776, 81 nnz/row, clamped x = 0 face, log-normal
+Young's modulus sigma 0.7 seed 3, nu 0.3, density U[0.8, 1.2]), consistent mass;
+gamma from the oracle's eigenvalues (mid-gap, 199 below it); L = 256, N = 8 SLRF
+poles (alpha 1, beta 0.01); mixed precision (complex FP32 COCG with FP64 defect
+correction, FP64 Rayleigh-Ritz and residuals), the multicolour node-block
+symmetric Gauss-Seidel preconditioner, warm starts across outer iterations.
 
-Workload c2 (default): 3D scalar vibration pencil, trilinear hexahedra on a
-64^3 grid of the unit cube with Dirichlet boundary (n = 250047, 27 nnz/row),
-log-normal coefficient (sigma 0.5, seed 2), consistent mass; gamma = 421
-(87 eigenvalues below it, Sylvester count from the oracle); L = 128, N = 6 SLRF
-poles (alpha 1, beta 0.01).  `value` is the mixed-precision form (complex FP32
-BiCGStab with FP64 defect correction, FP64 Rayleigh-Ritz and residuals); the
-plain FP64 form (complex FP64 BiCGStab, point Jacobi, inner tolerance 1e-13) is
-timed in the same run and reported under "fp64" for the comparison.
+A step is one outer iteration of Algorithm 1 on the workload (filter
+application, filter sum, Rayleigh-Ritz, residuals); complete solves run back to
+back and each is checked against the oracle's eigenvalues.  `value` counts the
+eigenpairs of the solves that ran entirely inside the K timed steps over the
+time of their steps.  Beside it, the 64^3 scalar pencil (C2) is solved once in
+the mixed and once in the FP64 form ("c2_64cube").
 
 Prints one JSON line.  `roofline` is measured live: HIP events around every
-launch of the dominant kernel (the complex-shifted sparse product) during the
-timed steps, against its algorithmic bytes (each processed column tile reads its
-input block and writes its output block once, the merged CSR once per launch).
-`roofline.traffic` is the HBM bytes per launch from the rocprofv3 FETCH_SIZE and
-WRITE_SIZE passes summarised in profiles/spmm_c2_pmc.txt (each scaled by what
-the counter reads for a copy kernel of known size), scaled to the launches of
-the timed steps; it is null when the kernel sources differ from the ones the
-counters were taken with.  `cpu_baseline` times the FP64 oracle's BiCGStab on a
-bounded sample of the same workload on the host and scales it to the whole
+launch of the dominant kernel (the COCG iteration's colour sweeps, which carry
+the product with A - sigma B) during the timed steps, against its algorithmic
+bytes.  `roofline.traffic` is the bytes per launch from the rocprofv3
+FETCH_SIZE and WRITE_SIZE passes summarised in profiles/spmm_c3_pmc.txt (each
+scaled by what the counter reads for a copy kernel of known size), scaled to the
+launches of the timed steps; it is null when the kernel sources differ from the
+ones the counters were taken with.  `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload on the host's cores and scales it to one
 solve.
 
-Counter collection (the probe runs full-width launches of the sparse product):
-    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_spmm|k_cocg_spmm|elementwise" \
-        --output-format csv -d <dir> -o run -- python3 bench.py --counters-probe
+Counter collection (the probe runs full-width launches of the products):
+    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_spmm|k_cocg_spmm|k_sgs_sweep|elementwise" \
+        --output-format csv -d <dir> -o run -- python3 bench.py --counters-probe --workload c3
     (again with WRITE_SIZE)
-    python bench.py --summarize-pmc <fetch csv> <write csv>  > profiles/spmm_c2_pmc.txt
+    python bench.py --summarize-pmc <fetch csv> <write csv> <probe log> --workload c3 > profiles/spmm_c3_pmc.txt
 """
 import argparse
 import csv
@@ -127,12 +128,14 @@ def _sample_worker(task):
     kind, k = task
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        if kind == "inner":
-            pc = "bjac3" if wl.get("precond", 0) == 3 else "jacobi"
+        if kind in ("inner", "setup"):
+            # "setup": the same call with no iteration (the preconditioner set-up and
+            # the start), which the iteration samples subtract
+            pc = {3: "bjac3", 4: "mcsgs", 5: "mcsgs3"}.get(wl.get("precond", 0), "jacobi")
             F = p.B @ pencils.start_block(p.n, _SAMPLE["cols"], 77 + k)
             solve = krylov.cocg if wl.get("solver", 0) == 1 else krylov.bicgstab
-            solve(p.A, p.B, sig[k % len(sig):k % len(sig) + 1], F, 0.0, _SAMPLE["iters"],
-                  fixed_iters=_SAMPLE["iters"], precond=pc)
+            its = _SAMPLE["iters"] if kind == "inner" else 0
+            solve(p.A, p.B, sig[k % len(sig):k % len(sig) + 1], F, 0.0, its, fixed_iters=its, precond=pc)
         elif kind == "mgs":
             subspace.mgs_b(pencils.start_block(p.n, _SAMPLE["mgs_cols"], 99 + k), p.B)
         else:
@@ -152,7 +155,7 @@ def cpu_sample(wl, sig):
     import multiprocessing as mp
     import platform
     ncpu = os.cpu_count() or 1
-    P = max(1, min(ncpu, 16))
+    P = max(2, min(ncpu, 16))     # one worker times the set-up, the others the iterations
     big = wl["pencil"].A.nnz > 1e7
     _SAMPLE.update(wl=wl, sig=sig, cols=4, iters=4 if big else 12, mgs_cols=6, res_cols=16)
     model = ""
@@ -167,32 +170,37 @@ def cpu_sample(wl, sig):
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(P) as pool:
-        inner = pool.map(_sample_worker, [("inner", k) for k in range(P)])
+        timed = pool.map(_sample_worker, [("setup", 0)] + [("inner", k) for k in range(1, P)])
         mgs = pool.map(_sample_worker, [("mgs", k) for k in range(P)])
         res = pool.map(_sample_worker, [("res", k) for k in range(P)])
     wall = time.perf_counter() - t0
     c, it, m, rc = _SAMPLE["cols"], _SAMPLE["iters"], _SAMPLE["mgs_cols"], _SAMPLE["res_cols"]
     # per unit of work, with P workers sharing the host: seconds of wall time per unit
+    setup = timed[0]
+    inner = [max(0.0, t - setup) for t in timed[1:]] or [0.0]
     return {"workers": P, "host_cpus": ncpu, "cpu_model": model, "wall_seconds": wall,
-            "s_per_column_iteration": max(inner) / (P * c * it),
+            "s_per_column_iteration": max(inner) / (max(1, P - 1) * c * it),
+            "s_setup_per_pole": setup,
             # mgs_b on m columns: 2 passes of m (m - 1) / 2 projections and 2 m norms,
             # each one product with B: m (m + 3) products
             "s_per_b_product": max(mgs) / (P * m * (m + 3)),
             "s_per_residual_column": max(res) / (P * rc),
             "sample": (f"{P} forked workers on {ncpu} host CPUs ({model}): oracle inner solver on 1 pole x {c} "
-                       f"columns x {it} iterations each, oracle.subspace.mgs_b on {m} columns each, "
+                       f"columns x {it} iterations in {P - 1} of them, its set-up alone in the other, "
+                       f"oracle.subspace.mgs_b on {m} columns each, "
                        f"oracle.subspace.relative_residuals on {rc} columns each; {wall:.1f} s wall")}
 
 
-def cpu_baseline(smp, solve_stats, L):
+def cpu_baseline(smp, solve_stats, L, N):
     """Scales the oracle sample to one complete solve of the workload: the GPU
-    solve's column-iterations (products with A - sigma B), plus per outer
-    iteration the oracle's two-pass B-Gram-Schmidt of the L filtered columns
-    (L (L + 3) products with B) and its residuals of the L Ritz pairs."""
+    solve's column-iterations (products with A - sigma B), the preconditioner
+    set-up of the N poles once, plus per outer iteration the oracle's two-pass
+    B-Gram-Schmidt of the L filtered columns (L (L + 3) products with B) and its
+    residuals of the L Ritz pairs."""
     outer = solve_stats["outer_iterations"]
     col_its = solve_stats["spmv_total"]
-    est = (col_its * smp["s_per_column_iteration"] + outer * L * (L + 3) * smp["s_per_b_product"]
-           + outer * L * smp["s_per_residual_column"])
+    est = (col_its * smp["s_per_column_iteration"] + N * smp["s_setup_per_pole"]
+           + outer * L * (L + 3) * smp["s_per_b_product"] + outer * L * smp["s_per_residual_column"])
     return {"value": solve_stats["n_found"] / est, "unit": "eigenpairs/s", "cores": smp["workers"],
             "kind": "oracle", "host_cpus": smp["host_cpus"], "cpu_model": smp["cpu_model"],
             "sample": smp["sample"] + (f"; scaled to one solve: {col_its} column-iterations, {outer} outer "
@@ -314,9 +322,10 @@ def summarize_pmc(fetch_csv, write_csv, probe_log, wl_key="c2"):
     fw = wr["copy"][0] / kib
     what = ("3D scalar vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768)" if wl_key == "c2" else
             "3D elasticity pencil 48^3 nodes x 3 (n=331776, 81 nnz/row), L=256, N=8 (K=2048)")
-    print("# HBM traffic of the complex-shifted sparse products (BiCGStab: k_spmm_v, k_spmm_t; COCG:")
-    print(f"# k_cocg_spmm), {what},")
-    print("# full-width launches.")
+    print("# Memory traffic of the complex-shifted sparse products (BiCGStab: k_spmm_v, k_spmm_t; COCG:")
+    print("# k_cocg_spmm; multicolour SGS: the iteration sweeps k_sgs_sweep, backward and forward),")
+    print(f"# {what}, full-width launches.  FETCH_SIZE and WRITE_SIZE count the L2's")
+    print("# traffic to the memory fabric (served by the MALL or by HBM).")
     print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
     print("#   rocprofv3 --pmc FETCH_SIZE --kernel-include-regex \"k_spmm|k_cocg_spmm|k_sgs_sweep|elementwise\" --output-format csv "
           f"-d R/gpurun_out/pmc_fetch -o run -- python3 R/bench.py --counters-probe --workload {wl_key}")
@@ -352,6 +361,77 @@ def summarize_pmc(fetch_csv, write_csv, probe_log, wl_key="c2"):
             print(f"full_launch_traffic_bytes {key}: {tot / len(kerns):.6e}")
             print(f"full_launch_algorithmic_bytes {key}: {a:.6e}")
             print(f"traffic_over_algorithmic {key}: {tot / len(kerns) / a:.3f}")
+
+
+MFMA_COUNTERS = ["SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_VALU_MFMA_BUSY_CYCLES",
+                 "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE"]
+MFMA_SHAPE = (331776, 256)        # the elasticity workload's n and L
+
+
+def mfma_probe():
+    """Short run for the MFMA counter pass: the Rayleigh-Ritz Gram kernel (FP64 and
+    the FP32 first-pass variant) and the Ritz update at the elasticity workload's
+    size, three launches each, through the kernel-level hooks."""
+    import torch
+
+    import paper_2503_21618_amd as slrf
+    n, L = MFMA_SHAPE
+    g = torch.Generator(device="cuda").manual_seed(3)
+    U, WA, WB = (torch.randn((n, L), dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
+    Z = torch.randn((L, L), dtype=torch.float64, device="cuda", generator=g)
+    for _ in range(3):
+        slrf.test_gram(U, WA, WB)
+        slrf.test_gram(U, WA, WB, f32=True)
+        slrf.test_gemm(U, Z)
+    torch.cuda.synchronize()
+    print(json.dumps({"n": n, "L": L, "gram_flops": 4.0 * n * L * L, "gemm_flops": 2.0 * n * L * L}), flush=True)
+
+
+def summarize_mfma(pmc_csv, trace_csv):
+    """MFMA use of k_gram / k_gemm_nz from one rocprofv3 --pmc pass (MFMA_COUNTERS)
+    and the kernel durations of a --kernel-trace run of the same probe."""
+    vals, durs = {}, {}
+    with open(pmc_csv) as f:
+        for row in csv.DictReader(f):
+            m = re.search(r"(k_gram<(true|false)>|k_gemm_nz)", row["Kernel_Name"])
+            if m and row["Counter_Name"] in MFMA_COUNTERS:
+                key = m.group(1)
+                vals.setdefault(key, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    with open(trace_csv) as f:
+        for row in csv.DictReader(f):
+            m = re.search(r"(k_gram<(true|false)>|k_gemm_nz)", row["Kernel_Name"])
+            if m:
+                durs.setdefault(m.group(1), []).append(
+                    (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9)
+    n, L = MFMA_SHAPE
+    alg = {"k_gram<false>": 4.0 * n * L * L, "k_gram<true>": 4.0 * n * L * L, "k_gemm_nz": 2.0 * n * L * L}
+    peak = {"k_gram<false>": 78.6e12, "k_gram<true>": 157.3e12, "k_gemm_nz": 78.6e12}
+    print(f"# MFMA use of the Rayleigh-Ritz kernels at n={n}, L={L} (three launches each).")
+    print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
+    print(f"#   rocprofv3 --pmc {' '.join(MFMA_COUNTERS)} --kernel-include-regex \"k_gram|k_gemm_nz\" "
+          "--output-format csv -d R/gpurun_out/pmc_mfma -o run -- python3 R/bench.py --mfma-probe")
+    print("#   rocprofv3 --kernel-trace --kernel-include-regex \"k_gram|k_gemm_nz\" --output-format csv "
+          "-d R/gpurun_out/trace_mfma -o run -- python3 R/bench.py --mfma-probe")
+    print("#   python3 bench.py --summarize-mfma <pmc csv> <kernel trace csv>")
+    print("# MOPS counters count MFMA work in units of 512 flops; busy fraction = MFMA busy cycles /")
+    print("# (GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs x 4 SIMDs); achieved = algorithmic flops / mean")
+    print("# duration (kernel trace), against the dense MFMA peak of the instruction's type.")
+    for key in ("k_gram<false>", "k_gram<true>", "k_gemm_nz"):
+        if key not in vals or key not in durs:
+            continue
+        v = {c: sum(x) / len(x) for c, x in vals[key].items()}
+        d = sum(durs[key]) / len(durs[key])
+        mops = v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) + v.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+        # GRBM_GUI_ACTIVE is summed over the 8 XCDs; the busy cycles over the SIMDs
+        busy = v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / max(1.0, v.get("GRBM_GUI_ACTIVE", 0.0) / 8 * 256 * 4)
+        print(f"{key} mean duration ms: {1e3 * d:.3f}")
+        for c in MFMA_COUNTERS:
+            if c in v:
+                print(f"{key} {c}: {v[c]:.4e}")
+        print(f"{key} MFMA flops from MOPS: {512 * mops:.4e} (algorithmic {alg[key]:.4e})")
+        print(f"{key} MFMA busy fraction: {busy:.3f}")
+        print(f"{key} achieved TFLOP/s: {alg[key] / d / 1e12:.2f} of {peak[key] / 1e12:.1f} "
+              f"({alg[key] / d / peak[key]:.3f})")
 
 
 def union_nnz(p):
@@ -890,7 +970,7 @@ def main_c3(slrf, args):
                             ("multicolour symmetric Gauss-Seidel" if args.precond == "sgs" else "point Jacobi"), **legs,
                             "mixed_over_fp64": legs["mixed"]["value"] / legs["fp64"]["value"]}
     if smp is not None:
-        out["cpu_baseline"] = cpu_baseline(smp, last, wl["L"])
+        out["cpu_baseline"] = cpu_baseline(smp, last, wl["L"], wl["N"])
     print(json.dumps(out), flush=True)
 
 
@@ -932,9 +1012,16 @@ def main():
                     help="short run for the rocprofv3 counter passes (see the module docstring)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
                     help="print the counter summary from two rocprofv3 CSVs")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="short run of the Rayleigh-Ritz MFMA kernels for the MFMA counter pass")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("PMC_CSV", "TRACE_CSV"),
+                    help="print the MFMA summary from the counter pass and a kernel trace")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, wl_key=args.workload)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the pole-sharded "
@@ -943,6 +1030,9 @@ def main():
 
     if args.counters_probe:
         counters_probe(args.workload)
+        return
+    if args.mfma_probe:
+        mfma_probe()
         return
 
     import torch
@@ -987,6 +1077,11 @@ def main():
     wl["recycle"] = 1 if args.recycle == "1" or (args.recycle == "auto" and wl["solver"] == 1) else 0
     p = wl["pencil"]
     sig, w, _ = slrf.design_poles(wl["N"], 1.0, 0.01, wl["gamma"])
+    smp = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline sample (before the GPU is used)...")
+        smp = cpu_sample(wl, sig)
+        log(smp["sample"])
     V0 = torch.from_numpy(pencils.start_block(p.n, wl["L"], 1)).cuda()
     forms = {}
     if args.precision in ("both", "mixed"):
@@ -1053,10 +1148,9 @@ def main():
                                  "spmv_total": f["results"][-1].stats["spmv_total"],
                                  "max_resid": f["results"][-1].stats["max_resid"]}
         out["cocg_over_bicgstab"] = m["value"] / f["value"]
-    if not args.no_cpu_baseline:
-        log("cpu baseline sample...")
-        ref = forms.get("fp64", m)
-        out["cpu_baseline"] = cpu_baseline(wl, sig, ref["results"][-1].stats)
+    if smp is not None:
+        ref = forms.get("fp64", m)      # the oracle is FP64: scale by the FP64 solve's work when it ran
+        out["cpu_baseline"] = cpu_baseline(smp, ref["results"][-1].stats, wl["L"], wl["N"])
     print(json.dumps(out), flush=True)
 
 

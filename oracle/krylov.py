@@ -338,7 +338,9 @@ def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None
             return np.concatenate([block_jacobi3_solve(blks[j], Y[:, j * L:(j + 1) * L])
                                    for j in range(N)], axis=1)
     elif precond in ("mcsgs", "mcsgs3"):
-        sgs = [MulticolourSGS(A, B, s, 3 if precond == "mcsgs3" else 1) for s in sigmas]
+        block = 3 if precond == "mcsgs3" else 1
+        colour = greedy_colouring(A, B, block)      # depends on the pattern only
+        sgs = [MulticolourSGS(A, B, s, block, colour=colour) for s in sigmas]
 
         def Minv(Y):
             return np.concatenate([sgs[j].apply(Y[:, j * L:(j + 1) * L]) for j in range(N)], axis=1)
