@@ -446,11 +446,15 @@ def batch_kernel_stats(results):
 
 
 def many_options(slrf, args, precision, **kw):
-    """Options of the batched, served and serial runs (scalar pencils, point
-    Jacobi: COCG unless --solver bicgstab): with --graph (the default) the Krylov
-    iteration chunks replay as hipGraphs and the per-launch kernel timers are
-    off; with --no-graph the kernels are timed (roofline fields)."""
+    """Options of the batched, served and serial runs: COCG unless --solver
+    bicgstab, with the multicolour point SGS preconditioner (--precond sgs, the
+    default; one block size serves every pencil of a batch) or point Jacobi;
+    with --graph (the default) the Krylov iteration chunks replay as hipGraphs
+    and the per-launch kernel timers are off; with --no-graph the kernels are
+    timed (roofline fields)."""
     kw.setdefault("solver", slrf.SOLVER_BICGSTAB if args.solver == "bicgstab" else slrf.SOLVER_COCG)
+    kw.setdefault("precond", slrf.PRECOND_SGS if args.precond == "sgs" and kw["solver"] == slrf.SOLVER_COCG
+                  else slrf.PRECOND_AUTO)
     kw.setdefault("recycle", 1 if args.recycle == "1" or (args.recycle == "auto" and kw["solver"] == 1) else 0)
     if args.graph:
         return slrf.default_options(precision=precision, graph=1, profile=0, **kw)
@@ -499,14 +503,14 @@ def run_batched(slrf, args):
     log(f"built {len(insts)} pencils in {time.perf_counter() - t0:.1f} s, "
         f"sum n = {sum(p.n for p, *_ in insts)}")
     N = 6
+    opt = many_options(slrf, args, slrf.MIXED, tune=1)
     pers = trans = 0
     for p, g, L, _ in insts:
-        a, b = slrf.batch_footprint(p.n, union_nnz(p), L, N, slrf.MIXED)
+        a, b = slrf.batch_footprint(p.n, union_nnz(p), L, N, options=opt)
         pers += a + 4096
         trans += b
     ws = pers + trans + (1 << 24)
     log(f"workspace {ws / 2**30:.1f} GiB (filter arena {trans / 2**30:.1f} GiB)")
-    opt = many_options(slrf, args, slrf.MIXED, tune=1)
     b = slrf.Batch(ws, trans, max_poles=N, options=opt, stream=torch.cuda.Stream())
     ids = []
     for p, g, L, _ in insts:
@@ -533,10 +537,12 @@ def run_batched(slrf, args):
     out = {"value": found / dt, "seconds": dt, "found": found, "steps": steps,
            "statuses_not_ok": bad, "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
     if not args.no_serial:
-        log("serial solves...")
-        out["serial"] = serial_solves(slrf, args, [(p, g, L) for p, g, L, _ in insts],
-                                      slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
-                                      args.serial_limit)
+        items = [(p, g, L) for p, g, L, _ in insts]
+        for tag, prec in (("mixed", slrf.MIXED), ("fp64", slrf.FP64)):
+            if args.serial_precision in (tag, "both"):
+                log(f"serial solves ({tag})...")
+                key = "serial" if args.serial_precision != "both" or tag == "mixed" else "serial_fp64"
+                out[key] = serial_solves(slrf, args, items, prec, args.serial_limit)
     return out, insts
 
 
@@ -555,7 +561,7 @@ def run_served(slrf, args):
     N = 6
     opt = many_options(slrf, args, slrf.MIXED)
     stream = torch.cuda.Stream()
-    fps = [slrf.batch_footprint(p.n, union_nnz(p), L, N, slrf.MIXED) for p, g, L, _ in reqs]
+    fps = [slrf.batch_footprint(p.n, union_nnz(p), L, N, options=opt) for p, g, L, _ in reqs]
     arena = int(args.arena_gb * 2**30)
     pool = int(args.pool_gb * 2**30)
     if max(t for _, t in fps) > arena or max(a for a, _ in fps) > pool:
@@ -682,7 +688,7 @@ def many_line(args, kind, out, desc):
         spmm_gbs = ks["spmm_bytes"] / ks["spmm_seconds"] / 1e9
         line["roofline"] = {"bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": None,
-                            "kernel": "k_spmm_v / k_spmm_t <float> (complex-shifted sparse product)",
+                            "kernel": "the complex-shifted sparse product or the SGS sweeps <float>",
                             "launches": ks["spmm_launches"],
                             "avg_launch_ms": 1e3 * ks["spmm_seconds"] / max(1, ks["spmm_launches"]),
                             "traffic_note": "counters are taken on the 64^3 scalar workload only"}
@@ -692,9 +698,10 @@ def many_line(args, kind, out, desc):
         line["roofline_note"] = ("hipGraph replay with kernel timers off; bench.py --no-graph times the "
                                  "kernels of this workload")
     line[kind] = out
-    ser = out.get("serial")
-    if ser and ser["value"] > 0:
-        line[f"over_serial_{ser['precision']}"] = out["value"] / ser["value"]
+    for key in ("serial", "serial_fp64"):
+        ser = out.get(key)
+        if ser and ser["value"] > 0:
+            line[f"over_serial_{ser['precision']}"] = out["value"] / ser["value"]
     return line
 
 
@@ -1006,7 +1013,7 @@ def main():
                     help="batched/served: time every kernel launch instead of replaying hipGraphs")
     ap.add_argument("--serial-limit", type=float, default=float("inf"),
                     help="stop the serial comparison after this many seconds of solves")
-    ap.add_argument("--serial-precision", default="fp64", choices=["fp64", "mixed"],
+    ap.add_argument("--serial-precision", default="fp64", choices=["fp64", "mixed", "both"],
                     help="precision of the one-pencil-at-a-time comparison")
     ap.add_argument("--counters-probe", action="store_true",
                     help="short run for the rocprofv3 counter passes (see the module docstring)")

@@ -269,41 +269,42 @@ __device__ __forceinline__ void shifted_group(int i0, cptr<int> rowptr, cptr<int
 
 constexpr int kNodeRows = 3;  // rows of a node triple (flags built on the host)
 constexpr int kNodeChunk = 8;
+constexpr int kSgsNodeChunk = 8;  // the same in the colour sweeps
 
 // Complex-shifted sparse product of a node triple: rows i0 .. i0 + 2 with the
 // same column list (checked on the host), so each input row is gathered once
 // for the three rows: a third of the gathers of three generic rows.  Entries
-// are taken in chunks of kNodeChunk (the CSR padding covers the overrun of the
+// are taken in chunks of NC (the CSR padding covers the overrun of the
 // last chunk; entries past the row end get zero coefficients and re-read row
 // i0, whose values PZ replaces by zeros as in shifted_row); each row's entries
 // are summed in entry order, as in shifted_row.
-template <typename R, int V, bool PZ = false>
+template <typename R, int V, bool PZ = false, int NC = kNodeChunk>
 __device__ __forceinline__ void shifted_node(int i0, cptr<int> rowptr, cptr<int> col, cptr<ab_pair<R>> ab,
                                              const cx<R>* __restrict__ Pc, int ld, const cx<R> (&sig)[V],
                                              cvec<R, V> (&q)[kNodeRows]) {
-  static_assert(kNodeChunk <= kCsrPad, "chunk longer than the CSR padding");
+  static_assert(NC <= kCsrPad, "chunk longer than the CSR padding");
   int kb[kNodeRows];
 #pragma unroll
   for (int r = 0; r < kNodeRows; ++r) kb[r] = rowptr[i0 + r];
   const int m = rowptr[i0 + 1] - kb[0];
   R apr[kNodeRows][V] = {}, api[kNodeRows][V] = {}, bpr[kNodeRows][V] = {}, bpi[kNodeRows][V] = {};
 #pragma unroll 1
-  for (int j = 0; j < m; j += kNodeChunk) {
-    int jj[kNodeChunk];
+  for (int j = 0; j < m; j += NC) {
+    int jj[NC];
 #pragma unroll
-    for (int u = 0; u < kNodeChunk; ++u) jj[u] = j + u < m ? col[kb[0] + j + u] : i0;
-    cvec<R, V> x[kNodeChunk];
+    for (int u = 0; u < NC; ++u) jj[u] = j + u < m ? col[kb[0] + j + u] : i0;
+    cvec<R, V> x[NC];
 #pragma unroll
-    for (int u = 0; u < kNodeChunk; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
+    for (int u = 0; u < NC; ++u) x[u] = ldv<R, V>(Pc + (size_t)jj[u] * ld);
     if constexpr (PZ) {
 #pragma unroll
-      for (int u = 0; u < kNodeChunk; ++u)
+      for (int u = 0; u < NC; ++u)
         if (j + u >= m) x[u] = cvec<R, V>{};
     }
 #pragma unroll
     for (int r = 0; r < kNodeRows; ++r) {
 #pragma unroll
-      for (int u = 0; u < kNodeChunk; ++u) {
+      for (int u = 0; u < NC; ++u) {
         ab_pair<R> ce = ldc(ab + kb[r] + j + u);
         if (j + u >= m) ce = ab_pair<R>{0, 0};
 #pragma unroll
@@ -1849,7 +1850,7 @@ __device__ __forceinline__ void sgs_couplings(const Inst& I, int k, const int* r
   const cptr<ab_pair<R>> ab = as_const(static_cast<const ab_pair<R>*>(abv));
   if constexpr (BS == 3) {
     if (I.nodes && as_const(I.nodes)[k] != 0) {
-      shifted_node<R, V, true>(3 * k, rowptr, col, ab, Gc, WAVE * V, sig, acc);
+      shifted_node<R, V, true, kSgsNodeChunk>(3 * k, rowptr, col, ab, Gc, WAVE * V, sig, acc);
       return;
     }
 #pragma unroll

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -23,6 +24,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -1673,114 +1675,180 @@ struct SolveJob {
   }
 };
 
-// One Rayleigh-Ritz pass (Section 3, B-orthonormalisation by the projected
-// pencil): Y = Xin Z with Z^T (Xin^T A Xin) Z = diag(theta), Z^T (Xin^T B Xin) Z = I.
-// f32: the two Gram products on FP32 MFMA (FP32 inputs, FP32 accumulation),
-// for the first projection of a mixed-precision outer iteration whose Ritz pairs
-// are still far from converged.  The update Y = Xin Z stays FP64 whatever Z is,
-// so span(Y) = span(Xin) to FP64 rounding and the FP64 pass that follows sees
-// the filtered subspace itself; only how nearly B-orthonormal Y comes out
-// depends on the FP32 Gram.
-slrf_status rr_pass(Env& env, SolveJob& J, const double* Xin, double* Y, std::vector<double>& theta,
-                    bool f32 = false) {
+// Runs f(q) for q < count on up to the host's hardware threads (the L x L
+// projected eigenproblems of the pencils of a step are independent).
+void parallel_for(int count, const std::function<void(int)>& f) {
+  const int nt = std::min<int>(count, std::max(1u, std::thread::hardware_concurrency()));
+  if (nt <= 1) {
+    for (int q = 0; q < count; ++q) f(q);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&]() {
+      for (int q = next++; q < count; q = next++) f(q);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// One Rayleigh-Ritz pass for every pencil of a step (Section 3,
+// B-orthonormalisation by the projected pencil): Y = Xin Z with
+// Z^T (Xin^T A Xin) Z = diag(theta), Z^T (Xin^T B Xin) Z = I.  The products and
+// Gram kernels of all pencils are queued, then one synchronisation, then the
+// projected eigenproblems run in parallel host threads, then the updates.
+// f32[q]: pencil q's two Gram products on FP32 MFMA (FP32 inputs, FP32
+// accumulation), for the first projection of a mixed-precision outer iteration
+// whose Ritz pairs are still far from converged.  The update Y = Xin Z stays
+// FP64 whatever Z is, so span(Y) = span(Xin) to FP64 rounding and the FP64 pass
+// that follows sees the filtered subspace itself; only how nearly B-orthonormal
+// Y comes out depends on the FP32 Gram.
+// Host Z buffers are kept in zs until the caller's next synchronisation.
+slrf_status rr_pass_all(Env& env, const std::vector<SolveJob*>& js, const std::vector<const double*>& Xin,
+                        const std::vector<double*>& Y, const std::vector<char>& f32,
+                        std::vector<std::vector<double>>& thetas, std::vector<std::vector<double>>& zs) {
   const hipStream_t s = env.stream;
-  const int n = (int)J.P->n, L = J.L;
-  launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, Xin, J.WA, J.WB);
-  launch_gram(s, n, L, Xin, J.WA, J.WB, J.part, J.nch, J.GA, J.GB, f32);
+  const int m = (int)js.size();
+  std::vector<std::vector<double>> hA(m), hB(m);
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    const int n = (int)J.P->n, L = J.L;
+    launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, Xin[q], J.WA, J.WB);
+    launch_gram(s, n, L, Xin[q], J.WA, J.WB, J.part, J.nch, J.GA, J.GB, f32[q] != 0);
+    hA[q].resize((size_t)L * L);
+    hB[q].resize((size_t)L * L);
+    HIPCHK(env, hipMemcpyAsync(hA[q].data(), J.GA, 8 * hA[q].size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(env, hipMemcpyAsync(hB[q].data(), J.GB, 8 * hB[q].size(), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(env, hipGetLastError());
-  std::vector<double> hA((size_t)L * L), hB((size_t)L * L), Z((size_t)L * L);
-  HIPCHK(env, hipMemcpyAsync(hA.data(), J.GA, 8 * hA.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(env, hipMemcpyAsync(hB.data(), J.GB, 8 * hB.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(env, hipStreamSynchronize(s));
-  theta.assign(L, 0.0);
-  if (!projected_pencil(L, hA.data(), hB.data(), theta.data(), Z.data(), f32 ? kF32GramFloor : 1e-15))
-    return fail(env, SLRF_E_BREAKDOWN, "projected pencil not solvable (non-finite or zero Gram matrix)");
-  HIPCHK(env, hipMemcpyAsync(J.Zd, Z.data(), 8 * Z.size(), hipMemcpyHostToDevice, s));
-  const double* xs[1] = {Xin};
-  double* ys[1] = {Y};
-  launch_gemm_nz(s, n, L, L, 1, xs, J.Zd, ys);
+  thetas.assign(m, {});
+  zs.assign(m, {});
+  std::vector<char> ok(m, 0);
+  parallel_for(m, [&](int q) {
+    const int L = js[q]->L;
+    thetas[q].assign(L, 0.0);
+    zs[q].assign((size_t)L * L, 0.0);
+    ok[q] = projected_pencil(L, hA[q].data(), hB[q].data(), thetas[q].data(), zs[q].data(),
+                             f32[q] ? kF32GramFloor : 1e-15);
+  });
+  for (int q = 0; q < m; ++q)
+    if (!ok[q]) return fail(env, SLRF_E_BREAKDOWN, "projected pencil not solvable (non-finite or zero Gram matrix)");
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    HIPCHK(env, hipMemcpyAsync(J.Zd, zs[q].data(), 8 * zs[q].size(), hipMemcpyHostToDevice, s));
+    const double* xs[1] = {Xin[q]};
+    double* ys[1] = {Y[q]};
+    launch_gemm_nz(s, (int)J.P->n, J.L, J.L, 1, xs, J.Zd, ys);
+  }
   HIPCHK(env, hipGetLastError());
-  HIPCHK(env, hipStreamSynchronize(s));  // Z host buffer lifetime
   return SLRF_OK;
 }
 
 // Rayleigh-Ritz (two passes), residuals rho_i and the stopping test of one
-// outer iteration, after the filter has written U.
-slrf_status finish_outer(Env& env, SolveJob& J, const slrf_filter_stats& fs) {
+// outer iteration for the pencils of a step, after the filter has written
+// their U.
+slrf_status finish_outer_all(Env& env, const std::vector<SolveJob*>& js, const std::vector<FilterJob>& fj) {
   const hipStream_t s = env.stream;
-  const int n = (int)J.P->n, L = J.L;
-  J.ss.filter_seconds += fs.seconds;
-  J.ss.spmv_total += fs.spmv;
-  J.iter_sum += fs.mean_iterations;
-  slrf_filter_stats& kk = J.ss.kernels;
-  kk.spmm_seconds += fs.spmm_seconds;
-  kk.spmm_launches += fs.spmm_launches;
-  kk.spmm_bytes += fs.spmm_bytes;
-  kk.spmm_columns += fs.spmm_columns;
-  kk.update_seconds += fs.update_seconds;
-  kk.update_launches += fs.update_launches;
-  kk.update_bytes += fs.update_bytes;
+  const int m = (int)js.size();
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    const slrf_filter_stats& fs = fj[q].stats;
+    J.ss.filter_seconds += fs.seconds;
+    J.ss.spmv_total += fs.spmv;
+    J.iter_sum += fs.mean_iterations;
+    slrf_filter_stats& kk = J.ss.kernels;
+    kk.spmm_seconds += fs.spmm_seconds;
+    kk.spmm_launches += fs.spmm_launches;
+    kk.spmm_bytes += fs.spmm_bytes;
+    kk.spmm_columns += fs.spmm_columns;
+    kk.update_seconds += fs.update_seconds;
+    kk.update_launches += fs.update_launches;
+    kk.update_bytes += fs.update_bytes;
+  }
   // Two projections.  In mixed precision the first one forms its Gram
   // matrices on FP32 MFMA while the previous residuals exceed 1e-6 (before the
   // first outer iteration they count as infinite): it only has to
   // B-orthonormalise approximately.  The second, which gives the Ritz pairs,
   // the residuals and the count, is always FP64.
-  const bool f32 = env.opt.precision == SLRF_MIXED && J.prev_maxr > kFirstPassF32Above;
-  std::vector<double> th1;
-  slrf_status st = rr_pass(env, J, J.U, J.X, th1, f32);
+  std::vector<const double*> x1(m), x2(m);
+  std::vector<double*> y1(m), y2(m);
+  std::vector<char> f32(m, 0), f64(m, 0);
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    x1[q] = J.U;
+    y1[q] = J.X;
+    x2[q] = J.X;
+    y2[q] = J.V;
+    f32[q] = env.opt.precision == SLRF_MIXED && J.prev_maxr > kFirstPassF32Above;
+  }
+  std::vector<std::vector<double>> th1, z1, th2, z2;
+  slrf_status st = rr_pass_all(env, js, x1, y1, f32, th1, z1);
   if (st != SLRF_OK) return st;
-  st = rr_pass(env, J, J.X, J.V, J.theta);
+  st = rr_pass_all(env, js, x2, y2, f64, th2, z2);
   if (st != SLRF_OK) return st;
-  launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, J.V, J.WA, J.WB);
-  HIPCHK(env, hipMemcpyAsync(J.th, J.theta.data(), 8 * (size_t)L, hipMemcpyHostToDevice, s));
-  launch_resid(s, n, L, J.WA, J.WB, J.th, J.rpart, J.nrr);
+  std::vector<std::vector<double>> sums(m);
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    const int n = (int)J.P->n, L = J.L;
+    J.theta = th2[q];
+    launch_spmm_real<double>(s, n, L, J.P->rowptr, J.P->col, J.P->ab64, J.V, J.WA, J.WB);
+    HIPCHK(env, hipMemcpyAsync(J.th, J.theta.data(), 8 * (size_t)L, hipMemcpyHostToDevice, s));
+    launch_resid(s, n, L, J.WA, J.WB, J.th, J.rpart, J.nrr);
+    sums[q].resize(2 * L);
+    HIPCHK(env, hipMemcpyAsync(sums[q].data(), J.rpart + (size_t)J.nrr * 2 * L, 16 * (size_t)L,
+                               hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(env, hipGetLastError());
-  std::vector<double> sums(2 * L);
-  HIPCHK(env, hipMemcpyAsync(sums.data(), J.rpart + (size_t)J.nrr * 2 * L, 16 * (size_t)L, hipMemcpyDeviceToHost, s));
-  HIPCHK(env, hipStreamSynchronize(s));
-  J.rho.assign(L, 0.0);
-  int count = 0;
-  bool all_ok = true;
-  double maxr = 0;
-  for (int c = 0; c < L; ++c) {
-    J.rho[c] = std::sqrt(sums[c]) / (std::fabs(J.theta[c]) * std::sqrt(sums[L + c]));
-    if (J.theta[c] > 0 && J.theta[c] <= J.gamma) {
-      ++count;
-      maxr = std::max(maxr, J.rho[c]);
-      if (!(J.rho[c] <= env.opt.outer_tol)) all_ok = false;
+  HIPCHK(env, hipStreamSynchronize(s));  // also the lifetime of the host Z buffers
+  for (int q = 0; q < m; ++q) {
+    SolveJob& J = *js[q];
+    const int n = (int)J.P->n, L = J.L;
+    J.rho.assign(L, 0.0);
+    int count = 0;
+    bool all_ok = true;
+    double maxr = 0;
+    for (int c = 0; c < L; ++c) {
+      J.rho[c] = std::sqrt(sums[q][c]) / (std::fabs(J.theta[c]) * std::sqrt(sums[q][L + c]));
+      if (J.theta[c] > 0 && J.theta[c] <= J.gamma) {
+        ++count;
+        maxr = std::max(maxr, J.rho[c]);
+        if (!(J.rho[c] <= env.opt.outer_tol)) all_ok = false;
+      }
     }
-  }
-  J.count = count;
-  J.ss.max_resid = maxr;
-  J.prev_prev = J.prev_maxr;
-  J.prev_maxr = count ? maxr : INFINITY;
-  if (env.verbose)
-    fprintf(stderr,
-            "[slrf] n=%d outer %d: inner its mean %.1f max %d (rounds %d, maxit %d, breakdown %d, max relres %.2e) "
-            "theta [%.6g, %.6g] count %d max rho %.3e\n",
-            n, J.k, fs.mean_iterations, fs.max_iterations, fs.refinements, fs.n_maxit, fs.n_breakdown, fs.max_relres,
-            J.theta[0], J.theta[L - 1], count, maxr);
-  if (count == L) {
-    J.done = true;
-    J.status = SLRF_E_SUBSPACE_TOO_SMALL;
-    J.msg = "all L Ritz values lie in (0, gamma]: increase L";
-  } else if (count == J.prev_count && all_ok) {
-    J.done = true;
-    J.status = SLRF_OK;
-  } else if (J.k >= std::max(1, env.opt.outer_maxit)) {
-    J.done = true;
-    J.status = SLRF_E_NOT_CONVERGED;
-    J.msg = "outer iteration limit reached";
-  }
-  J.prev_count = count;
-  if (J.done) {
-    J.ss.outer_iterations = J.k;
-    J.ss.inner_iterations = J.iter_sum / std::max(1, J.k);
-    int found = 0;
-    for (int c = 0; c < L; ++c)
-      if (J.theta[c] > 0 && J.theta[c] <= J.gamma && J.rho[c] <= env.opt.outer_tol) ++found;
-    J.ss.n_found = found;
-    J.ss.seconds = now_s() - J.t0;
+    J.count = count;
+    J.ss.max_resid = maxr;
+    J.prev_prev = J.prev_maxr;
+    J.prev_maxr = count ? maxr : INFINITY;
+    const slrf_filter_stats& fs = fj[q].stats;
+    if (env.verbose)
+      fprintf(stderr,
+              "[slrf] n=%d outer %d: inner its mean %.1f max %d (rounds %d, maxit %d, breakdown %d, max relres "
+              "%.2e) theta [%.6g, %.6g] count %d max rho %.3e\n",
+              n, J.k, fs.mean_iterations, fs.max_iterations, fs.refinements, fs.n_maxit, fs.n_breakdown,
+              fs.max_relres, J.theta[0], J.theta[L - 1], count, maxr);
+    if (count == L) {
+      J.done = true;
+      J.status = SLRF_E_SUBSPACE_TOO_SMALL;
+      J.msg = "all L Ritz values lie in (0, gamma]: increase L";
+    } else if (count == J.prev_count && all_ok) {
+      J.done = true;
+      J.status = SLRF_OK;
+    } else if (J.k >= std::max(1, env.opt.outer_maxit)) {
+      J.done = true;
+      J.status = SLRF_E_NOT_CONVERGED;
+      J.msg = "outer iteration limit reached";
+    }
+    J.prev_count = count;
+    if (J.done) {
+      J.ss.outer_iterations = J.k;
+      J.ss.inner_iterations = J.iter_sum / std::max(1, J.k);
+      int found = 0;
+      for (int c = 0; c < L; ++c)
+        if (J.theta[c] > 0 && J.theta[c] <= J.gamma && J.rho[c] <= env.opt.outer_tol) ++found;
+      J.ss.n_found = found;
+      J.ss.seconds = now_s() - J.t0;
+    }
   }
   return SLRF_OK;
 }
@@ -1820,7 +1888,7 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
   if (act.empty()) return SLRF_OK;
   slrf_status st = filter_batch(env, arena, fj);
   for (size_t q = 0; q < act.size(); ++q) act[q]->has_prev = st == SLRF_OK && fj[q].yprev != nullptr;
-  for (size_t q = 0; q < act.size() && st == SLRF_OK; ++q) st = finish_outer(env, *act[q], fj[q].stats);
+  if (st == SLRF_OK) st = finish_outer_all(env, act, fj);
   if (st != SLRF_OK)
     for (SolveJob* J : act)
       if (!J->done) {
