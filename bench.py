@@ -447,13 +447,14 @@ def batch_kernel_stats(results):
 
 def many_options(slrf, args, precision, **kw):
     """Options of the batched, served and serial runs: COCG unless --solver
-    bicgstab, with the multicolour point SGS preconditioner (--precond sgs, the
-    default; one block size serves every pencil of a batch) or point Jacobi;
+    bicgstab, with the multicolour SGS preconditioner (--precond sgs, the
+    default: node blocks for node-structured pencils, points for the others) or
+    point Jacobi;
     with --graph (the default) the Krylov iteration chunks replay as hipGraphs
     and the per-launch kernel timers are off; with --no-graph the kernels are
     timed (roofline fields)."""
     kw.setdefault("solver", slrf.SOLVER_BICGSTAB if args.solver == "bicgstab" else slrf.SOLVER_COCG)
-    kw.setdefault("precond", slrf.PRECOND_SGS if args.precond == "sgs" and kw["solver"] == slrf.SOLVER_COCG
+    kw.setdefault("precond", slrf.PRECOND_SGS3 if args.precond == "sgs" and kw["solver"] == slrf.SOLVER_COCG
                   else slrf.PRECOND_AUTO)
     kw.setdefault("recycle", 1 if args.recycle == "1" or (args.recycle == "auto" and kw["solver"] == 1) else 0)
     if args.graph:
@@ -547,28 +548,52 @@ def run_batched(slrf, args):
 
 
 def run_served(slrf, args):
-    """Poisson stream of interval eigensolves (pencils.serve_request) through the
-    continuous-batching server; the rate is 0.7 x the throughput measured on a
-    closed calibration batch of the first requests."""
+    """Poisson stream of interval eigensolves through the continuous-batching
+    server: requests over a pool of --structures pencils (pencils.serve_structure:
+    3D scalar and 3D elasticity alternating, n log-uniform on [--n-min, --n-max]),
+    each with its own NEV (log-uniform on [20, --nev-max]) and gamma
+    (pencils.serve_request_mix).  The arrival rate is 0.7 x the throughput of a
+    closed calibration batch of the first requests; requests arrive for
+    --duration seconds (at most --requests of them)."""
     import torch
+
+    import numpy as np
 
     import paper_2503_21618_amd.serve as serve
     import pencils
+    t0 = time.perf_counter()
+    structures = {}
+    for sid in range(args.structures):
+        structures[sid] = pencils.serve_structure(sid, n_range=(args.n_min, args.n_max))
+        log(f"structure {sid}: {structures[sid][1]} n={structures[sid][0].n} ({time.perf_counter() - t0:.0f} s)")
     R = args.requests
-    reqs = [pencils.serve_request(r, n_range=(args.n_min, args.n_max), nev_range=(20, args.nev_max))
-            for r in range(R)]
-    log(f"{R} requests, sum n = {sum(p.n for p, *_ in reqs)}")
+    specs = [pencils.serve_request_mix(r, structures, nev_range=(20, args.nev_max)) for r in range(R)]
     N = 6
     opt = many_options(slrf, args, slrf.MIXED)
-    stream = torch.cuda.Stream()
-    fps = [slrf.batch_footprint(p.n, union_nnz(p), L, N, options=opt) for p, g, L, _ in reqs]
-    arena = int(args.arena_gb * 2**30)
-    pool = int(args.pool_gb * 2**30)
-    if max(t for _, t in fps) > arena or max(a for a, _ in fps) > pool:
+    nnz = {sid: union_nnz(p) for sid, (p, _, _) in structures.items()}
+    fps = [slrf.batch_footprint(structures[sid][0].n, nnz[sid], L, N, options=opt) for sid, g, L, _ in specs]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    big_t = max(t for _, t in fps)
+    big_p = max(a for a, _ in fps)
+    arena = min(max(int(args.arena_gb * 2**30), int(1.3 * big_t)), budget - 2 * big_p)
+    pool = budget - arena
+    log(f"{R} request specs; largest transient {big_t / 2**30:.1f} GiB, persistent {big_p / 2**30:.1f} GiB; "
+        f"arena {arena / 2**30:.1f} GiB, pool {pool / 2**30:.1f} GiB")
+    if big_t > arena or big_p > pool:
         raise SystemExit("a request does not fit the arena or pool")
+    if args.serial_only:
+        # the comparison alone: the first --requests requests one at a time
+        items = [(structures[specs[i][0]][0], specs[i][1], specs[i][2]) for i in range(R)]
+        ser = serial_solves(slrf, args, items, slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
+                            args.serial_limit)
+        return {"value": ser["value"], "seconds": ser["seconds"], "found": ser["found"], "serial": ser,
+                "ks": {"spmm_seconds": 0}}, [structures[specs[i][0]][0] for i in range(ser["pencils"])]
+    stream = torch.cuda.Stream()
 
     def make(i, arrival):
-        p, g, L, _ = reqs[i]
+        sid, g, L, _ = specs[i]
+        p = structures[sid][0]
         sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
         return serve.Request(i, p.A, p.B, g, L, sig, w, arrival=arrival)
 
@@ -580,6 +605,7 @@ def run_served(slrf, args):
     t0 = time.perf_counter()
     while not srv.idle():
         srv.pump()
+        log(f"calibration: {len(srv.done)}/{C} done, {time.perf_counter() - t0:.0f} s")
     mu = C / (time.perf_counter() - t0)
     rate = 0.7 * mu
     log(f"calibration: {C} requests in {C / mu:.1f} s -> rate {rate:.3f} requests/s")
@@ -587,8 +613,10 @@ def run_served(slrf, args):
     del srv
     torch.cuda.empty_cache()
     arr = pencils.arrival_times(R, rate)
+    count = max(1, int(np.searchsorted(arr - arr[0], args.duration, side="right")))
+    log(f"{count} requests arrive within {args.duration:.0f} s")
     srv = serve.Server(pool + arena, arena, max_poles=N, options=opt, stream=stream)
-    pending = [make(i, float(arr[i])) for i in range(R)]
+    pending = [make(i, float(arr[i])) for i in range(count)]
     t0 = time.perf_counter()
     srv.clock = lambda: time.perf_counter() - t0
     last_log = 0.0
@@ -602,15 +630,17 @@ def run_served(slrf, args):
         srv.pump()
         if srv.clock() - last_log > 10:
             last_log = srv.clock()
-            log(f"served {len(srv.done)}/{R}, active {len(srv.active)}, queued {len(srv.queue)}, "
+            log(f"served {len(srv.done)}/{count}, active {len(srv.active)}, queued {len(srv.queue)}, "
                 f"t {last_log:.0f} s")
     makespan = max(c.finished for c in srv.done) - float(arr[0])
     res = [c.result for c in srv.done]
     found = sum(r.n_found for r in res)
     lat = serve.latency_stats(srv.done)
     ks = batch_kernel_stats(res)
-    out = {"value": found / makespan, "seconds": makespan, "found": found, "latency_s": lat,
+    kinds = [structures[specs[c.rid][0]][1] for c in srv.done]
+    out = {"value": found / makespan, "seconds": makespan, "requests": count, "found": found, "latency_s": lat,
            "rate_per_s": rate, "peak_active": srv.peak_active, "steps": srv.steps,
+           "elasticity_requests": kinds.count("elasticity"), "scalar_requests": kinds.count("scalar"),
            "statuses_not_ok": [c.rid for c in srv.done if c.result.status != 0],
            "max_resid": max(r.stats["max_resid"] for r in res), "ks": ks}
     srv.close()
@@ -618,10 +648,11 @@ def run_served(slrf, args):
     torch.cuda.empty_cache()
     if not args.no_serial:
         log("serial solves...")
-        out["serial"] = serial_solves(slrf, args, [(p, g, L) for p, g, L, _ in reqs],
+        items = [(structures[specs[i][0]][0], specs[i][1], specs[i][2]) for i in range(count)]
+        out["serial"] = serial_solves(slrf, args, items,
                                       slrf.MIXED if args.serial_precision == "mixed" else slrf.FP64,
                                       args.serial_limit)
-    return out, reqs
+    return out, [structures[specs[i][0]][0] for i in range(count)]
 
 
 def run_filters(slrf, args):
@@ -1001,10 +1032,14 @@ def main():
                          "the 64^3 workload), BiCGStab for the ILU(0) string")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
-    ap.add_argument("--requests", type=int, default=24, help="served workload: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="served workload: most requests")
+    ap.add_argument("--duration", type=float, default=600.0, help="served workload: seconds of arrivals")
+    ap.add_argument("--structures", type=int, default=16, help="served workload: distinct pencils")
+    ap.add_argument("--serial-only", action="store_true",
+                    help="served workload: only the one-at-a-time solves of the first --requests requests")
     ap.add_argument("--n-min", type=float, default=1e4, help="served workload: smallest pencil")
-    ap.add_argument("--n-max", type=float, default=1e5, help="served workload: largest pencil")
-    ap.add_argument("--nev-max", type=int, default=100, help="served workload: largest NEV")
+    ap.add_argument("--n-max", type=float, default=5e5, help="served workload: largest pencil")
+    ap.add_argument("--nev-max", type=int, default=300, help="served workload: largest NEV")
     ap.add_argument("--calibrate", type=int, default=6, help="served workload: calibration batch")
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--pool-gb", type=float, default=32.0)
@@ -1063,12 +1098,13 @@ def main():
         return
     if args.workload == "served":
         out, reqs = run_served(slrf, args)
-        desc = (f"{len(reqs)} Poisson-arriving requests (rate 0.7 x calibrated capacity), 3D scalar "
-                f"vibration pencils n log-uniform {args.n_min:.0e}..{args.n_max:.0e}, NEV log-uniform "
-                f"20..{args.nev_max}, L = ceil(1.2 NEV) to a multiple of 8, N=6, seeds 5000+r; continuous batching, "
-                "admission by HBM footprint, mixed precision; "
-                f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}"
-                f"{', warm starts' if args.recycle != '0' and args.solver != 'bicgstab' else ''}")
+        desc = (f"{len(reqs)} Poisson-arriving requests in {args.duration:.0f} s (rate 0.7 x calibrated "
+                f"capacity) over {args.structures} pencils, 3D scalar vibration and 3D elasticity alternating, "
+                f"n log-uniform {args.n_min:.0e}..{args.n_max:.0e}, NEV log-uniform 20..{args.nev_max}, "
+                "L = ceil(1.2 NEV) to a multiple of 8, N=6; continuous batching, admission by HBM footprint, "
+                f"mixed precision; inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}"
+                f"{', warm starts' if args.recycle != '0' and args.solver != 'bicgstab' else ''}"
+                f"{', multicolour SGS (node blocks for elasticity)' if args.precond == 'sgs' else ''}")
         print(json.dumps(many_line(args, "served", out, desc)), flush=True)
         return
     if args.workload == "c3":

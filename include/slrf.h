@@ -86,7 +86,10 @@ typedef struct {
                             graph (natural order; the parity classes on structured
                             grids); applied in the split form with one backward and one
                             forward colour sweep per iteration
-                          5 the same with the 3x3 node blocks as D (n divisible by 3)
+                          5 the same with the 3x3 node blocks as D for a pencil made of
+                            nodes (n divisible by 3 and at least half of its rows in
+                            triples 3k..3k+2 with one column pattern), the point form
+                            of 4 for any other pencil; a batch may hold both kinds
                           The shifted operator preconditioner of Section 4.2 is an ILU
                           (drop tolerance 1e-4) with RCM ordering; 4 and 5 are
                           symmetric stand-ins whose sweeps run in parallel. */

@@ -103,7 +103,7 @@ struct Batch {
   int rows_per_block;
   int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
   int groups;             // sparse-product row mode: 1 stencil groups, 2 node triples, 0 neither
-  int sgs;                // multicolour SGS block size of the batch's pencils (0 none, 1, 3)
+  int sgs;                // multicolour SGS of the batch's pencils: bit 0 point, bit 1 node blocks
   int sgs_ncol;           // most colours of any pencil (sweeps launch once per colour)
 };
 

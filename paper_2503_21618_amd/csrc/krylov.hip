@@ -1876,8 +1876,8 @@ __device__ __forceinline__ SgsBlocks<R, BS> sgs_blocks(const Inst& I, const Kryl
     return {static_cast<const cx<R>*>(I.sgsR) + o, static_cast<const cx<R>*>(I.sgsD) + o,
             static_cast<const cx<R>*>(I.bjac) + o};
   } else {
-    const size_t o = I.dn + (size_t)k * I.N + pole;
-    return {static_cast<const cx<R>*>(I.sgsR) + o, st.d + o, st.dinv + o};
+    const size_t o = (size_t)k * I.N + pole;
+    return {static_cast<const cx<R>*>(I.sgsR) + o, st.d + I.dn + o, st.dinv + I.dn + o};
   }
 }
 
@@ -1890,6 +1890,7 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
   const WgPos p = wg_pos(b.G);
   FOR_TILE_LIST(b, p, V, all_tiles ? b.n_tiles : as_const((const int*)b.n_active)[0],
                 all_tiles ? ti_ : as_const((const int*)b.active)[ti_])
+    if (I.sgs != BS) continue;  // the other block size's launch owns this pencil's tiles
     cx<R> da[V] = {};
     R db[V] = {};
     const bool go = colour < I.sgs_ncol &&
@@ -2027,15 +2028,21 @@ void sgs_sweeps(hipStream_t s, const Batch& b, const KrylovState<R>& st, int fir
   }
 }
 
-template <typename R, int BS>
+// One COCG iteration on the split system: the backward colour sweeps of every
+// block size present in the batch (each launch serves the pencils of its block
+// size), then the forward ones, then the scalars and the x, r update.
+template <typename R>
 void sgs_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit, bool first,
                    LaunchTimer* tm, const IterBytes& by) {
   const dim3 grid((unsigned)b.G), blk(WG);
   const dim3 cgrid((unsigned)b.n_tiles), cblk(kScWG);
   // backward: read r, p; write p, t; gather t once; the upper couplings and the blocks
-  sgs_sweeps<R, BS, kSgsBackIter>(s, b, st, first ? 1 : 0, tm, 5 * by.blk + 0.5 * by.sgs_blocks, by.sgs_upper);
+  const double tb = 5 * by.blk + 0.5 * by.sgs_blocks;
+  if (b.sgs & 1) sgs_sweeps<R, 1, kSgsBackIter>(s, b, st, first ? 1 : 0, tm, tb, by.sgs_upper);
+  if (b.sgs & 2) sgs_sweeps<R, 3, kSgsBackIter>(s, b, st, first ? 1 : 0, tm, tb, by.sgs_upper);
   // forward: read p, t; write u, q; gather u once; the lower couplings and the blocks
-  sgs_sweeps<R, BS, kSgsFwdIter>(s, b, st, 0, tm, 5 * by.blk + 0.5 * by.sgs_blocks, by.sgs_lower);
+  if (b.sgs & 1) sgs_sweeps<R, 1, kSgsFwdIter>(s, b, st, 0, tm, tb, by.sgs_lower);
+  if (b.sgs & 2) sgs_sweeps<R, 3, kSgsFwdIter>(s, b, st, 0, tm, tb, by.sgs_lower);
   k_cocg_alpha<R><<<cgrid, cblk, 0, s>>>(b, st);
   int* c = tm ? tm->begin(s, 1, 6 * by.blk, 0) : nullptr;
   k_cocg_update_xr<R><<<grid, blk, 0, s>>>(b, st, c);
@@ -2045,32 +2052,26 @@ void sgs_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R to
 
 template <typename R>
 void launch_sgs_finish(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
-  if (b.sgs == 3)
-    sgs_sweeps<R, 3, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
-  else
-    sgs_sweeps<R, 1, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
+  if (b.sgs & 1) sgs_sweeps<R, 1, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
+  if (b.sgs & 2) sgs_sweeps<R, 3, kSgsBackFinal>(s, b, st, 0, nullptr, 0, 0);
 }
 
 template <typename R>
 void launch_cocg_start(hipStream_t s, const Batch& b, const KrylovState<R>& st) {
-  if (b.sgs == 3)
-    sgs_sweeps<R, 3, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
-  else if (b.sgs == 1)
-    sgs_sweeps<R, 1, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
-  else
+  if (b.sgs) {
+    if (b.sgs & 1) sgs_sweeps<R, 1, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
+    if (b.sgs & 2) sgs_sweeps<R, 3, kSgsFwdStart>(s, b, st, 0, nullptr, 0, 0);
+  } else {
     k_cocg_start<R><<<dim3((unsigned)b.G), dim3(WG), 0, s>>>(b, st);
+  }
   k_cocg_init_scalars<R><<<dim3((unsigned)b.n_tiles), dim3(kScWG), 0, s>>>(b, st);
 }
 
 template <typename R>
 void launch_cocg_iteration(hipStream_t s, const Batch& b, const KrylovState<R>& st, R tol, int maxit,
                            bool first, LaunchTimer* tm, const IterBytes& by) {
-  if (b.sgs == 3) {
-    sgs_iteration<R, 3>(s, b, st, tol, maxit, first, tm, by);
-    return;
-  }
-  if (b.sgs == 1) {
-    sgs_iteration<R, 1>(s, b, st, tol, maxit, first, tm, by);
+  if (b.sgs) {
+    sgs_iteration<R>(s, b, st, tol, maxit, first, tm, by);
     return;
   }
   const dim3 grid((unsigned)b.G), blk(WG);

@@ -308,7 +308,7 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
     err = "unknown preconditioner";
     return SLRF_E_INVALID_ARG;
   }
-  if ((precond == 3 || precond == 5) && n % 3 != 0) {
+  if (precond == 3 && n % 3 != 0) {
     err = "node blocks need three unknowns per node (n divisible by 3)";
     return SLRF_E_INVALID_ARG;
   }
@@ -351,7 +351,15 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   P.nnz = nnz;
   P.use_ilu = use_ilu_for(precond, n, nnz);
   P.use_bjac = use_bjac_for(precond);
+  const std::vector<int32_t> groups = stencil_groups(n, rp, cl), nodes = node_triples(n, rp, cl);
+  int64_t n_group = 0, n_node = 0;
+  for (int32_t f : groups) n_group += f != 0;
+  for (int32_t f : nodes) n_node += f != 0;
+  // multicolour SGS: precond 5 takes the 3 x 3 node blocks where the pencil is
+  // made of nodes (n divisible by 3, at least half of its rows in node triples)
+  // and the point form elsewhere, so that one batch serves both kinds
   P.sgs = sgs_block_for(precond);
+  if (P.sgs == 3 && !(n % 3 == 0 && 2 * kNode * n_node >= n)) P.sgs = 1;
   P.mem = mem;
   P.mem_bytes = pencil_bytes(n, nnz, precond);
   Carver cv{mem, 0, P.mem_bytes};
@@ -430,10 +438,6 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
   }
   std::vector<int32_t> order;
   P.sched = band_schedule(n, rp, cl, band_rows, order) ? sched_dev : nullptr;
-  const std::vector<int32_t> groups = stencil_groups(n, rp, cl), nodes = node_triples(n, rp, cl);
-  int64_t n_group = 0, n_node = 0;
-  for (int32_t f : groups) n_group += f != 0;
-  for (int32_t f : nodes) n_node += f != 0;
   // one kind per pencil: the one that covers more rows
   P.nodes = n_node > 0 && kNode * n_node >= kGroup * n_group ? nodes_dev : nullptr;
   P.groups = n_group > 0 && !P.nodes ? groups_dev : nullptr;
@@ -1025,7 +1029,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   std::vector<int> tile_inst, col_inst;
   std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all, sgsR_all, sgsD_all;
   std::vector<double> sigc64, w;
-  int64_t dn = 0, ilu_off = 0, bjac_off = 0, sgs_off = 0;
+  int64_t dn = 0, ilu_off = 0, bjac_off = 0, sgs_off = 0, sgsd_off = 0;  // sgsd: node blocks' D only
   b.sgs = 0;
   b.sgs_ncol = 0;
   int col0 = 0, tile0 = 0;
@@ -1114,8 +1118,9 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
         for (const auto& v : Df) sgsD_all.push_back({(R)v.real(), (R)v.imag()});
       }
       I.sgsR = (const char*)lo.sgsR + sgs_off * sizeof(cx<R>);
-      I.sgsD = (const char*)lo.sgsD + sgs_off * sizeof(cx<R>);
+      I.sgsD = (const char*)lo.sgsD + sgsd_off * sizeof(cx<R>);
       sgs_off += (int64_t)j.N * (j.P->n / 3) * 9;
+      sgsd_off += (int64_t)j.N * (j.P->n / 3) * 9;
     } else if (j.P->sgs == 1) {
       // R = sqrt(d) per (row, pole), in the (n, N) layout of d at Inst::dn
       const std::vector<double>& ab = j.P->h_ab;
@@ -1127,18 +1132,18 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
             dB[i] = ab[2 * (size_t)q + 1];
           }
       // d is computed on the device in the Krylov precision from the same
-      // diagonals; R is rounded from the FP64 square root
-      sgsR_all.resize((size_t)(dn + (int64_t)I.n * I.N));
+      // diagonals; R is rounded from the FP64 square root; (n, N) layout
       for (int64_t i = 0; i < I.n; ++i)
         for (int p = 0; p < j.N; ++p) {
           const std::complex<double> r =
               std::sqrt(std::complex<double>(dA[i], 0.0) - std::complex<double>(j.sigma[2 * p], j.sigma[2 * p + 1]) * dB[i]);
-          sgsR_all[(size_t)(dn + i * I.N + p)] = {(R)r.real(), (R)r.imag()};
+          sgsR_all.push_back({(R)r.real(), (R)r.imag()});
         }
-      I.sgsR = lo.sgsR;
+      I.sgsR = (const char*)lo.sgsR + sgs_off * sizeof(cx<R>);
+      sgs_off += (int64_t)I.n * I.N;
     }
     if (j.P->sgs) {
-      b.sgs = std::max(b.sgs, j.P->sgs);
+      b.sgs |= j.P->sgs == 3 ? 2 : 1;
       b.sgs_ncol = std::max(b.sgs_ncol, j.P->sgs_ncol);
     }
     dn += (int64_t)I.n * I.N;

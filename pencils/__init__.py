@@ -340,6 +340,55 @@ def serve_request(r: int, seed0: int = 5000, n_range=(1e4, 1e5), nev_range=(20, 
     return scalar_q1(m, 3, sigma_ln, s), float(gamma), L, nev
 
 
+# Fitted power law of the elasticity family's low eigenvalues on the unit cube
+# (lambda_k ~ a k^p, fitted to the 48^3-node pencil's eigenvalues k = 20..199):
+# the serving mix uses it to pick gamma for about NEV eigenvalues.
+ELASTICITY_SPECTRUM = (1.216, 0.839)
+
+
+def serve_structure(sid: int, seed0: int = 7000, n_range=(1e4, 5e5), sigma_ln: float = 0.5):
+    """Structure sid of the mixed serving workload: even sid a 3D scalar
+    vibration pencil, odd sid a 3D elasticity pencil (log-normal Young's modulus
+    sigma 0.7, nu 0.3, density U[0.8, 1.2], clamped x = 0 face), size log-uniform
+    on n_range from uniform(seed0 + sid, 1), coefficient fields seeded seed0 + sid.
+    Returns (pencil, kind, grid size m)."""
+    s = seed0 + sid
+    u = uniform(s, 1)[0]
+    lo, hi = math.log(n_range[0]), math.log(n_range[1])
+    n_t = math.exp(lo + (hi - lo) * u)
+    if sid % 2 == 0:
+        m = int(round(n_t ** (1.0 / 3.0))) + 1
+        return scalar_q1(m, 3, sigma_ln, s), "scalar", m
+    nodes = max(4, int(round((n_t / 3.0) ** (1.0 / 3.0))))
+    return (elasticity_q1(nodes, nodes - 1, nodes - 1, 1.0 / nodes, 0.7, 0.3, (0.8, 1.2), s),
+            "elasticity", nodes)
+
+
+def serve_request_mix(r: int, structures: dict, seed0: int = 6000, nev_range=(20, 300)):
+    """Request r of the mixed serving workload over a pool of structures
+    (sid -> serve_structure(sid)): the structure is uniform over the pool, NEV
+    log-uniform on nev_range (seed seed0 + r).  gamma: for a scalar pencil
+    halfway between the NEV-th constant-coefficient eigenvalue of its grid and
+    the next distinct one (as serve_request); for an elasticity pencil the
+    fitted power law at NEV + 1/2, so that about NEV eigenvalues lie below it.
+    L = ceil(1.2 NEV) rounded up to a multiple of 8.  Returns (sid, gamma, L, NEV)."""
+    u = uniform(seed0 + r, 2)
+    ids = sorted(structures)
+    sid = ids[min(int(u[0] * len(ids)), len(ids) - 1)]
+    a, b = math.log(nev_range[0]), math.log(nev_range[1])
+    nev = int(round(math.exp(a + (b - a) * u[1])))
+    _, kind, m = structures[sid]
+    if kind == "scalar":
+        lam = cc_spectrum(m, 3, nev + 64)
+        above = lam[lam > lam[nev - 1] * (1 + 1e-12)]
+        gamma = 0.5 * (lam[nev - 1] + above[0])
+    else:
+        ca, cp = ELASTICITY_SPECTRUM
+        gamma = ca * (nev + 0.5) ** cp
+    L = int(math.ceil(math.ceil(1.2 * nev) / 8.0) * 8)
+    return sid, float(gamma), L, nev
+
+
 def arrival_times(count: int, rate: float, seed: int = 4999) -> np.ndarray:
     """Poisson arrivals: cumulative sums of exponential gaps -ln(u)/rate."""
     return np.cumsum(-np.log(uniform(seed, count)) / rate)

@@ -139,12 +139,83 @@ def test_sgs_solve_vs_dense(slrf, torch, kind, make, pc, opc, gamma, prec, recyc
     assert r.resid[:nf].max() <= 1e-8
 
 
-def test_sgs_rejected_with_bicgstab(slrf, torch):
+def test_sgs_rejected_with_bicgstab_and_node_fallback(slrf, torch):
     q = scalar()
     with pytest.raises(slrf.SlrfError):
         slrf.Solver(q.A, q.B, max_L=8, max_poles=2,
                     options=slrf.default_options(solver=slrf.SOLVER_BICGSTAB, precond=4))
-    with pytest.raises(slrf.SlrfError):   # node blocks need n divisible by 3
-        p = pencils.string_1d(100)
-        slrf.Solver(p.A, p.B, max_L=8, max_poles=2,
+    # node blocks where the pencil has none (n not divisible by 3): the point form
+    p = pencils.string_1d(100)
+    s = slrf.Solver(p.A, p.B, max_L=8, max_poles=2,
                     options=slrf.default_options(solver=slrf.SOLVER_COCG, precond=5))
+    s.close()
+
+
+def test_sgs_node_and_point_pencils_in_one_batch(slrf, torch):
+    """precond 5 takes node blocks for the elasticity pencil and the point form
+    for the scalar one; one batch holds both (one sweep launch per block size
+    and colour).  The scalar pencil gives bitwise its solve alone (n >= 8192 and
+    stencil rows: the same Krylov grid and row blocks) and its precond-4 solve;
+    the elasticity pencil runs on the scalar pencil's row blocks in the batch
+    (16 rows instead of its own 24), which reorders sums, so its found
+    eigenvalues agree with its solve alone to 1e-9.  Every pencil's eigenvalues
+    agree with the Lanczos reference (shift-invert, SciPy) to 1e-8."""
+    import scipy.sparse.linalg as sla
+    cases = []
+    for q, nev in ((pencils.scalar_q1(22, 3, 0.5, 12), 24),
+                   (pencils.elasticity_q1(14, 13, 13, 1.0 / 14, 0.7, 0.3, (0.8, 1.2), 5), 24)):
+        ev = np.sort(sla.eigsh(q.A.tocsc(), k=nev + 8, M=q.B.tocsc(), sigma=0.0, which="LM",
+                               return_eigenvectors=False))
+        k = nev
+        while (ev[k] - ev[k - 1]) / ev[k] < 1e-3:
+            k += 1
+        cases.append((q, 0.5 * (ev[k - 1] + ev[k]), 40, k, ev[:k]))
+    N = 6
+    opt = slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG, precond=slrf.PRECOND_SGS3, recycle=1)
+    alone = []
+    for i, (q, g, L, k, ev) in enumerate(cases):
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
+        say(f"case SGS precond 5 alone: pencil {i} n={q.n} NEV={k}")
+        s = slrf.Solver(q.A, q.B, max_L=L, max_poles=N, options=opt)
+        r = s.solve_interval(g, L, sig, w, V0=torch.from_numpy(pencils.start_block(q.n, L, 50 + i)).cuda())
+        s.close()
+        rel = np.abs(r.evals[:r.n_found] / ev - 1).max() if r.n_found == k else np.inf
+        say(f"  found {r.n_found}, rel eig err {rel:.2e}, outer {r.stats['outer_iterations']}")
+        assert r.status == 0 and r.n_found == k and rel <= 1e-8
+        alone.append(r)
+    # the scalar pencil under precond 4 (the point form precond 5 falls back to)
+    q, g, L, k, _ = cases[0]
+    sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
+    s = slrf.Solver(q.A, q.B, max_L=L, max_poles=N,
+                    options=slrf.default_options(precision=slrf.MIXED, solver=slrf.SOLVER_COCG,
+                                                 precond=slrf.PRECOND_SGS, recycle=1))
+    r4 = s.solve_interval(g, L, sig, w, V0=torch.from_numpy(pencils.start_block(q.n, L, 50)).cuda())
+    s.close()
+    assert np.array_equal(r4.evals, alone[0].evals) and torch.equal(r4.evecs, alone[0].evecs)
+    pers = trans = 0
+    for q, _, L, _, _ in cases:
+        a, t = slrf.batch_footprint(q.n, int((abs(q.A) + abs(q.B)).nnz), L, N, options=opt)
+        pers += a + 4096
+        trans += t
+    b = slrf.Batch(pers + trans + (1 << 20), trans, max_poles=N, options=opt)
+    ids = []
+    for i, (q, g, L, _, _) in enumerate(cases):
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g)
+        ids.append(b.add(q.A, q.B, g, L, sig, w, V0=pencils.start_block(q.n, L, 50 + i)))
+    steps = 0
+    while b.step() > 0:
+        steps += 1
+        assert steps < 60
+    for i, pid in enumerate(ids):
+        r = b.result(pid)
+        say(f"  batch pencil {i}: found {r.n_found}, outer {r.stats['outer_iterations']} "
+            f"(alone {alone[i].stats['outer_iterations']})")
+        nf = r.n_found
+        assert r.status == 0 and nf == alone[i].n_found == cases[i][3]
+        assert np.abs(r.evals[:nf] / cases[i][4] - 1).max() <= 1e-8
+        if i == 0:
+            assert np.array_equal(r.evals, alone[i].evals)
+            assert torch.equal(r.evecs, alone[i].evecs)
+        else:
+            assert np.abs(r.evals[:nf] / alone[i].evals[:nf] - 1).max() <= 1e-9
+    b.close()
