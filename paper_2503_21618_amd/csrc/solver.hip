@@ -1892,6 +1892,10 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
   }
   if (act.empty()) return SLRF_OK;
   slrf_status st = filter_batch(env, arena, fj);
+  // Y_prev (X_prev^T B X_new) is the projected start only for a B-orthonormal
+  // X_prev; after the first step X_prev is the raw start block, and the start
+  // it gives is still better than zero (a cold second step costs more Krylov
+  // iterations), so every step's solutions are kept
   for (size_t q = 0; q < act.size(); ++q) act[q]->has_prev = st == SLRF_OK && fj[q].yprev != nullptr;
   if (st == SLRF_OK) st = finish_outer_all(env, act, fj);
   if (st != SLRF_OK)
