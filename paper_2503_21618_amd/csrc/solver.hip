@@ -53,6 +53,7 @@ constexpr int kTimerSlots = 512;
 constexpr double kFirstPassF32Above = 1e-6;
 constexpr double kF32GramFloor = 1e-6;
 constexpr double kInnerTol32 = 1e-6;  // tightest relative tolerance of an FP32 correction solve
+constexpr double kBeyondGammaTarget = 1e-3;  // inner target of the columns beyond gamma
 constexpr int kMaxRounds = 6;         // defect-correction rounds per filter application
 constexpr int kDefaultPoles = 4;
 
@@ -744,6 +745,7 @@ struct FilterJob {
   const double* X;       // device (n, L)
   double* U;             // device (n, L)
   double target;         // relative accuracy of the shifted solves
+  const double* rhs_target = nullptr;  // mixed precision: per right-hand side (L), or null (target)
   slrf_filter_stats stats;
   // warm start (mixed precision): scratch for C = X_prev^T B X_new
   double* gpart = nullptr;  // gram_chunks(n, L) * 2 * L * L
@@ -1010,7 +1012,15 @@ hipError_t put_async(hipStream_t s, std::vector<std::vector<char>>& keep, void* 
 // the caller holds until the stream has passed the copies.
 // Column order (col_pole): right-hand-side-major with warm starts (mixed
 // precision, options.recycle), pole-major otherwise.
-int column_order(const Env& env) { return env.opt.precision == SLRF_MIXED && env.opt.recycle ? 1 : 0; }
+// Column order of the Krylov block: pole-major (0), so that the tiles of the
+// poles whose solves converge first retire early.  The kernels also take the
+// right-hand-side-major order (1), which paid with warm starts while every
+// column had one inner target; with the columns beyond gamma solved loosely
+// it is the slower one.
+int column_order(const Env& env) {
+  (void)env;
+  return 0;
+}
 
 template <typename R>
 slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
@@ -1488,7 +1498,9 @@ slrf_status filter_batch_mixed(Env& env, Carver& arena, std::vector<FilterJob>& 
   // gap between the current defect and that target.
   std::vector<double> tol_host;
   for (auto& j : jobs)
-    for (int64_t c = 0; c < padded_k(j.N * j.L, true); ++c) tol_host.push_back(j.target);
+    for (int64_t c = 0; c < padded_k(j.N * j.L, true); ++c)
+      tol_host.push_back(j.rhs_target && c < j.N * j.L ? j.rhs_target[col_rhs((int)c, j.L, j.N, column_order(env))]
+                                                       : j.target);
   const float tol32 = (float)kInnerTol32;  // unused: every column has its own
   HIPCHK(env, put_async(s, keep, lo.tol64, tol_host.data(), 8 * tol_host.size()));
   st.tolc = lo.tol32;
@@ -1644,6 +1656,7 @@ struct SolveJob {
          *GB = nullptr, *Zd = nullptr, *th = nullptr, *rpart = nullptr;
   cx<double>* Yprev = nullptr;  // warm starts: Y of the previous filter application
   double* Fprev = nullptr;      // and its right-hand side B X
+  std::vector<double> rhs_tgt;  // per right-hand side inner accuracy of the next application
   bool has_prev = false;        // Yprev and Fprev hold the previous outer iteration's
   int nch = 0, nrr = 0;
   int k = 0, prev_count = -1, count = 0;
@@ -1880,9 +1893,19 @@ slrf_status outer_step(Env& env, Carver arena, const std::vector<SolveJob*>& job
       if (J->prev_prev < INFINITY && J->prev_maxr > 0.3 * J->prev_prev) J->mix_c = std::max(1e-9, J->mix_c * 1e-2);
       target = std::max(1e-13, std::min(1e-3, J->mix_c * J->prev_maxr));
     }
-    fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, {}, J->part, J->GA, J->GB,
-                  J->nch});
+    fj.push_back({J->P, J->L, J->N, J->sig.data(), J->w.data(), J->V, J->U, target, nullptr, {}, J->part, J->GA,
+                  J->GB, J->nch});
     FilterJob& f = fj.back();
+    if (env.opt.precision == SLRF_MIXED && (int)J->theta.size() == J->L) {
+      // The columns of V are the Ritz vectors of the previous step, by value.
+      // Those beyond gamma only widen the subspace, and an inexact solve for
+      // them leaves the wanted directions in its span: they are solved to
+      // kBeyondGammaTarget (or the step's target if that is looser).
+      J->rhs_tgt.assign(J->L, target);
+      for (int l = 0; l < J->L; ++l)
+        if (J->theta[l] > J->gamma) J->rhs_tgt[l] = std::max(target, kBeyondGammaTarget);
+      f.rhs_target = J->rhs_tgt.data();
+    }
     if (env.opt.recycle && env.opt.precision == SLRF_MIXED && J->Yprev) {
       f.yprev = J->Yprev;
       f.fprev = J->Fprev;
