@@ -135,6 +135,20 @@ def test_golden_count_c2_is_plausible():
     assert 60 <= d["count_below_gamma"] <= 140
 
 
+def test_golden_c3_count_two_ways():
+    """The elasticity pencil's stored eigenvalues below gamma (the oracle's
+    shift-invert subspace iteration) and the Sylvester count of A - gamma B
+    (SuperLU's sparse LDL^T), both written by tests/golden/make_golden.py,
+    agree: every eigenvalue below gamma is in the list.  gamma sits mid-gap."""
+    with open(os.path.join(GOLDEN, "eig_elast3d_48_s3.json")) as f:
+        d = json.load(f)
+    ev = np.array(d["eigenvalues"])
+    assert d["n"] == 331776 and d["count"] == len(ev) == d["sparse_ldl_count"] == 199
+    assert np.all(np.diff(ev) >= 0) and ev[-1] < d["gamma"] < d["next_eigenvalue"]
+    assert min(d["gamma"] - ev[-1], d["next_eigenvalue"] - d["gamma"]) / d["gamma"] > 1e-3
+    assert d["converged"] and d["max_rho"] <= 1e-10
+
+
 # ---- filter and Krylov -----------------------------------------------------
 
 def test_filter_apply_closed_form_eigenvectors():
