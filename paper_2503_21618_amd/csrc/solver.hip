@@ -131,6 +131,16 @@ struct Pool {
 // ---------------------------------------------------------------------------
 // Pencils
 
+// Host copies of a pencil's preconditioner factors for one pole set in one
+// Krylov precision (element size rsize), kept across filter applications: the
+// poles of a solve do not change between its outer iterations, so the factors
+// are computed once per solve and re-uploaded from here.
+struct PrecTables {
+  int rsize = 0;
+  std::vector<double> sigma;
+  std::vector<char> ilu, bjac, sgsR, sgsD;
+};
+
 struct Pencil {
   int64_t n = 0, nnz = 0;
   int* rowptr = nullptr;
@@ -158,6 +168,7 @@ struct Pencil {
   size_t mem_bytes = 0;
   std::vector<int32_t> h_rp, h_cl, h_dpos;  // host copies for ILU(0) / block Jacobi
   std::vector<double> h_ab;
+  mutable PrecTables tables;  // the factors of the last pole set (upload_tables)
 };
 
 // The colours of a greedy colouring are at most the largest node degree + 1;
@@ -1022,6 +1033,65 @@ int column_order(const Env& env) {
   return 0;
 }
 
+// Fills P.tables with the preconditioner factors of the pole set sigma (2N)
+// in precision R, unless it already holds them: ILU(0) factors per pole, node
+// block inverses per pole (block Jacobi and node SGS), the node SGS factors
+// R and D per pole, or the point SGS factor R = sqrt(d) per (row, pole).
+template <typename R>
+slrf_status prec_tables(Env& env, const Pencil& P, int N, const double* sigma) {
+  PrecTables& T = P.tables;
+  if (T.rsize == (int)sizeof(R) && T.sigma.size() == (size_t)(2 * N) &&
+      std::equal(T.sigma.begin(), T.sigma.end(), sigma))
+    return SLRF_OK;
+  T = PrecTables{};
+  auto append = [](std::vector<char>& dst, const std::vector<std::complex<double>>& v) {
+    const size_t o = dst.size();
+    dst.resize(o + v.size() * sizeof(cx<R>));
+    cx<R>* out = reinterpret_cast<cx<R>*>(dst.data() + o);
+    for (size_t k = 0; k < v.size(); ++k) out[k] = {(R)v[k].real(), (R)v[k].imag()};
+  };
+  std::vector<std::complex<double>> f1, f2;
+  for (int p = 0; p < N; ++p) {
+    const std::complex<double> sg(sigma[2 * p], sigma[2 * p + 1]);
+    if (P.use_ilu) {
+      if (!ilu0_factor(P, sg, f1))
+        return fail(env, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
+      f1.resize((size_t)P.nnz);
+      append(T.ilu, f1);
+    }
+    if (P.use_bjac || P.sgs == 3) {
+      if (!bjac3_factor(P, sg, f1)) return fail(env, SLRF_E_BREAKDOWN, "singular node block of the shifted operator");
+      append(T.bjac, f1);
+    }
+    if (P.sgs == 3) {
+      if (!sgs3_factor(P, sg, f1, f2))
+        return fail(env, SLRF_E_BREAKDOWN, "node block of the shifted operator without a symmetric factor");
+      append(T.sgsR, f1);
+      append(T.sgsD, f2);
+    }
+  }
+  if (P.sgs == 1) {
+    // R = sqrt(d) per (row, pole), (n, N) layout; d itself is computed on the
+    // device in the Krylov precision from the same diagonals
+    std::vector<double> dA(P.n), dB(P.n);
+    for (int64_t i = 0; i < P.n; ++i)
+      for (int32_t q = P.h_rp[i]; q < P.h_rp[i + 1]; ++q)
+        if (P.h_cl[q] == i) {
+          dA[i] = P.h_ab[2 * (size_t)q];
+          dB[i] = P.h_ab[2 * (size_t)q + 1];
+        }
+    f1.resize((size_t)P.n * N);
+    for (int64_t i = 0; i < P.n; ++i)
+      for (int p = 0; p < N; ++p)
+        f1[(size_t)i * N + p] =
+            std::sqrt(std::complex<double>(dA[i], 0.0) - std::complex<double>(sigma[2 * p], sigma[2 * p + 1]) * dB[i]);
+    append(T.sgsR, f1);
+  }
+  T.rsize = (int)sizeof(R);
+  T.sigma.assign(sigma, sigma + 2 * N);
+  return SLRF_OK;
+}
+
 template <typename R>
 slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
                           std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
@@ -1037,7 +1107,13 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   }
   b.groups = any_group ? 1 : any_node ? 2 : 0;
   std::vector<int> tile_inst, col_inst;
-  std::vector<cx<R>> sigc, sigj, ilu_all, bjac_all, sgsR_all, sgsD_all;
+  std::vector<cx<R>> sigc, sigj;
+  struct Upload {
+    char* dst;
+    const char* src;  // a pencil's PrecTables, unchanged until the next application
+    size_t bytes;
+  };
+  std::vector<Upload> uploads;
   std::vector<double> sigc64, w;
   int64_t dn = 0, ilu_off = 0, bjac_off = 0, sgs_off = 0, sgsd_off = 0;  // sgsd: node blocks' D only
   b.sgs = 0;
@@ -1099,57 +1175,29 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
       sigc64.push_back(sigc64[sigc64.size() - 2]);
       sigc64.push_back(sigc64[sigc64.size() - 2]);
     }
+    slrf_status ts = prec_tables<R>(env, *j.P, j.N, j.sigma);
+    if (ts != SLRF_OK) return ts;
+    const PrecTables& T = j.P->tables;
     if (j.P->use_ilu) {
-      std::vector<std::complex<double>> fj;
-      for (int p = 0; p < j.N; ++p) {
-        if (!ilu0_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, fj))
-          return fail(env, SLRF_E_BREAKDOWN, "zero pivot in the ILU(0) factorisation of the shifted operator");
-        for (int64_t k = 0; k < j.P->nnz; ++k) ilu_all.push_back({(R)fj[k].real(), (R)fj[k].imag()});
-      }
       I.ilu = (const char*)lo.ilu + ilu_off * sizeof(cx<R>);
+      uploads.push_back({(char*)lo.ilu + ilu_off * sizeof(cx<R>), T.ilu.data(), T.ilu.size()});
       ilu_off += (int64_t)j.N * j.P->nnz;
     }
     if (j.P->use_bjac || j.P->sgs == 3) {
-      std::vector<std::complex<double>> fj;
-      for (int p = 0; p < j.N; ++p) {
-        if (!bjac3_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, fj))
-          return fail(env, SLRF_E_BREAKDOWN, "singular node block of the shifted operator");
-        for (const auto& v : fj) bjac_all.push_back({(R)v.real(), (R)v.imag()});
-      }
       I.bjac = (const char*)lo.bjac + bjac_off * sizeof(cx<R>);
+      uploads.push_back({(char*)lo.bjac + bjac_off * sizeof(cx<R>), T.bjac.data(), T.bjac.size()});
       bjac_off += (int64_t)j.N * (j.P->n / 3) * 9;
     }
     if (j.P->sgs == 3) {
-      std::vector<std::complex<double>> Rf, Df;
-      for (int p = 0; p < j.N; ++p) {
-        if (!sgs3_factor(*j.P, {j.sigma[2 * p], j.sigma[2 * p + 1]}, Rf, Df))
-          return fail(env, SLRF_E_BREAKDOWN, "node block of the shifted operator without a symmetric factor");
-        for (const auto& v : Rf) sgsR_all.push_back({(R)v.real(), (R)v.imag()});
-        for (const auto& v : Df) sgsD_all.push_back({(R)v.real(), (R)v.imag()});
-      }
       I.sgsR = (const char*)lo.sgsR + sgs_off * sizeof(cx<R>);
       I.sgsD = (const char*)lo.sgsD + sgsd_off * sizeof(cx<R>);
+      uploads.push_back({(char*)lo.sgsR + sgs_off * sizeof(cx<R>), T.sgsR.data(), T.sgsR.size()});
+      uploads.push_back({(char*)lo.sgsD + sgsd_off * sizeof(cx<R>), T.sgsD.data(), T.sgsD.size()});
       sgs_off += (int64_t)j.N * (j.P->n / 3) * 9;
       sgsd_off += (int64_t)j.N * (j.P->n / 3) * 9;
     } else if (j.P->sgs == 1) {
-      // R = sqrt(d) per (row, pole), in the (n, N) layout of d at Inst::dn
-      const std::vector<double>& ab = j.P->h_ab;
-      std::vector<double> dA(I.n), dB(I.n);
-      for (int64_t i = 0; i < I.n; ++i)
-        for (int32_t q = j.P->h_rp[i]; q < j.P->h_rp[i + 1]; ++q)
-          if (j.P->h_cl[q] == i) {
-            dA[i] = ab[2 * (size_t)q];
-            dB[i] = ab[2 * (size_t)q + 1];
-          }
-      // d is computed on the device in the Krylov precision from the same
-      // diagonals; R is rounded from the FP64 square root; (n, N) layout
-      for (int64_t i = 0; i < I.n; ++i)
-        for (int p = 0; p < j.N; ++p) {
-          const std::complex<double> r =
-              std::sqrt(std::complex<double>(dA[i], 0.0) - std::complex<double>(j.sigma[2 * p], j.sigma[2 * p + 1]) * dB[i]);
-          sgsR_all.push_back({(R)r.real(), (R)r.imag()});
-        }
       I.sgsR = (const char*)lo.sgsR + sgs_off * sizeof(cx<R>);
+      uploads.push_back({(char*)lo.sgsR + sgs_off * sizeof(cx<R>), T.sgsR.data(), T.sgsR.size()});
       sgs_off += (int64_t)I.n * I.N;
     }
     if (j.P->sgs) {
@@ -1175,13 +1223,8 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   HIPCHK(env, put_async(s, keep, lo.sig_j, sigj.data(), sizeof(cx<R>) * sigj.size()));
   HIPCHK(env, put_async(s, keep, lo.w, w.data(), 8 * w.size()));
   if (lo.sigma_col64) HIPCHK(env, put_async(s, keep, lo.sigma_col64, sigc64.data(), 8 * sigc64.size()));
-  if (!ilu_all.empty()) HIPCHK(env, put_async(s, keep, lo.ilu, ilu_all.data(), sizeof(cx<R>) * ilu_all.size()));
-  if (!bjac_all.empty())
-    HIPCHK(env, put_async(s, keep, lo.bjac, bjac_all.data(), sizeof(cx<R>) * bjac_all.size()));
-  if (!sgsR_all.empty())
-    HIPCHK(env, put_async(s, keep, lo.sgsR, sgsR_all.data(), sizeof(cx<R>) * sgsR_all.size()));
-  if (!sgsD_all.empty())
-    HIPCHK(env, put_async(s, keep, lo.sgsD, sgsD_all.data(), sizeof(cx<R>) * sgsD_all.size()));
+  for (const Upload& u : uploads)
+    if (u.bytes) HIPCHK(env, hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s));
   return SLRF_OK;
 }
 
