@@ -168,19 +168,30 @@ bool projected_pencil(int L, const double* GA, const double* GB, double* theta, 
   for (int i = 0; i < L; ++i)
     for (int j = 0; j < L; ++j)
       T[(size_t)i * L + j] = s[i] * V[(size_t)i * L + j] / std::sqrt(std::max(lam[j], floor_));
-  // C = T^T GA T
+  // C = T^T GA T, with GA symmetrised; the products run row by row over
+  // contiguous rows (i, k, j order)
+  std::vector<double> As((size_t)L * L);
   for (int i = 0; i < L; ++i)
-    for (int j = 0; j < L; ++j) {
-      double acc = 0;
-      for (int k = 0; k < L; ++k) acc += 0.5 * (GA[(size_t)i * L + k] + GA[(size_t)k * L + i]) * T[(size_t)k * L + j];
-      tmp[(size_t)i * L + j] = acc;
+    for (int k = 0; k < L; ++k) As[(size_t)i * L + k] = 0.5 * (GA[(size_t)i * L + k] + GA[(size_t)k * L + i]);
+  std::fill(tmp.begin(), tmp.end(), 0.0);
+  for (int i = 0; i < L; ++i) {
+    double* out = tmp.data() + (size_t)i * L;
+    for (int k = 0; k < L; ++k) {
+      const double a = As[(size_t)i * L + k];
+      const double* t = T.data() + (size_t)k * L;
+      for (int j = 0; j < L; ++j) out[j] += a * t[j];
     }
-  for (int i = 0; i < L; ++i)
-    for (int j = 0; j < L; ++j) {
-      double acc = 0;
-      for (int k = 0; k < L; ++k) acc += T[(size_t)k * L + i] * tmp[(size_t)k * L + j];
-      C[(size_t)i * L + j] = acc;
+  }
+  std::fill(C.begin(), C.end(), 0.0);
+  for (int k = 0; k < L; ++k) {
+    const double* t = T.data() + (size_t)k * L;
+    const double* m = tmp.data() + (size_t)k * L;
+    for (int i = 0; i < L; ++i) {
+      const double a = t[i];
+      double* out = C.data() + (size_t)i * L;
+      for (int j = 0; j < L; ++j) out[j] += a * m[j];
     }
+  }
   for (int i = 0; i < L; ++i)
     for (int j = 0; j < i; ++j) {
       const double a = 0.5 * (C[(size_t)i * L + j] + C[(size_t)j * L + i]);
@@ -189,12 +200,15 @@ bool projected_pencil(int L, const double* GA, const double* GB, double* theta, 
   if (!sym_eig(L, C.data(), th.data(), S.data())) return false;
   for (int j = 0; j < L; ++j) theta[j] = th[j];
   // Z = T S
-  for (int i = 0; i < L; ++i)
-    for (int j = 0; j < L; ++j) {
-      double acc = 0;
-      for (int k = 0; k < L; ++k) acc += T[(size_t)i * L + k] * S[(size_t)k * L + j];
-      Z[(size_t)i * L + j] = acc;
+  for (int i = 0; i < L; ++i) {
+    double* out = Z + (size_t)i * L;
+    std::fill(out, out + L, 0.0);
+    for (int k = 0; k < L; ++k) {
+      const double a = T[(size_t)i * L + k];
+      const double* sr = S.data() + (size_t)k * L;
+      for (int j = 0; j < L; ++j) out[j] += a * sr[j];
     }
+  }
   return true;
 }
 
