@@ -52,47 +52,6 @@ void launch_filter_sum(hipStream_t s, int n, int L, int N, int W, int rmaj, cons
                                                                              accumulate ? 1 : 0);
 }
 
-// Warm start of the shifted solves: Y0 = Y_prev C per pole, with the real L x L
-// C = X_prev^T B X_new (row-major, C[l * L + l']).  Y_prev, Y0: tile-major
-// complex FP64 blocks (tiles of W columns) in column order rmaj, K = N L
-// columns padded to Kp; the padding columns of Y0 are zero.  One thread per
-// (row, pole, kRecycleCols consecutive right-hand sides), poles varying fastest
-// across the lanes: each Y_prev value read serves kRecycleCols outputs.
-constexpr int kRecycleCols = 4;
-
-__global__ void k_recycle(int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* __restrict__ Yp,
-                          const double* __restrict__ C, cx<double>* __restrict__ Y0) {
-  const int per_row = (L + kRecycleCols - 1) / kRecycleCols * N;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * per_row) return;
-  const int64_t i = e / per_row;
-  const int g = (int)(e % per_row);
-  const int j = g % N, lp0 = g / N * kRecycleCols, cnt = min(kRecycleCols, L - lp0);
-  auto off = [&](int c) { return (int64_t)(c / W) * n * W + i * W + c % W; };
-  cx<double> y[kRecycleCols] = {};
-  for (int l = 0; l < L; ++l) {
-    const cx<double> v = Yp[off(col_of(j, l, L, N, rmaj))];
-    const double* cr = C + (int64_t)l * L + lp0;
-#pragma unroll
-    for (int u = 0; u < kRecycleCols; ++u) {
-      const double gu = u < cnt ? cr[u] : 0.0;
-      y[u].re += gu * v.re;
-      y[u].im += gu * v.im;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kRecycleCols; ++u)
-    if (u < cnt) Y0[off(col_of(j, lp0 + u, L, N, rmaj))] = y[u];
-  if (g == 0)
-    for (int c = N * L; c < Kp; ++c) Y0[off(c)] = {0.0, 0.0};
-}
-
-void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
-                    const double* C, cx<double>* Y0) {
-  const int64_t tot = (int64_t)n * ((L + kRecycleCols - 1) / kRecycleCols * N);
-  k_recycle<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, L, N, W, Kp, rmaj, Yp, C, Y0);
-}
-
 // Real products of the merged pencil with a real block: one wavefront per row.
 template <typename R>
 __global__ __launch_bounds__(WG) void k_spmm_real(int n, int L, const int* __restrict__ rowptr,
@@ -312,6 +271,76 @@ void launch_gemm_nz(hipStream_t s, int n, int L, int r, int nb, const double* co
     gbk.Y[b] = Y[b];
   }
   k_gemm_nz<<<dim3((n + 63) / 64, nb), dim3(WG), 0, s>>>(n, L, r, gbk, Z);
+}
+
+// Warm start of the shifted solves: Y0 = Y_prev C per pole, with the real L x L
+// C = X_prev^T B X_new (row-major, C[l * L + l']).  Y_prev, Y0: tile-major
+// complex FP64 blocks (tiles of W columns) in column order rmaj, K = N L
+// columns padded to Kp; the padding columns of Y0 are zero.  On FP64 MFMA: for
+// pole j the rows (i, re) and (i, im) of Y_prev's columns of that pole form a
+// 2n x L real matrix A_j, and Y0's columns of pole j are A_j C.  A wavefront
+// owns 16 rows of A_j (8 grid rows, both parts) and sweeps the output columns
+// 128 at a time; the pole-0 wavefronts also zero their rows' padding columns.
+__global__ __launch_bounds__(WG) void k_recycle(int n, int L, int N, int W, int Kp, int rmaj,
+                                               const double* __restrict__ Yp, const double* __restrict__ C,
+                                               double* __restrict__ Y0) {
+  using M = Mfma<false>;
+  const int j = blockIdx.y;
+  const int w = wave_id(), lane = lane_id();
+  const int li = lane >> 4, lj = lane & 15;
+  const int64_t rows = 2 * (int64_t)n;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + w * 16;
+  if (row0 >= rows) return;
+  // index (in doubles) of A_j[r][l]: grid row r / 2, part r % 2, column l of pole j
+  auto elem = [&](int64_t r, int l) -> int64_t {
+    const int c = col_of(j, l, L, N, rmaj);
+    return (((int64_t)(c / W) * n + (r >> 1)) * W + c % W) * 2 + (r & 1);
+  };
+  const int64_t ra = row0 + lj;
+  const bool rok = ra < rows;
+  for (int c0 = 0; c0 < L; c0 += 128) {
+    M::acc_t acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = M::acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < L; k0 += 4) {
+      const int k = k0 + li;
+      const double a = (rok && k < L) ? Yp[elem(ra, k)] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int cc = c0 + 16 * t + lj;
+        const double bv = (k < L && cc < L) ? C[(int64_t)k * L + cc] : 0.0;
+        acc[t] = M::op(a, bv, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + M::row(li, q);
+        const int cc = c0 + 16 * t + lj;
+        if (r < rows && cc < L) Y0[elem(r, cc)] = acc[t][q];
+      }
+  }
+  const int pad = Kp - N * L;
+  if (j == 0 && pad > 0) {
+    const int64_t i0 = row0 >> 1;
+    for (int e = lane; e < 8 * pad; e += WAVE) {
+      const int64_t i = i0 + e / pad;
+      const int c = N * L + e % pad;
+      if (i < n) {
+        const int64_t o = (((int64_t)(c / W) * n + i) * W + c % W) * 2;
+        Y0[o] = 0.0;
+        Y0[o + 1] = 0.0;
+      }
+    }
+  }
+}
+
+void launch_recycle(hipStream_t s, int n, int L, int N, int W, int Kp, int rmaj, const cx<double>* Yp,
+                    const double* C, cx<double>* Y0) {
+  const unsigned blocks = (unsigned)((2 * (int64_t)n + 63) / 64);
+  k_recycle<<<dim3(blocks, (unsigned)N), dim3(WG), 0, s>>>(n, L, N, W, Kp, rmaj, (const double*)Yp, C,
+                                                            (double*)Y0);
 }
 
 // Residual column sums over row blocks of 256 rows.
