@@ -60,13 +60,15 @@ class Server:
     ws_bytes: device workspace (pool + arena); arena_bytes: filter arena shared
     by the unfinished pencils of a step.  clock: returns the current time
     (default: wall clock relative to the server's start); tests pass a step
-    counter instead."""
+    counter instead.  make_batch: builds the batch (default lib.Batch); tests
+    of the scheduling pass a host-only stand-in with the same methods."""
     ws_bytes: int
     arena_bytes: int
     max_poles: int = 6
     options: object = None
     stream: object = None
     clock: object = None
+    make_batch: object = None
     batch: lib.Batch = field(init=False)
     queue: deque = field(init=False, default_factory=deque)
     active: dict = field(init=False, default_factory=dict)
@@ -75,8 +77,9 @@ class Server:
     peak_active: int = field(init=False, default=0)
 
     def __post_init__(self):
-        self.batch = lib.Batch(self.ws_bytes, self.arena_bytes, self.max_poles, self.options,
-                               stream=self.stream)
+        make = self.make_batch or (lambda: lib.Batch(self.ws_bytes, self.arena_bytes, self.max_poles,
+                                                     self.options, stream=self.stream))
+        self.batch = make()
         if self.clock is None:
             t0 = time.perf_counter()
             self.clock = lambda: time.perf_counter() - t0
