@@ -500,7 +500,7 @@ def run_batched(slrf, args):
 
     import pencils
     t0 = time.perf_counter()
-    insts = [pencils.batch_instance(i) for i in range(args.instances)]
+    insts = [pencils.batch_instance(i, n_range=(args.batch_n_min, args.batch_n_max)) for i in range(args.instances)]
     log(f"built {len(insts)} pencils in {time.perf_counter() - t0:.1f} s, "
         f"sum n = {sum(p.n for p, *_ in insts)}")
     N = 6
@@ -1032,6 +1032,8 @@ def main():
                          "the 64^3 workload), BiCGStab for the ILU(0) string")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of pencils")
+    ap.add_argument("--batch-n-min", type=float, default=5e3, help="batched workload: smallest pencil")
+    ap.add_argument("--batch-n-max", type=float, default=2e5, help="batched workload: largest pencil")
     ap.add_argument("--requests", type=int, default=2000, help="served workload: most requests")
     ap.add_argument("--duration", type=float, default=600.0, help="served workload: seconds of arrivals")
     ap.add_argument("--structures", type=int, default=16, help="served workload: distinct pencils")
@@ -1085,7 +1087,7 @@ def main():
     if args.workload == "batched":
         out, insts = run_batched(slrf, args)
         desc = (f"{len(insts)} independent 2D/3D scalar vibration pencils (bilinear/trilinear FE, "
-                "log-normal coefficient sigma=0.5, seeds 1000+i), n log-uniform 5e3..2e5 "
+                f"log-normal coefficient sigma=0.5, seeds 1000+i), n log-uniform {args.batch_n_min:.0e}..{args.batch_n_max:.0e} "
                 f"(sum {sum(p.n for p, *_ in insts)}), NEV 10..80 each with its own gamma, "
                 "L = ceil(1.2 NEV) to a multiple of 8, N=6; one batch, mixed precision, autotuned tiles; "
                 f"inner solver {'BiCGStab' if args.solver == 'bicgstab' else 'COCG'}"
