@@ -117,6 +117,26 @@ __device__ __forceinline__ void count_tile(int* counter) {
   if (counter && threadIdx.x == 0) atomicAdd(counter, 1);
 }
 
+// The partial sums of a workgroup that owns no rows of a tile's pencil are
+// zero: wavefront 0 stores them directly (the values wg_store_partial would
+// store), with no flags, LDS reduction or barrier.  In a batch of small
+// pencils most (workgroup, tile) pairs are of this kind.
+template <typename T, int V>
+__device__ __forceinline__ void zero_partial(int w, int lane, int cl0, int K, T* out) {
+  if (w != 0) return;
+#pragma unroll
+  for (int u = 0; u < V; ++u)
+    if (cl0 + u < K) out[V * lane + u] = T(0);
+}
+
+template <typename R, int V>
+__device__ __forceinline__ void zero_partial_cx(int w, int lane, int cl0, int K, cx<R>* out) {
+  if (w != 0) return;
+#pragma unroll
+  for (int u = 0; u < V; ++u)
+    if (cl0 + u < K) out[V * lane + u] = cx<R>{0, 0};
+}
+
 // Sums of the 4 wavefronts' per-lane values in a fixed order; lane l of wave 0
 // stores column v's sum at out[V l + v] (out points at this workgroup's slice of
 // the tile), for the columns before K.
@@ -830,22 +850,68 @@ __device__ __forceinline__ size_t slot_partial(int k, int per, int rot) {
   return (size_t)(8 * q + (k & 7));
 }
 
+// Which slots of a pencil can hold a nonzero partial.  A workgroup that owns
+// none of the pencil's rows stores zeros, and a sum that starts at +0 is not
+// changed by adding +0, so skipping those slots leaves every sum bit for bit as
+// it was.  kind 1: the row blocks of step_block (slot k is live if its first
+// row block exists); kind 2: the colour shares of the SGS sweeps (workgroup
+// x * per + q takes the g-th share of each colour, and shares past gs are
+// empty in every colour); kind 0: every slot.
+struct SlotLive {
+  int kind = 0;
+  int slab = 0, nrb = 0;
+  int gs = 0;
+  __device__ bool operator()(int k, int per, int rot) const {
+    const int j = k >> 3;
+    if (kind == 1) return j < slab && (k & 7) * slab + j < nrb;
+    if (kind == 2) {
+      const int q = j >= rot ? j - rot : j - rot + per;
+      return (k & 7) * per + q < gs;
+    }
+    return true;
+  }
+};
+
+__device__ __forceinline__ SlotLive rows_live(const Inst& I) {
+  SlotLive l;
+  l.kind = 1;
+  l.slab = I.slab;
+  l.nrb = I.nrb;
+  return l;
+}
+
+// shares of G workgroups: colour c's share size is ceil(size_c / G), so
+// workgroups g < ceil(size_c / share) have nodes of colour c
+__device__ __forceinline__ SlotLive sweep_live(const Inst& I, int G) {
+  SlotLive l;
+  l.kind = 2;
+  const cptr<int> cp = as_const(I.sgs_cptr);
+  for (int c = 0; c < I.sgs_ncol; ++c) {
+    const int sz = cp[c + 1] - cp[c];
+    if (sz <= 0) continue;
+    const int share = (sz + G - 1) / G;
+    l.gs = max(l.gs, (sz + share - 1) / share);
+  }
+  return l;
+}
+
 // Column sums of the partials: wavefront w of the block's nw (up to 16) adds
-// slots w, w + nw, ... in slot order, then the nw sums are added in wavefront
-// order (the order depends only on the block size).
+// slots w, w + nw, ... in slot order (the live ones), then the nw sums are
+// added in wavefront order (the order depends only on the block size).
 constexpr int kMaxScWaves = 16;
 // threads of the COCG scalar kernels (one block per column tile: the G partials
 // of each column are read by 16 wavefronts)
 constexpr int kScWG = kMaxScWaves * WAVE;
 template <typename T>
 __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int rot, int Ktot, int c,
-                                           bool valid) {
+                                           bool valid, const SlotLive& live = SlotLive{}) {
   __shared__ T red[kMaxScWaves][WAVE];
   const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
   T acc = 0;
   if (valid) {
 #pragma unroll 8
-    for (int k = w; k < G; k += nw) acc += part[slot_partial(k, per, rot) * Ktot + c];
+    for (int k = w; k < G; k += nw)
+      if (live(k, per, rot)) acc += part[slot_partial(k, per, rot) * Ktot + c];
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -857,13 +923,14 @@ __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, in
 
 template <typename R>
 __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int rot, int Ktot, int c,
-                                                  bool valid) {
+                                                  bool valid, const SlotLive& live = SlotLive{}) {
   __shared__ R rr[kMaxScWaves][WAVE], ri[kMaxScWaves][WAVE];
   const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
   R ar = 0, ai = 0;
   if (valid) {
 #pragma unroll 8
     for (int k = w; k < G; k += nw) {
+      if (!live(k, per, rot)) continue;
       const cx<R> v = part[slot_partial(k, per, rot) * Ktot + c];
       ar += v.re;
       ai += v.im;
@@ -1508,12 +1575,14 @@ __global__ __launch_bounds__(kScWG) void k_cocg_init_scalars(Batch b, KrylovStat
     b.active[blockIdx.x] = blockIdx.x;
     if (blockIdx.x == 0) b.n_active[0] = b.n_tiles;
   }
+  // with SGS both sums come from the first forward sweep
+  const SlotLive live = I.sgs ? sweep_live(I, b.G) : SlotLive{};
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const R nn = block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok);
-    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    const R nn = block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok, live);
+    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok, live);
     if (!lead || cl0 + v >= I.Kp) continue;
     st.fnorm[c] = sqrt(nn);
     st.rnorm[c] = sqrt(nn);
@@ -1560,11 +1629,13 @@ __global__ __launch_bounds__(kScWG) void k_cocg_alpha(Batch b, KrylovState<R> st
   constexpr int V = LaneWidth<R>::V;
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+  // [p, q] from the forward sweeps (SGS) or from the row blocks of the product
+  const SlotLive live = I.sgs ? sweep_live(I, b.G) : rows_live(I);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const cx<R> pq = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
+    const cx<R> pq = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok, live);
     if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
     const cx<R> rho = st.rho[c];
     if ((pq.re == 0 && pq.im == 0) || (rho.re == 0 && rho.im == 0) || !cfinite(pq)) {
@@ -1576,12 +1647,20 @@ __global__ __launch_bounds__(kScWG) void k_cocg_alpha(Batch b, KrylovState<R> st
   }
 }
 
-// x += alpha p, r -= alpha q for active columns; partials [r, M^{-1} r] and ||r||^2
+// x += alpha p, r -= alpha q for active columns; partials [r, M^{-1} r] and ||r||^2.
+// A pure stream: non-temporal loads and stores.
 template <typename R>
 __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R> st, int* counter) {
   constexpr int V = LaneWidth<R>::V;
   const WgPos p = wg_pos(b.G);
   FOR_ACTIVE_TILES(b, p, V)
+    const bool node_rows = I.bjac && !I.sgs;
+    if (node_rows ? (int)blockIdx.x * 4 >= I.n / 3 : step_block(I, p, 0) < 0) {  // no rows here
+      if (counter && tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) count_tile(counter);
+      zero_partial_cx<R, V>(p.w, p.lane, cl0, I.K, st.part_a + po);
+      zero_partial<R, V>(p.w, p.lane, cl0, I.K, st.part_b + po);
+      continue;
+    }
     cx<R> rz[V] = {};
     R nn[V] = {};
     if (tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) {
@@ -1594,17 +1673,17 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
         pole[v] = col_pole(cc0 + v, I.L, I.N, I.rmaj);
         alpha[v] = f[v] == COL_ACTIVE ? st.alpha[cg0 + v] : cx<R>{0, 0};
       }
-      if (I.bjac && !I.sgs) {  // node block Jacobi: one node per wavefront step
+      if (node_rows) {  // node block Jacobi: one node per wavefront step
         for (int k = blockIdx.x * 4 + p.w; k < I.n / 3; k += b.G * 4) {
           const size_t e0 = tb + (size_t)(3 * k) * (WAVE * V);
           cvec<R, V> x[3], r[3], pv[3], q[3], z[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
             const size_t e = e0 + (size_t)i * (WAVE * V);
-            x[i] = ldv<R, V>(st.x + e);
-            r[i] = ldv<R, V>(st.r + e);
-            pv[i] = ldv<R, V>(st.ph + e);
-            q[i] = ldv<R, V>(st.v + e);
+            x[i] = ldv_nt<R, V>(st.x + e);
+            r[i] = ldv_nt<R, V>(st.r + e);
+            pv[i] = ldv_nt<R, V>(st.ph + e);
+            q[i] = ldv_nt<R, V>(st.v + e);
           }
 #pragma unroll
           for (int i = 0; i < 3; ++i)
@@ -1626,8 +1705,8 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
               rz[v].im += t.im;
               nn[v] += rv.re * rv.re + rv.im * rv.im;
             }
-            stv<R, V>(st.x + e0 + (size_t)i * (WAVE * V), x[i]);
-            stv<R, V>(st.r + e0 + (size_t)i * (WAVE * V), r[i]);
+            stv_nt<R, V>(st.x + e0 + (size_t)i * (WAVE * V), x[i]);
+            stv_nt<R, V>(st.r + e0 + (size_t)i * (WAVE * V), r[i]);
           }
         }
       } else {
@@ -1638,10 +1717,10 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u) {
           e[u] = tb + (size_t)ic[u] * (WAVE * V);
-          x[u] = ldv<R, V>(st.x + e[u]);
-          r[u] = ldv<R, V>(st.r + e[u]);
-          pv[u] = ldv<R, V>(st.ph + e[u]);
-          q[u] = ldv<R, V>(st.v + e[u]);
+          x[u] = ldv_nt<R, V>(st.x + e[u]);
+          r[u] = ldv_nt<R, V>(st.r + e[u]);
+          pv[u] = ldv_nt<R, V>(st.ph + e[u]);
+          q[u] = ldv_nt<R, V>(st.v + e[u]);
         }
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u) {
@@ -1659,8 +1738,8 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_xr(Batch b, KrylovState<R
             rz[v].im += t.im;
             nn[v] += rv.re * rv.re + rv.im * rv.im;
           }
-          stv<R, V>(st.x + e[u], x[u]);
-          stv<R, V>(st.r + e[u], r[u]);
+          stv_nt<R, V>(st.x + e[u], x[u]);
+          stv_nt<R, V>(st.r + e[u], r[u]);
         }
       END_ROWS
       }
@@ -1676,12 +1755,14 @@ __global__ __launch_bounds__(kScWG) void k_cocg_beta(Batch b, KrylovState<R> st,
   constexpr int V = LaneWidth<R>::V;
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
+  // sums of the x, r update: row blocks, or grid-strided nodes (node block Jacobi)
+  const SlotLive live = I.bjac && !I.sgs ? SlotLive{} : rows_live(I);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
     const bool ok = cl0 + v < I.K;
-    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok);
-    const R nn = sqrt(block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok));
+    const cx<R> rz = block_col_sum_cx(st.part_a, b.G, I.rot, b.Ktot, c, ok, live);
+    const R nn = sqrt(block_col_sum(st.part_b, b.G, I.rot, b.Ktot, c, ok, live));
     if (!lead || !ok || st.flags[c] != COL_ACTIVE) continue;
     st.rnorm[c] = nn;
     if (nn <= (st.tolc ? st.tolc[c] : tol) * st.fnorm[c]) {
@@ -1780,7 +1861,9 @@ __global__ __launch_bounds__(WG, 4) void k_cocg_update_p(Batch b, KrylovState<R>
 //           q = W p and [p, q]; alpha; x' += alpha p, r' -= alpha q; beta
 //   finish: y = (D + U)^{-1} R x'
 // The partial sums of the forward sweeps are accumulated over the colour
-// launches in the workgroup's slot (fixed order: bitwise reproducible).
+// launches in the workgroup's slot (fixed order: bitwise reproducible).  A
+// node's own rows are read and written once per launch and go through
+// non-temporal accesses: L2 is left to the gathered rows of its neighbours.
 constexpr int kSgsBackIter = 0, kSgsBackFinal = 1, kSgsFwdIter = 2, kSgsFwdStart = 3;
 
 template <typename T, int V>
@@ -1891,10 +1974,28 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
   FOR_TILE_LIST(b, p, V, all_tiles ? b.n_tiles : as_const((const int*)b.n_active)[0],
                 all_tiles ? ti_ : as_const((const int*)b.active)[ti_])
     if (I.sgs != BS) continue;  // the other block size's launch owns this pencil's tiles
+    // a contiguous share of the colour's nodes per workgroup, XCD by XCD
+    int q0 = 0, q1 = 0;
+    if (colour < I.sgs_ncol) {
+      const cptr<int> cptr_ = as_const(I.sgs_cptr);
+      const int c0 = cptr_[colour], c1 = cptr_[colour + 1];
+      const int per = (c1 - c0 + b.G - 1) / b.G;
+      q0 = c0 + (p.x * p.per + p.q) * per;
+      q1 = min(c1, q0 + per);
+    }
+    if (q0 >= q1) {  // no nodes here: zero partials, written by the first colour launch
+      if (counter && colour < I.sgs_ncol &&
+          (all_tiles || tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)))
+        count_tile(counter);
+      if (fwd && !add) {
+        zero_partial_cx<R, V>(p.w, p.lane, cl0, I.K, st.part_a + po);
+        if (MODE == kSgsFwdStart) zero_partial<R, V>(p.w, p.lane, cl0, I.K, st.part_b + po);
+      }
+      continue;
+    }
     cx<R> da[V] = {};
     R db[V] = {};
-    const bool go = colour < I.sgs_ncol &&
-                    (all_tiles || tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE));
+    const bool go = all_tiles || tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE);
     if (go) {
       count_tile(counter);
       int f[V], pole[V];
@@ -1906,11 +2007,6 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
         sig[v] = st.sigma_col[cg0 + v];
         beta[v] = st.beta[cg0 + v];
       }
-      const cptr<int> cptr_ = as_const(I.sgs_cptr);
-      const int c0 = cptr_[colour], c1 = cptr_[colour + 1];
-      // a contiguous share of the colour's nodes per workgroup, XCD by XCD
-      const int per = (c1 - c0 + b.G - 1) / b.G;
-      const int q0 = c0 + (p.x * p.per + p.q) * per, q1 = min(c1, q0 + per);
       const cptr<int> nodes = as_const(I.sgs_nodes);
       for (int q = q0 + p.w; q < q1; q += 4) {
         const int k = nodes[q];
@@ -1921,8 +2017,8 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
         for (int i = 0; i < BS; ++i) {
           const size_t e = e0 + (size_t)i * (WAVE * V);
           if (MODE == kSgsBackIter) {
-            const cvec<R, V> rv = ldv<R, V>(st.r + e);
-            cvec<R, V> pv = first ? rv : ldv<R, V>(st.ph + e);
+            const cvec<R, V> rv = ldv_nt<R, V>(st.r + e);
+            cvec<R, V> pv = first ? rv : ldv_nt<R, V>(st.ph + e);
             if (!first) {
 #pragma unroll
               for (int v = 0; v < V; ++v)
@@ -1930,12 +2026,12 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
             }
             own[i] = pv;
           } else if (MODE == kSgsBackFinal) {
-            own[i] = ldv<R, V>(st.x + e);
+            own[i] = ldv_nt<R, V>(st.x + e);
           } else if (MODE == kSgsFwdIter) {
-            own[i] = ldv<R, V>(st.ph + e);
-            two[i] = ldv<R, V>(st.t + e);
+            own[i] = ldv_nt<R, V>(st.ph + e);
+            two[i] = ldv_nt<R, V>(st.t + e);
           } else {
-            own[i] = ldv<R, V>(st.r + e);
+            own[i] = ldv_nt<R, V>(st.r + e);
           }
         }
         if (fwd)
@@ -1991,17 +2087,17 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
         for (int i = 0; i < BS; ++i) {
           const size_t e = e0 + (size_t)i * (WAVE * V);
           if (MODE == kSgsBackIter) {
-            stv<R, V>(st.ph + e, own[i]);
-            stv<R, V>(st.t + e, res[i]);
+            stv_nt<R, V>(st.ph + e, own[i]);
+            stv_nt<R, V>(st.t + e, res[i]);
           } else if (MODE == kSgsBackFinal) {
-            stv<R, V>(st.t + e, res[i]);
-            stv<R, V>(st.x + e, res[i]);
+            stv_nt<R, V>(st.t + e, res[i]);
+            stv_nt<R, V>(st.x + e, res[i]);
           } else if (MODE == kSgsFwdIter) {
-            stv<R, V>(st.sh + e, res[i]);
-            stv<R, V>(st.v + e, out2[i]);
+            stv_nt<R, V>(st.sh + e, res[i]);
+            stv_nt<R, V>(st.v + e, out2[i]);
           } else {
-            stv<R, V>(st.sh + e, res[i]);
-            stv<R, V>(st.r + e, out2[i]);
+            stv_nt<R, V>(st.sh + e, res[i]);
+            stv_nt<R, V>(st.r + e, out2[i]);
           }
         }
       }

@@ -1097,7 +1097,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
                           std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
   const hipStream_t s = env.stream;
   insts.assign(jobs.size(), Inst{});
-  b.V = std::is_same<R, float>::value ? 2 : 1;
+  b.V = lane_width(std::is_same<R, float>::value);
   // sparse-product variant: stencil groups if some pencil has them, else node
   // triples if some pencil has those (1 and 2, the kernels' row modes)
   bool any_group = false, any_node = false;
@@ -1126,7 +1126,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.L = j.L;
     I.N = j.N;
     I.K = j.N * j.L;
-    I.Kp = (int)padded_k(I.K, b.V == 2);
+    I.Kp = (int)padded_k(I.K, std::is_same<R, float>::value);
     I.col0 = col0;
     I.tile0 = tile0;
     I.nnz = (int)j.P->nnz;
