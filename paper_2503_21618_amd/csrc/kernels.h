@@ -63,6 +63,7 @@ struct Inst {
   // Inst::dn like d; blocks: (N, n/3, 3, 3) row-major), sgsD the node blocks D
   // (blocks only; point pencils use d), bjac their inverses (blocks; point: dinv).
   int sgs, sgs_ncol;
+  int sgs_share, sgs_wgs;  // nodes of a colour per sweep workgroup (a multiple of 4), shares used
   const int* sgs_cptr;
   const int* sgs_nodes;
   const int* lrp;
@@ -100,6 +101,7 @@ struct Batch {
   int n_tiles;
   int Ktot;               // global columns, each pencil padded to Kp
   int G;                  // grid, a multiple of 8
+  int Gs;                 // grid of the multicolour SGS sweeps, a multiple of 8
   int rows_per_block;
   int V;                  // columns per lane (1 for complex FP64, 2 for complex FP32)
   int groups;             // sparse-product row mode: 1 stencil groups, 2 node triples, 0 neither
@@ -151,9 +153,10 @@ struct LaunchTimer {
     double tile_bytes;  // bytes of a launch that processes every tile (scale with tiles)
     double fixed;       // bytes read once per launch whatever the tiles (merged CSR)
     double share;       // share of one product with S a full-width launch performs
+    int grid;           // workgroups of the launch (0: the batch grid G)
   };
   Rec recs[512];
-  int* begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share = 1.0);
+  int* begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share = 1.0, int grid = 0);
   void end(hipStream_t s);
 };
 

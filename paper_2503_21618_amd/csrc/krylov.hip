@@ -850,48 +850,40 @@ __device__ __forceinline__ size_t slot_partial(int k, int per, int rot) {
   return (size_t)(8 * q + (k & 7));
 }
 
-// Which slots of a pencil can hold a nonzero partial.  A workgroup that owns
-// none of the pencil's rows stores zeros, and a sum that starts at +0 is not
-// changed by adding +0, so skipping those slots leaves every sum bit for bit as
-// it was.  kind 1: the row blocks of step_block (slot k is live if its first
-// row block exists); kind 2: the colour shares of the SGS sweeps (workgroup
-// x * per + q takes the g-th share of each colour, and shares past gs are
-// empty in every colour); kind 0: every slot.
-struct SlotLive {
+// Which slots of a pencil's partial sums to add.  A workgroup that owns none
+// of the pencil's rows stores zeros, and a sum that starts at +0 is not changed
+// by adding +0, so skipping those slots leaves every sum bit for bit as it was.
+//   kind 0: every slot k < G of the grid (row slot_partial(k, G / 8, rot));
+//   kind 1: the same slots, those whose first row block (step_block) exists;
+//   kind 2: the colour shares of the SGS sweeps: share g < count sits in the
+//           row of workgroup (x = g / per, q = g % per) of the sweep grid (per
+//           workgroups per XCD).  Shares are summed in share order, which does
+//           not depend on the sweep grid, so a pencil's sums are the same alone
+//           and in a batch.
+struct SlotSet {
   int kind = 0;
-  int slab = 0, nrb = 0;
-  int gs = 0;
-  __device__ bool operator()(int k, int per, int rot) const {
+  int slab = 0, nrb = 0;  // kind 1
+  int count = 0, per = 1;  // kind 2
+  __device__ bool live(int k) const {
+    if (kind != 1) return true;
     const int j = k >> 3;
-    if (kind == 1) return j < slab && (k & 7) * slab + j < nrb;
-    if (kind == 2) {
-      const int q = j >= rot ? j - rot : j - rot + per;
-      return (k & 7) * per + q < gs;
-    }
-    return true;
+    return j < slab && (k & 7) * slab + j < nrb;
   }
 };
 
-__device__ __forceinline__ SlotLive rows_live(const Inst& I) {
-  SlotLive l;
+__device__ __forceinline__ SlotSet rows_live(const Inst& I) {
+  SlotSet l;
   l.kind = 1;
   l.slab = I.slab;
   l.nrb = I.nrb;
   return l;
 }
 
-// shares of G workgroups: colour c's share size is ceil(size_c / G), so
-// workgroups g < ceil(size_c / share) have nodes of colour c
-__device__ __forceinline__ SlotLive sweep_live(const Inst& I, int G) {
-  SlotLive l;
+__device__ __forceinline__ SlotSet sweep_shares(const Inst& I, const Batch& b) {
+  SlotSet l;
   l.kind = 2;
-  const cptr<int> cp = as_const(I.sgs_cptr);
-  for (int c = 0; c < I.sgs_ncol; ++c) {
-    const int sz = cp[c + 1] - cp[c];
-    if (sz <= 0) continue;
-    const int share = (sz + G - 1) / G;
-    l.gs = max(l.gs, (sz + share - 1) / share);
-  }
+  l.count = I.sgs_wgs;
+  l.per = b.Gs >> 3;
   return l;
 }
 
@@ -902,16 +894,21 @@ constexpr int kMaxScWaves = 16;
 // threads of the COCG scalar kernels (one block per column tile: the G partials
 // of each column are read by 16 wavefronts)
 constexpr int kScWG = kMaxScWaves * WAVE;
+__device__ __forceinline__ size_t slot_row(const SlotSet& s, int k, int per, int rot) {
+  return s.kind == 2 ? (size_t)(8 * (k % s.per) + k / s.per) : slot_partial(k, per, rot);
+}
+
 template <typename T>
 __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, int rot, int Ktot, int c,
-                                           bool valid, const SlotLive& live = SlotLive{}) {
+                                           bool valid, const SlotSet& set = SlotSet{}) {
   __shared__ T red[kMaxScWaves][WAVE];
   const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
+  const int cnt = set.kind == 2 ? set.count : G;
   T acc = 0;
   if (valid) {
 #pragma unroll 8
-    for (int k = w; k < G; k += nw)
-      if (live(k, per, rot)) acc += part[slot_partial(k, per, rot) * Ktot + c];
+    for (int k = w; k < cnt; k += nw)
+      if (set.live(k)) acc += part[slot_row(set, k, per, rot) * Ktot + c];
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -923,15 +920,16 @@ __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, in
 
 template <typename R>
 __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int rot, int Ktot, int c,
-                                                  bool valid, const SlotLive& live = SlotLive{}) {
+                                                  bool valid, const SlotSet& set = SlotSet{}) {
   __shared__ R rr[kMaxScWaves][WAVE], ri[kMaxScWaves][WAVE];
   const int w = wave_id(), lane = lane_id(), per = G >> 3, nw = blockDim.x / WAVE;
+  const int cnt = set.kind == 2 ? set.count : G;
   R ar = 0, ai = 0;
   if (valid) {
 #pragma unroll 8
-    for (int k = w; k < G; k += nw) {
-      if (!live(k, per, rot)) continue;
-      const cx<R> v = part[slot_partial(k, per, rot) * Ktot + c];
+    for (int k = w; k < cnt; k += nw) {
+      if (!set.live(k)) continue;
+      const cx<R> v = part[slot_row(set, k, per, rot) * Ktot + c];
       ar += v.re;
       ai += v.im;
     }
@@ -1175,9 +1173,9 @@ __global__ __launch_bounds__(WG) void k_bjac_apply(Batch b, const int* __restric
   }
 }
 
-int* LaunchTimer::begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share) {
+int* LaunchTimer::begin(hipStream_t s, int kind, double tile_bytes, double fixed, double share, int grid) {
   if (used >= capacity || used >= 512) return nullptr;
-  recs[used] = {kind, tile_bytes, fixed, share};
+  recs[used] = {kind, tile_bytes, fixed, share, grid};
   (void)hipEventRecord(events[2 * used], s);
   return d_counts + used;
 }
@@ -1576,7 +1574,7 @@ __global__ __launch_bounds__(kScWG) void k_cocg_init_scalars(Batch b, KrylovStat
     if (blockIdx.x == 0) b.n_active[0] = b.n_tiles;
   }
   // with SGS both sums come from the first forward sweep
-  const SlotLive live = I.sgs ? sweep_live(I, b.G) : SlotLive{};
+  const SlotSet live = I.sgs ? sweep_shares(I, b) : SlotSet{};
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
@@ -1630,7 +1628,7 @@ __global__ __launch_bounds__(kScWG) void k_cocg_alpha(Batch b, KrylovState<R> st
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
   // [p, q] from the forward sweeps (SGS) or from the row blocks of the product
-  const SlotLive live = I.sgs ? sweep_live(I, b.G) : rows_live(I);
+  const SlotSet live = I.sgs ? sweep_shares(I, b) : rows_live(I);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
@@ -1756,7 +1754,7 @@ __global__ __launch_bounds__(kScWG) void k_cocg_beta(Batch b, KrylovState<R> st,
   SC_PROLOGUE(V)
   if (!tile_has<V>(st.flags, cg0, cl0, I.K, COL_ACTIVE, COL_ACTIVE)) return;
   // sums of the x, r update: row blocks, or grid-strided nodes (node block Jacobi)
-  const SlotLive live = I.bjac && !I.sgs ? SlotLive{} : rows_live(I);
+  const SlotSet live = I.bjac && !I.sgs ? SlotSet{} : rows_live(I);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int c = cg0 + v;
@@ -1970,18 +1968,18 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
   constexpr int V = LaneWidth<R>::V;
   constexpr bool all_tiles = MODE == kSgsBackFinal || MODE == kSgsFwdStart;
   constexpr bool fwd = MODE == kSgsFwdIter || MODE == kSgsFwdStart;
-  const WgPos p = wg_pos(b.G);
+  const WgPos p = wg_pos(b.Gs);
   FOR_TILE_LIST(b, p, V, all_tiles ? b.n_tiles : as_const((const int*)b.n_active)[0],
                 all_tiles ? ti_ : as_const((const int*)b.active)[ti_])
     if (I.sgs != BS) continue;  // the other block size's launch owns this pencil's tiles
-    // a contiguous share of the colour's nodes per workgroup, XCD by XCD
+    // share g = x * per + q of the colour's nodes: sgs_share consecutive nodes
+    // (a multiple of 4: each wavefront takes the same number), XCD by XCD
     int q0 = 0, q1 = 0;
     if (colour < I.sgs_ncol) {
       const cptr<int> cptr_ = as_const(I.sgs_cptr);
       const int c0 = cptr_[colour], c1 = cptr_[colour + 1];
-      const int per = (c1 - c0 + b.G - 1) / b.G;
-      q0 = c0 + (p.x * p.per + p.q) * per;
-      q1 = min(c1, q0 + per);
+      q0 = c0 + (p.x * p.per + p.q) * I.sgs_share;
+      q1 = min(c1, q0 + I.sgs_share);
     }
     if (q0 >= q1) {  // no nodes here: zero partials, written by the first colour launch
       if (counter && colour < I.sgs_ncol &&
@@ -2112,13 +2110,13 @@ __global__ __launch_bounds__(WG, 4) void k_sgs_sweep(Batch b, KrylovState<R> st,
 template <typename R, int BS, int MODE>
 void sgs_sweeps(hipStream_t s, const Batch& b, const KrylovState<R>& st, int first, LaunchTimer* tm,
                 double tile_bytes, double fixed) {
-  const dim3 grid((unsigned)b.G), blk(WG);
+  const dim3 grid((unsigned)b.Gs), blk(WG);
   constexpr bool fwd = MODE == kSgsFwdIter || MODE == kSgsFwdStart;
   const int nc = b.sgs_ncol;
   for (int q = 0; q < nc; ++q) {
     const int c = fwd ? q : nc - 1 - q;
     // a colour launch of one direction does 1 / (2 nc) of a product with S
-    int* cnt = tm ? tm->begin(s, 0, tile_bytes / nc, fixed / nc, 0.5 / nc) : nullptr;
+    int* cnt = tm ? tm->begin(s, 0, tile_bytes / nc, fixed / nc, 0.5 / nc, b.Gs) : nullptr;
     k_sgs_sweep<R, BS, MODE><<<grid, blk, 0, s>>>(b, st, c, q > 0 ? 1 : 0, first, cnt);
     if (cnt) tm->end(s);
   }

@@ -159,6 +159,7 @@ struct Pencil {
   bool use_bjac = false;  // node 3x3 block Jacobi
   // multicolour SGS: block size, colours, nodes by colour, lower / upper coupling CSRs
   int sgs = 0, sgs_ncol = 0;
+  int sgs_share = 4, sgs_wgs = 0;  // colour sweeps: nodes per workgroup, workgroups used
   int *sgs_cptr = nullptr, *sgs_nodes = nullptr;
   int *lrp = nullptr, *lcol = nullptr, *urp = nullptr, *ucol = nullptr;
   ab_pair<double>*lab64 = nullptr, *uab64 = nullptr;
@@ -408,6 +409,16 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
     cnodes.resize(nodes);
     std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
     for (int64_t k = 0; k < nodes; ++k) cnodes[fill[colour[k]]++] = (int32_t)k;
+    // Each sweep workgroup takes a share of a colour's nodes: the smallest
+    // multiple of 4 (the same count for each wavefront) that keeps the largest
+    // colour within kMaxGrid workgroups.  Small shares and a grid beyond the
+    // resident workgroups balance the wavefronts better than the row grid's
+    // fractional shares (elasticity 48^3: 8 nodes per workgroup, 1728
+    // workgroups, sweeps 9% faster than 13.5 per workgroup over 1024).
+    int64_t maxc = 1;
+    for (int c = 0; c < ncol; ++c) maxc = std::max<int64_t>(maxc, cptr[c + 1] - cptr[c]);
+    P.sgs_share = 4 * (int)((maxc + 4 * (int64_t)kMaxGrid - 1) / (4 * (int64_t)kMaxGrid));
+    P.sgs_wgs = (int)((maxc + P.sgs_share - 1) / P.sgs_share);
     lrp.assign(n + 1, 0);
     urp.assign(n + 1, 0);
     for (int64_t i = 0; i < n; ++i) {
@@ -669,7 +680,7 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
 
 // Reads back the event pairs and tile counters of the current window into the
 // kernel statistics, then clears the window.
-slrf_status harvest_timer(Env& env, int64_t total_tiles, int64_t total_cols, slrf_filter_stats* fs) {
+slrf_status harvest_timer(Env& env, int G, int64_t n_tiles, int64_t total_cols, slrf_filter_stats* fs) {
   LaunchTimer& tm = env.timer;
   if (tm.used == 0) return SLRF_OK;
   std::vector<int> cnt(tm.used);
@@ -679,7 +690,9 @@ slrf_status harvest_timer(Env& env, int64_t total_tiles, int64_t total_cols, slr
     float ms = 0;
     HIPCHK(env, hipEventElapsedTime(&ms, tm.events[2 * u], tm.events[2 * u + 1]));
     const LaunchTimer::Rec& r = tm.recs[u];
-    const double bytes = r.tile_bytes * (double)cnt[u] / (double)total_tiles + (cnt[u] > 0 ? r.fixed : 0.0);
+    // the counter adds one per (workgroup, tile) processed
+    const double total_tiles = (double)(r.grid > 0 ? r.grid : G) * (double)n_tiles;
+    const double bytes = r.tile_bytes * (double)cnt[u] / total_tiles + (cnt[u] > 0 ? r.fixed : 0.0);
     if (r.kind == 0) {
       fs->spmm_seconds += 1e-3 * ms;
       fs->spmm_launches += 1;
@@ -1118,6 +1131,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
   int64_t dn = 0, ilu_off = 0, bjac_off = 0, sgs_off = 0, sgsd_off = 0;  // sgsd: node blocks' D only
   b.sgs = 0;
   b.sgs_ncol = 0;
+  b.Gs = 8;
   int col0 = 0, tile0 = 0;
   for (size_t q = 0; q < jobs.size(); ++q) {
     const FilterJob& j = jobs[q];
@@ -1145,6 +1159,8 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.bjac = nullptr;
     I.sgs = j.P->sgs;
     I.sgs_ncol = j.P->sgs_ncol;
+    I.sgs_share = j.P->sgs_share;
+    I.sgs_wgs = j.P->sgs_wgs;
     I.sgs_cptr = j.P->sgs_cptr;
     I.sgs_nodes = j.P->sgs_nodes;
     I.lrp = j.P->lrp;
@@ -1203,6 +1219,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     if (j.P->sgs) {
       b.sgs |= j.P->sgs == 3 ? 2 : 1;
       b.sgs_ncol = std::max(b.sgs_ncol, j.P->sgs_ncol);
+      b.Gs = std::max(b.Gs, (j.P->sgs_wgs + 7) / 8 * 8);
     }
     dn += (int64_t)I.n * I.N;
     col0 += I.Kp;
@@ -1378,7 +1395,7 @@ slrf_status run_krylov(Env& env, const Batch& b, const KrylovState<R>& st, R tol
       return fail(env, SLRF_E_DEVICE, std::string("Krylov iteration: ") + hipGetErrorString(e));
     }
     if (tm) {
-      out = harvest_timer(env, (int64_t)b.G * b.n_tiles, (int64_t)b.Ktot, ks);
+      out = harvest_timer(env, b.G, (int64_t)b.n_tiles, (int64_t)b.Ktot, ks);
       if (out != SLRF_OK) break;
     }
     if (active == 0) break;
