@@ -157,12 +157,19 @@ class MulticolourSGS:
     so M^{-1} r is a forward sweep over the colours, (D + L) y = r, i.e.
     y_k = D_k^{-1} (r_k - sum_{colour(m) < colour(k)} S_km y_m), then a backward
     sweep, (D + U) z = D y, i.e. z_k = y_k - D_k^{-1} sum_{colour(m) > colour(k)} S_km z_m.
-    With S complex symmetric, U = L^T and M is complex symmetric too."""
+    With S complex symmetric, U = L^T and M is complex symmetric too.
 
-    def __init__(self, A, B, sigma: complex, block: int = 1, colour=None):
+    omega != 1 gives symmetric SOR: D is replaced by D / omega in all three
+    factors, M = (D/omega + L) (D/omega)^{-1} (D/omega + U) (the constant
+    factor of the textbook form, which no CG iterate depends on, is left out);
+    0 < omega < 2."""
+
+    def __init__(self, A, B, sigma: complex, block: int = 1, colour=None, omega: float = 1.0):
         n = A.shape[0]
         if block not in (1, 3) or n % block:
             raise ValueError("block must be 1, or 3 with n divisible by 3")
+        if not 0.0 < omega < 2.0:
+            raise ValueError("omega must lie in (0, 2)")
         self.n, self.block = n, block
         self.colour = greedy_colouring(A, B, block) if colour is None else np.asarray(colour)
         S = (A.astype(np.complex128) - sigma * B).tocoo()
@@ -179,7 +186,7 @@ class MulticolourSGS:
         blocks = np.zeros((nodes, block, block), np.complex128)
         Dc = self.D.tocoo()
         blocks[Dc.row // block, Dc.row % block, Dc.col % block] = Dc.data
-        self.blocks = blocks
+        self.blocks = blocks / omega
         self.order = [np.flatnonzero(self.colour == c) for c in range(int(self.colour.max()) + 1)]
 
     def _rows(self, nodes):
@@ -300,7 +307,7 @@ def bicgstab(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = 
 
 
 def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None,
-         precond: str = "jacobi"):
+         precond: str = "jacobi", omega: float = 1.0):
     """Conjugate orthogonal conjugate gradients (COCG; van der Vorst and Melissen,
     IEEE Trans. Magn. 26 (1990)) for every pole and column, an alternative to
     BiCGStab for the shifted systems of Section 3.
@@ -310,8 +317,8 @@ def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None
     in place of the inner product applies; it needs one product with S_j per
     iteration.  The preconditioner must be complex symmetric as well: point
     Jacobi, node block Jacobi, or multicolour symmetric Gauss-Seidel with point
-    ("mcsgs") or node ("mcsgs3") blocks (ILU(0) is not symmetric and is not
-    offered).
+    ("mcsgs") or node ("mcsgs3") blocks, relaxed by omega (symmetric SOR; 1:
+    plain SGS) (ILU(0) is not symmetric and is not offered).
     Same interface and conventions as ``bicgstab``: x_0 = 0, columns pole-major,
     convergence on the recursively updated residual ||r||_2 <= tol ||f||_2.
 
@@ -340,7 +347,7 @@ def cocg(A, B, sigmas, F, tol: float, maxit: int, fixed_iters: int | None = None
     elif precond in ("mcsgs", "mcsgs3"):
         block = 3 if precond == "mcsgs3" else 1
         colour = greedy_colouring(A, B, block)      # depends on the pattern only
-        sgs = [MulticolourSGS(A, B, s, block, colour=colour) for s in sigmas]
+        sgs = [MulticolourSGS(A, B, s, block, colour=colour, omega=omega) for s in sigmas]
 
         def Minv(Y):
             return np.concatenate([sgs[j].apply(Y[:, j * L:(j + 1) * L]) for j in range(N)], axis=1)

@@ -691,12 +691,14 @@ def test_greedy_colouring_is_the_parity_colouring():
     assert np.array_equal(c3, (k % nx) % 2 + 2 * ((k // nx) % 4 % 2) + 4 * ((k // (nx * 4)) % 2))
 
 
+@pytest.mark.parametrize("omega", [1.0, 0.7, 1.3])
 @pytest.mark.parametrize("block", [1, 3])
-def test_multicolour_sgs_defining_product(block):
+def test_multicolour_sgs_defining_product(block, omega):
     """M^{-1} r from the colour sweeps against the definition M = (D + L) D^{-1}
     (D + U), formed densely here from S = A - sigma B and the parity colours (D:
-    couplings within a node, L / U: to lower / higher colours).  M is complex
-    symmetric; the sweeps' result solves M z = r."""
+    couplings within a node, L / U: to lower / higher colours), with D / omega in
+    place of D for symmetric SOR (the textbook SSOR matrix times 2 - omega).  M
+    is complex symmetric; the sweeps' result solves M z = r."""
     if block == 1:
         q = pencils.scalar_q1(6, 3, 0.5, 3)
         col = _parity_colours_scalar(6, 3)
@@ -711,10 +713,14 @@ def test_multicolour_sgs_defining_product(block):
     same = node[:, None] == node[None, :]
     D, L, U = np.where(same, S, 0), np.where(cr > cc, S, 0), np.where(cr < cc, S, 0)
     assert np.abs(S - D - L - U).max() == 0.0     # coupled nodes never share a colour
-    M = (D + L) @ np.linalg.solve(D, D + U)
+    Dw = D / omega
+    M = (Dw + L) @ np.linalg.solve(Dw, Dw + U)
     assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    # the textbook SSOR matrix (D + w L) D^{-1} (D + w U) / (w (2 - w)) is M / (2 - w)
+    Mt = (D + omega * L) @ np.linalg.solve(D, D + omega * U) / (omega * (2 - omega))
+    assert np.abs(Mt * (2 - omega) - M).max() < 1e-12 * np.abs(M).max()
     R = np.random.default_rng(2).standard_normal((q.n, 3)) + 1j * np.random.default_rng(3).standard_normal((q.n, 3))
-    sgs = krylov.MulticolourSGS(q.A, q.B, sig, block)
+    sgs = krylov.MulticolourSGS(q.A, q.B, sig, block, omega=omega)
     assert np.array_equal(sgs.colour, col)
     Z = sgs.apply(R)
     assert np.abs(Z - np.linalg.solve(M, R)).max() < 1e-11 * np.abs(Z).max()
@@ -738,11 +744,13 @@ def test_multicolour_sgs_on_uncoupled_nodes_is_block_jacobi():
     assert np.abs(sgs.apply(R) - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-def test_cocg_sgs_real_shift_is_preconditioned_cg():
-    """With a real negative shift S is SPD and M = (D+L) D^{-1} (D+U) is SPD: COCG
-    with the multicolour SGS preconditioner is preconditioned CG, and its
-    iterates equal SciPy's CG with the same preconditioner (given here as the
-    dense inverse of M built from the definition)."""
+@pytest.mark.parametrize("omega", [1.0, 0.7])
+def test_cocg_sgs_real_shift_is_preconditioned_cg(omega):
+    """With a real negative shift S is SPD and M = (D+L) D^{-1} (D+U) is SPD (so is
+    its SOR form with D / omega, 0 < omega < 2): COCG with the multicolour SGS
+    preconditioner is preconditioned CG, and its iterates equal SciPy's CG with
+    the same preconditioner (given here as the dense inverse of M built from the
+    definition)."""
     import scipy.sparse.linalg as sla
     q = pencils.scalar_q1(6, 3, 0.5, 7)
     F = q.B @ pencils.start_block(q.n, 1, 3)
@@ -750,7 +758,7 @@ def test_cocg_sgs_real_shift_is_preconditioned_cg():
     S = (q.A + g * q.B).toarray()
     col = _parity_colours_scalar(6, 3)
     cr, cc = col[:, None], col[None, :]
-    D = np.diag(np.diag(S))
+    D = np.diag(np.diag(S)) / omega
     M = (D + np.where(cr > cc, S, 0)) @ np.linalg.solve(D, D + np.where(cr < cc, S, 0))
     Minv = np.linalg.inv(M)
     P = sla.LinearOperator(S.shape, matvec=lambda v: Minv @ v)
@@ -758,7 +766,7 @@ def test_cocg_sgs_real_shift_is_preconditioned_cg():
         xs = []
         sla.cg(S, F[:, 0], x0=np.zeros(q.n), rtol=1e-30, atol=0.0, maxiter=k, M=P,
                callback=lambda xk: xs.append(xk.copy()))
-        x, it, fl, _ = krylov.cocg(q.A, q.B, [-g + 0j], F, 0.0, k, fixed_iters=k, precond="mcsgs")
+        x, it, fl, _ = krylov.cocg(q.A, q.B, [-g + 0j], F, 0.0, k, fixed_iters=k, precond="mcsgs", omega=omega)
         assert len(xs) == k
         assert np.abs(x[:, 0] - xs[-1]).max() < 1e-11 * np.abs(xs[-1]).max()
 
