@@ -135,7 +135,9 @@ def _sample_worker(task):
             F = p.B @ pencils.start_block(p.n, _SAMPLE["cols"], 77 + k)
             solve = krylov.cocg if wl.get("solver", 0) == 1 else krylov.bicgstab
             its = _SAMPLE["iters"] if kind == "inner" else 0
-            solve(p.A, p.B, sig[k % len(sig):k % len(sig) + 1], F, 0.0, its, fixed_iters=its, precond=pc)
+            # node-block SGS at the library's default relaxation (sgs_omega 0: 0.7 for node blocks)
+            kw = {"omega": 0.7} if pc == "mcsgs3" else {}
+            solve(p.A, p.B, sig[k % len(sig):k % len(sig) + 1], F, 0.0, its, fixed_iters=its, precond=pc, **kw)
         elif kind == "mgs":
             subspace.mgs_b(pencils.start_block(p.n, _SAMPLE["mgs_cols"], 99 + k), p.B)
         else:

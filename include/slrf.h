@@ -123,6 +123,12 @@ typedef struct {
                           keeps Y_prev and B X_prev (n x N L complex and n x L real
                           FP64) with its own buffers, which the workspace sizes
                           include.  Default 0 (cold starts, x_0 = 0) */
+  double sgs_omega;    /* relaxation factor of the multicolour SGS (precond 4 and 5):
+                          symmetric SOR, D replaced by D / omega in
+                          M = (D + L) D^{-1} (D + U); a value in (0, 2) applies to
+                          every pencil (1: plain SGS).  0 (default): by block size,
+                          0.7 for 3x3 node blocks (fewer iterations than 1 on the
+                          elasticity pencils measured) and 1 for point blocks */
 } slrf_options;
 
 typedef struct {
@@ -164,7 +170,8 @@ typedef struct {
 
 /* Defaults: FP64, inner_tol 1e-13, inner_maxit 1000, outer_tol 1e-8,
  * outer_maxit 40, check_every 10, seed 1, precond 0 (auto), profile 0, graph 0,
- * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0, solver 0 (BiCGStab), recycle 0. */
+ * tile_rows / tile_wgs / band_rows 0 (defaults), tune 0, solver 0 (BiCGStab), recycle 0,
+ * sgs_omega 0 (by block size). */
 void slrf_default_options(slrf_options* opt);
 
 /* SLRF pole/weight design, Section 3.1: minimise the delta-weighted L2 distance

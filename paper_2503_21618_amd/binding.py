@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("outer_tol", C.c_double), ("outer_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("seed", C.c_uint64), ("precond", C.c_int32), ("profile", C.c_int32),
                 ("graph", C.c_int32), ("tile_rows", C.c_int32), ("tile_wgs", C.c_int32),
-                ("band_rows", C.c_int32), ("tune", C.c_int32), ("solver", C.c_int32), ("recycle", C.c_int32)]
+                ("band_rows", C.c_int32), ("tune", C.c_int32), ("solver", C.c_int32), ("recycle", C.c_int32),
+                ("sgs_omega", C.c_double)]
 
 
 class Poles(C.Structure):

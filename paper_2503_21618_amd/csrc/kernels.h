@@ -219,7 +219,7 @@ void launch_accumulate(hipStream_t s, const Batch& b, const cx<float>* x, const 
 // ---- per-pencil launchers -------------------------------------------------
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
-                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv);
+                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv, double cd = 1.0, double ci = 1.0);
 // U = sum_j 2 Re(w_j x[:, j L .. j L + L)), x a tile-major block (tiles of W
 // columns, each an n x W row-major panel)
 template <typename R>

@@ -9,23 +9,25 @@
 namespace slrf {
 
 
-// d = diag(A) - sigma_j diag(B), dinv = 1 / d
+// v = diag(A) - sigma_j diag(B); d = cd v, dinv = ci / v (cd = ci = 1: the
+// Jacobi diagonal and its inverse)
 template <typename R>
 __global__ void k_jacobi(int n, int N, const R* dA, const R* dB, const cx<R>* sigma, cx<R>* d,
-                         cx<R>* dinv) {
+                         cx<R>* dinv, R cd, R ci) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * N) return;
   const int i = (int)(e / N), j = (int)(e % N);
   const cx<R> s = sigma[j];
   const cx<R> v = {dA[i] - s.re * dB[i], -s.im * dB[i]};
-  d[e] = v;
-  dinv[e] = cdiv(cx<R>{1, 0}, v);
+  d[e] = {cd * v.re, cd * v.im};
+  dinv[e] = cdiv(cx<R>{ci, 0}, v);
 }
 template <typename R>
 void launch_jacobi_diag(hipStream_t s, int n, int N, const R* diagA, const R* diagB,
-                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv) {
+                        const cx<R>* sigma, cx<R>* d, cx<R>* dinv, double cd, double ci) {
   const int64_t tot = (int64_t)n * N;
-  k_jacobi<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, N, diagA, diagB, sigma, d, dinv);
+  k_jacobi<R><<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(n, N, diagA, diagB, sigma, d, dinv,
+                                                                        (R)cd, (R)ci);
 }
 
 // U[i, l] (+)= sum_j 2 Re(w_j x[i, col_of(j, l)])
@@ -422,7 +424,7 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
 // explicit instantiations
 #define SLRF_INST(R)                                                                                          \
   template void launch_jacobi_diag<R>(hipStream_t, int, int, const R*, const R*, const cx<R>*, cx<R>*,     \
-                                      cx<R>*);                                                              \
+                                      cx<R>*, double, double);                                              \
   template void launch_filter_sum<R>(hipStream_t, int, int, int, int, int, const cx<R>*, const double*,   \
                                      double*, bool);                                                        \
   template void launch_spmm_real<R>(hipStream_t, int, int, const int*, const int*, const ab_pair<R>*,      \

@@ -63,22 +63,25 @@ def elastic():
 CASES = [("point", scalar, 4, "mcsgs", 300.0), ("node", elastic, 5, "mcsgs3", 60.0)]
 
 
+@pytest.mark.parametrize("omega", [1.0, 0.7])
 @pytest.mark.parametrize("iters", [1, 3, 8])
 @pytest.mark.parametrize("kind,make,pc,opc,gamma", CASES)
-def test_sgs_iterates_match_oracle(slrf, torch, kind, make, pc, opc, gamma, iters):
+def test_sgs_iterates_match_oracle(slrf, torch, kind, make, pc, opc, gamma, iters, omega):
+    """FP64 iterates after a fixed number of iterations against the oracle's COCG
+    with the same multicolour SGS (omega = 1) or its symmetric SOR form."""
     q = make()
     L = 40                                           # K = 80: a ragged tile
     sig, w = golden_poles(4, gamma)
     sig, w = sig[:2], w[:2]
     X = pencils.start_block(q.n, L, 5)
-    say(f"case SGS-COCG iterates {kind} iters={iters} n={q.n} L={L} N=2")
+    say(f"case SGS-COCG iterates {kind} iters={iters} omega={omega} n={q.n} L={L} N=2")
     opt = slrf.default_options(inner_tol=0.0, inner_maxit=iters, check_every=1, solver=slrf.SOLVER_COCG,
-                               precond=pc)
+                               precond=pc, sgs_omega=omega)
     s = slrf.Solver(q.A, q.B, max_L=L, max_poles=2, options=opt)
     U, st = s.filter_apply(torch.from_numpy(X).cuda(), sig, w)
     U = U.cpu().numpy()
     s.close()
-    x, it, fl, _ = krylov.cocg(q.A, q.B, sig, q.B @ X, 0.0, iters, fixed_iters=iters, precond=opc)
+    x, it, fl, _ = krylov.cocg(q.A, q.B, sig, q.B @ X, 0.0, iters, fixed_iters=iters, precond=opc, omega=omega)
     Uo = sum(2.0 * np.real(w[j] * x[:, j * L:(j + 1) * L]) for j in range(2))
     err = np.abs(U - Uo).max() / np.abs(Uo).max()
     say(f"  rel err {err:.3e}, its max {st['max_iterations']}, spmv {st['spmv']}")
@@ -112,17 +115,18 @@ def test_sgs_filter_matches_exact_solve(slrf, torch, kind, make, pc, opc, gamma,
     assert its["sgs"] < 0.8 * its["jacobi"]
 
 
-@pytest.mark.parametrize("prec,recycle", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("prec,recycle,omega", [(0, 0, 1.0), (1, 0, 1.0), (1, 1, 1.0), (0, 0, 0.7), (1, 1, 0.7)])
 @pytest.mark.parametrize("kind,make,pc,opc,gamma", CASES)
-def test_sgs_solve_vs_dense(slrf, torch, kind, make, pc, opc, gamma, prec, recycle):
+def test_sgs_solve_vs_dense(slrf, torch, kind, make, pc, opc, gamma, prec, recycle, omega):
     q = make()
     ev, _ = dense.all_eigenpairs(q.A, q.B)
     k = 24
     g = 0.5 * (ev[k - 1] + ev[k])
     L = 40
     sig, w = golden_poles(6, g)
-    say(f"case SGS-COCG interval solve {kind} prec={prec} recycle={recycle} n={q.n} NEV={k}")
-    opt = slrf.default_options(precision=prec, solver=slrf.SOLVER_COCG, precond=pc, recycle=recycle)
+    say(f"case SGS-COCG interval solve {kind} prec={prec} recycle={recycle} omega={omega} n={q.n} NEV={k}")
+    opt = slrf.default_options(precision=prec, solver=slrf.SOLVER_COCG, precond=pc, recycle=recycle,
+                               sgs_omega=omega)
     s = slrf.Solver(q.A, q.B, max_L=L, max_poles=6, options=opt)
     r = s.solve_interval(g, L, sig, w, V0=torch.from_numpy(pencils.start_block(q.n, L, 7)).cuda())
     s.close()

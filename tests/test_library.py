@@ -234,8 +234,16 @@ def test_sgs_options_validated_on_the_host(lib):
         lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_BICGSTAB, precond=4))
     with pytest.raises(lib.SlrfError):
         lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=6))
+    for bad in (-0.5, 2.0, 2.5, float("nan")):       # the SOR relaxation factor lies in (0, 2)
+        with pytest.raises(lib.SlrfError):
+            lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=4,
+                                                                           sgs_omega=bad))
+    assert lib.default_options().sgs_omega == 0.0                # by block size
+    w07 = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=4,
+                                                                         sgs_omega=0.7))
     jac = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=1))
     sgs = lib.workspace_bytes(n, nnz, L, N, options=lib.default_options(solver=lib.SOLVER_COCG, precond=4))
     # two coupling CSRs ((a, b) in FP64 and FP32, column index) within the merged pattern's
     # size, their row pointers, the colour tables, and R = sqrt(d) per (row, pole)
     assert 0 < sgs - jac < 2 * (nnz + 16) * 28 + 4 * (n + 1) * 4 + 1025 * 4 + n * N * 16 + 2 ** 16
+    assert w07 == sgs                                # the relaxation changes values, not sizes
