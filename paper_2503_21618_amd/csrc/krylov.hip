@@ -906,9 +906,14 @@ __device__ __forceinline__ T block_col_sum(const T* __restrict__ part, int G, in
   const int cnt = set.kind == 2 ? set.count : G;
   T acc = 0;
   if (valid) {
+    // a skipped slot adds +0 (its load is redirected to row 0, a cached line):
+    // the loads stay unconditional, so the unrolled ones are all in flight
 #pragma unroll 8
-    for (int k = w; k < cnt; k += nw)
-      if (set.live(k)) acc += part[slot_row(set, k, per, rot) * Ktot + c];
+    for (int k = w; k < cnt; k += nw) {
+      const bool on = set.live(k);
+      const T v = part[(on ? slot_row(set, k, per, rot) : 0) * Ktot + c];
+      acc += on ? v : T(0);
+    }
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -928,10 +933,10 @@ __device__ __forceinline__ cx<R> block_col_sum_cx(const cx<R>* part, int G, int 
   if (valid) {
 #pragma unroll 8
     for (int k = w; k < cnt; k += nw) {
-      if (!set.live(k)) continue;
-      const cx<R> v = part[slot_row(set, k, per, rot) * Ktot + c];
-      ar += v.re;
-      ai += v.im;
+      const bool on = set.live(k);
+      const cx<R> v = part[(on ? slot_row(set, k, per, rot) : 0) * Ktot + c];
+      ar += on ? v.re : R(0);
+      ai += on ? v.im : R(0);
     }
   }
   rr[w][lane] = ar;
