@@ -160,7 +160,7 @@ struct Pencil {
   bool use_bjac = false;  // node 3x3 block Jacobi
   // multicolour SGS: block size, colours, nodes by colour, lower / upper coupling CSRs
   int sgs = 0, sgs_ncol = 0;
-  int sgs_share = 4, sgs_wgs = 0;  // colour sweeps: nodes per workgroup, workgroups used
+  int64_t sgs_maxc = 0;  // nodes of the largest colour
   int *sgs_cptr = nullptr, *sgs_nodes = nullptr;
   int *lrp = nullptr, *lcol = nullptr, *urp = nullptr, *ucol = nullptr;
   ab_pair<double>*lab64 = nullptr, *uab64 = nullptr;
@@ -410,16 +410,8 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
     cnodes.resize(nodes);
     std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
     for (int64_t k = 0; k < nodes; ++k) cnodes[fill[colour[k]]++] = (int32_t)k;
-    // Each sweep workgroup takes a share of a colour's nodes: the smallest
-    // multiple of 4 (the same count for each wavefront) that keeps the largest
-    // colour within kMaxGrid workgroups.  Small shares and a grid beyond the
-    // resident workgroups balance the wavefronts better than the row grid's
-    // fractional shares (elasticity 48^3: 8 nodes per workgroup, 1728
-    // workgroups, sweeps 9% faster than 13.5 per workgroup over 1024).
-    int64_t maxc = 1;
-    for (int c = 0; c < ncol; ++c) maxc = std::max<int64_t>(maxc, cptr[c + 1] - cptr[c]);
-    P.sgs_share = 4 * (int)((maxc + 4 * (int64_t)kMaxGrid - 1) / (4 * (int64_t)kMaxGrid));
-    P.sgs_wgs = (int)((maxc + P.sgs_share - 1) / P.sgs_share);
+    P.sgs_maxc = 1;
+    for (int c = 0; c < ncol; ++c) P.sgs_maxc = std::max<int64_t>(P.sgs_maxc, cptr[c + 1] - cptr[c]);
     lrp.assign(n + 1, 0);
     urp.assign(n + 1, 0);
     for (int64_t i = 0; i < n; ++i) {
@@ -1141,6 +1133,25 @@ slrf_status prec_tables(Env& env, const Pencil& P, int N, const double* sigma) {
   return SLRF_OK;
 }
 
+// Each colour-sweep workgroup takes a share of a colour's nodes: the smallest
+// multiple of 4 (the same count for each wavefront) that keeps the largest
+// colour within a cap of workgroups.  A job with at least 8 column tiles (long
+// launches, bound by bandwidth) takes the largest grid, 2048: more, smaller
+// shares balance better than one resident generation (48^3 elasticity, 16
+// tiles: 8 nodes per workgroup over 1728 workgroups, a full-width launch
+// 1.63 ms against 1.77 ms for 13.5 over 1024).  Fewer tiles (short launches,
+// bound by latency) stay within the 1024 resident workgroups (scalar pencils
+// of n ~ 1e5 with 3 to 5 tiles: 4% faster than with the larger grid).  The
+// share depends on the job alone, not on the batch.
+void sgs_shares(const Pencil& P, int tiles, int& share, int& wgs) {
+  share = 4;
+  wgs = 0;
+  if (!P.sgs || P.sgs_maxc < 1) return;  // no colour sweeps for this pencil
+  const int64_t cap = tiles >= 8 ? kMaxGrid : 8 * kWgPerXcd;
+  share = 4 * (int)((P.sgs_maxc + 4 * cap - 1) / (4 * cap));
+  wgs = (int)((P.sgs_maxc + share - 1) / share);
+}
+
 template <typename R>
 slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLayout& lo, Batch& b,
                           std::vector<Inst>& insts, std::vector<std::vector<char>>& keep) {
@@ -1195,8 +1206,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     I.bjac = nullptr;
     I.sgs = j.P->sgs;
     I.sgs_ncol = j.P->sgs_ncol;
-    I.sgs_share = j.P->sgs_share;
-    I.sgs_wgs = j.P->sgs_wgs;
+    sgs_shares(*j.P, I.Kp / (64 * b.V), I.sgs_share, I.sgs_wgs);
     I.sgs_cptr = j.P->sgs_cptr;
     I.sgs_nodes = j.P->sgs_nodes;
     I.lrp = j.P->lrp;
@@ -1255,7 +1265,7 @@ slrf_status upload_tables(Env& env, std::vector<FilterJob>& jobs, const FilterLa
     if (j.P->sgs) {
       b.sgs |= j.P->sgs == 3 ? 2 : 1;
       b.sgs_ncol = std::max(b.sgs_ncol, j.P->sgs_ncol);
-      b.Gs = std::max(b.Gs, (j.P->sgs_wgs + 7) / 8 * 8);
+      b.Gs = std::max(b.Gs, (I.sgs_wgs + 7) / 8 * 8);
     }
     dn += (int64_t)I.n * I.N;
     col0 += I.Kp;
