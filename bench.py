@@ -51,7 +51,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "eigenpairs/s at rel. residual 1e-8, mixed vs FP64; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA without packed (two-wide) instructions, which this build does not emit:
+# FP32 FMA without packed (two-wide) instructions, which the HIP sources are compiled not to emit:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz; FP64 FMA runs at the same rate
 FP32_NONPACKED_TFS = 78.6
 FP64_TFS = 78.6

@@ -1,0 +1,59 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard and the counter
+summary that turns rocprofv3 FETCH_SIZE / WRITE_SIZE values into bytes per
+launch through the copy-kernel calibration."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def run_bench(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, timeout=120, cwd=ROOT)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = run_bench("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def write_csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (kernel, value) in enumerate(rows):
+            f.write(f'{i},"{kernel}",{counter},{value}\n')
+
+
+def test_counter_summary_calibration(tmp_path):
+    """A copy of 1 GiB that FETCH_SIZE reads as half its bytes and WRITE_SIZE as
+    all of them gives factors 0.5 and 1.0; a sweep launch's counters are divided
+    by them, averaged over its dispatches, and compared with the probe's
+    algorithmic bytes."""
+    copy = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda>(int)"
+    back = "void slrf::k_sgs_sweep<float, 3, 0>(slrf::Batch, slrf::KrylovState<float>, int, int, int, int*)"
+    fwd = "void slrf::k_sgs_sweep<float, 3, 2>(slrf::Batch, slrf::KrylovState<float>, int, int, int, int*)"
+    final = "void slrf::k_sgs_sweep<float, 3, 1>(slrf::Batch, slrf::KrylovState<float>, int, int, int, int*)"
+    kib = (1 << 30) / 1024
+    fetch = tmp_path / "fetch.csv"
+    write = tmp_path / "write.csv"
+    # the final sweep (mode 1) is not an iteration sweep and must be left out
+    write_csv(fetch, "FETCH_SIZE", [(copy, 0.5 * kib), (back, 4e6), (fwd, 6e6), (final, 9e9)])
+    write_csv(write, "WRITE_SIZE", [(copy, kib), (back, 1e6), (fwd, 1e6), (final, 9e9)])
+    probe = tmp_path / "probe.log"
+    probe.write_text('# probe\n{"family": "sgs", "dtype": "float", "full_launch_algorithmic_bytes": 3.43e9}\n')
+    r = run_bench("--summarize-pmc", str(fetch), str(write), str(probe), "--workload", "c3")
+    assert r.returncode == 0, r.stderr
+    out = {}
+    for line in r.stdout.splitlines():
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.rsplit(":", 1)
+        out[k.strip()] = v.strip()
+    assert float(out["copy_fetch_factor"]) == 0.5
+    assert float(out["copy_write_factor"]) == 1.0
+    assert out["k_sgs_sweep<float> dispatches"] == "2"
+    expect = 5e6 * 1024 / 0.5 + 1e6 * 1024 / 1.0
+    assert abs(float(out["full_launch_traffic_bytes sgs float"]) / expect - 1) < 1e-6
+    assert abs(float(out["traffic_over_algorithmic sgs float"]) - expect / 3.43e9) < 1e-3
