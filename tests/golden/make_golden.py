@@ -6,6 +6,8 @@ and the shared input generator ``pencils``.
     python tests/golden/make_golden.py eig_c2    # eigenvalues of the 64^3 scalar pencil in (0, 421]
     python tests/golden/make_golden.py eig_c3    # eigenvalues of the 48^3-node elasticity pencil
     python tests/golden/make_golden.py count_c3  # inertia count of that pencil at its gamma
+    python tests/golden/make_golden.py eig_batch # eigenvalues of eight batched-recipe pencils
+    python tests/golden/make_golden.py eig_serve # eigenvalues of the serving test's six requests
 
 Pole tables: the oracle's SLRF design (ridge-regularised least squares, see
 oracle/poles.py) at gamma = 1, alpha = 1, beta = 0.01 (the paper's Section 4.2
@@ -140,6 +142,36 @@ def make_eig_c3():
     _log(f"c3: gamma {gamma}, {k} eigenvalues, gap {gap:.2e}, max rho {out['max_rho']:.2e}")
 
 
+BATCH_N_RANGE = (2e3, 1.5e4)
+SERVE_TEST_INSTANCES = [1, 6, 8, 34, 42, 51]
+
+
+def make_eig_batch(indices=range(8), n_range=BATCH_N_RANGE, name="eig_batch8_n2e3_1.5e4.json"):
+    """Eigenvalues in (0, gamma] of instances of the batched workload's recipe
+    (pencils.batch_instance; by default the first eight with sizes cut to
+    2e3..1.5e4 rows), by shift-invert subspace iteration, with their Sylvester
+    counts beside them."""
+    out = {"n_range": list(n_range), "instances": [],
+           "source": "oracle.shift_invert.subspace_iteration (shift 0, banded Cholesky); "
+                     "oracle.inertia.sparse_ldl_count"}
+    for i in indices:
+        p, gamma, L, nev = pencils.batch_instance(i, n_range=n_range)
+        t = time.time()
+        F = banded.band_cholesky(p.A)
+        V0 = pencils.start_block(p.n, max(2 * nev, L + 16), 100 + i)
+        r = shift_invert.subspace_iteration(p.A, p.B, gamma, V0, tol=1e-11, factor=F)
+        cnt = inertia.sparse_ldl_count(p.A, p.B, gamma)
+        if not r.converged or cnt != len(r.theta):
+            raise RuntimeError(f"instance {i}: converged {r.converged}, {len(r.theta)} values, count {cnt}")
+        out["instances"].append({
+            "index": i, "pencil": p.name, "n": p.n, "gamma": gamma, "L": L, "count": cnt,
+            "eigenvalues": r.theta.tolist(), "next_ritz_value": float(r.theta_all[len(r.theta)]),
+            "max_rho": float(r.rho.max()), "iterations": r.iterations, "seconds": time.time() - t})
+        _log(f"batch instance {i}: n={p.n}, {cnt} eigenvalues, max rho {r.rho.max():.1e}")
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["poles", "count_c2"]
     if "poles" in what:
@@ -152,3 +184,7 @@ if __name__ == "__main__":
         make_eig_c3()
     if "count_c3" in what:
         make_count_c3()
+    if "eig_batch" in what:
+        make_eig_batch()
+    if "eig_serve" in what:   # the requests of the serving loop's GPU test
+        make_eig_batch(SERVE_TEST_INSTANCES, (5e3, 2e5), "eig_serve6.json")

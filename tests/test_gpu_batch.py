@@ -10,6 +10,9 @@
   leaving when done, results unchanged.
 * hipGraph replay of the iteration chunks gives bitwise the eager result.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as sla
@@ -218,10 +221,13 @@ def test_graph_replay_bitwise_equals_eager(slrf, torch, prec):
 
 def test_batched_workload_recipe_with_autotune_and_graph(slrf, torch):
     """Eight instances of the batched workload's recipe (sizes cut to 2e3..1.5e4
-    rows so the oracle's inertia count stays quick), mixed precision, autotuned
-    tiles, graph replay: every instance converges to the oracle's count and
+    rows so the oracle stays quick), mixed precision, autotuned tiles, graph
+    replay: every instance finds the oracle's count and eigenvalues (stored by
+    tests/golden/make_golden.py from its shift-invert subspace iteration) and
     agrees with its FP64 solve alone."""
-    insts = [pencils.batch_instance(i, n_range=(2e3, 1.5e4)) for i in range(8)]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "eig_batch8_n2e3_1.5e4.json")) as f:
+        gold = json.load(f)
+    insts = [pencils.batch_instance(i, n_range=tuple(gold["n_range"])) for i in range(8)]
     cases = [(p, g, L, k) for p, g, L, k in insts]
     ws, arena = ws_for(slrf, cases, 1)
     stream = torch.cuda.Stream()
@@ -234,15 +240,18 @@ def test_batched_workload_recipe_with_autotune_and_graph(slrf, torch):
     res = [b.result(pid) for pid in ids]
     torch.cuda.synchronize()
     b.close()
-    for (p, gamma, L, nev), r in zip(cases, res):
+    for (p, gamma, L, nev), r, g in zip(cases, res, gold["instances"]):
         s = slrf.Solver(p.A, p.B, max_L=L, max_poles=4)
         a = s.solve_interval(gamma, L)
         s.close()
         nf = r.n_found
         cnt = inertia.sparse_ldl_count(p.A, p.B, gamma)
         rel = np.abs(r.evals[:nf] / a.evals[:nf] - 1).max()
-        say(f"  n={p.n} dim={p.meta['dim']} nev~{nev} L={L}: found {nf} (count {cnt}), "
-            f"outer {r.stats['outer_iterations']}, rel vs FP64 alone {rel:.1e}")
-        assert r.status == 0 and nf == cnt == a.n_found
-        assert rel < 1e-9
+        ev_o = np.array(g["eigenvalues"])
+        assert g["n"] == p.n and g["gamma"] == gamma and g["count"] == len(ev_o)
+        rel_o = np.abs(r.evals[:nf] / ev_o[:nf] - 1).max() if nf == len(ev_o) else np.inf
+        say(f"  n={p.n} dim={p.meta['dim']} nev~{nev} L={L}: found {nf} (count {cnt}, oracle {len(ev_o)}), "
+            f"outer {r.stats['outer_iterations']}, rel vs FP64 alone {rel:.1e}, vs oracle {rel_o:.1e}")
+        assert r.status == 0 and nf == cnt == a.n_found == len(ev_o)
+        assert rel < 1e-9 and rel_o < 1e-9
         assert r.resid[:nf].max() <= 1e-8

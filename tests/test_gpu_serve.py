@@ -2,7 +2,11 @@
 while others run are admitted as pool and arena space frees up, their work
 shares each batched launch, and every result is the same as the request solved
 alone, within the stated tolerance (eigenvalues to 1e-9 relative, the same count
-of converged pairs, residuals <= 1e-8)."""
+of converged pairs, residuals <= 1e-8), and the same as the oracle's eigenvalues
+stored in tests/golden/eig_serve6.json."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -30,12 +34,15 @@ def say(*a):
     print(*a, flush=True)
 
 
+INSTANCES = [1, 6, 8, 34, 42, 51]
+
+
 def requests(serve):
     """Six small requests (2D and 3D scalar pencils, different n, L, gamma) and the
     server step at which each arrives."""
     out = []
     arrive = [0, 0, 1, 2, 4, 5]
-    for k, i in enumerate([1, 6, 8, 34, 42, 51]):
+    for k, i in enumerate(INSTANCES):
         p, gamma, L, _ = pencils.batch_instance(i)
         V0 = pencils.start_block(p.n, L, 500 + k)
         out.append(serve.Request(k, p.A, p.B, gamma, L, V0=V0, arrival=float(arrive[k])))
@@ -45,6 +52,9 @@ def requests(serve):
 @pytest.mark.parametrize("prec", [1, 0])
 def test_results_same_alone_and_in_the_mix(slrf, torch, prec):
     import paper_2503_21618_amd.serve as serve
+    with open(os.path.join(os.path.dirname(__file__), "golden", "eig_serve6.json")) as f:
+        gold = json.load(f)["instances"]
+    assert [g["index"] for g in gold] == INSTANCES
     reqs = requests(serve)
     opt = slrf.default_options(precision=prec)
     alone = {}
@@ -79,11 +89,15 @@ def test_results_same_alone_and_in_the_mix(slrf, torch, prec):
         req = reqs[c.rid]
         nf = r.n_found
         rel = np.abs(r.evals[:nf] / a.evals[:nf] - 1).max()
-        say(f"  request {c.rid}: n={req.A.shape[0]} found {nf} (alone {a.n_found}), rel diff {rel:.1e}, "
+        ev_o = np.array(gold[c.rid]["eigenvalues"])
+        assert gold[c.rid]["n"] == req.A.shape[0] and gold[c.rid]["gamma"] == req.gamma
+        rel_o = np.abs(r.evals[:nf] / ev_o[:nf] - 1).max() if nf == len(ev_o) else np.inf
+        say(f"  request {c.rid}: n={req.A.shape[0]} found {nf} (alone {a.n_found}, oracle {len(ev_o)}), "
+            f"rel diff {rel:.1e}, vs oracle {rel_o:.1e}, "
             f"arrive {c.arrival:.0f} admitted {c.admitted:.0f} finished {c.finished:.0f}")
         assert r.status == 0 and a.status == 0
-        assert nf == a.n_found == inertia.sparse_ldl_count(req.A, req.B, req.gamma)
-        assert rel < 1e-9
+        assert nf == a.n_found == inertia.sparse_ldl_count(req.A, req.B, req.gamma) == len(ev_o)
+        assert rel < 1e-9 and rel_o < 1e-9
         assert r.resid[:nf].max() <= 1e-8
         assert c.admitted >= c.arrival and c.finished > c.admitted
     srv.close()

@@ -149,6 +149,28 @@ def test_golden_c3_count_two_ways():
     assert d["converged"] and d["max_rho"] <= 1e-10
 
 
+@pytest.mark.parametrize("name,count", [("eig_batch8_n2e3_1.5e4.json", 8), ("eig_serve6.json", 6)])
+def test_golden_batch_eigenvalues_against_arpack(name, count):
+    """The stored eigenvalues of batched-recipe pencils (the oracle's shift-invert
+    subspace iteration, written by tests/golden/make_golden.py) against ARPACK's
+    shift-invert Lanczos (scipy eigsh, an independent routine) on the regenerated
+    pencils: the same count below gamma and the same values to 1e-10 relative."""
+    import scipy.sparse.linalg as sla
+    with open(os.path.join(GOLDEN, name)) as f:
+        d = json.load(f)
+    assert len(d["instances"]) == count
+    for inst in d["instances"]:
+        p, gamma, L, _ = pencils.batch_instance(inst["index"], n_range=tuple(d["n_range"]))
+        assert p.n == inst["n"] and gamma == inst["gamma"] and L == inst["L"]
+        ev = np.array(inst["eigenvalues"])
+        k = inst["count"] + 6
+        ref = np.sort(sla.eigsh(p.A.tocsc(), k=k, M=p.B.tocsc(), sigma=0.0, which="LM",
+                                return_eigenvectors=False, tol=1e-14))
+        assert int((ref <= gamma).sum()) == inst["count"] == len(ev)
+        assert np.abs(ev / ref[:len(ev)] - 1).max() < 1e-10
+        assert ev[-1] < gamma < inst["next_ritz_value"]
+
+
 # ---- filter and Krylov -----------------------------------------------------
 
 def test_filter_apply_closed_form_eigenvectors():
