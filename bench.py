@@ -365,6 +365,45 @@ def summarize_pmc(fetch_csv, write_csv, probe_log, wl_key="c2"):
             print(f"traffic_over_algorithmic {key}: {tot / len(kerns) / a:.3f}")
 
 
+def summarize_tcc(csv_path, wl_key="c3"):
+    """Prints the L2 (TCC) hit rate per kernel from one rocprofv3 pass with the
+    TCC_HIT_sum and TCC_MISS_sum counters over the counter probe."""
+    acc = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            ms = re.search(r"k_sgs_sweep<(float|double), (\d+), (\d+)>", name)
+            mc = re.search(r"k_cocg_spmm<(float|double)", name)
+            key = ("copy" if "elementwise" in name and "neg" in name else
+                   f"k_sgs_sweep<{ms.group(1)}, {ms.group(2)}, {ms.group(3)}>" if ms else
+                   f"k_cocg_spmm<{mc.group(1)}>" if mc else None)
+            if key:
+                acc.setdefault(key, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    what = ("3D scalar vibration pencil 64^3 (n=250047, 27 nnz/row), L=128, N=6 (K=768)" if wl_key == "c2" else
+            "3D elasticity pencil 48^3 nodes x 3 (n=331776, 81 nnz/row), L=256, N=8 (K=2048)")
+    print("# L2 (TCC) hits and misses of the complex-shifted sparse products and colour sweeps,")
+    print(f"# {what}, full-width launches of the counter probe (fixed inner iterations).")
+    print("# k_sgs_sweep<R, B, M>: B block size (3 node), M 0 backward iteration, 2 forward")
+    print("# iteration, 3 forward start, 1 backward final; k_cocg_spmm: the node-triple product of")
+    print("# the block Jacobi form.  Requests per dispatch, averaged over the kernel's dispatches.")
+    print("# Commands (repository root R, run from /tmp with TMPDIR=/tmp):")
+    print("#   rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --kernel-include-regex \"k_cocg_spmm|k_sgs_sweep|elementwise\" "
+          f"--output-format csv -d <out>/pmc_tcc -o run -- python3 R/bench.py --counters-probe --workload {wl_key}")
+    print("#   python3 bench.py --summarize-tcc <out>/pmc_tcc/run_counter_collection.csv "
+          f"--workload {wl_key}")
+    print(f"source_sha256: {kernel_source_hash()}")
+    for key in sorted(acc):
+        d = acc[key]
+        if "TCC_HIT_sum" not in d or "TCC_MISS_sum" not in d:
+            continue
+        hit = sum(d["TCC_HIT_sum"]) / len(d["TCC_HIT_sum"])
+        miss = sum(d["TCC_MISS_sum"]) / len(d["TCC_MISS_sum"])
+        print(f"{key} dispatches: {len(d['TCC_HIT_sum'])}")
+        print(f"{key} TCC_HIT per dispatch: {hit:.4e}")
+        print(f"{key} TCC_MISS per dispatch: {miss:.4e}")
+        print(f"{key} hit_rate: {hit / max(hit + miss, 1.0):.3f}")
+
+
 MFMA_COUNTERS = ["SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_VALU_MFMA_BUSY_CYCLES",
                  "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE"]
 MFMA_SHAPE = (331776, 256)        # the elasticity workload's n and L
@@ -1058,6 +1097,8 @@ def main():
                     help="short run for the rocprofv3 counter passes (see the module docstring)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
                     help="print the counter summary from two rocprofv3 CSVs")
+    ap.add_argument("--summarize-tcc", metavar="TCC_CSV",
+                    help="print the L2 hit rates from a TCC_HIT_sum / TCC_MISS_sum counter pass")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="short run of the Rayleigh-Ritz MFMA kernels for the MFMA counter pass")
     ap.add_argument("--summarize-mfma", nargs=2, metavar=("PMC_CSV", "TRACE_CSV"),
@@ -1065,6 +1106,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, wl_key=args.workload)
+        return
+    if args.summarize_tcc:
+        summarize_tcc(args.summarize_tcc, wl_key=args.workload)
         return
     if args.summarize_mfma:
         summarize_mfma(*args.summarize_mfma)

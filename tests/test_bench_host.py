@@ -57,3 +57,20 @@ def test_counter_summary_calibration(tmp_path):
     expect = 5e6 * 1024 / 0.5 + 1e6 * 1024 / 1.0
     assert abs(float(out["full_launch_traffic_bytes sgs float"]) / expect - 1) < 1e-6
     assert abs(float(out["traffic_over_algorithmic sgs float"]) - expect / 3.43e9) < 1e-3
+
+
+def test_l2_summary_hit_rate(tmp_path):
+    """Hit rate = hits / (hits + misses), averaged per dispatch, per sweep mode."""
+    back = "void slrf::k_sgs_sweep<float, 3, 0>(slrf::Batch, slrf::KrylovState<float>, int, int, int, int*)"
+    fwd = "void slrf::k_sgs_sweep<float, 3, 2>(slrf::Batch, slrf::KrylovState<float>, int, int, int, int*)"
+    path = tmp_path / "tcc.csv"
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (k, h, m) in enumerate([(back, 10, 30), (back, 30, 50), (fwd, 3, 1)]):
+            f.write(f'{i},"{k}",TCC_HIT_sum,{h}\n{i},"{k}",TCC_MISS_sum,{m}\n')
+    r = run_bench("--summarize-tcc", str(path), "--workload", "c3")
+    assert r.returncode == 0, r.stderr
+    lines = dict(l.rsplit(":", 1) for l in r.stdout.splitlines() if not l.startswith("#") and ":" in l)
+    assert lines["k_sgs_sweep<float, 3, 0> dispatches"].strip() == "2"
+    assert float(lines["k_sgs_sweep<float, 3, 0> hit_rate"]) == 0.333
+    assert float(lines["k_sgs_sweep<float, 3, 2> hit_rate"]) == 0.75
