@@ -172,6 +172,50 @@ def make_eig_batch(indices=range(8), n_range=BATCH_N_RANGE, name="eig_batch8_n2e
         json.dump(out, f, indent=1)
 
 
+SERVE_MIX = [("scalar", 1), ("elasticity", (10, 7101)), ("scalar", 8), ("elasticity", (12, 7103))]
+
+
+def make_eig_serve_mix():
+    """The requests of the served-mix GPU test: two scalar pencils of the batched
+    recipe (their own gamma) and two small elasticity pencils of the serving
+    recipe (nodes^3 free nodes x 3, log-normal Young's modulus sigma 0.7, nu 0.3,
+    density U[0.8, 1.2]) with gamma in the middle of the widest relative gap
+    that leaves 25..40 eigenvalues below it."""
+    out = {"requests": [], "source": "oracle.shift_invert.subspace_iteration (shift 0, banded Cholesky); "
+                                     "oracle.inertia.sparse_ldl_count"}
+    for kind, arg in SERVE_MIX:
+        t = time.time()
+        if kind == "scalar":
+            p, gamma, L, _ = pencils.batch_instance(arg)
+            rec = {"kind": kind, "index": arg}
+        else:
+            nodes, seed = arg
+            p = pencils.elasticity_q1(nodes, nodes - 1, nodes - 1, 1.0 / nodes, 0.7, 0.3, (0.8, 1.2), seed)
+            F = banded.band_cholesky(p.A)
+            ca, cp = pencils.ELASTICITY_SPECTRUM
+            lo = shift_invert.subspace_iteration(p.A, p.B, ca * 50.0 ** cp, pencils.start_block(p.n, 96, seed),
+                                                 tol=1e-11, factor=F)
+            th = lo.theta
+            k = max(range(25, min(41, len(th))), key=lambda k: (th[k] - th[k - 1]) / th[k])
+            gamma = float(0.5 * (th[k - 1] + th[k]))
+            L = int(np.ceil(np.ceil(1.2 * k) / 8.0) * 8)
+            rec = {"kind": kind, "nodes": nodes, "seed": seed,
+                   "relative_gap": float((th[k] - th[k - 1]) / th[k])}
+        F = banded.band_cholesky(p.A)
+        V0 = pencils.start_block(p.n, L + 24, 200 + len(out["requests"]))
+        r = shift_invert.subspace_iteration(p.A, p.B, gamma, V0, tol=1e-11, factor=F)
+        cnt = inertia.sparse_ldl_count(p.A, p.B, gamma)
+        if not r.converged or cnt != len(r.theta):
+            raise RuntimeError(f"{kind} {arg}: converged {r.converged}, {len(r.theta)} values, count {cnt}")
+        rec.update({"pencil": p.name, "n": p.n, "gamma": gamma, "L": L, "count": cnt,
+                    "eigenvalues": r.theta.tolist(), "next_ritz_value": float(r.theta_all[len(r.theta)]),
+                    "max_rho": float(r.rho.max()), "seconds": time.time() - t})
+        out["requests"].append(rec)
+        _log(f"serve mix {kind} {arg}: n={p.n}, gamma {gamma:.6g}, {cnt} eigenvalues")
+    with open(os.path.join(HERE, "eig_serve_mix4.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["poles", "count_c2"]
     if "poles" in what:
@@ -186,5 +230,7 @@ if __name__ == "__main__":
         make_count_c3()
     if "eig_batch" in what:
         make_eig_batch()
+    if "eig_serve_mix" in what:
+        make_eig_serve_mix()
     if "eig_serve" in what:   # the requests of the serving loop's GPU test
         make_eig_batch(SERVE_TEST_INSTANCES, (5e3, 2e5), "eig_serve6.json")

@@ -101,3 +101,63 @@ def test_results_same_alone_and_in_the_mix(slrf, torch, prec):
         assert r.resid[:nf].max() <= 1e-8
         assert c.admitted >= c.arrival and c.finished > c.admitted
     srv.close()
+
+
+def mix_pencil(req):
+    """The pencil of one request of tests/golden/eig_serve_mix4.json."""
+    if req["kind"] == "scalar":
+        return pencils.batch_instance(req["index"])[0]
+    k = req["nodes"]
+    return pencils.elasticity_q1(k, k - 1, k - 1, 1.0 / k, 0.7, 0.3, (0.8, 1.2), req["seed"])
+
+
+def test_served_mix_configuration_matches_oracle(slrf, torch):
+    """The served workload's configuration (mixed precision, COCG, multicolour SGS
+    with node blocks for the elasticity pencils and points for the scalar ones,
+    warm starts, graph replay, N = 6 designed poles per request) on two scalar and
+    two elasticity requests arriving over three steps, with room for about half
+    of them at once: every request finds the oracle's count and eigenvalues
+    (tests/golden/eig_serve_mix4.json) with residuals <= 1e-8."""
+    import paper_2503_21618_amd.serve as serve
+    with open(os.path.join(os.path.dirname(__file__), "golden", "eig_serve_mix4.json")) as f:
+        gold = json.load(f)["requests"]
+    N = 6
+    opt = slrf.default_options(precision=1, solver=slrf.SOLVER_COCG, precond=slrf.PRECOND_SGS3, recycle=1,
+                               graph=1, profile=0)
+    reqs, pers, trans = [], 0, 0
+    for k, g in enumerate(gold):
+        p = mix_pencil(g)
+        assert p.n == g["n"]
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, g["gamma"])
+        V0 = pencils.start_block(p.n, g["L"], 600 + k)
+        reqs.append(serve.Request(k, p.A, p.B, g["gamma"], g["L"], sig, w, V0=V0, arrival=float(k // 2 + k % 2)))
+        a, b = slrf.batch_footprint(p.n, int((abs(p.A) + abs(p.B)).nnz), g["L"], N, options=opt)
+        pers += a + 4096
+        trans += b
+    srv = serve.Server(pers + trans // 2 + (1 << 20), trans // 2, max_poles=N, options=opt,
+                       stream=torch.cuda.Stream())
+    srv.clock = lambda: float(srv.steps)
+    pending = sorted(reqs, key=lambda r: r.arrival)
+    while pending or not srv.idle():
+        while pending and pending[0].arrival <= srv.steps:
+            srv.submit(pending.pop(0))
+        if srv.idle() and pending:
+            srv.steps += 1
+            continue
+        srv.pump()
+        assert srv.steps < 200
+    torch.cuda.synchronize()
+    say(f"case served mix: {len(srv.done)} done in {srv.steps} steps, peak active {srv.peak_active}")
+    assert len(srv.done) == len(reqs)
+    for c in sorted(srv.done, key=lambda c: c.rid):
+        g, r = gold[c.rid], c.result
+        nf = r.n_found
+        ev_o = np.array(g["eigenvalues"])
+        rel_o = np.abs(r.evals[:nf] / ev_o[:nf] - 1).max() if nf == len(ev_o) else np.inf
+        say(f"  request {c.rid} ({g['kind']}, n={g['n']}, L={g['L']}): found {nf} (oracle {len(ev_o)}), "
+            f"rel vs oracle {rel_o:.1e}, max rho {r.resid[:nf].max():.1e}, "
+            f"outer {r.stats['outer_iterations']}, admitted {c.admitted:.0f} finished {c.finished:.0f}")
+        assert r.status == 0 and nf == len(ev_o) == g["count"]
+        assert rel_o < 1e-9
+        assert r.resid[:nf].max() <= 1e-8
+    srv.close()

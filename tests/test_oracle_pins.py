@@ -171,6 +171,34 @@ def test_golden_batch_eigenvalues_against_arpack(name, count):
         assert ev[-1] < gamma < inst["next_ritz_value"]
 
 
+def serve_mix_pencil(req):
+    """The pencil of one request of tests/golden/eig_serve_mix4.json, regenerated."""
+    if req["kind"] == "scalar":
+        return pencils.batch_instance(req["index"])[0]
+    k = req["nodes"]
+    return pencils.elasticity_q1(k, k - 1, k - 1, 1.0 / k, 0.7, 0.3, (0.8, 1.2), req["seed"])
+
+
+def test_golden_serve_mix_against_arpack():
+    """The served-mix requests' stored eigenvalues (two scalar, two elasticity
+    pencils) against ARPACK's shift-invert Lanczos: the same count below gamma,
+    the same values to 1e-10 relative, and gamma mid-gap."""
+    import scipy.sparse.linalg as sla
+    with open(os.path.join(GOLDEN, "eig_serve_mix4.json")) as f:
+        d = json.load(f)
+    assert [r["kind"] for r in d["requests"]] == ["scalar", "elasticity", "scalar", "elasticity"]
+    for req in d["requests"]:
+        p = serve_mix_pencil(req)
+        assert p.n == req["n"]
+        ev = np.array(req["eigenvalues"])
+        ref = np.sort(sla.eigsh(p.A.tocsc(), k=req["count"] + 6, M=p.B.tocsc(), sigma=0.0, which="LM",
+                                return_eigenvectors=False, tol=1e-14))
+        assert int((ref <= req["gamma"]).sum()) == req["count"] == len(ev)
+        assert np.abs(ev / ref[:len(ev)] - 1).max() < 1e-10
+        assert ev[-1] < req["gamma"] < req["next_ritz_value"]
+        assert req["count"] < req["L"]
+
+
 # ---- filter and Krylov -----------------------------------------------------
 
 def test_filter_apply_closed_form_eigenvectors():
