@@ -18,13 +18,21 @@ rational filter for large-scale eigenvalue problems", arXiv:2503.21618):
                exact direct solves (Algorithm 1, steps "Solve"/"Compute U";
                the conjugate-pair reduction of Section 3).
   krylov.py    Right-preconditioned BiCGStab (van der Vorst 1992, the inner
-               solver of Sections 2 and 4.2) for the shifted systems, point-Jacobi
-               preconditioner of the shifted operator.
+               solver of Sections 2 and 4.2) and COCG (van der Vorst and
+               Melissen 1990) for the shifted systems; preconditioners of the
+               shifted operator: point Jacobi, ILU(0), 3x3 node-block Jacobi
+               and the multicolour symmetric Gauss-Seidel / SOR (greedy
+               colouring of the node graph).
   inertia.py   Eigenvalue counts below gamma by Sylvester's law of inertia.
   dense.py     All eigenpairs of a tiny pencil (Cholesky reduction).
   subspace.py  Algorithm 1 (rational filter subspace iteration) with exact
                solves, B-orthonormalisation, Rayleigh-Ritz and the relative
                residual of Algorithm 1 / Section 4.2.
+  banded.py    Banded Cholesky of A and block-elimination inertia counts for
+               the large structured-grid pencils.
+  shift_invert.py  Eigenpairs in (0, gamma] of the large pencils by
+               shift-invert subspace iteration (Algorithm 1 with the filter
+               1/lambda, the Ericsson-Ruhe method of Section 1).
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*``
 against closed forms, invariants or brute force, except the numerical pole
