@@ -209,8 +209,10 @@ slrf_status slrf_workspace_bytes(int64_t n, int64_t nnz_union, int64_t L, int32_
 slrf_status slrf_workspace_bytes_for(int64_t n, int64_t nnz_union, int64_t L, int32_t N,
                                      const slrf_options* opt, size_t* bytes);
 
-/* Validates A and B (square, sorted in-range columns, finite values, symmetric
- * pattern sizes, positive diagonals), merges them into one CSR over the union
+/* Validates A and B (square, sorted in-range columns, finite values, positive
+ * diagonals, symmetric: |m_ij - m_ji| <= 1e-10 sqrt(m_ii m_jj) for M = A and
+ * M = B, an entry stored on one side only counting as zero; SLRF_E_INVALID_ARG
+ * otherwise), merges them into one CSR over the union
  * pattern with (a_ij, b_ij) value pairs, and uploads it into the workspace.
  * d_workspace: device, 256-byte aligned, ws_bytes from slrf_workspace_bytes_for
  * with the largest L and N that later calls use and the same options.  hip_stream: a hipStream_t

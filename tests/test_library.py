@@ -6,6 +6,7 @@ import os
 import re
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import pencils
@@ -164,6 +165,30 @@ def test_create_rejects_bad_matrices(lib):
     st, msg = _create(lib, p.A, p.B, ws_ptr=0x100001)
     assert st == 3
     st, msg = _create(lib, p.A, p.B, ws_bytes=1024)
+    assert st == 3 and "needs" in msg
+
+
+def test_create_rejects_non_symmetric_pencils(lib):
+    """A and B must be symmetric (the pencil of Section 1): entry (i, j) against
+    (j, i) to 1e-10 of sqrt(m_ii m_jj), an entry stored on one side only
+    counting as zero.  Accepted pencils pass on to the workspace-size check."""
+    p = pencils.string_1d(20)
+    Aa = p.A.tolil()
+    Aa[0, 1] = Aa[0, 1] * (1 + 1e-6)                  # relative 1e-6: rejected
+    st, msg = _create(lib, Aa.tocsr(), p.B, ws_bytes=1024)
+    assert st == 1 and "A is not symmetric" in msg and "(0, 1)" in msg
+    Bb = p.B.tolil()
+    Bb[0, 5] = 1e-3 * Bb[0, 0]                        # stored on one side only
+    st, msg = _create(lib, p.A, Bb.tocsr(), ws_bytes=1024)
+    assert st == 1 and "B is not symmetric" in msg
+    Az = p.A.tocoo()
+    Az = sp.csr_matrix((np.append(Az.data, 0.0), (np.append(Az.row, 0), np.append(Az.col, 7))), shape=Az.shape)
+    assert Az.nnz == p.A.nnz + 1                      # an explicit zero at (0, 7) only: accepted
+    st, msg = _create(lib, Az, p.B, ws_bytes=1024)
+    assert st == 3 and "needs" in msg
+    Ar = p.A.tolil()
+    Ar[0, 1] = Ar[0, 1] * (1 + 1e-14)                 # rounding-level asymmetry: accepted
+    st, msg = _create(lib, Ar.tocsr(), p.B, ws_bytes=1024)
     assert st == 3 and "needs" in msg
 
 
