@@ -42,7 +42,7 @@ typedef struct slrf_ctx_s* slrf_ctx;
 
 typedef enum {
   SLRF_OK = 0,
-  SLRF_E_INVALID_ARG = 1,        /* bad size, NULL pointer, unsorted/out-of-range CSR, NaN */
+  SLRF_E_INVALID_ARG = 1,        /* bad size, NULL pointer, unsorted/out-of-range CSR, NaN, A or B not symmetric */
   SLRF_E_NOT_SPD = 2,            /* a diagonal entry of A or B is <= 0 or missing */
   SLRF_E_WORKSPACE = 3,          /* workspace too small or misaligned (256 B) */
   SLRF_E_DEVICE = 4,             /* a HIP runtime call failed */
@@ -101,7 +101,8 @@ typedef struct {
                           needs a non-NULL stream and profile = 0, else ignored.  0: off */
   /* Work decomposition of the Krylov kernels (0 = default).  They change the
    * order of floating-point sums, not the method. */
-  int32_t tile_rows;   /* rows per row block (default 8, 1..64) */
+  int32_t tile_rows;   /* rows per row block (default 16, or 24 for a batch of
+                          node-triple pencils only; 1..64) */
   int32_t tile_wgs;    /* workgroups per XCD (default 128, 1..256; grid = 8 * this) */
   int32_t band_rows;   /* rows per sub-band of the sparse-product row order (default
                           1024; -1 = natural row order); applied when a pencil is built */
@@ -113,9 +114,10 @@ typedef struct {
                           the paper's choice), 1 COCG, conjugate gradients with the
                           bilinear form u^T v for the complex-symmetric A - sigma_j B
                           (one sparse product per iteration; symmetric
-                          preconditioners only: precond 0 then selects point
-                          Jacobi, 3 node block Jacobi, and 2 (ILU(0)) is rejected
-                          with SLRF_E_INVALID_ARG) */
+                          preconditioners only: 1 point Jacobi (also what
+                          precond 0 selects), 3 node block Jacobi, 4 and 5 the
+                          multicolour SGS; 2 (ILU(0)) is rejected with
+                          SLRF_E_INVALID_ARG) */
   int32_t recycle;     /* 1 (mixed precision): each outer iteration after a pencil's
                           first starts its shifted solves from the previous one's
                           solutions carried to the new block, Y0 = Y_prev (X_prev^T B
@@ -252,7 +254,8 @@ slrf_status slrf_create_static(slrf_ctx* out, int64_t n,
  *   U = sum_j 2 Re(w_j Y_j),  (A - sigma_j B) Y_j = B X  for j = 1..N,
  * every (pole, column) system solved by right-preconditioned BiCGStab (the
  * preconditioner of slrf_options.precond), x_0 = 0 and shadow residual B X, or by
- * COCG with point or node block Jacobi (slrf_options.solver = 1).  d_X, d_U: device (n, L) row-major float64
+ * COCG with point or node block Jacobi or the multicolour SGS (slrf_options.solver = 1).
+ * d_X, d_U: device (n, L) row-major float64
  * (may not alias).  stats may be NULL.  Returns SLRF_OK even if some columns hit
  * inner_maxit or broke down; stats reports them. */
 slrf_status slrf_filter_apply(slrf_ctx ctx, const slrf_poles* poles, int64_t L,

@@ -697,9 +697,11 @@ slrf_status setup_env(Env& env, const slrf_options* opt, void* hip_stream) {
   if (env.opt.sgs_omega != 0.0 && !(env.opt.sgs_omega > 0.0 && env.opt.sgs_omega < 2.0))
     return fail(env, SLRF_E_INVALID_ARG, "sgs_omega must be 0 (by block size) or lie in (0, 2)");
   if (env.opt.solver == 1) {
-    // COCG needs a complex-symmetric preconditioner: point or node block Jacobi
+    // COCG needs a complex-symmetric preconditioner: point or node block Jacobi,
+    // or the multicolour SGS
     if (env.opt.precond == 2)
-      return fail(env, SLRF_E_INVALID_ARG, "COCG takes point or node block Jacobi (ILU(0) is not symmetric)");
+      return fail(env, SLRF_E_INVALID_ARG,
+                  "COCG takes point or node block Jacobi or the multicolour SGS (ILU(0) is not symmetric)");
     if (env.opt.precond == 0) env.opt.precond = 1;
   }
   if (!(env.opt.inner_tol >= 0) || !(env.opt.outer_tol >= 0))
