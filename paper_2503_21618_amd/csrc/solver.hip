@@ -355,42 +355,58 @@ slrf_status build_pencil(int64_t n, const int32_t* a_rowptr, const int32_t* a_co
       return SLRF_E_NOT_SPD;
     }
   const int64_t nnz = (int64_t)cl.size();
-  // A and B symmetric (the pencil of Section 1): entry (i, j) against (j, i),
-  // an entry missing on one side counting as zero, to 1e-10 of the diagonal
-  // scale sqrt(m_ii m_jj).  The transpose of the merged pattern lists each
-  // column's rows in ascending order, so row i and column i are merged in step.
-  // Checked in the validation pass (mem == nullptr), which both callers run on
-  // the same arrays before the pass that uploads.
+  // A and B symmetric (the pencil of Section 1): every stored entry (i, j) of
+  // the merged pattern against (j, i), found by bisection in the sorted row j
+  // (an entry stored on one side only counts as zero there), to 1e-10 of the
+  // diagonal scale sqrt(m_ii m_jj).  Rows are split over host threads; the
+  // first failing row is reported.  Checked in the validation pass
+  // (mem == nullptr), which both callers run on the same arrays before the pass
+  // that uploads.
   if (!mem) {
-    std::vector<int32_t> tp(n + 1, 0), trow(nnz), tk(nnz);  // nnz <= INT32_MAX (int32 row pointers)
-    for (int64_t k = 0; k < nnz; ++k) tp[cl[k] + 1]++;
-    for (int64_t j = 0; j < n; ++j) tp[j + 1] += tp[j];
-    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
-    for (int64_t i = 0; i < n; ++i)
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int32_t q = fill[cl[k]]++;
-        trow[q] = (int32_t)i;
-        tk[q] = (int32_t)k;
-      }
     constexpr double kSymTol = 1e-10;
-    for (int64_t i = 0; i < n; ++i) {
-      int32_t k = rp[i], q = tp[i];
-      while (k < rp[i + 1] || q < tp[i + 1]) {
-        const int32_t j = k < rp[i + 1] ? cl[k] : INT32_MAX, t = q < tp[i + 1] ? trow[q] : INT32_MAX;
-        const int32_t c = std::min(j, t);
-        const double aij = j == c ? ab[2 * (size_t)k] : 0.0, bij = j == c ? ab[2 * (size_t)k + 1] : 0.0;
-        const double aji = t == c ? ab[2 * (size_t)tk[q]] : 0.0, bji = t == c ? ab[2 * (size_t)tk[q] + 1] : 0.0;
-        if (!(std::fabs(aij - aji) <= kSymTol * std::sqrt(dA[i] * dA[c])) ||
-            !(std::fabs(bij - bji) <= kSymTol * std::sqrt(dB[i] * dB[c]))) {
-          err = std::string(std::fabs(aij - aji) <= kSymTol * std::sqrt(dA[i] * dA[c]) ? "B" : "A") +
-                " is not symmetric: entries (" + std::to_string(i) + ", " + std::to_string(c) + ") and (" +
-                std::to_string(c) + ", " + std::to_string(i) + ") differ";
-          return SLRF_E_INVALID_ARG;
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                 nnz / 200000 + 1}));
+    std::vector<int64_t> bad(nt, -1), badc(nt, -1);
+    auto check_rows = [&](int t) {
+      const int64_t i0 = n * t / nt, i1 = n * (t + 1) / nt;
+      for (int64_t i = i0; i < i1; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+          const int32_t j = cl[k];
+          if (j == i) continue;
+          const int32_t* lo = cl.data() + rp[j];
+          const int32_t* hi = cl.data() + rp[j + 1];
+          const int32_t* f = std::lower_bound(lo, hi, (int32_t)i);
+          const bool has = f != hi && *f == i;
+          const size_t q = has ? (size_t)(f - cl.data()) : 0;
+          const double aji = has ? ab[2 * q] : 0.0, bji = has ? ab[2 * q + 1] : 0.0;
+          if (!(std::fabs(ab[2 * (size_t)k] - aji) <= kSymTol * std::sqrt(dA[i] * dA[j])) ||
+              !(std::fabs(ab[2 * (size_t)k + 1] - bji) <= kSymTol * std::sqrt(dB[i] * dB[j]))) {
+            bad[t] = i;
+            badc[t] = j;
+            return;
+          }
         }
-        if (j == c) ++k;
-        if (t == c) ++q;
-      }
+    };
+    if (nt == 1) {
+      check_rows(0);
+    } else {
+      std::vector<std::thread> pool;
+      for (int t = 0; t < nt; ++t) pool.emplace_back(check_rows, t);
+      for (auto& th : pool) th.join();
     }
+    for (int t = 0; t < nt; ++t)
+      if (bad[t] >= 0) {
+        const int64_t i = bad[t], j = badc[t];
+        const int32_t* f = std::lower_bound(cl.data() + rp[i], cl.data() + rp[i + 1], (int32_t)j);
+        const size_t k = (size_t)(f - cl.data());
+        const int32_t* g = std::lower_bound(cl.data() + rp[j], cl.data() + rp[j + 1], (int32_t)i);
+        const bool has = g != cl.data() + rp[j + 1] && *g == i;
+        const double aji = has ? ab[2 * (size_t)(g - cl.data())] : 0.0;
+        const bool a_bad = !(std::fabs(ab[2 * k] - aji) <= kSymTol * std::sqrt(dA[i] * dA[j]));
+        err = std::string(a_bad ? "A" : "B") + " is not symmetric: entries (" + std::to_string(i) + ", " +
+              std::to_string(j) + ") and (" + std::to_string(j) + ", " + std::to_string(i) + ") differ";
+        return SLRF_E_INVALID_ARG;
+      }
   }
   if (nnz_out) *nnz_out = nnz;
   if (precond == 2 && !ilu_allowed(n, nnz)) {
