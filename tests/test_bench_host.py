@@ -74,3 +74,41 @@ def test_l2_summary_hit_rate(tmp_path):
     assert lines["k_sgs_sweep<float, 3, 0> dispatches"].strip() == "2"
     assert float(lines["k_sgs_sweep<float, 3, 0> hit_rate"]) == 0.333
     assert float(lines["k_sgs_sweep<float, 3, 2> hit_rate"]) == 0.75
+
+
+def load_bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_roofline_fields_pick_the_nearer_roof():
+    """The dominant kernel's line: algorithmic bytes and flops over the timed
+    launches' seconds, each against its peak; the bound is the roof with the
+    larger fraction, and frac = achieved / peak in the bound's unit."""
+    b = load_bench()
+    ks = {"spmm_seconds": 2.0, "spmm_bytes": 4.0e12, "spmm_launches": 1000}
+    r = b.roofline_fields(ks, "k", "float", 2.0e13)          # 2 TB/s = 0.25 of HBM; 10 TF/s
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 2000.0) < 1e-9 and r["peak"] == b.HBM_PEAK_GBS
+    assert abs(r["frac"] - 0.25) < 1e-12
+    assert abs(r["avg_launch_ms"] - 2.0) < 1e-12 and r["algorithmic_bytes_per_launch"] == 4.0e9
+    r = b.roofline_fields(ks, "k", "double", 1.2e14)         # 60 TF/s of 78.6: the ALU roof is nearer
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert abs(r["frac"] - 60.0 / b.FP64_TFS) < 1e-12
+
+
+def test_cpu_baseline_scaling():
+    """The oracle sample scaled to one solve: column-iterations, the set-up of
+    the N poles, and per outer iteration L (L + 3) B-products and L residuals."""
+    b = load_bench()
+    smp = {"s_per_column_iteration": 1e-3, "s_setup_per_pole": 2.0, "s_per_b_product": 1e-4,
+           "s_per_residual_column": 1e-2, "workers": 16, "host_cpus": 32, "cpu_model": "x", "sample": "s"}
+    stats = {"outer_iterations": 5, "spmv_total": 10000, "n_found": 50}
+    out = b.cpu_baseline(smp, stats, 64, 8)
+    est = 10000 * 1e-3 + 8 * 2.0 + 5 * 64 * 67 * 1e-4 + 5 * 64 * 1e-2
+    assert abs(out["estimated_solve_seconds"] - est) < 1e-12
+    assert abs(out["value"] - 50 / est) < 1e-12
+    assert out["cores"] == 16 and out["kind"] == "oracle" and out["unit"] == "eigenpairs/s"
