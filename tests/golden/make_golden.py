@@ -8,6 +8,8 @@ and the shared input generator ``pencils``.
     python tests/golden/make_golden.py count_c3  # inertia count of that pencil at its gamma
     python tests/golden/make_golden.py eig_batch # eigenvalues of eight batched-recipe pencils
     python tests/golden/make_golden.py eig_serve # eigenvalues of the serving test's six requests
+    python tests/golden/make_golden.py eig_batch_full  # the batched workload's first four pencils
+    python tests/golden/make_golden.py eig_serve_mix   # the served-mix test's four requests
 
 Pole tables: the oracle's SLRF design (ridge-regularised least squares, see
 oracle/poles.py) at gamma = 1, alpha = 1, beta = 0.01 (the paper's Section 4.2
@@ -230,6 +232,8 @@ if __name__ == "__main__":
         make_count_c3()
     if "eig_batch" in what:
         make_eig_batch()
+    if "eig_batch_full" in what:   # the first instances of the batched workload at full size
+        make_eig_batch(range(4), (5e3, 2e5), "eig_batch_full4.json")
     if "eig_serve_mix" in what:
         make_eig_serve_mix()
     if "eig_serve" in what:   # the requests of the serving loop's GPU test

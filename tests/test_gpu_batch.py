@@ -255,3 +255,46 @@ def test_batched_workload_recipe_with_autotune_and_graph(slrf, torch):
         assert r.status == 0 and nf == cnt == a.n_found == len(ev_o)
         assert rel < 1e-9 and rel_o < 1e-9
         assert r.resid[:nf].max() <= 1e-8
+
+
+def test_batched_workload_full_size_instances_match_oracle(slrf, torch):
+    """The batched workload's first four pencils at full size (n = 101,124 2D,
+    11,664 2D, 19,683 3D, 24,389 3D) in its configuration: one batch, mixed
+    precision, COCG with the multicolour SGS, warm starts, autotuned tiles,
+    graph replay, N = 6 designed poles each.  Every pencil finds the oracle's
+    count and eigenvalues (tests/golden/eig_batch_full4.json) with residuals
+    <= 1e-8."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "eig_batch_full4.json")) as f:
+        gold = json.load(f)
+    N = 6
+    opt = slrf.default_options(precision=1, solver=slrf.SOLVER_COCG, precond=slrf.PRECOND_SGS3, recycle=1,
+                               graph=1, profile=0, tune=1)
+    insts = [pencils.batch_instance(g["index"], n_range=tuple(gold["n_range"])) for g in gold["instances"]]
+    pers = trans = 0
+    for (p, _, L, _), g in zip(insts, gold["instances"]):
+        assert p.n == g["n"] and L == g["L"]
+        a, b = slrf.batch_footprint(p.n, int((abs(p.A) + abs(p.B)).nnz), L, N, options=opt)
+        pers += a + 4096
+        trans += b
+    say("case batched workload, first four instances at full size")
+    bt = slrf.Batch(pers + trans + (1 << 24), trans, max_poles=N, options=opt, stream=torch.cuda.Stream())
+    ids = []
+    for p, gamma, L, _ in insts:
+        sig, w, _ = slrf.design_poles(N, 1.0, 0.01, gamma)
+        ids.append(bt.add(p.A, p.B, gamma, L, sig, w))
+    steps = 0
+    while bt.step() > 0:
+        steps += 1
+        assert steps < 60
+    res = [bt.result(pid) for pid in ids]
+    torch.cuda.synchronize()
+    bt.close()
+    for (p, gamma, L, _), r, g in zip(insts, res, gold["instances"]):
+        nf = r.n_found
+        ev_o = np.array(g["eigenvalues"])
+        rel_o = np.abs(r.evals[:nf] / ev_o[:nf] - 1).max() if nf == len(ev_o) else np.inf
+        say(f"  n={p.n} dim={p.meta['dim']} L={L}: found {nf} (oracle {len(ev_o)}), rel vs oracle {rel_o:.1e}, "
+            f"max rho {r.resid[:nf].max():.1e}, outer {r.stats['outer_iterations']}")
+        assert r.status == 0 and nf == len(ev_o) == g["count"]
+        assert rel_o < 1e-9
+        assert r.resid[:nf].max() <= 1e-8

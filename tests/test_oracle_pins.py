@@ -149,7 +149,8 @@ def test_golden_c3_count_two_ways():
     assert d["converged"] and d["max_rho"] <= 1e-10
 
 
-@pytest.mark.parametrize("name,count", [("eig_batch8_n2e3_1.5e4.json", 8), ("eig_serve6.json", 6)])
+@pytest.mark.parametrize("name,count", [("eig_batch8_n2e3_1.5e4.json", 8), ("eig_serve6.json", 6),
+                                        ("eig_batch_full4.json", 4)])
 def test_golden_batch_eigenvalues_against_arpack(name, count):
     """The stored eigenvalues of batched-recipe pencils (the oracle's shift-invert
     subspace iteration, written by tests/golden/make_golden.py) against ARPACK's
